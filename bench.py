@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X Newton step (one GPU).
+
+A step is one Newton iteration of the given-length load sequence of the 3D
+penny-shaped crack workload (Kuhn n=20 -> 48,000 P2 tetrahedra, 1.44M
+displacement DOF, FP64): assemble R and J, build the block-Jacobi
+preconditioner, GMRES to a true relative residual of 1e-10, update.  The
+timed steps continue the load sequence from its start (converged load
+steps end with w_old <- w(u)), after W untimed warm-up steps and a reset.
+
+Printed JSON line: value = FP64 Newton steps/s.  Extra fields: GMRES
+throughput, the same steps in FP32-IR mode (speed-up and state error
+against FP64), the roofline of the dominant kernel (block-sparse Jacobian
+product, timed with HIP events on the library stream inside the timed
+region), and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Newton steps/s & GMRES iters/s (MDOF), FP32-IR vs FP64 at rel.res 1e-10"
+HBM_PEAK_GBS = 8000.0
+
+
+def run_steps(ctx, st0, K, W, profile):
+    """W warm-up Newton iterations, reset, then K timed iterations of the
+    load sequence.  Returns (seconds, per-step stats, final state)."""
+    import torch
+    ctx.set_state(st0.u, st0.p, st0.w_old)
+    for _ in range(W):
+        ns = ctx.newton_step()
+        if ns.converged:
+            ctx.end_load_step()
+    ctx.set_state(st0.u, st0.p, st0.w_old)
+    ctx.reset_profile()
+    ctx.set_options(profile=1 if profile else 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(K):
+        ns = ctx.newton_step()
+        stats.append((ns.lin.gmres_iters, ns.lin.ir_steps, ns.lin.true_relres, ns.du_rel,
+                      ns.dp_rel, ns.converged))
+        if ns.converged:
+            ctx.end_load_step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile()
+    ctx.set_options(profile=0)
+    return dt, stats, prof, ctx.get_state()
+
+
+def cpu_baseline(prob, gpu_iters_per_step):
+    """The oracle on a bounded sample of the same workload, single thread:
+    volume terms of every element, interface terms of a quarter of the
+    faces, the block-Jacobi setup and 20 GMRES(60) iterations on the full
+    block pattern.  Scaled to one Newton step with the GPU's GMRES iteration
+    count per step."""
+    from threadpoolctl import threadpool_limits
+    import numpy as np
+    from oracle import assemble as asm
+    from oracle import newton, solve
+    from oracle.newton import Case
+    with threadpool_limits(limits=1):
+        case = Case.from_problem(prob)
+        st = newton.initial_state(case)
+        m = case.mesh
+        args = (m, case.itf, case.prm, st.u, st.p, st.w_old, st.s_p, case.src_pnode, case.src_q0)
+        t = time.perf_counter()
+        asm.assemble(*args, faces=np.zeros(0, dtype=np.int64))
+        t_vol = time.perf_counter() - t
+        q = m.nf // 4
+        t = time.perf_counter()
+        S = asm.assemble(*args, faces=np.arange(q))
+        t_quarter = time.perf_counter() - t
+        t_faces = (t_quarter - t_vol) * m.nf / q
+        t = time.perf_counter()
+        pc = solve.BlockJacobi(m, S)
+        op = solve.Operator(m, S)
+        t_bj = time.perf_counter() - t
+        n_it = 20
+        t = time.perf_counter()
+        solve.gmres(op, -S.R, pc, m=60, rtol=1e-30, maxit=n_it)
+        t_it = (time.perf_counter() - t) / n_it
+    t_step = t_vol + t_faces + t_bj + gpu_iters_per_step * t_it
+    return {"value": 1.0 / t_step, "unit": "Newton steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle (numpy, 1 thread): volume terms of all {m.ne} elements "
+                       f"({t_vol:.1f} s), interface terms of {q}/{m.nf} faces scaled to all "
+                       f"({t_faces:.1f} s), block-Jacobi setup ({t_bj:.1f} s), {n_it} GMRES(60) "
+                       f"iterations ({t_it:.3f} s each) scaled to the GPU's "
+                       f"{gpu_iters_per_step:.0f} iterations per Newton step")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=2, help="synthetic workload index (1, 2, 3, 5)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-ir", action="store_true", help="skip the FP32-IR comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
+              "multi-GPU sharding is a design, not an implementation", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_1911_10275_amd as hf
+    import synth
+
+    prob = synth.config(args.workload)
+    print(f"bench: workload {prob.name}: {prob.n_elem} elements, {prob.n_udof} displacement DOF",
+          file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = hf.context_for_problem(prob, device=0, stream=stream)
+    sz = ctx.sizes
+    N = sz.n_u + sz.n_p
+
+    class St:  # start of the load sequence: u = 0, p = sigma_c, w_old = 0
+        u = np.zeros(sz.n_u)
+        p = np.full(sz.n_p, prob.material.sigma_c)
+        w_old = np.zeros((sz.n_face, sz.nq_face))
+
+    K, W = args.steps, args.warmup
+    dt64, st64, prof, state64 = run_steps(ctx, St, K, W, profile=True)
+    iters64 = [s[0] for s in st64]
+    for s in st64:
+        assert s[2] <= 1e-10, "FP64 solve missed the 1e-10 true residual"
+    print(f"bench: fp64 {K} steps in {dt64:.3f} s, GMRES iterations {iters64}", file=sys.stderr,
+          flush=True)
+    # dominant kernel: the FP64 block-sparse Jacobian product
+    bs = sz.block_size
+    spmv_bytes = sz.n_blocks * bs * bs * 8 + sz.n_blocks * 4 + (sz.n_elem + 1) * 8 + 2 * N * 8
+    spmv_ms = prof.ms_spmv64 / max(prof.n_spmv64, 1)
+    achieved = spmv_bytes / (spmv_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": K / dt64,
+        "unit": "Newton steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * dt64 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": prob.name, "elements": int(sz.n_elem), "dof": int(N),
+                   "u_dof": int(sz.n_u), "p_dof": int(sz.n_p), "element": f"P{prob.order}",
+                   "dim": prob.dim, "precision": "fp64", "gmres_m": 60, "rtol": 1e-10},
+        "gmres": {"iters_per_step": float(np.mean(iters64)),
+                  "iters_per_s": float(sum(iters64) / dt64),
+                  "mdof_iters_per_s": float(sum(iters64) * N / dt64 / 1e6)},
+        "roofline": {"bound": "hbm", "kernel": "k_bsr_spmv<double,30>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": int(spmv_bytes),
+                     "avg_launch_ms": spmv_ms, "launches": int(prof.n_spmv64)},
+        "kernel_ms": {"assemble": prof.ms_assemble, "spmv64": prof.ms_spmv64,
+                      "precond": prof.ms_precond, "ortho": prof.ms_ortho,
+                      "blockinv": prof.ms_blockinv},
+    }
+    if not args.no_ir:
+        ctx.set_options(precision=hf.HF_FP32_IR)
+        dt32, st32, prof32, state32 = run_steps(ctx, St, K, W, profile=False)
+        iters32 = [s[0] for s in st32]
+        for s in st32:
+            assert s[2] <= 1e-10, "FP32-IR solve missed the 1e-10 true residual"
+        u64, p64, w64, _ = state64
+        u32, p32, w32, _ = state32
+        rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+        out["fp32_ir"] = {"newton_steps_per_s": K / dt32, "speedup_vs_fp64": dt64 / dt32,
+                          "iters_per_step": float(np.mean(iters32)),
+                          "ir_steps_per_step": float(np.mean([s[1] for s in st32])),
+                          "mdof_iters_per_s": float(sum(iters32) * N / dt32 / 1e6),
+                          "rel_err_vs_fp64": {"u": rel(u32, u64), "p": rel(p32, p64),
+                                              "w": rel(w32, w64)}}
+        print(f"bench: fp32-ir {K} steps in {dt32:.3f} s, GMRES iterations {iters32}",
+              file=sys.stderr, flush=True)
+    ctx.close()
+    if not args.no_cpu:
+        print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(prob, float(np.mean(iters64)))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

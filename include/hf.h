@@ -1,0 +1,227 @@
+/*
+ * hf.h -- C ABI of the MI355X (gfx950) Newton step for the fully-coupled
+ * hydraulic-fracture model of Giovanardi, Serebrinsky and Radovitzky
+ * (arXiv 1911.10275).
+ *
+ * The library computes one Newton-Raphson iteration of the monolithic system
+ * of Sec. "Computational framework": the discrete elastostatics of eq.
+ * (discreteElastoStatics) on a discontinuous-Galerkin / cohesive-zone P^k
+ * discretisation (interface elements on every interior face), coupled to
+ * the continuous P^k lubrication equation eq. (discreteLubrication) on the
+ * interface skeleton, linearised as the 2x2 block system eq.
+ * (fully-coupled-fully-discrete) and solved with right-preconditioned
+ * restarted GMRES (block-Jacobi preconditioner) in FP64, or with an FP32
+ * inner GMRES under FP64 iterative refinement (GMRES-IR).  alpha (the
+ * cohesive-law activation) and beta (the fluid flag) are inputs and stay
+ * frozen, as inside one time step of the paper's algorithm.
+ *
+ * Conventions
+ *  - Every call returns hf_status (HF_OK = 0); no C++ exception crosses the
+ *    ABI.  hf_last_error() gives the message of the last failure of a ctx.
+ *  - Host arrays passed in are borrowed for the duration of the call and
+ *    copied; output arrays are caller-allocated.  *_device variants take
+ *    device pointers that must stay valid until the ctx stream has finished
+ *    the call's work.
+ *  - Call order: hf_upload_mesh -> [hf_upload_interfaces, hf_set_material,
+ *    hf_set_injection] -> hf_finalize -> hf_set_state -> {hf_assemble |
+ *    hf_solve | hf_newton_step | hf_newton_solve | hf_end_load_step}.
+ *    Any other order returns HF_ESTATE.
+ *  - One fracture instance per context (inst = 0).
+ *
+ * Canonical orderings (shared with any caller-side checker)
+ *  - Element node order: the simplex vertices as given, then (P2) edge
+ *    midpoints of edges (01),(12),(20) in 2D and (01),(12),(20),(03),(13),(23)
+ *    in 3D.  Displacement vector u: index (e*nodes_per_elem + a)*dim + i.
+ *  - Interior faces: sorted by their ascending vertex-id tuple.  The "-"
+ *    element is the lower element id; n is its outward unit normal;
+ *    [[u]] = u+ - u-; opening w = [[u]] . n (eq. displacementJump).
+ *  - Face integration points: conical-product Gauss rule on the face simplex
+ *    whose vertices are the face vertices in ascending id order; order+1
+ *    points per direction, first collapsed coordinate outermost, ascending.
+ *  - Pressure unknowns: only on skeleton nodes of faces with beta = 1;
+ *    vertex nodes ascending by vertex id, then edge-midpoint nodes ascending
+ *    by (lo, hi) vertex ids.
+ */
+#ifndef HF_H
+#define HF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HF_OK = 0,
+  HF_EINVAL = -1,     /* bad argument (null pointer, size, index, value) */
+  HF_ENOMEM = -2,     /* device or host allocation failed */
+  HF_EDEVICE = -3,    /* a HIP runtime call or kernel launch failed */
+  HF_ESTATE = -4,     /* call out of order */
+  HF_ESINGULAR = -5,  /* zero / non-finite pivot in a preconditioner block */
+  HF_ENOCONV = -6,    /* GMRES, refinement or Newton hit its iteration cap */
+  HF_ENONFINITE = -7  /* NaN or Inf in an input state or a computed result */
+} hf_status;
+
+typedef struct hf_ctx hf_ctx;
+
+enum { HF_FP64 = 0, HF_FP32_IR = 1 };
+
+typedef struct {
+  int precision;       /* HF_FP64: FP64 GMRES; HF_FP32_IR: FP32 inner GMRES +
+                          FP32 block inverses, FP64 residual and update */
+  int gmres_m;         /* restart length, 1..256 (default 60) */
+  int gmres_maxit;     /* GMRES iterations per linear solve (default 20000) */
+  int ir_maxit;        /* refinement steps per linear solve (default 100) */
+  int newton_maxit;    /* iterations of hf_newton_solve (default 25) */
+  double rtol;         /* true relative residual of every solve (1e-10) */
+  double rtol_inner;   /* FP32 inner GMRES reduction per refinement (1e-2) */
+  double newton_tol;   /* ||dU|| <= tol ||U|| and ||dP|| <= tol ||P|| (1e-10) */
+  double b_stab;       /* DG stabilisation parameter b (default 10) */
+  double p_cutoff;     /* pressure cut-off value when cutoff_on != 0 */
+  int cutoff_on;       /* clamp p >= p_cutoff after each update (default 0) */
+  int device;          /* HIP device ordinal (default 0) */
+  int profile;         /* 1: time kernel classes with HIP events (default 0) */
+  void *stream;        /* hipStream_t to run on; NULL: a stream the ctx creates */
+} hf_options;
+
+typedef struct {
+  double E, nu;        /* Young's modulus, Poisson ratio (plane strain in 2D) */
+  double sigma_c;      /* cohesive strength of eq. (tsl) */
+  double G_c;          /* fracture energy, delta_c = 2 G_c / sigma_c */
+  double mu;           /* fluid viscosity of eq. (lubrication) */
+  double dt;           /* backward-Euler time step */
+} hf_material;
+
+typedef struct {
+  int64_t n_elem, nodes_per_elem, n_u, n_p, n_face, n_blocks;
+  int32_t dim, order, nq_face, block_size;
+} hf_sizes;
+
+typedef struct {
+  int gmres_iters;     /* total (inner) GMRES iterations */
+  int ir_steps;        /* refinement steps (FP32-IR), 0 for FP64 */
+  int restarts;
+  double true_relres;  /* ||b - J dx|| / ||b||, recomputed in FP64 */
+  double seconds;      /* wall time of the solve */
+} hf_solve_stats;
+
+typedef struct {
+  hf_solve_stats lin;  /* of the last linear solve (summed in hf_newton_solve) */
+  double du_rel, dp_rel;   /* ||dU||/||U||, ||dP||/||P|| of the last update */
+  double res_norm;     /* ||R|| at the start of the last iteration */
+  int iterations;      /* Newton iterations taken */
+  int converged;       /* 1 when both relative increments <= newton_tol */
+} hf_newton_stats;
+
+typedef struct {
+  /* accumulated device time (ms) and launch counts of kernel classes, when
+     hf_options.profile = 1; reset by hf_reset_profile */
+  double ms_assemble, ms_blockinv, ms_spmv64, ms_spmv32, ms_precond, ms_ortho;
+  int64_t n_assemble, n_blockinv, n_spmv64, n_spmv32, n_precond, n_ortho;
+} hf_profile;
+
+/* Fill *opt with the defaults listed above. */
+void hf_default_options(hf_options *opt);
+
+/* Create a context on opt->device (NULL opt: defaults).  *out owns all the
+   device memory of the instance; release it with hf_destroy. */
+hf_status hf_create(const hf_options *opt, hf_ctx **out);
+void hf_destroy(hf_ctx *ctx);
+const char *hf_last_error(const hf_ctx *ctx);
+/* Change options after creation (precision, tolerances, caps, profile). */
+hf_status hf_set_options(hf_ctx *ctx, const hf_options *opt);
+
+/* Bulk mesh (Sec. "Computational framework": partition of the domain into
+   simplices carrying independent P^k displacement nodes).
+   dim 2|3, order 1|2; xyz (n_vert*dim) coordinates; elem_vert
+   (n_elem*(dim+1)) vertex ids of straight-sided simplices; dirichlet_vert
+   (n_vert, 0/1, nullable): a node copy is clamped (u = 0, strong) when it
+   lies on a boundary facet whose vertices are all flagged.  Builds the
+   interior-face list.  *inst_out = 0. */
+hf_status hf_upload_mesh(hf_ctx *ctx, int dim, int order, int64_t n_vert, const double *xyz,
+                         int64_t n_elem, const int32_t *elem_vert,
+                         const uint8_t *dirichlet_vert, int32_t *inst_out);
+
+/* Interior faces after hf_upload_mesh: *n_face; face_vert (n_face*dim
+   ascending vertex ids, nullable); face_elem (n_face*2: minus, plus element,
+   nullable); *nq_face = integration points per face (nullable). */
+hf_status hf_get_faces(hf_ctx *ctx, int32_t inst, int64_t *n_face, int32_t *face_vert,
+                       int32_t *face_elem, int32_t *nq_face);
+
+/* Interface state (eq. weakElastoStatics, the alpha and beta fields):
+   qp_state (n_face*nq, face-major): 0 intact (DG flux + stabilisation),
+   1 cohesive law of eq. (tsl) active, 2 traction-free (pre-crack); alpha = 1
+   where state >= 1.  beta (n_face): 1 = the face carries fluid.  Default:
+   all 0. */
+hf_status hf_upload_interfaces(hf_ctx *ctx, int32_t inst, const uint8_t *qp_state,
+                               const uint8_t *beta);
+
+hf_status hf_set_material(hf_ctx *ctx, int32_t inst, const hf_material *mat);
+
+/* Point injections Q0 (right-hand side of eq. discreteLubrication) at
+   skeleton vertices; each vertex must belong to a face with beta = 1. */
+hf_status hf_set_injection(hf_ctx *ctx, int32_t inst, int32_t n_src, const int64_t *vert,
+                           const double *q0);
+
+/* Build layout, block pattern, geometry and pressure numbering on the
+   device.  No uploads after this call. */
+hf_status hf_finalize(hf_ctx *ctx);
+hf_status hf_get_sizes(hf_ctx *ctx, int32_t inst, hf_sizes *out);
+/* Pressure-node keys (n_p*2): (vertex, -1) or (lo, hi) of an edge node. */
+hf_status hf_get_pnodes(hf_ctx *ctx, int32_t inst, int64_t *keys);
+
+/* State at the start of a load step: u (n_u), p (n_p), w_old (n_face*nq,
+   the opening of the previous step, source of eq. discreteLubrication;
+   nullable = keep).  Rejects non-finite values (HF_ENONFINITE).  Also fixes
+   the fluid-row scale s_p = 12 mu (L / w_ref)^3 with L the largest bounding
+   box extent and w_ref = max(max w_old on fluid faces, 0.01 delta_c). */
+hf_status hf_set_state(hf_ctx *ctx, int32_t inst, const double *u, const double *p,
+                       const double *w_old);
+/* u, p, w (current opening at face points), w_old: each nullable. */
+hf_status hf_get_state(hf_ctx *ctx, int32_t inst, double *u, double *p, double *w,
+                       double *w_old);
+/* Device-pointer variants on the ctx stream (FP64 arrays, same layouts). */
+hf_status hf_set_state_device(hf_ctx *ctx, int32_t inst, const double *u, const double *p,
+                              const double *w_old);
+hf_status hf_get_state_device(hf_ctx *ctx, int32_t inst, double *u, double *p);
+
+/* Residual R and Jacobian J = [[A, B], [C, D]] at the current state
+   (eq. discreteElastoStatics, eq. discreteLubrication and their exact
+   derivative).  *res_norm = ||R|| (nullable). */
+hf_status hf_assemble(hf_ctx *ctx, double *res_norm);
+/* Build the preconditioner and solve J dx = -R to the true relative
+   residual rtol (GMRES or GMRES-IR per options); dx is kept in the ctx. */
+hf_status hf_solve(hf_ctx *ctx, hf_solve_stats *stats);
+/* One Newton iteration: assemble + solve + update u, p (+ optional cut-off).
+   On HF_ENOCONV / HF_ESINGULAR / HF_ENONFINITE the state is unchanged. */
+hf_status hf_newton_step(hf_ctx *ctx, hf_newton_stats *stats);
+/* Newton iterations until converged or newton_maxit (HF_ENOCONV, state
+   restored to the start of the call). */
+hf_status hf_newton_solve(hf_ctx *ctx, hf_newton_stats *stats);
+/* End of a given-length load step: w_old <- w(u), s_p recomputed. */
+hf_status hf_end_load_step(hf_ctx *ctx);
+
+/* ---- inspection hooks (tests, benchmarks) ---- */
+/* R_u (n_u), R_p (n_p) of the last hf_assemble. */
+hf_status hf_get_residual(hf_ctx *ctx, int32_t inst, double *R_u, double *R_p);
+/* Block rows of A for n_rows elements: cols (n_rows*(dim+2), -1 = no block),
+   blocks (n_rows*(dim+2)*bs*bs, row-major bs x bs; slot 0 = diagonal, slot
+   1+f = neighbour across local face f). */
+hf_status hf_get_block_rows(hf_ctx *ctx, int32_t inst, int64_t n_rows, const int32_t *elems,
+                            int32_t *cols, double *blocks);
+/* Dense coupling blocks (small meshes): B (n_u*n_p), C (n_p*n_u),
+   D (n_p*n_p), row-major; each nullable. */
+hf_status hf_get_coupling(hf_ctx *ctx, int32_t inst, double *B, double *C, double *D);
+/* Increment dx = (du, dp) of the last hf_solve. */
+hf_status hf_get_increment(hf_ctx *ctx, int32_t inst, double *du, double *dp);
+/* y = J x on device vectors of length n_u + n_p; precision HF_FP64 uses the
+   FP64 matrix (double*), HF_FP32_IR the FP32 copy (float*) built by the
+   last hf_solve in FP32-IR mode. */
+hf_status hf_apply_jacobian(hf_ctx *ctx, int precision, const void *x, void *y);
+hf_status hf_get_profile(hf_ctx *ctx, hf_profile *out);
+hf_status hf_reset_profile(hf_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HF_H */

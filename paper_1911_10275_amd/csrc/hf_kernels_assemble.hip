@@ -1,0 +1,673 @@
+// Assembly kernels for gfx950: geometry, the element-centric residual and
+// Jacobian rows of the displacement equations, the fluid rows, and the
+// opening at face points.
+//
+// Element-centric assembly: every element (one workgroup) computes its own
+// row of blocks -- the diagonal block (bulk term plus the self part of each of
+// its interface elements) and one off-diagonal block per interior face -- so
+// every block is written exactly once, with a fixed summation order, no
+// atomics and no staging.  Each interface integral is therefore evaluated by
+// both of its elements, each for its own test functions.
+#include <cmath>
+
+#include "hf_internal.h"
+
+namespace hf {
+
+__constant__ RuleTables c_rules;
+
+hipError_t launch_set_rules(const RuleTables &rt, hipStream_t st) {
+  return hipMemcpyToSymbolAsync(HIP_SYMBOL(c_rules), &rt, sizeof(RuleTables), 0,
+                                hipMemcpyHostToDevice, st);
+}
+
+// ---------------------------------------------------------------------------
+// Lagrange P1/P2 on simplices in barycentric coordinates
+// node order: vertices, then edges (01),(12),(20),(03),(13),(23)
+// ---------------------------------------------------------------------------
+template <int D, int K>
+struct Lag {
+  static constexpr int NN = (K == 1) ? D + 1 : (D + 1) * (D + 2) / 2;
+  __device__ static constexpr int ea(int k) {
+    return k < 3 ? (D == 1 ? 0 : k) : k - 3;
+  }
+  __device__ static constexpr int eb(int k) {
+    return D == 1 ? 1 : (k < 3 ? (k + 1) % 3 : 3);
+  }
+  __device__ static void phi(const double *lam, double *out) {
+    if (K == 1) {
+#pragma unroll
+      for (int a = 0; a <= D; ++a) out[a] = lam[a];
+    } else {
+#pragma unroll
+      for (int a = 0; a <= D; ++a) out[a] = lam[a] * (2.0 * lam[a] - 1.0);
+#pragma unroll
+      for (int k = 0; k < NN - D - 1; ++k) out[D + 1 + k] = 4.0 * lam[ea(k)] * lam[eb(k)];
+    }
+  }
+  // d phi_a / d lam_k
+  __device__ static void dphi(const double *lam, double out[][D + 1]) {
+#pragma unroll
+    for (int a = 0; a < NN; ++a)
+#pragma unroll
+      for (int k = 0; k <= D; ++k) out[a][k] = 0.0;
+    if (K == 1) {
+#pragma unroll
+      for (int a = 0; a <= D; ++a) out[a][a] = 1.0;
+    } else {
+#pragma unroll
+      for (int a = 0; a <= D; ++a) out[a][a] = 4.0 * lam[a] - 1.0;
+#pragma unroll
+      for (int k = 0; k < NN - D - 1; ++k) {
+        out[D + 1 + k][ea(k)] = 4.0 * lam[eb(k)];
+        out[D + 1 + k][eb(k)] = 4.0 * lam[ea(k)];
+      }
+    }
+  }
+};
+
+template <int DIM, int ORDER>
+struct Cfg {
+  static constexpr int NN = Lag<DIM, ORDER>::NN;
+  static constexpr int BU = NN * DIM;
+  static constexpr int NF = DIM + 1;
+  static constexpr int NQF = (DIM == 2) ? ORDER + 1 : (ORDER + 1) * (ORDER + 1);
+  static constexpr int NQV = (DIM == 2) ? ORDER * ORDER : ORDER * ORDER * ORDER;
+  static constexpr int NNF = Lag<DIM - 1, ORDER>::NN;
+};
+
+// ---------------------------------------------------------------------------
+// Geometry: gradients of barycentrics, |det J|; face normal, area, h, metric
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void k_geom_elem(KParams kp) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= kp.s.ne) return;
+  const int32_t *ev = kp.m.elem_vert + e * (DIM + 1);
+  double X0[DIM], J[DIM][DIM];
+  for (int c = 0; c < DIM; ++c) X0[c] = kp.m.xyz[(int64_t)ev[0] * DIM + c];
+  for (int k = 0; k < DIM; ++k)
+    for (int c = 0; c < DIM; ++c) J[c][k] = kp.m.xyz[(int64_t)ev[k + 1] * DIM + c] - X0[c];
+  double Ji[DIM][DIM], det;
+  if constexpr (DIM == 2) {
+    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    Ji[0][0] = J[1][1] / det;
+    Ji[0][1] = -J[0][1] / det;
+    Ji[1][0] = -J[1][0] / det;
+    Ji[1][1] = J[0][0] / det;
+  } else {
+    // inverse = adjugate / det, adjugate = cofactor^T
+    double cof[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        int r1 = (r + 1) % 3, r2 = (r + 2) % 3, c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        cof[r][c] = J[r1][c1] * J[r2][c2] - J[r1][c2] * J[r2][c1];
+      }
+    det = J[0][0] * cof[0][0] + J[0][1] * cof[0][1] + J[0][2] * cof[0][2];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) Ji[r][c] = cof[c][r] / det;
+  }
+  double *gl = kp.m.gl + e * (DIM + 1) * DIM;
+  for (int x = 0; x < DIM; ++x) {
+    double s = 0.0;
+    for (int k = 0; k < DIM; ++k) {
+      gl[(k + 1) * DIM + x] = Ji[k][x];
+      s += Ji[k][x];
+    }
+    gl[x] = -s;
+  }
+  kp.m.detabs[e] = fabs(det);
+}
+
+template <int DIM>
+__global__ void k_geom_face(KParams kp) {
+  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= kp.s.nf) return;
+  const int32_t *fv = kp.m.face_vert + f * DIM;
+  double V[DIM][DIM];
+  for (int k = 0; k < DIM; ++k)
+    for (int c = 0; c < DIM; ++c) V[k][c] = kp.m.xyz[(int64_t)fv[k] * DIM + c];
+  double n[DIM], area;
+  double t1[DIM];
+  for (int c = 0; c < DIM; ++c) t1[c] = V[1][c] - V[0][c];
+  if constexpr (DIM == 2) {
+    n[0] = t1[1];
+    n[1] = -t1[0];
+    area = sqrt(n[0] * n[0] + n[1] * n[1]);
+    kp.m.ginv[f] = 1.0 / (t1[0] * t1[0] + t1[1] * t1[1]);
+  } else {
+    double t2[3];
+    for (int c = 0; c < 3; ++c) t2[c] = V[2][c] - V[0][c];
+    n[0] = t1[1] * t2[2] - t1[2] * t2[1];
+    n[1] = t1[2] * t2[0] - t1[0] * t2[2];
+    n[2] = t1[0] * t2[1] - t1[1] * t2[0];
+    double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    area = 0.5 * nn;
+    double g11 = t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2];
+    double g22 = t2[0] * t2[0] + t2[1] * t2[1] + t2[2] * t2[2];
+    double g12 = t1[0] * t2[0] + t1[1] * t2[1] + t1[2] * t2[2];
+    double dg = g11 * g22 - g12 * g12;
+    double *gi = kp.m.ginv + f * 4;
+    gi[0] = g22 / dg;
+    gi[1] = -g12 / dg;
+    gi[2] = -g12 / dg;
+    gi[3] = g11 / dg;
+  }
+  // orient outward of the minus element: away from its vertex opposite the face
+  int32_t em = kp.m.face_em[f], ep = kp.m.face_ep[f];
+  int32_t vopp = kp.m.elem_vert[(int64_t)em * (DIM + 1) + kp.m.face_lfm[f]];
+  double dotv = 0.0, nrm = 0.0;
+  for (int c = 0; c < DIM; ++c) {
+    dotv += n[c] * (kp.m.xyz[(int64_t)vopp * DIM + c] - V[0][c]);
+    nrm += n[c] * n[c];
+  }
+  nrm = sqrt(nrm);
+  double sg = dotv > 0.0 ? -1.0 : 1.0;
+  for (int c = 0; c < DIM; ++c) kp.m.normal[f * DIM + c] = sg * n[c] / nrm;
+  kp.m.area[f] = area;
+  const double fact = (DIM == 2) ? 2.0 : 6.0;
+  double vm = kp.m.detabs[em] / fact, vp = kp.m.detabs[ep] / fact;
+  kp.m.hf[f] = fmin(vm, vp) / area;
+}
+
+hipError_t launch_geometry(const KParams &kp, hipStream_t st) {
+  const int nt = 128;
+  int ge = (int)((kp.s.ne + nt - 1) / nt), gf = (int)((kp.s.nf + nt - 1) / nt);
+  if (kp.s.dim == 2) {
+    if (ge) hipLaunchKernelGGL(k_geom_elem<2>, dim3(ge), dim3(nt), 0, st, kp);
+    if (gf) hipLaunchKernelGGL(k_geom_face<2>, dim3(gf), dim3(nt), 0, st, kp);
+  } else {
+    if (ge) hipLaunchKernelGGL(k_geom_elem<3>, dim3(ge), dim3(nt), 0, st, kp);
+    if (gf) hipLaunchKernelGGL(k_geom_face<3>, dim3(gf), dim3(nt), 0, st, kp);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Interface law (normal cohesive traction) and cubic-law conductivity
+// ---------------------------------------------------------------------------
+__device__ inline void traction_law(int state, double w, double sigma_c, double delta_c,
+                                    double kc, double &T, double &dT) {
+  T = 0.0;
+  dT = 0.0;
+  if (state == 1) {
+    if (w < 0.0) {
+      T = sigma_c + kc * w;
+      dT = kc;
+    } else if (w <= delta_c) {
+      T = sigma_c * (1.0 - w / delta_c);
+      dT = -sigma_c / delta_c;
+    }
+  } else if (state == 2) {
+    if (w < 0.0) {
+      T = kc * w;
+      dT = kc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Element-centric assembly of the displacement rows
+// ---------------------------------------------------------------------------
+template <int DIM, int ORDER, int NT>
+__global__ __launch_bounds__(NT) void k_assemble(KParams kp, const double *__restrict__ u,
+                                                 const double *__restrict__ p,
+                                                 const double *__restrict__ w_old,
+                                                 double *__restrict__ A, double *__restrict__ R,
+                                                 double *__restrict__ Bs,
+                                                 double *__restrict__ Cs) {
+  using C = Cfg<DIM, ORDER>;
+  constexpr int NN = C::NN, BU = C::BU, NF = C::NF, NQF = C::NQF, NQV = C::NQV, NNF = C::NNF;
+  constexpr int NQ = NQF > NQV ? NQF : NQV;
+  const int64_t e = blockIdx.x;
+  const int tid = threadIdx.x;
+  const double lam = kp.lam, G = kp.G;
+
+  __shared__ double s_gl[NF][DIM], s_gln[NF][DIM];
+  __shared__ double s_ue[BU], s_un[BU];
+  __shared__ double s_diag[BU * BU];
+  __shared__ double s_phE[NQ][NN], s_gphE[NQ][NN][DIM];
+  __shared__ double s_phN[NQF][NN], s_gphN[NQF][NN][DIM];
+  __shared__ double s_X[2][NQF][BU][DIM];
+  __shared__ double s_tau[NQF][DIM], s_W[NQF], s_al[NQF], s_dT[NQF];
+  __shared__ double s_eta[NQF][NNF], s_fc[NQF][NNF];
+  __shared__ double s_R[BU];
+  __shared__ double s_n[DIM];
+  __shared__ double s_ginv[(DIM - 1) * (DIM - 1)];
+  __shared__ int s_pe[DIM], s_pn[DIM];
+
+  const double det = kp.m.detabs[e];
+  if (tid < NF * DIM) s_gl[tid / DIM][tid % DIM] = kp.m.gl[e * NF * DIM + tid];
+  for (int r = tid; r < BU; r += NT) s_ue[r] = u[e * BU + r];
+  __syncthreads();
+
+  // ---- bulk term: K_e and r_e = int sigma(u) : grad(phi) ----------------
+  for (int t = tid; t < NQV * NN; t += NT) {
+    const int q = t / NN, a = t % NN;
+    double lamq[DIM + 1], dph[NN][DIM + 1];
+    for (int k = 0; k <= DIM; ++k) lamq[k] = c_rules.vq_lam[q][k];
+    Lag<DIM, ORDER>::dphi(lamq, dph);
+    for (int x = 0; x < DIM; ++x) {
+      double g = 0.0;
+      for (int k = 0; k <= DIM; ++k) g += dph[a][k] * s_gl[k][x];
+      s_gphE[q][a][x] = g;
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < BU * BU; idx += NT) {
+    const int c = idx / BU, r = idx % BU;
+    const int a = r / DIM, i = r % DIM, b = c / DIM, j = c % DIM;
+    double k = 0.0;
+    for (int q = 0; q < NQV; ++q) {
+      double gg = 0.0;
+      for (int x = 0; x < DIM; ++x) gg += s_gphE[q][a][x] * s_gphE[q][b][x];
+      double v = lam * s_gphE[q][a][i] * s_gphE[q][b][j] + G * s_gphE[q][a][j] * s_gphE[q][b][i];
+      if (i == j) v += G * gg;
+      k += c_rules.vq_w[q] * det * v;
+    }
+    s_diag[idx] = k;
+  }
+  for (int r = tid; r < BU; r += NT) {
+    const int a = r / DIM, i = r % DIM;
+    double acc = 0.0;
+    for (int q = 0; q < NQV; ++q) {
+      double gu[DIM][DIM];
+      for (int ii = 0; ii < DIM; ++ii)
+        for (int x = 0; x < DIM; ++x) {
+          double g = 0.0;
+          for (int b = 0; b < NN; ++b) g += s_ue[b * DIM + ii] * s_gphE[q][b][x];
+          gu[ii][x] = g;
+        }
+      double tr = 0.0;
+      for (int x = 0; x < DIM; ++x) tr += gu[x][x];
+      double sn = 0.0;
+      for (int x = 0; x < DIM; ++x) {
+        double sig = G * (gu[i][x] + gu[x][i]) + (i == x ? lam * tr : 0.0);
+        sn += sig * s_gphE[q][a][x];
+      }
+      acc += c_rules.vq_w[q] * det * sn;
+    }
+    s_R[r] = acc;
+  }
+  // zero this element's coupling strips (owned by this workgroup)
+  const int64_t sp0 = kp.m.sp_ptr[e], sp1 = kp.m.sp_ptr[e + 1];
+  for (int r = tid; r < BU; r += NT)
+    for (int64_t k = sp0; k < sp1; ++k) {
+      Bs[k * BU + r] = 0.0;
+      Cs[k * BU + r] = 0.0;
+    }
+  __syncthreads();
+
+  const uint32_t clamp = kp.m.clamp[e];
+
+  // ---- interface elements -----------------------------------------------
+  for (int lf = 0; lf < NF; ++lf) {
+    const int32_t f = kp.m.fid[e * NF + lf];
+    if (f < 0) continue;  // boundary facet: clamped rows or zero traction
+    const int32_t nb = kp.m.nbr[e * NF + lf];
+    const bool minus = (kp.m.face_em[f] == (int32_t)e);
+    const double sgE = minus ? -1.0 : 1.0, sgN = -sgE;
+    const double area = kp.m.area[f];
+    const double bh = kp.b_stab / kp.m.hf[f];
+    const double kc = bh * (lam + 2.0 * G);
+    const int beta = kp.m.beta[f];
+    const int slot = kp.m.slot[f];
+    if (tid < DIM) {
+      s_n[tid] = kp.m.normal[(int64_t)f * DIM + tid];
+      s_pe[tid] = minus ? kp.m.fperm_m[(int64_t)f * DIM + tid] : kp.m.fperm_p[(int64_t)f * DIM + tid];
+      s_pn[tid] = minus ? kp.m.fperm_p[(int64_t)f * DIM + tid] : kp.m.fperm_m[(int64_t)f * DIM + tid];
+    }
+    if (tid < (DIM - 1) * (DIM - 1)) s_ginv[tid] = kp.m.ginv[(int64_t)f * (DIM - 1) * (DIM - 1) + tid];
+    if (tid < NF * DIM) s_gln[tid / DIM][tid % DIM] = kp.m.gl[(int64_t)nb * NF * DIM + tid];
+    for (int r = tid; r < BU; r += NT) s_un[r] = u[(int64_t)nb * BU + r];
+    __syncthreads();
+    // shape functions of both elements at the face points
+    for (int t = tid; t < 2 * NQF; t += NT) {
+      const int side = t / NQF, q = t % NQF;
+      double lamq[DIM + 1];
+      for (int k = 0; k <= DIM; ++k) lamq[k] = 0.0;
+      const int *perm = side == 0 ? s_pe : s_pn;
+      for (int k = 0; k < DIM; ++k) lamq[perm[k]] = c_rules.fq_mu[q][k];
+      double ph[NN], dph[NN][DIM + 1];
+      Lag<DIM, ORDER>::phi(lamq, ph);
+      Lag<DIM, ORDER>::dphi(lamq, dph);
+      for (int a = 0; a < NN; ++a) {
+        for (int x = 0; x < DIM; ++x) {
+          double g = 0.0;
+          for (int k = 0; k <= DIM; ++k) g += dph[a][k] * (side == 0 ? s_gl[k][x] : s_gln[k][x]);
+          if (side == 0) s_gphE[q][a][x] = g; else s_gphN[q][a][x] = g;
+        }
+        if (side == 0) s_phE[q][a] = ph[a]; else s_phN[q][a] = ph[a];
+      }
+    }
+    __syncthreads();
+    // per-point traction tau, interface-law tangent, fluid coefficients
+    for (int q = tid; q < NQF; q += NT) {
+      double uE[DIM], uN[DIM], gE[DIM][DIM], gN[DIM][DIM];
+      for (int i = 0; i < DIM; ++i) {
+        double a0 = 0.0, a1 = 0.0;
+        for (int a = 0; a < NN; ++a) {
+          a0 += s_phE[q][a] * s_ue[a * DIM + i];
+          a1 += s_phN[q][a] * s_un[a * DIM + i];
+        }
+        uE[i] = a0;
+        uN[i] = a1;
+        for (int x = 0; x < DIM; ++x) {
+          double b0 = 0.0, b1 = 0.0;
+          for (int a = 0; a < NN; ++a) {
+            b0 += s_ue[a * DIM + i] * s_gphE[q][a][x];
+            b1 += s_un[a * DIM + i] * s_gphN[q][a][x];
+          }
+          gE[i][x] = b0;
+          gN[i][x] = b1;
+        }
+      }
+      double trE = 0.0, trN = 0.0;
+      for (int x = 0; x < DIM; ++x) {
+        trE += gE[x][x];
+        trN += gN[x][x];
+      }
+      double jump[DIM], w = 0.0;
+      for (int i = 0; i < DIM; ++i) {
+        jump[i] = sgE * uE[i] + sgN * uN[i];  // u+ - u-
+        w += jump[i] * s_n[i];
+      }
+      const int st = kp.m.qp_state[(int64_t)f * NQF + q];
+      const double al = st > 0 ? 1.0 : 0.0;
+      double T, dT;
+      traction_law(st, w, kp.sigma_c, kp.delta_c, kc, T, dT);
+      double ph_p = 0.0;
+      double eta[NNF];
+      double geta[NNF][DIM - 1];
+      if (beta) {
+        double mu_[DIM], dmu[NNF][DIM];
+        for (int k = 0; k < DIM; ++k) mu_[k] = c_rules.fq_mu[q][k];
+        Lag<DIM - 1, ORDER>::phi(mu_, eta);
+        Lag<DIM - 1, ORDER>::dphi(mu_, dmu);
+        for (int k = 0; k < NNF; ++k)
+          for (int s = 0; s < DIM - 1; ++s) geta[k][s] = dmu[k][s + 1] - dmu[k][0];
+        for (int k = 0; k < NNF; ++k) ph_p += eta[k] * p[kp.m.face_pn[(int64_t)slot * NNF + k]];
+      }
+      for (int i = 0; i < DIM; ++i) {
+        double sn = 0.0;  // 0.5 (sigma_E + sigma_N) n, component i
+        for (int x = 0; x < DIM; ++x) {
+          double sE = G * (gE[i][x] + gE[x][i]) + (i == x ? lam * trE : 0.0);
+          double sN = G * (gN[i][x] + gN[x][i]) + (i == x ? lam * trN : 0.0);
+          sn += 0.5 * (sE + sN) * s_n[x];
+        }
+        double cj = G * jump[i];
+        double jn = 0.0;
+        for (int x = 0; x < DIM; ++x) jn += jump[x] * s_n[x];
+        cj += (lam + G) * s_n[i] * jn;
+        s_tau[q][i] = (1.0 - al) * (sn + bh * cj) + al * T * s_n[i] - (beta ? ph_p * s_n[i] : 0.0);
+      }
+      const double W = c_rules.fq_w[q] * area;
+      s_W[q] = W;
+      s_al[q] = al;
+      s_dT[q] = dT;
+      if (beta) {
+        const double wp = w > 0.0 ? w : 0.0;
+        const double dK = 3.0 * wp * wp / (12.0 * kp.mu);
+        double gp[DIM - 1];
+        for (int s = 0; s < DIM - 1; ++s) {
+          double g = 0.0;
+          for (int k = 0; k < NNF; ++k) g += geta[k][s] * p[kp.m.face_pn[(int64_t)slot * NNF + k]];
+          gp[s] = g;
+        }
+        for (int k = 0; k < NNF; ++k) {
+          double gg = 0.0;
+          for (int s = 0; s < DIM - 1; ++s)
+            for (int t2 = 0; t2 < DIM - 1; ++t2) gg += gp[s] * s_ginv[s * (DIM - 1) + t2] * geta[k][t2];
+          s_eta[q][k] = eta[k];
+          s_fc[q][k] = kp.s_p * (dK * gg + eta[k] / kp.dt);
+        }
+      }
+    }
+    __syncthreads();
+    // residual of this element's test functions
+    for (int r = tid; r < BU; r += NT) {
+      const int a = r / DIM, i = r % DIM;
+      double acc = 0.0;
+      for (int q = 0; q < NQF; ++q) acc += s_W[q] * sgE * s_phE[q][a] * s_tau[q][i];
+      s_R[r] += acc;
+    }
+    // X^t_q[b,j,i] = d tau_i / d u^t_{b,j}
+    for (int idx = tid; idx < 2 * NQF * BU * DIM; idx += NT) {
+      const int i = idx % DIM;
+      const int c = (idx / DIM) % BU;
+      const int q = (idx / (DIM * BU)) % NQF;
+      const int side = idx / (DIM * BU * NQF);
+      const int b = c / DIM, j = c % DIM;
+      const double sg = side == 0 ? sgE : sgN;
+      const double ph = side == 0 ? s_phE[q][b] : s_phN[q][b];
+      double gph[DIM];
+      for (int x = 0; x < DIM; ++x) gph[x] = side == 0 ? s_gphE[q][b][x] : s_gphN[q][b][x];
+      double gn = 0.0;
+      for (int x = 0; x < DIM; ++x) gn += gph[x] * s_n[x];
+      double cons = 0.5 * (lam * gph[j] * s_n[i] + G * gph[i] * s_n[j] + (i == j ? G * gn : 0.0));
+      double chat = (i == j ? G : 0.0) + (lam + G) * s_n[i] * s_n[j];
+      double pen = bh * chat * sg * ph;
+      double coh = s_dT[q] * s_n[i] * s_n[j] * sg * ph;
+      s_X[side][q][c][i] = (1.0 - s_al[q]) * (cons + pen) + s_al[q] * coh;
+    }
+    __syncthreads();
+    // self block (into the diagonal) and the off-diagonal block of this face
+    double *Aoff = A + (int64_t)kp.m.blk_of[e * NF + lf] * BU * BU;
+    for (int idx = tid; idx < BU * BU; idx += NT) {
+      const int c = idx / BU, r = idx % BU;
+      const int a = r / DIM, i = r % DIM;
+      double vs = 0.0, vo = 0.0;
+      for (int q = 0; q < NQF; ++q) {
+        const double t = s_W[q] * sgE * s_phE[q][a];
+        vs += t * s_X[0][q][c][i];
+        vo += t * s_X[1][q][c][i];
+      }
+      s_diag[idx] += vs;
+      Aoff[idx] = ((clamp >> r) & 1u) ? 0.0 : vo;
+    }
+    // coupling strips: B (d R_u / d p) and C (d R_p / d u_e) of this face
+    if (beta) {
+      for (int r = tid; r < BU; r += NT) {
+        const int a = r / DIM, i = r % DIM;
+        for (int k = 0; k < NNF; ++k) {
+          const int32_t ix = kp.m.fs_idx[((int64_t)e * NF + lf) * NNF + k];
+          double bv = 0.0, cv = 0.0;
+          for (int q = 0; q < NQF; ++q) {
+            bv += s_W[q] * sgE * s_phE[q][a] * (-s_eta[q][k] * s_n[i]);
+            cv += s_W[q] * s_fc[q][k] * sgE * s_phE[q][a] * s_n[i];
+          }
+          Bs[(int64_t)ix * BU + r] += bv;
+          Cs[(int64_t)ix * BU + r] += cv;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- strong Dirichlet rows and write-back ------------------------------
+  double *Ad = A + kp.m.blk_ptr[e] * BU * BU;
+  for (int idx = tid; idx < BU * BU; idx += NT) {
+    const int c = idx / BU, r = idx % BU;
+    double v = s_diag[idx];
+    if ((clamp >> r) & 1u) v = (r == c) ? 1.0 : 0.0;
+    Ad[idx] = v;
+  }
+  for (int r = tid; r < BU; r += NT) {
+    const bool cl = (clamp >> r) & 1u;
+    R[e * BU + r] = cl ? s_ue[r] : s_R[r];
+    if (cl)
+      for (int64_t k = sp0; k < sp1; ++k) Bs[k * BU + r] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fluid rows: R_p and the dense row of D, one thread per pressure node
+// ---------------------------------------------------------------------------
+template <int DIM, int ORDER>
+__global__ void k_fluid_rows(KParams kp, const double *__restrict__ u,
+                             const double *__restrict__ p, const double *__restrict__ w_old,
+                             double *__restrict__ R, double *__restrict__ D) {
+  using C = Cfg<DIM, ORDER>;
+  constexpr int NN = C::NN, BU = C::BU, NQF = C::NQF, NNF = C::NNF;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t np = kp.s.n_p;
+  if (i >= np) return;
+  double *Drow = D + i * np;
+  for (int64_t j = 0; j < np; ++j) Drow[j] = 0.0;
+  double Ri = 0.0;
+  for (int32_t t = kp.m.pf_ptr[i]; t < kp.m.pf_ptr[i + 1]; ++t) {
+    const int32_t fa = kp.m.pf_fa[t], kk = kp.m.pf_k[t];
+    const int32_t f = kp.m.act_face[fa];
+    const int32_t em = kp.m.face_em[f], ep = kp.m.face_ep[f];
+    double n[DIM];
+    for (int x = 0; x < DIM; ++x) n[x] = kp.m.normal[(int64_t)f * DIM + x];
+    const double area = kp.m.area[f];
+    double gi[(DIM - 1) * (DIM - 1)];
+    for (int s = 0; s < (DIM - 1) * (DIM - 1); ++s) gi[s] = kp.m.ginv[(int64_t)f * (DIM - 1) * (DIM - 1) + s];
+    int32_t pn[NNF];
+    for (int k = 0; k < NNF; ++k) pn[k] = kp.m.face_pn[(int64_t)fa * NNF + k];
+    for (int q = 0; q < NQF; ++q) {
+      double lm[DIM + 1], lp[DIM + 1];
+      for (int k = 0; k <= DIM; ++k) lm[k] = lp[k] = 0.0;
+      for (int k = 0; k < DIM; ++k) {
+        lm[kp.m.fperm_m[(int64_t)f * DIM + k]] = c_rules.fq_mu[q][k];
+        lp[kp.m.fperm_p[(int64_t)f * DIM + k]] = c_rules.fq_mu[q][k];
+      }
+      double phm[NN], php[NN];
+      Lag<DIM, ORDER>::phi(lm, phm);
+      Lag<DIM, ORDER>::phi(lp, php);
+      double w = 0.0;
+      for (int x = 0; x < DIM; ++x) {
+        double um = 0.0, up = 0.0;
+        for (int a = 0; a < NN; ++a) {
+          um += phm[a] * u[(int64_t)em * BU + a * DIM + x];
+          up += php[a] * u[(int64_t)ep * BU + a * DIM + x];
+        }
+        w += (up - um) * n[x];
+      }
+      const double wp = w > 0.0 ? w : 0.0;
+      const double K = wp * wp * wp / (12.0 * kp.mu);
+      double mu_[DIM], eta[NNF], dmu[NNF][DIM], geta[NNF][DIM - 1];
+      for (int k = 0; k < DIM; ++k) mu_[k] = c_rules.fq_mu[q][k];
+      Lag<DIM - 1, ORDER>::phi(mu_, eta);
+      Lag<DIM - 1, ORDER>::dphi(mu_, dmu);
+      for (int k = 0; k < NNF; ++k)
+        for (int s = 0; s < DIM - 1; ++s) geta[k][s] = dmu[k][s + 1] - dmu[k][0];
+      double gp[DIM - 1];
+      for (int s = 0; s < DIM - 1; ++s) {
+        double g = 0.0;
+        for (int k = 0; k < NNF; ++k) g += geta[k][s] * p[pn[k]];
+        gp[s] = g;
+      }
+      const double W = c_rules.fq_w[q] * area;
+      double gpg = 0.0;
+      for (int s = 0; s < DIM - 1; ++s)
+        for (int t2 = 0; t2 < DIM - 1; ++t2) gpg += gp[s] * gi[s * (DIM - 1) + t2] * geta[kk][t2];
+      const double wo = w_old[(int64_t)f * NQF + q];
+      Ri += kp.s_p * W * (K * gpg + (w - wo) / kp.dt * eta[kk]);
+      for (int l = 0; l < NNF; ++l) {
+        double gg = 0.0;
+        for (int s = 0; s < DIM - 1; ++s)
+          for (int t2 = 0; t2 < DIM - 1; ++t2) gg += geta[l][s] * gi[s * (DIM - 1) + t2] * geta[kk][t2];
+        Drow[pn[l]] += kp.s_p * W * K * gg;
+      }
+    }
+  }
+  for (int64_t s = 0; s < kp.s.n_src; ++s)
+    if (kp.m.src_node[s] == i) Ri -= kp.s_p * kp.m.src_q0[s];
+  R[kp.s.n_u + i] = Ri;
+}
+
+// ---------------------------------------------------------------------------
+// Opening w = [[u]] . n at every face point
+// ---------------------------------------------------------------------------
+template <int DIM, int ORDER>
+__global__ void k_opening(KParams kp, const double *__restrict__ u, double *__restrict__ w) {
+  using C = Cfg<DIM, ORDER>;
+  constexpr int NN = C::NN, BU = C::BU, NQF = C::NQF;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= kp.s.nf * NQF) return;
+  const int64_t f = t / NQF;
+  const int q = (int)(t % NQF);
+  const int32_t em = kp.m.face_em[f], ep = kp.m.face_ep[f];
+  double lm[DIM + 1], lp[DIM + 1];
+  for (int k = 0; k <= DIM; ++k) lm[k] = lp[k] = 0.0;
+  for (int k = 0; k < DIM; ++k) {
+    lm[kp.m.fperm_m[f * DIM + k]] = c_rules.fq_mu[q][k];
+    lp[kp.m.fperm_p[f * DIM + k]] = c_rules.fq_mu[q][k];
+  }
+  double phm[NN], php[NN];
+  Lag<DIM, ORDER>::phi(lm, phm);
+  Lag<DIM, ORDER>::phi(lp, php);
+  double acc = 0.0;
+  for (int x = 0; x < DIM; ++x) {
+    double um = 0.0, up = 0.0;
+    for (int a = 0; a < NN; ++a) {
+      um += phm[a] * u[(int64_t)em * BU + a * DIM + x];
+      up += php[a] * u[(int64_t)ep * BU + a * DIM + x];
+    }
+    acc += (up - um) * kp.m.normal[f * DIM + x];
+  }
+  w[t] = acc;
+}
+
+// max of w over the face points of fluid faces (single workgroup)
+__global__ void k_wmax(KParams kp, const double *__restrict__ w, double *out) {
+  __shared__ double sm[256];
+  const int nq = kp.s.nqf;
+  double mx = -1e300;
+  for (int64_t t = threadIdx.x; t < kp.s.n_act * nq; t += blockDim.x) {
+    const int32_t f = kp.m.act_face[t / nq];
+    mx = fmax(mx, w[(int64_t)f * nq + t % nq]);
+  }
+  sm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+template <int DIM, int ORDER>
+static hipError_t assemble_impl(const KParams &kp, const double *u, const double *p,
+                                const double *w_old, double *A, double *R, double *Bs,
+                                double *Cs, double *D, hipStream_t st) {
+  constexpr int NT = (Cfg<DIM, ORDER>::BU >= 24) ? 128 : 64;
+  if (kp.s.ne) hipLaunchKernelGGL((k_assemble<DIM, ORDER, NT>), dim3((unsigned)kp.s.ne), dim3(NT), 0, st,
+                                  kp, u, p, w_old, A, R, Bs, Cs);
+  if (kp.s.n_p)
+    hipLaunchKernelGGL((k_fluid_rows<DIM, ORDER>), dim3((unsigned)((kp.s.n_p + 63) / 64)), dim3(64), 0,
+                       st, kp, u, p, w_old, R, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(const KParams &kp, const double *u, const double *p,
+                           const double *w_old, double *A, double *R, double *Bs, double *Cs,
+                           double *D, hipStream_t st) {
+  const int d = kp.s.dim, o = kp.s.order;
+  if (d == 2 && o == 1) return assemble_impl<2, 1>(kp, u, p, w_old, A, R, Bs, Cs, D, st);
+  if (d == 2 && o == 2) return assemble_impl<2, 2>(kp, u, p, w_old, A, R, Bs, Cs, D, st);
+  if (d == 3 && o == 1) return assemble_impl<3, 1>(kp, u, p, w_old, A, R, Bs, Cs, D, st);
+  if (d == 3 && o == 2) return assemble_impl<3, 2>(kp, u, p, w_old, A, R, Bs, Cs, D, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_opening(const KParams &kp, const double *u, double *w, hipStream_t st) {
+  const int64_t n = kp.s.nf * kp.s.nqf;
+  if (!n) return hipSuccess;
+  dim3 g((unsigned)((n + 127) / 128)), b(128);
+  const int d = kp.s.dim, o = kp.s.order;
+  if (d == 2 && o == 1) hipLaunchKernelGGL((k_opening<2, 1>), g, b, 0, st, kp, u, w);
+  else if (d == 2 && o == 2) hipLaunchKernelGGL((k_opening<2, 2>), g, b, 0, st, kp, u, w);
+  else if (d == 3 && o == 1) hipLaunchKernelGGL((k_opening<3, 1>), g, b, 0, st, kp, u, w);
+  else hipLaunchKernelGGL((k_opening<3, 2>), g, b, 0, st, kp, u, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_wmax(const KParams &kp, const double *w, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_wmax, dim3(1), dim3(256), 0, st, kp, w, out);
+  return hipGetLastError();
+}
+
+}  // namespace hf

@@ -1,0 +1,52 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol declared
+in include/hf.h, and its host-side argument handling works without a GPU
+(no compute calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hf.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    decl = r"^\s*(?:hf_status|void|const char)\s*\*?\s*(hf_[a-z_0-9]+)\s*\("
+    return sorted(set(re.findall(decl, txt, flags=re.MULTILINE)))
+
+
+def test_header_and_binding_agree():
+    import paper_1911_10275_amd as hf
+    assert sorted(hf.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1911_10275_amd as hf
+    lib = hf.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_default_options_and_null_handling():
+    import paper_1911_10275_amd as hf
+    lib = hf.load()
+    o = hf.default_options()
+    assert o.gmres_m == 60 and o.rtol == 1e-10 and o.precision == hf.HF_FP64
+    assert o.rtol_inner == 1e-2 and o.b_stab == 10.0 and o.newton_maxit == 25
+    assert lib.hf_create(C.byref(o), None) == hf.HF_EINVAL
+    assert lib.hf_assemble(None, None) == hf.HF_EINVAL
+    assert lib.hf_finalize(None) == hf.HF_EINVAL
+    assert lib.hf_last_error(None) == b"null context"
+    lib.hf_destroy(None)
+
+
+def test_create_without_gpu_fails_cleanly():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    import paper_1911_10275_amd as hf
+    with pytest.raises(hf.HFError) as ei:
+        hf.Context()
+    assert ei.value.status in (hf.HF_EDEVICE, hf.HF_EINVAL)

@@ -1,0 +1,210 @@
+"""GPU parity of the HIP Newton-step path against the FP64 CPU oracle.
+
+Every call goes through the C ABI (libhf.so via its ctypes binding).  Sizes
+are chosen so that the oracle finishes in seconds while the kernels still
+see several tiles and a ragged tail (element counts not divisible by the
+rows per workgroup of the block product, vector lengths spanning several
+reduction blocks).
+
+Tolerances: assembled R and J blocks 1e-12 relative to the largest entry of
+the compared array (same formulas, different summation order); Jacobian
+products 1e-13; converged Newton states 1e-8 in u, p and the opening w
+(the build's parity gate); every linear solve reaches a true relative
+residual of 1e-10.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import assemble as asm
+from oracle import newton, solve
+from oracle.newton import Case
+
+pytestmark = pytest.mark.gpu
+
+hf = pytest.importorskip("paper_1911_10275_amd")
+
+SMALL = {
+    "2d_p1_n9": lambda: synth.kgd_small(9, 1, steps=3),
+    "2d_p2_n7": lambda: synth.kgd_small(7, 2, steps=2),
+    "3d_p1_n4": lambda: synth.penny_small(4, 1, steps=2),
+    "3d_p2_n3": lambda: synth.penny_problem(3, 2, 21, synth.Material(1.0, 0.2, 1e-3, 1e-4, 1e-3, 1.0),
+                                            1e-4, radius=0.34, ring_width=0.2, load_steps=2,
+                                            name="penny_n3_p2"),
+}
+
+
+def _pair(prob):
+    case = Case.from_problem(prob)
+    ctx = hf.context_for_problem(prob)
+    fv, fe, nq = ctx.faces()
+    # the canonical face order and labels are part of the boundary contract
+    assert fv.shape == case.mesh.face_vert.shape
+    np.testing.assert_array_equal(fv, case.mesh.face_vert)
+    np.testing.assert_array_equal(fe[:, 0], case.mesh.face_em)
+    np.testing.assert_array_equal(fe[:, 1], case.mesh.face_ep)
+    assert nq == case.mesh.nq
+    keys = ctx.pnodes()
+    ok = [(k[1], -1) if k[0] == "v" else (k[1], k[2]) for k in case.itf.p_keys]
+    np.testing.assert_array_equal(keys, np.array(ok, dtype=np.int64).reshape(-1, 2))
+    return case, ctx
+
+
+def _random_state(case, seed):
+    m = case.mesh
+    rng = np.random.default_rng(seed)
+    u = rng.normal(size=m.n_u) * 0.05
+    p = rng.uniform(0.0, 2e-3, case.itf.n_p)
+    wo = rng.uniform(0.0, 1e-2, (m.nf, m.nq))
+    return u, p, wo
+
+
+def _rel(a, b):
+    s = max(np.abs(a).max(), np.abs(b).max(), 1e-300)
+    return np.abs(a - b).max() / s
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_assembly_parity(name):
+    prob = SMALL[name]()
+    case, ctx = _pair(prob)
+    m = case.mesh
+    u, p, wo = _random_state(case, 3)
+    ctx.set_state(u, p, wo)
+    rn = ctx.assemble()
+    s_p = newton.fluid_scale(case, wo)
+    S = asm.assemble(m, case.itf, case.prm, u, p, wo, s_p, case.src_pnode, case.src_q0)
+    ru, rp = ctx.residual()
+    assert _rel(ru, S.R_u) < 1e-12
+    if case.itf.n_p:
+        assert _rel(rp, S.R_p) < 1e-12
+    assert rn == pytest.approx(np.linalg.norm(S.R), rel=1e-12)
+    # every block row of A
+    cols, blocks = ctx.block_rows(np.arange(m.ne))
+    ref = {}
+    for e in range(m.ne):
+        ref[(e, e)] = S.A_diag[e]
+    for f in range(m.nf):
+        ref[(m.face_em[f], m.face_ep[f])] = S.A_mp[f]
+        ref[(m.face_ep[f], m.face_em[f])] = S.A_pm[f]
+    scale = max(np.abs(b).max() for b in ref.values())
+    err = 0.0
+    for e in range(m.ne):
+        for s in range(cols.shape[1]):
+            c = cols[e, s]
+            if c < 0:
+                assert not np.any(blocks[e, s])
+                continue
+            err = max(err, np.abs(blocks[e, s] - ref[(e, c)]).max())
+    assert err / scale < 1e-12
+    B, Cm, D = ctx.coupling()
+    if case.itf.n_p:
+        assert _rel(B, S.B.toarray()) < 1e-12
+        assert _rel(Cm, S.C.toarray()) < 1e-12
+        assert _rel(D, S.D.toarray()) < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_jacobian_product_parity(name):
+    torch = pytest.importorskip("torch")
+    prob = SMALL[name]()
+    case, ctx = _pair(prob)
+    u, p, wo = _random_state(case, 4)
+    ctx.set_state(u, p, wo)
+    ctx.assemble()
+    S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo),
+                     case.src_pnode, case.src_q0)
+    op = solve.Operator(case.mesh, S)
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=op.n)
+    xd = torch.tensor(x, device="cuda")
+    yd = torch.empty_like(xd)
+    torch.cuda.synchronize()
+    ctx.apply_jacobian(xd.data_ptr(), yd.data_ptr())
+    torch.cuda.synchronize()
+    assert _rel(yd.cpu().numpy(), op(x)) < 1e-13
+    ctx.close()
+
+
+def _gpu_run(ctx, case, steps, precision):
+    ctx.set_options(precision=precision)
+    st0 = newton.initial_state(case)
+    ctx.set_state(st0.u, st0.p, st0.w_old)
+    out = []
+    for _ in range(steps):
+        ns = ctx.newton_solve()
+        assert ns.converged
+        assert ns.lin.true_relres <= 1e-10
+        ctx.end_load_step()
+        out.append((ctx.get_state(), ns))
+    return out
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("precision", [hf.HF_FP64, hf.HF_FP32_IR], ids=["fp64", "fp32ir"])
+def test_newton_load_steps_parity(name, precision):
+    """Converged states of every given-length load step match the oracle to
+    1e-8 (u, p, and the opening w at every face point)."""
+    prob = SMALL[name]()
+    case, ctx = _pair(prob)
+    steps = prob.load_steps
+    ref = newton.run(case, steps, solver="gmres")
+    assert all(ns.converged for _, ns in ref)
+    got = _gpu_run(ctx, case, steps, precision)
+    for (st, ns_ref), ((u, p, w, wo), ns) in zip(ref, got):
+        assert np.linalg.norm(u - st.u) <= 1e-8 * np.linalg.norm(st.u)
+        if case.itf.n_p:
+            assert np.linalg.norm(p - st.p) <= 1e-8 * np.linalg.norm(st.p)
+        fa = case.itf.active_faces
+        assert np.linalg.norm(wo[fa] - st.w_old[fa]) <= 1e-8 * np.linalg.norm(st.w_old[fa])
+        assert np.linalg.norm(w - wo) <= 1e-14 * max(np.linalg.norm(wo), 1e-300)
+        assert abs(ns.iterations - ns_ref.iterations) <= 1
+    ctx.close()
+
+
+def test_determinism_bitwise():
+    prob = SMALL["3d_p2_n3"]()
+    case, ctx = _pair(prob)
+    u, p, wo = _random_state(case, 6)
+    res = []
+    for _ in range(2):
+        ctx.set_state(u, p, wo)
+        ctx.assemble()
+        st = ctx.solve()
+        ru, rp = ctx.residual()
+        du, dp = ctx.increment()
+        res.append((ru, rp, du, dp, st.gmres_iters))
+    for a, b in zip(res[0][:4], res[1][:4]):
+        np.testing.assert_array_equal(a, b)
+    assert res[0][4] == res[1][4]
+    ctx.close()
+
+
+def test_failure_paths():
+    prob = SMALL["2d_p1_n9"]()
+    case, ctx = _pair(prob)
+    st0 = newton.initial_state(case)
+    # call order
+    with pytest.raises(hf.HFError) as ei:
+        ctx.assemble()
+    assert ei.value.status == hf.HF_ESTATE
+    # non-finite state
+    bad = st0.u.copy()
+    bad[3] = np.nan
+    with pytest.raises(hf.HFError) as ei:
+        ctx.set_state(bad, st0.p, st0.w_old)
+    assert ei.value.status == hf.HF_ENONFINITE
+    # iteration cap: GMRES stops at 1 iteration, the state stays unchanged
+    ctx.set_state(st0.u, st0.p, st0.w_old)
+    ctx.set_options(gmres_maxit=1)
+    with pytest.raises(hf.HFError) as ei:
+        ctx.newton_solve()
+    assert ei.value.status == hf.HF_ENOCONV
+    u, p, _, _ = ctx.get_state()
+    np.testing.assert_array_equal(u, st0.u)
+    np.testing.assert_array_equal(p, st0.p)
+    ctx.set_options(gmres_maxit=20000)
+    ns = ctx.newton_solve()
+    assert ns.converged
+    ctx.close()
