@@ -200,6 +200,18 @@ hf_status hf_newton_step(hf_ctx *ctx, hf_newton_stats *stats);
 hf_status hf_newton_solve(hf_ctx *ctx, hf_newton_stats *stats);
 /* End of a given-length load step: w_old <- w(u), s_p recomputed. */
 hf_status hf_end_load_step(hf_ctx *ctx);
+/* Starting state of the first load step: the uniform-pressure elastic
+   predictor.  With the pressure held fixed at 1 the displacement rows are
+   solved for u1 (one linear solve, same solver options); V1 = crack volume
+   of u1 over the fluid faces; then p0 = (sum Q0) dt / V1 and the state
+   becomes u = p0 u1, p = p0 on every pressure node (w_old unchanged).  This
+   gives the opening and pressure of a crack that stores the first step's
+   injected volume under uniform pressure, so the cubic-law conductivity is
+   not degenerate at the first Newton iterate (the paper starts the same
+   test from uniform pressure and opening, Sec. "Verification of the
+   fully-coupled algorithm").  *p0_out (nullable) = p0.  No-op without
+   pressure nodes or injection. */
+hf_status hf_initial_guess(hf_ctx *ctx, double *p0_out);
 
 /* ---- inspection hooks (tests, benchmarks) ---- */
 /* R_u (n_u), R_p (n_p) of the last hf_assemble. */

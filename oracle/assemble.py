@@ -134,7 +134,7 @@ class System:
 def assemble(mesh: Mesh, itf: Interfaces, prm: Params, u: np.ndarray, p: np.ndarray,
              w_old: np.ndarray, s_p: float, src_pnode, src_q0, ubar: Optional[np.ndarray] = None,
              jacobian: bool = True, faces: Optional[np.ndarray] = None,
-             face_chunk: int = 4096) -> System:
+             elements: Optional[np.ndarray] = None, face_chunk: int = 4096) -> System:
     """Residual (and Jacobian) at the state (u, p).
 
     u: (n_u,) element-major DG displacement copies, index (e*nn + a)*d + i
@@ -142,6 +142,8 @@ def assemble(mesh: Mesh, itf: Interfaces, prm: Params, u: np.ndarray, p: np.ndar
     w_old: (nf, nq) opening of the previous load step at face points
     faces: optional subset of interior faces to include (default all); used
         to evaluate selected element rows.
+    elements: optional subset of elements whose bulk term is included
+        (default all; the others get a zero bulk term).
     """
     m = mesh
     d, nn, bu = m.dim, m.nn, m.bu
@@ -150,19 +152,23 @@ def assemble(mesh: Mesh, itf: Interfaces, prm: Params, u: np.ndarray, p: np.ndar
     n_p = itf.n_p
 
     # ---------------- bulk term: sum_e int_e C eps(u) : eps(v) ------------------
+    E = np.arange(m.ne) if elements is None else np.asarray(elements, dtype=np.int64)
     lq = shapes.ref_to_bary(m.vq_pts)
     dphi = shapes.dphi_dlam(lq, d, m.order)                     # (nqv, nn, d+1)
-    gphi = np.einsum("qak,ekx->eqax", dphi, m.grad_lam)          # (ne, nqv, nn, d)
-    wdet = m.vq_w[None, :] * np.abs(m.detJ)[:, None]            # (ne, nqv)
-    grad_u = np.einsum("eai,eqax->eqix", ue, gphi)
+    gphi = np.einsum("qak,ekx->eqax", dphi, m.grad_lam[E])       # (nE, nqv, nn, d)
+    wdet = m.vq_w[None, :] * np.abs(m.detJ[E])[:, None]         # (nE, nqv)
+    grad_u = np.einsum("eai,eqax->eqix", ue[E], gphi)
     sig = _stress(grad_u, lam, G)
-    R_u = np.einsum("eq,eqix,eqax->eai", wdet, sig, gphi).reshape(-1)
+    R_u = np.zeros((m.ne, nn, d))
+    R_u[E] = np.einsum("eq,eqix,eqax->eai", wdet, sig, gphi)
+    R_u = R_u.reshape(-1)
     if jacobian:
         eye = np.eye(d)
         K = (lam * np.einsum("eq,eqai,eqbj->eaibj", wdet, gphi, gphi)
              + G * np.einsum("eq,eqax,eqbx,ij->eaibj", wdet, gphi, gphi, eye)
              + G * np.einsum("eq,eqaj,eqbi->eaibj", wdet, gphi, gphi))
-        A_diag = K.reshape(m.ne, bu, bu).copy()
+        A_diag = np.zeros((m.ne, bu, bu))
+        A_diag[E] = K.reshape(len(E), bu, bu)
         A_mp = np.zeros((m.nf, bu, bu))
         A_pm = np.zeros((m.nf, bu, bu))
     R_p = np.zeros(n_p)

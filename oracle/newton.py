@@ -81,11 +81,30 @@ def fluid_scale(case: Case, w_old: np.ndarray) -> float:
     return 12.0 * case.prm.mu * (L / w_ref) ** 3
 
 
-def initial_state(case: Case) -> State:
+def initial_state(case: Case, predictor: bool = False) -> State:
+    """Start of the load sequence: w_old = 0 and either u = 0, p = sigma_c,
+    or (predictor) the uniform-pressure elastic state: with the pressure held
+    at 1 on every node the displacement equations give u1 (direct sparse
+    solve), V1 = crack volume of u1 on the fluid faces, p0 = sum(Q0) dt / V1,
+    u = p0 u1, p = p0.  The paper starts its given-length test from uniform
+    pressure and opening; the predictor is the elastically compatible form
+    of such a start (a reading)."""
     m = case.mesh
     w0 = np.zeros((m.nf, m.nq))
-    return State(u=np.zeros(m.n_u), p=np.full(case.itf.n_p, case.prm.sigma_c), w_old=w0,
-                 s_p=fluid_scale(case, w0))
+    st = State(u=np.zeros(m.n_u), p=np.full(case.itf.n_p, case.prm.sigma_c), w_old=w0,
+               s_p=fluid_scale(case, w0))
+    q = float(np.sum(case.src_q0))
+    if not predictor or case.itf.n_p == 0 or q <= 0.0:
+        return st
+    import scipy.sparse.linalg as spla
+    from .assemble import bsr_A
+    S = assemble(m, case.itf, case.prm, np.zeros(m.n_u), np.ones(case.itf.n_p), w0, st.s_p,
+                 case.src_pnode, case.src_q0)
+    u1 = spla.spsolve(bsr_A(m, S).tocsc(), -S.R_u)
+    fa = case.itf.active_faces
+    V1 = float(np.sum(m.fq_w[None, :] * m.area[fa][:, None] * opening(m, u1)[fa]))
+    p0 = q * case.prm.dt / V1
+    return State(u=p0 * u1, p=np.full(case.itf.n_p, p0), w_old=w0, s_p=st.s_p)
 
 
 @dataclasses.dataclass
@@ -156,10 +175,10 @@ def end_load_step(case: Case, state: State) -> State:
     return State(state.u, state.p, w, fluid_scale(case, w))
 
 
-def run(case: Case, steps: int, **kw):
+def run(case: Case, steps: int, predictor: bool = False, **kw):
     """Given-length load-step loop; returns the list of converged states and
     Newton statistics."""
-    st = initial_state(case)
+    st = initial_state(case, predictor)
     out = []
     for _ in range(steps):
         st, ns = newton_solve(case, st, **kw)

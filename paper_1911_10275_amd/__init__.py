@@ -30,7 +30,7 @@ EXPORTS = [
     "hf_upload_mesh", "hf_get_faces", "hf_upload_interfaces", "hf_set_material",
     "hf_set_injection", "hf_finalize", "hf_get_sizes", "hf_get_pnodes", "hf_set_state",
     "hf_get_state", "hf_set_state_device", "hf_get_state_device", "hf_assemble", "hf_solve",
-    "hf_newton_step", "hf_newton_solve", "hf_end_load_step", "hf_get_residual",
+    "hf_newton_step", "hf_newton_solve", "hf_end_load_step", "hf_initial_guess", "hf_get_residual",
     "hf_get_block_rows", "hf_get_coupling", "hf_get_increment", "hf_apply_jacobian",
     "hf_get_profile", "hf_reset_profile",
 ]
@@ -123,6 +123,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hf_newton_step": (C.c_int, [vp, P(NewtonStats)]),
         "hf_newton_solve": (C.c_int, [vp, P(NewtonStats)]),
         "hf_end_load_step": (C.c_int, [vp]),
+        "hf_initial_guess": (C.c_int, [vp, P(C.c_double)]),
         "hf_get_residual": (C.c_int, [vp, C.c_int32, vp, vp]),
         "hf_get_block_rows": (C.c_int, [vp, C.c_int32, C.c_int64, vp, vp, vp]),
         "hf_get_coupling": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
@@ -301,6 +302,12 @@ class Context:
 
     def end_load_step(self):
         self._check(self.lib.hf_end_load_step(self.h), "hf_end_load_step")
+
+    def initial_guess(self) -> float:
+        """Uniform-pressure elastic predictor for the first load step; returns p0."""
+        p0 = C.c_double()
+        self._check(self.lib.hf_initial_guess(self.h, C.byref(p0)), "hf_initial_guess")
+        return p0.value
 
     # -- inspection ------------------------------------------------------------------
     def residual(self):

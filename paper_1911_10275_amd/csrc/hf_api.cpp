@@ -7,6 +7,8 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -76,6 +78,7 @@ KParams kparams(const hf_ctx *ctx) {
   kp.dt = ctx->mat.dt;
   kp.b_stab = ctx->opt.b_stab;
   kp.s_p = ctx->s_p;
+  kp.freeze_p = ctx->freeze_p;
   return kp;
 }
 
@@ -876,6 +879,15 @@ static hf_status vnorm(hf_ctx *ctx, const T *x, int64_t n, double &out) {
   return HF_OK;
 }
 
+static bool trace_on() {
+  static int on = -1;
+  if (on < 0) {
+    const char *e = std::getenv("HF_TRACE");
+    on = (e && *e && *e != '0') ? 1 : 0;
+  }
+  return on == 1;
+}
+
 // Right-preconditioned restarted GMRES(m) on J x = b in precision T with
 // classical Gram-Schmidt applied twice.  x starts at 0.  A cycle ends when the
 // recursive residual estimate reaches rtol ||b|| or after m steps; with
@@ -974,6 +986,9 @@ static hf_status gmres(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T *
     HIPCHK(launch_sub_t<T>(b, ws.w, ws.r, N, ctx->stream));
     TRY(vnorm<T>(ctx, ws.r, N, beta));
     if (!std::isfinite(beta)) return fail(ctx, HF_ENONFINITE, "non-finite residual in GMRES");
+    if (trace_on())
+      std::fprintf(stderr, "hf gmres(%s): it %d restart %d estimate %.3e true %.3e\n",
+                   sizeof(T) == 8 ? "fp64" : "fp32", iters, restarts, est / bnorm, beta / bnorm);
   }
 }
 
@@ -1158,6 +1173,40 @@ extern "C" hf_status hf_newton_solve(hf_ctx *ctx, hf_newton_stats *stats) {
     if (st == HF_OK) st = fail(ctx, HF_ENOCONV, "Newton did not converge within newton_maxit");
     return st;
   }
+  return HF_OK;
+}
+
+extern "C" hf_status hf_initial_guess(hf_ctx *ctx, double *p0_out) {
+  TRY(check_ctx(ctx, 3));
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  const Sizes &s = ctx->s;
+  double q_total = 0.0;
+  for (double q : ctx->h.src_q0) q_total += q;
+  if (!s.n_p || q_total <= 0.0) {
+    if (p0_out) *p0_out = 0.0;
+    return HF_OK;  // nothing to predict: keep the state
+  }
+  // unit-pressure elastic response u1 with the pressure held fixed
+  HIPCHK(hipMemsetAsync(ctx->xs, 0, s.n_u * sizeof(double), ctx->stream));
+  HIPCHK(launch_fill(1.0, ctx->xs + s.n_u, s.n_p, ctx->stream));
+  ctx->freeze_p = 1;
+  hf_status st = do_assemble(ctx, nullptr);
+  if (st == HF_OK) st = do_solve(ctx, nullptr);
+  ctx->freeze_p = 0;
+  if (st != HF_OK) return st;
+  HIPCHK(hipMemcpyAsync(ctx->xs, ctx->dx, s.n_u * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(launch_set_rules(ctx->rules, ctx->stream));
+  HIPCHK(launch_fluid_volume(kparams(ctx), ctx->xs, ctx->partial, ctx->red, ctx->stream));
+  TRY(sync_read(ctx, 1));
+  const double V1 = ctx->red_h[0];
+  if (!(V1 > 0.0) || !std::isfinite(V1))
+    return fail(ctx, HF_ENONFINITE, "unit-pressure crack volume is not positive");
+  const double p0 = q_total * ctx->mat.dt / V1;
+  HIPCHK(launch_axpby(0.0, ctx->dx, p0, ctx->xs, s.n_u, ctx->stream));  // u0 = p0 u1
+  HIPCHK(launch_fill(p0, ctx->xs + s.n_u, s.n_p, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (p0_out) *p0_out = p0;
+  ctx->stage = 3;
   return HF_OK;
 }
 

@@ -106,6 +106,7 @@ struct KParams {
   Sizes s;
   DevMesh m;
   double lam, G, sigma_c, delta_c, mu, dt, b_stab, s_p;
+  int freeze_p;  // 1: pressure held fixed (fluid rows become p-rows of the identity)
 };
 
 // ---------------------------------------------------------------------------
@@ -160,6 +161,7 @@ struct hf_ctx {
   hf::DevMesh m;
   hf::RuleTables rules{};
   double s_p = 1.0;
+  int freeze_p = 0;
   std::vector<void *> allocs;   // every device allocation, released by hf_destroy
   // state: xs = [u; p]
   double *xs = nullptr, *xs_save = nullptr, *xs_start = nullptr, *w_old = nullptr, *w_tmp = nullptr;
@@ -197,6 +199,9 @@ hipError_t launch_assemble(const KParams &kp, const double *u, const double *p,
                            double *Cs, double *D, hipStream_t st);
 hipError_t launch_opening(const KParams &kp, const double *u, double *w, hipStream_t st);
 hipError_t launch_wmax(const KParams &kp, const double *w, double *out, hipStream_t st);
+hipError_t launch_fluid_volume(const KParams &kp, const double *u, double *partial, double *out,
+                               hipStream_t st);
+hipError_t launch_fill(double v, double *x, int64_t n, hipStream_t st);
 hipError_t launch_blockinv(const KParams &kp, const double *A, double *inv, float *inv32,
                            int *flag, hipStream_t st);
 hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,

@@ -477,7 +477,7 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const double *__res
             cv += s_W[q] * s_fc[q][k] * sgE * s_phE[q][a] * s_n[i];
           }
           Bs[(int64_t)ix * BU + r] += bv;
-          Cs[(int64_t)ix * BU + r] += cv;
+          if (!kp.freeze_p) Cs[(int64_t)ix * BU + r] += cv;
         }
       }
     }
@@ -514,6 +514,11 @@ __global__ void k_fluid_rows(KParams kp, const double *__restrict__ u,
   if (i >= np) return;
   double *Drow = D + i * np;
   for (int64_t j = 0; j < np; ++j) Drow[j] = 0.0;
+  if (kp.freeze_p) {  // pressure held at its current value: dp = 0
+    Drow[i] = 1.0;
+    R[kp.s.n_u + i] = 0.0;
+    return;
+  }
   double Ri = 0.0;
   for (int32_t t = kp.m.pf_ptr[i]; t < kp.m.pf_ptr[i + 1]; ++t) {
     const int32_t fa = kp.m.pf_fa[t], kk = kp.m.pf_k[t];
@@ -611,6 +616,50 @@ __global__ void k_opening(KParams kp, const double *__restrict__ u, double *__re
   w[t] = acc;
 }
 
+// crack volume sum_{fluid faces} sum_q W_q w_q: block partials, reduced by k_reduce
+template <int DIM, int ORDER>
+__global__ __launch_bounds__(256) void k_fluid_volume(KParams kp, const double *__restrict__ u,
+                                                      double *__restrict__ partial) {
+  using C = Cfg<DIM, ORDER>;
+  constexpr int NN = C::NN, BU = C::BU, NQF = C::NQF;
+  __shared__ double sm[256];
+  double acc = 0.0;
+  const int64_t n = kp.s.n_act * NQF;
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t t0 = blockIdx.x * chunk, t1 = min(n, t0 + chunk);
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
+    const int64_t f = kp.m.act_face[t / NQF];
+    const int q = (int)(t % NQF);
+    const int32_t em = kp.m.face_em[f], ep = kp.m.face_ep[f];
+    double lm[DIM + 1], lp[DIM + 1];
+    for (int k = 0; k <= DIM; ++k) lm[k] = lp[k] = 0.0;
+    for (int k = 0; k < DIM; ++k) {
+      lm[kp.m.fperm_m[f * DIM + k]] = c_rules.fq_mu[q][k];
+      lp[kp.m.fperm_p[f * DIM + k]] = c_rules.fq_mu[q][k];
+    }
+    double phm[NN], php[NN];
+    Lag<DIM, ORDER>::phi(lm, phm);
+    Lag<DIM, ORDER>::phi(lp, php);
+    double w = 0.0;
+    for (int x = 0; x < DIM; ++x) {
+      double um = 0.0, up = 0.0;
+      for (int a = 0; a < NN; ++a) {
+        um += phm[a] * u[(int64_t)em * BU + a * DIM + x];
+        up += php[a] * u[(int64_t)ep * BU + a * DIM + x];
+      }
+      w += (up - um) * kp.m.normal[f * DIM + x];
+    }
+    acc += c_rules.fq_w[q] * kp.m.area[f] * w;
+  }
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
+}
+
 // max of w over the face points of fluid faces (single workgroup)
 __global__ void k_wmax(KParams kp, const double *__restrict__ w, double *out) {
   __shared__ double sm[256];
@@ -663,6 +712,22 @@ hipError_t launch_opening(const KParams &kp, const double *u, double *w, hipStre
   else if (d == 3 && o == 1) hipLaunchKernelGGL((k_opening<3, 1>), g, b, 0, st, kp, u, w);
   else hipLaunchKernelGGL((k_opening<3, 2>), g, b, 0, st, kp, u, w);
   return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double *partial, int nblk, int k, double *out,
+                                  hipStream_t st);
+
+hipError_t launch_fluid_volume(const KParams &kp, const double *u, double *partial, double *out,
+                               hipStream_t st) {
+  const int nb = 64;
+  const int d = kp.s.dim, o = kp.s.order;
+  if (d == 2 && o == 1) hipLaunchKernelGGL((k_fluid_volume<2, 1>), dim3(nb), dim3(256), 0, st, kp, u, partial);
+  else if (d == 2 && o == 2) hipLaunchKernelGGL((k_fluid_volume<2, 2>), dim3(nb), dim3(256), 0, st, kp, u, partial);
+  else if (d == 3 && o == 1) hipLaunchKernelGGL((k_fluid_volume<3, 1>), dim3(nb), dim3(256), 0, st, kp, u, partial);
+  else hipLaunchKernelGGL((k_fluid_volume<3, 2>), dim3(nb), dim3(256), 0, st, kp, u, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_partials(partial, nb, 1, out, st);
 }
 
 hipError_t launch_wmax(const KParams &kp, const double *w, double *out, hipStream_t st) {

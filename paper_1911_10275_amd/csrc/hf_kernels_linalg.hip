@@ -504,6 +504,25 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double *__restrict
   if (threadIdx.x == 0) out[i] = sm[0];
 }
 
+hipError_t launch_reduce_partials(const double *partial, int nblk, int k, double *out,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(k), dim3(kRedThreads), 0, st, partial, nblk, k, out);
+  return hipGetLastError();
+}
+
+__global__ void k_fill(double v, double *__restrict__ x, int64_t n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    x[t] = v;
+}
+hipError_t launch_fill(double v, double *x, int64_t n, hipStream_t st) {
+  if (!n) return hipSuccess;
+  int64_t g = (n + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(256), 0, st, v, x, n);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_mdot(const T *V, int64_t ldv, int k, const T *w, int64_t n, double *partial,
                        double *out, hipStream_t st) {

@@ -127,10 +127,12 @@ def test_jacobian_product_parity(name):
     ctx.close()
 
 
-def _gpu_run(ctx, case, steps, precision):
+def _gpu_run(ctx, case, steps, precision, predictor=False):
     ctx.set_options(precision=precision)
     st0 = newton.initial_state(case)
     ctx.set_state(st0.u, st0.p, st0.w_old)
+    if predictor:
+        ctx.initial_guess()
     out = []
     for _ in range(steps):
         ns = ctx.newton_solve()
@@ -160,6 +162,28 @@ def test_newton_load_steps_parity(name, precision):
         assert np.linalg.norm(wo[fa] - st.w_old[fa]) <= 1e-8 * np.linalg.norm(st.w_old[fa])
         assert np.linalg.norm(w - wo) <= 1e-14 * max(np.linalg.norm(wo), 1e-300)
         assert abs(ns.iterations - ns_ref.iterations) <= 1
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["2d_p1_n9", "3d_p2_n3"])
+def test_predictor_and_load_steps_parity(name):
+    """The uniform-pressure elastic predictor (pressure and crack volume) and
+    the load steps that start from it match the oracle."""
+    prob = SMALL[name]()
+    case, ctx = _pair(prob)
+    ref0 = newton.initial_state(case, predictor=True)
+    st0 = newton.initial_state(case)
+    ctx.set_state(st0.u, st0.p, st0.w_old)
+    p0 = ctx.initial_guess()
+    u, p, _, _ = ctx.get_state()
+    assert p0 == pytest.approx(ref0.p[0], rel=1e-8)
+    np.testing.assert_allclose(p, ref0.p, rtol=1e-8)
+    assert np.linalg.norm(u - ref0.u) <= 1e-7 * np.linalg.norm(ref0.u)
+    ref = newton.run(case, prob.load_steps, predictor=True)
+    got = _gpu_run(ctx, case, prob.load_steps, hf.HF_FP64, predictor=True)
+    for (st, _), ((u, p, w, wo), ns) in zip(ref, got):
+        assert np.linalg.norm(u - st.u) <= 1e-8 * np.linalg.norm(st.u)
+        assert np.linalg.norm(p - st.p) <= 1e-8 * np.linalg.norm(st.p)
     ctx.close()
 
 
