@@ -117,6 +117,7 @@ def main():
     ap.add_argument("--workload", type=int, default=2, help="synthetic workload index (1, 2, 3, 5)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ir", action="store_true", help="skip the FP32-IR comparison")
+    ap.add_argument("--gmres-m", type=int, default=60, help="GMRES restart length")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
@@ -131,7 +132,7 @@ def main():
     print(f"bench: workload {prob.name}: {prob.n_elem} elements, {prob.n_udof} displacement DOF",
           file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream().cuda_stream
-    ctx = hf.context_for_problem(prob, device=0, stream=stream)
+    ctx = hf.context_for_problem(prob, device=0, stream=stream, gmres_m=args.gmres_m)
     sz = ctx.sizes
     N = sz.n_u + sz.n_p
 
@@ -170,7 +171,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": prob.name, "elements": int(sz.n_elem), "dof": int(N),
                    "u_dof": int(sz.n_u), "p_dof": int(sz.n_p), "element": f"P{prob.order}",
-                   "dim": prob.dim, "precision": "fp64", "gmres_m": 60, "rtol": 1e-10},
+                   "dim": prob.dim, "precision": "fp64", "gmres_m": args.gmres_m, "rtol": 1e-10},
         "gmres": {"iters_per_step": float(np.mean(iters64)),
                   "iters_per_s": float(sum(iters64) / dt64),
                   "mdof_iters_per_s": float(sum(iters64) * N / dt64 / 1e6)},

@@ -674,7 +674,10 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
   TRY(dalloc(ctx, &ctx->rhs, N));
   TRY(dalloc(ctx, &ctx->r64, N));
   TRY(dalloc(ctx, &ctx->t64, N));
-  TRY(dalloc(ctx, &ctx->partial, (int64_t)1024 * kMaxKrylov));
+  // reduction partials: the largest of (blocks x outputs) over every reduction
+  const int64_t n_partial = std::max<int64_t>((int64_t)1024 * kMaxKrylov,
+                                              (int64_t)ortho_blocks(N) * (kMaxKrylov + 1));
+  TRY(dalloc(ctx, &ctx->partial, n_partial));
   TRY(dalloc(ctx, &ctx->red, 4 * kMaxKrylov));
   HIPCHK(hipMemsetAsync(ctx->xs, 0, N * sizeof(double), ctx->stream));
   HIPCHK(hipMemsetAsync(ctx->w_old, 0, s.nf * s.nqf * sizeof(double), ctx->stream));
@@ -888,6 +891,16 @@ static bool trace_on() {
   return on == 1;
 }
 
+// HF_REORTH=0 disables the second Gram-Schmidt pass (experiments only)
+static bool reorth_allowed() {
+  static int on = -1;
+  if (on < 0) {
+    const char *e = std::getenv("HF_REORTH");
+    on = (e && *e == '0') ? 0 : 1;
+  }
+  return on == 1;
+}
+
 // Right-preconditioned restarted GMRES(m) on J x = b in precision T with
 // classical Gram-Schmidt applied twice.  x starts at 0.  A cycle ends when the
 // recursive residual estimate reaches rtol ||b|| or after m steps; with
@@ -928,19 +941,30 @@ static hf_status gmres(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T *
       TRY(apply_M<T>(ctx, kp, op, vj, ws.z));
       TRY(apply_J<T>(ctx, kp, op, ws.z, ws.w));
       const int kk = j + 1;
+      // classical Gram-Schmidt with the DGKS re-orthogonalisation test:
+      // h = V^T w, w1 = w - V h; repeat once more when ||w1|| < ||w|| / sqrt(2)
       {
         ProfScope ps(ctx, P_ORTHO);
-        HIPCHK(launch_mdot<T>(ws.V, N, kk, ws.w, N, ctx->partial, ctx->red, ctx->stream));
-        HIPCHK(launch_update_mdot<T>(ws.V, N, kk, ctx->red, ws.w, N, ctx->partial, ctx->red + kk,
-                                     ctx->stream));
-        HIPCHK(launch_update_norm<T>(ws.V, N, kk, ctx->red + kk, ws.w, N, ctx->partial,
-                                     ctx->red + 2 * kk, ctx->stream));
+        HIPCHK(launch_proj<T>(ws.V, N, kk, ws.w, N, ctx->partial, ctx->red, ctx->stream));
+        HIPCHK(launch_orth_update<T>(ws.V, N, kk, ctx->red, ws.w, N, ctx->partial,
+                                     ctx->red + kk + 1, ctx->stream));
       }
-      TRY(sync_read(ctx, 2 * kk + 1));
+      TRY(sync_read(ctx, kk + 2));
       ++iters;
-      const double *hr = ctx->red_h;
-      for (int i = 0; i < kk; ++i) H[i * m + j] = hr[i] + hr[kk + i];
-      const double hn = std::sqrt(hr[2 * kk]);
+      for (int i = 0; i < kk; ++i) H[i * m + j] = ctx->red_h[i];
+      double hn = std::sqrt(ctx->red_h[kk + 1]);
+      if (reorth_allowed() && hn < std::sqrt(0.5 * ctx->red_h[kk])) {
+        {
+          ProfScope ps(ctx, P_ORTHO);
+          HIPCHK(launch_proj<T>(ws.V, N, kk, ws.w, N, ctx->partial, ctx->red, ctx->stream));
+          HIPCHK(launch_orth_update<T>(ws.V, N, kk, ctx->red, ws.w, N, ctx->partial,
+                                       ctx->red + kk + 1, ctx->stream));
+        }
+        TRY(sync_read(ctx, kk + 2));
+        for (int i = 0; i < kk; ++i) H[i * m + j] += ctx->red_h[i];
+        hn = std::sqrt(ctx->red_h[kk + 1]);
+        ++ctx->n_reorth;
+      }
       if (!std::isfinite(hn)) return fail(ctx, HF_ENONFINITE, "non-finite Krylov vector");
       H[kk * m + j] = hn;
       if (hn > 0.0) HIPCHK(launch_scale_copy<T>(ws.w, 1.0 / hn, ws.V + (int64_t)kk * N, N, ctx->stream));
@@ -987,8 +1011,9 @@ static hf_status gmres(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T *
     TRY(vnorm<T>(ctx, ws.r, N, beta));
     if (!std::isfinite(beta)) return fail(ctx, HF_ENONFINITE, "non-finite residual in GMRES");
     if (trace_on())
-      std::fprintf(stderr, "hf gmres(%s): it %d restart %d estimate %.3e true %.3e\n",
-                   sizeof(T) == 8 ? "fp64" : "fp32", iters, restarts, est / bnorm, beta / bnorm);
+      std::fprintf(stderr, "hf gmres(%s): it %d restart %d estimate %.3e true %.3e reorth %lld\n",
+                   sizeof(T) == 8 ? "fp64" : "fp32", iters, restarts, est / bnorm, beta / bnorm,
+                   (long long)ctx->n_reorth);
   }
 }
 

@@ -162,6 +162,7 @@ struct hf_ctx {
   hf::RuleTables rules{};
   double s_p = 1.0;
   int freeze_p = 0;
+  int64_t n_reorth = 0;         // Gram-Schmidt re-orthogonalisations taken (diagnostic)
   std::vector<void *> allocs;   // every device allocation, released by hf_destroy
   // state: xs = [u; p]
   double *xs = nullptr, *xs_save = nullptr, *xs_start = nullptr, *w_old = nullptr, *w_tmp = nullptr;
@@ -216,6 +217,7 @@ hipError_t launch_precond(const KParams &kp, const T *inv, const T *Sinv, const 
                           hipStream_t st);
 // Krylov BLAS (deterministic two-stage reductions)
 int reduce_blocks(int64_t n);
+int ortho_blocks(int64_t n);  // blocks of the Gram-Schmidt passes (partials per output)
 template <typename T>
 hipError_t launch_mdot(const T *V, int64_t ldv, int k, const T *w, int64_t n, double *partial,
                        double *out, hipStream_t st);
@@ -224,6 +226,13 @@ hipError_t launch_update_mdot(const T *V, int64_t ldv, int k, const double *h, T
                               double *partial, double *out, hipStream_t st);
 template <typename T>
 hipError_t launch_update_norm(const T *V, int64_t ldv, int k, const double *h, T *w, int64_t n,
+                              double *partial, double *out, hipStream_t st);
+// Gram-Schmidt passes: out[0..k) = V^T w, out[k] = ||w||^2; and w -= V h, out[0] = ||w||^2
+template <typename T>
+hipError_t launch_proj(const T *V, int64_t ldv, int k, const T *w, int64_t n, double *partial,
+                       double *out, hipStream_t st);
+template <typename T>
+hipError_t launch_orth_update(const T *V, int64_t ldv, int k, const double *h, T *w, int64_t n,
                               double *partial, double *out, hipStream_t st);
 template <typename T>
 hipError_t launch_scale_copy(const T *w, double inv_norm, T *v, int64_t n, hipStream_t st);

@@ -45,6 +45,25 @@ struct Lag {
       for (int k = 0; k < NN - D - 1; ++k) out[D + 1 + k] = 4.0 * lam[ea(k)] * lam[eb(k)];
     }
   }
+  // one basis function and its barycentric derivatives
+  __device__ static double phi_one(int a, const double *lam) {
+    if (K == 1) return lam[a];
+    if (a <= D) return lam[a] * (2.0 * lam[a] - 1.0);
+    const int k = a - D - 1;
+    return 4.0 * lam[ea(k)] * lam[eb(k)];
+  }
+  __device__ static void dphi_one(int a, const double *lam, double *out) {
+    for (int k = 0; k <= D; ++k) out[k] = 0.0;
+    if (K == 1) {
+      out[a] = 1.0;
+    } else if (a <= D) {
+      out[a] = 4.0 * lam[a] - 1.0;
+    } else {
+      const int k = a - D - 1;
+      out[ea(k)] = 4.0 * lam[eb(k)];
+      out[eb(k)] = 4.0 * lam[ea(k)];
+    }
+  }
   // d phi_a / d lam_k
   __device__ static void dphi(const double *lam, double out[][D + 1]) {
 #pragma unroll
@@ -207,7 +226,21 @@ __device__ inline void traction_law(int state, double w, double sigma_c, double 
 }
 
 // ---------------------------------------------------------------------------
-// Element-centric assembly of the displacement rows
+// Element-centric assembly of the displacement rows.
+//
+// Interface blocks.  With c_qa = W_q s_e phi^e_a(x_q) (s_e = -1 on the minus
+// side, +1 on the plus side), the block of test node a / trial node b of side
+// t is
+//   B[a i][b j] = lam/2 n_i M1[a][b][j] + G/2 n_j M1[a][b][i] + G/2 d_ij M2[a][b]
+//               + (b/h) s_t Chat_ij M3[a][b] + s_t n_i n_j M4[a][b]
+// with the moment matrices over the face points
+//   M1[a][b][x] = sum_q c_qa (1-alpha_q) dphi^t_b/dx_x,  M2 = sum_q c_qa (1-alpha_q) grad phi^t_b . n,
+//   M3[a][b]    = sum_q c_qa (1-alpha_q) phi^t_b,         M4 = sum_q c_qa alpha_q T'(w_q) phi^t_b,
+// which is the derivative of the interface traction
+//   tau = (1-alpha)(<sigma(u)> n + (b/h) Chat [[u]]) + alpha T(w) n - beta p n
+// tested with s_e phi^e_a e_i.  Bulk block: K[a i][b j] = lam P[a][b][i][j]
+// + G d_ij tr P[a][b] + G P[a][b][j][i], P[a][b][x][y] = sum_q w_q |det J|
+// dphi_a/dx_x dphi_b/dx_y.
 // ---------------------------------------------------------------------------
 template <int DIM, int ORDER, int NT>
 __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const double *__restrict__ u,
@@ -225,12 +258,15 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const double *__res
 
   __shared__ double s_gl[NF][DIM], s_gln[NF][DIM];
   __shared__ double s_ue[BU], s_un[BU];
-  __shared__ double s_diag[BU * BU];
+  __shared__ double s_diag[BU * BU], s_off[BU * BU];
   __shared__ double s_phE[NQ][NN], s_gphE[NQ][NN][DIM];
   __shared__ double s_phN[NQF][NN], s_gphN[NQF][NN][DIM];
-  __shared__ double s_X[2][NQF][BU][DIM];
+  __shared__ double s_c[NQF][NN];             // W_q s_e phi^e_a
+  __shared__ double s_M[2][NN][NN][DIM + 3];  // M1 (DIM), M2, M3, M4 per trial side
+  __shared__ double s_gu[NQ][DIM][DIM];       // displacement gradient at the points
   __shared__ double s_tau[NQF][DIM], s_W[NQF], s_al[NQF], s_dT[NQF];
   __shared__ double s_eta[NQF][NNF], s_fc[NQF][NNF];
+  __shared__ double s_wq[NQF], s_gp[NQF][DIM - 1];
   __shared__ double s_R[BU];
   __shared__ double s_n[DIM];
   __shared__ double s_ginv[(DIM - 1) * (DIM - 1)];
@@ -241,48 +277,52 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const double *__res
   for (int r = tid; r < BU; r += NT) s_ue[r] = u[e * BU + r];
   __syncthreads();
 
-  // ---- bulk term: K_e and r_e = int sigma(u) : grad(phi) ----------------
+  // ---- bulk term ----------------------------------------------------------
   for (int t = tid; t < NQV * NN; t += NT) {
     const int q = t / NN, a = t % NN;
-    double lamq[DIM + 1], dph[NN][DIM + 1];
+    double lamq[DIM + 1], dph[DIM + 1];
     for (int k = 0; k <= DIM; ++k) lamq[k] = c_rules.vq_lam[q][k];
-    Lag<DIM, ORDER>::dphi(lamq, dph);
+    Lag<DIM, ORDER>::dphi_one(a, lamq, dph);
     for (int x = 0; x < DIM; ++x) {
       double g = 0.0;
-      for (int k = 0; k <= DIM; ++k) g += dph[a][k] * s_gl[k][x];
+      for (int k = 0; k <= DIM; ++k) g += dph[k] * s_gl[k][x];
       s_gphE[q][a][x] = g;
     }
   }
   __syncthreads();
-  for (int idx = tid; idx < BU * BU; idx += NT) {
-    const int c = idx / BU, r = idx % BU;
-    const int a = r / DIM, i = r % DIM, b = c / DIM, j = c % DIM;
-    double k = 0.0;
-    for (int q = 0; q < NQV; ++q) {
-      double gg = 0.0;
-      for (int x = 0; x < DIM; ++x) gg += s_gphE[q][a][x] * s_gphE[q][b][x];
-      double v = lam * s_gphE[q][a][i] * s_gphE[q][b][j] + G * s_gphE[q][a][j] * s_gphE[q][b][i];
-      if (i == j) v += G * gg;
-      k += c_rules.vq_w[q] * det * v;
-    }
-    s_diag[idx] = k;
+  for (int t = tid; t < NQV * DIM * DIM; t += NT) {
+    const int q = t / (DIM * DIM), i = (t / DIM) % DIM, x = t % DIM;
+    double g = 0.0;
+    for (int b = 0; b < NN; ++b) g += s_ue[b * DIM + i] * s_gphE[q][b][x];
+    s_gu[q][i][x] = g;
   }
+  for (int t = tid; t < NN * NN; t += NT) {
+    const int a = t / NN, b = t % NN;
+    double P[DIM][DIM];
+    for (int x = 0; x < DIM; ++x)
+      for (int y = 0; y < DIM; ++y) P[x][y] = 0.0;
+    for (int q = 0; q < NQV; ++q) {
+      const double wq = c_rules.vq_w[q] * det;
+      for (int x = 0; x < DIM; ++x)
+        for (int y = 0; y < DIM; ++y) P[x][y] += wq * s_gphE[q][a][x] * s_gphE[q][b][y];
+    }
+    double tr = 0.0;
+    for (int x = 0; x < DIM; ++x) tr += P[x][x];
+    for (int i = 0; i < DIM; ++i)
+      for (int j = 0; j < DIM; ++j)
+        s_diag[(b * DIM + j) * BU + a * DIM + i] =
+            lam * P[i][j] + G * P[j][i] + (i == j ? G * tr : 0.0);
+  }
+  __syncthreads();
   for (int r = tid; r < BU; r += NT) {
     const int a = r / DIM, i = r % DIM;
     double acc = 0.0;
     for (int q = 0; q < NQV; ++q) {
-      double gu[DIM][DIM];
-      for (int ii = 0; ii < DIM; ++ii)
-        for (int x = 0; x < DIM; ++x) {
-          double g = 0.0;
-          for (int b = 0; b < NN; ++b) g += s_ue[b * DIM + ii] * s_gphE[q][b][x];
-          gu[ii][x] = g;
-        }
       double tr = 0.0;
-      for (int x = 0; x < DIM; ++x) tr += gu[x][x];
+      for (int x = 0; x < DIM; ++x) tr += s_gu[q][x][x];
       double sn = 0.0;
       for (int x = 0; x < DIM; ++x) {
-        double sig = G * (gu[i][x] + gu[x][i]) + (i == x ? lam * tr : 0.0);
+        const double sig = G * (s_gu[q][i][x] + s_gu[q][x][i]) + (i == x ? lam * tr : 0.0);
         sn += sig * s_gphE[q][a][x];
       }
       acc += c_rules.vq_w[q] * det * sn;
@@ -322,148 +362,157 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const double *__res
     for (int r = tid; r < BU; r += NT) s_un[r] = u[(int64_t)nb * BU + r];
     __syncthreads();
     // shape functions of both elements at the face points
-    for (int t = tid; t < 2 * NQF; t += NT) {
-      const int side = t / NQF, q = t % NQF;
+    for (int t = tid; t < 2 * NQF * NN; t += NT) {
+      const int side = t / (NQF * NN), q = (t / NN) % NQF, a = t % NN;
       double lamq[DIM + 1];
       for (int k = 0; k <= DIM; ++k) lamq[k] = 0.0;
       const int *perm = side == 0 ? s_pe : s_pn;
       for (int k = 0; k < DIM; ++k) lamq[perm[k]] = c_rules.fq_mu[q][k];
-      double ph[NN], dph[NN][DIM + 1];
-      Lag<DIM, ORDER>::phi(lamq, ph);
-      Lag<DIM, ORDER>::dphi(lamq, dph);
-      for (int a = 0; a < NN; ++a) {
-        for (int x = 0; x < DIM; ++x) {
-          double g = 0.0;
-          for (int k = 0; k <= DIM; ++k) g += dph[a][k] * (side == 0 ? s_gl[k][x] : s_gln[k][x]);
-          if (side == 0) s_gphE[q][a][x] = g; else s_gphN[q][a][x] = g;
-        }
-        if (side == 0) s_phE[q][a] = ph[a]; else s_phN[q][a] = ph[a];
+      double dph[DIM + 1];
+      Lag<DIM, ORDER>::dphi_one(a, lamq, dph);
+      const double ph = Lag<DIM, ORDER>::phi_one(a, lamq);
+      for (int x = 0; x < DIM; ++x) {
+        double g = 0.0;
+        for (int k = 0; k <= DIM; ++k) g += dph[k] * (side == 0 ? s_gl[k][x] : s_gln[k][x]);
+        if (side == 0) s_gphE[q][a][x] = g; else s_gphN[q][a][x] = g;
       }
+      if (side == 0) s_phE[q][a] = ph; else s_phN[q][a] = ph;
     }
     __syncthreads();
-    // per-point traction tau, interface-law tangent, fluid coefficients
+    // per-point traction tau and interface-law tangent
     for (int q = tid; q < NQF; q += NT) {
-      double uE[DIM], uN[DIM], gE[DIM][DIM], gN[DIM][DIM];
+      double jump[DIM], ga[DIM][DIM];
       for (int i = 0; i < DIM; ++i) {
         double a0 = 0.0, a1 = 0.0;
         for (int a = 0; a < NN; ++a) {
           a0 += s_phE[q][a] * s_ue[a * DIM + i];
           a1 += s_phN[q][a] * s_un[a * DIM + i];
         }
-        uE[i] = a0;
-        uN[i] = a1;
+        jump[i] = sgE * a0 + sgN * a1;  // u+ - u-
         for (int x = 0; x < DIM; ++x) {
-          double b0 = 0.0, b1 = 0.0;
-          for (int a = 0; a < NN; ++a) {
-            b0 += s_ue[a * DIM + i] * s_gphE[q][a][x];
-            b1 += s_un[a * DIM + i] * s_gphN[q][a][x];
-          }
-          gE[i][x] = b0;
-          gN[i][x] = b1;
+          double b0 = 0.0;
+          for (int a = 0; a < NN; ++a)
+            b0 += s_ue[a * DIM + i] * s_gphE[q][a][x] + s_un[a * DIM + i] * s_gphN[q][a][x];
+          ga[i][x] = 0.5 * b0;  // average of the two sides' displacement gradients
         }
       }
-      double trE = 0.0, trN = 0.0;
+      double tr = 0.0, w = 0.0;
       for (int x = 0; x < DIM; ++x) {
-        trE += gE[x][x];
-        trN += gN[x][x];
-      }
-      double jump[DIM], w = 0.0;
-      for (int i = 0; i < DIM; ++i) {
-        jump[i] = sgE * uE[i] + sgN * uN[i];  // u+ - u-
-        w += jump[i] * s_n[i];
+        tr += ga[x][x];
+        w += jump[x] * s_n[x];
       }
       const int st = kp.m.qp_state[(int64_t)f * NQF + q];
       const double al = st > 0 ? 1.0 : 0.0;
       double T, dT;
       traction_law(st, w, kp.sigma_c, kp.delta_c, kc, T, dT);
       double ph_p = 0.0;
-      double eta[NNF];
-      double geta[NNF][DIM - 1];
+      double gp[DIM - 1];
+      for (int s2 = 0; s2 < DIM - 1; ++s2) gp[s2] = 0.0;
       if (beta) {
-        double mu_[DIM], dmu[NNF][DIM];
+        double mu_[DIM];
         for (int k = 0; k < DIM; ++k) mu_[k] = c_rules.fq_mu[q][k];
-        Lag<DIM - 1, ORDER>::phi(mu_, eta);
-        Lag<DIM - 1, ORDER>::dphi(mu_, dmu);
-        for (int k = 0; k < NNF; ++k)
-          for (int s = 0; s < DIM - 1; ++s) geta[k][s] = dmu[k][s + 1] - dmu[k][0];
-        for (int k = 0; k < NNF; ++k) ph_p += eta[k] * p[kp.m.face_pn[(int64_t)slot * NNF + k]];
+        for (int k = 0; k < NNF; ++k) {
+          const double pk = p[kp.m.face_pn[(int64_t)slot * NNF + k]];
+          double dmu[DIM];
+          Lag<DIM - 1, ORDER>::dphi_one(k, mu_, dmu);
+          ph_p += Lag<DIM - 1, ORDER>::phi_one(k, mu_) * pk;
+          for (int s2 = 0; s2 < DIM - 1; ++s2) gp[s2] += (dmu[s2 + 1] - dmu[0]) * pk;
+        }
       }
       for (int i = 0; i < DIM; ++i) {
-        double sn = 0.0;  // 0.5 (sigma_E + sigma_N) n, component i
+        double sn = 0.0;  // <sigma> n, component i (sigma is linear in grad u)
         for (int x = 0; x < DIM; ++x) {
-          double sE = G * (gE[i][x] + gE[x][i]) + (i == x ? lam * trE : 0.0);
-          double sN = G * (gN[i][x] + gN[x][i]) + (i == x ? lam * trN : 0.0);
-          sn += 0.5 * (sE + sN) * s_n[x];
+          const double sa = G * (ga[i][x] + ga[x][i]) + (i == x ? lam * tr : 0.0);
+          sn += sa * s_n[x];
         }
-        double cj = G * jump[i];
-        double jn = 0.0;
-        for (int x = 0; x < DIM; ++x) jn += jump[x] * s_n[x];
-        cj += (lam + G) * s_n[i] * jn;
+        const double cj = G * jump[i] + (lam + G) * s_n[i] * w;
         s_tau[q][i] = (1.0 - al) * (sn + bh * cj) + al * T * s_n[i] - (beta ? ph_p * s_n[i] : 0.0);
       }
-      const double W = c_rules.fq_w[q] * area;
-      s_W[q] = W;
+      s_W[q] = c_rules.fq_w[q] * area;
       s_al[q] = al;
       s_dT[q] = dT;
-      if (beta) {
-        const double wp = w > 0.0 ? w : 0.0;
+      s_wq[q] = w;
+      for (int s2 = 0; s2 < DIM - 1; ++s2) s_gp[q][s2] = gp[s2];
+    }
+    __syncthreads();
+    // fluid coefficients of the C strips: s_p (K'(w) grad p . grad eta_k + eta_k / dt)
+    if (beta) {
+      for (int t = tid; t < NQF * NNF; t += NT) {
+        const int q = t / NNF, k = t % NNF;
+        double mu_[DIM], dmu[DIM];
+        for (int c2 = 0; c2 < DIM; ++c2) mu_[c2] = c_rules.fq_mu[q][c2];
+        Lag<DIM - 1, ORDER>::dphi_one(k, mu_, dmu);
+        const double eta = Lag<DIM - 1, ORDER>::phi_one(k, mu_);
+        const double wp = s_wq[q] > 0.0 ? s_wq[q] : 0.0;
         const double dK = 3.0 * wp * wp / (12.0 * kp.mu);
-        double gp[DIM - 1];
-        for (int s = 0; s < DIM - 1; ++s) {
-          double g = 0.0;
-          for (int k = 0; k < NNF; ++k) g += geta[k][s] * p[kp.m.face_pn[(int64_t)slot * NNF + k]];
-          gp[s] = g;
-        }
-        for (int k = 0; k < NNF; ++k) {
-          double gg = 0.0;
-          for (int s = 0; s < DIM - 1; ++s)
-            for (int t2 = 0; t2 < DIM - 1; ++t2) gg += gp[s] * s_ginv[s * (DIM - 1) + t2] * geta[k][t2];
-          s_eta[q][k] = eta[k];
-          s_fc[q][k] = kp.s_p * (dK * gg + eta[k] / kp.dt);
-        }
+        double gg = 0.0;
+        for (int s2 = 0; s2 < DIM - 1; ++s2)
+          for (int t2 = 0; t2 < DIM - 1; ++t2)
+            gg += s_gp[q][s2] * s_ginv[s2 * (DIM - 1) + t2] * (dmu[t2 + 1] - dmu[0]);
+        s_eta[q][k] = eta;
+        s_fc[q][k] = kp.s_p * (dK * gg + eta / kp.dt);
       }
+    }
+    for (int t = tid; t < NQF * NN; t += NT) {
+      const int q = t / NN, a = t % NN;
+      s_c[q][a] = s_W[q] * sgE * s_phE[q][a];
     }
     __syncthreads();
     // residual of this element's test functions
     for (int r = tid; r < BU; r += NT) {
       const int a = r / DIM, i = r % DIM;
       double acc = 0.0;
-      for (int q = 0; q < NQF; ++q) acc += s_W[q] * sgE * s_phE[q][a] * s_tau[q][i];
+      for (int q = 0; q < NQF; ++q) acc += s_c[q][a] * s_tau[q][i];
       s_R[r] += acc;
     }
-    // X^t_q[b,j,i] = d tau_i / d u^t_{b,j}
-    for (int idx = tid; idx < 2 * NQF * BU * DIM; idx += NT) {
-      const int i = idx % DIM;
-      const int c = (idx / DIM) % BU;
-      const int q = (idx / (DIM * BU)) % NQF;
-      const int side = idx / (DIM * BU * NQF);
-      const int b = c / DIM, j = c % DIM;
-      const double sg = side == 0 ? sgE : sgN;
-      const double ph = side == 0 ? s_phE[q][b] : s_phN[q][b];
-      double gph[DIM];
-      for (int x = 0; x < DIM; ++x) gph[x] = side == 0 ? s_gphE[q][b][x] : s_gphN[q][b][x];
-      double gn = 0.0;
-      for (int x = 0; x < DIM; ++x) gn += gph[x] * s_n[x];
-      double cons = 0.5 * (lam * gph[j] * s_n[i] + G * gph[i] * s_n[j] + (i == j ? G * gn : 0.0));
-      double chat = (i == j ? G : 0.0) + (lam + G) * s_n[i] * s_n[j];
-      double pen = bh * chat * sg * ph;
-      double coh = s_dT[q] * s_n[i] * s_n[j] * sg * ph;
-      s_X[side][q][c][i] = (1.0 - s_al[q]) * (cons + pen) + s_al[q] * coh;
+    // moment matrices M1..M4 of both trial sides
+    for (int t = tid; t < 2 * NN * NN; t += NT) {
+      const int side = t / (NN * NN), a = (t / NN) % NN, b = t % NN;
+      double m1[DIM], m2 = 0.0, m3 = 0.0, m4 = 0.0;
+      for (int x = 0; x < DIM; ++x) m1[x] = 0.0;
+      for (int q = 0; q < NQF; ++q) {
+        const double ca = s_c[q][a];
+        const double c1 = ca * (1.0 - s_al[q]);
+        const double ph = side == 0 ? s_phE[q][b] : s_phN[q][b];
+        double gn = 0.0;
+        for (int x = 0; x < DIM; ++x) {
+          const double g = side == 0 ? s_gphE[q][b][x] : s_gphN[q][b][x];
+          m1[x] += c1 * g;
+          gn += g * s_n[x];
+        }
+        m2 += c1 * gn;
+        m3 += c1 * ph;
+        m4 += ca * s_al[q] * s_dT[q] * ph;
+      }
+      for (int x = 0; x < DIM; ++x) s_M[side][a][b][x] = m1[x];
+      s_M[side][a][b][DIM] = m2;
+      s_M[side][a][b][DIM + 1] = m3;
+      s_M[side][a][b][DIM + 2] = m4;
     }
     __syncthreads();
-    // self block (into the diagonal) and the off-diagonal block of this face
+    // self block (into the diagonal) and the off-diagonal block
+    for (int t = tid; t < NN * NN; t += NT) {
+      const int a = t / NN, b = t % NN;
+      for (int side = 0; side < 2; ++side) {
+        const double sg = side == 0 ? sgE : sgN;
+        const double *M = s_M[side][a][b];
+        for (int i = 0; i < DIM; ++i)
+          for (int j = 0; j < DIM; ++j) {
+            const double ninj = s_n[i] * s_n[j];
+            const double chat = (i == j ? G : 0.0) + (lam + G) * ninj;
+            double v = 0.5 * lam * s_n[i] * M[j] + 0.5 * G * s_n[j] * M[i] +
+                       bh * sg * chat * M[DIM + 1] + sg * ninj * M[DIM + 2];
+            if (i == j) v += 0.5 * G * M[DIM];
+            const int idx = (b * DIM + j) * BU + a * DIM + i;
+            if (side == 0) s_diag[idx] += v; else s_off[idx] = v;
+          }
+      }
+    }
+    __syncthreads();
     double *Aoff = A + (int64_t)kp.m.blk_of[e * NF + lf] * BU * BU;
     for (int idx = tid; idx < BU * BU; idx += NT) {
-      const int c = idx / BU, r = idx % BU;
-      const int a = r / DIM, i = r % DIM;
-      double vs = 0.0, vo = 0.0;
-      for (int q = 0; q < NQF; ++q) {
-        const double t = s_W[q] * sgE * s_phE[q][a];
-        vs += t * s_X[0][q][c][i];
-        vo += t * s_X[1][q][c][i];
-      }
-      s_diag[idx] += vs;
-      Aoff[idx] = ((clamp >> r) & 1u) ? 0.0 : vo;
+      const int r = idx % BU;
+      Aoff[idx] = ((clamp >> r) & 1u) ? 0.0 : s_off[idx];
     }
     // coupling strips: B (d R_u / d p) and C (d R_p / d u_e) of this face
     if (beta) {
@@ -473,7 +522,7 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const double *__res
           const int32_t ix = kp.m.fs_idx[((int64_t)e * NF + lf) * NNF + k];
           double bv = 0.0, cv = 0.0;
           for (int q = 0; q < NQF; ++q) {
-            bv += s_W[q] * sgE * s_phE[q][a] * (-s_eta[q][k] * s_n[i]);
+            bv -= s_c[q][a] * s_eta[q][k] * s_n[i];
             cv += s_W[q] * s_fc[q][k] * sgE * s_phE[q][a] * s_n[i];
           }
           Bs[(int64_t)ix * BU + r] += bv;

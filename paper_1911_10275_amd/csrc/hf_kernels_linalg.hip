@@ -610,6 +610,137 @@ template hipError_t launch_update_norm<double>(const double *, int64_t, int, con
 template hipError_t launch_update_norm<float>(const float *, int64_t, int, const double *,
                                               float *, int64_t, double *, double *, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Gram-Schmidt passes with register tiling.  A block owns OR_ROWS rows per
+// thread (1024 rows); w stays in registers while the basis vectors stream in
+// tiles of OR_TILE, so every thread keeps OR_ROWS * OR_TILE loads in flight.
+// ---------------------------------------------------------------------------
+constexpr int OR_ROWS = 4;
+constexpr int OR_TILE = 8;
+constexpr int OR_CHUNK = kRedThreads * OR_ROWS;
+
+int ortho_blocks(int64_t n) { return (int)((n + OR_CHUNK - 1) / OR_CHUNK); }
+
+// partial[b*(k+1) + i] = sum over the block's rows of V_i w (i < k), and
+// partial[b*(k+1) + k] = sum of w^2
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_proj(const T *__restrict__ V, int64_t ldv, int k,
+                                                      const T *__restrict__ w, int64_t n,
+                                                      double *__restrict__ partial) {
+  __shared__ double wsum[kMaxKrylov + 1][kRedThreads / 64];
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int64_t r0 = (int64_t)blockIdx.x * OR_CHUNK + tid;
+  double wr[OR_ROWS];
+  double nn = 0.0;
+#pragma unroll
+  for (int s = 0; s < OR_ROWS; ++s) {
+    const int64_t r = r0 + (int64_t)s * kRedThreads;
+    wr[s] = r < n ? (double)w[r] : 0.0;
+    nn += wr[s] * wr[s];
+  }
+  for (int i0 = 0; i0 < k; i0 += OR_TILE) {
+    double acc[OR_TILE];
+#pragma unroll
+    for (int q = 0; q < OR_TILE; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int s = 0; s < OR_ROWS; ++s) {
+      const int64_t r = r0 + (int64_t)s * kRedThreads;
+      if (r < n) {
+#pragma unroll
+        for (int q = 0; q < OR_TILE; ++q)
+          if (i0 + q < k) acc[q] += (double)V[(int64_t)(i0 + q) * ldv + r] * wr[s];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < OR_TILE; ++q) {
+      const double v = wave_sum(acc[q]);
+      if (lane == 0 && i0 + q < k) wsum[i0 + q][wv] = v;
+    }
+  }
+  nn = wave_sum(nn);
+  if (lane == 0) wsum[k][wv] = nn;
+  __syncthreads();
+  for (int i = tid; i <= k; i += kRedThreads) {
+    double s2 = 0.0;
+    for (int q = 0; q < kRedThreads / 64; ++q) s2 += wsum[i][q];
+    partial[(int64_t)blockIdx.x * (k + 1) + i] = s2;
+  }
+}
+
+// w -= sum_i h_i V_i ; partial[b] = sum of the new w^2
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_orth_update(const T *__restrict__ V, int64_t ldv,
+                                                             int k, const double *__restrict__ h,
+                                                             T *__restrict__ w, int64_t n,
+                                                             double *__restrict__ partial) {
+  __shared__ double sh[kMaxKrylov];
+  __shared__ double wsum[kRedThreads / 64];
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  for (int i = tid; i < k; i += kRedThreads) sh[i] = h[i];
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.x * OR_CHUNK + tid;
+  double acc[OR_ROWS];
+#pragma unroll
+  for (int s = 0; s < OR_ROWS; ++s) {
+    const int64_t r = r0 + (int64_t)s * kRedThreads;
+    acc[s] = r < n ? (double)w[r] : 0.0;
+  }
+  for (int i0 = 0; i0 < k; i0 += OR_TILE) {
+#pragma unroll
+    for (int s = 0; s < OR_ROWS; ++s) {
+      const int64_t r = r0 + (int64_t)s * kRedThreads;
+      if (r < n) {
+#pragma unroll
+        for (int q = 0; q < OR_TILE; ++q)
+          if (i0 + q < k) acc[s] -= sh[i0 + q] * (double)V[(int64_t)(i0 + q) * ldv + r];
+      }
+    }
+  }
+  double nn = 0.0;
+#pragma unroll
+  for (int s = 0; s < OR_ROWS; ++s) {
+    const int64_t r = r0 + (int64_t)s * kRedThreads;
+    if (r < n) {
+      const T v = (T)acc[s];
+      w[r] = v;
+      nn += (double)v * (double)v;
+    }
+  }
+  nn = wave_sum(nn);
+  if (lane == 0) wsum[wv] = nn;
+  __syncthreads();
+  if (tid == 0) {
+    double s2 = 0.0;
+    for (int q = 0; q < kRedThreads / 64; ++q) s2 += wsum[q];
+    partial[blockIdx.x] = s2;
+  }
+}
+
+template <typename T>
+hipError_t launch_proj(const T *V, int64_t ldv, int k, const T *w, int64_t n, double *partial,
+                       double *out, hipStream_t st) {
+  const int nb = ortho_blocks(n);
+  hipLaunchKernelGGL(k_proj<T>, dim3(nb), dim3(kRedThreads), 0, st, V, ldv, k, w, n, partial);
+  hipLaunchKernelGGL(k_reduce, dim3(k + 1), dim3(kRedThreads), 0, st, partial, nb, k + 1, out);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_orth_update(const T *V, int64_t ldv, int k, const double *h, T *w, int64_t n,
+                              double *partial, double *out, hipStream_t st) {
+  const int nb = ortho_blocks(n);
+  hipLaunchKernelGGL(k_orth_update<T>, dim3(nb), dim3(kRedThreads), 0, st, V, ldv, k, h, w, n, partial);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, st, partial, nb, 1, out);
+  return hipGetLastError();
+}
+template hipError_t launch_proj<double>(const double *, int64_t, int, const double *, int64_t,
+                                        double *, double *, hipStream_t);
+template hipError_t launch_proj<float>(const float *, int64_t, int, const float *, int64_t,
+                                       double *, double *, hipStream_t);
+template hipError_t launch_orth_update<double>(const double *, int64_t, int, const double *,
+                                               double *, int64_t, double *, double *, hipStream_t);
+template hipError_t launch_orth_update<float>(const float *, int64_t, int, const double *,
+                                              float *, int64_t, double *, double *, hipStream_t);
+
 static inline dim3 grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 65536) g = 65536;
