@@ -26,7 +26,18 @@
  *    hf_set_injection] -> hf_finalize -> hf_set_state -> {hf_assemble |
  *    hf_solve | hf_newton_step | hf_newton_solve | hf_end_load_step}.
  *    Any other order returns HF_ESTATE.
- *  - One fracture instance per context (inst = 0).
+ *  - Batching: a context holds one or more independent fracture instances
+ *    (one hf_upload_mesh call each; ids 0, 1, ... in call order) with the
+ *    same dim and order but their own mesh, interfaces, material, injection
+ *    and state.  Every compute call (hf_assemble .. hf_end_load_step) works
+ *    on all instances in the same kernel launches and reports per-instance
+ *    results in caller arrays of hf_instance_count() entries; its return
+ *    value is HF_OK when every instance succeeded, else the status of the
+ *    lowest failing instance (hf_last_error names it).  A failure of one
+ *    instance never changes the result of another.
+ *  - Context vectors (hf_apply_jacobian) are the concatenation
+ *    [u_0, u_1, .., u_{B-1}, p_0, p_1, .., p_{B-1}]; hf_get_sizes gives each
+ *    instance's offsets.
  *
  * Canonical orderings (shared with any caller-side checker)
  *  - Element node order: the simplex vertices as given, then (P2) edge
@@ -81,6 +92,8 @@ typedef struct {
   int cutoff_on;       /* clamp p >= p_cutoff after each update (default 0) */
   int device;          /* HIP device ordinal (default 0) */
   int profile;         /* 1: time kernel classes with HIP events (default 0) */
+  int use_graphs;      /* 1: replay chunks of GMRES iterations from captured HIP
+                          graphs (default 1; ignored while profile = 1) */
   void *stream;        /* hipStream_t to run on; NULL: a stream the ctx creates */
 } hf_options;
 
@@ -93,16 +106,19 @@ typedef struct {
 } hf_material;
 
 typedef struct {
-  int64_t n_elem, nodes_per_elem, n_u, n_p, n_face, n_blocks;
+  int64_t n_elem, nodes_per_elem, n_u, n_p, n_face, n_blocks;  /* of the instance */
+  int64_t u_offset, p_offset;  /* its u and p in the context vectors (after hf_finalize) */
+  int64_t n_total;             /* length of the context vectors, all instances */
   int32_t dim, order, nq_face, block_size;
 } hf_sizes;
 
 typedef struct {
   int gmres_iters;     /* total (inner) GMRES iterations */
   int ir_steps;        /* refinement steps (FP32-IR), 0 for FP64 */
-  int restarts;
+  int restarts;        /* GMRES cycles */
+  int status;          /* hf_status of this instance's solve */
   double true_relres;  /* ||b - J dx|| / ||b||, recomputed in FP64 */
-  double seconds;      /* wall time of the solve */
+  double seconds;      /* wall time of the (batched) solve */
 } hf_solve_stats;
 
 typedef struct {
@@ -111,6 +127,8 @@ typedef struct {
   double res_norm;     /* ||R|| at the start of the last iteration */
   int iterations;      /* Newton iterations taken */
   int converged;       /* 1 when both relative increments <= newton_tol */
+  int status;          /* hf_status of this instance */
+  int reserved;
 } hf_newton_stats;
 
 typedef struct {
@@ -130,6 +148,8 @@ void hf_destroy(hf_ctx *ctx);
 const char *hf_last_error(const hf_ctx *ctx);
 /* Change options after creation (precision, tolerances, caps, profile). */
 hf_status hf_set_options(hf_ctx *ctx, const hf_options *opt);
+/* Number of instances uploaded so far. */
+hf_status hf_instance_count(hf_ctx *ctx, int32_t *n);
 
 /* Bulk mesh (Sec. "Computational framework": partition of the domain into
    simplices carrying independent P^k displacement nodes).
@@ -137,7 +157,8 @@ hf_status hf_set_options(hf_ctx *ctx, const hf_options *opt);
    (n_elem*(dim+1)) vertex ids of straight-sided simplices; dirichlet_vert
    (n_vert, 0/1, nullable): a node copy is clamped (u = 0, strong) when it
    lies on a boundary facet whose vertices are all flagged.  Builds the
-   interior-face list.  *inst_out = 0. */
+   interior-face list.  Each call adds one instance: *inst_out = its id
+   (nullable).  All instances share dim and order. */
 hf_status hf_upload_mesh(hf_ctx *ctx, int dim, int order, int64_t n_vert, const double *xyz,
                          int64_t n_elem, const int32_t *elem_vert,
                          const uint8_t *dirichlet_vert, int32_t *inst_out);
@@ -156,6 +177,8 @@ hf_status hf_get_faces(hf_ctx *ctx, int32_t inst, int64_t *n_face, int32_t *face
 hf_status hf_upload_interfaces(hf_ctx *ctx, int32_t inst, const uint8_t *qp_state,
                                const uint8_t *beta);
 
+/* Material of an instance; required before hf_finalize, may change later
+   (e.g. between load steps). */
 hf_status hf_set_material(hf_ctx *ctx, int32_t inst, const hf_material *mat);
 
 /* Point injections Q0 (right-hand side of eq. discreteLubrication) at
@@ -164,7 +187,9 @@ hf_status hf_set_injection(hf_ctx *ctx, int32_t inst, int32_t n_src, const int64
                            const double *q0);
 
 /* Build layout, block pattern, geometry and pressure numbering on the
-   device.  No uploads after this call. */
+   device for all instances.  No mesh, interface or injection uploads after
+   this call.  Limit: 4096 pressure nodes per instance (dense pressure
+   block). */
 hf_status hf_finalize(hf_ctx *ctx);
 hf_status hf_get_sizes(hf_ctx *ctx, int32_t inst, hf_sizes *out);
 /* Pressure-node keys (n_p*2): (vertex, -1) or (lo, hi) of an edge node. */
@@ -174,7 +199,8 @@ hf_status hf_get_pnodes(hf_ctx *ctx, int32_t inst, int64_t *keys);
    the opening of the previous step, source of eq. discreteLubrication;
    nullable = keep).  Rejects non-finite values (HF_ENONFINITE).  Also fixes
    the fluid-row scale s_p = 12 mu (L / w_ref)^3 with L the largest bounding
-   box extent and w_ref = max(max w_old on fluid faces, 0.01 delta_c). */
+   box extent and w_ref = max(max w_old on fluid faces, 0.01 delta_c), per
+   instance.  Instances never given a state start from zero. */
 hf_status hf_set_state(hf_ctx *ctx, int32_t inst, const double *u, const double *p,
                        const double *w_old);
 /* u, p, w (current opening at face points), w_old: each nullable. */
@@ -187,16 +213,20 @@ hf_status hf_get_state_device(hf_ctx *ctx, int32_t inst, double *u, double *p);
 
 /* Residual R and Jacobian J = [[A, B], [C, D]] at the current state
    (eq. discreteElastoStatics, eq. discreteLubrication and their exact
-   derivative).  *res_norm = ||R|| (nullable). */
+   derivative), all instances.  res_norm[b] = ||R_b|| (nullable array). */
 hf_status hf_assemble(hf_ctx *ctx, double *res_norm);
-/* Build the preconditioner and solve J dx = -R to the true relative
-   residual rtol (GMRES or GMRES-IR per options); dx is kept in the ctx. */
+/* Build the preconditioner and solve J dx = -R of every instance to the
+   true relative residual rtol (GMRES or GMRES-IR per options); dx is kept
+   in the ctx; stats[b] per instance (nullable array). */
 hf_status hf_solve(hf_ctx *ctx, hf_solve_stats *stats);
-/* One Newton iteration: assemble + solve + update u, p (+ optional cut-off).
-   On HF_ENOCONV / HF_ESINGULAR / HF_ENONFINITE the state is unchanged. */
+/* One Newton iteration of every instance: assemble + solve + update u, p
+   (+ optional cut-off).  An instance whose solve fails (HF_ENOCONV,
+   HF_ESINGULAR, HF_ENONFINITE) keeps its state.  stats[b] per instance. */
 hf_status hf_newton_step(hf_ctx *ctx, hf_newton_stats *stats);
-/* Newton iterations until converged or newton_maxit (HF_ENOCONV, state
-   restored to the start of the call). */
+/* Newton iterations until every instance has converged or failed; an
+   instance stops iterating once converged.  An instance that has not
+   converged within newton_maxit (HF_ENOCONV) or failed gets back its state
+   at the start of the call.  stats[b] per instance (nullable array). */
 hf_status hf_newton_solve(hf_ctx *ctx, hf_newton_stats *stats);
 /* End of a given-length load step: w_old <- w(u), s_p recomputed. */
 hf_status hf_end_load_step(hf_ctx *ctx);
@@ -209,8 +239,9 @@ hf_status hf_end_load_step(hf_ctx *ctx);
    injected volume under uniform pressure, so the cubic-law conductivity is
    not degenerate at the first Newton iterate (the paper starts the same
    test from uniform pressure and opening, Sec. "Verification of the
-   fully-coupled algorithm").  *p0_out (nullable) = p0.  No-op without
-   pressure nodes or injection. */
+   fully-coupled algorithm").  p0_out[b] (nullable array) = p0 of instance b;
+   instances without pressure nodes or injection keep their state (p0 = 0);
+   an instance whose predictor fails keeps its state. */
 hf_status hf_initial_guess(hf_ctx *ctx, double *p0_out);
 
 /* ---- inspection hooks (tests, benchmarks) ---- */
@@ -224,9 +255,10 @@ hf_status hf_get_block_rows(hf_ctx *ctx, int32_t inst, int64_t n_rows, const int
 /* Dense coupling blocks (small meshes): B (n_u*n_p), C (n_p*n_u),
    D (n_p*n_p), row-major; each nullable. */
 hf_status hf_get_coupling(hf_ctx *ctx, int32_t inst, double *B, double *C, double *D);
-/* Increment dx = (du, dp) of the last hf_solve. */
+/* Increment dx = (du, dp) of an instance from the last solve. */
 hf_status hf_get_increment(hf_ctx *ctx, int32_t inst, double *du, double *dp);
-/* y = J x on device vectors of length n_u + n_p; precision HF_FP64 uses the
+/* y = J x on device context vectors (length n_total, all instances);
+   precision HF_FP64 uses the
    FP64 matrix (double*), HF_FP32_IR the FP32 copy (float*) built by the
    last hf_solve in FP32-IR mode. */
 hf_status hf_apply_jacobian(hf_ctx *ctx, int precision, const void *x, void *y);

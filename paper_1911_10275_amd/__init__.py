@@ -27,6 +27,7 @@ STATUS_NAMES = {0: "HF_OK", -1: "HF_EINVAL", -2: "HF_ENOMEM", -3: "HF_EDEVICE", 
 # every symbol include/hf.h declares
 EXPORTS = [
     "hf_default_options", "hf_create", "hf_destroy", "hf_last_error", "hf_set_options",
+    "hf_instance_count",
     "hf_upload_mesh", "hf_get_faces", "hf_upload_interfaces", "hf_set_material",
     "hf_set_injection", "hf_finalize", "hf_get_sizes", "hf_get_pnodes", "hf_set_state",
     "hf_get_state", "hf_set_state_device", "hf_get_state_device", "hf_assemble", "hf_solve",
@@ -41,7 +42,7 @@ class Options(C.Structure):
                 ("ir_maxit", C.c_int), ("newton_maxit", C.c_int), ("rtol", C.c_double),
                 ("rtol_inner", C.c_double), ("newton_tol", C.c_double), ("b_stab", C.c_double),
                 ("p_cutoff", C.c_double), ("cutoff_on", C.c_int), ("device", C.c_int),
-                ("profile", C.c_int), ("stream", C.c_void_p)]
+                ("profile", C.c_int), ("use_graphs", C.c_int), ("stream", C.c_void_p)]
 
 
 class Material(C.Structure):
@@ -52,18 +53,20 @@ class Material(C.Structure):
 class Sizes(C.Structure):
     _fields_ = [("n_elem", C.c_int64), ("nodes_per_elem", C.c_int64), ("n_u", C.c_int64),
                 ("n_p", C.c_int64), ("n_face", C.c_int64), ("n_blocks", C.c_int64),
+                ("u_offset", C.c_int64), ("p_offset", C.c_int64), ("n_total", C.c_int64),
                 ("dim", C.c_int32), ("order", C.c_int32), ("nq_face", C.c_int32),
                 ("block_size", C.c_int32)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("gmres_iters", C.c_int), ("ir_steps", C.c_int), ("restarts", C.c_int),
-                ("true_relres", C.c_double), ("seconds", C.c_double)]
+                ("status", C.c_int), ("true_relres", C.c_double), ("seconds", C.c_double)]
 
 
 class NewtonStats(C.Structure):
     _fields_ = [("lin", SolveStats), ("du_rel", C.c_double), ("dp_rel", C.c_double),
-                ("res_norm", C.c_double), ("iterations", C.c_int), ("converged", C.c_int)]
+                ("res_norm", C.c_double), ("iterations", C.c_int), ("converged", C.c_int),
+                ("status", C.c_int), ("reserved", C.c_int)]
 
 
 class Profile(C.Structure):
@@ -105,6 +108,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hf_destroy": (None, [vp]),
         "hf_last_error": (C.c_char_p, [vp]),
         "hf_set_options": (C.c_int, [vp, P(Options)]),
+        "hf_instance_count": (C.c_int, [vp, P(C.c_int32)]),
         "hf_upload_mesh": (C.c_int, [vp, C.c_int, C.c_int, C.c_int64, vp, C.c_int64, vp, vp,
                                      P(C.c_int32)]),
         "hf_get_faces": (C.c_int, [vp, C.c_int32, P(C.c_int64), vp, vp, P(C.c_int32)]),
@@ -160,7 +164,13 @@ def default_options(**kw) -> Options:
 
 
 class Context:
-    """One fracture instance on one GPU (owns the library context)."""
+    """One or more fracture instances on one GPU (owns the library context).
+
+    Per-instance calls take ``inst`` (default 0).  The compute calls work on
+    every instance at once; with one instance they return scalars / single
+    stats, with several a numpy array / list (one entry per instance).  With
+    ``check=False`` they return the per-instance results even when some
+    instance failed (inspect ``.status``)."""
 
     def __init__(self, **options):
         self.lib = load()
@@ -170,7 +180,8 @@ class Context:
         if st != HF_OK:
             raise HFError(st, "hf_create failed (is a gfx950 GPU visible?)")
         self.h = h
-        self.sizes = None
+        self.sizes = None      # of instance 0, after finalize
+        self.isizes = []       # of every instance, after finalize
 
     # -- lifecycle ---------------------------------------------------------
     def close(self):
@@ -194,16 +205,19 @@ class Context:
         if st != HF_OK:
             raise HFError(st, f"{what}: {self.lib.hf_last_error(self.h).decode()}")
 
-    def status(self, st):
-        return st
-
     def set_options(self, **kw):
         for k, v in kw.items():
             setattr(self.opt, k, v)
         self._check(self.lib.hf_set_options(self.h, C.byref(self.opt)), "hf_set_options")
 
+    @property
+    def n_inst(self) -> int:
+        n = C.c_int32()
+        self._check(self.lib.hf_instance_count(self.h, C.byref(n)), "hf_instance_count")
+        return n.value
+
     # -- setup ---------------------------------------------------------------
-    def upload_mesh(self, dim, order, xyz, elem, dirichlet_vert=None):
+    def upload_mesh(self, dim, order, xyz, elem, dirichlet_vert=None) -> int:
         xyz = _arr(xyz, np.float64)
         elem = _arr(elem, np.int32)
         dv = None if dirichlet_vert is None else _arr(dirichlet_vert, np.uint8)
@@ -213,134 +227,149 @@ class Context:
                     "hf_upload_mesh")
         return inst.value
 
-    def faces(self):
+    def faces(self, inst=0):
         nf = C.c_int64()
         nq = C.c_int32()
-        self._check(self.lib.hf_get_faces(self.h, 0, C.byref(nf), None, None, C.byref(nq)),
+        self._check(self.lib.hf_get_faces(self.h, inst, C.byref(nf), None, None, C.byref(nq)),
                     "hf_get_faces")
-        s = self.get_sizes()
+        s = self.get_sizes(inst)
         fv = np.empty((nf.value, s.dim), dtype=np.int32)
         fe = np.empty((nf.value, 2), dtype=np.int32)
-        self._check(self.lib.hf_get_faces(self.h, 0, C.byref(nf), _ptr(fv), _ptr(fe), None),
+        self._check(self.lib.hf_get_faces(self.h, inst, C.byref(nf), _ptr(fv), _ptr(fe), None),
                     "hf_get_faces")
         return fv, fe, nq.value
 
-    def upload_interfaces(self, qp_state=None, beta=None):
+    def upload_interfaces(self, qp_state=None, beta=None, inst=0):
         q = None if qp_state is None else _arr(qp_state, np.uint8)
         b = None if beta is None else _arr(beta, np.uint8)
-        self._check(self.lib.hf_upload_interfaces(self.h, 0, _ptr(q), _ptr(b)),
+        self._check(self.lib.hf_upload_interfaces(self.h, inst, _ptr(q), _ptr(b)),
                     "hf_upload_interfaces")
 
-    def set_material(self, E, nu, sigma_c, G_c, mu, dt):
+    def set_material(self, E, nu, sigma_c, G_c, mu, dt, inst=0):
         m = Material(E, nu, sigma_c, G_c, mu, dt)
-        self._check(self.lib.hf_set_material(self.h, 0, C.byref(m)), "hf_set_material")
+        self._check(self.lib.hf_set_material(self.h, inst, C.byref(m)), "hf_set_material")
 
-    def set_injection(self, vert, q0):
+    def set_injection(self, vert, q0, inst=0):
         v = _arr(vert, np.int64)
         q = _arr(q0, np.float64)
-        self._check(self.lib.hf_set_injection(self.h, 0, len(v), _ptr(v), _ptr(q)),
+        self._check(self.lib.hf_set_injection(self.h, inst, len(v), _ptr(v), _ptr(q)),
                     "hf_set_injection")
 
     def finalize(self):
         self._check(self.lib.hf_finalize(self.h), "hf_finalize")
-        self.sizes = self.get_sizes()
+        self.isizes = [self.get_sizes(b) for b in range(self.n_inst)]
+        self.sizes = self.isizes[0]
 
-    def get_sizes(self) -> Sizes:
+    def get_sizes(self, inst=0) -> Sizes:
         s = Sizes()
-        self._check(self.lib.hf_get_sizes(self.h, 0, C.byref(s)), "hf_get_sizes")
+        self._check(self.lib.hf_get_sizes(self.h, inst, C.byref(s)), "hf_get_sizes")
         return s
 
-    def pnodes(self):
-        s = self.get_sizes()
+    def pnodes(self, inst=0):
+        s = self.get_sizes(inst)
         k = np.empty((s.n_p, 2), dtype=np.int64)
-        self._check(self.lib.hf_get_pnodes(self.h, 0, _ptr(k)), "hf_get_pnodes")
+        self._check(self.lib.hf_get_pnodes(self.h, inst, _ptr(k)), "hf_get_pnodes")
         return k
 
     # -- state ---------------------------------------------------------------
-    def set_state(self, u, p, w_old=None):
+    def set_state(self, u, p, w_old=None, inst=0):
         u = _arr(u, np.float64)
         p = _arr(p, np.float64)
         w = None if w_old is None else _arr(w_old, np.float64)
-        self._check(self.lib.hf_set_state(self.h, 0, _ptr(u), _ptr(p), _ptr(w)), "hf_set_state")
+        self._check(self.lib.hf_set_state(self.h, inst, _ptr(u), _ptr(p), _ptr(w)),
+                    "hf_set_state")
 
-    def get_state(self):
-        s = self.sizes
+    def get_state(self, inst=0):
+        s = self.isizes[inst]
         u = np.empty(s.n_u)
         p = np.empty(s.n_p)
         w = np.empty((s.n_face, s.nq_face))
         wo = np.empty((s.n_face, s.nq_face))
-        self._check(self.lib.hf_get_state(self.h, 0, _ptr(u), _ptr(p), _ptr(w), _ptr(wo)),
+        self._check(self.lib.hf_get_state(self.h, inst, _ptr(u), _ptr(p), _ptr(w), _ptr(wo)),
                     "hf_get_state")
         return u, p, w, wo
 
-    def set_state_device(self, u_ptr, p_ptr, w_old_ptr=None):
-        self._check(self.lib.hf_set_state_device(self.h, 0, C.c_void_p(u_ptr),
+    def set_state_device(self, u_ptr, p_ptr, w_old_ptr=None, inst=0):
+        self._check(self.lib.hf_set_state_device(self.h, inst, C.c_void_p(u_ptr),
                                                  C.c_void_p(p_ptr),
                                                  None if w_old_ptr is None else C.c_void_p(w_old_ptr)),
                     "hf_set_state_device")
 
-    # -- the Newton step -----------------------------------------------------------
-    def assemble(self) -> float:
-        r = C.c_double()
-        self._check(self.lib.hf_assemble(self.h, C.byref(r)), "hf_assemble")
-        return r.value
+    # -- the Newton step (all instances) -------------------------------------------
+    def _one(self, arr):
+        return arr[0] if len(arr) == 1 else arr
 
-    def solve(self) -> SolveStats:
-        st = SolveStats()
-        self._check(self.lib.hf_solve(self.h, C.byref(st)), "hf_solve")
-        return st
+    def assemble(self):
+        r = np.zeros(self.n_inst)
+        self._check(self.lib.hf_assemble(self.h, r.ctypes.data_as(C.POINTER(C.c_double))),
+                    "hf_assemble")
+        return float(r[0]) if len(r) == 1 else r
 
-    def newton_step(self) -> NewtonStats:
-        st = NewtonStats()
-        self._check(self.lib.hf_newton_step(self.h, C.byref(st)), "hf_newton_step")
-        return st
+    def solve(self, check=True):
+        st = (SolveStats * self.n_inst)()
+        rc = self.lib.hf_solve(self.h, st)
+        if check:
+            self._check(rc, "hf_solve")
+        return self._one(list(st))
 
-    def newton_solve(self) -> NewtonStats:
-        st = NewtonStats()
-        self._check(self.lib.hf_newton_solve(self.h, C.byref(st)), "hf_newton_solve")
-        return st
+    def newton_step(self, check=True):
+        st = (NewtonStats * self.n_inst)()
+        rc = self.lib.hf_newton_step(self.h, st)
+        if check:
+            self._check(rc, "hf_newton_step")
+        return self._one(list(st))
+
+    def newton_solve(self, check=True):
+        st = (NewtonStats * self.n_inst)()
+        rc = self.lib.hf_newton_solve(self.h, st)
+        if check:
+            self._check(rc, "hf_newton_solve")
+        return self._one(list(st))
 
     def end_load_step(self):
         self._check(self.lib.hf_end_load_step(self.h), "hf_end_load_step")
 
-    def initial_guess(self) -> float:
-        """Uniform-pressure elastic predictor for the first load step; returns p0."""
-        p0 = C.c_double()
-        self._check(self.lib.hf_initial_guess(self.h, C.byref(p0)), "hf_initial_guess")
-        return p0.value
+    def initial_guess(self):
+        """Uniform-pressure elastic predictor for the first load step; returns p0
+        (an array with one entry per instance when there are several)."""
+        p0 = np.zeros(self.n_inst)
+        self._check(self.lib.hf_initial_guess(self.h, p0.ctypes.data_as(C.POINTER(C.c_double))),
+                    "hf_initial_guess")
+        return float(p0[0]) if len(p0) == 1 else p0
 
     # -- inspection ------------------------------------------------------------------
-    def residual(self):
-        s = self.sizes
+    def residual(self, inst=0):
+        s = self.isizes[inst]
         ru = np.empty(s.n_u)
         rp = np.empty(s.n_p)
-        self._check(self.lib.hf_get_residual(self.h, 0, _ptr(ru), _ptr(rp)), "hf_get_residual")
+        self._check(self.lib.hf_get_residual(self.h, inst, _ptr(ru), _ptr(rp)), "hf_get_residual")
         return ru, rp
 
-    def block_rows(self, elems):
-        s = self.sizes
+    def block_rows(self, elems, inst=0):
+        s = self.isizes[inst]
         e = _arr(elems, np.int32)
         ns = s.dim + 2
         cols = np.empty((len(e), ns), dtype=np.int32)
         blocks = np.empty((len(e), ns, s.block_size, s.block_size))
-        self._check(self.lib.hf_get_block_rows(self.h, 0, len(e), _ptr(e), _ptr(cols),
+        self._check(self.lib.hf_get_block_rows(self.h, inst, len(e), _ptr(e), _ptr(cols),
                                                _ptr(blocks)), "hf_get_block_rows")
         return cols, blocks
 
-    def coupling(self):
-        s = self.sizes
+    def coupling(self, inst=0):
+        s = self.isizes[inst]
         B = np.empty((s.n_u, s.n_p))
         Cm = np.empty((s.n_p, s.n_u))
         D = np.empty((s.n_p, s.n_p))
-        self._check(self.lib.hf_get_coupling(self.h, 0, _ptr(B), _ptr(Cm), _ptr(D)),
+        self._check(self.lib.hf_get_coupling(self.h, inst, _ptr(B), _ptr(Cm), _ptr(D)),
                     "hf_get_coupling")
         return B, Cm, D
 
-    def increment(self):
-        s = self.sizes
+    def increment(self, inst=0):
+        s = self.isizes[inst]
         du = np.empty(s.n_u)
         dp = np.empty(s.n_p)
-        self._check(self.lib.hf_get_increment(self.h, 0, _ptr(du), _ptr(dp)), "hf_get_increment")
+        self._check(self.lib.hf_get_increment(self.h, inst, _ptr(du), _ptr(dp)),
+                    "hf_get_increment")
         return du, dp
 
     def apply_jacobian(self, x_ptr, y_ptr, precision=HF_FP64):
@@ -356,16 +385,9 @@ class Context:
         self._check(self.lib.hf_reset_profile(self.h), "hf_reset_profile")
 
 
-def context_for_problem(prob, b_stab: float = 10.0, **options) -> Context:
-    """Build a finalized Context from a problem description with attributes
-    dim, order, xyz, elem, dirichlet_vert, crack_faces (sorted vertex ids),
-    crack_state, crack_beta, src_vert, src_q0 and material (E, nu, sigma_c,
-    G_c, mu, dt).  Crack faces are located among the library's interior faces
-    by their vertex ids; every integration point of a crack face gets its
-    state."""
-    ctx = Context(b_stab=b_stab, **options)
-    ctx.upload_mesh(prob.dim, prob.order, prob.xyz, prob.elem, prob.dirichlet_vert)
-    fv, _, nq = ctx.faces()
+def _upload_problem(ctx: Context, prob) -> int:
+    inst = ctx.upload_mesh(prob.dim, prob.order, prob.xyz, prob.elem, prob.dirichlet_vert)
+    fv, _, nq = ctx.faces(inst)
     index = {tuple(r): i for i, r in enumerate(fv.tolist())}
     qs = np.zeros((len(fv), nq), dtype=np.uint8)
     beta = np.zeros(len(fv), dtype=np.uint8)
@@ -374,9 +396,27 @@ def context_for_problem(prob, b_stab: float = 10.0, **options) -> Context:
         f = index[tuple(sorted(int(v) for v in key))]
         qs[f, :] = st
         beta[f] = bt
-    ctx.upload_interfaces(qs, beta)
+    ctx.upload_interfaces(qs, beta, inst=inst)
     m = prob.material
-    ctx.set_material(m.E, m.nu, m.sigma_c, m.G_c, m.mu, m.dt)
-    ctx.set_injection(np.asarray(prob.src_vert), np.asarray(prob.src_q0))
+    ctx.set_material(m.E, m.nu, m.sigma_c, m.G_c, m.mu, m.dt, inst=inst)
+    ctx.set_injection(np.asarray(prob.src_vert), np.asarray(prob.src_q0), inst=inst)
+    return inst
+
+
+def context_for_problems(probs, b_stab: float = 10.0, **options) -> Context:
+    """Build a finalized Context holding one instance per problem.  A problem
+    has attributes dim, order, xyz, elem, dirichlet_vert, crack_faces (vertex
+    ids), crack_state, crack_beta, src_vert, src_q0 and material (E, nu,
+    sigma_c, G_c, mu, dt).  Crack faces are located among the library's
+    interior faces by their vertex ids; every integration point of a crack
+    face gets its state."""
+    ctx = Context(b_stab=b_stab, **options)
+    for prob in probs:
+        _upload_problem(ctx, prob)
     ctx.finalize()
     return ctx
+
+
+def context_for_problem(prob, b_stab: float = 10.0, **options) -> Context:
+    """A finalized single-instance Context (see ``context_for_problems``)."""
+    return context_for_problems([prob], b_stab=b_stab, **options)

@@ -1,8 +1,16 @@
 // C ABI of the Newton-step library: argument checking, host topology and
 // layout construction, device allocation, and the GMRES / GMRES-IR / Newton
 // drivers that sequence the device kernels.  Every arithmetic step of the
-// Newton iteration runs in the HIP kernels; the host only orders them, reads
-// back scalar reduction results and applies the Givens rotations of GMRES.
+// Newton iteration runs in the HIP kernels; the host orders the launches and
+// reads back per-instance scalars once per chunk of GMRES iterations.
+//
+// Batching: a context holds one or more instances of one element type.
+// Their arrays are concatenated (elements, faces, pressure nodes; vectors as
+// [u_0 .. u_{B-1}, p_0 .. p_{B-1}]), every kernel launch covers all
+// instances, and the Krylov scalars (dots, norms, Hessenberg matrices,
+// rotations, convergence) live per instance on the device.  An instance that
+// has converged or failed is masked out of the rest of a solve; the status of
+// every instance is reported separately.
 #include <algorithm>
 #include <array>
 #include <chrono>
@@ -13,11 +21,107 @@
 #include <map>
 #include <new>
 #include <set>
-#include <stdexcept>
+#include <string>
+#include <vector>
 
 #include "hf_internal.h"
 
 using namespace hf;
+
+namespace {
+
+constexpr int kChunkRows = 1024;  // rows per reduction chunk (256 threads x 4 rows)
+constexpr int kIterChunk = 10;    // GMRES iterations between host checks
+
+struct Mat {
+  double E = 1, nu = 0.25, sigma_c = 1e-3, G_c = 1e-4, mu = 1e-3, dt = 1;
+  bool set = false;
+};
+
+// one instance as uploaded, in its own (local) numbering
+struct InstHost {
+  int64_t n_vert = 0, ne = 0, nf = 0, n_p = 0, n_act = 0;
+  std::vector<double> xyz;
+  std::vector<int32_t> elem;
+  std::vector<uint8_t> dirichlet;
+  std::vector<int32_t> face_vert, face_em, face_ep, fperm_m, fperm_p, face_lfm, nbr, fid;
+  std::vector<uint32_t> clamp;
+  std::vector<uint8_t> qp_state, beta;
+  std::vector<int64_t> src_vert;
+  std::vector<double> src_q0;
+  std::vector<int64_t> pkeys;  // (v, -1) or (lo, hi) per pressure node
+  Mat mat;
+  double bbox_L = 1.0;
+};
+
+template <typename T>
+struct KrylovWs {
+  T *V = nullptr;  // (m+1) basis vectors of length N, vector i at V + i*N
+  T *w = nullptr, *z = nullptr, *r = nullptr, *t = nullptr, *b = nullptr, *x = nullptr;
+  int m = 0;
+  int64_t n = 0;
+  std::vector<hipGraphExec_t> graphs;  // captured iteration chunks, by first iteration / kIterChunk
+};
+
+struct SolveOut {
+  int iters = 0, restarts = 0;
+  double relres = 0.0;
+  hf_status st = HF_OK;
+};
+
+}  // namespace
+
+struct hf_ctx {
+  hf_options opt{};
+  std::string err;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int stage = 0;  // 0 created, 1 mesh, 2 finalized, 3 state set, 4 assembled, 5 solved
+  std::vector<InstHost> inst;
+  Sizes s;
+  DevMesh m;
+  RuleTables rules{};
+  int freeze_p = 0;
+  std::vector<void *> allocs;
+  // per-instance offsets (host) and their device copies
+  std::vector<int64_t> eoff, foff, voff, doff;
+  std::vector<int32_t> poff, aoff;
+  std::vector<InstPar> ipar;
+  InstPar *d_ipar = nullptr;
+  int32_t *d_einst = nullptr, *d_pinst = nullptr, *d_poff = nullptr, *d_aoff = nullptr;
+  int64_t *d_doff = nullptr;
+  // batched Krylov state
+  KrylovDev kd;
+  int kd_m = 0;
+  double *k_s1 = nullptr, *k_s2 = nullptr, *k_n1 = nullptr, *k_n2 = nullptr, *k_scale = nullptr;
+  double *k_y = nullptr, *k_est = nullptr, *k_beta2 = nullptr, *k_coef = nullptr;
+  int *k_flag = nullptr, *k_count = nullptr, *k_upd = nullptr;
+  // state xs = [u; p] of all instances
+  double *xs = nullptr, *xs_save = nullptr, *xs_start = nullptr, *w_old = nullptr, *w_tmp = nullptr;
+  // assembled system
+  double *R = nullptr, *A = nullptr, *Bs = nullptr, *Cs = nullptr;
+  double *D = nullptr, *S = nullptr, *Sinv = nullptr, *T = nullptr, *inv = nullptr;
+  float *A32 = nullptr, *Bs32 = nullptr, *Cs32 = nullptr, *D32 = nullptr, *Sinv32 = nullptr;
+  float *inv32 = nullptr;
+  bool have32 = false;
+  int *flag = nullptr;
+  double *dx = nullptr, *rhs = nullptr, *r64 = nullptr, *t64 = nullptr;
+  KrylovWs<double> k64;
+  KrylovWs<float> k32;
+  double *partial = nullptr, *red = nullptr;
+  // pinned host staging: downloads (hd, hi) and uploads (hu)
+  double *hd = nullptr;
+  int *hi = nullptr;
+  char *hu = nullptr;
+  size_t hd_n = 0, hi_n = 0, hu_n = 0;
+  bool hu_pending = false;  // an upload from hu may still be in flight
+  std::vector<std::string> ierr;  // message of each instance's failure in the current call
+  // profile
+  std::vector<hipEvent_t> evpool;
+  size_t ev_used = 0;
+  std::vector<std::array<int64_t, 3>> ev_pending;
+  hf_profile prof{};
+};
 
 namespace {
 
@@ -33,10 +137,10 @@ hf_status fail(hf_ctx *ctx, hf_status st, const std::string &msg) {
       return fail(ctx, HF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-#define TRY(call)                 \
-  do {                            \
-    hf_status s_ = (call);        \
-    if (s_ != HF_OK) return s_;   \
+#define TRY(call)               \
+  do {                          \
+    hf_status s_ = (call);      \
+    if (s_ != HF_OK) return s_; \
   } while (0)
 
 template <typename T>
@@ -49,6 +153,15 @@ hf_status dalloc(hf_ctx *ctx, T **p, int64_t n) {
   ctx->allocs.push_back(q);
   *p = (T *)q;
   return HF_OK;
+}
+
+template <typename T>
+void dfree(hf_ctx *ctx, T **p) {
+  if (!*p) return;
+  auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), (void *)*p);
+  if (it != ctx->allocs.end()) ctx->allocs.erase(it);
+  (void)hipFree((void *)*p);
+  *p = nullptr;
 }
 
 template <typename T>
@@ -65,19 +178,20 @@ bool all_finite(const double *x, int64_t n) {
   return true;
 }
 
+int nI(const hf_ctx *ctx) { return (int)ctx->inst.size(); }
+
 KParams kparams(const hf_ctx *ctx) {
   KParams kp;
   kp.s = ctx->s;
   kp.m = ctx->m;
-  const double E = ctx->mat.E, nu = ctx->mat.nu;
-  kp.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
-  kp.G = E / (2.0 * (1.0 + nu));
-  kp.sigma_c = ctx->mat.sigma_c;
-  kp.delta_c = 2.0 * ctx->mat.G_c / ctx->mat.sigma_c;
-  kp.mu = ctx->mat.mu;
-  kp.dt = ctx->mat.dt;
+  kp.ip = ctx->d_ipar;
+  kp.einst = ctx->d_einst;
+  kp.pinst = ctx->d_pinst;
+  kp.poff = ctx->d_poff;
+  kp.doff = ctx->d_doff;
+  kp.aoff = ctx->d_aoff;
+  kp.n_inst = nI(ctx);
   kp.b_stab = ctx->opt.b_stab;
-  kp.s_p = ctx->s_p;
   kp.freeze_p = ctx->freeze_p;
   return kp;
 }
@@ -91,14 +205,86 @@ hf_status check_ctx(hf_ctx *ctx, int need_stage) {
 }
 
 hf_status check_inst(hf_ctx *ctx, int32_t inst) {
-  if (inst != 0) return fail(ctx, HF_EINVAL, "one instance per context: inst must be 0");
+  if (inst < 0 || inst >= nI(ctx)) return fail(ctx, HF_EINVAL, "instance id out of range");
   return HF_OK;
 }
 
-hf_status sync_read(hf_ctx *ctx, int n) {
-  HIPCHK(hipMemcpyAsync(ctx->red_h, ctx->red, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+// pinned staging buffers, grown on demand
+hf_status ensure_host(hf_ctx *ctx, size_t nd, size_t ni, size_t nu) {
+  if (ctx->hu_pending && nu > ctx->hu_n) {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->hu_pending = false;
+  }
+  if (nd > ctx->hd_n) {
+    if (ctx->hd) (void)hipHostFree(ctx->hd);
+    ctx->hd = nullptr;
+    if (hipHostMalloc((void **)&ctx->hd, nd * sizeof(double)) != hipSuccess)
+      return fail(ctx, HF_ENOMEM, "pinned host allocation failed");
+    ctx->hd_n = nd;
+  }
+  if (ni > ctx->hi_n) {
+    if (ctx->hi) (void)hipHostFree(ctx->hi);
+    ctx->hi = nullptr;
+    if (hipHostMalloc((void **)&ctx->hi, ni * sizeof(int)) != hipSuccess)
+      return fail(ctx, HF_ENOMEM, "pinned host allocation failed");
+    ctx->hi_n = ni;
+  }
+  if (nu > ctx->hu_n) {
+    if (ctx->hu) (void)hipHostFree(ctx->hu);
+    ctx->hu = nullptr;
+    if (hipHostMalloc((void **)&ctx->hu, nu) != hipSuccess)
+      return fail(ctx, HF_ENOMEM, "pinned host allocation failed");
+    ctx->hu_n = nu;
+  }
   return HF_OK;
+}
+
+// device -> host of n doubles into ctx->hd (synchronises the stream)
+hf_status get_d(hf_ctx *ctx, const double *dev, int64_t n) {
+  TRY(ensure_host(ctx, (size_t)n, 0, 0));
+  if (n) HIPCHK(hipMemcpyAsync(ctx->hd, dev, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->hu_pending = false;
+  return HF_OK;
+}
+
+// device -> host of n ints into ctx->hi + off (no synchronisation)
+hf_status get_i_async(hf_ctx *ctx, const int *dev, int64_t n, int64_t off) {
+  if (n) HIPCHK(hipMemcpyAsync(ctx->hi + off, dev, n * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  return HF_OK;
+}
+
+// host -> device of a small array through pinned staging.  The staging
+// buffer is reused only after the stream has been synchronised since the
+// last upload, so an upload in flight is never overwritten.
+template <typename T>
+hf_status put(hf_ctx *ctx, T *dev, const std::vector<T> &v) {
+  const size_t bytes = v.size() * sizeof(T);
+  if (!bytes) return HF_OK;
+  if (ctx->hu_pending) {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->hu_pending = false;
+  }
+  TRY(ensure_host(ctx, 0, 0, bytes));
+  std::memcpy(ctx->hu, v.data(), bytes);
+  HIPCHK(hipMemcpyAsync(dev, ctx->hu, bytes, hipMemcpyHostToDevice, ctx->stream));
+  ctx->hu_pending = true;
+  return HF_OK;
+}
+
+hf_status sync(hf_ctx *ctx) {
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->hu_pending = false;
+  return HF_OK;
+}
+
+bool trace_on() {
+  static int on = -1;
+  if (on < 0) {
+    const char *e = std::getenv("HF_TRACE");
+    on = (e && *e && *e != '0') ? 1 : 0;
+  }
+  return on == 1;
 }
 
 // ---- profiling of kernel classes ------------------------------------------
@@ -136,6 +322,7 @@ void resolve_profile(hf_ctx *ctx) {
     return;
   }
   (void)hipStreamSynchronize(ctx->stream);
+  ctx->hu_pending = false;
   double *ms[P_NCLASS] = {&ctx->prof.ms_assemble, &ctx->prof.ms_blockinv, &ctx->prof.ms_spmv64,
                           &ctx->prof.ms_spmv32, &ctx->prof.ms_precond, &ctx->prof.ms_ortho};
   int64_t *cnt[P_NCLASS] = {&ctx->prof.n_assemble, &ctx->prof.n_blockinv, &ctx->prof.n_spmv64,
@@ -149,6 +336,37 @@ void resolve_profile(hf_ctx *ctx) {
   }
   ctx->ev_pending.clear();
   ctx->ev_used = 0;
+}
+
+template <typename T>
+void release_graphs(KrylovWs<T> &ws) {
+  for (auto &ge : ws.graphs)
+    if (ge) (void)hipGraphExecDestroy(ge);
+  ws.graphs.clear();
+}
+
+void release_all_graphs(hf_ctx *ctx) {
+  release_graphs(ctx->k64);
+  release_graphs(ctx->k32);
+}
+
+// record the reason of instance b's failure
+void note(hf_ctx *ctx, int b, const std::string &msg) {
+  if ((int)ctx->ierr.size() <= b) ctx->ierr.resize(b + 1);
+  if (ctx->ierr[b].empty()) ctx->ierr[b] = msg;
+}
+
+// the first failing instance gives the call's status and message
+hf_status first_failure(hf_ctx *ctx, const std::vector<hf_status> &st, const char *what) {
+  hf_status out = HF_OK;
+  for (size_t b = 0; b < st.size() && out == HF_OK; ++b)
+    if (st[b] != HF_OK) {
+      const std::string why = b < ctx->ierr.size() && !ctx->ierr[b].empty() ? ctx->ierr[b] : what;
+      ctx->err = "instance " + std::to_string(b) + ": " + why;
+      out = st[b];
+    }
+  ctx->ierr.clear();
+  return out;
 }
 
 }  // namespace
@@ -170,6 +388,7 @@ extern "C" void hf_default_options(hf_options *o) {
   o->cutoff_on = 0;
   o->device = 0;
   o->profile = 0;
+  o->use_graphs = 1;
   o->stream = nullptr;
 }
 
@@ -203,8 +422,8 @@ extern "C" hf_status hf_create(const hf_options *opt, hf_ctx **out) {
     if (hipStreamCreate(&ctx->stream) != hipSuccess) { delete ctx; return HF_EDEVICE; }
     ctx->own_stream = true;
   }
-  if (hipHostMalloc((void **)&ctx->red_h, 4 * kMaxKrylov * sizeof(double)) != hipSuccess) {
-    delete ctx;
+  if (ensure_host(ctx, 64, 64, 256) != HF_OK) {
+    hf_destroy(ctx);
     return HF_ENOMEM;
   }
   *out = ctx;
@@ -215,8 +434,11 @@ extern "C" void hf_destroy(hf_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->opt.device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  release_all_graphs(ctx);
   for (void *p : ctx->allocs) (void)hipFree(p);
-  if (ctx->red_h) (void)hipHostFree(ctx->red_h);
+  if (ctx->hd) (void)hipHostFree(ctx->hd);
+  if (ctx->hi) (void)hipHostFree(ctx->hi);
+  if (ctx->hu) (void)hipHostFree(ctx->hu);
   for (hipEvent_t ev : ctx->evpool) (void)hipEventDestroy(ev);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -231,37 +453,41 @@ extern "C" hf_status hf_set_options(hf_ctx *ctx, const hf_options *opt) {
   TRY(validate_options(ctx, *opt));
   if (opt->device != ctx->opt.device || opt->stream != ctx->opt.stream)
     return fail(ctx, HF_EINVAL, "device and stream are fixed at hf_create");
+  release_all_graphs(ctx);  // captured chunks hold the old tolerances and restart length
   ctx->opt = *opt;
   return HF_OK;
 }
 
+extern "C" hf_status hf_instance_count(hf_ctx *ctx, int32_t *n) {
+  if (!ctx || !n) return HF_EINVAL;
+  *n = nI(ctx);
+  return HF_OK;
+}
+
 // ===========================================================================
-// Mesh upload: interior faces, neighbours, clamped node copies
+// Mesh upload: interior faces, neighbours, clamped node copies (per instance)
 // ===========================================================================
 extern "C" hf_status hf_upload_mesh(hf_ctx *ctx, int dim, int order, int64_t n_vert,
                                     const double *xyz, int64_t n_elem, const int32_t *elem_vert,
                                     const uint8_t *dirichlet_vert, int32_t *inst_out) {
   if (!ctx) return HF_EINVAL;
-  if (ctx->stage != 0) return fail(ctx, HF_ESTATE, "one instance per context: mesh already uploaded");
+  if (ctx->stage >= 2) return fail(ctx, HF_ESTATE, "no mesh uploads after hf_finalize");
   if (dim != 2 && dim != 3) return fail(ctx, HF_EINVAL, "dim must be 2 or 3");
   if (order != 1 && order != 2) return fail(ctx, HF_EINVAL, "order must be 1 or 2");
+  if (!ctx->inst.empty() && (dim != ctx->s.dim || order != ctx->s.order))
+    return fail(ctx, HF_EINVAL, "all instances of a context share dim and order");
   if (n_vert <= 0 || n_elem <= 0 || !xyz || !elem_vert)
     return fail(ctx, HF_EINVAL, "empty mesh or null array");
-  if (n_elem > (int64_t)INT32_MAX / 8) return fail(ctx, HF_EINVAL, "too many elements");
+  if (n_elem > (int64_t)INT32_MAX / 8 || n_vert > (int64_t)INT32_MAX / 4)
+    return fail(ctx, HF_EINVAL, "mesh too large");
   if (!all_finite(xyz, n_vert * dim)) return fail(ctx, HF_ENONFINITE, "non-finite vertex coordinate");
   const int NF = dim + 1;
   for (int64_t i = 0; i < n_elem * NF; ++i)
     if (elem_vert[i] < 0 || elem_vert[i] >= n_vert) return fail(ctx, HF_EINVAL, "vertex id out of range");
-  Sizes &s = ctx->s;
-  s.dim = dim;
-  s.order = order;
-  s.nn = order == 1 ? dim + 1 : (dim + 1) * (dim + 2) / 2;
-  s.bu = s.nn * dim;
-  s.nnf = order == 1 ? dim : dim * (dim + 1) / 2;
-  s.n_vert = n_vert;
-  s.ne = n_elem;
-  s.n_u = n_elem * s.bu;
-  HostLayout &h = ctx->h;
+  const int nn = order == 1 ? dim + 1 : (dim + 1) * (dim + 2) / 2;
+  InstHost h;
+  h.n_vert = n_vert;
+  h.ne = n_elem;
   h.xyz.assign(xyz, xyz + n_vert * dim);
   h.elem.assign(elem_vert, elem_vert + n_elem * NF);
   h.dirichlet.assign(n_vert, 0);
@@ -292,10 +518,6 @@ extern "C" hf_status hf_upload_mesh(hf_ctx *ctx, int dim, int order, int64_t n_v
   });
   h.nbr.assign(n_elem * NF, -1);
   h.fid.assign(n_elem * NF, -1);
-  h.face_vert.clear();
-  h.face_em.clear();
-  h.face_ep.clear();
-  h.face_lfm.clear();
   std::vector<std::array<int32_t, 3>> bfacets;
   for (size_t i = 0; i < recs.size();) {
     size_t j = i + 1;
@@ -317,10 +539,10 @@ extern "C" hf_status hf_upload_mesh(hf_ctx *ctx, int dim, int order, int64_t n_v
     }
     i = j;
   }
-  s.nf = (int64_t)h.face_em.size();
-  h.fperm_m.assign(s.nf * dim, 0);
-  h.fperm_p.assign(s.nf * dim, 0);
-  for (int64_t f = 0; f < s.nf; ++f)
+  h.nf = (int64_t)h.face_em.size();
+  h.fperm_m.assign(h.nf * dim, 0);
+  h.fperm_p.assign(h.nf * dim, 0);
+  for (int64_t f = 0; f < h.nf; ++f)
     for (int k = 0; k < dim; ++k) {
       const int32_t v = h.face_vert[f * dim + k];
       for (int c = 0; c < NF; ++c) {
@@ -345,7 +567,7 @@ extern "C" hf_status hf_upload_mesh(hf_ctx *ctx, int dim, int order, int64_t n_v
   for (int64_t e = 0; e < n_elem; ++e) {
     uint32_t mask = 0;
     const int32_t *ev = &h.elem[e * NF];
-    for (int a = 0; a < s.nn; ++a) {
+    for (int a = 0; a < nn; ++a) {
       bool c;
       if (a < NF) {
         c = cv[ev[a]];
@@ -359,39 +581,58 @@ extern "C" hf_status hf_upload_mesh(hf_ctx *ctx, int dim, int order, int64_t n_v
     }
     h.clamp[e] = mask;
   }
-  // quadrature rules
-  Rule fr = simplex_rule(dim - 1, order + 1);
-  Rule vr = simplex_rule(dim, order);
-  double wsum = 0.0;
-  for (double w : fr.w) wsum += w;
-  RuleTables &rt = ctx->rules;
-  std::memset(&rt, 0, sizeof(rt));
-  rt.nqf = fr.nq();
-  rt.nqv = vr.nq();
-  for (int q = 0; q < rt.nqf; ++q) {
-    double sum = 0.0;
-    for (int k = 0; k < dim - 1; ++k) {
-      rt.fq_mu[q][k + 1] = fr.pts[q * (dim - 1) + k];
-      sum += fr.pts[q * (dim - 1) + k];
+  if (ctx->inst.empty()) {
+    // quadrature rules (shared by every instance of the context)
+    Rule fr = simplex_rule(dim - 1, order + 1);
+    Rule vr = simplex_rule(dim, order);
+    double wsum = 0.0;
+    for (double w : fr.w) wsum += w;
+    RuleTables &rt = ctx->rules;
+    std::memset(&rt, 0, sizeof(rt));
+    rt.nqf = fr.nq();
+    rt.nqv = vr.nq();
+    for (int q = 0; q < rt.nqf; ++q) {
+      double sum = 0.0;
+      for (int k = 0; k < dim - 1; ++k) {
+        rt.fq_mu[q][k + 1] = fr.pts[q * (dim - 1) + k];
+        sum += fr.pts[q * (dim - 1) + k];
+      }
+      rt.fq_mu[q][0] = 1.0 - sum;
+      rt.fq_w[q] = fr.w[q] / wsum;
     }
-    rt.fq_mu[q][0] = 1.0 - sum;
-    rt.fq_w[q] = fr.w[q] / wsum;
-  }
-  for (int q = 0; q < rt.nqv; ++q) {
-    double sum = 0.0;
-    for (int k = 0; k < dim; ++k) {
-      rt.vq_lam[q][k + 1] = vr.pts[q * dim + k];
-      sum += vr.pts[q * dim + k];
+    for (int q = 0; q < rt.nqv; ++q) {
+      double sum = 0.0;
+      for (int k = 0; k < dim; ++k) {
+        rt.vq_lam[q][k + 1] = vr.pts[q * dim + k];
+        sum += vr.pts[q * dim + k];
+      }
+      rt.vq_lam[q][0] = 1.0 - sum;
+      rt.vq_w[q] = vr.w[q];
     }
-    rt.vq_lam[q][0] = 1.0 - sum;
-    rt.vq_w[q] = vr.w[q];
+    Sizes &s = ctx->s;
+    s.dim = dim;
+    s.order = order;
+    s.nn = nn;
+    s.bu = nn * dim;
+    s.nnf = order == 1 ? dim : dim * (dim + 1) / 2;
+    s.nqf = rt.nqf;
+    s.nqv = rt.nqv;
   }
-  s.nqf = rt.nqf;
-  s.nqv = rt.nqv;
-  h.qp_state.assign(s.nf * s.nqf, 0);
-  h.beta.assign(s.nf, 0);
+  h.qp_state.assign(h.nf * ctx->s.nqf, 0);
+  h.beta.assign(h.nf, 0);
+  double L = 0.0;  // largest bounding-box extent (fluid-row scale)
+  for (int c = 0; c < dim; ++c) {
+    double lo = 1e300, hi = -1e300;
+    for (int64_t v = 0; v < n_vert; ++v) {
+      lo = std::min(lo, h.xyz[v * dim + c]);
+      hi = std::max(hi, h.xyz[v * dim + c]);
+    }
+    L = std::max(L, hi - lo);
+  }
+  h.bbox_L = L;
+  ctx->inst.push_back(std::move(h));
   ctx->stage = 1;
-  if (inst_out) *inst_out = 0;
+  if (inst_out) *inst_out = nI(ctx) - 1;
   return HF_OK;
 }
 
@@ -399,13 +640,14 @@ extern "C" hf_status hf_get_faces(hf_ctx *ctx, int32_t inst, int64_t *n_face, in
                                   int32_t *face_elem, int32_t *nq_face) {
   TRY(check_ctx(ctx, 1));
   TRY(check_inst(ctx, inst));
-  if (n_face) *n_face = ctx->s.nf;
+  const InstHost &h = ctx->inst[inst];
+  if (n_face) *n_face = h.nf;
   if (nq_face) *nq_face = ctx->s.nqf;
-  if (face_vert) std::memcpy(face_vert, ctx->h.face_vert.data(), ctx->h.face_vert.size() * 4);
+  if (face_vert) std::memcpy(face_vert, h.face_vert.data(), h.face_vert.size() * sizeof(int32_t));
   if (face_elem)
-    for (int64_t f = 0; f < ctx->s.nf; ++f) {
-      face_elem[2 * f] = ctx->h.face_em[f];
-      face_elem[2 * f + 1] = ctx->h.face_ep[f];
+    for (int64_t f = 0; f < h.nf; ++f) {
+      face_elem[2 * f] = h.face_em[f];
+      face_elem[2 * f + 1] = h.face_ep[f];
     }
   return HF_OK;
 }
@@ -415,18 +657,28 @@ extern "C" hf_status hf_upload_interfaces(hf_ctx *ctx, int32_t inst, const uint8
   TRY(check_ctx(ctx, 1));
   TRY(check_inst(ctx, inst));
   if (ctx->stage >= 2) return fail(ctx, HF_ESTATE, "interfaces are fixed after hf_finalize");
-  const int64_t n = ctx->s.nf * ctx->s.nqf;
+  InstHost &h = ctx->inst[inst];
+  const int64_t n = h.nf * ctx->s.nqf;
   if (qp_state) {
     for (int64_t i = 0; i < n; ++i)
       if (qp_state[i] > 2) return fail(ctx, HF_EINVAL, "interface state must be 0, 1 or 2");
-    ctx->h.qp_state.assign(qp_state, qp_state + n);
   }
   if (beta) {
-    for (int64_t f = 0; f < ctx->s.nf; ++f)
+    for (int64_t f = 0; f < h.nf; ++f)
       if (beta[f] > 1) return fail(ctx, HF_EINVAL, "beta must be 0 or 1");
-    ctx->h.beta.assign(beta, beta + ctx->s.nf);
   }
+  if (qp_state) h.qp_state.assign(qp_state, qp_state + n);
+  if (beta) h.beta.assign(beta, beta + h.nf);
   return HF_OK;
+}
+
+static void inst_par(const Mat &m, InstPar &P) {
+  P.lam = m.E * m.nu / ((1.0 + m.nu) * (1.0 - 2.0 * m.nu));
+  P.G = m.E / (2.0 * (1.0 + m.nu));
+  P.sigma_c = m.sigma_c;
+  P.delta_c = 2.0 * m.G_c / m.sigma_c;
+  P.mu = m.mu;
+  P.dt = m.dt;
 }
 
 extern "C" hf_status hf_set_material(hf_ctx *ctx, int32_t inst, const hf_material *mat) {
@@ -436,13 +688,21 @@ extern "C" hf_status hf_set_material(hf_ctx *ctx, int32_t inst, const hf_materia
   if (!(mat->E > 0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !(mat->sigma_c > 0) ||
       !(mat->G_c > 0) || !(mat->mu > 0) || !(mat->dt > 0))
     return fail(ctx, HF_EINVAL, "material: need E, sigma_c, G_c, mu, dt > 0 and -1 < nu < 0.5");
-  ctx->mat.E = mat->E;
-  ctx->mat.nu = mat->nu;
-  ctx->mat.sigma_c = mat->sigma_c;
-  ctx->mat.G_c = mat->G_c;
-  ctx->mat.mu = mat->mu;
-  ctx->mat.dt = mat->dt;
-  ctx->mat.set = true;
+  Mat &m = ctx->inst[inst].mat;
+  m.E = mat->E;
+  m.nu = mat->nu;
+  m.sigma_c = mat->sigma_c;
+  m.G_c = mat->G_c;
+  m.mu = mat->mu;
+  m.dt = mat->dt;
+  m.set = true;
+  if (ctx->stage >= 2) {  // a later load step may change the material (same layout)
+    const double s_p = ctx->ipar[inst].s_p;
+    inst_par(m, ctx->ipar[inst]);
+    ctx->ipar[inst].s_p = s_p;
+    TRY(put(ctx, ctx->d_ipar, ctx->ipar));
+    TRY(sync(ctx));
+  }
   return HF_OK;
 }
 
@@ -452,107 +712,178 @@ extern "C" hf_status hf_set_injection(hf_ctx *ctx, int32_t inst, int32_t n_src,
   TRY(check_inst(ctx, inst));
   if (ctx->stage >= 2) return fail(ctx, HF_ESTATE, "injection is fixed after hf_finalize");
   if (n_src < 0 || (n_src > 0 && (!vert || !q0))) return fail(ctx, HF_EINVAL, "bad sources");
+  InstHost &h = ctx->inst[inst];
   for (int i = 0; i < n_src; ++i) {
-    if (vert[i] < 0 || vert[i] >= ctx->s.n_vert) return fail(ctx, HF_EINVAL, "source vertex out of range");
+    if (vert[i] < 0 || vert[i] >= h.n_vert) return fail(ctx, HF_EINVAL, "source vertex out of range");
     if (!std::isfinite(q0[i])) return fail(ctx, HF_ENONFINITE, "non-finite Q0");
   }
-  ctx->h.src_vert.assign(vert, vert + n_src);
-  ctx->h.src_q0.assign(q0, q0 + n_src);
+  h.src_vert.assign(vert, vert + n_src);
+  h.src_q0.assign(q0, q0 + n_src);
   return HF_OK;
 }
 
 // ===========================================================================
-// Finalize: pressure numbering, coupling strips, block pattern, device data
+// Finalize: pressure numbering, concatenation, coupling strips, block
+// pattern, reduction chunks, device data
 // ===========================================================================
 extern "C" hf_status hf_finalize(hf_ctx *ctx) {
   TRY(check_ctx(ctx, 1));
   if (ctx->stage >= 2) return fail(ctx, HF_ESTATE, "already finalized");
-  if (!ctx->mat.set) return fail(ctx, HF_ESTATE, "hf_set_material must precede hf_finalize");
+  for (int b = 0; b < nI(ctx); ++b)
+    if (!ctx->inst[b].mat.set)
+      return fail(ctx, HF_ESTATE, "instance " + std::to_string(b) + ": hf_set_material must precede hf_finalize");
   HIPCHK(hipSetDevice(ctx->opt.device));
   Sizes &s = ctx->s;
-  HostLayout &h = ctx->h;
-  const int dim = s.dim, NF = dim + 1, NNF = s.nnf, BU = s.bu;
-  // ---- active faces and pressure nodes -----------------------------------
-  h.act_face.clear();
-  h.slot.assign(s.nf, -1);
-  for (int64_t f = 0; f < s.nf; ++f)
-    if (h.beta[f]) {
-      h.slot[f] = (int32_t)h.act_face.size();
-      h.act_face.push_back((int32_t)f);
-    }
-  s.n_act = (int64_t)h.act_face.size();
+  const int dim = s.dim, NF = dim + 1, NNF = s.nnf, BU = s.bu, NQ = s.nqf;
+  const int B = nI(ctx);
   static const int FE2[3][2] = {{0, 1}, {1, 2}, {2, 0}};
-  auto face_keys = [&](int64_t f, std::vector<std::pair<int64_t, int64_t>> &ks) {
-    ks.clear();
-    const int32_t *fv = &h.face_vert[f * dim];
-    for (int k = 0; k < dim; ++k) ks.push_back({fv[k], -1});
-    if (s.order == 2) {
-      const int ne_f = dim == 2 ? 1 : 3;
-      for (int q = 0; q < ne_f; ++q) {
-        int32_t a = fv[FE2[q][0]], b = fv[FE2[q][1]];
-        ks.push_back({std::min(a, b), std::max(a, b)});
+
+  // ---- per instance: fluid faces and pressure nodes (local numbering) -------
+  std::vector<std::vector<int32_t>> loc_act(B), loc_face_pn(B), loc_src(B);
+  for (int b = 0; b < B; ++b) {
+    InstHost &h = ctx->inst[b];
+    auto face_keys = [&](int64_t f, std::vector<std::pair<int64_t, int64_t>> &ks) {
+      ks.clear();
+      const int32_t *fv = &h.face_vert[f * dim];
+      for (int k = 0; k < dim; ++k) ks.push_back({fv[k], -1});
+      if (s.order == 2) {
+        const int ne_f = dim == 2 ? 1 : 3;
+        for (int q = 0; q < ne_f; ++q) {
+          int32_t a = fv[FE2[q][0]], c = fv[FE2[q][1]];
+          ks.push_back({std::min(a, c), std::max(a, c)});
+        }
       }
+    };
+    std::vector<std::pair<int64_t, int64_t>> vkeys, ekeys, ks;
+    for (int64_t f = 0; f < h.nf; ++f)
+      if (h.beta[f]) {
+        loc_act[b].push_back((int32_t)f);
+        face_keys(f, ks);
+        for (auto &k : ks) (k.second < 0 ? vkeys : ekeys).push_back(k);
+      }
+    std::sort(vkeys.begin(), vkeys.end());
+    vkeys.erase(std::unique(vkeys.begin(), vkeys.end()), vkeys.end());
+    std::sort(ekeys.begin(), ekeys.end());
+    ekeys.erase(std::unique(ekeys.begin(), ekeys.end()), ekeys.end());
+    std::map<std::pair<int64_t, int64_t>, int32_t> pidx;
+    h.pkeys.clear();
+    for (auto &k : vkeys) {
+      pidx[k] = (int32_t)pidx.size();
+      h.pkeys.push_back(k.first);
+      h.pkeys.push_back(-1);
     }
-  };
-  std::vector<std::pair<int64_t, int64_t>> vkeys, ekeys, ks;
-  for (int32_t f : h.act_face) {
-    face_keys(f, ks);
-    for (auto &k : ks) (k.second < 0 ? vkeys : ekeys).push_back(k);
+    for (auto &k : ekeys) {
+      pidx[k] = (int32_t)pidx.size();
+      h.pkeys.push_back(k.first);
+      h.pkeys.push_back(k.second);
+    }
+    h.n_p = (int64_t)pidx.size();
+    h.n_act = (int64_t)loc_act[b].size();
+    if (h.n_p > 4096)
+      return fail(ctx, HF_EINVAL, "instance " + std::to_string(b) +
+                                      ": more than 4096 pressure nodes (dense pressure block limit)");
+    for (int32_t f : loc_act[b]) {
+      face_keys(f, ks);
+      for (int k = 0; k < NNF; ++k) loc_face_pn[b].push_back(pidx.at(ks[k]));
+    }
+    for (size_t i = 0; i < h.src_vert.size(); ++i) {
+      auto it = pidx.find({h.src_vert[i], -1});
+      if (it == pidx.end())
+        return fail(ctx, HF_EINVAL, "instance " + std::to_string(b) + ": injection vertex is not on a fluid face");
+      loc_src[b].push_back(it->second);
+    }
   }
-  std::sort(vkeys.begin(), vkeys.end());
-  vkeys.erase(std::unique(vkeys.begin(), vkeys.end()), vkeys.end());
-  std::sort(ekeys.begin(), ekeys.end());
-  ekeys.erase(std::unique(ekeys.begin(), ekeys.end()), ekeys.end());
-  std::map<std::pair<int64_t, int64_t>, int32_t> pidx;
-  h.pkeys.clear();
-  for (auto &k : vkeys) { pidx[k] = (int32_t)pidx.size(); h.pkeys.push_back(k.first); h.pkeys.push_back(-1); }
-  for (auto &k : ekeys) { pidx[k] = (int32_t)pidx.size(); h.pkeys.push_back(k.first); h.pkeys.push_back(k.second); }
-  s.n_p = (int64_t)pidx.size();
-  if (s.n_p > 4096) return fail(ctx, HF_EINVAL, "more than 4096 pressure nodes (dense pressure block limit)");
-  h.face_pn.assign(s.n_act * NNF, -1);
-  for (int64_t a = 0; a < s.n_act; ++a) {
-    face_keys(h.act_face[a], ks);
-    for (int k = 0; k < NNF; ++k) h.face_pn[a * NNF + k] = pidx.at(ks[k]);
+
+  // ---- offsets and concatenation --------------------------------------------
+  ctx->eoff.assign(B + 1, 0);
+  ctx->foff.assign(B + 1, 0);
+  ctx->voff.assign(B + 1, 0);
+  ctx->doff.assign(B + 1, 0);
+  ctx->poff.assign(B + 1, 0);
+  ctx->aoff.assign(B + 1, 0);
+  for (int b = 0; b < B; ++b) {
+    const InstHost &h = ctx->inst[b];
+    ctx->eoff[b + 1] = ctx->eoff[b] + h.ne;
+    ctx->foff[b + 1] = ctx->foff[b] + h.nf;
+    ctx->voff[b + 1] = ctx->voff[b] + h.n_vert;
+    ctx->doff[b + 1] = ctx->doff[b] + h.n_p * h.n_p;
+    ctx->poff[b + 1] = ctx->poff[b] + (int32_t)h.n_p;
+    ctx->aoff[b + 1] = ctx->aoff[b] + (int32_t)h.n_act;
   }
-  std::vector<int32_t> src_node;
-  for (size_t i = 0; i < h.src_vert.size(); ++i) {
-    auto it = pidx.find({h.src_vert[i], -1});
-    if (it == pidx.end()) return fail(ctx, HF_EINVAL, "injection vertex is not on a fluid face");
-    src_node.push_back(it->second);
+  if (ctx->eoff[B] > (int64_t)INT32_MAX / 8 || ctx->voff[B] > (int64_t)INT32_MAX / 4 ||
+      ctx->foff[B] > (int64_t)INT32_MAX / 16)
+    return fail(ctx, HF_EINVAL, "instances too large together");
+  s.n_vert = ctx->voff[B];
+  s.ne = ctx->eoff[B];
+  s.nf = ctx->foff[B];
+  s.n_u = s.ne * BU;
+  s.n_p = ctx->poff[B];
+  s.n_act = ctx->aoff[B];
+  std::vector<double> xyz, src_q0;
+  std::vector<int32_t> elem, face_vert, face_em, face_ep, fperm_m, fperm_p, face_lfm, nbr, fid;
+  std::vector<int32_t> slot, act_face, face_pn, src_node, einst, pinst;
+  std::vector<uint32_t> clamp;
+  std::vector<uint8_t> qp_state, beta;
+  for (int b = 0; b < B; ++b) {
+    const InstHost &h = ctx->inst[b];
+    const int32_t vo = (int32_t)ctx->voff[b], eo = (int32_t)ctx->eoff[b], fo = (int32_t)ctx->foff[b];
+    const int32_t po = ctx->poff[b], ao = ctx->aoff[b];
+    xyz.insert(xyz.end(), h.xyz.begin(), h.xyz.end());
+    for (int32_t v : h.elem) elem.push_back(v + vo);
+    for (int32_t v : h.face_vert) face_vert.push_back(v + vo);
+    for (int32_t e : h.face_em) face_em.push_back(e + eo);
+    for (int32_t e : h.face_ep) face_ep.push_back(e + eo);
+    fperm_m.insert(fperm_m.end(), h.fperm_m.begin(), h.fperm_m.end());
+    fperm_p.insert(fperm_p.end(), h.fperm_p.begin(), h.fperm_p.end());
+    face_lfm.insert(face_lfm.end(), h.face_lfm.begin(), h.face_lfm.end());
+    for (int32_t e : h.nbr) nbr.push_back(e < 0 ? -1 : e + eo);
+    for (int32_t f : h.fid) fid.push_back(f < 0 ? -1 : f + fo);
+    clamp.insert(clamp.end(), h.clamp.begin(), h.clamp.end());
+    qp_state.insert(qp_state.end(), h.qp_state.begin(), h.qp_state.end());
+    beta.insert(beta.end(), h.beta.begin(), h.beta.end());
+    std::vector<int32_t> sl(h.nf, -1);
+    for (size_t a = 0; a < loc_act[b].size(); ++a) sl[loc_act[b][a]] = (int32_t)a + ao;
+    slot.insert(slot.end(), sl.begin(), sl.end());
+    for (int32_t f : loc_act[b]) act_face.push_back(f + fo);
+    for (int32_t pn : loc_face_pn[b]) face_pn.push_back(pn + po);
+    for (int32_t sn : loc_src[b]) src_node.push_back(sn + po);
+    src_q0.insert(src_q0.end(), h.src_q0.begin(), h.src_q0.end());
+    einst.insert(einst.end(), (size_t)h.ne, b);
+    pinst.insert(pinst.end(), (size_t)h.n_p, b);
   }
   s.n_src = (int64_t)src_node.size();
-  // ---- coupling strips: per element, the pressure nodes of its fluid faces
+
+  // ---- coupling strips: per element, the pressure nodes of its fluid faces --
   std::vector<int64_t> sp_ptr(s.ne + 1, 0);
   std::vector<int32_t> sp_pnode, sp_elem, sp_se, strip_elems, fs_idx(s.ne * NF * NNF, -1);
   std::vector<int64_t> t_ptr(1, 0);
   for (int64_t e = 0; e < s.ne; ++e) {
     std::vector<int32_t> nodes;
     for (int lf = 0; lf < NF; ++lf) {
-      int32_t f = h.fid[e * NF + lf];
-      if (f < 0 || !h.beta[f]) continue;
-      for (int k = 0; k < NNF; ++k) nodes.push_back(h.face_pn[(int64_t)h.slot[f] * NNF + k]);
+      int32_t f = fid[e * NF + lf];
+      if (f < 0 || !beta[f]) continue;
+      for (int k = 0; k < NNF; ++k) nodes.push_back(face_pn[(int64_t)slot[f] * NNF + k]);
     }
     std::sort(nodes.begin(), nodes.end());
     nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
     sp_ptr[e + 1] = sp_ptr[e] + (int64_t)nodes.size();
-    if (!nodes.empty()) {
-      if (nodes.size() > 32) return fail(ctx, HF_EINVAL, "coupling strip too long");
-      const int32_t se = (int32_t)strip_elems.size();
-      strip_elems.push_back((int32_t)e);
-      t_ptr.push_back(t_ptr.back() + (int64_t)nodes.size() * (int64_t)nodes.size());
-      for (int32_t nd : nodes) {
-        sp_pnode.push_back(nd);
-        sp_elem.push_back((int32_t)e);
-        sp_se.push_back(se);
-      }
-      for (int lf = 0; lf < NF; ++lf) {
-        int32_t f = h.fid[e * NF + lf];
-        if (f < 0 || !h.beta[f]) continue;
-        for (int k = 0; k < NNF; ++k) {
-          int32_t nd = h.face_pn[(int64_t)h.slot[f] * NNF + k];
-          int pos = (int)(std::lower_bound(nodes.begin(), nodes.end(), nd) - nodes.begin());
-          fs_idx[(e * NF + lf) * NNF + k] = (int32_t)(sp_ptr[e] + pos);
-        }
+    if (nodes.empty()) continue;
+    if (nodes.size() > 32) return fail(ctx, HF_EINVAL, "coupling strip too long");
+    const int32_t se = (int32_t)strip_elems.size();
+    strip_elems.push_back((int32_t)e);
+    t_ptr.push_back(t_ptr.back() + (int64_t)nodes.size() * (int64_t)nodes.size());
+    for (int32_t nd : nodes) {
+      sp_pnode.push_back(nd);
+      sp_elem.push_back((int32_t)e);
+      sp_se.push_back(se);
+    }
+    for (int lf = 0; lf < NF; ++lf) {
+      int32_t f = fid[e * NF + lf];
+      if (f < 0 || !beta[f]) continue;
+      for (int k = 0; k < NNF; ++k) {
+        int32_t nd = face_pn[(int64_t)slot[f] * NNF + k];
+        int pos = (int)(std::lower_bound(nodes.begin(), nodes.end(), nd) - nodes.begin());
+        fs_idx[(e * NF + lf) * NNF + k] = (int32_t)(sp_ptr[e] + pos);
       }
     }
   }
@@ -570,7 +901,7 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
   {
     std::vector<std::vector<std::pair<int32_t, int32_t>>> lists(s.n_p);
     for (int64_t a = 0; a < s.n_act; ++a)
-      for (int k = 0; k < NNF; ++k) lists[h.face_pn[a * NNF + k]].push_back({(int32_t)a, k});
+      for (int k = 0; k < NNF; ++k) lists[face_pn[a * NNF + k]].push_back({(int32_t)a, k});
     for (int64_t i = 0; i < s.n_p; ++i) {
       pf_ptr[i + 1] = pf_ptr[i] + (int32_t)lists[i].size();
       for (auto &pr : lists[i]) {
@@ -579,13 +910,13 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
       }
     }
   }
-  // ---- block pattern: diagonal, then one block per interior local face ----
+  // ---- block pattern: diagonal, then one block per interior local face ------
   std::vector<int64_t> blk_ptr(s.ne + 1, 0);
   std::vector<int32_t> blk_col, blk_of(s.ne * NF, -1);
   for (int64_t e = 0; e < s.ne; ++e) {
     blk_col.push_back((int32_t)e);
     for (int lf = 0; lf < NF; ++lf) {
-      int32_t nb = h.nbr[e * NF + lf];
+      int32_t nb = nbr[e * NF + lf];
       if (nb < 0) continue;
       blk_of[e * NF + lf] = (int32_t)blk_col.size();
       blk_col.push_back(nb);
@@ -597,45 +928,55 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
   std::vector<int32_t> ident_col(s.ne);
   for (int64_t e = 0; e <= s.ne; ++e) ident_ptr[e] = e;
   for (int64_t e = 0; e < s.ne; ++e) ident_col[e] = (int32_t)e;
-  // bounding box extent (fluid-row scale)
-  double L = 0.0;
-  for (int c = 0; c < dim; ++c) {
-    double lo = 1e300, hi = -1e300;
-    for (int64_t v = 0; v < s.n_vert; ++v) {
-      lo = std::min(lo, h.xyz[v * dim + c]);
-      hi = std::max(hi, h.xyz[v * dim + c]);
-    }
-    L = std::max(L, hi - lo);
+  // ---- reduction chunks: at most kChunkRows rows, never across instances ----
+  std::vector<int64_t> c_row0;
+  std::vector<int32_t> c_len, c_inst, cptr(B + 1, 0);
+  for (int b = 0; b < B; ++b) {
+    auto add = [&](int64_t r0, int64_t r1) {
+      for (int64_t r = r0; r < r1; r += kChunkRows) {
+        c_row0.push_back(r);
+        c_len.push_back((int32_t)std::min<int64_t>(kChunkRows, r1 - r));
+        c_inst.push_back(b);
+      }
+    };
+    add(ctx->eoff[b] * BU, ctx->eoff[b + 1] * BU);
+    add(s.n_u + ctx->poff[b], s.n_u + ctx->poff[b + 1]);
+    cptr[b + 1] = (int32_t)c_row0.size();
   }
-  h.bbox_L = L;
+  // ---- per-instance parameters ------------------------------------------------
+  ctx->ipar.assign(B, InstPar{});
+  for (int b = 0; b < B; ++b) {
+    inst_par(ctx->inst[b].mat, ctx->ipar[b]);
+    ctx->ipar[b].s_p = 1.0;
+  }
 
-  // ---- device data -----------------------------------------------------------
+  // ---- device data ---------------------------------------------------------------
   DevMesh &m = ctx->m;
-  TRY(upload(ctx, &m.xyz, h.xyz));
-  TRY(upload(ctx, &m.elem_vert, h.elem));
+  TRY(upload(ctx, &m.xyz, xyz));
+  TRY(upload(ctx, &m.elem_vert, elem));
   TRY(dalloc(ctx, &m.gl, s.ne * NF * dim));
   TRY(dalloc(ctx, &m.detabs, s.ne));
-  TRY(upload(ctx, &m.nbr, h.nbr));
-  TRY(upload(ctx, &m.fid, h.fid));
+  TRY(upload(ctx, &m.nbr, nbr));
+  TRY(upload(ctx, &m.fid, fid));
   TRY(upload(ctx, &m.blk_of, blk_of));
-  TRY(upload(ctx, &m.clamp, h.clamp));
+  TRY(upload(ctx, &m.clamp, clamp));
   TRY(upload(ctx, &m.blk_ptr, blk_ptr));
   TRY(upload(ctx, &m.blk_col, blk_col));
-  TRY(upload(ctx, &m.face_vert, h.face_vert));
-  TRY(upload(ctx, &m.face_em, h.face_em));
-  TRY(upload(ctx, &m.face_ep, h.face_ep));
-  TRY(upload(ctx, &m.fperm_m, h.fperm_m));
-  TRY(upload(ctx, &m.fperm_p, h.fperm_p));
-  TRY(upload(ctx, &m.face_lfm, h.face_lfm));
+  TRY(upload(ctx, &m.face_vert, face_vert));
+  TRY(upload(ctx, &m.face_em, face_em));
+  TRY(upload(ctx, &m.face_ep, face_ep));
+  TRY(upload(ctx, &m.fperm_m, fperm_m));
+  TRY(upload(ctx, &m.fperm_p, fperm_p));
+  TRY(upload(ctx, &m.face_lfm, face_lfm));
   TRY(dalloc(ctx, &m.normal, s.nf * dim));
   TRY(dalloc(ctx, &m.area, s.nf));
   TRY(dalloc(ctx, &m.hf, s.nf));
   TRY(dalloc(ctx, &m.ginv, s.nf * (dim - 1) * (dim - 1)));
-  TRY(upload(ctx, &m.qp_state, h.qp_state));
-  TRY(upload(ctx, &m.beta, h.beta));
-  TRY(upload(ctx, &m.slot, h.slot));
-  TRY(upload(ctx, &m.act_face, h.act_face));
-  TRY(upload(ctx, &m.face_pn, h.face_pn));
+  TRY(upload(ctx, &m.qp_state, qp_state));
+  TRY(upload(ctx, &m.beta, beta));
+  TRY(upload(ctx, &m.slot, slot));
+  TRY(upload(ctx, &m.act_face, act_face));
+  TRY(upload(ctx, &m.face_pn, face_pn));
   TRY(upload(ctx, &m.fs_idx, fs_idx));
   TRY(upload(ctx, &m.sp_ptr, sp_ptr));
   TRY(upload(ctx, &m.sp_pnode, sp_pnode));
@@ -647,43 +988,79 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
   TRY(upload(ctx, &m.pf_fa, pf_fa));
   TRY(upload(ctx, &m.pf_k, pf_k));
   TRY(upload(ctx, &m.src_node, src_node));
-  TRY(upload(ctx, &m.src_q0, h.src_q0));
+  TRY(upload(ctx, &m.src_q0, src_q0));
   TRY(upload(ctx, &m.strip_elems, strip_elems));
   TRY(upload(ctx, &m.t_ptr, t_ptr));
   TRY(upload(ctx, &m.ident_ptr, ident_ptr));
   TRY(upload(ctx, &m.ident_col, ident_col));
+  TRY(upload(ctx, &ctx->d_ipar, ctx->ipar));
+  TRY(upload(ctx, &ctx->d_einst, einst));
+  TRY(upload(ctx, &ctx->d_pinst, pinst));
+  TRY(upload(ctx, &ctx->d_poff, ctx->poff));
+  TRY(upload(ctx, &ctx->d_aoff, ctx->aoff));
+  TRY(upload(ctx, &ctx->d_doff, ctx->doff));
+  KrylovDev &kd = ctx->kd;
+  kd.n_inst = B;
+  kd.n_chunks = (int)c_row0.size();
+  {
+    int64_t *p0;
+    int32_t *p1, *p2, *p3;
+    TRY(upload(ctx, &p0, c_row0));
+    TRY(upload(ctx, &p1, c_len));
+    TRY(upload(ctx, &p2, c_inst));
+    TRY(upload(ctx, &p3, cptr));
+    kd.c_row0 = p0;
+    kd.c_len = p1;
+    kd.c_inst = p2;
+    kd.cptr = p3;
+  }
+  TRY(dalloc(ctx, &kd.solving, B));
+  TRY(dalloc(ctx, &kd.kconv, B));
+  TRY(dalloc(ctx, &kd.its, B));
+  TRY(dalloc(ctx, &kd.status, B));
+  TRY(dalloc(ctx, &kd.nbasis, B));
+  TRY(dalloc(ctx, &kd.itmax, B));
+  TRY(dalloc(ctx, &kd.bnorm, B));
+  TRY(dalloc(ctx, &ctx->k_n1, B));
+  TRY(dalloc(ctx, &ctx->k_n2, B));
+  TRY(dalloc(ctx, &ctx->k_scale, B));
+  TRY(dalloc(ctx, &ctx->k_est, B));
+  TRY(dalloc(ctx, &ctx->k_beta2, B));
+  TRY(dalloc(ctx, &ctx->k_coef, B));
+  TRY(dalloc(ctx, &ctx->k_flag, B));
+  TRY(dalloc(ctx, &ctx->k_upd, B));
+  TRY(dalloc(ctx, &ctx->k_count, 1));
   // system and work buffers
   const int64_t N = s.N();
   TRY(dalloc(ctx, &ctx->xs, N));
   TRY(dalloc(ctx, &ctx->xs_save, N));
   TRY(dalloc(ctx, &ctx->xs_start, N));
-  TRY(dalloc(ctx, &ctx->w_old, s.nf * s.nqf));
-  TRY(dalloc(ctx, &ctx->w_tmp, s.nf * s.nqf));
+  TRY(dalloc(ctx, &ctx->w_old, s.nf * NQ));
+  TRY(dalloc(ctx, &ctx->w_tmp, s.nf * NQ));
   TRY(dalloc(ctx, &ctx->R, N));
   TRY(dalloc(ctx, &ctx->A, s.n_blocks * BU * BU));
   TRY(dalloc(ctx, &ctx->Bs, s.n_strip * BU));
   TRY(dalloc(ctx, &ctx->Cs, s.n_strip * BU));
-  TRY(dalloc(ctx, &ctx->D, s.n_p * s.n_p));
-  TRY(dalloc(ctx, &ctx->S, s.n_p * s.n_p));
-  TRY(dalloc(ctx, &ctx->Sinv, s.n_p * s.n_p));
-  TRY(dalloc(ctx, &ctx->Sinv32, s.n_p * s.n_p));
+  TRY(dalloc(ctx, &ctx->D, ctx->doff[B]));
+  TRY(dalloc(ctx, &ctx->S, ctx->doff[B]));
+  TRY(dalloc(ctx, &ctx->Sinv, ctx->doff[B]));
+  TRY(dalloc(ctx, &ctx->Sinv32, ctx->doff[B]));
   TRY(dalloc(ctx, &ctx->T, s.n_t));
   TRY(dalloc(ctx, &ctx->inv, s.ne * BU * BU));
-  TRY(dalloc(ctx, &ctx->flag, 4));
+  TRY(dalloc(ctx, &ctx->flag, B));
   TRY(dalloc(ctx, &ctx->dx, N));
   TRY(dalloc(ctx, &ctx->rhs, N));
   TRY(dalloc(ctx, &ctx->r64, N));
   TRY(dalloc(ctx, &ctx->t64, N));
-  // reduction partials: the largest of (blocks x outputs) over every reduction
-  const int64_t n_partial = std::max<int64_t>((int64_t)1024 * kMaxKrylov,
-                                              (int64_t)ortho_blocks(N) * (kMaxKrylov + 1));
-  TRY(dalloc(ctx, &ctx->partial, n_partial));
-  TRY(dalloc(ctx, &ctx->red, 4 * kMaxKrylov));
+  // reduction partials: chunks x (largest number of outputs of one reduction)
+  TRY(dalloc(ctx, &ctx->partial, (int64_t)kd.n_chunks * (kMaxKrylov + 1)));
+  TRY(dalloc(ctx, &ctx->red, 4 * (int64_t)B));
+  TRY(ensure_host(ctx, 4 * (size_t)B + 8, 4 * (size_t)B + 8, 8 * (size_t)B + 64));
   HIPCHK(hipMemsetAsync(ctx->xs, 0, N * sizeof(double), ctx->stream));
-  HIPCHK(hipMemsetAsync(ctx->w_old, 0, s.nf * s.nqf * sizeof(double), ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->w_old, 0, s.nf * NQ * sizeof(double), ctx->stream));
   HIPCHK(launch_set_rules(ctx->rules, ctx->stream));
   HIPCHK(launch_geometry(kparams(ctx), ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  TRY(sync(ctx));
   ctx->stage = 2;
   return HF_OK;
 }
@@ -692,42 +1069,79 @@ extern "C" hf_status hf_get_sizes(hf_ctx *ctx, int32_t inst, hf_sizes *out) {
   TRY(check_ctx(ctx, 1));
   TRY(check_inst(ctx, inst));
   if (!out) return fail(ctx, HF_EINVAL, "null output");
-  const Sizes &s = ctx->s;
-  out->n_elem = s.ne;
-  out->nodes_per_elem = s.nn;
-  out->n_u = s.n_u;
-  out->n_p = ctx->stage >= 2 ? s.n_p : 0;
-  out->n_face = s.nf;
-  out->n_blocks = ctx->stage >= 2 ? s.n_blocks : 0;
-  out->dim = s.dim;
-  out->order = s.order;
-  out->nq_face = s.nqf;
-  out->block_size = s.bu;
+  const InstHost &h = ctx->inst[inst];
+  const bool fin = ctx->stage >= 2;
+  std::memset(out, 0, sizeof(*out));
+  out->n_elem = h.ne;
+  out->nodes_per_elem = ctx->s.nn;
+  out->n_u = h.ne * ctx->s.bu;
+  out->n_p = fin ? h.n_p : 0;
+  out->n_face = h.nf;
+  out->n_blocks = fin ? h.ne + 2 * h.nf : 0;
+  out->u_offset = fin ? ctx->eoff[inst] * ctx->s.bu : 0;
+  out->p_offset = fin ? ctx->s.n_u + ctx->poff[inst] : 0;
+  out->n_total = fin ? ctx->s.N() : 0;
+  out->dim = ctx->s.dim;
+  out->order = ctx->s.order;
+  out->nq_face = ctx->s.nqf;
+  out->block_size = ctx->s.bu;
   return HF_OK;
 }
 
 extern "C" hf_status hf_get_pnodes(hf_ctx *ctx, int32_t inst, int64_t *keys) {
   TRY(check_ctx(ctx, 2));
   TRY(check_inst(ctx, inst));
-  if (!keys && ctx->s.n_p) return fail(ctx, HF_EINVAL, "null output");
-  if (ctx->s.n_p) std::memcpy(keys, ctx->h.pkeys.data(), ctx->h.pkeys.size() * sizeof(int64_t));
+  const InstHost &h = ctx->inst[inst];
+  if (!keys && h.n_p) return fail(ctx, HF_EINVAL, "null output");
+  if (h.n_p) std::memcpy(keys, h.pkeys.data(), h.pkeys.size() * sizeof(int64_t));
   return HF_OK;
 }
 
 // ===========================================================================
 // State
 // ===========================================================================
+static double *useg(hf_ctx *ctx, double *v, int b) { return v + ctx->eoff[b] * ctx->s.bu; }
+static double *pseg(hf_ctx *ctx, double *v, int b) { return v + ctx->s.n_u + ctx->poff[b]; }
+static int64_t ulen(const hf_ctx *ctx, int b) { return ctx->inst[b].ne * ctx->s.bu; }
+static int64_t plen(const hf_ctx *ctx, int b) { return ctx->inst[b].n_p; }
+
+// copy instance b's part of a state vector (device to device)
+static hf_status copy_inst(hf_ctx *ctx, double *dst, double *src, int b) {
+  HIPCHK(hipMemcpyAsync(useg(ctx, dst, b), useg(ctx, src, b), ulen(ctx, b) * sizeof(double),
+                        hipMemcpyDeviceToDevice, ctx->stream));
+  if (plen(ctx, b))
+    HIPCHK(hipMemcpyAsync(pseg(ctx, dst, b), pseg(ctx, src, b), plen(ctx, b) * sizeof(double),
+                          hipMemcpyDeviceToDevice, ctx->stream));
+  return HF_OK;
+}
+
+// fluid-row scale of every instance from its w_old
 static hf_status update_fluid_scale(hf_ctx *ctx) {
-  const double delta_c = 2.0 * ctx->mat.G_c / ctx->mat.sigma_c;
-  double wmax = -1e300;
+  const int B = nI(ctx);
   if (ctx->s.n_act) {
     HIPCHK(launch_wmax(kparams(ctx), ctx->w_old, ctx->red, ctx->stream));
-    TRY(sync_read(ctx, 1));
-    wmax = ctx->red_h[0];
+    TRY(get_d(ctx, ctx->red, B));
   }
-  const double w_ref = std::max(wmax, 0.01 * delta_c);
-  const double L = ctx->h.bbox_L;
-  ctx->s_p = 12.0 * ctx->mat.mu * std::pow(L / w_ref, 3);
+  for (int b = 0; b < B; ++b) {
+    const Mat &m = ctx->inst[b].mat;
+    const double delta_c = 2.0 * m.G_c / m.sigma_c;
+    const double wmax = ctx->inst[b].n_act ? ctx->hd[b] : -1e300;
+    const double w_ref = std::max(wmax, 0.01 * delta_c);
+    ctx->ipar[b].s_p = 12.0 * m.mu * std::pow(ctx->inst[b].bbox_L / w_ref, 3);
+  }
+  TRY(put(ctx, ctx->d_ipar, ctx->ipar));
+  return HF_OK;
+}
+
+static hf_status set_state_impl(hf_ctx *ctx, int32_t inst, const double *u, const double *p,
+                                const double *w_old, hipMemcpyKind kind) {
+  const InstHost &h = ctx->inst[inst];
+  const int nq = ctx->s.nqf;
+  HIPCHK(hipMemcpyAsync(useg(ctx, ctx->xs, inst), u, ulen(ctx, inst) * sizeof(double), kind, ctx->stream));
+  if (h.n_p) HIPCHK(hipMemcpyAsync(pseg(ctx, ctx->xs, inst), p, h.n_p * sizeof(double), kind, ctx->stream));
+  if (w_old)
+    HIPCHK(hipMemcpyAsync(ctx->w_old + ctx->foff[inst] * nq, w_old, h.nf * nq * sizeof(double), kind,
+                          ctx->stream));
   return HF_OK;
 }
 
@@ -735,18 +1149,14 @@ extern "C" hf_status hf_set_state(hf_ctx *ctx, int32_t inst, const double *u, co
                                   const double *w_old) {
   TRY(check_ctx(ctx, 2));
   TRY(check_inst(ctx, inst));
-  const Sizes &s = ctx->s;
-  if (!u || (s.n_p && !p)) return fail(ctx, HF_EINVAL, "null state array");
-  if (!all_finite(u, s.n_u) || (s.n_p && !all_finite(p, s.n_p)) ||
-      (w_old && !all_finite(w_old, s.nf * s.nqf)))
+  const InstHost &h = ctx->inst[inst];
+  if (!u || (h.n_p && !p)) return fail(ctx, HF_EINVAL, "null state array");
+  if (!all_finite(u, ulen(ctx, inst)) || (h.n_p && !all_finite(p, h.n_p)) ||
+      (w_old && !all_finite(w_old, h.nf * ctx->s.nqf)))
     return fail(ctx, HF_ENONFINITE, "non-finite value in the state");
-  HIPCHK(hipMemcpyAsync(ctx->xs, u, s.n_u * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-  if (s.n_p)
-    HIPCHK(hipMemcpyAsync(ctx->xs + s.n_u, p, s.n_p * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-  if (w_old)
-    HIPCHK(hipMemcpyAsync(ctx->w_old, w_old, s.nf * s.nqf * sizeof(double), hipMemcpyHostToDevice,
-                          ctx->stream));
+  TRY(set_state_impl(ctx, inst, u, p, w_old, hipMemcpyHostToDevice));
   TRY(update_fluid_scale(ctx));
+  TRY(sync(ctx));
   ctx->stage = 3;
   return HF_OK;
 }
@@ -755,18 +1165,14 @@ extern "C" hf_status hf_set_state_device(hf_ctx *ctx, int32_t inst, const double
                                          const double *p, const double *w_old) {
   TRY(check_ctx(ctx, 2));
   TRY(check_inst(ctx, inst));
-  const Sizes &s = ctx->s;
-  if (!u || (s.n_p && !p)) return fail(ctx, HF_EINVAL, "null state array");
-  HIPCHK(hipMemcpyAsync(ctx->xs, u, s.n_u * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-  if (s.n_p)
-    HIPCHK(hipMemcpyAsync(ctx->xs + s.n_u, p, s.n_p * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-  if (w_old)
-    HIPCHK(hipMemcpyAsync(ctx->w_old, w_old, s.nf * s.nqf * sizeof(double), hipMemcpyDeviceToDevice,
-                          ctx->stream));
-  HIPCHK(launch_norm2(ctx->xs, s.N(), ctx->partial, ctx->red, ctx->stream));
-  TRY(sync_read(ctx, 1));
-  if (!std::isfinite(ctx->red_h[0])) return fail(ctx, HF_ENONFINITE, "non-finite value in the state");
+  const InstHost &h = ctx->inst[inst];
+  if (!u || (h.n_p && !p)) return fail(ctx, HF_EINVAL, "null state array");
+  TRY(set_state_impl(ctx, inst, u, p, w_old, hipMemcpyDeviceToDevice));
+  HIPCHK(launch_seg_norms(ctx->kd, ctx->xs, ctx->partial, ctx->red, ctx->stream));
+  TRY(get_d(ctx, ctx->red, nI(ctx)));
+  if (!std::isfinite(ctx->hd[inst])) return fail(ctx, HF_ENONFINITE, "non-finite value in the state");
   TRY(update_fluid_scale(ctx));
+  TRY(sync(ctx));
   ctx->stage = 3;
   return HF_OK;
 }
@@ -775,36 +1181,44 @@ extern "C" hf_status hf_get_state(hf_ctx *ctx, int32_t inst, double *u, double *
                                   double *w_old) {
   TRY(check_ctx(ctx, 2));
   TRY(check_inst(ctx, inst));
-  const Sizes &s = ctx->s;
-  if (u) HIPCHK(hipMemcpyAsync(u, ctx->xs, s.n_u * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  if (p && s.n_p)
-    HIPCHK(hipMemcpyAsync(p, ctx->xs + s.n_u, s.n_p * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  const InstHost &h = ctx->inst[inst];
+  const int nq = ctx->s.nqf;
+  if (u)
+    HIPCHK(hipMemcpyAsync(u, useg(ctx, ctx->xs, inst), ulen(ctx, inst) * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+  if (p && h.n_p)
+    HIPCHK(hipMemcpyAsync(p, pseg(ctx, ctx->xs, inst), h.n_p * sizeof(double), hipMemcpyDeviceToHost,
+                          ctx->stream));
   if (w) {
     HIPCHK(launch_set_rules(ctx->rules, ctx->stream));
     HIPCHK(launch_opening(kparams(ctx), ctx->xs, ctx->w_tmp, ctx->stream));
-    HIPCHK(hipMemcpyAsync(w, ctx->w_tmp, s.nf * s.nqf * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(w, ctx->w_tmp + ctx->foff[inst] * nq, h.nf * nq * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
   }
   if (w_old)
-    HIPCHK(hipMemcpyAsync(w_old, ctx->w_old, s.nf * s.nqf * sizeof(double), hipMemcpyDeviceToHost,
-                          ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipMemcpyAsync(w_old, ctx->w_old + ctx->foff[inst] * nq, h.nf * nq * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+  TRY(sync(ctx));
   return HF_OK;
 }
 
 extern "C" hf_status hf_get_state_device(hf_ctx *ctx, int32_t inst, double *u, double *p) {
   TRY(check_ctx(ctx, 2));
   TRY(check_inst(ctx, inst));
-  const Sizes &s = ctx->s;
-  if (u) HIPCHK(hipMemcpyAsync(u, ctx->xs, s.n_u * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-  if (p && s.n_p)
-    HIPCHK(hipMemcpyAsync(p, ctx->xs + s.n_u, s.n_p * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  if (u)
+    HIPCHK(hipMemcpyAsync(u, useg(ctx, ctx->xs, inst), ulen(ctx, inst) * sizeof(double),
+                          hipMemcpyDeviceToDevice, ctx->stream));
+  if (p && plen(ctx, inst))
+    HIPCHK(hipMemcpyAsync(p, pseg(ctx, ctx->xs, inst), plen(ctx, inst) * sizeof(double),
+                          hipMemcpyDeviceToDevice, ctx->stream));
   return HF_OK;
 }
 
 // ===========================================================================
 // Assembly
 // ===========================================================================
-static hf_status do_assemble(hf_ctx *ctx, double *res_norm) {
+// R, J of every instance; rn[b] = ||R_b|| (may be non-finite: callers decide)
+static hf_status do_assemble(hf_ctx *ctx, std::vector<double> &rn) {
   const Sizes &s = ctx->s;
   KParams kp = kparams(ctx);
   HIPCHK(launch_set_rules(ctx->rules, ctx->stream));  // the rule tables are module-global
@@ -813,11 +1227,10 @@ static hf_status do_assemble(hf_ctx *ctx, double *res_norm) {
     HIPCHK(launch_assemble(kp, ctx->xs, ctx->xs + s.n_u, ctx->w_old, ctx->A, ctx->R, ctx->Bs,
                            ctx->Cs, ctx->D, ctx->stream));
   }
-  HIPCHK(launch_norm2(ctx->R, s.N(), ctx->partial, ctx->red, ctx->stream));
-  TRY(sync_read(ctx, 1));
-  const double rn = std::sqrt(ctx->red_h[0]);
-  if (!std::isfinite(rn)) return fail(ctx, HF_ENONFINITE, "non-finite residual");
-  if (res_norm) *res_norm = rn;
+  HIPCHK(launch_seg_norms(ctx->kd, ctx->R, ctx->partial, ctx->red, ctx->stream));
+  TRY(get_d(ctx, ctx->red, nI(ctx)));
+  rn.assign(nI(ctx), 0.0);
+  for (int b = 0; b < nI(ctx); ++b) rn[b] = std::sqrt(ctx->hd[b]);
   ctx->have32 = false;
   return HF_OK;
 }
@@ -825,13 +1238,19 @@ static hf_status do_assemble(hf_ctx *ctx, double *res_norm) {
 extern "C" hf_status hf_assemble(hf_ctx *ctx, double *res_norm) {
   TRY(check_ctx(ctx, 3));
   HIPCHK(hipSetDevice(ctx->opt.device));
-  TRY(do_assemble(ctx, res_norm));
+  std::vector<double> rn;
+  TRY(do_assemble(ctx, rn));
   ctx->stage = std::max(ctx->stage, 4);
+  for (int b = 0; b < nI(ctx); ++b) {
+    if (res_norm) res_norm[b] = rn[b];
+    if (!std::isfinite(rn[b]))
+      return fail(ctx, HF_ENONFINITE, "instance " + std::to_string(b) + ": non-finite residual");
+  }
   return HF_OK;
 }
 
 // ===========================================================================
-// Krylov solvers
+// Batched Krylov solvers
 // ===========================================================================
 template <typename T>
 struct Ops {
@@ -842,7 +1261,37 @@ template <typename T>
 static hf_status ensure_ws(hf_ctx *ctx, KrylovWs<T> &ws) {
   const int m = ctx->opt.gmres_m;
   const int64_t N = ctx->s.N();
-  if (ws.V && ws.m >= m && ws.n == N) return HF_OK;
+  const int B = nI(ctx);
+  if (ctx->kd_m < m) {
+    KrylovDev &kd = ctx->kd;
+    TRY(sync(ctx));
+    dfree(ctx, &kd.H);
+    dfree(ctx, &kd.cs);
+    dfree(ctx, &kd.sn);
+    dfree(ctx, &kd.g);
+    dfree(ctx, &ctx->k_s1);
+    dfree(ctx, &ctx->k_s2);
+    dfree(ctx, &ctx->k_y);
+    TRY(dalloc(ctx, &kd.H, (int64_t)B * (m + 1) * m));
+    TRY(dalloc(ctx, &kd.cs, (int64_t)B * m));
+    TRY(dalloc(ctx, &kd.sn, (int64_t)B * m));
+    TRY(dalloc(ctx, &kd.g, (int64_t)B * (m + 1)));
+    TRY(dalloc(ctx, &ctx->k_s1, (int64_t)B * (m + 2)));
+    TRY(dalloc(ctx, &ctx->k_s2, (int64_t)B * (m + 2)));
+    TRY(dalloc(ctx, &ctx->k_y, (int64_t)B * m));
+    ctx->kd_m = m;
+    release_all_graphs(ctx);  // the captured chunks hold the old pointers
+  }
+  if (ws.V && ws.m == m && ws.n == N) return HF_OK;
+  release_graphs(ws);
+  TRY(sync(ctx));
+  dfree(ctx, &ws.V);
+  dfree(ctx, &ws.w);
+  dfree(ctx, &ws.z);
+  dfree(ctx, &ws.r);
+  dfree(ctx, &ws.t);
+  dfree(ctx, &ws.b);
+  dfree(ctx, &ws.x);
   TRY(dalloc(ctx, &ws.V, (int64_t)(m + 1) * N));
   TRY(dalloc(ctx, &ws.w, N));
   TRY(dalloc(ctx, &ws.z, N));
@@ -857,13 +1306,8 @@ static hf_status ensure_ws(hf_ctx *ctx, KrylovWs<T> &ws) {
 
 template <typename T>
 static hf_status apply_J(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *x, T *y) {
-  if (sizeof(T) == 8) {
-    ProfScope ps(ctx, P_SPMV64);
-    HIPCHK(launch_spmv<T>(kp, op.A, op.Bs, op.Cs, op.D, x, y, ctx->stream));
-  } else {
-    ProfScope ps(ctx, P_SPMV32);
-    HIPCHK(launch_spmv<T>(kp, op.A, op.Bs, op.Cs, op.D, x, y, ctx->stream));
-  }
+  ProfScope ps(ctx, sizeof(T) == 8 ? P_SPMV64 : P_SPMV32);
+  HIPCHK(launch_spmv<T>(kp, op.A, op.Bs, op.Cs, op.D, x, y, ctx->stream));
   return HF_OK;
 }
 
@@ -874,161 +1318,193 @@ static hf_status apply_M(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const
   return HF_OK;
 }
 
+// Arnoldi step j of every instance still iterating (kernel launches only, so
+// that a chunk of steps can be captured in a graph): w = J M^-1 v_j;
+// classical Gram-Schmidt h = V^T w, w -= V h, repeated once when
+// ||w1|| < ||w|| / sqrt(2) (Daniel-Gragg-Kaufman-Stewart); Givens update of
+// H and g; v_{j+1} = w / ||w||.
 template <typename T>
-static hf_status vnorm(hf_ctx *ctx, const T *x, int64_t n, double &out) {
-  HIPCHK(launch_mdot<T>(x, 0, 1, x, n, ctx->partial, ctx->red, ctx->stream));
-  TRY(sync_read(ctx, 1));
-  out = std::sqrt(ctx->red_h[0]);
+static hf_status arnoldi_step(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, KrylovWs<T> &ws,
+                              int j, double rtol) {
+  const int64_t N = ctx->s.N();
+  const KrylovDev &kd = ctx->kd;
+  const int m = ws.m, k = j + 1, ks = j + 2;
+  TRY(apply_M<T>(ctx, kp, op, ws.V + (int64_t)j * N, ws.z));
+  TRY(apply_J<T>(ctx, kp, op, ws.z, ws.w));
+  ProfScope ps(ctx, P_ORTHO);
+  HIPCHK(ks_proj<T>(kd, ws.V, N, k, ws.w, nullptr, ctx->partial, ctx->k_s1, ctx->stream));
+  HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s1, ks, ws.w, nullptr, ctx->partial, ctx->k_n1, ctx->stream));
+  HIPCHK(ks_reorth_flag(kd, ctx->k_s1 + k, ks, ctx->k_n1, ctx->k_flag, ctx->stream));
+  HIPCHK(ks_proj<T>(kd, ws.V, N, k, ws.w, ctx->k_flag, ctx->partial, ctx->k_s2, ctx->stream));
+  HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s2, ks, ws.w, ctx->k_flag, ctx->partial, ctx->k_n2,
+                      ctx->stream));
+  HIPCHK(ks_arnoldi(kd, j, m, ctx->k_s1, ks, ctx->k_s2, ks, ctx->k_flag, ctx->k_n1, ctx->k_n2, rtol,
+                    ctx->k_scale, ctx->stream));
+  HIPCHK(ks_scale<T>(kd, ws.w, ctx->k_scale, ws.V + (int64_t)(j + 1) * N, ctx->stream));
   return HF_OK;
 }
 
-static bool trace_on() {
-  static int on = -1;
-  if (on < 0) {
-    const char *e = std::getenv("HF_TRACE");
-    on = (e && *e && *e != '0') ? 1 : 0;
-  }
-  return on == 1;
-}
-
-// HF_REORTH=0 disables the second Gram-Schmidt pass (experiments only)
-static bool reorth_allowed() {
-  static int on = -1;
-  if (on < 0) {
-    const char *e = std::getenv("HF_REORTH");
-    on = (e && *e == '0') ? 0 : 1;
-  }
-  return on == 1;
-}
-
-// Right-preconditioned restarted GMRES(m) on J x = b in precision T with
-// classical Gram-Schmidt applied twice.  x starts at 0.  A cycle ends when the
-// recursive residual estimate reaches rtol ||b|| or after m steps; with
-// explicit_check the residual b - J x is then recomputed and decides.
+// Arnoldi steps j0 .. j1-1, replayed from a captured graph when enabled
 template <typename T>
-static hf_status gmres(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T *b, T *x,
-                       double rtol, int maxit, bool explicit_check, int &iters, int &restarts,
-                       double &relres) {
-  const KParams kp = kparams(ctx);
-  const int64_t N = ctx->s.N();
-  const int m = ctx->opt.gmres_m;
-  HIPCHK(hipMemsetAsync(x, 0, N * sizeof(T), ctx->stream));
-  double bnorm;
-  TRY(vnorm<T>(ctx, b, N, bnorm));
-  if (!std::isfinite(bnorm)) return fail(ctx, HF_ENONFINITE, "non-finite right-hand side");
-  if (bnorm == 0.0) {
-    relres = 0.0;
+static hf_status arnoldi_chunk(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, KrylovWs<T> &ws,
+                               int j0, int j1, double rtol) {
+  const bool graphs = ctx->opt.use_graphs && !ctx->opt.profile;
+  if (!graphs) {
+    for (int j = j0; j < j1; ++j) TRY(arnoldi_step<T>(ctx, kp, op, ws, j, rtol));
     return HF_OK;
   }
-  HIPCHK(hipMemcpyAsync(ws.r, b, N * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
-  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  double beta = bnorm;
-  while (true) {
-    if (explicit_check && beta <= rtol * bnorm) {
-      relres = beta / bnorm;
-      return HF_OK;
+  const size_t gi = (size_t)(j0 / kIterChunk);
+  if (ws.graphs.size() <= gi) ws.graphs.resize(gi + 1, nullptr);
+  if (!ws.graphs[gi]) {
+    HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    hf_status st = HF_OK;
+    for (int j = j0; j < j1 && st == HF_OK; ++j) st = arnoldi_step<T>(ctx, kp, op, ws, j, rtol);
+    hipGraph_t g = nullptr;
+    hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
+    if (st != HF_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
     }
-    if (iters >= maxit) {
-      relres = beta / bnorm;
-      return fail(ctx, HF_ENOCONV, "GMRES reached its iteration cap");
-    }
-    HIPCHK(launch_scale_copy<T>(ws.r, 1.0 / beta, ws.V, N, ctx->stream));
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
-      T *vj = ws.V + (int64_t)j * N;
-      TRY(apply_M<T>(ctx, kp, op, vj, ws.z));
-      TRY(apply_J<T>(ctx, kp, op, ws.z, ws.w));
-      const int kk = j + 1;
-      // classical Gram-Schmidt with the DGKS re-orthogonalisation test:
-      // h = V^T w, w1 = w - V h; repeat once more when ||w1|| < ||w|| / sqrt(2)
-      {
-        ProfScope ps(ctx, P_ORTHO);
-        HIPCHK(launch_proj<T>(ws.V, N, kk, ws.w, N, ctx->partial, ctx->red, ctx->stream));
-        HIPCHK(launch_orth_update<T>(ws.V, N, kk, ctx->red, ws.w, N, ctx->partial,
-                                     ctx->red + kk + 1, ctx->stream));
-      }
-      TRY(sync_read(ctx, kk + 2));
-      ++iters;
-      for (int i = 0; i < kk; ++i) H[i * m + j] = ctx->red_h[i];
-      double hn = std::sqrt(ctx->red_h[kk + 1]);
-      if (reorth_allowed() && hn < std::sqrt(0.5 * ctx->red_h[kk])) {
-        {
-          ProfScope ps(ctx, P_ORTHO);
-          HIPCHK(launch_proj<T>(ws.V, N, kk, ws.w, N, ctx->partial, ctx->red, ctx->stream));
-          HIPCHK(launch_orth_update<T>(ws.V, N, kk, ctx->red, ws.w, N, ctx->partial,
-                                       ctx->red + kk + 1, ctx->stream));
-        }
-        TRY(sync_read(ctx, kk + 2));
-        for (int i = 0; i < kk; ++i) H[i * m + j] += ctx->red_h[i];
-        hn = std::sqrt(ctx->red_h[kk + 1]);
-        ++ctx->n_reorth;
-      }
-      if (!std::isfinite(hn)) return fail(ctx, HF_ENONFINITE, "non-finite Krylov vector");
-      H[kk * m + j] = hn;
-      if (hn > 0.0) HIPCHK(launch_scale_copy<T>(ws.w, 1.0 / hn, ws.V + (int64_t)kk * N, N, ctx->stream));
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
-        H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
-        H[i * m + j] = t;
-      }
-      const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
-      if (den == 0.0) {
-        cs[j] = 1.0;
-        sn[j] = 0.0;
-      } else {
-        cs[j] = H[j * m + j] / den;
-        sn[j] = H[(j + 1) * m + j] / den;
-      }
-      H[j * m + j] = cs[j] * H[j * m + j] + sn[j] * H[(j + 1) * m + j];
-      H[(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      k = j + 1;
-      if (std::fabs(g[j + 1]) <= rtol * bnorm || iters >= maxit || hn == 0.0) break;
-    }
-    // y = H(1:k,1:k)^-1 g ; x += M^-1 V y
-    for (int i = k - 1; i >= 0; --i) {
-      double acc = g[i];
-      for (int c = i + 1; c < k; ++c) acc -= H[i * m + c] * y[c];
-      y[i] = acc / H[i * m + i];
-    }
-    std::memcpy(ctx->red_h, y.data(), k * sizeof(double));
-    HIPCHK(hipMemcpyAsync(ctx->red, ctx->red_h, k * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(launch_combine<T>(ws.V, N, k, ctx->red, ws.t, N, ctx->stream));
-    TRY(apply_M<T>(ctx, kp, op, ws.t, ws.z));
-    HIPCHK(launch_axpy_t<T>(1.0, ws.z, x, N, ctx->stream));
-    ++restarts;
-    const double est = std::fabs(g[k]);
-    if (!explicit_check && (est <= rtol * bnorm || iters >= maxit)) {
-      HIPCHK(hipStreamSynchronize(ctx->stream));
-      relres = est / bnorm;
-      return HF_OK;
-    }
-    TRY(apply_J<T>(ctx, kp, op, x, ws.w));
-    HIPCHK(launch_sub_t<T>(b, ws.w, ws.r, N, ctx->stream));
-    TRY(vnorm<T>(ctx, ws.r, N, beta));
-    if (!std::isfinite(beta)) return fail(ctx, HF_ENONFINITE, "non-finite residual in GMRES");
-    if (trace_on())
-      std::fprintf(stderr, "hf gmres(%s): it %d restart %d estimate %.3e true %.3e reorth %lld\n",
-                   sizeof(T) == 8 ? "fp64" : "fp32", iters, restarts, est / bnorm, beta / bnorm,
-                   (long long)ctx->n_reorth);
+    if (ec != hipSuccess) return fail(ctx, HF_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    hipGraphExec_t ge = nullptr;
+    ec = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ec != hipSuccess) return fail(ctx, HF_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ec));
+    ws.graphs[gi] = ge;
   }
+  HIPCHK(hipGraphLaunch(ws.graphs[gi], ctx->stream));
+  return HF_OK;
 }
 
-static hf_status build_preconditioner(hf_ctx *ctx) {
+// Right-preconditioned restarted GMRES(m) on J x = b in precision T for the
+// instances with on[b] = 1, all in the same launches.  x starts at 0.  A
+// cycle of an instance ends when its recursive residual estimate reaches
+// rtol ||b_b||, at its iteration cap cap[b], or after m steps.  With
+// explicit_check the residual b - J x is then recomputed and decides; without
+// it (the inner solve of GMRES-IR) the estimate decides.  out[b] receives the
+// iterations, cycles, relative residual and status of each solved instance.
+template <typename T>
+static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T *bvec, T *x,
+                         double rtol, bool explicit_check, std::vector<int> on,
+                         const std::vector<int> &cap, std::vector<SolveOut> &out) {
+  const KParams kp = kparams(ctx);
+  const int64_t N = ctx->s.N();
+  const int m = ws.m, B = nI(ctx);
+  KrylovDev &kd = ctx->kd;
+  hipStream_t st = ctx->stream;
+  out.assign(B, SolveOut{});
+  TRY(put(ctx, kd.solving, on));
+  TRY(put(ctx, kd.itmax, cap));
+  HIPCHK(ks_zero<T>(kd, x, 1, st));
+  HIPCHK(ks_norms<T>(kd, bvec, ctx->partial, ctx->k_beta2, st));
+  HIPCHK(ks_begin(kd, ctx->k_beta2, st));
+  HIPCHK(hipMemcpyAsync(ws.r, bvec, N * sizeof(T), hipMemcpyDeviceToDevice, st));
+  TRY(get_d(ctx, ctx->k_beta2, B));
+  std::vector<double> bnorm(B), beta2(ctx->hd, ctx->hd + B), est(B);
+  std::vector<int> its(B, 0), stat(B, 0);
+  for (int b = 0; b < B; ++b) {
+    bnorm[b] = std::sqrt(beta2[b]);
+    if (!on[b]) continue;
+    if (!std::isfinite(bnorm[b])) {
+      out[b].st = HF_ENONFINITE;
+      note(ctx, b, "non-finite right-hand side");
+      on[b] = 0;
+    } else if (bnorm[b] == 0.0) {
+      on[b] = 0;  // x = 0 solves it
+    }
+  }
+  while (true) {
+    bool any = false;
+    for (int b = 0; b < B; ++b) {
+      if (!on[b]) continue;
+      const double beta = std::sqrt(beta2[b]);
+      out[b].relres = beta / bnorm[b];
+      if (!std::isfinite(beta)) {
+        out[b].st = HF_ENONFINITE;
+        note(ctx, b, "non-finite residual in GMRES");
+        on[b] = 0;
+      } else if (explicit_check && beta <= rtol * bnorm[b]) {
+        on[b] = 0;
+      } else if (out[b].iters >= cap[b]) {
+        if (explicit_check) {
+          out[b].st = HF_ENOCONV;
+          note(ctx, b, "GMRES reached its iteration cap");
+        }
+        on[b] = 0;
+      } else {
+        any = true;
+      }
+    }
+    if (!any) break;
+    TRY(put(ctx, kd.solving, on));
+    HIPCHK(ks_cycle_start(kd, m, ctx->k_beta2, ctx->k_scale, st));
+    HIPCHK(ks_scale<T>(kd, ws.r, ctx->k_scale, ws.V, st));
+    for (int j0 = 0; j0 < m; j0 += kIterChunk) {
+      const int j1 = std::min(j0 + kIterChunk, m);
+      TRY(arnoldi_chunk<T>(ctx, kp, op, ws, j0, j1, rtol));
+      if (j1 == m) break;
+      HIPCHK(ks_count_active(kd, ctx->k_count, st));
+      TRY(get_i_async(ctx, ctx->k_count, 1, 0));
+      TRY(sync(ctx));
+      if (ctx->hi[0] == 0) break;
+    }
+    // x += M^-1 V y with y = H^-1 g per instance
+    HIPCHK(ks_solve_y(kd, m, ctx->k_y, ctx->k_est, st));
+    HIPCHK(ks_combine<T>(kd, ws.V, N, ctx->k_y, m, ws.t, st));
+    TRY(apply_M<T>(ctx, kp, op, ws.t, ws.z));
+    HIPCHK((ks_axpy<T, T>(kd, nullptr, ws.z, x, st)));
+    // true residual: restart vector and explicit check
+    TRY(apply_J<T>(ctx, kp, op, x, ws.w));
+    HIPCHK(ks_sub<T>(kd, bvec, ws.w, ws.r, st));
+    HIPCHK(ks_norms<T>(kd, ws.r, ctx->partial, ctx->k_beta2, st));
+    TRY(get_i_async(ctx, kd.its, B, 0));
+    TRY(get_i_async(ctx, kd.status, B, B));
+    HIPCHK(hipMemcpyAsync(ctx->hd + B, ctx->k_est, B * sizeof(double), hipMemcpyDeviceToHost, st));
+    TRY(get_d(ctx, ctx->k_beta2, B));
+    for (int b = 0; b < B; ++b) {
+      beta2[b] = ctx->hd[b];
+      est[b] = ctx->hd[B + b];
+      its[b] = ctx->hi[b];
+      stat[b] = ctx->hi[B + b];
+    }
+    for (int b = 0; b < B; ++b) {
+      if (!on[b]) continue;
+      out[b].iters = its[b];
+      out[b].restarts += 1;
+      if (stat[b] != 0) {
+        out[b].st = HF_ENONFINITE;
+        note(ctx, b, "non-finite Krylov vector");
+        on[b] = 0;
+      } else if (!explicit_check && (est[b] <= rtol * bnorm[b] || its[b] >= cap[b])) {
+        out[b].relres = est[b] / bnorm[b];
+        on[b] = 0;
+      }
+    }
+    if (trace_on())
+      for (int b = 0; b < B; ++b)
+        if (out[b].restarts && (on[b] || out[b].iters == its[b]))
+          std::fprintf(stderr, "hf gmres(%s) inst %d: it %d cycle %d estimate %.3e true %.3e\n",
+                       sizeof(T) == 8 ? "fp64" : "fp32", b, its[b], out[b].restarts,
+                       est[b] / bnorm[b], std::sqrt(beta2[b]) / bnorm[b]);
+  }
+  return HF_OK;
+}
+
+// block-Jacobi factors of every instance; instances with a singular block
+// are reported in st and dropped from on
+static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::vector<hf_status> &st) {
   const Sizes &s = ctx->s;
   const KParams kp = kparams(ctx);
+  const int B = nI(ctx);
   const bool ir = ctx->opt.precision == HF_FP32_IR;
   if (ir && !ctx->inv32) {
     TRY(dalloc(ctx, &ctx->inv32, s.ne * s.bu * s.bu));
     TRY(dalloc(ctx, &ctx->A32, s.n_blocks * s.bu * s.bu));
     TRY(dalloc(ctx, &ctx->Bs32, s.n_strip * s.bu));
     TRY(dalloc(ctx, &ctx->Cs32, s.n_strip * s.bu));
-    TRY(dalloc(ctx, &ctx->D32, s.n_p * s.n_p));
+    TRY(dalloc(ctx, &ctx->D32, ctx->doff[B]));
   }
-  HIPCHK(hipMemsetAsync(ctx->flag, 0, sizeof(int), ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->flag, 0, B * sizeof(int), ctx->stream));
   {
     ProfScope ps(ctx, P_INV);
     HIPCHK(launch_blockinv(kp, ctx->A, ctx->inv, ir ? ctx->inv32 : nullptr, ctx->flag, ctx->stream));
@@ -1039,200 +1515,345 @@ static hf_status build_preconditioner(hf_ctx *ctx) {
     HIPCHK(launch_convert(ctx->A, ctx->A32, s.n_blocks * s.bu * s.bu, ctx->stream));
     HIPCHK(launch_convert(ctx->Bs, ctx->Bs32, s.n_strip * s.bu, ctx->stream));
     HIPCHK(launch_convert(ctx->Cs, ctx->Cs32, s.n_strip * s.bu, ctx->stream));
-    HIPCHK(launch_convert(ctx->D, ctx->D32, s.n_p * s.n_p, ctx->stream));
+    HIPCHK(launch_convert(ctx->D, ctx->D32, ctx->doff[B], ctx->stream));
     ctx->have32 = true;
   }
-  int flag = 0;
-  HIPCHK(hipMemcpyAsync(&flag, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  if (flag & 1) return fail(ctx, HF_ESINGULAR, "zero or non-finite pivot in an element block");
-  if (flag & 2) return fail(ctx, HF_ESINGULAR, "zero or non-finite pivot in the pressure block");
+  TRY(get_i_async(ctx, ctx->flag, B, 0));
+  TRY(sync(ctx));
+  for (int b = 0; b < B; ++b) {
+    if (!on[b] || !ctx->hi[b]) continue;
+    st[b] = HF_ESINGULAR;
+    on[b] = 0;
+    note(ctx, b, (ctx->hi[b] & 1) ? "zero or non-finite pivot in an element block"
+                                  : "zero or non-finite pivot in the pressure block");
+  }
   return HF_OK;
 }
 
-static hf_status do_solve(hf_ctx *ctx, hf_solve_stats *stats) {
+// J dx = -R for the instances with on[b] = 1 (GMRES in FP64, or FP32 GMRES
+// under FP64 iterative refinement); per-instance results in ls.
+static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve_stats> &ls) {
   const auto t0 = std::chrono::steady_clock::now();
   const Sizes &s = ctx->s;
   const int64_t N = s.N();
+  const int B = nI(ctx);
   const KParams kp = kparams(ctx);
-  hf_solve_stats st{};
-  TRY(build_preconditioner(ctx));
-  HIPCHK(launch_axpby(-1.0, ctx->R, 0.0, ctx->rhs, N, ctx->stream));  // b = -R
-  hf_status status = HF_OK;
+  KrylovDev &kd = ctx->kd;
+  hipStream_t stm = ctx->stream;
+  std::vector<hf_status> st(B, HF_OK);
+  ls.assign(B, hf_solve_stats{});
+  const std::vector<int> on0 = on;
+  TRY(build_preconditioner(ctx, on, st));
+  HIPCHK(launch_axpby(-1.0, ctx->R, 0.0, ctx->rhs, N, stm));  // b = -R
   if (ctx->opt.precision == HF_FP64) {
     TRY(ensure_ws<double>(ctx, ctx->k64));
     Ops<double> op{ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->inv, ctx->Sinv};
-    status = gmres<double>(ctx, op, ctx->k64, ctx->rhs, ctx->dx, ctx->opt.rtol, ctx->opt.gmres_maxit,
-                           true, st.gmres_iters, st.restarts, st.true_relres);
+    std::vector<SolveOut> out;
+    TRY(gmres_b<double>(ctx, op, ctx->k64, ctx->rhs, ctx->dx, ctx->opt.rtol, true, on,
+                        std::vector<int>(B, ctx->opt.gmres_maxit), out));
+    for (int b = 0; b < B; ++b) {
+      if (!on[b]) continue;
+      ls[b].gmres_iters = out[b].iters;
+      ls[b].restarts = out[b].restarts;
+      ls[b].true_relres = out[b].relres;
+      st[b] = out[b].st;
+    }
   } else {
     TRY(ensure_ws<float>(ctx, ctx->k32));
     Ops<double> op64{ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->inv, ctx->Sinv};
     Ops<float> op32{ctx->A32, ctx->Bs32, ctx->Cs32, ctx->D32, ctx->inv32, ctx->Sinv32};
-    HIPCHK(hipMemsetAsync(ctx->dx, 0, N * sizeof(double), ctx->stream));
-    HIPCHK(hipMemcpyAsync(ctx->r64, ctx->rhs, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    double bnorm;
-    TRY(vnorm<double>(ctx, ctx->rhs, N, bnorm));
-    if (!std::isfinite(bnorm)) return fail(ctx, HF_ENONFINITE, "non-finite right-hand side");
-    st.true_relres = 0.0;
-    const int cap = 20 * ctx->opt.gmres_m;
-    if (bnorm > 0.0) {
-      status = HF_ENOCONV;
-      for (int outer = 0; outer < ctx->opt.ir_maxit; ++outer) {
-        double rn;
-        TRY(vnorm<double>(ctx, ctx->r64, N, rn));
-        st.true_relres = rn / bnorm;
-        if (!std::isfinite(rn)) return fail(ctx, HF_ENONFINITE, "non-finite refinement residual");
-        if (rn <= ctx->opt.rtol * bnorm) {
-          status = HF_OK;
-          break;
-        }
-        if (st.gmres_iters >= ctx->opt.gmres_maxit) break;
-        HIPCHK(launch_cast_scale(ctx->r64, 1.0 / rn, ctx->k32.b, N, ctx->stream));
-        int inner_it = 0, inner_rs = 0;
-        double est = 0.0;
-        const int lim = std::min(cap, ctx->opt.gmres_maxit - st.gmres_iters);
-        hf_status is = gmres<float>(ctx, op32, ctx->k32, ctx->k32.b, ctx->k32.x, ctx->opt.rtol_inner,
-                                    lim, false, inner_it, inner_rs, est);
-        if (is != HF_OK && is != HF_ENOCONV) return is;
-        st.gmres_iters += inner_it;
-        st.restarts += inner_rs;
-        st.ir_steps += 1;
-        HIPCHK(launch_cast_axpy(rn, ctx->k32.x, ctx->dx, N, ctx->stream));
-        TRY(apply_J<double>(ctx, kp, op64, ctx->dx, ctx->t64));
-        HIPCHK(launch_sub(ctx->rhs, ctx->t64, ctx->r64, N, ctx->stream));
+    TRY(put(ctx, kd.solving, on));
+    HIPCHK(ks_zero<double>(kd, ctx->dx, 1, stm));
+    HIPCHK(hipMemcpyAsync(ctx->r64, ctx->rhs, N * sizeof(double), hipMemcpyDeviceToDevice, stm));
+    HIPCHK(ks_norms<double>(kd, ctx->rhs, ctx->partial, ctx->red, stm));
+    TRY(get_d(ctx, ctx->red, B));
+    std::vector<double> bnorm(B), rn(B);
+    for (int b = 0; b < B; ++b) bnorm[b] = std::sqrt(ctx->hd[b]);
+    for (int b = 0; b < B; ++b) {
+      if (!on[b]) continue;
+      if (!std::isfinite(bnorm[b])) {
+        st[b] = HF_ENONFINITE;
+        note(ctx, b, "non-finite right-hand side");
+        on[b] = 0;
+      } else if (bnorm[b] == 0.0) {
+        on[b] = 0;
       }
-      if (status != HF_OK) fail(ctx, HF_ENOCONV, "GMRES-IR did not reach rtol within its caps");
+    }
+    const int cap_inner = 20 * ctx->opt.gmres_m;
+    for (int outer = 0;; ++outer) {
+      HIPCHK(ks_norms<double>(kd, ctx->r64, ctx->partial, ctx->red, stm));
+      TRY(get_d(ctx, ctx->red, B));
+      bool any = false;
+      for (int b = 0; b < B; ++b) {
+        if (!on[b]) continue;
+        rn[b] = std::sqrt(ctx->hd[b]);
+        ls[b].true_relres = rn[b] / bnorm[b];
+        if (!std::isfinite(rn[b])) {
+          st[b] = HF_ENONFINITE;
+          note(ctx, b, "non-finite refinement residual");
+          on[b] = 0;
+        } else if (rn[b] <= ctx->opt.rtol * bnorm[b]) {
+          on[b] = 0;
+        } else if (outer >= ctx->opt.ir_maxit || ls[b].gmres_iters >= ctx->opt.gmres_maxit) {
+          st[b] = HF_ENOCONV;
+          note(ctx, b, "GMRES-IR did not reach rtol within its caps");
+          on[b] = 0;
+        } else {
+          any = true;
+        }
+      }
+      if (!any) break;
+      std::vector<double> coef(B, 0.0);
+      std::vector<int> cap(B, 0);
+      for (int b = 0; b < B; ++b)
+        if (on[b]) {
+          coef[b] = 1.0 / rn[b];
+          cap[b] = std::min(cap_inner, ctx->opt.gmres_maxit - ls[b].gmres_iters);
+        }
+      TRY(put(ctx, kd.solving, on));
+      TRY(put(ctx, ctx->k_coef, coef));
+      HIPCHK((ks_cast<float, double>(kd, ctx->r64, ctx->k_coef, ctx->k32.b, stm)));
+      std::vector<SolveOut> out;
+      TRY(gmres_b<float>(ctx, op32, ctx->k32, ctx->k32.b, ctx->k32.x, ctx->opt.rtol_inner, false, on,
+                         cap, out));
+      for (int b = 0; b < B; ++b) {
+        if (!on[b]) continue;
+        ls[b].gmres_iters += out[b].iters;
+        ls[b].restarts += out[b].restarts;
+        ls[b].ir_steps += 1;
+        coef[b] = rn[b];
+        if (out[b].st == HF_ENONFINITE) {
+          st[b] = HF_ENONFINITE;
+          on[b] = 0;
+        }
+      }
+      // dx += ||r|| d ; r = b - J dx (FP64)
+      TRY(put(ctx, kd.solving, on));
+      TRY(put(ctx, ctx->k_coef, coef));
+      HIPCHK((ks_axpy<double, float>(kd, ctx->k_coef, ctx->k32.x, ctx->dx, stm)));
+      TRY(apply_J<double>(ctx, kp, op64, ctx->dx, ctx->t64));
+      HIPCHK(ks_sub<double>(kd, ctx->rhs, ctx->t64, ctx->r64, stm));
     }
   }
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  if (stats) *stats = st;
-  return status;
+  TRY(sync(ctx));
+  const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int b = 0; b < B; ++b) {
+    ls[b].seconds = sec;
+    ls[b].status = on0[b] ? st[b] : HF_OK;
+  }
+  return HF_OK;
+}
+
+static hf_status status_of(hf_ctx *ctx, const std::vector<hf_solve_stats> &ls, const char *what) {
+  std::vector<hf_status> st(ls.size());
+  for (size_t b = 0; b < ls.size(); ++b) st[b] = (hf_status)ls[b].status;
+  return first_failure(ctx, st, what);
 }
 
 extern "C" hf_status hf_solve(hf_ctx *ctx, hf_solve_stats *stats) {
   TRY(check_ctx(ctx, 4));
+  ctx->ierr.clear();
   HIPCHK(hipSetDevice(ctx->opt.device));
-  TRY(do_solve(ctx, stats));
+  std::vector<hf_solve_stats> ls;
+  TRY(do_solve(ctx, std::vector<int>(nI(ctx), 1), ls));
+  if (stats) std::copy(ls.begin(), ls.end(), stats);
   ctx->stage = 5;
-  return HF_OK;
+  return status_of(ctx, ls, "linear solve failed");
 }
 
 // ===========================================================================
 // Newton
 // ===========================================================================
-static hf_status do_newton_step(hf_ctx *ctx, hf_newton_stats *ns) {
+// One Newton iteration of the instances with on[b] = 1: assemble (all),
+// solve, update the instances whose solve succeeded.  An instance whose
+// solve or update fails keeps its state.
+static hf_status do_newton_step(hf_ctx *ctx, const std::vector<int> &on, std::vector<hf_newton_stats> &ns) {
   const Sizes &s = ctx->s;
-  double rn = 0.0;
-  TRY(do_assemble(ctx, &rn));
+  const int B = nI(ctx);
+  ns.assign(B, hf_newton_stats{});
+  std::vector<double> rn;
+  TRY(do_assemble(ctx, rn));
   ctx->stage = std::max(ctx->stage, 4);
-  hf_solve_stats ls{};
-  hf_status st = do_solve(ctx, &ls);
-  if (ns) {
-    ns->lin = ls;
-    ns->res_norm = rn;
+  std::vector<int> act(on);
+  for (int b = 0; b < B; ++b) {
+    ns[b].res_norm = rn[b];
+    if (act[b] && !std::isfinite(rn[b])) {
+      act[b] = 0;
+      ns[b].status = HF_ENONFINITE;
+      note(ctx, b, "non-finite residual");
+    }
   }
-  if (st != HF_OK) return st;  // state untouched
+  std::vector<hf_solve_stats> ls;
+  TRY(do_solve(ctx, act, ls));
+  std::vector<int> upd(B, 0);
+  for (int b = 0; b < B; ++b) {
+    if (!on[b]) continue;
+    ns[b].lin = ls[b];
+    if (act[b]) ns[b].status = ls[b].status;
+    upd[b] = act[b] && ls[b].status == HF_OK;
+  }
   HIPCHK(hipMemcpyAsync(ctx->xs_save, ctx->xs, s.N() * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-  HIPCHK(launch_newton_update(ctx->dx, ctx->xs, s.n_u, ctx->xs + s.n_u, s.n_p, ctx->opt.cutoff_on,
-                              ctx->opt.p_cutoff, ctx->partial, ctx->red, ctx->stream));
-  TRY(sync_read(ctx, 4));
-  const double du = std::sqrt(ctx->red_h[0]), un = std::sqrt(ctx->red_h[1]);
-  const double dp = std::sqrt(ctx->red_h[2]), pn = std::sqrt(ctx->red_h[3]);
-  if (!std::isfinite(du) || !std::isfinite(un) || !std::isfinite(dp) || !std::isfinite(pn)) {
-    HIPCHK(hipMemcpyAsync(ctx->xs, ctx->xs_save, s.N() * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    return fail(ctx, HF_ENONFINITE, "non-finite Newton update");
+  TRY(put(ctx, ctx->k_upd, upd));
+  HIPCHK(launch_snewton_update(ctx->kd, ctx->dx, ctx->xs, s.n_u, ctx->k_upd, ctx->opt.cutoff_on,
+                               ctx->opt.p_cutoff, ctx->partial, ctx->red, ctx->stream));
+  TRY(get_d(ctx, ctx->red, 4 * B));
+  for (int b = 0; b < B; ++b) {
+    if (!upd[b]) continue;
+    const double du = std::sqrt(ctx->hd[4 * b]), un = std::sqrt(ctx->hd[4 * b + 1]);
+    const double dp = std::sqrt(ctx->hd[4 * b + 2]), pn = std::sqrt(ctx->hd[4 * b + 3]);
+    if (!std::isfinite(du) || !std::isfinite(un) || !std::isfinite(dp) || !std::isfinite(pn)) {
+      TRY(copy_inst(ctx, ctx->xs, ctx->xs_save, b));
+      ns[b].status = HF_ENONFINITE;
+      note(ctx, b, "non-finite Newton update");
+      continue;
+    }
+    const double ru = un > 0.0 ? du / un : du;
+    const double rp = ctx->inst[b].n_p ? (pn > 0.0 ? dp / pn : dp) : 0.0;
+    ns[b].du_rel = ru;
+    ns[b].dp_rel = rp;
+    ns[b].iterations = 1;
+    ns[b].converged = (ru <= ctx->opt.newton_tol && rp <= ctx->opt.newton_tol) ? 1 : 0;
   }
-  const double ru = un > 0.0 ? du / un : du;
-  const double rp = s.n_p ? (pn > 0.0 ? dp / pn : dp) : 0.0;
-  if (ns) {
-    ns->du_rel = ru;
-    ns->dp_rel = rp;
-    ns->iterations += 1;
-    ns->converged = (ru <= ctx->opt.newton_tol && rp <= ctx->opt.newton_tol) ? 1 : 0;
-  }
+  TRY(sync(ctx));
   ctx->stage = 3;
   return HF_OK;
+}
+
+static hf_status newton_status(hf_ctx *ctx, const std::vector<hf_newton_stats> &ns) {
+  std::vector<hf_status> st(ns.size());
+  for (size_t b = 0; b < ns.size(); ++b) st[b] = (hf_status)ns[b].status;
+  return first_failure(ctx, st, "Newton iteration failed");
 }
 
 extern "C" hf_status hf_newton_step(hf_ctx *ctx, hf_newton_stats *stats) {
   TRY(check_ctx(ctx, 3));
+  ctx->ierr.clear();
   HIPCHK(hipSetDevice(ctx->opt.device));
-  hf_newton_stats ns{};
-  hf_status st = do_newton_step(ctx, &ns);
-  if (stats) *stats = ns;
-  return st;
+  std::vector<hf_newton_stats> ns;
+  TRY(do_newton_step(ctx, std::vector<int>(nI(ctx), 1), ns));
+  if (stats) std::copy(ns.begin(), ns.end(), stats);
+  return newton_status(ctx, ns);
 }
 
 extern "C" hf_status hf_newton_solve(hf_ctx *ctx, hf_newton_stats *stats) {
   TRY(check_ctx(ctx, 3));
+  ctx->ierr.clear();
   HIPCHK(hipSetDevice(ctx->opt.device));
+  const int B = nI(ctx);
   const int64_t N = ctx->s.N();
   HIPCHK(hipMemcpyAsync(ctx->xs_start, ctx->xs, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-  hf_newton_stats acc{};
-  hf_status st = HF_OK;
+  std::vector<hf_newton_stats> acc(B);
+  std::vector<int> on(B, 1);
   for (int k = 0; k < ctx->opt.newton_maxit; ++k) {
-    hf_newton_stats one{};
-    st = do_newton_step(ctx, &one);
-    acc.lin.gmres_iters += one.lin.gmres_iters;
-    acc.lin.ir_steps += one.lin.ir_steps;
-    acc.lin.restarts += one.lin.restarts;
-    acc.lin.true_relres = std::max(acc.lin.true_relres, one.lin.true_relres);
-    acc.lin.seconds += one.lin.seconds;
-    acc.du_rel = one.du_rel;
-    acc.dp_rel = one.dp_rel;
-    acc.res_norm = one.res_norm;
-    acc.iterations += 1;
-    if (st != HF_OK) break;
-    if (one.converged) {
-      acc.converged = 1;
-      break;
+    if (std::none_of(on.begin(), on.end(), [](int v) { return v != 0; })) break;
+    std::vector<hf_newton_stats> one;
+    TRY(do_newton_step(ctx, on, one));
+    for (int b = 0; b < B; ++b) {
+      if (!on[b]) continue;
+      hf_newton_stats &a = acc[b];
+      a.lin.gmres_iters += one[b].lin.gmres_iters;
+      a.lin.ir_steps += one[b].lin.ir_steps;
+      a.lin.restarts += one[b].lin.restarts;
+      a.lin.true_relres = std::max(a.lin.true_relres, one[b].lin.true_relres);
+      a.lin.seconds += one[b].lin.seconds;
+      a.lin.status = one[b].lin.status;
+      a.du_rel = one[b].du_rel;
+      a.dp_rel = one[b].dp_rel;
+      a.res_norm = one[b].res_norm;
+      a.iterations += 1;
+      if (one[b].status != HF_OK) {
+        a.status = one[b].status;
+        on[b] = 0;
+      } else if (one[b].converged) {
+        a.converged = 1;
+        on[b] = 0;
+      }
     }
   }
-  if (stats) *stats = acc;
-  if (st != HF_OK || !acc.converged) {
-    // restore the state at the start of the call
-    HIPCHK(hipMemcpyAsync(ctx->xs, ctx->xs_start, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    if (st == HF_OK) st = fail(ctx, HF_ENOCONV, "Newton did not converge within newton_maxit");
-    return st;
+  for (int b = 0; b < B; ++b) {
+    if (acc[b].converged) continue;
+    // restore the instance's state at the start of the call
+    TRY(copy_inst(ctx, ctx->xs, ctx->xs_start, b));
+    if (acc[b].status == HF_OK) {
+      acc[b].status = HF_ENOCONV;
+      note(ctx, b, "Newton did not converge within newton_maxit");
+    }
   }
-  return HF_OK;
+  TRY(sync(ctx));
+  if (stats) std::copy(acc.begin(), acc.end(), stats);
+  return newton_status(ctx, acc);
 }
 
 extern "C" hf_status hf_initial_guess(hf_ctx *ctx, double *p0_out) {
   TRY(check_ctx(ctx, 3));
+  ctx->ierr.clear();
   HIPCHK(hipSetDevice(ctx->opt.device));
   const Sizes &s = ctx->s;
-  double q_total = 0.0;
-  for (double q : ctx->h.src_q0) q_total += q;
-  if (!s.n_p || q_total <= 0.0) {
-    if (p0_out) *p0_out = 0.0;
-    return HF_OK;  // nothing to predict: keep the state
+  const int B = nI(ctx);
+  std::vector<int> pred(B, 0);
+  std::vector<double> qtot(B, 0.0), p0(B, 0.0);
+  for (int b = 0; b < B; ++b) {
+    for (double q : ctx->inst[b].src_q0) qtot[b] += q;
+    pred[b] = ctx->inst[b].n_p > 0 && qtot[b] > 0.0;  // else nothing to predict: keep the state
+  }
+  if (std::none_of(pred.begin(), pred.end(), [](int v) { return v != 0; })) {
+    if (p0_out) std::fill(p0_out, p0_out + B, 0.0);
+    return HF_OK;
   }
   // unit-pressure elastic response u1 with the pressure held fixed
-  HIPCHK(hipMemsetAsync(ctx->xs, 0, s.n_u * sizeof(double), ctx->stream));
-  HIPCHK(launch_fill(1.0, ctx->xs + s.n_u, s.n_p, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->xs_save, ctx->xs, s.N() * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  for (int b = 0; b < B; ++b)
+    if (pred[b]) {
+      HIPCHK(hipMemsetAsync(useg(ctx, ctx->xs, b), 0, ulen(ctx, b) * sizeof(double), ctx->stream));
+      HIPCHK(launch_fill(1.0, pseg(ctx, ctx->xs, b), plen(ctx, b), ctx->stream));
+    }
   ctx->freeze_p = 1;
-  hf_status st = do_assemble(ctx, nullptr);
-  if (st == HF_OK) st = do_solve(ctx, nullptr);
+  std::vector<double> rn;
+  std::vector<hf_solve_stats> ls;
+  hf_status st = do_assemble(ctx, rn);
+  std::vector<hf_status> fst(B, HF_OK);
+  if (st == HF_OK) {
+    for (int b = 0; b < B; ++b)
+      if (pred[b] && !std::isfinite(rn[b])) {
+        fst[b] = HF_ENONFINITE;
+        note(ctx, b, "non-finite residual");
+        pred[b] = 0;
+      }
+    st = do_solve(ctx, pred, ls);
+  }
   ctx->freeze_p = 0;
   if (st != HF_OK) return st;
-  HIPCHK(hipMemcpyAsync(ctx->xs, ctx->dx, s.n_u * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  for (int b = 0; b < B; ++b)
+    if (pred[b] && ls[b].status != HF_OK) {
+      fst[b] = (hf_status)ls[b].status;
+      pred[b] = 0;
+    }
+  for (int b = 0; b < B; ++b)
+    if (pred[b])
+      HIPCHK(hipMemcpyAsync(useg(ctx, ctx->xs, b), useg(ctx, ctx->dx, b), ulen(ctx, b) * sizeof(double),
+                            hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(launch_set_rules(ctx->rules, ctx->stream));
-  HIPCHK(launch_fluid_volume(kparams(ctx), ctx->xs, ctx->partial, ctx->red, ctx->stream));
-  TRY(sync_read(ctx, 1));
-  const double V1 = ctx->red_h[0];
-  if (!(V1 > 0.0) || !std::isfinite(V1))
-    return fail(ctx, HF_ENONFINITE, "unit-pressure crack volume is not positive");
-  const double p0 = q_total * ctx->mat.dt / V1;
-  HIPCHK(launch_axpby(0.0, ctx->dx, p0, ctx->xs, s.n_u, ctx->stream));  // u0 = p0 u1
-  HIPCHK(launch_fill(p0, ctx->xs + s.n_u, s.n_p, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  if (p0_out) *p0_out = p0;
+  HIPCHK(launch_fluid_volume(kparams(ctx), ctx->xs, nullptr, ctx->red, ctx->stream));
+  TRY(get_d(ctx, ctx->red, B));
+  for (int b = 0; b < B; ++b) {
+    if (!pred[b]) continue;
+    const double V1 = ctx->hd[b];
+    if (!(V1 > 0.0) || !std::isfinite(V1)) {
+      fst[b] = HF_ENONFINITE;
+      note(ctx, b, "unit-pressure crack volume is not positive");
+      pred[b] = 0;
+      continue;
+    }
+    p0[b] = qtot[b] * ctx->inst[b].mat.dt / V1;
+    HIPCHK(launch_axpby(0.0, useg(ctx, ctx->dx, b), p0[b], useg(ctx, ctx->xs, b), ulen(ctx, b), ctx->stream));
+    HIPCHK(launch_fill(p0[b], pseg(ctx, ctx->xs, b), plen(ctx, b), ctx->stream));
+  }
+  for (int b = 0; b < B; ++b)
+    if (fst[b] != HF_OK) TRY(copy_inst(ctx, ctx->xs, ctx->xs_save, b));  // keep the old state
+  TRY(sync(ctx));
+  if (p0_out) std::copy(p0.begin(), p0.end(), p0_out);
   ctx->stage = 3;
-  return HF_OK;
+  return first_failure(ctx, fst, "elastic predictor failed");
 }
 
 extern "C" hf_status hf_end_load_step(hf_ctx *ctx) {
@@ -1241,6 +1862,7 @@ extern "C" hf_status hf_end_load_step(hf_ctx *ctx) {
   HIPCHK(launch_set_rules(ctx->rules, ctx->stream));
   HIPCHK(launch_opening(kparams(ctx), ctx->xs, ctx->w_old, ctx->stream));
   TRY(update_fluid_scale(ctx));
+  TRY(sync(ctx));
   ctx->stage = 3;
   return HF_OK;
 }
@@ -1251,11 +1873,13 @@ extern "C" hf_status hf_end_load_step(hf_ctx *ctx) {
 extern "C" hf_status hf_get_residual(hf_ctx *ctx, int32_t inst, double *R_u, double *R_p) {
   TRY(check_ctx(ctx, 4));
   TRY(check_inst(ctx, inst));
-  const Sizes &s = ctx->s;
-  if (R_u) HIPCHK(hipMemcpyAsync(R_u, ctx->R, s.n_u * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  if (R_p && s.n_p)
-    HIPCHK(hipMemcpyAsync(R_p, ctx->R + s.n_u, s.n_p * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (R_u)
+    HIPCHK(hipMemcpyAsync(R_u, useg(ctx, ctx->R, inst), ulen(ctx, inst) * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+  if (R_p && plen(ctx, inst))
+    HIPCHK(hipMemcpyAsync(R_p, pseg(ctx, ctx->R, inst), plen(ctx, inst) * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+  TRY(sync(ctx));
   return HF_OK;
 }
 
@@ -1264,28 +1888,27 @@ extern "C" hf_status hf_get_block_rows(hf_ctx *ctx, int32_t inst, int64_t n_rows
   TRY(check_ctx(ctx, 4));
   TRY(check_inst(ctx, inst));
   const Sizes &s = ctx->s;
+  const InstHost &h = ctx->inst[inst];
   const int NF = s.dim + 1, BU = s.bu, NS = s.dim + 2;
   if (n_rows < 0 || (n_rows && (!elems || !cols || !blocks))) return fail(ctx, HF_EINVAL, "bad arguments");
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  // host copy of the block positions
+  for (int64_t i = 0; i < n_rows; ++i)
+    if (elems[i] < 0 || elems[i] >= h.ne) return fail(ctx, HF_EINVAL, "element out of range");
+  TRY(sync(ctx));
   std::vector<double> buf(BU * BU);
   for (int64_t i = 0; i < n_rows; ++i) {
-    const int32_t e = elems[i];
-    if (e < 0 || e >= s.ne) return fail(ctx, HF_EINVAL, "element out of range");
+    const int32_t el = elems[i];
+    const int64_t e = ctx->eoff[inst] + el;  // context numbering
     for (int slot = 0; slot < NS; ++slot) {
       int64_t blk = -1;
       int32_t col = -1;
       if (slot == 0) {
-        // diagonal block is the first of the row
-        int64_t bp = 0;
-        HIPCHK(hipMemcpy(&bp, ctx->m.blk_ptr + e, sizeof(int64_t), hipMemcpyDeviceToHost));
-        blk = bp;
-        col = e;
-      } else if (slot - 1 < NF && ctx->h.nbr[(int64_t)e * NF + slot - 1] >= 0) {
-        int32_t b = 0;
-        HIPCHK(hipMemcpy(&b, ctx->m.blk_of + (int64_t)e * NF + slot - 1, sizeof(int32_t), hipMemcpyDeviceToHost));
-        blk = b;
-        col = ctx->h.nbr[(int64_t)e * NF + slot - 1];
+        HIPCHK(hipMemcpy(&blk, ctx->m.blk_ptr + e, sizeof(int64_t), hipMemcpyDeviceToHost));
+        col = el;
+      } else if (h.nbr[(int64_t)el * NF + slot - 1] >= 0) {
+        int32_t bi = 0;
+        HIPCHK(hipMemcpy(&bi, ctx->m.blk_of + e * NF + slot - 1, sizeof(int32_t), hipMemcpyDeviceToHost));
+        blk = bi;
+        col = h.nbr[(int64_t)el * NF + slot - 1];
       }
       cols[i * NS + slot] = col;
       double *out = blocks + (i * NS + slot) * BU * BU;
@@ -1306,35 +1929,45 @@ extern "C" hf_status hf_get_coupling(hf_ctx *ctx, int32_t inst, double *B, doubl
   TRY(check_inst(ctx, inst));
   const Sizes &s = ctx->s;
   const int BU = s.bu;
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  std::vector<double> bs(s.n_strip * BU), cs(s.n_strip * BU);
+  const int64_t nu = ulen(ctx, inst), np = plen(ctx, inst);
+  const int64_t e0 = ctx->eoff[inst], e1 = ctx->eoff[inst + 1], p0 = ctx->poff[inst];
+  TRY(sync(ctx));
   std::vector<int64_t> sp_ptr(s.ne + 1);
-  std::vector<int32_t> sp_pnode(s.n_strip);
-  HIPCHK(hipMemcpy(bs.data(), ctx->Bs, bs.size() * sizeof(double), hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(cs.data(), ctx->Cs, cs.size() * sizeof(double), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(sp_ptr.data(), ctx->m.sp_ptr, sp_ptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
-  if (s.n_strip)
-    HIPCHK(hipMemcpy(sp_pnode.data(), ctx->m.sp_pnode, sp_pnode.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-  if (B) std::fill(B, B + s.n_u * s.n_p, 0.0);
-  if (C) std::fill(C, C + s.n_p * s.n_u, 0.0);
-  for (int64_t e = 0; e < s.ne; ++e)
-    for (int64_t k = sp_ptr[e]; k < sp_ptr[e + 1]; ++k)
+  const int64_t k0 = sp_ptr[e0], k1 = sp_ptr[e1];
+  std::vector<double> bs((k1 - k0) * BU), cs((k1 - k0) * BU);
+  std::vector<int32_t> sp_pnode(k1 - k0);
+  if (k1 > k0) {
+    HIPCHK(hipMemcpy(bs.data(), ctx->Bs + k0 * BU, bs.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(cs.data(), ctx->Cs + k0 * BU, cs.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(sp_pnode.data(), ctx->m.sp_pnode + k0, sp_pnode.size() * sizeof(int32_t),
+                     hipMemcpyDeviceToHost));
+  }
+  if (B) std::fill(B, B + nu * np, 0.0);
+  if (C) std::fill(C, C + np * nu, 0.0);
+  for (int64_t e = e0; e < e1; ++e)
+    for (int64_t k = sp_ptr[e]; k < sp_ptr[e + 1]; ++k) {
+      const int64_t pl = sp_pnode[k - k0] - p0, el = e - e0;
       for (int r = 0; r < BU; ++r) {
-        if (B) B[(e * BU + r) * s.n_p + sp_pnode[k]] = bs[k * BU + r];
-        if (C) C[sp_pnode[k] * s.n_u + e * BU + r] = cs[k * BU + r];
+        if (B) B[(el * BU + r) * np + pl] = bs[(k - k0) * BU + r];
+        if (C) C[pl * nu + el * BU + r] = cs[(k - k0) * BU + r];
       }
-  if (D && s.n_p) HIPCHK(hipMemcpy(D, ctx->D, s.n_p * s.n_p * sizeof(double), hipMemcpyDeviceToHost));
+    }
+  if (D && np)
+    HIPCHK(hipMemcpy(D, ctx->D + ctx->doff[inst], np * np * sizeof(double), hipMemcpyDeviceToHost));
   return HF_OK;
 }
 
 extern "C" hf_status hf_get_increment(hf_ctx *ctx, int32_t inst, double *du, double *dp) {
   TRY(check_ctx(ctx, 3));
   TRY(check_inst(ctx, inst));
-  const Sizes &s = ctx->s;
-  if (du) HIPCHK(hipMemcpyAsync(du, ctx->dx, s.n_u * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  if (dp && s.n_p)
-    HIPCHK(hipMemcpyAsync(dp, ctx->dx + s.n_u, s.n_p * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (du)
+    HIPCHK(hipMemcpyAsync(du, useg(ctx, ctx->dx, inst), ulen(ctx, inst) * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+  if (dp && plen(ctx, inst))
+    HIPCHK(hipMemcpyAsync(dp, pseg(ctx, ctx->dx, inst), plen(ctx, inst) * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+  TRY(sync(ctx));
   return HF_OK;
 }
 

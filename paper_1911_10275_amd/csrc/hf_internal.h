@@ -102,95 +102,36 @@ struct Sizes {
 // ---------------------------------------------------------------------------
 // Kernel parameter block (passed by value)
 // ---------------------------------------------------------------------------
+// material and fluid-row scale of one instance
+struct InstPar {
+  double lam, G, sigma_c, delta_c, mu, dt, s_p, pad;
+};
+
 struct KParams {
   Sizes s;
   DevMesh m;
-  double lam, G, sigma_c, delta_c, mu, dt, b_stab, s_p;
+  const InstPar *ip;       // n_inst
+  const int32_t *einst;    // ne: instance of each element
+  const int32_t *pinst;    // n_p: instance of each pressure node
+  const int32_t *poff;     // n_inst+1: first pressure node of each instance
+  const int64_t *doff;     // n_inst+1: offset of each instance's dense pressure block
+  const int32_t *aoff;     // n_inst+1: first active (fluid) face of each instance
+  int n_inst;
+  double b_stab;
   int freeze_p;  // 1: pressure held fixed (fluid rows become p-rows of the identity)
 };
 
-// ---------------------------------------------------------------------------
-// Host-side layout built by hf_upload_mesh / hf_finalize
-// ---------------------------------------------------------------------------
-struct HostLayout {
-  std::vector<double> xyz;
-  std::vector<int32_t> elem;            // ne*(dim+1)
-  std::vector<uint8_t> dirichlet;       // n_vert
-  std::vector<int32_t> face_vert;       // nf*dim (sorted)
-  std::vector<int32_t> face_em, face_ep, fperm_m, fperm_p, face_lfm;
-  std::vector<int32_t> nbr, fid;        // ne*(dim+1)
-  std::vector<uint32_t> clamp;          // ne
-  std::vector<uint8_t> qp_state, beta;
-  std::vector<int64_t> src_vert;
-  std::vector<double> src_q0;
-  // finalize
-  std::vector<int64_t> pkeys;           // n_p*2
-  std::vector<int32_t> act_face, face_pn, slot;
-  double bbox_L = 1.0;
-};
-
-struct Material {
-  double E = 1, nu = 0.25, sigma_c = 1e-3, G_c = 1e-4, mu = 1e-3, dt = 1;
-  bool set = false;
+// device view of the batched Krylov state (see hf_kernels_krylov.hip)
+struct KrylovDev {
+  int n_inst = 0, n_chunks = 0;
+  const int64_t *c_row0 = nullptr;
+  const int32_t *c_len = nullptr, *c_inst = nullptr, *cptr = nullptr;
+  int *solving = nullptr, *kconv = nullptr, *its = nullptr, *status = nullptr, *nbasis = nullptr;
+  int *itmax = nullptr;  // per-instance cap on the iterations of the current solve
+  double *bnorm = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
 };
 
 }  // namespace hf
-
-// ---------------------------------------------------------------------------
-// Context
-// ---------------------------------------------------------------------------
-namespace hf {
-template <typename T>
-struct KrylovWs {
-  T *V = nullptr;   // (m+1) x N basis, column i at V + i*N
-  T *w = nullptr, *z = nullptr, *r = nullptr, *t = nullptr, *b = nullptr, *x = nullptr;
-  int m = 0;
-  int64_t n = 0;
-};
-}  // namespace hf
-
-struct hf_ctx {
-  hf_options opt{};
-  std::string err;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int stage = 0;  // 0 created, 1 mesh, 2 finalized, 3 state set, 4 assembled, 5 solved
-  hf::Sizes s;
-  hf::HostLayout h;
-  hf::Material mat;
-  hf::DevMesh m;
-  hf::RuleTables rules{};
-  double s_p = 1.0;
-  int freeze_p = 0;
-  int64_t n_reorth = 0;         // Gram-Schmidt re-orthogonalisations taken (diagnostic)
-  std::vector<void *> allocs;   // every device allocation, released by hf_destroy
-  // state: xs = [u; p]
-  double *xs = nullptr, *xs_save = nullptr, *xs_start = nullptr, *w_old = nullptr, *w_tmp = nullptr;
-  // assembled system
-  double *R = nullptr;          // N residual
-  double *A = nullptr;          // n_blocks*bu*bu (column-major blocks, row panels)
-  double *Bs = nullptr, *Cs = nullptr;      // n_strip*bu coupling strips
-  double *D = nullptr, *S = nullptr, *Sinv = nullptr;   // n_p*n_p dense
-  double *T = nullptr;          // Schur staging
-  double *inv = nullptr;        // ne*bu*bu block inverses (column-major)
-  float *A32 = nullptr, *Bs32 = nullptr, *Cs32 = nullptr, *D32 = nullptr, *Sinv32 = nullptr;
-  float *inv32 = nullptr;
-  bool have32 = false;          // FP32 copies current
-  int *flag = nullptr;          // device error flags
-  // FP64 work vectors
-  double *dx = nullptr, *rhs = nullptr, *r64 = nullptr, *t64 = nullptr;
-  hf::KrylovWs<double> k64;
-  hf::KrylovWs<float> k32;
-  double *partial = nullptr;    // reduction partials
-  double *red = nullptr;        // reduction results (device)
-  double *red_h = nullptr;      // pinned host copy
-  // profile: events recorded around kernel classes without host waits,
-  // resolved into totals by hf_get_profile
-  std::vector<hipEvent_t> evpool;
-  size_t ev_used = 0;
-  std::vector<std::array<int64_t, 3>> ev_pending;  // (class, start event, end event)
-  hf_profile prof{};
-};
 
 namespace hf {
 // launchers (hf_kernels_*.hip)
@@ -203,8 +144,10 @@ hipError_t launch_wmax(const KParams &kp, const double *w, double *out, hipStrea
 hipError_t launch_fluid_volume(const KParams &kp, const double *u, double *partial, double *out,
                                hipStream_t st);
 hipError_t launch_fill(double v, double *x, int64_t n, hipStream_t st);
+// flag[b] |= 1 on a zero or non-finite pivot in an element block of instance b
 hipError_t launch_blockinv(const KParams &kp, const double *A, double *inv, float *inv32,
                            int *flag, hipStream_t st);
+// flag[b] |= 2 on a zero or non-finite pivot in the pressure block of instance b
 hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,
                         const double *Cs, const double *D, double *Z, double *T, double *S,
                         double *Sinv, float *Sinv32, int *flag, hipStream_t st);
@@ -254,4 +197,45 @@ hipError_t launch_newton_update(const double *dx, double *u, int64_t n_u, double
 hipError_t launch_norm2(const double *x, int64_t n, double *partial, double *out,
                         hipStream_t st);
 hipError_t launch_set_rules(const RuleTables &rt, hipStream_t st);
+hipError_t launch_seg_norms(const KrylovDev &kd, const double *x, double *partial, double *out,
+                            hipStream_t st);
+hipError_t launch_snewton_update(const KrylovDev &kd, const double *dx, double *x, int64_t n_u,
+                                 const int *upd, int cutoff_on, double cutoff, double *partial,
+                                 double *out, hipStream_t st);
+
+// batched Krylov (hf_kernels_krylov.hip)
+template <typename T>
+hipError_t ks_proj(const KrylovDev &kd, const T *V, int64_t ldv, int k, const T *w,
+                   const int *gate, double *partial, double *out, hipStream_t st);
+template <typename T>
+hipError_t ks_update(const KrylovDev &kd, const T *V, int64_t ldv, int k, const double *h,
+                     int hstride, T *w, const int *gate, double *partial, double *out,
+                     hipStream_t st);
+template <typename T>
+hipError_t ks_scale(const KrylovDev &kd, const T *w, const double *scale, T *v, hipStream_t st);
+template <typename T>
+hipError_t ks_combine(const KrylovDev &kd, const T *V, int64_t ldv, const double *y, int ystride,
+                      T *out, hipStream_t st);
+template <typename TX, typename TZ>
+hipError_t ks_axpy(const KrylovDev &kd, const double *coef, const TZ *z, TX *x, hipStream_t st);
+template <typename T>
+hipError_t ks_sub(const KrylovDev &kd, const T *b, const T *jx, T *r, hipStream_t st);
+template <typename TY, typename TX>
+hipError_t ks_cast(const KrylovDev &kd, const TX *x, const double *coef, TY *y, hipStream_t st);
+template <typename T>
+hipError_t ks_zero(const KrylovDev &kd, T *x, int only_solving, hipStream_t st);
+hipError_t ks_reorth_flag(const KrylovDev &kd, const double *n0, int n0s, const double *n1, int *flag,
+                          hipStream_t st);
+hipError_t ks_arnoldi(const KrylovDev &kd, int j, int m, const double *s1, int s1s, const double *s2,
+                      int s2s, const int *reorth, const double *n1, const double *n2, double rtol,
+                      double *scale, hipStream_t st);
+// out[b] = ||x_b||^2 for every instance (no gating)
+template <typename T>
+hipError_t ks_norms(const KrylovDev &kd, const T *x, double *partial, double *out, hipStream_t st);
+// start of a solve: bnorm = sqrt(n2), kconv = -1, its = 0, status = 0
+hipError_t ks_begin(const KrylovDev &kd, const double *n2, hipStream_t st);
+hipError_t ks_count_active(const KrylovDev &kd, int *count, hipStream_t st);
+hipError_t ks_solve_y(const KrylovDev &kd, int m, double *y, double *est, hipStream_t st);
+hipError_t ks_cycle_start(const KrylovDev &kd, int m, const double *beta2, double *scale,
+                          hipStream_t st);
 }  // namespace hf

@@ -254,7 +254,8 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const double *__res
   constexpr int NQ = NQF > NQV ? NQF : NQV;
   const int64_t e = blockIdx.x;
   const int tid = threadIdx.x;
-  const double lam = kp.lam, G = kp.G;
+  const InstPar P = kp.ip[kp.einst[e]];
+  const double lam = P.lam, G = P.G;
 
   __shared__ double s_gl[NF][DIM], s_gln[NF][DIM];
   __shared__ double s_ue[BU], s_un[BU];
@@ -404,7 +405,7 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const double *__res
       const int st = kp.m.qp_state[(int64_t)f * NQF + q];
       const double al = st > 0 ? 1.0 : 0.0;
       double T, dT;
-      traction_law(st, w, kp.sigma_c, kp.delta_c, kc, T, dT);
+      traction_law(st, w, P.sigma_c, P.delta_c, kc, T, dT);
       double ph_p = 0.0;
       double gp[DIM - 1];
       for (int s2 = 0; s2 < DIM - 1; ++s2) gp[s2] = 0.0;
@@ -444,13 +445,13 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const double *__res
         Lag<DIM - 1, ORDER>::dphi_one(k, mu_, dmu);
         const double eta = Lag<DIM - 1, ORDER>::phi_one(k, mu_);
         const double wp = s_wq[q] > 0.0 ? s_wq[q] : 0.0;
-        const double dK = 3.0 * wp * wp / (12.0 * kp.mu);
+        const double dK = 3.0 * wp * wp / (12.0 * P.mu);
         double gg = 0.0;
         for (int s2 = 0; s2 < DIM - 1; ++s2)
           for (int t2 = 0; t2 < DIM - 1; ++t2)
             gg += s_gp[q][s2] * s_ginv[s2 * (DIM - 1) + t2] * (dmu[t2 + 1] - dmu[0]);
         s_eta[q][k] = eta;
-        s_fc[q][k] = kp.s_p * (dK * gg + eta / kp.dt);
+        s_fc[q][k] = P.s_p * (dK * gg + eta / P.dt);
       }
     }
     for (int t = tid; t < NQF * NN; t += NT) {
@@ -559,12 +560,15 @@ __global__ void k_fluid_rows(KParams kp, const double *__restrict__ u,
   using C = Cfg<DIM, ORDER>;
   constexpr int NN = C::NN, BU = C::BU, NQF = C::NQF, NNF = C::NNF;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t np = kp.s.n_p;
-  if (i >= np) return;
-  double *Drow = D + i * np;
-  for (int64_t j = 0; j < np; ++j) Drow[j] = 0.0;
+  if (i >= kp.s.n_p) return;
+  const int b = kp.pinst[i];
+  const InstPar P = kp.ip[b];
+  const int32_t p0 = kp.poff[b];
+  const int64_t nb = kp.poff[b + 1] - p0;
+  double *Drow = D + kp.doff[b] + (i - p0) * nb;
+  for (int64_t j = 0; j < nb; ++j) Drow[j] = 0.0;
   if (kp.freeze_p) {  // pressure held at its current value: dp = 0
-    Drow[i] = 1.0;
+    Drow[i - p0] = 1.0;
     R[kp.s.n_u + i] = 0.0;
     return;
   }
@@ -587,48 +591,47 @@ __global__ void k_fluid_rows(KParams kp, const double *__restrict__ u,
         lm[kp.m.fperm_m[(int64_t)f * DIM + k]] = c_rules.fq_mu[q][k];
         lp[kp.m.fperm_p[(int64_t)f * DIM + k]] = c_rules.fq_mu[q][k];
       }
-      double phm[NN], php[NN];
-      Lag<DIM, ORDER>::phi(lm, phm);
-      Lag<DIM, ORDER>::phi(lp, php);
       double w = 0.0;
       for (int x = 0; x < DIM; ++x) {
         double um = 0.0, up = 0.0;
         for (int a = 0; a < NN; ++a) {
-          um += phm[a] * u[(int64_t)em * BU + a * DIM + x];
-          up += php[a] * u[(int64_t)ep * BU + a * DIM + x];
+          um += Lag<DIM, ORDER>::phi_one(a, lm) * u[(int64_t)em * BU + a * DIM + x];
+          up += Lag<DIM, ORDER>::phi_one(a, lp) * u[(int64_t)ep * BU + a * DIM + x];
         }
         w += (up - um) * n[x];
       }
       const double wp = w > 0.0 ? w : 0.0;
-      const double K = wp * wp * wp / (12.0 * kp.mu);
-      double mu_[DIM], eta[NNF], dmu[NNF][DIM], geta[NNF][DIM - 1];
+      const double K = wp * wp * wp / (12.0 * P.mu);
+      double mu_[DIM];
       for (int k = 0; k < DIM; ++k) mu_[k] = c_rules.fq_mu[q][k];
-      Lag<DIM - 1, ORDER>::phi(mu_, eta);
-      Lag<DIM - 1, ORDER>::dphi(mu_, dmu);
-      for (int k = 0; k < NNF; ++k)
-        for (int s = 0; s < DIM - 1; ++s) geta[k][s] = dmu[k][s + 1] - dmu[k][0];
       double gp[DIM - 1];
-      for (int s = 0; s < DIM - 1; ++s) {
-        double g = 0.0;
-        for (int k = 0; k < NNF; ++k) g += geta[k][s] * p[pn[k]];
-        gp[s] = g;
+      for (int s = 0; s < DIM - 1; ++s) gp[s] = 0.0;
+      for (int k = 0; k < NNF; ++k) {
+        double dmu[DIM];
+        Lag<DIM - 1, ORDER>::dphi_one(k, mu_, dmu);
+        for (int s = 0; s < DIM - 1; ++s) gp[s] += (dmu[s + 1] - dmu[0]) * p[pn[k]];
       }
+      double dk[DIM];
+      Lag<DIM - 1, ORDER>::dphi_one(kk, mu_, dk);
+      const double etak = Lag<DIM - 1, ORDER>::phi_one(kk, mu_);
       const double W = c_rules.fq_w[q] * area;
       double gpg = 0.0;
       for (int s = 0; s < DIM - 1; ++s)
-        for (int t2 = 0; t2 < DIM - 1; ++t2) gpg += gp[s] * gi[s * (DIM - 1) + t2] * geta[kk][t2];
+        for (int t2 = 0; t2 < DIM - 1; ++t2) gpg += gp[s] * gi[s * (DIM - 1) + t2] * (dk[t2 + 1] - dk[0]);
       const double wo = w_old[(int64_t)f * NQF + q];
-      Ri += kp.s_p * W * (K * gpg + (w - wo) / kp.dt * eta[kk]);
+      Ri += P.s_p * W * (K * gpg + (w - wo) / P.dt * etak);
       for (int l = 0; l < NNF; ++l) {
+        double dl[DIM];
+        Lag<DIM - 1, ORDER>::dphi_one(l, mu_, dl);
         double gg = 0.0;
         for (int s = 0; s < DIM - 1; ++s)
-          for (int t2 = 0; t2 < DIM - 1; ++t2) gg += geta[l][s] * gi[s * (DIM - 1) + t2] * geta[kk][t2];
-        Drow[pn[l]] += kp.s_p * W * K * gg;
+          for (int t2 = 0; t2 < DIM - 1; ++t2) gg += (dl[s + 1] - dl[0]) * gi[s * (DIM - 1) + t2] * (dk[t2 + 1] - dk[0]);
+        Drow[pn[l] - p0] += P.s_p * W * K * gg;
       }
     }
   }
   for (int64_t s = 0; s < kp.s.n_src; ++s)
-    if (kp.m.src_node[s] == i) Ri -= kp.s_p * kp.m.src_q0[s];
+    if (kp.m.src_node[s] == i) Ri -= P.s_p * kp.m.src_q0[s];
   R[kp.s.n_u + i] = Ri;
 }
 
@@ -665,17 +668,16 @@ __global__ void k_opening(KParams kp, const double *__restrict__ u, double *__re
   w[t] = acc;
 }
 
-// crack volume sum_{fluid faces} sum_q W_q w_q: block partials, reduced by k_reduce
+// crack volume of each instance: out[b] = sum over its fluid faces and points of W_q w_q
 template <int DIM, int ORDER>
 __global__ __launch_bounds__(256) void k_fluid_volume(KParams kp, const double *__restrict__ u,
-                                                      double *__restrict__ partial) {
+                                                      double *__restrict__ out) {
   using C = Cfg<DIM, ORDER>;
   constexpr int NN = C::NN, BU = C::BU, NQF = C::NQF;
   __shared__ double sm[256];
+  const int b = blockIdx.x;
   double acc = 0.0;
-  const int64_t n = kp.s.n_act * NQF;
-  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t t0 = blockIdx.x * chunk, t1 = min(n, t0 + chunk);
+  const int64_t t0 = (int64_t)kp.aoff[b] * NQF, t1 = (int64_t)kp.aoff[b + 1] * NQF;
   for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
     const int64_t f = kp.m.act_face[t / NQF];
     const int q = (int)(t % NQF);
@@ -686,15 +688,12 @@ __global__ __launch_bounds__(256) void k_fluid_volume(KParams kp, const double *
       lm[kp.m.fperm_m[f * DIM + k]] = c_rules.fq_mu[q][k];
       lp[kp.m.fperm_p[f * DIM + k]] = c_rules.fq_mu[q][k];
     }
-    double phm[NN], php[NN];
-    Lag<DIM, ORDER>::phi(lm, phm);
-    Lag<DIM, ORDER>::phi(lp, php);
     double w = 0.0;
     for (int x = 0; x < DIM; ++x) {
       double um = 0.0, up = 0.0;
       for (int a = 0; a < NN; ++a) {
-        um += phm[a] * u[(int64_t)em * BU + a * DIM + x];
-        up += php[a] * u[(int64_t)ep * BU + a * DIM + x];
+        um += Lag<DIM, ORDER>::phi_one(a, lm) * u[(int64_t)em * BU + a * DIM + x];
+        up += Lag<DIM, ORDER>::phi_one(a, lp) * u[(int64_t)ep * BU + a * DIM + x];
       }
       w += (up - um) * kp.m.normal[f * DIM + x];
     }
@@ -706,15 +705,16 @@ __global__ __launch_bounds__(256) void k_fluid_volume(KParams kp, const double *
     if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
+  if (threadIdx.x == 0) out[b] = sm[0];
 }
 
-// max of w over the face points of fluid faces (single workgroup)
+// max of w over the face points of each instance's fluid faces: out[b]
 __global__ void k_wmax(KParams kp, const double *__restrict__ w, double *out) {
   __shared__ double sm[256];
   const int nq = kp.s.nqf;
+  const int b = blockIdx.x;
   double mx = -1e300;
-  for (int64_t t = threadIdx.x; t < kp.s.n_act * nq; t += blockDim.x) {
+  for (int64_t t = (int64_t)kp.aoff[b] * nq + threadIdx.x; t < (int64_t)kp.aoff[b + 1] * nq; t += blockDim.x) {
     const int32_t f = kp.m.act_face[t / nq];
     mx = fmax(mx, w[(int64_t)f * nq + t % nq]);
   }
@@ -724,7 +724,7 @@ __global__ void k_wmax(KParams kp, const double *__restrict__ w, double *out) {
     if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = sm[0];
+  if (threadIdx.x == 0) out[b] = sm[0];
 }
 
 template <int DIM, int ORDER>
@@ -763,24 +763,20 @@ hipError_t launch_opening(const KParams &kp, const double *u, double *w, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_partials(const double *partial, int nblk, int k, double *out,
-                                  hipStream_t st);
-
 hipError_t launch_fluid_volume(const KParams &kp, const double *u, double *partial, double *out,
                                hipStream_t st) {
-  const int nb = 64;
+  (void)partial;
+  const int nb = kp.n_inst;
   const int d = kp.s.dim, o = kp.s.order;
-  if (d == 2 && o == 1) hipLaunchKernelGGL((k_fluid_volume<2, 1>), dim3(nb), dim3(256), 0, st, kp, u, partial);
-  else if (d == 2 && o == 2) hipLaunchKernelGGL((k_fluid_volume<2, 2>), dim3(nb), dim3(256), 0, st, kp, u, partial);
-  else if (d == 3 && o == 1) hipLaunchKernelGGL((k_fluid_volume<3, 1>), dim3(nb), dim3(256), 0, st, kp, u, partial);
-  else hipLaunchKernelGGL((k_fluid_volume<3, 2>), dim3(nb), dim3(256), 0, st, kp, u, partial);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_reduce_partials(partial, nb, 1, out, st);
+  if (d == 2 && o == 1) hipLaunchKernelGGL((k_fluid_volume<2, 1>), dim3(nb), dim3(256), 0, st, kp, u, out);
+  else if (d == 2 && o == 2) hipLaunchKernelGGL((k_fluid_volume<2, 2>), dim3(nb), dim3(256), 0, st, kp, u, out);
+  else if (d == 3 && o == 1) hipLaunchKernelGGL((k_fluid_volume<3, 1>), dim3(nb), dim3(256), 0, st, kp, u, out);
+  else hipLaunchKernelGGL((k_fluid_volume<3, 2>), dim3(nb), dim3(256), 0, st, kp, u, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_wmax(const KParams &kp, const double *w, double *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_wmax, dim3(1), dim3(256), 0, st, kp, w, out);
+  hipLaunchKernelGGL(k_wmax, dim3(kp.n_inst), dim3(256), 0, st, kp, w, out);
   return hipGetLastError();
 }
 

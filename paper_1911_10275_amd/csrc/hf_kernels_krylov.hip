@@ -1,0 +1,546 @@
+// Batched Krylov kernels for gfx950: GMRES vector work segmented by
+// instance, and the per-instance Hessenberg / Givens / least-squares steps
+// on the device, so that a chunk of GMRES iterations runs without host
+// round trips (and can be captured in a HIP graph).
+//
+// Row chunks.  The rows of the global vector [u_all; p_all] are cut into
+// chunks of at most KC_CHUNK rows that never straddle two instances; chunk c
+// covers rows [row0[c], row0[c] + len[c]) of instance inst[c], and the
+// chunks of instance b are [cptr[b], cptr[b+1]).  Each chunk writes one
+// partial per output; k_seg_reduce sums the partials of an instance in a
+// fixed order, so every reduction is bitwise reproducible.
+//
+// Instance state (one entry per instance): solving[b] (1 while the instance
+// still iterates in this cycle), kconv[b] (-1, or the basis size at which the
+// cycle stopped), bnorm[b], H[b] ((m+1) x m, row-major), cs/sn[b] (m), g[b]
+// (m+1), scale[b] (1/||w|| used to normalise the next basis vector).
+#include <cmath>
+
+#include "hf_internal.h"
+
+namespace hf {
+
+constexpr int KT = 256;        // threads per block
+constexpr int KR = 4;          // rows per thread
+constexpr int KTILE = 8;       // basis vectors per tile
+
+__device__ inline double kwave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__device__ inline bool inst_on(const KrylovDev &kd, int b) {
+  return kd.solving[b] != 0 && kd.kconv[b] < 0;
+}
+
+// partial[c*(k+1) + i] = chunk sum of V_i w (i < k); partial[c*(k+1) + k] = chunk sum of w^2.
+// With gate != nullptr the chunk only works when gate[inst] != 0.
+template <typename T>
+__global__ __launch_bounds__(KT) void k_sproj(KrylovDev kd, const T *__restrict__ V, int64_t ldv,
+                                              int k, const T *__restrict__ w,
+                                              const int *__restrict__ gate,
+                                              double *__restrict__ partial) {
+  __shared__ double wsum[kMaxKrylov + 1][KT / 64];
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int b = kd.c_inst[c];
+  double *out = partial + (int64_t)c * (k + 1);
+  if (!inst_on(kd, b) || (gate && !gate[b])) {
+    for (int i = tid; i <= k; i += KT) out[i] = 0.0;
+    return;
+  }
+  const int64_t row0 = kd.c_row0[c];
+  const int len = kd.c_len[c];
+  double wr[KR];
+  double nn = 0.0;
+#pragma unroll
+  for (int s = 0; s < KR; ++s) {
+    const int rr = tid + s * KT;
+    wr[s] = rr < len ? (double)w[row0 + rr] : 0.0;
+    nn += wr[s] * wr[s];
+  }
+  for (int i0 = 0; i0 < k; i0 += KTILE) {
+    double acc[KTILE];
+#pragma unroll
+    for (int q = 0; q < KTILE; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int s = 0; s < KR; ++s) {
+      const int rr = tid + s * KT;
+      if (rr < len) {
+#pragma unroll
+        for (int q = 0; q < KTILE; ++q)
+          if (i0 + q < k) acc[q] += (double)V[(int64_t)(i0 + q) * ldv + row0 + rr] * wr[s];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KTILE; ++q) {
+      const double v = kwave_sum(acc[q]);
+      if (lane == 0 && i0 + q < k) wsum[i0 + q][wv] = v;
+    }
+  }
+  nn = kwave_sum(nn);
+  if (lane == 0) wsum[k][wv] = nn;
+  __syncthreads();
+  for (int i = tid; i <= k; i += KT) {
+    double s2 = 0.0;
+    for (int q = 0; q < KT / 64; ++q) s2 += wsum[i][q];
+    out[i] = s2;
+  }
+}
+
+// w -= V h_b (h_b = h + b*hstride); partial[c] = chunk sum of the new w^2.
+template <typename T>
+__global__ __launch_bounds__(KT) void k_supdate(KrylovDev kd, const T *__restrict__ V, int64_t ldv,
+                                                int k, const double *__restrict__ h, int hstride,
+                                                T *__restrict__ w, const int *__restrict__ gate,
+                                                double *__restrict__ partial) {
+  __shared__ double sh[kMaxKrylov];
+  __shared__ double wsum[KT / 64];
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int b = kd.c_inst[c];
+  if (!inst_on(kd, b) || (gate && !gate[b])) {
+    if (tid == 0) partial[c] = 0.0;
+    return;
+  }
+  for (int i = tid; i < k; i += KT) sh[i] = h[(int64_t)b * hstride + i];
+  __syncthreads();
+  const int64_t row0 = kd.c_row0[c];
+  const int len = kd.c_len[c];
+  double acc[KR];
+#pragma unroll
+  for (int s = 0; s < KR; ++s) {
+    const int rr = tid + s * KT;
+    acc[s] = rr < len ? (double)w[row0 + rr] : 0.0;
+  }
+  for (int i0 = 0; i0 < k; i0 += KTILE) {
+#pragma unroll
+    for (int s = 0; s < KR; ++s) {
+      const int rr = tid + s * KT;
+      if (rr < len) {
+#pragma unroll
+        for (int q = 0; q < KTILE; ++q)
+          if (i0 + q < k) acc[s] -= sh[i0 + q] * (double)V[(int64_t)(i0 + q) * ldv + row0 + rr];
+      }
+    }
+  }
+  double nn = 0.0;
+#pragma unroll
+  for (int s = 0; s < KR; ++s) {
+    const int rr = tid + s * KT;
+    if (rr < len) {
+      const T v = (T)acc[s];
+      w[row0 + rr] = v;
+      nn += (double)v * (double)v;
+    }
+  }
+  nn = kwave_sum(nn);
+  if (lane == 0) wsum[wv] = nn;
+  __syncthreads();
+  if (tid == 0) {
+    double s2 = 0.0;
+    for (int q = 0; q < KT / 64; ++q) s2 += wsum[q];
+    partial[c] = s2;
+  }
+}
+
+// out[b*nout + i] = sum over the chunks of instance b of partial[c*nout + i]
+__global__ __launch_bounds__(KT) void k_seg_reduce(KrylovDev kd, const double *__restrict__ partial,
+                                                   int nout, double *__restrict__ out) {
+  __shared__ double sm[KT];
+  const int b = blockIdx.x, i = blockIdx.y;
+  const int c0 = kd.cptr[b], c1 = kd.cptr[b + 1];
+  double acc = 0.0;
+  for (int c = c0 + threadIdx.x; c < c1; c += KT) acc += partial[(int64_t)c * nout + i];
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = KT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[(int64_t)b * nout + i] = sm[0];
+}
+
+// v[r] = w[r] * scale[inst]   (scale = 0 for instances that are not iterating)
+template <typename T>
+__global__ __launch_bounds__(KT) void k_sscale(KrylovDev kd, const T *__restrict__ w,
+                                               const double *__restrict__ scale, T *__restrict__ v) {
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int b = kd.c_inst[c];
+  const double s = kd.solving[b] ? scale[b] : 0.0;
+  const int64_t row0 = kd.c_row0[c];
+  const int len = kd.c_len[c];
+  // exact zeros (not w * 0) for idle instances, whatever w holds
+  for (int rr = tid; rr < len; rr += KT) v[row0 + rr] = s == 0.0 ? T(0) : (T)((double)w[row0 + rr] * s);
+}
+
+// out[r] = sum_{i < nb} y_b[i] V_i[r], nb = basis size of the instance's cycle
+template <typename T>
+__global__ __launch_bounds__(KT) void k_scombine(KrylovDev kd, const T *__restrict__ V, int64_t ldv,
+                                                 const double *__restrict__ y, int ystride,
+                                                 const int *__restrict__ nbasis, T *__restrict__ out) {
+  __shared__ double sy[kMaxKrylov];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int b = kd.c_inst[c];
+  const int nb = kd.solving[b] ? nbasis[b] : 0;
+  for (int i = tid; i < nb; i += KT) sy[i] = y[(int64_t)b * ystride + i];
+  __syncthreads();
+  const int64_t row0 = kd.c_row0[c];
+  const int len = kd.c_len[c];
+  for (int rr = tid; rr < len; rr += KT) {
+    double acc = 0.0;
+    for (int i = 0; i < nb; ++i) acc += sy[i] * (double)V[(int64_t)i * ldv + row0 + rr];
+    out[row0 + rr] = (T)acc;
+  }
+}
+
+// x[r] += a_b * z[r]  (a_b = coef[inst] or 1 when coef is null; only iterating instances)
+template <typename TX, typename TZ>
+__global__ __launch_bounds__(KT) void k_saxpy(KrylovDev kd, const double *__restrict__ coef,
+                                              const TZ *__restrict__ z, TX *__restrict__ x) {
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int b = kd.c_inst[c];
+  if (!kd.solving[b]) return;
+  const double a = coef ? coef[b] : 1.0;
+  const int64_t row0 = kd.c_row0[c];
+  const int len = kd.c_len[c];
+  for (int rr = tid; rr < len; rr += KT) x[row0 + rr] = (TX)((double)x[row0 + rr] + a * (double)z[row0 + rr]);
+}
+
+// r = b - Jx for iterating instances (others untouched)
+template <typename T>
+__global__ __launch_bounds__(KT) void k_ssub(KrylovDev kd, const T *__restrict__ bvec,
+                                             const T *__restrict__ jx, T *__restrict__ r) {
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int b = kd.c_inst[c];
+  if (!kd.solving[b]) return;
+  const int64_t row0 = kd.c_row0[c];
+  const int len = kd.c_len[c];
+  for (int rr = tid; rr < len; rr += KT) r[row0 + rr] = bvec[row0 + rr] - jx[row0 + rr];
+}
+
+// y[r] = (T)(x[r] * coef[inst])  (precision cast with per-instance scale; 0 when idle)
+template <typename TY, typename TX>
+__global__ __launch_bounds__(KT) void k_scast(KrylovDev kd, const TX *__restrict__ x,
+                                              const double *__restrict__ coef, TY *__restrict__ y) {
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int b = kd.c_inst[c];
+  const double a = kd.solving[b] ? coef[b] : 0.0;
+  const int64_t row0 = kd.c_row0[c];
+  const int len = kd.c_len[c];
+  for (int rr = tid; rr < len; rr += KT) y[row0 + rr] = a == 0.0 ? TY(0) : (TY)(a * (double)x[row0 + rr]);
+}
+
+// zero a vector segment-wise (graph-safe replacement of memset)
+template <typename T>
+__global__ __launch_bounds__(KT) void k_szero(KrylovDev kd, T *__restrict__ x, int only_solving) {
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int b = kd.c_inst[c];
+  if (only_solving && !kd.solving[b]) return;
+  const int64_t row0 = kd.c_row0[c];
+  const int len = kd.c_len[c];
+  for (int rr = tid; rr < len; rr += KT) x[row0 + rr] = T(0);
+}
+
+// Re-orthogonalisation test (Daniel-Gragg-Kaufman-Stewart): flag[b] = 1 when
+// ||w1|| < ||w|| / sqrt(2).  n0 = ||w||^2 (stride n0s), n1 = ||w1||^2.
+__global__ void k_reorth_flag(KrylovDev kd, const double *__restrict__ n0, int n0s,
+                              const double *__restrict__ n1, int *__restrict__ flag) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= kd.n_inst) return;
+  flag[b] = inst_on(kd, b) && (n1[b] < 0.5 * n0[(int64_t)b * n0s]) ? 1 : 0;
+}
+
+// Arnoldi step j of every iterating instance: column j of H from the two
+// Gram-Schmidt passes, previous rotations, the new rotation, the residual
+// estimate; stop the cycle of an instance when the estimate reaches
+// rtol * bnorm, on breakdown, or at its iteration cap.
+__global__ void k_arnoldi(KrylovDev kd, int j, int m, const double *__restrict__ s1, int s1s,
+                          const double *__restrict__ s2, int s2s, const int *__restrict__ reorth,
+                          const double *__restrict__ n1, const double *__restrict__ n2,
+                          double rtol, double *__restrict__ scale) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= kd.n_inst) return;
+  if (!inst_on(kd, b)) {
+    scale[b] = 0.0;
+    return;
+  }
+  double *H = kd.H + (int64_t)b * (m + 1) * m;
+  double *cs = kd.cs + (int64_t)b * m, *sn = kd.sn + (int64_t)b * m, *g = kd.g + (int64_t)b * (m + 1);
+  const bool ro = reorth[b] != 0;
+  for (int i = 0; i <= j; ++i)
+    H[i * m + j] = s1[(int64_t)b * s1s + i] + (ro ? s2[(int64_t)b * s2s + i] : 0.0);
+  const double hn = sqrt(ro ? n2[b] : n1[b]);
+  H[(j + 1) * m + j] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+    H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+    H[i * m + j] = t;
+  }
+  const double den = hypot(H[j * m + j], H[(j + 1) * m + j]);
+  if (den == 0.0) {
+    cs[j] = 1.0;
+    sn[j] = 0.0;
+  } else {
+    cs[j] = H[j * m + j] / den;
+    sn[j] = H[(j + 1) * m + j] / den;
+  }
+  H[j * m + j] = cs[j] * H[j * m + j] + sn[j] * H[(j + 1) * m + j];
+  H[(j + 1) * m + j] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  kd.its[b] += 1;
+  const bool fin = !isfinite(hn) || !isfinite(g[j + 1]);
+  if (fin) kd.status[b] = 2;
+  if (fabs(g[j + 1]) <= rtol * kd.bnorm[b] || hn == 0.0 || kd.its[b] >= kd.itmax[b] || j + 1 == m ||
+      fin)
+    kd.kconv[b] = j + 1;
+  scale[b] = hn > 0.0 ? 1.0 / hn : 0.0;
+}
+
+// number of instances still iterating in this cycle -> *count
+__global__ void k_count_active(KrylovDev kd, int *count) {
+  __shared__ int sm[256];
+  int c = 0;
+  for (int b = threadIdx.x; b < kd.n_inst; b += 256) c += inst_on(kd, b) ? 1 : 0;
+  sm[threadIdx.x] = c;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = sm[0];
+}
+
+// y_b = H_b(1:k,1:k)^-1 g_b (back substitution), k = kconv[b]; est[b] = |g_b[k]|
+__global__ void k_solve_y(KrylovDev kd, int m, double *__restrict__ y, double *__restrict__ est) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= kd.n_inst) return;
+  if (!kd.solving[b]) {
+    kd.nbasis[b] = 0;
+    return;
+  }
+  const int k = kd.kconv[b] < 0 ? m : kd.kconv[b];
+  const double *H = kd.H + (int64_t)b * (m + 1) * m;
+  const double *g = kd.g + (int64_t)b * (m + 1);
+  double *yb = y + (int64_t)b * m;
+  for (int i = k - 1; i >= 0; --i) {
+    double acc = g[i];
+    for (int c2 = i + 1; c2 < k; ++c2) acc -= H[i * m + c2] * yb[c2];
+    yb[i] = acc / H[i * m + i];
+  }
+  kd.nbasis[b] = k;
+  est[b] = fabs(g[k]);
+}
+
+// start of a cycle: g = (beta, 0, ...), kconv = -1, scale = 1/beta for
+// iterating instances with beta > 0 (an instance with beta = 0 is done)
+__global__ void k_cycle_start(KrylovDev kd, int m, const double *__restrict__ beta2,
+                              double *__restrict__ scale) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= kd.n_inst) return;
+  double *g = kd.g + (int64_t)b * (m + 1);
+  for (int i = 0; i <= m; ++i) g[i] = 0.0;
+  kd.kconv[b] = -1;
+  const double beta = sqrt(beta2[b]);
+  g[0] = beta;
+  scale[b] = (kd.solving[b] && beta > 0.0) ? 1.0 / beta : 0.0;
+  if (kd.solving[b] && !(beta > 0.0)) kd.kconv[b] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t ks_proj(const KrylovDev &kd, const T *V, int64_t ldv, int k, const T *w,
+                   const int *gate, double *partial, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sproj<T>, dim3(kd.n_chunks), dim3(KT), 0, st, kd, V, ldv, k, w, gate, partial);
+  hipLaunchKernelGGL(k_seg_reduce, dim3(kd.n_inst, k + 1), dim3(KT), 0, st, kd, partial, k + 1, out);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t ks_update(const KrylovDev &kd, const T *V, int64_t ldv, int k, const double *h,
+                     int hstride, T *w, const int *gate, double *partial, double *out,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_supdate<T>, dim3(kd.n_chunks), dim3(KT), 0, st, kd, V, ldv, k, h, hstride, w,
+                     gate, partial);
+  hipLaunchKernelGGL(k_seg_reduce, dim3(kd.n_inst, 1), dim3(KT), 0, st, kd, partial, 1, out);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t ks_scale(const KrylovDev &kd, const T *w, const double *scale, T *v, hipStream_t st) {
+  hipLaunchKernelGGL(k_sscale<T>, dim3(kd.n_chunks), dim3(KT), 0, st, kd, w, scale, v);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t ks_combine(const KrylovDev &kd, const T *V, int64_t ldv, const double *y, int ystride,
+                      T *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_scombine<T>, dim3(kd.n_chunks), dim3(KT), 0, st, kd, V, ldv, y, ystride,
+                     kd.nbasis, out);
+  return hipGetLastError();
+}
+template <typename TX, typename TZ>
+hipError_t ks_axpy(const KrylovDev &kd, const double *coef, const TZ *z, TX *x, hipStream_t st) {
+  hipLaunchKernelGGL((k_saxpy<TX, TZ>), dim3(kd.n_chunks), dim3(KT), 0, st, kd, coef, z, x);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t ks_sub(const KrylovDev &kd, const T *b, const T *jx, T *r, hipStream_t st) {
+  hipLaunchKernelGGL(k_ssub<T>, dim3(kd.n_chunks), dim3(KT), 0, st, kd, b, jx, r);
+  return hipGetLastError();
+}
+template <typename TY, typename TX>
+hipError_t ks_cast(const KrylovDev &kd, const TX *x, const double *coef, TY *y, hipStream_t st) {
+  hipLaunchKernelGGL((k_scast<TY, TX>), dim3(kd.n_chunks), dim3(KT), 0, st, kd, x, coef, y);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t ks_zero(const KrylovDev &kd, T *x, int only_solving, hipStream_t st) {
+  hipLaunchKernelGGL(k_szero<T>, dim3(kd.n_chunks), dim3(KT), 0, st, kd, x, only_solving);
+  return hipGetLastError();
+}
+hipError_t ks_reorth_flag(const KrylovDev &kd, const double *n0, int n0s, const double *n1, int *flag,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_reorth_flag, dim3((kd.n_inst + 63) / 64), dim3(64), 0, st, kd, n0, n0s, n1, flag);
+  return hipGetLastError();
+}
+hipError_t ks_arnoldi(const KrylovDev &kd, int j, int m, const double *s1, int s1s, const double *s2,
+                      int s2s, const int *reorth, const double *n1, const double *n2, double rtol,
+                      double *scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_arnoldi, dim3((kd.n_inst + 63) / 64), dim3(64), 0, st, kd, j, m, s1, s1s, s2,
+                     s2s, reorth, n1, n2, rtol, scale);
+  return hipGetLastError();
+}
+hipError_t ks_count_active(const KrylovDev &kd, int *count, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, st, kd, count);
+  return hipGetLastError();
+}
+hipError_t ks_solve_y(const KrylovDev &kd, int m, double *y, double *est, hipStream_t st) {
+  hipLaunchKernelGGL(k_solve_y, dim3((kd.n_inst + 63) / 64), dim3(64), 0, st, kd, m, y, est);
+  return hipGetLastError();
+}
+hipError_t ks_cycle_start(const KrylovDev &kd, int m, const double *beta2, double *scale,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_cycle_start, dim3((kd.n_inst + 63) / 64), dim3(64), 0, st, kd, m, beta2, scale);
+  return hipGetLastError();
+}
+
+#define KS_INST(T)                                                                              \
+  template hipError_t ks_proj<T>(const KrylovDev &, const T *, int64_t, int, const T *,          \
+                                 const int *, double *, double *, hipStream_t);                 \
+  template hipError_t ks_update<T>(const KrylovDev &, const T *, int64_t, int, const double *,   \
+                                   int, T *, const int *, double *, double *, hipStream_t);     \
+  template hipError_t ks_scale<T>(const KrylovDev &, const T *, const double *, T *, hipStream_t); \
+  template hipError_t ks_combine<T>(const KrylovDev &, const T *, int64_t, const double *, int,  \
+                                    T *, hipStream_t);                                          \
+  template hipError_t ks_sub<T>(const KrylovDev &, const T *, const T *, T *, hipStream_t);      \
+  template hipError_t ks_zero<T>(const KrylovDev &, T *, int, hipStream_t);
+KS_INST(double)
+KS_INST(float)
+template hipError_t ks_axpy<double, double>(const KrylovDev &, const double *, const double *, double *, hipStream_t);
+template hipError_t ks_axpy<float, float>(const KrylovDev &, const double *, const float *, float *, hipStream_t);
+template hipError_t ks_axpy<double, float>(const KrylovDev &, const double *, const float *, double *, hipStream_t);
+template hipError_t ks_cast<float, double>(const KrylovDev &, const double *, const double *, float *, hipStream_t);
+template hipError_t ks_cast<double, double>(const KrylovDev &, const double *, const double *, double *, hipStream_t);
+
+
+// ---------------------------------------------------------------------------
+// per-instance norms and the Newton update (all instances, no gating)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(KT) void k_snorm2(KrylovDev kd, const T *__restrict__ x,
+                                               double *__restrict__ partial) {
+  __shared__ double wsum[KT / 64];
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int64_t row0 = kd.c_row0[c];
+  const int len = kd.c_len[c];
+  double acc = 0.0;
+  for (int rr = tid; rr < len; rr += KT) {
+    const double v = (double)x[row0 + rr];
+    acc += v * v;
+  }
+  acc = kwave_sum(acc);
+  if (lane == 0) wsum[wv] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double s2 = 0.0;
+    for (int q = 0; q < KT / 64; ++q) s2 += wsum[q];
+    partial[c] = s2;
+  }
+}
+
+template <typename T>
+hipError_t ks_norms(const KrylovDev &kd, const T *x, double *partial, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_snorm2<T>, dim3(kd.n_chunks), dim3(KT), 0, st, kd, x, partial);
+  hipLaunchKernelGGL(k_seg_reduce, dim3(kd.n_inst, 1), dim3(KT), 0, st, kd, partial, 1, out);
+  return hipGetLastError();
+}
+template hipError_t ks_norms<double>(const KrylovDev &, const double *, double *, double *, hipStream_t);
+template hipError_t ks_norms<float>(const KrylovDev &, const float *, double *, double *, hipStream_t);
+
+hipError_t launch_seg_norms(const KrylovDev &kd, const double *x, double *partial, double *out,
+                            hipStream_t st) {
+  return ks_norms<double>(kd, x, partial, out, st);
+}
+
+__global__ void k_begin(KrylovDev kd, const double *__restrict__ n2) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= kd.n_inst) return;
+  kd.bnorm[b] = sqrt(n2[b]);
+  kd.kconv[b] = -1;
+  kd.its[b] = 0;
+  kd.status[b] = 0;
+}
+hipError_t ks_begin(const KrylovDev &kd, const double *n2, hipStream_t st) {
+  hipLaunchKernelGGL(k_begin, dim3((kd.n_inst + 63) / 64), dim3(64), 0, st, kd, n2);
+  return hipGetLastError();
+}
+
+// x += dx on instances with upd[b] != 0 (p >= cut-off when enabled);
+// partial[c*4 + (0..3)] = ||du||^2, ||u||^2, ||dp||^2, ||p||^2 of the chunk
+__global__ __launch_bounds__(KT) void k_snewton_update(KrylovDev kd, const double *__restrict__ dx,
+                                                       double *__restrict__ x, int64_t n_u,
+                                                       const int *__restrict__ upd, int cutoff_on,
+                                                       double cutoff, double *__restrict__ partial) {
+  __shared__ double wsum[4][KT / 64];
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int b = kd.c_inst[c];
+  const bool on = upd[b] != 0;
+  const int64_t row0 = kd.c_row0[c];
+  const int len = kd.c_len[c];
+  double a0 = 0.0, a1 = 0.0;
+  const bool isp = row0 >= n_u;
+  for (int rr = tid; rr < len; rr += KT) {
+    const int64_t r = row0 + rr;
+    const double d = on ? dx[r] : 0.0;
+    double v = x[r] + d;
+    if (isp && on && cutoff_on && v < cutoff) v = cutoff;
+    if (on) x[r] = v;
+    a0 += d * d;
+    a1 += v * v;
+  }
+  a0 = kwave_sum(a0);
+  a1 = kwave_sum(a1);
+  if (lane == 0) {
+    wsum[isp ? 2 : 0][wv] = a0;
+    wsum[isp ? 3 : 1][wv] = a1;
+    wsum[isp ? 0 : 2][wv] = 0.0;
+    wsum[isp ? 1 : 3][wv] = 0.0;
+  }
+  __syncthreads();
+  if (tid < 4) {
+    double s2 = 0.0;
+    for (int q = 0; q < KT / 64; ++q) s2 += wsum[tid][q];
+    partial[(int64_t)c * 4 + tid] = s2;
+  }
+}
+
+hipError_t launch_snewton_update(const KrylovDev &kd, const double *dx, double *x, int64_t n_u,
+                                 const int *upd, int cutoff_on, double cutoff, double *partial,
+                                 double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_snewton_update, dim3(kd.n_chunks), dim3(KT), 0, st, kd, dx, x, n_u, upd,
+                     cutoff_on, cutoff, partial);
+  hipLaunchKernelGGL(k_seg_reduce, dim3(kd.n_inst, 4), dim3(KT), 0, st, kd, partial, 4, out);
+  return hipGetLastError();
+}
+
+}  // namespace hf

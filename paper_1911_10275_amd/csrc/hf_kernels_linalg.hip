@@ -110,9 +110,13 @@ __global__ __launch_bounds__(NT) void k_bsr_spmv(
   }
 }
 
-// pressure rows: y_p[i] = sum_strips C x_u + sum_j D[i][j] x_p[j]  (one wave per row)
+// pressure rows: y_p[i] = sum_strips C x_u + sum_j D_b[i][j] x_p[j] over the dense block
+// of the row's instance b (one wave per row)
 template <typename T, int BU>
-__global__ __launch_bounds__(64) void k_prows(int64_t np, const int32_t *__restrict__ pc_ptr,
+__global__ __launch_bounds__(64) void k_prows(int64_t np, const int32_t *__restrict__ pinst,
+                                              const int32_t *__restrict__ poff,
+                                              const int64_t *__restrict__ doff,
+                                              const int32_t *__restrict__ pc_ptr,
                                               const int32_t *__restrict__ pc_ent,
                                               const int32_t *__restrict__ sp_elem,
                                               const T *__restrict__ Cs, const T *__restrict__ D,
@@ -128,7 +132,10 @@ __global__ __launch_bounds__(64) void k_prows(int64_t np, const int32_t *__restr
       if (lane < BU) acc += (double)Cs[(int64_t)ent * BU + lane] * (double)xu[e * BU + lane];
     }
   }
-  for (int64_t j = lane; j < np; j += 64) acc += (double)D[i * np + j] * (double)xp[j];
+  const int b = pinst[i];
+  const int64_t p0 = poff[b], nb = poff[b + 1] - p0;
+  const T *Drow = D + doff[b] + (i - p0) * nb;
+  for (int64_t j = lane; j < nb; j += 64) acc += (double)Drow[j] * (double)xp[p0 + j];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) yp[i] = (T)acc;
@@ -146,8 +153,8 @@ static void spmv_bu(const KParams &kp, const T *A, const T *Bs, const T *Cs, con
                        x + kp.s.n_u, y);
   if (kp.s.n_p)
     hipLaunchKernelGGL((k_prows<T, BU>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp.s.n_p,
-                       kp.m.pc_ptr, kp.m.pc_ent, kp.m.sp_elem, Cs, D, x, x + kp.s.n_u,
-                       y + kp.s.n_u);
+                       kp.pinst, kp.poff, kp.doff, kp.m.pc_ptr, kp.m.pc_ent, kp.m.sp_elem, Cs, D, x,
+                       x + kp.s.n_u, y + kp.s.n_u);
 }
 
 template <typename T>
@@ -181,7 +188,8 @@ static void precond_bu(const KParams &kp, const T *inv, const T *Sinv, const T *
                        ne, ident_ptr, ident_col, inv, nullptr, nullptr, nullptr, r, nullptr, z);
   if (kp.s.n_p)
     hipLaunchKernelGGL((k_prows<T, BU>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp.s.n_p,
-                       nullptr, nullptr, nullptr, nullptr, Sinv, r, r + kp.s.n_u, z + kp.s.n_u);
+                       kp.pinst, kp.poff, kp.doff, nullptr, nullptr, nullptr, nullptr, Sinv, r,
+                       r + kp.s.n_u, z + kp.s.n_u);
 }
 
 template <typename T>
@@ -210,6 +218,7 @@ template hipError_t launch_precond<float>(const KParams &, const float *, const 
 // ---------------------------------------------------------------------------
 template <int BU>
 __global__ __launch_bounds__(64) void k_blockinv(int64_t ne, const int64_t *__restrict__ blk_ptr,
+                                                 const int32_t *__restrict__ einst,
                                                  const double *__restrict__ A,
                                                  double *__restrict__ inv,
                                                  float *__restrict__ inv32, int *flag) {
@@ -240,7 +249,7 @@ __global__ __launch_bounds__(64) void k_blockinv(int64_t ne, const int64_t *__re
     const int p = idx;
     const double piv = __shfl(a[k], p, 64);
     if (!(fabs(piv) > 0.0) || !isfinite(piv)) {
-      if (lane == 0) atomicOr(flag, 1);
+      if (lane == 0) atomicOr(flag + einst[e], 1);
       return;
     }
     if (lane == p) {
@@ -278,9 +287,9 @@ hipError_t launch_blockinv(const KParams &kp, const double *A, double *inv, floa
   const int64_t ne = kp.s.ne;
   if (!ne) return hipSuccess;
   switch (kp.s.bu) {
-    case 6: hipLaunchKernelGGL(k_blockinv<6>, dim3((unsigned)ne), dim3(64), 0, st, ne, kp.m.blk_ptr, A, inv, inv32, flag); break;
-    case 12: hipLaunchKernelGGL(k_blockinv<12>, dim3((unsigned)ne), dim3(64), 0, st, ne, kp.m.blk_ptr, A, inv, inv32, flag); break;
-    case 30: hipLaunchKernelGGL(k_blockinv<30>, dim3((unsigned)ne), dim3(64), 0, st, ne, kp.m.blk_ptr, A, inv, inv32, flag); break;
+    case 6: hipLaunchKernelGGL(k_blockinv<6>, dim3((unsigned)ne), dim3(64), 0, st, ne, kp.m.blk_ptr, kp.einst, A, inv, inv32, flag); break;
+    case 12: hipLaunchKernelGGL(k_blockinv<12>, dim3((unsigned)ne), dim3(64), 0, st, ne, kp.m.blk_ptr, kp.einst, A, inv, inv32, flag); break;
+    case 30: hipLaunchKernelGGL(k_blockinv<30>, dim3((unsigned)ne), dim3(64), 0, st, ne, kp.m.blk_ptr, kp.einst, A, inv, inv32, flag); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -320,14 +329,17 @@ __global__ __launch_bounds__(64) void k_schur_t(KParams kp, const double *__rest
   }
 }
 
-// per pressure row: S[i][:] = D[i][:] - sum of the T blocks that touch row i
+// per pressure row: S_b[i][:] = D_b[i][:] - sum of the T blocks that touch row i
 __global__ void k_schur_gather(KParams kp, const double *__restrict__ D,
                                const double *__restrict__ T, const int32_t *__restrict__ sp_se,
                                double *__restrict__ S) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t np = kp.s.n_p;
-  if (i >= np) return;
-  for (int64_t j = 0; j < np; ++j) S[i * np + j] = D[i * np + j];
+  if (i >= kp.s.n_p) return;
+  const int b = kp.pinst[i];
+  const int64_t p0 = kp.poff[b], nb = kp.poff[b + 1] - p0;
+  double *Srow = S + kp.doff[b] + (i - p0) * nb;
+  const double *Drow = D + kp.doff[b] + (i - p0) * nb;
+  for (int64_t j = 0; j < nb; ++j) Srow[j] = Drow[j];
   for (int32_t c = kp.m.pc_ptr[i]; c < kp.m.pc_ptr[i + 1]; ++c) {
     const int32_t ent = kp.m.pc_ent[c];
     const int64_t e = kp.m.sp_elem[ent];
@@ -335,15 +347,22 @@ __global__ void k_schur_gather(KParams kp, const double *__restrict__ D,
     const int ns = (int)(kp.m.sp_ptr[e + 1] - s0);
     const int rho = (int)(ent - s0);
     const double *Te = T + kp.m.t_ptr[sp_se[ent]];
-    for (int c2 = 0; c2 < ns; ++c2) S[i * np + kp.m.sp_pnode[s0 + c2]] -= Te[rho * ns + c2];
+    for (int c2 = 0; c2 < ns; ++c2) Srow[kp.m.sp_pnode[s0 + c2] - p0] -= Te[rho * ns + c2];
   }
 }
 
 // dense Gauss-Jordan inverse with partial pivoting, one workgroup, in place
 constexpr int kMaxDenseP = 4096;
-__global__ __launch_bounds__(256) void k_dense_inv(int64_t n, double *__restrict__ W,
-                                                   double *__restrict__ out,
-                                                   float *__restrict__ out32, int *flag) {
+__global__ __launch_bounds__(256) void k_dense_inv(const int32_t *__restrict__ poff,
+                                                   const int64_t *__restrict__ doff,
+                                                   double *__restrict__ Wall,
+                                                   double *__restrict__ outall,
+                                                   float *__restrict__ out32all, int *flag) {
+  const int bi = blockIdx.x;
+  const int64_t n = poff[bi + 1] - poff[bi];
+  double *W = Wall + doff[bi];
+  double *out = outall + doff[bi];
+  float *out32 = out32all + doff[bi];
   __shared__ double colk[kMaxDenseP];
   __shared__ int perm[kMaxDenseP];
   __shared__ double sv[256];
@@ -377,7 +396,7 @@ __global__ __launch_bounds__(256) void k_dense_inv(int64_t n, double *__restrict
     const double pv = (p < n) ? W[(int64_t)p * n + k] : 0.0;
     __syncthreads();
     if (!(fabs(pv) > 0.0) || !isfinite(pv)) {
-      if (tid == 0) atomicOr(flag, 2);
+      if (tid == 0) atomicOr(flag + bi, 2);
       return;
     }
     if (tid == 0) perm[k] = p;
@@ -422,12 +441,12 @@ hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,
   (void)Z;
   const int64_t np = kp.s.n_p;
   if (!np) return hipSuccess;
-  if (np > kMaxDenseP) return hipErrorInvalidValue;
   if (kp.s.n_se)
     hipLaunchKernelGGL(k_schur_t, dim3((unsigned)kp.s.n_se), dim3(64), 0, st, kp, inv, Bs, Cs, T);
   hipLaunchKernelGGL(k_schur_gather, dim3((unsigned)((np + 63) / 64)), dim3(64), 0, st, kp, D, T,
                      kp.m.sp_se, S);
-  hipLaunchKernelGGL(k_dense_inv, dim3(1), dim3(256), 0, st, np, S, Sinv, Sinv32, flag);
+  hipLaunchKernelGGL(k_dense_inv, dim3(kp.n_inst), dim3(256), 0, st, kp.poff, kp.doff, S, Sinv,
+                     Sinv32, flag);
   return hipGetLastError();
 }
 
@@ -785,9 +804,15 @@ template hipError_t launch_combine<double>(const double *, int64_t, int, const d
 template hipError_t launch_combine<float>(const float *, int64_t, int, const double *, float *,
                                           int64_t, hipStream_t);
 
+// y = a x + b y; a term with a zero coefficient is not read, so y may start
+// uninitialised when b = 0
 __global__ void k_axpby(double a, const double *__restrict__ x, double b, double *__restrict__ y,
                         int64_t n) {
-  GRID_STRIDE(t, n) y[t] = a * x[t] + b * y[t];
+  GRID_STRIDE(t, n) {
+    double v = a == 0.0 ? 0.0 : a * x[t];
+    if (b != 0.0) v += b * y[t];
+    y[t] = v;
+  }
 }
 hipError_t launch_axpby(double a, const double *x, double b, double *y, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_axpby, grid_for(n), dim3(256), 0, st, a, x, b, y, n);

@@ -1,0 +1,172 @@
+"""Batched execution: several independent fracture instances in one context.
+
+Every kernel launch covers all instances and every reduction is segmented by
+instance with the same chunking an instance gets on its own, so a batched
+run must reproduce each instance's single-instance run bit for bit (same
+iterates, same iteration counts), match the FP64 oracle to 1e-8, and keep a
+failing instance from touching the others.  The batches mix mesh sizes,
+materials, injection rates and an instance without fluid (no pressure
+unknowns, zero load), as the ensemble workload does.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import newton
+from oracle.newton import Case
+
+pytestmark = pytest.mark.gpu
+
+hf = pytest.importorskip("paper_1911_10275_amd")
+
+
+def _kgd(n, seed, E, nu, mu, q0, steps=2):
+    mat = synth.Material(E=E, nu=nu, sigma_c=1e-3, G_c=1e-4, mu=mu, dt=1.0)
+    return synth.kgd_problem(n, 1, seed, mat, q0, half_length=0.15, ring=1, load_steps=steps,
+                             name=f"kgd_n{n}_s{seed}")
+
+
+def _dry(prob):
+    """The same mesh with its cracks cohesive but dry: no pressure unknowns."""
+    k = len(prob.crack_faces)
+    return dataclasses.replace(prob, crack_state=np.ones(k, np.uint8),
+                               crack_beta=np.zeros(k, np.uint8),
+                               src_vert=np.zeros(0, np.int64), src_q0=np.zeros(0),
+                               name=prob.name + "_dry")
+
+
+def batch_2d():
+    a = _kgd(9, 21, 1.0, 0.25, 1e-3, 1e-4)
+    b = _kgd(7, 22, 2.0, 0.30, 1e-2, 3e-4)
+    c = _kgd(12, 23, 0.7, 0.18, 3e-4, 5e-5)
+    return [a, b, _dry(_kgd(8, 24, 1.3, 0.2, 1e-3, 1e-4)), c]
+
+
+def batch_3d():
+    mat = synth.Material(1.0, 0.2, 1e-3, 1e-4, 1e-3, 1.0)
+    a = synth.penny_problem(3, 2, 21, mat, 1e-4, radius=0.34, ring_width=0.2, load_steps=2)
+    b = synth.penny_problem(4, 2, 31, dataclasses.replace(mat, E=1.5, mu=3e-3), 2e-4,
+                            radius=0.3, ring_width=0.2, load_steps=2)
+    return [a, b]
+
+
+def _start(ctx, probs):
+    for i, prob in enumerate(probs):
+        st0 = newton.initial_state(Case.from_problem(prob))
+        ctx.set_state(st0.u, st0.p, st0.w_old, inst=i)
+
+
+def _run(ctx, probs, precision, steps):
+    ctx.set_options(precision=precision)
+    _start(ctx, probs)
+    p0 = np.atleast_1d(ctx.initial_guess())
+    out = []
+    for _ in range(steps):
+        ns = ctx.newton_solve()
+        ns = ns if isinstance(ns, list) else [ns]
+        ctx.end_load_step()
+        out.append(([ctx.get_state(i) for i in range(len(probs))], ns))
+    return p0, out
+
+
+@pytest.mark.parametrize("batch", [batch_2d, batch_3d], ids=["2d_p1", "3d_p2"])
+@pytest.mark.parametrize("precision", [hf.HF_FP64, hf.HF_FP32_IR], ids=["fp64", "fp32ir"])
+def test_batched_equals_single_instance_bitwise(batch, precision):
+    probs = batch()
+    steps = 2
+    ctx = hf.context_for_problems(probs)
+    assert ctx.n_inst == len(probs)
+    p0_b, got = _run(ctx, probs, precision, steps)
+    ctx.close()
+    for i, prob in enumerate(probs):
+        solo = hf.context_for_problem(prob)
+        p0_s, ref = _run(solo, [prob], precision, steps)
+        solo.close()
+        assert p0_b[i] == p0_s[0]
+        for (sb, nsb), (ss, nss) in zip(got, ref):
+            for x, y in zip(sb[i], ss[0]):
+                np.testing.assert_array_equal(x, y)
+            assert nsb[i].converged == 1 and nss[0].converged == 1
+            assert nsb[i].iterations == nss[0].iterations
+            assert nsb[i].lin.gmres_iters == nss[0].lin.gmres_iters
+            assert nsb[i].lin.true_relres <= 1e-10
+
+
+def test_batched_oracle_parity():
+    """Each instance of a batched run (predictor + two load steps) matches the
+    FP64 oracle run of that instance alone to 1e-8."""
+    probs = batch_2d()
+    ctx = hf.context_for_problems(probs)
+    _, got = _run(ctx, probs, hf.HF_FP64, 2)
+    ctx.close()
+    for i, prob in enumerate(probs):
+        case = Case.from_problem(prob)
+        ref = newton.run(case, 2, predictor=True)
+        for (st, _), (states, ns) in zip(ref, got):
+            u, p, w, wo = states[i]
+            assert np.linalg.norm(u - st.u) <= 1e-8 * max(np.linalg.norm(st.u), 1e-300)
+            if case.itf.n_p:
+                assert np.linalg.norm(p - st.p) <= 1e-8 * np.linalg.norm(st.p)
+                fa = case.itf.active_faces
+                assert np.linalg.norm(wo[fa] - st.w_old[fa]) <= 1e-8 * np.linalg.norm(st.w_old[fa])
+
+
+def test_batched_failure_isolation():
+    """With a GMRES cap between the iteration counts of two instances, the one
+    that needs fewer iterations takes exactly its single-instance Newton
+    step, the other reports HF_ENOCONV and keeps its state."""
+    probs = [_kgd(6, 41, 1.0, 0.25, 1e-3, 1e-4), _kgd(16, 42, 1.0, 0.25, 1e-3, 1e-4)]
+    its, solo_state = [], []
+    for prob in probs:
+        solo = hf.context_for_problem(prob)
+        _start(solo, [prob])
+        solo.initial_guess()
+        ns = solo.newton_step()
+        its.append(ns.lin.gmres_iters)
+        solo_state.append(solo.get_state())
+        solo.close()
+    assert its[0] < its[1]
+    cap = (its[0] + its[1]) // 2
+    ctx = hf.context_for_problems(probs)
+    _start(ctx, probs)
+    ctx.initial_guess()
+    ctx.set_options(gmres_maxit=cap)
+    before = ctx.get_state(1)
+    ns = ctx.newton_step(check=False)
+    assert ns[0].status == hf.HF_OK and ns[0].lin.gmres_iters == its[0]
+    assert ns[1].status == hf.HF_ENOCONV
+    for x, y in zip(ctx.get_state(0), solo_state[0]):
+        np.testing.assert_array_equal(x, y)
+    for x, y in zip(ctx.get_state(1), before):
+        np.testing.assert_array_equal(x, y)
+    with pytest.raises(hf.HFError) as ei:
+        ctx.newton_step()
+    assert ei.value.status == hf.HF_ENOCONV
+    assert "instance 1" in str(ei.value)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [hf.HF_FP64, hf.HF_FP32_IR], ids=["fp64", "fp32ir"])
+def test_graph_replay_equals_eager(precision):
+    """GMRES chunks replayed from captured HIP graphs give bit-identical
+    results to eager launches, over repeated solves with host work between
+    the replays."""
+    prob = synth.penny_problem(3, 2, 21, synth.Material(1.0, 0.2, 1e-3, 1e-4, 1e-3, 1.0), 1e-4,
+                               radius=0.34, ring_width=0.2, load_steps=2)
+    res = {}
+    for graphs in (0, 1):
+        ctx = hf.context_for_problem(prob, use_graphs=graphs, precision=precision)
+        _start(ctx, [prob])
+        ctx.initial_guess()
+        seq = []
+        for _ in range(3):
+            ns = ctx.newton_step()
+            seq.append((ctx.increment(), ns.lin.gmres_iters))
+        res[graphs] = seq
+        ctx.close()
+    for (d0, i0), (d1, i1) in zip(res[0], res[1]):
+        assert i0 == i1
+        for x, y in zip(d0, d1):
+            np.testing.assert_array_equal(x, y)
