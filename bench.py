@@ -14,7 +14,10 @@ Printed JSON line: value = FP64 Newton steps/s.  Extra fields: GMRES
 throughput, the same steps in FP32-IR mode (speed-up and state error
 against FP64), the roofline of the dominant kernel (block-sparse Jacobian
 product, timed with HIP events on the library stream inside the timed
-region), and the CPU oracle timed on a bounded sample of the same workload.
+region: the GMRES iterations replay captured HIP graphs, so the events time
+the products outside them, one per restart cycle, same kernel and data), the
+batched ensemble workload (64 2D instances, see ``ensemble_block``), and the
+CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -29,6 +32,26 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Newton steps/s & GMRES iters/s (MDOF), FP32-IR vs FP64 at rel.res 1e-10"
 HBM_PEAK_GBS = 8000.0
+
+
+def spmv_traffic(workload):
+    """HBM bytes per FP64 Jacobian product from the committed hardware-counter
+    summary of this workload, or None when there is none or the product's
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "spmv_fp64_penny3d_p2_48k.md")
+    src = os.path.join(ROOT, "paper_1911_10275_amd", "csrc", "hf_kernels_spmv.hip")
+    if workload != 2 or not os.path.exists(path):
+        return None
+    text = open(path).read()
+    t = re.search(r"^traffic_bytes_per_launch = (\d+)$", text, re.M)
+    h = re.search(r"^source_sha256 = ([0-9a-f]{64})$", text, re.M)
+    if not t or not h:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+        return None
+    return int(t.group(1))
 
 
 def run_steps(ctx, st0, K, W, profile):
@@ -109,6 +132,102 @@ def cpu_baseline(prob, gpu_iters_per_step):
                        f"iterations per Newton step")}
 
 
+def counters_probe(prob):
+    """Launches for hardware-counter runs: one copy of 1 GiB between two
+    device buffers (a kernel of known traffic: 1 GiB read, 1 GiB written),
+    then five FP64 block-sparse Jacobian products of the workload."""
+    import numpy as np
+    import torch
+    import paper_1911_10275_amd as hf
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = hf.context_for_problem(prob, device=0, stream=stream)
+    sz = ctx.sizes
+    ctx.set_state(np.zeros(sz.n_u), np.full(sz.n_p, prob.material.sigma_c))
+    ctx.assemble()
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    x = torch.randn(sz.n_total, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        ctx.apply_jacobian(x.data_ptr(), y.data_ptr())
+    torch.cuda.synchronize()
+    ctx.close()
+    print(f"counters probe done: copy 1 GiB, 5 products, N = {sz.n_total}", file=sys.stderr)
+
+
+def ensemble_block(K, gmres_m):
+    """The batched 2D KGD ensemble: 64 instances (1k-20k triangles, mixed P1 /
+    P2, materials and injection drawn per instance).  The P1 and the P2
+    instances each form one batched context (every kernel launch covers all
+    instances of the context); the two contexts run concurrently on two
+    streams from two host threads.  One ensemble step = one Newton iteration
+    (assemble, block-Jacobi, GMRES to 1e-10, update) of every instance, from
+    the uniform-pressure predictor; K timed steps after one warm-up step and
+    a reset, in FP64 and in FP32-IR."""
+    import threading
+    import numpy as np
+    import torch
+    import paper_1911_10275_amd as hf
+    import synth
+    probs = synth.ensemble(64, seed=4)
+    groups = [[p for p in probs if p.order == o] for o in (1, 2)]
+    ctxs, starts, streams = [], [], []
+    for ps in groups:
+        stm = torch.cuda.Stream()
+        c = hf.context_for_problems(ps, device=0, stream=stm.cuda_stream, gmres_m=gmres_m)
+        for i, p in enumerate(ps):
+            s = c.isizes[i]
+            c.set_state(np.zeros(s.n_u), np.full(s.n_p, p.material.sigma_c),
+                        np.zeros((s.n_face, s.nq_face)), inst=i)
+        c.initial_guess()
+        starts.append([c.get_state(i) for i in range(len(ps))])
+        ctxs.append(c)
+        streams.append(stm)
+
+    def reset(c, st):
+        for i, (u, p, _, wo) in enumerate(st):
+            c.set_state(u, p, wo, inst=i)
+
+    def steps(c, n, sink):
+        for _ in range(n):
+            sink.append(c.newton_step(check=False))
+
+    res = {}
+    for name, prec in (("fp64", hf.HF_FP64), ("fp32_ir", hf.HF_FP32_IR)):
+        for c, st in zip(ctxs, starts):
+            c.set_options(precision=prec)
+            reset(c, st)
+            c.newton_step(check=False)
+            reset(c, st)
+        torch.cuda.synchronize()
+        sinks = [[] for _ in ctxs]
+        threads = [threading.Thread(target=steps, args=(c, K, sk)) for c, sk in zip(ctxs, sinks)]
+        t0 = time.perf_counter()
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        flat = [n for sk in sinks for step in sk for n in step]
+        ok = [n for n in flat if n.lin.status == 0]
+        dof = sum(c.sizes.n_total for c in ctxs)
+        gits = sum(n.lin.gmres_iters for n in flat)
+        res[name] = {"steps_per_s": K / dt, "instance_newton_steps_per_s": len(flat) / dt,
+                     "ms_per_step": 1e3 * dt / K, "gmres_iters_per_s": gits / dt,
+                     "failed_solves": len(flat) - len(ok),
+                     "max_true_relres_converged": max(n.lin.true_relres for n in ok)}
+        print(f"bench: ensemble {name} {K} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    for c in ctxs:
+        c.close()
+    res["speedup_fp32_ir_vs_fp64"] = res["fp32_ir"]["steps_per_s"] / res["fp64"]["steps_per_s"]
+    res["config"] = {"instances": len(probs), "p1": len(groups[0]), "p2": len(groups[1]),
+                     "triangles": int(sum(p.n_elem for p in probs)), "dof": int(dof),
+                     "contexts": 2, "streams": 2}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +237,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ir", action="store_true", help="skip the FP32-IR comparison")
     ap.add_argument("--gmres-m", type=int, default=60, help="GMRES restart length")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble")
+    ap.add_argument("--ensemble-steps", type=int, default=3)
+    ap.add_argument("--ensemble-m", type=int, default=120, help="GMRES restart length, ensemble")
+    ap.add_argument("--counters", action="store_true",
+                    help="hardware-counter probe: 5 FP64 Jacobian products of the workload and "
+                         "one 1 GiB device copy (calibration), nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
@@ -129,6 +254,9 @@ def main():
     import synth
 
     prob = synth.config(args.workload)
+    if args.counters:
+        counters_probe(prob)
+        return
     print(f"bench: workload {prob.name}: {prob.n_elem} elements, {prob.n_udof} displacement DOF",
           file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream().cuda_stream
@@ -177,11 +305,11 @@ def main():
                   "mdof_iters_per_s": float(sum(iters64) * N / dt64 / 1e6)},
         "roofline": {"bound": "hbm", "kernel": "k_bsr_spmv<double,30>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": int(spmv_bytes),
+                     "traffic": spmv_traffic(args.workload), "bytes_per_launch": int(spmv_bytes),
                      "avg_launch_ms": spmv_ms, "launches": int(prof.n_spmv64)},
-        "kernel_ms": {"assemble": prof.ms_assemble, "spmv64": prof.ms_spmv64,
-                      "precond": prof.ms_precond, "ortho": prof.ms_ortho,
-                      "blockinv": prof.ms_blockinv},
+        # HIP-event times of the launches outside the graph-replayed GMRES chunks
+        "kernel_ms_outside_graphs": {"assemble": prof.ms_assemble, "spmv64": prof.ms_spmv64,
+                                     "precond": prof.ms_precond, "blockinv": prof.ms_blockinv},
     }
     if not args.no_ir:
         ctx.set_options(precision=hf.HF_FP32_IR)
@@ -201,6 +329,8 @@ def main():
         print(f"bench: fp32-ir {K} steps in {dt32:.3f} s, GMRES iterations {iters32}",
               file=sys.stderr, flush=True)
     ctx.close()
+    if not args.no_ensemble:
+        out["ensemble"] = ensemble_block(args.ensemble_steps, args.ensemble_m)
     if not args.no_cpu:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob, float(np.mean(iters64)))

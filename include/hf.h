@@ -91,9 +91,11 @@ typedef struct {
   double p_cutoff;     /* pressure cut-off value when cutoff_on != 0 */
   int cutoff_on;       /* clamp p >= p_cutoff after each update (default 0) */
   int device;          /* HIP device ordinal (default 0) */
-  int profile;         /* 1: time kernel classes with HIP events (default 0) */
+  int profile;         /* 1: time kernel classes with HIP events (default 0);
+                          with use_graphs = 1 only the launches outside the
+                          captured GMRES chunks are timed */
   int use_graphs;      /* 1: replay chunks of GMRES iterations from captured HIP
-                          graphs (default 1; ignored while profile = 1) */
+                          graphs (default 1) */
   void *stream;        /* hipStream_t to run on; NULL: a stream the ctx creates */
 } hf_options;
 

@@ -115,6 +115,7 @@ struct hf_ctx {
   char *hu = nullptr;
   size_t hd_n = 0, hi_n = 0, hu_n = 0;
   bool hu_pending = false;  // an upload from hu may still be in flight
+  bool capturing = false;   // a GMRES chunk is being captured into a graph
   std::vector<std::string> ierr;  // message of each instance's failure in the current call
   // profile
   std::vector<hipEvent_t> evpool;
@@ -302,13 +303,15 @@ int take_event(hf_ctx *ctx) {
 struct ProfScope {
   hf_ctx *ctx;
   int cls, e0 = -1;
+  // no events inside a graph capture: only launches outside captured
+  // chunks are timed when graphs are on
   ProfScope(hf_ctx *c, int k) : ctx(c), cls(k) {
-    if (!ctx->opt.profile) return;
+    if (!ctx->opt.profile || ctx->capturing) return;
     e0 = take_event(ctx);
     if (e0 >= 0) (void)hipEventRecord(ctx->evpool[e0], ctx->stream);
   }
   ~ProfScope() {
-    if (!ctx->opt.profile || e0 < 0) return;
+    if (e0 < 0) return;
     int e1 = take_event(ctx);
     if (e1 < 0) return;
     (void)hipEventRecord(ctx->evpool[e1], ctx->stream);
@@ -1304,17 +1307,28 @@ static hf_status ensure_ws(hf_ctx *ctx, KrylovWs<T> &ws) {
   return HF_OK;
 }
 
+// rows of the instances being solved (mode 1) or still iterating (mode 2)
+static RowSel rows(const hf_ctx *ctx, int mode) {
+  RowSel r;
+  r.solving = ctx->kd.solving;
+  r.kconv = ctx->kd.kconv;
+  r.mode = mode;
+  return r;
+}
+
 template <typename T>
-static hf_status apply_J(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *x, T *y) {
+static hf_status apply_J(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *x, T *y,
+                         const RowSel &sel) {
   ProfScope ps(ctx, sizeof(T) == 8 ? P_SPMV64 : P_SPMV32);
-  HIPCHK(launch_spmv<T>(kp, op.A, op.Bs, op.Cs, op.D, x, y, ctx->stream));
+  HIPCHK(launch_spmv<T>(kp, op.A, op.Bs, op.Cs, op.D, x, y, sel, ctx->stream));
   return HF_OK;
 }
 
 template <typename T>
-static hf_status apply_M(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *r, T *z) {
+static hf_status apply_M(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *r, T *z,
+                         const RowSel &sel) {
   ProfScope ps(ctx, P_PREC);
-  HIPCHK(launch_precond<T>(kp, op.inv, op.Sinv, r, z, ctx->stream));
+  HIPCHK(launch_precond<T>(kp, op.inv, op.Sinv, r, z, sel, ctx->stream));
   return HF_OK;
 }
 
@@ -1329,8 +1343,8 @@ static hf_status arnoldi_step(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, 
   const int64_t N = ctx->s.N();
   const KrylovDev &kd = ctx->kd;
   const int m = ws.m, k = j + 1, ks = j + 2;
-  TRY(apply_M<T>(ctx, kp, op, ws.V + (int64_t)j * N, ws.z));
-  TRY(apply_J<T>(ctx, kp, op, ws.z, ws.w));
+  TRY(apply_M<T>(ctx, kp, op, ws.V + (int64_t)j * N, ws.z, rows(ctx, 2)));
+  TRY(apply_J<T>(ctx, kp, op, ws.z, ws.w, rows(ctx, 2)));
   ProfScope ps(ctx, P_ORTHO);
   HIPCHK(ks_proj<T>(kd, ws.V, N, k, ws.w, nullptr, ctx->partial, ctx->k_s1, ctx->stream));
   HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s1, ks, ws.w, nullptr, ctx->partial, ctx->k_n1, ctx->stream));
@@ -1348,8 +1362,7 @@ static hf_status arnoldi_step(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, 
 template <typename T>
 static hf_status arnoldi_chunk(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, KrylovWs<T> &ws,
                                int j0, int j1, double rtol) {
-  const bool graphs = ctx->opt.use_graphs && !ctx->opt.profile;
-  if (!graphs) {
+  if (!ctx->opt.use_graphs) {
     for (int j = j0; j < j1; ++j) TRY(arnoldi_step<T>(ctx, kp, op, ws, j, rtol));
     return HF_OK;
   }
@@ -1357,8 +1370,10 @@ static hf_status arnoldi_chunk(hf_ctx *ctx, const KParams &kp, const Ops<T> &op,
   if (ws.graphs.size() <= gi) ws.graphs.resize(gi + 1, nullptr);
   if (!ws.graphs[gi]) {
     HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    ctx->capturing = true;
     hf_status st = HF_OK;
     for (int j = j0; j < j1 && st == HF_OK; ++j) st = arnoldi_step<T>(ctx, kp, op, ws, j, rtol);
+    ctx->capturing = false;
     hipGraph_t g = nullptr;
     hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
     if (st != HF_OK) {
@@ -1451,10 +1466,10 @@ static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T
     // x += M^-1 V y with y = H^-1 g per instance
     HIPCHK(ks_solve_y(kd, m, ctx->k_y, ctx->k_est, st));
     HIPCHK(ks_combine<T>(kd, ws.V, N, ctx->k_y, m, ws.t, st));
-    TRY(apply_M<T>(ctx, kp, op, ws.t, ws.z));
+    TRY(apply_M<T>(ctx, kp, op, ws.t, ws.z, rows(ctx, 1)));
     HIPCHK((ks_axpy<T, T>(kd, nullptr, ws.z, x, st)));
     // true residual: restart vector and explicit check
-    TRY(apply_J<T>(ctx, kp, op, x, ws.w));
+    TRY(apply_J<T>(ctx, kp, op, x, ws.w, rows(ctx, 1)));
     HIPCHK(ks_sub<T>(kd, bvec, ws.w, ws.r, st));
     HIPCHK(ks_norms<T>(kd, ws.r, ctx->partial, ctx->k_beta2, st));
     TRY(get_i_async(ctx, kd.its, B, 0));
@@ -1631,7 +1646,7 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
       TRY(put(ctx, kd.solving, on));
       TRY(put(ctx, ctx->k_coef, coef));
       HIPCHK((ks_axpy<double, float>(kd, ctx->k_coef, ctx->k32.x, ctx->dx, stm)));
-      TRY(apply_J<double>(ctx, kp, op64, ctx->dx, ctx->t64));
+      TRY(apply_J<double>(ctx, kp, op64, ctx->dx, ctx->t64, rows(ctx, 1)));
       HIPCHK(ks_sub<double>(kd, ctx->rhs, ctx->t64, ctx->r64, stm));
     }
   }
@@ -1977,11 +1992,11 @@ extern "C" hf_status hf_apply_jacobian(hf_ctx *ctx, int precision, const void *x
   const KParams kp = kparams(ctx);
   if (precision == HF_FP64) {
     Ops<double> op{ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->inv, ctx->Sinv};
-    TRY(apply_J<double>(ctx, kp, op, (const double *)x, (double *)y));
+    TRY(apply_J<double>(ctx, kp, op, (const double *)x, (double *)y, RowSel{}));
   } else if (precision == HF_FP32_IR) {
     if (!ctx->have32) return fail(ctx, HF_ESTATE, "no FP32 matrix: run hf_solve in FP32-IR mode first");
     Ops<float> op{ctx->A32, ctx->Bs32, ctx->Cs32, ctx->D32, ctx->inv32, ctx->Sinv32};
-    TRY(apply_J<float>(ctx, kp, op, (const float *)x, (float *)y));
+    TRY(apply_J<float>(ctx, kp, op, (const float *)x, (float *)y, RowSel{}));
   } else {
     return fail(ctx, HF_EINVAL, "precision");
   }

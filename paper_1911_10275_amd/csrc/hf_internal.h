@@ -131,6 +131,13 @@ struct KrylovDev {
   double *bnorm = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
 };
 
+// rows a batched product works on: all (mode 0), the instances being solved
+// (mode 1), or those still iterating in their GMRES cycle (mode 2)
+struct RowSel {
+  const int *solving = nullptr, *kconv = nullptr;
+  int mode = 0;
+};
+
 }  // namespace hf
 
 namespace hf {
@@ -152,53 +159,22 @@ hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,
                         const double *Cs, const double *D, double *Z, double *T, double *S,
                         double *Sinv, float *Sinv32, int *flag, hipStream_t st);
 hipError_t launch_convert(const double *in, float *out, int64_t n, hipStream_t st);
+// y = J x (rows outside sel are left untouched)
 template <typename T>
 hipError_t launch_spmv(const KParams &kp, const T *A, const T *Bs, const T *Cs, const T *D,
-                       const T *x, T *y, hipStream_t st);
+                       const T *x, T *y, const RowSel &sel, hipStream_t st);
+// z = M^-1 r, block-Jacobi (rows outside sel are left untouched)
 template <typename T>
 hipError_t launch_precond(const KParams &kp, const T *inv, const T *Sinv, const T *r, T *z,
-                          hipStream_t st);
-// Krylov BLAS (deterministic two-stage reductions)
-int reduce_blocks(int64_t n);
-int ortho_blocks(int64_t n);  // blocks of the Gram-Schmidt passes (partials per output)
-template <typename T>
-hipError_t launch_mdot(const T *V, int64_t ldv, int k, const T *w, int64_t n, double *partial,
-                       double *out, hipStream_t st);
-template <typename T>
-hipError_t launch_update_mdot(const T *V, int64_t ldv, int k, const double *h, T *w, int64_t n,
-                              double *partial, double *out, hipStream_t st);
-template <typename T>
-hipError_t launch_update_norm(const T *V, int64_t ldv, int k, const double *h, T *w, int64_t n,
-                              double *partial, double *out, hipStream_t st);
-// Gram-Schmidt passes: out[0..k) = V^T w, out[k] = ||w||^2; and w -= V h, out[0] = ||w||^2
-template <typename T>
-hipError_t launch_proj(const T *V, int64_t ldv, int k, const T *w, int64_t n, double *partial,
-                       double *out, hipStream_t st);
-template <typename T>
-hipError_t launch_orth_update(const T *V, int64_t ldv, int k, const double *h, T *w, int64_t n,
-                              double *partial, double *out, hipStream_t st);
-template <typename T>
-hipError_t launch_scale_copy(const T *w, double inv_norm, T *v, int64_t n, hipStream_t st);
-template <typename T>
-hipError_t launch_combine(const T *V, int64_t ldv, int k, const double *y, T *out, int64_t n,
-                          hipStream_t st);
+                          const RowSel &sel, hipStream_t st);
 hipError_t launch_axpby(double a, const double *x, double b, double *y, int64_t n,
                         hipStream_t st);
-hipError_t launch_cast_axpy(double a, const float *x, double *y, int64_t n, hipStream_t st);
-hipError_t launch_cast_scale(const double *x, double a, float *y, int64_t n, hipStream_t st);
-hipError_t launch_sub(const double *b, const double *Jx, double *r, int64_t n, hipStream_t st);
-template <typename T>
-hipError_t launch_sub_t(const T *b, const T *Jx, T *r, int64_t n, hipStream_t st);
-template <typename T>
-hipError_t launch_axpy_t(double a, const T *x, T *y, int64_t n, hipStream_t st);
-hipError_t launch_newton_update(const double *dx, double *u, int64_t n_u, double *p,
-                                int64_t n_p, int cutoff_on, double cutoff, double *partial,
-                                double *out, hipStream_t st);
-hipError_t launch_norm2(const double *x, int64_t n, double *partial, double *out,
-                        hipStream_t st);
 hipError_t launch_set_rules(const RuleTables &rt, hipStream_t st);
+// out[b] = ||x_b||^2 of every instance
 hipError_t launch_seg_norms(const KrylovDev &kd, const double *x, double *partial, double *out,
                             hipStream_t st);
+// x += dx on instances with upd[b] != 0 (p clamped to the cut-off when on);
+// out[4b + 0..3] = ||du||^2, ||u||^2, ||dp||^2, ||p||^2 of instance b
 hipError_t launch_snewton_update(const KrylovDev &kd, const double *dx, double *x, int64_t n_u,
                                  const int *upd, int cutoff_on, double cutoff, double *partial,
                                  double *out, hipStream_t st);

@@ -160,17 +160,18 @@ __global__ __launch_bounds__(KT) void k_seg_reduce(KrylovDev kd, const double *_
   if (threadIdx.x == 0) out[(int64_t)b * nout + i] = sm[0];
 }
 
-// v[r] = w[r] * scale[inst]   (scale = 0 for instances that are not iterating)
+// v[r] = w[r] * scale[inst] for instances with a non-zero scale (the others,
+// not iterating, keep whatever their rows hold: no kernel reads them)
 template <typename T>
 __global__ __launch_bounds__(KT) void k_sscale(KrylovDev kd, const T *__restrict__ w,
                                                const double *__restrict__ scale, T *__restrict__ v) {
   const int c = blockIdx.x, tid = threadIdx.x;
   const int b = kd.c_inst[c];
   const double s = kd.solving[b] ? scale[b] : 0.0;
+  if (s == 0.0) return;  // idle instance: its basis rows are never read
   const int64_t row0 = kd.c_row0[c];
   const int len = kd.c_len[c];
-  // exact zeros (not w * 0) for idle instances, whatever w holds
-  for (int rr = tid; rr < len; rr += KT) v[row0 + rr] = s == 0.0 ? T(0) : (T)((double)w[row0 + rr] * s);
+  for (int rr = tid; rr < len; rr += KT) v[row0 + rr] = (T)((double)w[row0 + rr] * s);
 }
 
 // out[r] = sum_{i < nb} y_b[i] V_i[r], nb = basis size of the instance's cycle

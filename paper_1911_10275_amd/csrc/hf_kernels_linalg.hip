@@ -1,214 +1,11 @@
-// Linear-algebra kernels for gfx950: block-sparse Jacobian product,
-// pressure rows, batched block inverses, the Schur pressure block, and the
-// Krylov vector kernels with deterministic two-stage reductions.
-//
-// Jacobian storage.  Element row e of A is one contiguous "row panel": its
-// blocks (diagonal first, then one per interior face in local-face order)
-// each stored column-major, so the panel is a column-major bs x (nb*bs)
-// matrix.  The product streams each panel with 16-byte loads: a group of L
-// lanes reads CH = LA*EL consecutive values per step, and because CH is a
-// multiple of bs every lane keeps the same rows at every step; the products
-// are summed per lane and combined across lanes in a fixed order at the end.
+// Linear-algebra kernels for gfx950: batched inverses of the element
+// blocks, the Schur pressure block and its inverse, precision conversion and
+// vector fills.
 #include <cmath>
 
 #include "hf_internal.h"
 
 namespace hf {
-
-// ---------------------------------------------------------------------------
-// Block-sparse product y = A x (+ B x_p on rows with coupling strips)
-// ---------------------------------------------------------------------------
-__host__ __device__ constexpr int active_lanes(int L, int EL, int BU) {
-  int la = L;
-  while (la > 0 && (la * EL) % BU != 0) --la;
-  return la;
-}
-
-template <typename T>
-struct Vec16;
-template <>
-struct Vec16<double> {
-  using type = double2;
-  static constexpr int EL = 2;
-};
-template <>
-struct Vec16<float> {
-  using type = float4;
-  static constexpr int EL = 4;
-};
-
-template <typename T, int BU>
-struct SpmvShape {
-  static constexpr int EL = Vec16<T>::EL;
-  static constexpr int L = BU >= 24 ? 64 : (BU >= 12 ? 32 : 16);
-  static constexpr int LA = active_lanes(L, EL, BU);
-  static constexpr int CH = LA * EL;
-  static constexpr int RPC = CH / BU;  // columns advanced per step
-  static_assert(CH % BU == 0, "chunk must hold whole columns");
-};
-
-template <typename T>
-__device__ inline T vget(const typename Vec16<T>::type &v, int s);
-template <>
-__device__ inline double vget<double>(const double2 &v, int s) { return s == 0 ? v.x : v.y; }
-template <>
-__device__ inline float vget<float>(const float4 &v, int s) {
-  return s == 0 ? v.x : (s == 1 ? v.y : (s == 2 ? v.z : v.w));
-}
-
-template <typename T, int BU, int NT, bool STRIPS>
-__global__ __launch_bounds__(NT) void k_bsr_spmv(
-    int64_t ne, const int64_t *__restrict__ blk_ptr, const int32_t *__restrict__ blk_col,
-    const T *__restrict__ A, const int64_t *__restrict__ sp_ptr,
-    const int32_t *__restrict__ sp_pnode, const T *__restrict__ Bs, const T *__restrict__ x,
-    const T *__restrict__ xp, T *__restrict__ y) {
-  using S = SpmvShape<T, BU>;
-  constexpr int L = S::L, EL = S::EL, LA = S::LA, CH = S::CH, RPC = S::RPC, G = NT / L;
-  using V = typename Vec16<T>::type;
-  __shared__ T xs[G][5 * BU];
-  __shared__ T part[G][CH];
-  const int g = threadIdx.x / L, lane = threadIdx.x % L;
-  const int64_t e = (int64_t)blockIdx.x * G + g;
-  int64_t b0 = 0;
-  int nb = 0;
-  if (e < ne) {
-    b0 = blk_ptr[e];
-    nb = (int)(blk_ptr[e + 1] - b0);
-    for (int t = lane; t < nb * BU; t += L) xs[g][t] = x[(int64_t)blk_col[b0 + t / BU] * BU + t % BU];
-  }
-  __syncthreads();
-  T acc[EL];
-#pragma unroll
-  for (int s = 0; s < EL; ++s) acc[s] = T(0);
-  if (e < ne && lane < LA) {
-    const T *panel = A + b0 * BU * BU;
-    const int total = nb * BU * BU;
-    int colS[EL];
-#pragma unroll
-    for (int s = 0; s < EL; ++s) colS[s] = (lane * EL + s) / BU;
-    int f = lane * EL, cb = 0;
-#pragma unroll 4
-    for (; f < total; f += CH, cb += RPC) {
-      const V v = *(const V *)(panel + f);
-#pragma unroll
-      for (int s = 0; s < EL; ++s) acc[s] += vget<T>(v, s) * xs[g][cb + colS[s]];
-    }
-  }
-  if (lane < LA) {
-#pragma unroll
-    for (int s = 0; s < EL; ++s) part[g][lane * EL + s] = acc[s];
-  }
-  __syncthreads();
-  if (e < ne && lane < BU) {
-    T sum = T(0);
-#pragma unroll
-    for (int t = 0; t < RPC; ++t) sum += part[g][lane + BU * t];
-    if (STRIPS) {
-      for (int64_t k = sp_ptr[e]; k < sp_ptr[e + 1]; ++k) sum += Bs[k * BU + lane] * xp[sp_pnode[k]];
-    }
-    y[e * BU + lane] = sum;
-  }
-}
-
-// pressure rows: y_p[i] = sum_strips C x_u + sum_j D_b[i][j] x_p[j] over the dense block
-// of the row's instance b (one wave per row)
-template <typename T, int BU>
-__global__ __launch_bounds__(64) void k_prows(int64_t np, const int32_t *__restrict__ pinst,
-                                              const int32_t *__restrict__ poff,
-                                              const int64_t *__restrict__ doff,
-                                              const int32_t *__restrict__ pc_ptr,
-                                              const int32_t *__restrict__ pc_ent,
-                                              const int32_t *__restrict__ sp_elem,
-                                              const T *__restrict__ Cs, const T *__restrict__ D,
-                                              const T *__restrict__ xu, const T *__restrict__ xp,
-                                              T *__restrict__ yp) {
-  const int64_t i = blockIdx.x;
-  const int lane = threadIdx.x;
-  double acc = 0.0;
-  if (pc_ptr) {
-    for (int32_t c = pc_ptr[i]; c < pc_ptr[i + 1]; ++c) {
-      const int32_t ent = pc_ent[c];
-      const int64_t e = sp_elem[ent];
-      if (lane < BU) acc += (double)Cs[(int64_t)ent * BU + lane] * (double)xu[e * BU + lane];
-    }
-  }
-  const int b = pinst[i];
-  const int64_t p0 = poff[b], nb = poff[b + 1] - p0;
-  const T *Drow = D + doff[b] + (i - p0) * nb;
-  for (int64_t j = lane; j < nb; j += 64) acc += (double)Drow[j] * (double)xp[p0 + j];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) yp[i] = (T)acc;
-}
-
-template <typename T, int BU>
-static void spmv_bu(const KParams &kp, const T *A, const T *Bs, const T *Cs, const T *D,
-                    const T *x, T *y, hipStream_t st) {
-  using S = SpmvShape<T, BU>;
-  constexpr int NT = 256, G = NT / S::L;
-  const int64_t ne = kp.s.ne;
-  if (ne)
-    hipLaunchKernelGGL((k_bsr_spmv<T, BU, NT, true>), dim3((unsigned)((ne + G - 1) / G)), dim3(NT), 0, st,
-                       ne, kp.m.blk_ptr, kp.m.blk_col, A, kp.m.sp_ptr, kp.m.sp_pnode, Bs, x,
-                       x + kp.s.n_u, y);
-  if (kp.s.n_p)
-    hipLaunchKernelGGL((k_prows<T, BU>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp.s.n_p,
-                       kp.pinst, kp.poff, kp.doff, kp.m.pc_ptr, kp.m.pc_ent, kp.m.sp_elem, Cs, D, x,
-                       x + kp.s.n_u, y + kp.s.n_u);
-}
-
-template <typename T>
-hipError_t launch_spmv(const KParams &kp, const T *A, const T *Bs, const T *Cs, const T *D,
-                       const T *x, T *y, hipStream_t st) {
-  switch (kp.s.bu) {
-    case 6: spmv_bu<T, 6>(kp, A, Bs, Cs, D, x, y, st); break;
-    case 12: spmv_bu<T, 12>(kp, A, Bs, Cs, D, x, y, st); break;
-    case 30: spmv_bu<T, 30>(kp, A, Bs, Cs, D, x, y, st); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-template hipError_t launch_spmv<double>(const KParams &, const double *, const double *,
-                                        const double *, const double *, const double *,
-                                        double *, hipStream_t);
-template hipError_t launch_spmv<float>(const KParams &, const float *, const float *,
-                                       const float *, const float *, const float *, float *,
-                                       hipStream_t);
-
-// block-Jacobi apply: z_u = blockdiag(inv) r_u (the same streaming kernel on
-// the identity block pattern), z_p = S^-1 r_p
-template <typename T, int BU>
-static void precond_bu(const KParams &kp, const T *inv, const T *Sinv, const T *r, T *z,
-                       hipStream_t st, const int64_t *ident_ptr, const int32_t *ident_col) {
-  using S = SpmvShape<T, BU>;
-  constexpr int NT = 256, G = NT / S::L;
-  const int64_t ne = kp.s.ne;
-  if (ne)
-    hipLaunchKernelGGL((k_bsr_spmv<T, BU, NT, false>), dim3((unsigned)((ne + G - 1) / G)), dim3(NT), 0, st,
-                       ne, ident_ptr, ident_col, inv, nullptr, nullptr, nullptr, r, nullptr, z);
-  if (kp.s.n_p)
-    hipLaunchKernelGGL((k_prows<T, BU>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp.s.n_p,
-                       kp.pinst, kp.poff, kp.doff, nullptr, nullptr, nullptr, nullptr, Sinv, r,
-                       r + kp.s.n_u, z + kp.s.n_u);
-}
-
-template <typename T>
-hipError_t launch_precond(const KParams &kp, const T *inv, const T *Sinv, const T *r, T *z,
-                          hipStream_t st) {
-  const int64_t *ip = kp.m.ident_ptr;
-  const int32_t *ic = kp.m.ident_col;
-  switch (kp.s.bu) {
-    case 6: precond_bu<T, 6>(kp, inv, Sinv, r, z, st, ip, ic); break;
-    case 12: precond_bu<T, 12>(kp, inv, Sinv, r, z, st, ip, ic); break;
-    case 30: precond_bu<T, 30>(kp, inv, Sinv, r, z, st, ip, ic); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-template hipError_t launch_precond<double>(const KParams &, const double *, const double *,
-                                           const double *, double *, hipStream_t);
-template hipError_t launch_precond<float>(const KParams &, const float *, const float *,
-                                          const float *, float *, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Batched inverse of the diagonal element blocks: Gauss-Jordan with partial
@@ -464,71 +261,8 @@ hipError_t launch_convert(const double *in, float *out, int64_t n, hipStream_t s
 }
 
 // ---------------------------------------------------------------------------
-// Krylov vector kernels.  Reductions: each block writes one partial per
-// output in a fixed order; k_reduce sums the partials of each output in a
-// fixed tree.  Results are therefore bitwise reproducible for a given size.
+// Vector fills and updates (the batched Krylov kernels are in hf_kernels_krylov.hip)
 // ---------------------------------------------------------------------------
-constexpr int kRedThreads = 256;
-constexpr int kMaxBlocks = 1024;
-
-int reduce_blocks(int64_t n) {
-  int64_t b = (n + 2047) / 2048;
-  if (b < 1) b = 1;
-  if (b > kMaxBlocks) b = kMaxBlocks;
-  return (int)b;
-}
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
-
-// block partial of k dot products (or norms) -> partial[blockIdx*k + i]
-template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_mdot(const T *__restrict__ V, int64_t ldv, int k,
-                                                      const T *__restrict__ w, int64_t n,
-                                                      double *__restrict__ partial) {
-  __shared__ double wsum[kMaxKrylov][kRedThreads / 64];
-  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
-  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
-  for (int i = 0; i < k; ++i) {
-    double acc = 0.0;
-    const T *vi = V + i * ldv;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += kRedThreads) acc += (double)vi[r] * (double)w[r];
-    acc = wave_sum(acc);
-    if (lane == 0) wsum[i][wv] = acc;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < k; i += kRedThreads) {
-    double s = 0.0;
-    for (int q = 0; q < kRedThreads / 64; ++q) s += wsum[i][q];
-    partial[(int64_t)blockIdx.x * k + i] = s;
-  }
-}
-
-__global__ __launch_bounds__(kRedThreads) void k_reduce(const double *__restrict__ partial, int nblk,
-                                                        int k, double *__restrict__ out) {
-  __shared__ double sm[kRedThreads];
-  const int i = blockIdx.x;
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kRedThreads) acc += partial[(int64_t)b * k + i];
-  sm[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[i] = sm[0];
-}
-
-hipError_t launch_reduce_partials(const double *partial, int nblk, int k, double *out,
-                                  hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(k), dim3(kRedThreads), 0, st, partial, nblk, k, out);
-  return hipGetLastError();
-}
-
 __global__ void k_fill(double v, double *__restrict__ x, int64_t n) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
        t += (int64_t)gridDim.x * blockDim.x)
@@ -542,224 +276,6 @@ hipError_t launch_fill(double v, double *x, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_mdot(const T *V, int64_t ldv, int k, const T *w, int64_t n, double *partial,
-                       double *out, hipStream_t st) {
-  const int nb = reduce_blocks(n);
-  hipLaunchKernelGGL(k_mdot<T>, dim3(nb), dim3(kRedThreads), 0, st, V, ldv, k, w, n, partial);
-  hipLaunchKernelGGL(k_reduce, dim3(k), dim3(kRedThreads), 0, st, partial, nb, k, out);
-  return hipGetLastError();
-}
-template hipError_t launch_mdot<double>(const double *, int64_t, int, const double *, int64_t,
-                                        double *, double *, hipStream_t);
-template hipError_t launch_mdot<float>(const float *, int64_t, int, const float *, int64_t,
-                                       double *, double *, hipStream_t);
-
-// w -= sum_i h_i V_i ; then partial dots V_i . w (MODE 1) or ||w||^2 (MODE 2)
-template <typename T, int MODE>
-__global__ __launch_bounds__(kRedThreads) void k_update(const T *__restrict__ V, int64_t ldv, int k,
-                                                        const double *__restrict__ h,
-                                                        T *__restrict__ w, int64_t n,
-                                                        double *__restrict__ partial) {
-  __shared__ double sh[kMaxKrylov];
-  __shared__ double wsum[kMaxKrylov][kRedThreads / 64];
-  for (int i = threadIdx.x; i < k; i += kRedThreads) sh[i] = h[i];
-  __syncthreads();
-  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
-  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
-  double nacc = 0.0;
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += kRedThreads) {
-    double acc = (double)w[r];
-    for (int i = 0; i < k; ++i) acc -= sh[i] * (double)V[i * ldv + r];
-    const T wr = (T)acc;
-    w[r] = wr;
-    nacc += (double)wr * (double)wr;
-  }
-  if (MODE == 2) {
-    nacc = wave_sum(nacc);
-    if (lane == 0) wsum[0][wv] = nacc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int q = 0; q < kRedThreads / 64; ++q) s += wsum[0][q];
-      partial[blockIdx.x] = s;
-    }
-    return;
-  }
-  // MODE 1: partial dots with the updated w (re-read of this block's rows)
-  __syncthreads();
-  for (int i = 0; i < k; ++i) {
-    double acc = 0.0;
-    const T *vi = V + i * ldv;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += kRedThreads) acc += (double)vi[r] * (double)w[r];
-    acc = wave_sum(acc);
-    if (lane == 0) wsum[i][wv] = acc;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < k; i += kRedThreads) {
-    double s = 0.0;
-    for (int q = 0; q < kRedThreads / 64; ++q) s += wsum[i][q];
-    partial[(int64_t)blockIdx.x * k + i] = s;
-  }
-}
-
-template <typename T>
-hipError_t launch_update_mdot(const T *V, int64_t ldv, int k, const double *h, T *w, int64_t n,
-                              double *partial, double *out, hipStream_t st) {
-  const int nb = reduce_blocks(n);
-  hipLaunchKernelGGL((k_update<T, 1>), dim3(nb), dim3(kRedThreads), 0, st, V, ldv, k, h, w, n, partial);
-  hipLaunchKernelGGL(k_reduce, dim3(k), dim3(kRedThreads), 0, st, partial, nb, k, out);
-  return hipGetLastError();
-}
-template <typename T>
-hipError_t launch_update_norm(const T *V, int64_t ldv, int k, const double *h, T *w, int64_t n,
-                              double *partial, double *out, hipStream_t st) {
-  const int nb = reduce_blocks(n);
-  hipLaunchKernelGGL((k_update<T, 2>), dim3(nb), dim3(kRedThreads), 0, st, V, ldv, k, h, w, n, partial);
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, st, partial, nb, 1, out);
-  return hipGetLastError();
-}
-template hipError_t launch_update_mdot<double>(const double *, int64_t, int, const double *,
-                                               double *, int64_t, double *, double *, hipStream_t);
-template hipError_t launch_update_mdot<float>(const float *, int64_t, int, const double *,
-                                              float *, int64_t, double *, double *, hipStream_t);
-template hipError_t launch_update_norm<double>(const double *, int64_t, int, const double *,
-                                               double *, int64_t, double *, double *, hipStream_t);
-template hipError_t launch_update_norm<float>(const float *, int64_t, int, const double *,
-                                              float *, int64_t, double *, double *, hipStream_t);
-
-// ---------------------------------------------------------------------------
-// Gram-Schmidt passes with register tiling.  A block owns OR_ROWS rows per
-// thread (1024 rows); w stays in registers while the basis vectors stream in
-// tiles of OR_TILE, so every thread keeps OR_ROWS * OR_TILE loads in flight.
-// ---------------------------------------------------------------------------
-constexpr int OR_ROWS = 4;
-constexpr int OR_TILE = 8;
-constexpr int OR_CHUNK = kRedThreads * OR_ROWS;
-
-int ortho_blocks(int64_t n) { return (int)((n + OR_CHUNK - 1) / OR_CHUNK); }
-
-// partial[b*(k+1) + i] = sum over the block's rows of V_i w (i < k), and
-// partial[b*(k+1) + k] = sum of w^2
-template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_proj(const T *__restrict__ V, int64_t ldv, int k,
-                                                      const T *__restrict__ w, int64_t n,
-                                                      double *__restrict__ partial) {
-  __shared__ double wsum[kMaxKrylov + 1][kRedThreads / 64];
-  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
-  const int64_t r0 = (int64_t)blockIdx.x * OR_CHUNK + tid;
-  double wr[OR_ROWS];
-  double nn = 0.0;
-#pragma unroll
-  for (int s = 0; s < OR_ROWS; ++s) {
-    const int64_t r = r0 + (int64_t)s * kRedThreads;
-    wr[s] = r < n ? (double)w[r] : 0.0;
-    nn += wr[s] * wr[s];
-  }
-  for (int i0 = 0; i0 < k; i0 += OR_TILE) {
-    double acc[OR_TILE];
-#pragma unroll
-    for (int q = 0; q < OR_TILE; ++q) acc[q] = 0.0;
-#pragma unroll
-    for (int s = 0; s < OR_ROWS; ++s) {
-      const int64_t r = r0 + (int64_t)s * kRedThreads;
-      if (r < n) {
-#pragma unroll
-        for (int q = 0; q < OR_TILE; ++q)
-          if (i0 + q < k) acc[q] += (double)V[(int64_t)(i0 + q) * ldv + r] * wr[s];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < OR_TILE; ++q) {
-      const double v = wave_sum(acc[q]);
-      if (lane == 0 && i0 + q < k) wsum[i0 + q][wv] = v;
-    }
-  }
-  nn = wave_sum(nn);
-  if (lane == 0) wsum[k][wv] = nn;
-  __syncthreads();
-  for (int i = tid; i <= k; i += kRedThreads) {
-    double s2 = 0.0;
-    for (int q = 0; q < kRedThreads / 64; ++q) s2 += wsum[i][q];
-    partial[(int64_t)blockIdx.x * (k + 1) + i] = s2;
-  }
-}
-
-// w -= sum_i h_i V_i ; partial[b] = sum of the new w^2
-template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_orth_update(const T *__restrict__ V, int64_t ldv,
-                                                             int k, const double *__restrict__ h,
-                                                             T *__restrict__ w, int64_t n,
-                                                             double *__restrict__ partial) {
-  __shared__ double sh[kMaxKrylov];
-  __shared__ double wsum[kRedThreads / 64];
-  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
-  for (int i = tid; i < k; i += kRedThreads) sh[i] = h[i];
-  __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * OR_CHUNK + tid;
-  double acc[OR_ROWS];
-#pragma unroll
-  for (int s = 0; s < OR_ROWS; ++s) {
-    const int64_t r = r0 + (int64_t)s * kRedThreads;
-    acc[s] = r < n ? (double)w[r] : 0.0;
-  }
-  for (int i0 = 0; i0 < k; i0 += OR_TILE) {
-#pragma unroll
-    for (int s = 0; s < OR_ROWS; ++s) {
-      const int64_t r = r0 + (int64_t)s * kRedThreads;
-      if (r < n) {
-#pragma unroll
-        for (int q = 0; q < OR_TILE; ++q)
-          if (i0 + q < k) acc[s] -= sh[i0 + q] * (double)V[(int64_t)(i0 + q) * ldv + r];
-      }
-    }
-  }
-  double nn = 0.0;
-#pragma unroll
-  for (int s = 0; s < OR_ROWS; ++s) {
-    const int64_t r = r0 + (int64_t)s * kRedThreads;
-    if (r < n) {
-      const T v = (T)acc[s];
-      w[r] = v;
-      nn += (double)v * (double)v;
-    }
-  }
-  nn = wave_sum(nn);
-  if (lane == 0) wsum[wv] = nn;
-  __syncthreads();
-  if (tid == 0) {
-    double s2 = 0.0;
-    for (int q = 0; q < kRedThreads / 64; ++q) s2 += wsum[q];
-    partial[blockIdx.x] = s2;
-  }
-}
-
-template <typename T>
-hipError_t launch_proj(const T *V, int64_t ldv, int k, const T *w, int64_t n, double *partial,
-                       double *out, hipStream_t st) {
-  const int nb = ortho_blocks(n);
-  hipLaunchKernelGGL(k_proj<T>, dim3(nb), dim3(kRedThreads), 0, st, V, ldv, k, w, n, partial);
-  hipLaunchKernelGGL(k_reduce, dim3(k + 1), dim3(kRedThreads), 0, st, partial, nb, k + 1, out);
-  return hipGetLastError();
-}
-template <typename T>
-hipError_t launch_orth_update(const T *V, int64_t ldv, int k, const double *h, T *w, int64_t n,
-                              double *partial, double *out, hipStream_t st) {
-  const int nb = ortho_blocks(n);
-  hipLaunchKernelGGL(k_orth_update<T>, dim3(nb), dim3(kRedThreads), 0, st, V, ldv, k, h, w, n, partial);
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, st, partial, nb, 1, out);
-  return hipGetLastError();
-}
-template hipError_t launch_proj<double>(const double *, int64_t, int, const double *, int64_t,
-                                        double *, double *, hipStream_t);
-template hipError_t launch_proj<float>(const float *, int64_t, int, const float *, int64_t,
-                                       double *, double *, hipStream_t);
-template hipError_t launch_orth_update<double>(const double *, int64_t, int, const double *,
-                                               double *, int64_t, double *, double *, hipStream_t);
-template hipError_t launch_orth_update<float>(const float *, int64_t, int, const double *,
-                                              float *, int64_t, double *, double *, hipStream_t);
-
 static inline dim3 grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 65536) g = 65536;
@@ -768,41 +284,6 @@ static inline dim3 grid_for(int64_t n) {
 }
 #define GRID_STRIDE(t, n) \
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < (n); t += (int64_t)gridDim.x * blockDim.x)
-
-template <typename T>
-__global__ void k_scale_copy(const T *__restrict__ w, double s, T *__restrict__ v, int64_t n) {
-  GRID_STRIDE(t, n) v[t] = (T)((double)w[t] * s);
-}
-template <typename T>
-hipError_t launch_scale_copy(const T *w, double inv_norm, T *v, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_scale_copy<T>, grid_for(n), dim3(256), 0, st, w, inv_norm, v, n);
-  return hipGetLastError();
-}
-template hipError_t launch_scale_copy<double>(const double *, double, double *, int64_t, hipStream_t);
-template hipError_t launch_scale_copy<float>(const float *, double, float *, int64_t, hipStream_t);
-
-template <typename T>
-__global__ void k_combine(const T *__restrict__ V, int64_t ldv, int k, const double *__restrict__ y,
-                          T *__restrict__ out, int64_t n) {
-  __shared__ double sy[kMaxKrylov];
-  for (int i = threadIdx.x; i < k; i += blockDim.x) sy[i] = y[i];
-  __syncthreads();
-  GRID_STRIDE(t, n) {
-    double acc = 0.0;
-    for (int i = 0; i < k; ++i) acc += sy[i] * (double)V[i * ldv + t];
-    out[t] = (T)acc;
-  }
-}
-template <typename T>
-hipError_t launch_combine(const T *V, int64_t ldv, int k, const double *y, T *out, int64_t n,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_combine<T>, grid_for(n), dim3(256), 0, st, V, ldv, k, y, out, n);
-  return hipGetLastError();
-}
-template hipError_t launch_combine<double>(const double *, int64_t, int, const double *, double *,
-                                           int64_t, hipStream_t);
-template hipError_t launch_combine<float>(const float *, int64_t, int, const double *, float *,
-                                          int64_t, hipStream_t);
 
 // y = a x + b y; a term with a zero coefficient is not read, so y may start
 // uninitialised when b = 0
@@ -817,103 +298,6 @@ __global__ void k_axpby(double a, const double *__restrict__ x, double b, double
 hipError_t launch_axpby(double a, const double *x, double b, double *y, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_axpby, grid_for(n), dim3(256), 0, st, a, x, b, y, n);
   return hipGetLastError();
-}
-__global__ void k_cast_axpy(double a, const float *__restrict__ x, double *__restrict__ y, int64_t n) {
-  GRID_STRIDE(t, n) y[t] += a * (double)x[t];
-}
-hipError_t launch_cast_axpy(double a, const float *x, double *y, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_cast_axpy, grid_for(n), dim3(256), 0, st, a, x, y, n);
-  return hipGetLastError();
-}
-__global__ void k_cast_scale(const double *__restrict__ x, double a, float *__restrict__ y, int64_t n) {
-  GRID_STRIDE(t, n) y[t] = (float)(a * x[t]);
-}
-hipError_t launch_cast_scale(const double *x, double a, float *y, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_cast_scale, grid_for(n), dim3(256), 0, st, x, a, y, n);
-  return hipGetLastError();
-}
-__global__ void k_sub(const double *__restrict__ b, const double *__restrict__ Jx,
-                      double *__restrict__ r, int64_t n) {
-  GRID_STRIDE(t, n) r[t] = b[t] - Jx[t];
-}
-hipError_t launch_sub(const double *b, const double *Jx, double *r, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_sub, grid_for(n), dim3(256), 0, st, b, Jx, r, n);
-  return hipGetLastError();
-}
-template <typename T>
-__global__ void k_sub_t(const T *__restrict__ b, const T *__restrict__ Jx, T *__restrict__ r,
-                        int64_t n) {
-  GRID_STRIDE(t, n) r[t] = b[t] - Jx[t];
-}
-template <typename T>
-hipError_t launch_sub_t(const T *b, const T *Jx, T *r, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_sub_t<T>, grid_for(n), dim3(256), 0, st, b, Jx, r, n);
-  return hipGetLastError();
-}
-template hipError_t launch_sub_t<double>(const double *, const double *, double *, int64_t, hipStream_t);
-template hipError_t launch_sub_t<float>(const float *, const float *, float *, int64_t, hipStream_t);
-template <typename T>
-__global__ void k_axpy_t(double a, const T *__restrict__ x, T *__restrict__ y, int64_t n) {
-  GRID_STRIDE(t, n) y[t] = (T)((double)y[t] + a * (double)x[t]);
-}
-template <typename T>
-hipError_t launch_axpy_t(double a, const T *x, T *y, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_axpy_t<T>, grid_for(n), dim3(256), 0, st, a, x, y, n);
-  return hipGetLastError();
-}
-template hipError_t launch_axpy_t<double>(double, const double *, double *, int64_t, hipStream_t);
-template hipError_t launch_axpy_t<float>(double, const float *, float *, int64_t, hipStream_t);
-
-// u += du, p += dp (optional cut-off); partials of ||du||^2, ||u||^2, ||dp||^2, ||p||^2
-__global__ __launch_bounds__(kRedThreads) void k_newton_update(const double *__restrict__ dx,
-                                                               double *__restrict__ u, int64_t n_u,
-                                                               double *__restrict__ p, int64_t n_p,
-                                                               int cutoff_on, double cutoff,
-                                                               double *__restrict__ partial) {
-  __shared__ double wsum[4][kRedThreads / 64];
-  const int64_t n = n_u + n_p;
-  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += kRedThreads) {
-    const double d = dx[r];
-    if (r < n_u) {
-      const double v = u[r] + d;
-      u[r] = v;
-      a[0] += d * d;
-      a[1] += v * v;
-    } else {
-      double v = p[r - n_u] + d;
-      if (cutoff_on && v < cutoff) v = cutoff;
-      p[r - n_u] = v;
-      a[2] += d * d;
-      a[3] += v * v;
-    }
-  }
-  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
-  for (int c = 0; c < 4; ++c) {
-    double s = wave_sum(a[c]);
-    if (lane == 0) wsum[c][wv] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < 4) {
-    double s = 0.0;
-    for (int q = 0; q < kRedThreads / 64; ++q) s += wsum[threadIdx.x][q];
-    partial[(int64_t)blockIdx.x * 4 + threadIdx.x] = s;
-  }
-}
-hipError_t launch_newton_update(const double *dx, double *u, int64_t n_u, double *p, int64_t n_p,
-                                int cutoff_on, double cutoff, double *partial, double *out,
-                                hipStream_t st) {
-  const int nb = reduce_blocks(n_u + n_p);
-  hipLaunchKernelGGL(k_newton_update, dim3(nb), dim3(kRedThreads), 0, st, dx, u, n_u, p, n_p,
-                     cutoff_on, cutoff, partial);
-  hipLaunchKernelGGL(k_reduce, dim3(4), dim3(kRedThreads), 0, st, partial, nb, 4, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_norm2(const double *x, int64_t n, double *partial, double *out, hipStream_t st) {
-  return launch_mdot<double>(x, 0, 1, x, n, partial, out, st);
 }
 
 }  // namespace hf

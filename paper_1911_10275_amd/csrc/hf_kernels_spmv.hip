@@ -1,0 +1,234 @@
+// Block-sparse Jacobian product and block-Jacobi apply for gfx950.
+//
+// Jacobian storage.  Element row e of A is one contiguous "row panel": its
+// blocks (diagonal first, then one per interior face in local-face order)
+// each stored column-major, so the panel is a column-major bs x (nb*bs)
+// matrix.  The product streams each panel with 16-byte loads: a group of L
+// lanes reads CH = LA*EL consecutive values per step, and because CH is a
+// multiple of bs every lane keeps the same rows at every step; the products
+// are summed per lane and combined across lanes in a fixed order at the end.
+// The x values a row panel needs are staged in LDS first.
+#include <cmath>
+
+#include "hf_internal.h"
+
+namespace hf {
+
+// ---------------------------------------------------------------------------
+// Block-sparse product y = A x (+ B x_p on rows with coupling strips)
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int active_lanes(int L, int EL, int BU) {
+  int la = L;
+  while (la > 0 && (la * EL) % BU != 0) --la;
+  return la;
+}
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int EL = 2;
+};
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int EL = 4;
+};
+
+template <typename T, int BU>
+struct SpmvShape {
+  static constexpr int EL = Vec16<T>::EL;
+  static constexpr int L = BU >= 24 ? 64 : (BU >= 12 ? 32 : 16);
+  static constexpr int LA = active_lanes(L, EL, BU);
+  static constexpr int CH = LA * EL;
+  static constexpr int RPC = CH / BU;  // columns advanced per step
+  static_assert(CH % BU == 0, "chunk must hold whole columns");
+};
+
+template <typename T>
+__device__ inline T vget(const typename Vec16<T>::type &v, int s);
+template <>
+__device__ inline double vget<double>(const double2 &v, int s) { return s == 0 ? v.x : v.y; }
+template <>
+__device__ inline float vget<float>(const float4 &v, int s) {
+  return s == 0 ? v.x : (s == 1 ? v.y : (s == 2 ? v.z : v.w));
+}
+
+// Instance mask of the batched solver: a row of instance b is computed when
+// mode = 0, when solving[b] (mode 1), or when solving[b] and kconv[b] < 0
+// (mode 2, the instance still iterates in its cycle); other rows are left
+// untouched.
+struct RowMask {
+  const int32_t *inst;  // instance of each element (or pressure node)
+  const int *solving, *kconv;
+  int mode;
+  __device__ bool live(int64_t r) const {
+    if (!mode) return true;
+    const int b = inst[r];
+    return solving[b] != 0 && (mode == 1 || kconv[b] < 0);
+  }
+};
+
+template <typename T, int BU, int NT, bool STRIPS>
+__global__ __launch_bounds__(NT) void k_bsr_spmv(
+    int64_t ne, const int64_t *__restrict__ blk_ptr, const int32_t *__restrict__ blk_col,
+    const T *__restrict__ A, const int64_t *__restrict__ sp_ptr,
+    const int32_t *__restrict__ sp_pnode, const T *__restrict__ Bs, const T *__restrict__ x,
+    const T *__restrict__ xp, T *__restrict__ y, RowMask mask) {
+  using S = SpmvShape<T, BU>;
+  constexpr int L = S::L, EL = S::EL, LA = S::LA, CH = S::CH, RPC = S::RPC, G = NT / L;
+  using V = typename Vec16<T>::type;
+  __shared__ T xs[G][5 * BU];
+  __shared__ T part[G][CH];
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  const int64_t e = (int64_t)blockIdx.x * G + g;
+  const bool live = e < ne && mask.live(e);
+  int64_t b0 = 0;
+  int nb = 0;
+  if (live) {
+    b0 = blk_ptr[e];
+    nb = (int)(blk_ptr[e + 1] - b0);
+    for (int t = lane; t < nb * BU; t += L) xs[g][t] = x[(int64_t)blk_col[b0 + t / BU] * BU + t % BU];
+  }
+  __syncthreads();
+  T acc[EL];
+#pragma unroll
+  for (int s = 0; s < EL; ++s) acc[s] = T(0);
+  if (live && lane < LA) {
+    const T *panel = A + b0 * BU * BU;
+    const int total = nb * BU * BU;
+    int colS[EL];
+#pragma unroll
+    for (int s = 0; s < EL; ++s) colS[s] = (lane * EL + s) / BU;
+    int f = lane * EL, cb = 0;
+#pragma unroll 4
+    for (; f < total; f += CH, cb += RPC) {
+      const V v = *(const V *)(panel + f);
+#pragma unroll
+      for (int s = 0; s < EL; ++s) acc[s] += vget<T>(v, s) * xs[g][cb + colS[s]];
+    }
+  }
+  if (lane < LA) {
+#pragma unroll
+    for (int s = 0; s < EL; ++s) part[g][lane * EL + s] = acc[s];
+  }
+  __syncthreads();
+  if (live && lane < BU) {
+    T sum = T(0);
+#pragma unroll
+    for (int t = 0; t < RPC; ++t) sum += part[g][lane + BU * t];
+    if (STRIPS) {
+      for (int64_t k = sp_ptr[e]; k < sp_ptr[e + 1]; ++k) sum += Bs[k * BU + lane] * xp[sp_pnode[k]];
+    }
+    y[e * BU + lane] = sum;
+  }
+}
+
+// pressure rows: y_p[i] = sum_strips C x_u + sum_j D_b[i][j] x_p[j] over the dense block
+// of the row's instance b (one wave per row)
+template <typename T, int BU>
+__global__ __launch_bounds__(64) void k_prows(int64_t np, const int32_t *__restrict__ pinst,
+                                              const int32_t *__restrict__ poff,
+                                              const int64_t *__restrict__ doff,
+                                              const int32_t *__restrict__ pc_ptr,
+                                              const int32_t *__restrict__ pc_ent,
+                                              const int32_t *__restrict__ sp_elem,
+                                              const T *__restrict__ Cs, const T *__restrict__ D,
+                                              const T *__restrict__ xu, const T *__restrict__ xp,
+                                              T *__restrict__ yp, RowMask mask) {
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (!mask.live(i)) return;  // the whole wave leaves together
+  double acc = 0.0;
+  if (pc_ptr) {
+    for (int32_t c = pc_ptr[i]; c < pc_ptr[i + 1]; ++c) {
+      const int32_t ent = pc_ent[c];
+      const int64_t e = sp_elem[ent];
+      if (lane < BU) acc += (double)Cs[(int64_t)ent * BU + lane] * (double)xu[e * BU + lane];
+    }
+  }
+  const int b = pinst[i];
+  const int64_t p0 = poff[b], nb = poff[b + 1] - p0;
+  const T *Drow = D + doff[b] + (i - p0) * nb;
+  for (int64_t j = lane; j < nb; j += 64) acc += (double)Drow[j] * (double)xp[p0 + j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) yp[i] = (T)acc;
+}
+
+template <typename T, int BU>
+static void spmv_bu(const KParams &kp, const T *A, const T *Bs, const T *Cs, const T *D,
+                    const T *x, T *y, const RowSel &sel, hipStream_t st) {
+  const RowMask me{kp.einst, sel.solving, sel.kconv, sel.mode};
+  const RowMask mp{kp.pinst, sel.solving, sel.kconv, sel.mode};
+  using S = SpmvShape<T, BU>;
+  constexpr int NT = 256, G = NT / S::L;
+  const int64_t ne = kp.s.ne;
+  if (ne)
+    hipLaunchKernelGGL((k_bsr_spmv<T, BU, NT, true>), dim3((unsigned)((ne + G - 1) / G)), dim3(NT), 0, st,
+                       ne, kp.m.blk_ptr, kp.m.blk_col, A, kp.m.sp_ptr, kp.m.sp_pnode, Bs, x,
+                       x + kp.s.n_u, y, me);
+  if (kp.s.n_p)
+    hipLaunchKernelGGL((k_prows<T, BU>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp.s.n_p,
+                       kp.pinst, kp.poff, kp.doff, kp.m.pc_ptr, kp.m.pc_ent, kp.m.sp_elem, Cs, D, x,
+                       x + kp.s.n_u, y + kp.s.n_u, mp);
+}
+
+template <typename T>
+hipError_t launch_spmv(const KParams &kp, const T *A, const T *Bs, const T *Cs, const T *D,
+                       const T *x, T *y, const RowSel &sel, hipStream_t st) {
+  switch (kp.s.bu) {
+    case 6: spmv_bu<T, 6>(kp, A, Bs, Cs, D, x, y, sel, st); break;
+    case 12: spmv_bu<T, 12>(kp, A, Bs, Cs, D, x, y, sel, st); break;
+    case 30: spmv_bu<T, 30>(kp, A, Bs, Cs, D, x, y, sel, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_spmv<double>(const KParams &, const double *, const double *,
+                                        const double *, const double *, const double *,
+                                        double *, const RowSel &, hipStream_t);
+template hipError_t launch_spmv<float>(const KParams &, const float *, const float *,
+                                       const float *, const float *, const float *, float *,
+                                       const RowSel &, hipStream_t);
+
+// block-Jacobi apply: z_u = blockdiag(inv) r_u (the same streaming kernel on
+// the identity block pattern), z_p = S^-1 r_p
+template <typename T, int BU>
+static void precond_bu(const KParams &kp, const T *inv, const T *Sinv, const T *r, T *z,
+                       const RowSel &sel, hipStream_t st, const int64_t *ident_ptr,
+                       const int32_t *ident_col) {
+  const RowMask me{kp.einst, sel.solving, sel.kconv, sel.mode};
+  const RowMask mp{kp.pinst, sel.solving, sel.kconv, sel.mode};
+  using S = SpmvShape<T, BU>;
+  constexpr int NT = 256, G = NT / S::L;
+  const int64_t ne = kp.s.ne;
+  if (ne)
+    hipLaunchKernelGGL((k_bsr_spmv<T, BU, NT, false>), dim3((unsigned)((ne + G - 1) / G)), dim3(NT), 0, st,
+                       ne, ident_ptr, ident_col, inv, nullptr, nullptr, nullptr, r, nullptr, z, me);
+  if (kp.s.n_p)
+    hipLaunchKernelGGL((k_prows<T, BU>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp.s.n_p,
+                       kp.pinst, kp.poff, kp.doff, nullptr, nullptr, nullptr, nullptr, Sinv, r,
+                       r + kp.s.n_u, z + kp.s.n_u, mp);
+}
+
+template <typename T>
+hipError_t launch_precond(const KParams &kp, const T *inv, const T *Sinv, const T *r, T *z,
+                          const RowSel &sel, hipStream_t st) {
+  const int64_t *ip = kp.m.ident_ptr;
+  const int32_t *ic = kp.m.ident_col;
+  switch (kp.s.bu) {
+    case 6: precond_bu<T, 6>(kp, inv, Sinv, r, z, sel, st, ip, ic); break;
+    case 12: precond_bu<T, 12>(kp, inv, Sinv, r, z, sel, st, ip, ic); break;
+    case 30: precond_bu<T, 30>(kp, inv, Sinv, r, z, sel, st, ip, ic); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_precond<double>(const KParams &, const double *, const double *,
+                                           const double *, double *, const RowSel &, hipStream_t);
+template hipError_t launch_precond<float>(const KParams &, const float *, const float *,
+                                          const float *, float *, const RowSel &, hipStream_t);
+
+}  // namespace hf

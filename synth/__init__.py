@@ -406,7 +406,10 @@ def ensemble(count: int = 64, seed: int = 4) -> List[Problem]:
     """Batched 2D KGD ensemble: instance i uses seed 1000*seed + i; triangle
     count log-uniform in [1e3, 2e4] (n = round(sqrt(n_tri/2))), order P1/P2 by
     coin flip, E ~ U[0.5, 2], nu ~ U[0.15, 0.35], mu and Q0 log-uniform in
-    [1e-4, 1e-1] and [1e-5, 1e-3]."""
+    [1e-4, 1e-1] and [1e-5, 1e-3].  The time step is dt = 1e-4 / Q0, so that
+    every instance injects the same volume per load step as the 2D KGD
+    workload (Q0 = 1e-4, dt = 1); with dt = 1 the instances with the largest
+    Q0 take steps too long for the Newton iteration to converge."""
     out = []
     for i in range(count):
         s = 1000 * seed + i
@@ -419,6 +422,7 @@ def ensemble(count: int = 64, seed: int = 4) -> List[Problem]:
                        mu=math.exp(math.log(1e-4) + u[4] * (math.log(1e-1) - math.log(1e-4))),
                        dt=1.0)
         q0 = math.exp(math.log(1e-5) + u[5] * (math.log(1e-3) - math.log(1e-5)))
+        mat = dataclasses.replace(mat, dt=1e-4 / q0)
         out.append(kgd_problem(n, order, s, mat, q0, half_length=0.05, ring=2,
                                load_steps=10, name=f"ens{i}_n{n}_p{order}"))
     return out
