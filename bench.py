@@ -238,6 +238,9 @@ def main():
     ap.add_argument("--no-ir", action="store_true", help="skip the FP32-IR comparison")
     ap.add_argument("--gmres-m", type=int, default=60, help="GMRES restart length")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble")
+    ap.add_argument("--tune", type=int, default=0, choices=(-1, 0, 1),
+                    help="autotune level before timing (-1: none); choices cached in "
+                         "paper_1911_10275_amd/tuning_cache.txt")
     ap.add_argument("--ensemble-steps", type=int, default=3)
     ap.add_argument("--ensemble-m", type=int, default=120, help="GMRES restart length, ensemble")
     ap.add_argument("--counters", action="store_true",
@@ -273,6 +276,20 @@ def main():
     print(f"bench: predictor p0 = {p0:.4e}", file=sys.stderr, flush=True)
 
     K, W = args.steps, args.warmup
+    tuned = {}
+    tune_cache = os.path.join(ROOT, "paper_1911_10275_amd", "tuning_cache.txt")
+
+    def tune(name):
+        if args.tune < 0:
+            return
+        ctx.set_state(St.u, St.p, St.w_old)
+        ctx.assemble()
+        t0 = time.perf_counter()
+        tuned[name] = ctx.autotune(level=args.tune, cache_path=tune_cache).as_dict()
+        print(f"bench: {name} tuning {tuned[name]} ({time.perf_counter() - t0:.1f} s, untimed)",
+              file=sys.stderr, flush=True)
+
+    tune("fp64")
     dt64, st64, prof, state64 = run_steps(ctx, St, K, W, profile=True)
     iters64 = [s[0] for s in st64]
     for s in st64:
@@ -299,7 +316,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": prob.name, "elements": int(sz.n_elem), "dof": int(N),
                    "u_dof": int(sz.n_u), "p_dof": int(sz.n_p), "element": f"P{prob.order}",
-                   "dim": prob.dim, "precision": "fp64", "gmres_m": args.gmres_m, "rtol": 1e-10},
+                   "dim": prob.dim, "precision": "fp64",
+                   "gmres_m": tuned.get("fp64", {}).get("gmres_m", args.gmres_m), "rtol": 1e-10},
         "gmres": {"iters_per_step": float(np.mean(iters64)),
                   "iters_per_s": float(sum(iters64) / dt64),
                   "mdof_iters_per_s": float(sum(iters64) * N / dt64 / 1e6)},
@@ -313,6 +331,7 @@ def main():
     }
     if not args.no_ir:
         ctx.set_options(precision=hf.HF_FP32_IR)
+        tune("fp32_ir")
         dt32, st32, prof32, state32 = run_steps(ctx, St, K, W, profile=False)
         iters32 = [s[0] for s in st32]
         for s in st32:
@@ -329,6 +348,7 @@ def main():
         print(f"bench: fp32-ir {K} steps in {dt32:.3f} s, GMRES iterations {iters32}",
               file=sys.stderr, flush=True)
     ctx.close()
+    out["tuning"] = tuned
     if not args.no_ensemble:
         out["ensemble"] = ensemble_block(args.ensemble_steps, args.ensemble_m)
     if not args.no_cpu:

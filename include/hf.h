@@ -133,6 +133,24 @@ typedef struct {
   int reserved;
 } hf_newton_stats;
 
+/* Kernel schedules and solver choices (all zero = defaults).  Changing them
+   never changes what is solved: the schedules only change the rounding
+   order, the solver choices the Krylov iterates, and every solve still
+   reaches the true relative residual rtol. */
+typedef struct {
+  int spmv_var;        /* lanes per element row of the Jacobian product:
+                          0 = 64/32/16 for block size 30/12/6, 1 = half */
+  int prec_var;        /* the same for the block-Jacobi apply */
+  int ortho_var;       /* rows per thread of the Gram-Schmidt passes:
+                          0 = 4, 1 = 8, 2 = 2 (1024-row chunks) */
+  int reorth;          /* second classical Gram-Schmidt pass: 0 = when
+                          ||w1|| < ||w|| / sqrt(2) (default), 1 = always,
+                          2 = never in FP64 solves (the FP32 inner solves
+                          of GMRES-IR keep the test) */
+  int gmres_m;         /* restart length (0 = keep hf_options.gmres_m) */
+  int reserved[3];
+} hf_tuning;
+
 typedef struct {
   /* accumulated device time (ms) and launch counts of kernel classes, when
      hf_options.profile = 1; reset by hf_reset_profile */
@@ -265,6 +283,23 @@ hf_status hf_get_increment(hf_ctx *ctx, int32_t inst, double *du, double *dp);
    last hf_solve in FP32-IR mode. */
 hf_status hf_apply_jacobian(hf_ctx *ctx, int precision, const void *x, void *y);
 hf_status hf_get_profile(hf_ctx *ctx, hf_profile *out);
+
+/* ---- tuning ---- */
+hf_status hf_get_tuning(hf_ctx *ctx, hf_tuning *out);
+/* Out-of-range fields give HF_EINVAL and change nothing. */
+hf_status hf_set_tuning(hf_ctx *ctx, const hf_tuning *t);
+/* Autotuner (after hf_assemble; uses the assembled system and leaves it
+   in place).  level 0: times every variant of the Jacobian product, the
+   block-Jacobi apply and the Gram-Schmidt passes (HIP events, 10 launches
+   each after warm-up) in the context's precision and keeps the fastest;
+   level 1: then also times complete linear solves for restart lengths
+   {60, 120} x re-orthogonalisation {test, never} and keeps the fastest
+   whose solves all converge.  cache_path (nullable): a text file of
+   "key choices" lines; the key names the GPU architecture, dim, order,
+   sizes, instance count, precision and level.  A line with the context's
+   key is applied without timing; otherwise the result is appended.
+   *out (nullable) receives the choice. */
+hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path, hf_tuning *out);
 hf_status hf_reset_profile(hf_ctx *ctx);
 
 #ifdef __cplusplus

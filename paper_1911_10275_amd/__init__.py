@@ -33,7 +33,7 @@ EXPORTS = [
     "hf_get_state", "hf_set_state_device", "hf_get_state_device", "hf_assemble", "hf_solve",
     "hf_newton_step", "hf_newton_solve", "hf_end_load_step", "hf_initial_guess", "hf_get_residual",
     "hf_get_block_rows", "hf_get_coupling", "hf_get_increment", "hf_apply_jacobian",
-    "hf_get_profile", "hf_reset_profile",
+    "hf_get_profile", "hf_reset_profile", "hf_get_tuning", "hf_set_tuning", "hf_autotune",
 ]
 
 
@@ -67,6 +67,15 @@ class NewtonStats(C.Structure):
     _fields_ = [("lin", SolveStats), ("du_rel", C.c_double), ("dp_rel", C.c_double),
                 ("res_norm", C.c_double), ("iterations", C.c_int), ("converged", C.c_int),
                 ("status", C.c_int), ("reserved", C.c_int)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("spmv_var", C.c_int), ("prec_var", C.c_int), ("ortho_var", C.c_int),
+                ("reorth", C.c_int), ("gmres_m", C.c_int), ("reserved", C.c_int * 3)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k in ("spmv_var", "prec_var", "ortho_var", "reorth",
+                                               "gmres_m")}
 
 
 class Profile(C.Structure):
@@ -135,6 +144,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hf_apply_jacobian": (C.c_int, [vp, C.c_int, vp, vp]),
         "hf_get_profile": (C.c_int, [vp, P(Profile)]),
         "hf_reset_profile": (C.c_int, [vp]),
+        "hf_get_tuning": (C.c_int, [vp, P(Tuning)]),
+        "hf_set_tuning": (C.c_int, [vp, P(Tuning)]),
+        "hf_autotune": (C.c_int, [vp, C.c_int, C.c_char_p, P(Tuning)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -383,6 +395,30 @@ class Context:
 
     def reset_profile(self):
         self._check(self.lib.hf_reset_profile(self.h), "hf_reset_profile")
+
+    # -- tuning --------------------------------------------------------------------------
+    def tuning(self) -> Tuning:
+        t = Tuning()
+        self._check(self.lib.hf_get_tuning(self.h, C.byref(t)), "hf_get_tuning")
+        return t
+
+    def set_tuning(self, **kw):
+        t = self.tuning()
+        for k, v in kw.items():
+            if k not in Tuning().as_dict():
+                raise KeyError(k)
+            setattr(t, k, v)
+        self._check(self.lib.hf_set_tuning(self.h, C.byref(t)), "hf_set_tuning")
+        self.opt.gmres_m = t.gmres_m
+
+    def autotune(self, level=0, cache_path=None) -> Tuning:
+        """Pick kernel schedules (level 0) and restart length / re-orthogonalisation
+        (level 1) by timing them on the assembled system; see hf_autotune."""
+        t = Tuning()
+        cp = None if cache_path is None else os.fsencode(cache_path)
+        self._check(self.lib.hf_autotune(self.h, level, cp, C.byref(t)), "hf_autotune")
+        self.opt.gmres_m = t.gmres_m
+        return t
 
 
 def _upload_problem(ctx: Context, prob) -> int:

@@ -18,7 +18,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <new>
 #include <set>
 #include <string>
@@ -30,7 +32,6 @@ using namespace hf;
 
 namespace {
 
-constexpr int kChunkRows = 1024;  // rows per reduction chunk (256 threads x 4 rows)
 constexpr int kIterChunk = 10;    // GMRES iterations between host checks
 
 struct Mat {
@@ -116,6 +117,7 @@ struct hf_ctx {
   size_t hd_n = 0, hi_n = 0, hu_n = 0;
   bool hu_pending = false;  // an upload from hu may still be in flight
   bool capturing = false;   // a GMRES chunk is being captured into a graph
+  hf_tuning tune{};         // kernel schedules and solver choices
   std::vector<std::string> ierr;  // message of each instance's failure in the current call
   // profile
   std::vector<hipEvent_t> evpool;
@@ -194,6 +196,8 @@ KParams kparams(const hf_ctx *ctx) {
   kp.n_inst = nI(ctx);
   kp.b_stab = ctx->opt.b_stab;
   kp.freeze_p = ctx->freeze_p;
+  kp.spmv_var = ctx->tune.spmv_var;
+  kp.prec_var = ctx->tune.prec_var;
   return kp;
 }
 
@@ -1005,6 +1009,7 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
   KrylovDev &kd = ctx->kd;
   kd.n_inst = B;
   kd.n_chunks = (int)c_row0.size();
+  kd.ortho_var = ctx->tune.ortho_var;
   {
     int64_t *p0;
     int32_t *p1, *p2, *p3;
@@ -1348,10 +1353,15 @@ static hf_status arnoldi_step(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, 
   ProfScope ps(ctx, P_ORTHO);
   HIPCHK(ks_proj<T>(kd, ws.V, N, k, ws.w, nullptr, ctx->partial, ctx->k_s1, ctx->stream));
   HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s1, ks, ws.w, nullptr, ctx->partial, ctx->k_n1, ctx->stream));
-  HIPCHK(ks_reorth_flag(kd, ctx->k_s1 + k, ks, ctx->k_n1, ctx->k_flag, ctx->stream));
-  HIPCHK(ks_proj<T>(kd, ws.V, N, k, ws.w, ctx->k_flag, ctx->partial, ctx->k_s2, ctx->stream));
-  HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s2, ks, ws.w, ctx->k_flag, ctx->partial, ctx->k_n2,
-                      ctx->stream));
+  // single-pass Gram-Schmidt loses orthogonality too fast in FP32: the inner
+  // solves of GMRES-IR keep the re-orthogonalisation test
+  const int pol = (sizeof(T) == 4 && ctx->tune.reorth == 2) ? 0 : ctx->tune.reorth;
+  HIPCHK(ks_reorth_flag(kd, ctx->k_s1 + k, ks, ctx->k_n1, pol, ctx->k_flag, ctx->stream));
+  if (pol != 2) {
+    HIPCHK(ks_proj<T>(kd, ws.V, N, k, ws.w, ctx->k_flag, ctx->partial, ctx->k_s2, ctx->stream));
+    HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s2, ks, ws.w, ctx->k_flag, ctx->partial, ctx->k_n2,
+                        ctx->stream));
+  }
   HIPCHK(ks_arnoldi(kd, j, m, ctx->k_s1, ks, ctx->k_s2, ks, ctx->k_flag, ctx->k_n1, ctx->k_n2, rtol,
                     ctx->k_scale, ctx->stream));
   HIPCHK(ks_scale<T>(kd, ws.w, ctx->k_scale, ws.V + (int64_t)(j + 1) * N, ctx->stream));
@@ -2014,5 +2024,182 @@ extern "C" hf_status hf_reset_profile(hf_ctx *ctx) {
   if (!ctx) return HF_EINVAL;
   resolve_profile(ctx);
   std::memset(&ctx->prof, 0, sizeof(ctx->prof));
+  return HF_OK;
+}
+
+// ===========================================================================
+// Tuning
+// ===========================================================================
+extern "C" hf_status hf_get_tuning(hf_ctx *ctx, hf_tuning *out) {
+  if (!ctx || !out) return HF_EINVAL;
+  *out = ctx->tune;
+  if (!out->gmres_m) out->gmres_m = ctx->opt.gmres_m;
+  return HF_OK;
+}
+
+extern "C" hf_status hf_set_tuning(hf_ctx *ctx, const hf_tuning *t) {
+  if (!ctx || !t) return HF_EINVAL;
+  if (t->spmv_var < 0 || t->spmv_var > 1 || t->prec_var < 0 || t->prec_var > 1 || t->ortho_var < 0 ||
+      t->ortho_var > 2 || t->reorth < 0 || t->reorth > 2 || t->gmres_m < 0 || t->gmres_m > kMaxKrylov - 1)
+    return fail(ctx, HF_EINVAL, "tuning value out of range");
+  release_all_graphs(ctx);  // the captured chunks hold the old schedule
+  ctx->tune = *t;
+  if (t->gmres_m) ctx->opt.gmres_m = t->gmres_m;
+  ctx->tune.gmres_m = 0;
+  ctx->kd.ortho_var = t->ortho_var;
+  return HF_OK;
+}
+
+namespace {
+
+// average device time (ms) of fn() over reps launches after two warm-up calls
+template <typename F>
+hf_status time_ms(hf_ctx *ctx, int reps, F fn, double &ms) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  hf_status st = HF_OK;
+  for (int i = 0; i < 2 && st == HF_OK; ++i) st = fn();
+  if (st == HF_OK) {
+    (void)hipEventRecord(e0, ctx->stream);
+    for (int i = 0; i < reps && st == HF_OK; ++i) st = fn();
+    (void)hipEventRecord(e1, ctx->stream);
+    (void)hipEventSynchronize(e1);
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    ms = t / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+std::string tune_key(hf_ctx *ctx, int level) {
+  hipDeviceProp_t prop;
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&prop, ctx->opt.device) == hipSuccess) arch = prop.gcnArchName;
+  for (char &c : arch)
+    if (c == ' ' || c == ':') c = '_';
+  std::ostringstream k;
+  k << arch << "_d" << ctx->s.dim << "p" << ctx->s.order << "_ne" << ctx->s.ne << "_nf" << ctx->s.nf
+    << "_np" << ctx->s.n_p << "_B" << nI(ctx) << "_prec" << ctx->opt.precision << "_L" << level;
+  return k.str();
+}
+
+template <typename T>
+hf_status tune_kernels(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, hf_tuning &best) {
+  const int64_t N = ctx->s.N();
+  const int B = nI(ctx);
+  KrylovDev &kd = ctx->kd;
+  TRY(ensure_ws<T>(ctx, ws));
+  HIPCHK(hipMemsetAsync(ws.V, 0, (size_t)(ws.m + 1) * N * sizeof(T), ctx->stream));
+  HIPCHK(hipMemsetAsync(ws.w, 0, N * sizeof(T), ctx->stream));
+  HIPCHK(hipMemsetAsync(ws.z, 0, N * sizeof(T), ctx->stream));
+  TRY(put(ctx, kd.solving, std::vector<int>(B, 1)));
+  HIPCHK(hipMemsetAsync(kd.kconv, 0xFF, B * sizeof(int), ctx->stream));  // -1: iterating
+  const RowSel all{};
+  double best_ms = 1e300;
+  for (int v = 0; v <= 1; ++v) {
+    ctx->tune.spmv_var = v;
+    const KParams kp = kparams(ctx);
+    double ms = 0.0;
+    TRY(time_ms(ctx, 10, [&]() { return apply_J<T>(ctx, kp, op, ws.z, ws.w, all); }, ms));
+    if (ms < best_ms) best_ms = ms, best.spmv_var = v;
+  }
+  best_ms = 1e300;
+  for (int v = 0; v <= 1; ++v) {
+    ctx->tune.prec_var = v;
+    const KParams kp = kparams(ctx);
+    double ms = 0.0;
+    TRY(time_ms(ctx, 10, [&]() { return apply_M<T>(ctx, kp, op, ws.z, ws.t, all); }, ms));
+    if (ms < best_ms) best_ms = ms, best.prec_var = v;
+  }
+  best_ms = 1e300;
+  const int k = std::max(1, ws.m / 2), ks = k + 1;
+  for (int v = 0; v <= 2; ++v) {
+    kd.ortho_var = v;
+    double ms = 0.0;
+    TRY(time_ms(ctx, 10, [&]() -> hf_status {
+      HIPCHK(ks_proj<T>(kd, ws.V, N, k, ws.w, nullptr, ctx->partial, ctx->k_s1, ctx->stream));
+      HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s1, ks, ws.w, nullptr, ctx->partial, ctx->k_n1,
+                          ctx->stream));
+      return HF_OK;
+    }, ms));
+    if (ms < best_ms) best_ms = ms, best.ortho_var = v;
+  }
+  TRY(sync(ctx));
+  return HF_OK;
+}
+
+}  // namespace
+
+extern "C" hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path, hf_tuning *out) {
+  TRY(check_ctx(ctx, 4));
+  if (level < 0 || level > 1) return fail(ctx, HF_EINVAL, "autotune level must be 0 or 1");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  ctx->ierr.clear();
+  const std::string key = tune_key(ctx, level);
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      hf_tuning t{};
+      if (ls >> k >> t.spmv_var >> t.prec_var >> t.ortho_var >> t.reorth >> t.gmres_m && k == key) {
+        TRY(hf_set_tuning(ctx, &t));
+        if (out) TRY(hf_get_tuning(ctx, out));
+        return HF_OK;
+      }
+    }
+  }
+  const int B = nI(ctx);
+  const hf_tuning saved = ctx->tune;
+  std::vector<int> on(B, 1);
+  std::vector<hf_status> st(B, HF_OK);
+  TRY(build_preconditioner(ctx, on, st));
+  if (first_failure(ctx, st, "singular block") != HF_OK) return HF_ESINGULAR;
+  hf_tuning best = saved;
+  release_all_graphs(ctx);
+  if (ctx->opt.precision == HF_FP64) {
+    Ops<double> op{ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->inv, ctx->Sinv};
+    TRY(tune_kernels<double>(ctx, op, ctx->k64, best));
+  } else {
+    Ops<float> op{ctx->A32, ctx->Bs32, ctx->Cs32, ctx->D32, ctx->inv32, ctx->Sinv32};
+    TRY(tune_kernels<float>(ctx, op, ctx->k32, best));
+  }
+  best.gmres_m = ctx->opt.gmres_m;
+  TRY(hf_set_tuning(ctx, &best));
+  if (level >= 1) {
+    double best_s = 1e300;
+    hf_tuning pick = best;
+    const int ms[2] = {60, 120};
+    const int pols[2] = {0, 2};
+    for (int mi = 0; mi < 2; ++mi)
+      for (int pi = 0; pi < 2; ++pi) {
+        hf_tuning t = best;
+        t.gmres_m = ms[mi];
+        t.reorth = pols[pi];
+        TRY(hf_set_tuning(ctx, &t));
+        std::vector<hf_solve_stats> ls;
+        TRY(do_solve(ctx, on, ls));  // warm-up: allocation and graph capture
+        const auto t0 = std::chrono::steady_clock::now();
+        TRY(do_solve(ctx, on, ls));
+        const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        bool ok = true;
+        for (const auto &l : ls) ok = ok && l.status == HF_OK;
+        if (ok && sec < best_s) best_s = sec, pick = t;
+      }
+    ctx->ierr.clear();
+    TRY(hf_set_tuning(ctx, &pick));
+  }
+  if (out) TRY(hf_get_tuning(ctx, out));
+  if (cache_path) {
+    hf_tuning t;
+    TRY(hf_get_tuning(ctx, &t));
+    std::ofstream o(cache_path, std::ios::app);
+    o << key << " " << t.spmv_var << " " << t.prec_var << " " << t.ortho_var << " " << t.reorth << " "
+      << t.gmres_m << "\n";
+  }
   return HF_OK;
 }

@@ -29,6 +29,7 @@ Rule simplex_rule(int dim, int n);
 constexpr int kMaxNq = 9;      // face points of 3D P2 (3 x 3)
 constexpr int kMaxKrylov = 257;  // basis vectors (restart length + 1)
 constexpr int kMaxNqv = 8;     // volume points of 3D P2 (2 x 2 x 2)
+constexpr int kChunkRows = 1024;  // rows of a reduction chunk of the batched Krylov kernels
 
 // Rule tables, in the device constant bank (set per context before launch).
 struct RuleTables {
@@ -119,11 +120,13 @@ struct KParams {
   int n_inst;
   double b_stab;
   int freeze_p;  // 1: pressure held fixed (fluid rows become p-rows of the identity)
+  int spmv_var = 0, prec_var = 0;  // lanes per element row: 0 wide, 1 half (tuning)
 };
 
 // device view of the batched Krylov state (see hf_kernels_krylov.hip)
 struct KrylovDev {
   int n_inst = 0, n_chunks = 0;
+  int ortho_var = 0;  // rows per thread of the Gram-Schmidt passes: 0 -> 4, 1 -> 8, 2 -> 2
   const int64_t *c_row0 = nullptr;
   const int32_t *c_len = nullptr, *c_inst = nullptr, *cptr = nullptr;
   int *solving = nullptr, *kconv = nullptr, *its = nullptr, *status = nullptr, *nbasis = nullptr;
@@ -200,8 +203,10 @@ template <typename TY, typename TX>
 hipError_t ks_cast(const KrylovDev &kd, const TX *x, const double *coef, TY *y, hipStream_t st);
 template <typename T>
 hipError_t ks_zero(const KrylovDev &kd, T *x, int only_solving, hipStream_t st);
-hipError_t ks_reorth_flag(const KrylovDev &kd, const double *n0, int n0s, const double *n1, int *flag,
-                          hipStream_t st);
+// flag[b] = 1 when instance b takes a second Gram-Schmidt pass: policy 0 when
+// ||w1||^2 < ||w||^2 / 2 (n1, n0), 1 always, 2 never
+hipError_t ks_reorth_flag(const KrylovDev &kd, const double *n0, int n0s, const double *n1, int policy,
+                          int *flag, hipStream_t st);
 hipError_t ks_arnoldi(const KrylovDev &kd, int j, int m, const double *s1, int s1s, const double *s2,
                       int s2s, const int *reorth, const double *n1, const double *n2, double rtol,
                       double *scale, hipStream_t st);

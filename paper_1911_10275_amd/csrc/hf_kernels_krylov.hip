@@ -20,9 +20,8 @@
 
 namespace hf {
 
-constexpr int KT = 256;        // threads per block
-constexpr int KR = 4;          // rows per thread
-constexpr int KTILE = 8;       // basis vectors per tile
+constexpr int KT = 256;        // threads per block of the vector kernels
+constexpr int KTILE = 8;       // basis vectors per tile of the Gram-Schmidt passes
 
 __device__ inline double kwave_sum(double v) {
 #pragma unroll
@@ -36,26 +35,27 @@ __device__ inline bool inst_on(const KrylovDev &kd, int b) {
 
 // partial[c*(k+1) + i] = chunk sum of V_i w (i < k); partial[c*(k+1) + k] = chunk sum of w^2.
 // With gate != nullptr the chunk only works when gate[inst] != 0.
-template <typename T>
-__global__ __launch_bounds__(KT) void k_sproj(KrylovDev kd, const T *__restrict__ V, int64_t ldv,
+template <typename T, int RR>
+__global__ __launch_bounds__(kChunkRows / RR) void k_sproj(KrylovDev kd, const T *__restrict__ V, int64_t ldv,
                                               int k, const T *__restrict__ w,
                                               const int *__restrict__ gate,
                                               double *__restrict__ partial) {
-  __shared__ double wsum[kMaxKrylov + 1][KT / 64];
+  constexpr int NTH = kChunkRows / RR;
+  __shared__ double wsum[kMaxKrylov + 1][NTH / 64];
   const int c = blockIdx.x, tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int b = kd.c_inst[c];
   double *out = partial + (int64_t)c * (k + 1);
   if (!inst_on(kd, b) || (gate && !gate[b])) {
-    for (int i = tid; i <= k; i += KT) out[i] = 0.0;
+    for (int i = tid; i <= k; i += NTH) out[i] = 0.0;
     return;
   }
   const int64_t row0 = kd.c_row0[c];
   const int len = kd.c_len[c];
-  double wr[KR];
+  double wr[RR];
   double nn = 0.0;
 #pragma unroll
-  for (int s = 0; s < KR; ++s) {
-    const int rr = tid + s * KT;
+  for (int s = 0; s < RR; ++s) {
+    const int rr = tid + s * NTH;
     wr[s] = rr < len ? (double)w[row0 + rr] : 0.0;
     nn += wr[s] * wr[s];
   }
@@ -64,8 +64,8 @@ __global__ __launch_bounds__(KT) void k_sproj(KrylovDev kd, const T *__restrict_
 #pragma unroll
     for (int q = 0; q < KTILE; ++q) acc[q] = 0.0;
 #pragma unroll
-    for (int s = 0; s < KR; ++s) {
-      const int rr = tid + s * KT;
+    for (int s = 0; s < RR; ++s) {
+      const int rr = tid + s * NTH;
       if (rr < len) {
 #pragma unroll
         for (int q = 0; q < KTILE; ++q)
@@ -81,41 +81,42 @@ __global__ __launch_bounds__(KT) void k_sproj(KrylovDev kd, const T *__restrict_
   nn = kwave_sum(nn);
   if (lane == 0) wsum[k][wv] = nn;
   __syncthreads();
-  for (int i = tid; i <= k; i += KT) {
+  for (int i = tid; i <= k; i += NTH) {
     double s2 = 0.0;
-    for (int q = 0; q < KT / 64; ++q) s2 += wsum[i][q];
+    for (int q = 0; q < NTH / 64; ++q) s2 += wsum[i][q];
     out[i] = s2;
   }
 }
 
 // w -= V h_b (h_b = h + b*hstride); partial[c] = chunk sum of the new w^2.
-template <typename T>
-__global__ __launch_bounds__(KT) void k_supdate(KrylovDev kd, const T *__restrict__ V, int64_t ldv,
+template <typename T, int RR>
+__global__ __launch_bounds__(kChunkRows / RR) void k_supdate(KrylovDev kd, const T *__restrict__ V, int64_t ldv,
                                                 int k, const double *__restrict__ h, int hstride,
                                                 T *__restrict__ w, const int *__restrict__ gate,
                                                 double *__restrict__ partial) {
+  constexpr int NTH = kChunkRows / RR;
   __shared__ double sh[kMaxKrylov];
-  __shared__ double wsum[KT / 64];
+  __shared__ double wsum[NTH / 64];
   const int c = blockIdx.x, tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int b = kd.c_inst[c];
   if (!inst_on(kd, b) || (gate && !gate[b])) {
     if (tid == 0) partial[c] = 0.0;
     return;
   }
-  for (int i = tid; i < k; i += KT) sh[i] = h[(int64_t)b * hstride + i];
+  for (int i = tid; i < k; i += NTH) sh[i] = h[(int64_t)b * hstride + i];
   __syncthreads();
   const int64_t row0 = kd.c_row0[c];
   const int len = kd.c_len[c];
-  double acc[KR];
+  double acc[RR];
 #pragma unroll
-  for (int s = 0; s < KR; ++s) {
-    const int rr = tid + s * KT;
+  for (int s = 0; s < RR; ++s) {
+    const int rr = tid + s * NTH;
     acc[s] = rr < len ? (double)w[row0 + rr] : 0.0;
   }
   for (int i0 = 0; i0 < k; i0 += KTILE) {
 #pragma unroll
-    for (int s = 0; s < KR; ++s) {
-      const int rr = tid + s * KT;
+    for (int s = 0; s < RR; ++s) {
+      const int rr = tid + s * NTH;
       if (rr < len) {
 #pragma unroll
         for (int q = 0; q < KTILE; ++q)
@@ -125,8 +126,8 @@ __global__ __launch_bounds__(KT) void k_supdate(KrylovDev kd, const T *__restric
   }
   double nn = 0.0;
 #pragma unroll
-  for (int s = 0; s < KR; ++s) {
-    const int rr = tid + s * KT;
+  for (int s = 0; s < RR; ++s) {
+    const int rr = tid + s * NTH;
     if (rr < len) {
       const T v = (T)acc[s];
       w[row0 + rr] = v;
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(KT) void k_supdate(KrylovDev kd, const T *__restric
   __syncthreads();
   if (tid == 0) {
     double s2 = 0.0;
-    for (int q = 0; q < KT / 64; ++q) s2 += wsum[q];
+    for (int q = 0; q < NTH / 64; ++q) s2 += wsum[q];
     partial[c] = s2;
   }
 }
@@ -244,58 +245,74 @@ __global__ __launch_bounds__(KT) void k_szero(KrylovDev kd, T *__restrict__ x, i
 
 // Re-orthogonalisation test (Daniel-Gragg-Kaufman-Stewart): flag[b] = 1 when
 // ||w1|| < ||w|| / sqrt(2).  n0 = ||w||^2 (stride n0s), n1 = ||w1||^2.
+// policy 0: the test; 1: always (every iterating instance); 2: never
 __global__ void k_reorth_flag(KrylovDev kd, const double *__restrict__ n0, int n0s,
-                              const double *__restrict__ n1, int *__restrict__ flag) {
+                              const double *__restrict__ n1, int policy, int *__restrict__ flag) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= kd.n_inst) return;
-  flag[b] = inst_on(kd, b) && (n1[b] < 0.5 * n0[(int64_t)b * n0s]) ? 1 : 0;
+  const bool test = policy == 1 || (policy == 0 && n1[b] < 0.5 * n0[(int64_t)b * n0s]);
+  flag[b] = inst_on(kd, b) && test ? 1 : 0;
 }
 
 // Arnoldi step j of every iterating instance: column j of H from the two
 // Gram-Schmidt passes, previous rotations, the new rotation, the residual
 // estimate; stop the cycle of an instance when the estimate reaches
 // rtol * bnorm, on breakdown, or at its iteration cap.
-__global__ void k_arnoldi(KrylovDev kd, int j, int m, const double *__restrict__ s1, int s1s,
-                          const double *__restrict__ s2, int s2s, const int *__restrict__ reorth,
-                          const double *__restrict__ n1, const double *__restrict__ n2,
-                          double rtol, double *__restrict__ scale) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= kd.n_inst) return;
-  if (!inst_on(kd, b)) {
-    scale[b] = 0.0;
+// One wavefront per instance: the lanes gather column j of H (both passes)
+// and the previous rotations into LDS, lane 0 applies the rotations in
+// sequence (the column entry being rotated stays in a register), and the
+// lanes write the column back.
+__global__ __launch_bounds__(64) void k_arnoldi(KrylovDev kd, int j, int m,
+                                                const double *__restrict__ s1, int s1s,
+                                                const double *__restrict__ s2, int s2s,
+                                                const int *__restrict__ reorth,
+                                                const double *__restrict__ n1,
+                                                const double *__restrict__ n2, double rtol,
+                                                double *__restrict__ scale) {
+  __shared__ double col[kMaxKrylov + 1], c_s[kMaxKrylov], s_s[kMaxKrylov];
+  const int b = blockIdx.x, lane = threadIdx.x;
+  if (!inst_on(kd, b)) {  // uniform over the block
+    if (lane == 0) scale[b] = 0.0;
     return;
   }
   double *H = kd.H + (int64_t)b * (m + 1) * m;
   double *cs = kd.cs + (int64_t)b * m, *sn = kd.sn + (int64_t)b * m, *g = kd.g + (int64_t)b * (m + 1);
   const bool ro = reorth[b] != 0;
-  for (int i = 0; i <= j; ++i)
-    H[i * m + j] = s1[(int64_t)b * s1s + i] + (ro ? s2[(int64_t)b * s2s + i] : 0.0);
-  const double hn = sqrt(ro ? n2[b] : n1[b]);
-  H[(j + 1) * m + j] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
-    H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
-    H[i * m + j] = t;
+  for (int i = lane; i <= j; i += 64)
+    col[i] = s1[(int64_t)b * s1s + i] + (ro ? s2[(int64_t)b * s2s + i] : 0.0);
+  for (int i = lane; i < j; i += 64) {
+    c_s[i] = cs[i];
+    s_s[i] = sn[i];
   }
-  const double den = hypot(H[j * m + j], H[(j + 1) * m + j]);
-  if (den == 0.0) {
-    cs[j] = 1.0;
-    sn[j] = 0.0;
-  } else {
-    cs[j] = H[j * m + j] / den;
-    sn[j] = H[(j + 1) * m + j] / den;
+  __syncthreads();
+  if (lane == 0) {
+    const double hn = sqrt(ro ? n2[b] : n1[b]);
+    double a = col[0];
+    for (int i = 0; i < j; ++i) {
+      const double nx = col[i + 1];
+      col[i] = c_s[i] * a + s_s[i] * nx;
+      a = -s_s[i] * a + c_s[i] * nx;
+    }
+    const double den = hypot(a, hn);
+    const double c = den == 0.0 ? 1.0 : a / den;
+    const double sj = den == 0.0 ? 0.0 : hn / den;
+    cs[j] = c;
+    sn[j] = sj;
+    col[j] = c * a + sj * hn;
+    col[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sj * gj;
+    g[j] = c * gj;
+    const int its = kd.its[b] + 1;
+    kd.its[b] = its;
+    const bool fin = !isfinite(hn) || !isfinite(g[j + 1]);
+    if (fin) kd.status[b] = 2;
+    if (fabs(g[j + 1]) <= rtol * kd.bnorm[b] || hn == 0.0 || its >= kd.itmax[b] || j + 1 == m || fin)
+      kd.kconv[b] = j + 1;
+    scale[b] = hn > 0.0 ? 1.0 / hn : 0.0;
   }
-  H[j * m + j] = cs[j] * H[j * m + j] + sn[j] * H[(j + 1) * m + j];
-  H[(j + 1) * m + j] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  kd.its[b] += 1;
-  const bool fin = !isfinite(hn) || !isfinite(g[j + 1]);
-  if (fin) kd.status[b] = 2;
-  if (fabs(g[j + 1]) <= rtol * kd.bnorm[b] || hn == 0.0 || kd.its[b] >= kd.itmax[b] || j + 1 == m ||
-      fin)
-    kd.kconv[b] = j + 1;
-  scale[b] = hn > 0.0 ? 1.0 / hn : 0.0;
+  __syncthreads();
+  for (int i = lane; i <= j + 1; i += 64) H[i * m + j] = col[i];
 }
 
 // number of instances still iterating in this cycle -> *count
@@ -351,10 +368,27 @@ __global__ void k_cycle_start(KrylovDev kd, int m, const double *__restrict__ be
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+template <typename T, int RR>
+static void sproj_launch(const KrylovDev &kd, const T *V, int64_t ldv, int k, const T *w,
+                         const int *gate, double *partial, hipStream_t st) {
+  hipLaunchKernelGGL((k_sproj<T, RR>), dim3(kd.n_chunks), dim3(kChunkRows / RR), 0, st, kd, V, ldv, k,
+                     w, gate, partial);
+}
+template <typename T, int RR>
+static void supdate_launch(const KrylovDev &kd, const T *V, int64_t ldv, int k, const double *h,
+                           int hstride, T *w, const int *gate, double *partial, hipStream_t st) {
+  hipLaunchKernelGGL((k_supdate<T, RR>), dim3(kd.n_chunks), dim3(kChunkRows / RR), 0, st, kd, V, ldv,
+                     k, h, hstride, w, gate, partial);
+}
+
 template <typename T>
 hipError_t ks_proj(const KrylovDev &kd, const T *V, int64_t ldv, int k, const T *w,
                    const int *gate, double *partial, double *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sproj<T>, dim3(kd.n_chunks), dim3(KT), 0, st, kd, V, ldv, k, w, gate, partial);
+  switch (kd.ortho_var) {
+    case 1: sproj_launch<T, 8>(kd, V, ldv, k, w, gate, partial, st); break;
+    case 2: sproj_launch<T, 2>(kd, V, ldv, k, w, gate, partial, st); break;
+    default: sproj_launch<T, 4>(kd, V, ldv, k, w, gate, partial, st); break;
+  }
   hipLaunchKernelGGL(k_seg_reduce, dim3(kd.n_inst, k + 1), dim3(KT), 0, st, kd, partial, k + 1, out);
   return hipGetLastError();
 }
@@ -362,8 +396,11 @@ template <typename T>
 hipError_t ks_update(const KrylovDev &kd, const T *V, int64_t ldv, int k, const double *h,
                      int hstride, T *w, const int *gate, double *partial, double *out,
                      hipStream_t st) {
-  hipLaunchKernelGGL(k_supdate<T>, dim3(kd.n_chunks), dim3(KT), 0, st, kd, V, ldv, k, h, hstride, w,
-                     gate, partial);
+  switch (kd.ortho_var) {
+    case 1: supdate_launch<T, 8>(kd, V, ldv, k, h, hstride, w, gate, partial, st); break;
+    case 2: supdate_launch<T, 2>(kd, V, ldv, k, h, hstride, w, gate, partial, st); break;
+    default: supdate_launch<T, 4>(kd, V, ldv, k, h, hstride, w, gate, partial, st); break;
+  }
   hipLaunchKernelGGL(k_seg_reduce, dim3(kd.n_inst, 1), dim3(KT), 0, st, kd, partial, 1, out);
   return hipGetLastError();
 }
@@ -399,16 +436,17 @@ hipError_t ks_zero(const KrylovDev &kd, T *x, int only_solving, hipStream_t st) 
   hipLaunchKernelGGL(k_szero<T>, dim3(kd.n_chunks), dim3(KT), 0, st, kd, x, only_solving);
   return hipGetLastError();
 }
-hipError_t ks_reorth_flag(const KrylovDev &kd, const double *n0, int n0s, const double *n1, int *flag,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_reorth_flag, dim3((kd.n_inst + 63) / 64), dim3(64), 0, st, kd, n0, n0s, n1, flag);
+hipError_t ks_reorth_flag(const KrylovDev &kd, const double *n0, int n0s, const double *n1, int policy,
+                          int *flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_reorth_flag, dim3((kd.n_inst + 63) / 64), dim3(64), 0, st, kd, n0, n0s, n1, policy,
+                     flag);
   return hipGetLastError();
 }
 hipError_t ks_arnoldi(const KrylovDev &kd, int j, int m, const double *s1, int s1s, const double *s2,
                       int s2s, const int *reorth, const double *n1, const double *n2, double rtol,
                       double *scale, hipStream_t st) {
-  hipLaunchKernelGGL(k_arnoldi, dim3((kd.n_inst + 63) / 64), dim3(64), 0, st, kd, j, m, s1, s1s, s2,
-                     s2s, reorth, n1, n2, rtol, scale);
+  hipLaunchKernelGGL(k_arnoldi, dim3(kd.n_inst), dim3(64), 0, st, kd, j, m, s1, s1s, s2, s2s, reorth,
+                     n1, n2, rtol, scale);
   return hipGetLastError();
 }
 hipError_t ks_count_active(const KrylovDev &kd, int *count, hipStream_t st) {

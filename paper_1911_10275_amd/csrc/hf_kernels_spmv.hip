@@ -36,10 +36,13 @@ struct Vec16<float> {
   static constexpr int EL = 4;
 };
 
-template <typename T, int BU>
+// lanes per element row: the wide shape (variant 0) or half of it (variant 1)
+__host__ __device__ constexpr int wide_lanes(int BU) { return BU >= 24 ? 64 : (BU >= 12 ? 32 : 16); }
+
+template <typename T, int BU, int L_>
 struct SpmvShape {
   static constexpr int EL = Vec16<T>::EL;
-  static constexpr int L = BU >= 24 ? 64 : (BU >= 12 ? 32 : 16);
+  static constexpr int L = L_;
   static constexpr int LA = active_lanes(L, EL, BU);
   static constexpr int CH = LA * EL;
   static constexpr int RPC = CH / BU;  // columns advanced per step
@@ -70,13 +73,13 @@ struct RowMask {
   }
 };
 
-template <typename T, int BU, int NT, bool STRIPS>
+template <typename T, int BU, int LN, int NT, bool STRIPS>
 __global__ __launch_bounds__(NT) void k_bsr_spmv(
     int64_t ne, const int64_t *__restrict__ blk_ptr, const int32_t *__restrict__ blk_col,
     const T *__restrict__ A, const int64_t *__restrict__ sp_ptr,
     const int32_t *__restrict__ sp_pnode, const T *__restrict__ Bs, const T *__restrict__ x,
     const T *__restrict__ xp, T *__restrict__ y, RowMask mask) {
-  using S = SpmvShape<T, BU>;
+  using S = SpmvShape<T, BU, LN>;
   constexpr int L = S::L, EL = S::EL, LA = S::LA, CH = S::CH, RPC = S::RPC, G = NT / L;
   using V = typename Vec16<T>::type;
   __shared__ T xs[G][5 * BU];
@@ -157,18 +160,31 @@ __global__ __launch_bounds__(64) void k_prows(int64_t np, const int32_t *__restr
   if (lane == 0) yp[i] = (T)acc;
 }
 
+// element rows of the product with LN lanes per row
+template <typename T, int BU, int LN, bool STRIPS>
+static void rows_launch(int64_t ne, const int64_t *ptr, const int32_t *col, const T *A,
+                        const int64_t *sp_ptr, const int32_t *sp_pnode, const T *Bs, const T *x,
+                        const T *xp, T *y, const RowMask &me, hipStream_t st) {
+  constexpr int NT = 256, G = NT / LN;
+  hipLaunchKernelGGL((k_bsr_spmv<T, BU, LN, NT, STRIPS>), dim3((unsigned)((ne + G - 1) / G)), dim3(NT),
+                     0, st, ne, ptr, col, A, sp_ptr, sp_pnode, Bs, x, xp, y, me);
+}
+
 template <typename T, int BU>
 static void spmv_bu(const KParams &kp, const T *A, const T *Bs, const T *Cs, const T *D,
                     const T *x, T *y, const RowSel &sel, hipStream_t st) {
   const RowMask me{kp.einst, sel.solving, sel.kconv, sel.mode};
   const RowMask mp{kp.pinst, sel.solving, sel.kconv, sel.mode};
-  using S = SpmvShape<T, BU>;
-  constexpr int NT = 256, G = NT / S::L;
+  constexpr int LW = wide_lanes(BU);
   const int64_t ne = kp.s.ne;
-  if (ne)
-    hipLaunchKernelGGL((k_bsr_spmv<T, BU, NT, true>), dim3((unsigned)((ne + G - 1) / G)), dim3(NT), 0, st,
-                       ne, kp.m.blk_ptr, kp.m.blk_col, A, kp.m.sp_ptr, kp.m.sp_pnode, Bs, x,
-                       x + kp.s.n_u, y, me);
+  if (ne) {
+    if (kp.spmv_var == 1)
+      rows_launch<T, BU, LW / 2, true>(ne, kp.m.blk_ptr, kp.m.blk_col, A, kp.m.sp_ptr, kp.m.sp_pnode,
+                                       Bs, x, x + kp.s.n_u, y, me, st);
+    else
+      rows_launch<T, BU, LW, true>(ne, kp.m.blk_ptr, kp.m.blk_col, A, kp.m.sp_ptr, kp.m.sp_pnode, Bs,
+                                   x, x + kp.s.n_u, y, me, st);
+  }
   if (kp.s.n_p)
     hipLaunchKernelGGL((k_prows<T, BU>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp.s.n_p,
                        kp.pinst, kp.poff, kp.doff, kp.m.pc_ptr, kp.m.pc_ent, kp.m.sp_elem, Cs, D, x,
@@ -201,12 +217,16 @@ static void precond_bu(const KParams &kp, const T *inv, const T *Sinv, const T *
                        const int32_t *ident_col) {
   const RowMask me{kp.einst, sel.solving, sel.kconv, sel.mode};
   const RowMask mp{kp.pinst, sel.solving, sel.kconv, sel.mode};
-  using S = SpmvShape<T, BU>;
-  constexpr int NT = 256, G = NT / S::L;
+  constexpr int LW = wide_lanes(BU);
   const int64_t ne = kp.s.ne;
-  if (ne)
-    hipLaunchKernelGGL((k_bsr_spmv<T, BU, NT, false>), dim3((unsigned)((ne + G - 1) / G)), dim3(NT), 0, st,
-                       ne, ident_ptr, ident_col, inv, nullptr, nullptr, nullptr, r, nullptr, z, me);
+  if (ne) {
+    if (kp.prec_var == 1)
+      rows_launch<T, BU, LW / 2, false>(ne, ident_ptr, ident_col, inv, nullptr, nullptr, nullptr, r,
+                                        nullptr, z, me, st);
+    else
+      rows_launch<T, BU, LW, false>(ne, ident_ptr, ident_col, inv, nullptr, nullptr, nullptr, r,
+                                    nullptr, z, me, st);
+  }
   if (kp.s.n_p)
     hipLaunchKernelGGL((k_prows<T, BU>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp.s.n_p,
                        kp.pinst, kp.poff, kp.doff, nullptr, nullptr, nullptr, nullptr, Sinv, r,
