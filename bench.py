@@ -144,6 +144,9 @@ def counters_probe(prob):
     sz = ctx.sizes
     ctx.set_state(np.zeros(sz.n_u), np.full(sz.n_p, prob.material.sigma_c))
     ctx.assemble()
+    cache = os.path.join(ROOT, "paper_1911_10275_amd", "tuning_cache.txt")
+    if os.path.exists(cache):  # the schedule the benchmark chose (cache lookup, no timing)
+        ctx.autotune(level=-1, cache_path=cache)
     a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
@@ -152,8 +155,9 @@ def counters_probe(prob):
     for _ in range(5):
         ctx.apply_jacobian(x.data_ptr(), y.data_ptr())
     torch.cuda.synchronize()
+    print(f"counters probe done: copy 1 GiB, 5 products, N = {sz.n_total}, "
+          f"tuning {ctx.tuning().as_dict()}", file=sys.stderr)
     ctx.close()
-    print(f"counters probe done: copy 1 GiB, 5 products, N = {sz.n_total}", file=sys.stderr)
 
 
 def ensemble_block(K, gmres_m):
@@ -164,7 +168,9 @@ def ensemble_block(K, gmres_m):
     streams from two host threads.  One ensemble step = one Newton iteration
     (assemble, block-Jacobi, GMRES to 1e-10, update) of every instance, from
     the uniform-pressure predictor; K timed steps after one warm-up step and
-    a reset, in FP64 and in FP32-IR."""
+    a reset, in FP64 and in FP32-IR.  A linear solve that has not reached
+    1e-10 within 6,000 GMRES iterations counts as failed (reported; its
+    instance keeps its state and its step is not counted)."""
     import threading
     import numpy as np
     import torch
@@ -175,7 +181,8 @@ def ensemble_block(K, gmres_m):
     ctxs, starts, streams = [], [], []
     for ps in groups:
         stm = torch.cuda.Stream()
-        c = hf.context_for_problems(ps, device=0, stream=stm.cuda_stream, gmres_m=gmres_m)
+        c = hf.context_for_problems(ps, device=0, stream=stm.cuda_stream, gmres_m=gmres_m,
+                                    gmres_maxit=6000)
         for i, p in enumerate(ps):
             s = c.isizes[i]
             c.set_state(np.zeros(s.n_u), np.full(s.n_p, p.material.sigma_c),
@@ -214,7 +221,7 @@ def ensemble_block(K, gmres_m):
         ok = [n for n in flat if n.lin.status == 0]
         dof = sum(c.sizes.n_total for c in ctxs)
         gits = sum(n.lin.gmres_iters for n in flat)
-        res[name] = {"steps_per_s": K / dt, "instance_newton_steps_per_s": len(flat) / dt,
+        res[name] = {"steps_per_s": K / dt, "instance_newton_steps_per_s": len(ok) / dt,
                      "ms_per_step": 1e3 * dt / K, "gmres_iters_per_s": gits / dt,
                      "failed_solves": len(flat) - len(ok),
                      "max_true_relres_converged": max(n.lin.true_relres for n in ok)}
@@ -238,7 +245,7 @@ def main():
     ap.add_argument("--no-ir", action="store_true", help="skip the FP32-IR comparison")
     ap.add_argument("--gmres-m", type=int, default=60, help="GMRES restart length")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble")
-    ap.add_argument("--tune", type=int, default=0, choices=(-1, 0, 1),
+    ap.add_argument("--tune", type=int, default=1, choices=(-1, 0, 1),
                     help="autotune level before timing (-1: none); choices cached in "
                          "paper_1911_10275_amd/tuning_cache.txt")
     ap.add_argument("--ensemble-steps", type=int, default=3)

@@ -143,10 +143,19 @@ typedef struct {
   int prec_var;        /* the same for the block-Jacobi apply */
   int ortho_var;       /* rows per thread of the Gram-Schmidt passes:
                           0 = 4, 1 = 8, 2 = 2 (1024-row chunks) */
-  int reorth;          /* second classical Gram-Schmidt pass: 0 = when
-                          ||w1|| < ||w|| / sqrt(2) (default), 1 = always,
-                          2 = never in FP64 solves (the FP32 inner solves
-                          of GMRES-IR keep the test) */
+  int reorth;          /* orthogonalisation of the Krylov basis.
+                          CGS2 = classical Gram-Schmidt with a second pass
+                          when ||w1|| < ||w|| / sqrt(2); MGS1 = modified
+                          Gram-Schmidt in its single-reduction form (the
+                          projections on all basis vectors from one pass
+                          over the basis plus the basis' new Gram row, then
+                          one update pass).
+                          0 (default): CGS2; 1: classical Gram-Schmidt with
+                          the second pass always; 2: one classical pass in
+                          FP64 solves; 3: MGS1 in FP64 solves; 4: MGS1 in
+                          both precisions.  With 2 and 3 the FP32 inner
+                          solves of GMRES-IR use CGS2 (single-pass schemes
+                          lose orthogonality too fast in FP32). */
   int gmres_m;         /* restart length (0 = keep hf_options.gmres_m) */
   int reserved[3];
 } hf_tuning;
@@ -293,12 +302,14 @@ hf_status hf_set_tuning(hf_ctx *ctx, const hf_tuning *t);
    block-Jacobi apply and the Gram-Schmidt passes (HIP events, 10 launches
    each after warm-up) in the context's precision and keeps the fastest;
    level 1: then also times complete linear solves for restart lengths
-   {60, 120} x re-orthogonalisation {test, never} and keeps the fastest
+   {60, 120} x orthogonalisation {0, 3} and keeps the fastest
    whose solves all converge.  cache_path (nullable): a text file of
    "key choices" lines; the key names the GPU architecture, dim, order,
    sizes, instance count, precision and level.  A line with the context's
    key is applied without timing; otherwise the result is appended.
-   *out (nullable) receives the choice. */
+   level -1: apply the cached level-1 choice, else the level-0 one, else
+   keep the current choice; never times.  *out (nullable) receives the
+   choice. */
 hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path, hf_tuning *out);
 hf_status hf_reset_profile(hf_ctx *ctx);
 

@@ -412,8 +412,9 @@ class Context:
         self.opt.gmres_m = t.gmres_m
 
     def autotune(self, level=0, cache_path=None) -> Tuning:
-        """Pick kernel schedules (level 0) and restart length / re-orthogonalisation
-        (level 1) by timing them on the assembled system; see hf_autotune."""
+        """Pick kernel schedules (level 0) and restart length / orthogonalisation
+        (level 1) by timing them on the assembled system, or apply the cached
+        choice without timing (level -1); see hf_autotune."""
         t = Tuning()
         cp = None if cache_path is None else os.fsencode(cache_path)
         self._check(self.lib.hf_autotune(self.h, level, cp, C.byref(t)), "hf_autotune")

@@ -1061,7 +1061,7 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
   TRY(dalloc(ctx, &ctx->r64, N));
   TRY(dalloc(ctx, &ctx->t64, N));
   // reduction partials: chunks x (largest number of outputs of one reduction)
-  TRY(dalloc(ctx, &ctx->partial, (int64_t)kd.n_chunks * (kMaxKrylov + 1)));
+  TRY(dalloc(ctx, &ctx->partial, (int64_t)kd.n_chunks * (2 * kMaxKrylov + 1)));
   TRY(dalloc(ctx, &ctx->red, 4 * (int64_t)B));
   TRY(ensure_host(ctx, 4 * (size_t)B + 8, 4 * (size_t)B + 8, 8 * (size_t)B + 64));
   HIPCHK(hipMemsetAsync(ctx->xs, 0, N * sizeof(double), ctx->stream));
@@ -1277,6 +1277,7 @@ static hf_status ensure_ws(hf_ctx *ctx, KrylovWs<T> &ws) {
     dfree(ctx, &kd.cs);
     dfree(ctx, &kd.sn);
     dfree(ctx, &kd.g);
+    dfree(ctx, &kd.L);
     dfree(ctx, &ctx->k_s1);
     dfree(ctx, &ctx->k_s2);
     dfree(ctx, &ctx->k_y);
@@ -1284,7 +1285,8 @@ static hf_status ensure_ws(hf_ctx *ctx, KrylovWs<T> &ws) {
     TRY(dalloc(ctx, &kd.cs, (int64_t)B * m));
     TRY(dalloc(ctx, &kd.sn, (int64_t)B * m));
     TRY(dalloc(ctx, &kd.g, (int64_t)B * (m + 1)));
-    TRY(dalloc(ctx, &ctx->k_s1, (int64_t)B * (m + 2)));
+    TRY(dalloc(ctx, &kd.L, (int64_t)B * (m + 1) * (m + 1)));
+    TRY(dalloc(ctx, &ctx->k_s1, (int64_t)B * (2 * m + 2)));
     TRY(dalloc(ctx, &ctx->k_s2, (int64_t)B * (m + 2)));
     TRY(dalloc(ctx, &ctx->k_y, (int64_t)B * m));
     ctx->kd_m = m;
@@ -1351,11 +1353,30 @@ static hf_status arnoldi_step(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, 
   TRY(apply_M<T>(ctx, kp, op, ws.V + (int64_t)j * N, ws.z, rows(ctx, 2)));
   TRY(apply_J<T>(ctx, kp, op, ws.z, ws.w, rows(ctx, 2)));
   ProfScope ps(ctx, P_ORTHO);
+  // orthogonalisation scheme: single-pass modified Gram-Schmidt from one
+  // reduction, or classical Gram-Schmidt with a second pass by policy
+  // (0 when ||w1|| < ||w|| / sqrt(2), 1 always, 2 never).  Single-pass
+  // schemes lose orthogonality too fast in FP32: the inner solves of
+  // GMRES-IR keep the tested second pass unless MGS is asked for both.
+  const int r = ctx->tune.reorth;
+  const bool fp32 = sizeof(T) == 4;
+  const bool mgs = r == 4 || (r == 3 && !fp32);
+  const int pol = r == 1 ? 1 : (r == 2 && !fp32) ? 2 : 0;
+  if (mgs) {
+    // single-pass modified Gram-Schmidt from one reduction (inverse compact
+    // WY form): s = V^T w and the new Gram row in one pass over V, h from
+    // (I + L) h = s, one update pass w -= V h
+    HIPCHK(ks_proj2<T>(kd, ws.V, N, k, ws.w, ctx->partial, ctx->k_s1, ctx->stream));
+    HIPCHK(ks_icwy(kd, j, m, ctx->k_s1, kd.L, ctx->k_s2, m + 2, ctx->stream));
+    HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s2, m + 2, ws.w, nullptr, ctx->partial, ctx->k_n1,
+                        ctx->stream));
+    HIPCHK(ks_arnoldi(kd, j, m, ctx->k_s2, m + 2, ctx->k_s2, m + 2, nullptr, ctx->k_n1, ctx->k_n1, rtol,
+                      ctx->k_scale, ctx->stream));
+    HIPCHK(ks_scale<T>(kd, ws.w, ctx->k_scale, ws.V + (int64_t)(j + 1) * N, ctx->stream));
+    return HF_OK;
+  }
   HIPCHK(ks_proj<T>(kd, ws.V, N, k, ws.w, nullptr, ctx->partial, ctx->k_s1, ctx->stream));
   HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s1, ks, ws.w, nullptr, ctx->partial, ctx->k_n1, ctx->stream));
-  // single-pass Gram-Schmidt loses orthogonality too fast in FP32: the inner
-  // solves of GMRES-IR keep the re-orthogonalisation test
-  const int pol = (sizeof(T) == 4 && ctx->tune.reorth == 2) ? 0 : ctx->tune.reorth;
   HIPCHK(ks_reorth_flag(kd, ctx->k_s1 + k, ks, ctx->k_n1, pol, ctx->k_flag, ctx->stream));
   if (pol != 2) {
     HIPCHK(ks_proj<T>(kd, ws.V, N, k, ws.w, ctx->k_flag, ctx->partial, ctx->k_s2, ctx->stream));
@@ -2040,7 +2061,7 @@ extern "C" hf_status hf_get_tuning(hf_ctx *ctx, hf_tuning *out) {
 extern "C" hf_status hf_set_tuning(hf_ctx *ctx, const hf_tuning *t) {
   if (!ctx || !t) return HF_EINVAL;
   if (t->spmv_var < 0 || t->spmv_var > 1 || t->prec_var < 0 || t->prec_var > 1 || t->ortho_var < 0 ||
-      t->ortho_var > 2 || t->reorth < 0 || t->reorth > 2 || t->gmres_m < 0 || t->gmres_m > kMaxKrylov - 1)
+      t->ortho_var > 2 || t->reorth < 0 || t->reorth > 4 || t->gmres_m < 0 || t->gmres_m > kMaxKrylov - 1)
     return fail(ctx, HF_EINVAL, "tuning value out of range");
   release_all_graphs(ctx);  // the captured chunks hold the old schedule
   ctx->tune = *t;
@@ -2135,11 +2156,12 @@ hf_status tune_kernels(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, hf_tuning
 
 extern "C" hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path, hf_tuning *out) {
   TRY(check_ctx(ctx, 4));
-  if (level < 0 || level > 1) return fail(ctx, HF_EINVAL, "autotune level must be 0 or 1");
+  if (level < -1 || level > 1) return fail(ctx, HF_EINVAL, "autotune level must be -1, 0 or 1");
   HIPCHK(hipSetDevice(ctx->opt.device));
   ctx->ierr.clear();
-  const std::string key = tune_key(ctx, level);
-  if (cache_path) {
+  // cached choice for this key (level -1: the level-1 choice, else the level-0 one)
+  for (int lv = level < 0 ? 1 : level; lv >= (level < 0 ? 0 : level) && cache_path; --lv) {
+    const std::string key = tune_key(ctx, lv);
     std::ifstream in(cache_path);
     std::string line;
     while (std::getline(in, line)) {
@@ -2153,6 +2175,11 @@ extern "C" hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path,
       }
     }
   }
+  if (level < 0) {  // nothing cached: keep the current choice
+    if (out) TRY(hf_get_tuning(ctx, out));
+    return HF_OK;
+  }
+  const std::string key = tune_key(ctx, level);
   const int B = nI(ctx);
   const hf_tuning saved = ctx->tune;
   std::vector<int> on(B, 1);
@@ -2174,7 +2201,7 @@ extern "C" hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path,
     double best_s = 1e300;
     hf_tuning pick = best;
     const int ms[2] = {60, 120};
-    const int pols[2] = {0, 2};
+    const int pols[2] = {0, 3};
     for (int mi = 0; mi < 2; ++mi)
       for (int pi = 0; pi < 2; ++pi) {
         hf_tuning t = best;

@@ -132,6 +132,7 @@ struct KrylovDev {
   int *solving = nullptr, *kconv = nullptr, *its = nullptr, *status = nullptr, *nbasis = nullptr;
   int *itmax = nullptr;  // per-instance cap on the iterations of the current solve
   double *bnorm = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
+  double *L = nullptr;  // strictly lower Gram factor of the basis (single-pass MGS)
 };
 
 // rows a batched product works on: all (mode 0), the instances being solved
@@ -210,6 +211,15 @@ hipError_t ks_reorth_flag(const KrylovDev &kd, const double *n0, int n0s, const 
 hipError_t ks_arnoldi(const KrylovDev &kd, int j, int m, const double *s1, int s1s, const double *s2,
                       int s2s, const int *reorth, const double *n1, const double *n2, double rtol,
                       double *scale, hipStream_t st);
+// one-reduce projection for the single-pass modified Gram-Schmidt: out (per
+// instance, stride 2k-1) = V_{0..k-1}^T w, then V_{0..k-2}^T v_{k-1}
+template <typename T>
+hipError_t ks_proj2(const KrylovDev &kd, const T *V, int64_t ldv, int k, const T *w, double *partial,
+                    double *out, hipStream_t st);
+// h (stride hstride) = (I + L)^-1 s with row j of L taken from sv and stored
+// in Lmat ((m+1) x (m+1) per instance)
+hipError_t ks_icwy(const KrylovDev &kd, int j, int m, const double *sv, double *Lmat, double *h,
+                   int hstride, hipStream_t st);
 // out[b] = ||x_b||^2 for every instance (no gating)
 template <typename T>
 hipError_t ks_norms(const KrylovDev &kd, const T *x, double *partial, double *out, hipStream_t st);

@@ -22,11 +22,43 @@ namespace hf {
 
 constexpr int KT = 256;        // threads per block of the vector kernels
 constexpr int KTILE = 8;       // basis vectors per tile of the Gram-Schmidt passes
+constexpr int KTILE2 = 4;      // basis vectors per tile of the two-vector projection (registers)
 
 __device__ inline double kwave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
+}
+
+// Sums each of NV per-lane values over the 64 lanes of a wavefront by
+// recursive halving: at offsets 32, 16, ... a lane keeps half of its values
+// (chosen by its lane bit) and adds the partner's copy of that half; the last
+// offsets add single values.  Lane l ends with the total of value idx, idx
+// read from its high lane bits; the lanes whose low bits (below 64/NV) are
+// zero hold the NV totals.  NV - 1 + log2(64/NV) exchanges instead of
+// 6 NV; the order of the additions is fixed.
+template <int NV>
+__device__ inline double wave_multi_sum(double *v, int lane, int &idx) {
+  static_assert(NV == 8 || NV == 16, "tile of 8 or 16 values");
+  constexpr int LOGNV = NV == 8 ? 3 : 4;
+  idx = 0;
+#pragma unroll
+  for (int st = 0; st < LOGNV; ++st) {
+    const int o = 32 >> st;
+    const bool up = (lane & o) != 0;
+    const int h = NV >> (st + 1);
+#pragma unroll
+    for (int q = 0; q < h; ++q) {
+      const double mine = up ? v[q + h] : v[q];
+      const double other = up ? v[q] : v[q + h];
+      v[q] = mine + __shfl_xor(other, o, 64);
+    }
+    idx = 2 * idx + (up ? 1 : 0);
+  }
+  double t = v[0];
+#pragma unroll
+  for (int o = 32 >> LOGNV; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  return t;
 }
 
 __device__ inline bool inst_on(const KrylovDev &kd, int b) {
@@ -72,11 +104,9 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_sproj(KrylovDev kd, const T
           if (i0 + q < k) acc[q] += (double)V[(int64_t)(i0 + q) * ldv + row0 + rr] * wr[s];
       }
     }
-#pragma unroll
-    for (int q = 0; q < KTILE; ++q) {
-      const double v = kwave_sum(acc[q]);
-      if (lane == 0 && i0 + q < k) wsum[i0 + q][wv] = v;
-    }
+    int idx;
+    const double v = wave_multi_sum<KTILE>(acc, lane, idx);
+    if ((lane & (64 / KTILE - 1)) == 0 && i0 + idx < k) wsum[i0 + idx][wv] = v;
   }
   nn = kwave_sum(nn);
   if (lane == 0) wsum[k][wv] = nn;
@@ -142,6 +172,115 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_supdate(KrylovDev kd, const
     for (int q = 0; q < NTH / 64; ++q) s2 += wsum[q];
     partial[c] = s2;
   }
+}
+
+// One-reduce projection of the single-pass (inverse compact WY) modified
+// Gram-Schmidt: with k = j+1 basis vectors and v_j = V_{k-1},
+// partial[c*nout + i] = chunk sum of V_i w (i < k) and
+// partial[c*nout + k + l] = chunk sum of V_l v_j (l < k-1); nout = 2k - 1.
+template <typename T, int RR>
+__global__ __launch_bounds__(kChunkRows / RR) void k_sproj2(KrylovDev kd, const T *__restrict__ V,
+                                                            int64_t ldv, int k,
+                                                            const T *__restrict__ w,
+                                                            double *__restrict__ partial) {
+  constexpr int NTH = kChunkRows / RR;
+  __shared__ double wsum[2 * kMaxKrylov][NTH / 64];
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int b = kd.c_inst[c];
+  const int nout = 2 * k - 1;
+  double *out = partial + (int64_t)c * nout;
+  if (!inst_on(kd, b)) {
+    for (int i = tid; i < nout; i += NTH) out[i] = 0.0;
+    return;
+  }
+  const int64_t row0 = kd.c_row0[c];
+  const int len = kd.c_len[c];
+  const T *vj = V + (int64_t)(k - 1) * ldv;
+  double wr[RR], vr[RR];
+#pragma unroll
+  for (int s = 0; s < RR; ++s) {
+    const int rr = tid + s * NTH;
+    wr[s] = rr < len ? (double)w[row0 + rr] : 0.0;
+    vr[s] = rr < len ? (double)vj[row0 + rr] : 0.0;
+  }
+  for (int i0 = 0; i0 < k; i0 += KTILE2) {
+    double acc[2 * KTILE2];
+#pragma unroll
+    for (int q = 0; q < 2 * KTILE2; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int s = 0; s < RR; ++s) {
+      const int rr = tid + s * NTH;
+      if (rr < len) {
+#pragma unroll
+        for (int q = 0; q < KTILE2; ++q)
+          if (i0 + q < k) {
+            const double x = (double)V[(int64_t)(i0 + q) * ldv + row0 + rr];
+            acc[q] += x * wr[s];
+            acc[KTILE2 + q] += x * vr[s];
+          }
+      }
+    }
+    int idx;
+    const double v = wave_multi_sum<2 * KTILE2>(acc, lane, idx);
+    if ((lane & (64 / (2 * KTILE2) - 1)) == 0) {
+      const int i = i0 + (idx % KTILE2);
+      if (idx < KTILE2 && i < k) wsum[i][wv] = v;
+      if (idx >= KTILE2 && i < k - 1) wsum[k + i][wv] = v;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < nout; i += NTH) {
+    double s2 = 0.0;
+    for (int q = 0; q < NTH / 64; ++q) s2 += wsum[i][q];
+    out[i] = s2;
+  }
+}
+
+// Coefficients of the single-pass modified Gram-Schmidt from one reduction:
+// row j of the strictly lower Gram factor, L[j][l] = v_j . v_l (l < j), is
+// stored; h solves (I + L) h = s (s_i = v_i . w, i <= j) by forward
+// substitution, which reproduces the projections of the sequential
+// (modified) Gram-Schmidt.  One wavefront per iterating instance; for
+// j < 64 the factor is staged in LDS and eliminated column by column.
+constexpr int kIcwyLds = 64;
+__global__ __launch_bounds__(64) void k_icwy(KrylovDev kd, int j, int m, const double *__restrict__ sv,
+                                             double *__restrict__ Lmat, double *__restrict__ h,
+                                             int hstride) {
+  __shared__ double hs[kMaxKrylov];
+  __shared__ double Ls[kIcwyLds][kIcwyLds + 1];
+  const int b = blockIdx.x, lane = threadIdx.x;
+  if (!inst_on(kd, b)) return;  // uniform over the block
+  const int k = j + 1, nout = 2 * k - 1, ld = m + 1;
+  const double *sb = sv + (int64_t)b * nout;
+  double *Lb = Lmat + (int64_t)b * ld * ld;
+  for (int l = lane; l < j; l += 64) Lb[(int64_t)j * ld + l] = sb[k + l];
+  for (int i = lane; i <= j; i += 64) hs[i] = sb[i];
+  if (j < kIcwyLds) {
+    for (int t = lane; t < j * j; t += 64) {
+      const int i = t / j, l = t % j;
+      if (l < i) Ls[i][l] = Lb[(int64_t)i * ld + l];
+    }
+    for (int l = lane; l < j; l += 64) Ls[j][l] = sb[k + l];
+    __syncthreads();
+    for (int l = 0; l < j; ++l) {  // h_l is final: remove it from the rows below
+      const double hl = hs[l];
+      const int i = l + 1 + lane;
+      if (i <= j) hs[i] -= Ls[i][l] * hl;
+      __syncthreads();
+    }
+  } else {
+    __syncthreads();
+    for (int i = 0; i <= j; ++i) {
+      const double *Li = i == j ? sb + k : Lb + (int64_t)i * ld;  // row i of L (row j from sv)
+      double acc = 0.0;
+      for (int l = lane; l < i; l += 64) acc += Li[l] * hs[l];
+      acc = kwave_sum(acc);
+      if (lane == 0) hs[i] -= acc;  // lane 0 holds the wave total
+      __syncthreads();
+    }
+  }
+  double *hb = h + (int64_t)b * hstride;
+  for (int i = lane; i <= j; i += 64) hb[i] = hs[i];
 }
 
 // out[b*nout + i] = sum over the chunks of instance b of partial[c*nout + i]
@@ -277,7 +416,7 @@ __global__ __launch_bounds__(64) void k_arnoldi(KrylovDev kd, int j, int m,
   }
   double *H = kd.H + (int64_t)b * (m + 1) * m;
   double *cs = kd.cs + (int64_t)b * m, *sn = kd.sn + (int64_t)b * m, *g = kd.g + (int64_t)b * (m + 1);
-  const bool ro = reorth[b] != 0;
+  const bool ro = reorth && reorth[b] != 0;
   for (int i = lane; i <= j; i += 64)
     col[i] = s1[(int64_t)b * s1s + i] + (ro ? s2[(int64_t)b * s2s + i] : 0.0);
   for (int i = lane; i < j; i += 64) {
@@ -436,6 +575,34 @@ hipError_t ks_zero(const KrylovDev &kd, T *x, int only_solving, hipStream_t st) 
   hipLaunchKernelGGL(k_szero<T>, dim3(kd.n_chunks), dim3(KT), 0, st, kd, x, only_solving);
   return hipGetLastError();
 }
+template <typename T, int RR>
+static void sproj2_launch(const KrylovDev &kd, const T *V, int64_t ldv, int k, const T *w,
+                          double *partial, hipStream_t st) {
+  hipLaunchKernelGGL((k_sproj2<T, RR>), dim3(kd.n_chunks), dim3(kChunkRows / RR), 0, st, kd, V, ldv, k,
+                     w, partial);
+}
+template <typename T>
+hipError_t ks_proj2(const KrylovDev &kd, const T *V, int64_t ldv, int k, const T *w, double *partial,
+                    double *out, hipStream_t st) {
+  switch (kd.ortho_var) {
+    case 1: sproj2_launch<T, 8>(kd, V, ldv, k, w, partial, st); break;
+    case 2: sproj2_launch<T, 2>(kd, V, ldv, k, w, partial, st); break;
+    default: sproj2_launch<T, 4>(kd, V, ldv, k, w, partial, st); break;
+  }
+  hipLaunchKernelGGL(k_seg_reduce, dim3(kd.n_inst, 2 * k - 1), dim3(KT), 0, st, kd, partial, 2 * k - 1,
+                     out);
+  return hipGetLastError();
+}
+template hipError_t ks_proj2<double>(const KrylovDev &, const double *, int64_t, int, const double *,
+                                     double *, double *, hipStream_t);
+template hipError_t ks_proj2<float>(const KrylovDev &, const float *, int64_t, int, const float *,
+                                    double *, double *, hipStream_t);
+hipError_t ks_icwy(const KrylovDev &kd, int j, int m, const double *sv, double *Lmat, double *h,
+                   int hstride, hipStream_t st) {
+  hipLaunchKernelGGL(k_icwy, dim3(kd.n_inst), dim3(64), 0, st, kd, j, m, sv, Lmat, h, hstride);
+  return hipGetLastError();
+}
+
 hipError_t ks_reorth_flag(const KrylovDev &kd, const double *n0, int n0s, const double *n1, int policy,
                           int *flag, hipStream_t st) {
   hipLaunchKernelGGL(k_reorth_flag, dim3((kd.n_inst + 63) / 64), dim3(64), 0, st, kd, n0, n0s, n1, policy,

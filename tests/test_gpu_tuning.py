@@ -2,7 +2,7 @@
 
 Every schedule variant (lanes per row of the Jacobian product and of the
 block-Jacobi apply, rows per thread of the Gram-Schmidt passes) and every
-re-orthogonalisation policy must leave the converged Newton states within
+orthogonalisation scheme must leave the converged Newton states within
 the parity bar of the FP64 oracle (1e-8) with every solve at a true relative
 residual of 1e-10.  The autotuner must return valid choices, apply them, and
 read them back from its cache file without timing.
@@ -28,6 +28,8 @@ VARIANTS = [
     dict(spmv_var=1, prec_var=1, ortho_var=1, reorth=1),
     dict(spmv_var=0, prec_var=1, ortho_var=2, reorth=2),
     dict(spmv_var=1, prec_var=0, ortho_var=0, reorth=0, gmres_m=90),
+    dict(spmv_var=0, prec_var=0, ortho_var=0, reorth=4),
+    dict(spmv_var=1, prec_var=1, ortho_var=1, reorth=3, gmres_m=90),
 ]
 
 
@@ -76,7 +78,7 @@ def test_variants_match_oracle(name, vi, precision):
 def test_set_tuning_rejects_out_of_range():
     ctx = hf.context_for_problem(synth.kgd_small(6, 1))
     before = ctx.tuning().as_dict()
-    for bad in (dict(spmv_var=2), dict(ortho_var=3), dict(reorth=-1), dict(gmres_m=300)):
+    for bad in (dict(spmv_var=2), dict(ortho_var=3), dict(reorth=5), dict(reorth=-1), dict(gmres_m=300)):
         with pytest.raises(hf.HFError) as ei:
             ctx.set_tuning(**bad)
         assert ei.value.status == hf.HF_EINVAL
@@ -96,7 +98,7 @@ def test_autotune_and_cache(tmp_path, precision):
     ctx.assemble()
     t = ctx.autotune(level=1, cache_path=str(cache))
     assert t.spmv_var in (0, 1) and t.prec_var in (0, 1) and t.ortho_var in (0, 1, 2)
-    assert t.reorth in (0, 2) and t.gmres_m in (60, 120)
+    assert t.reorth in (0, 3) and t.gmres_m in (60, 120)
     assert ctx.tuning().as_dict() == t.as_dict()
     lines = cache.read_text().splitlines()
     assert len(lines) == 1 and lines[0].split()[1:] == [str(v) for v in t.as_dict().values()]
