@@ -181,13 +181,13 @@ def ensemble_block(K, gmres_m):
     ctxs, starts, streams = [], [], []
     for ps in groups:
         stm = torch.cuda.Stream()
-        c = hf.context_for_problems(ps, device=0, stream=stm.cuda_stream, gmres_m=gmres_m,
-                                    gmres_maxit=6000)
+        c = hf.context_for_problems(ps, device=0, stream=stm.cuda_stream, gmres_m=gmres_m)
         for i, p in enumerate(ps):
             s = c.isizes[i]
             c.set_state(np.zeros(s.n_u), np.full(s.n_p, p.material.sigma_c),
                         np.zeros((s.n_face, s.nq_face)), inst=i)
         c.initial_guess()
+        c.set_options(gmres_maxit=6000)
         starts.append([c.get_state(i) for i in range(len(ps))])
         ctxs.append(c)
         streams.append(stm)

@@ -96,6 +96,11 @@ typedef struct {
                           captured GMRES chunks are timed */
   int use_graphs;      /* 1: replay chunks of GMRES iterations from captured HIP
                           graphs (default 1) */
+  int mfma_inverse;    /* 1: in FP32-IR mode, FP32 inverses of 30 x 30 element
+                          blocks on the matrix cores (16 x 16 tile Schur
+                          scheme, falls back to FP64 Gauss-Jordan on a tile
+                          pivot failure); 0: FP64 Gauss-Jordan rounded to
+                          FP32 (default 1) */
   void *stream;        /* hipStream_t to run on; NULL: a stream the ctx creates */
 } hf_options;
 
@@ -165,6 +170,9 @@ typedef struct {
      hf_options.profile = 1; reset by hf_reset_profile */
   double ms_assemble, ms_blockinv, ms_spmv64, ms_spmv32, ms_precond, ms_ortho;
   int64_t n_assemble, n_blockinv, n_spmv64, n_spmv32, n_precond, n_ortho;
+  /* preconditioner builds with the matrix-core FP32 inverses, and those that
+     fell back to FP64 Gauss-Jordan (counted whatever hf_options.profile is) */
+  int64_t n_inv_mfma, n_inv_fallback;
 } hf_profile;
 
 /* Fill *opt with the defaults listed above. */
@@ -286,6 +294,13 @@ hf_status hf_get_block_rows(hf_ctx *ctx, int32_t inst, int64_t n_rows, const int
 hf_status hf_get_coupling(hf_ctx *ctx, int32_t inst, double *B, double *C, double *D);
 /* Increment dx = (du, dp) of an instance from the last solve. */
 hf_status hf_get_increment(hf_ctx *ctx, int32_t inst, double *du, double *dp);
+/* Element-block inverses of the block-Jacobi preconditioner after a solve:
+   n_rows*bs*bs row-major blocks of the elements given (instance numbering);
+   precision HF_FP64 = the FP64 inverses (in FP32-IR mode with the matrix-
+   core inverses these exist only for elements with coupling strips),
+   HF_FP32_IR = the FP32 inverses the inner solves use. */
+hf_status hf_get_block_inverse(hf_ctx *ctx, int32_t inst, int64_t n_rows, const int32_t *elems,
+                               int precision, double *out);
 /* y = J x on device context vectors (length n_total, all instances);
    precision HF_FP64 uses the
    FP64 matrix (double*), HF_FP32_IR the FP32 copy (float*) built by the

@@ -34,6 +34,7 @@ EXPORTS = [
     "hf_newton_step", "hf_newton_solve", "hf_end_load_step", "hf_initial_guess", "hf_get_residual",
     "hf_get_block_rows", "hf_get_coupling", "hf_get_increment", "hf_apply_jacobian",
     "hf_get_profile", "hf_reset_profile", "hf_get_tuning", "hf_set_tuning", "hf_autotune",
+    "hf_get_block_inverse",
 ]
 
 
@@ -42,7 +43,8 @@ class Options(C.Structure):
                 ("ir_maxit", C.c_int), ("newton_maxit", C.c_int), ("rtol", C.c_double),
                 ("rtol_inner", C.c_double), ("newton_tol", C.c_double), ("b_stab", C.c_double),
                 ("p_cutoff", C.c_double), ("cutoff_on", C.c_int), ("device", C.c_int),
-                ("profile", C.c_int), ("use_graphs", C.c_int), ("stream", C.c_void_p)]
+                ("profile", C.c_int), ("use_graphs", C.c_int), ("mfma_inverse", C.c_int),
+                ("stream", C.c_void_p)]
 
 
 class Material(C.Structure):
@@ -82,7 +84,8 @@ class Profile(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("ms_assemble", "ms_blockinv", "ms_spmv64", "ms_spmv32",
                                            "ms_precond", "ms_ortho")] + \
                [(n, C.c_int64) for n in ("n_assemble", "n_blockinv", "n_spmv64", "n_spmv32",
-                                          "n_precond", "n_ortho")]
+                                          "n_precond", "n_ortho", "n_inv_mfma",
+                                          "n_inv_fallback")]
 
 
 class HFError(RuntimeError):
@@ -145,6 +148,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hf_get_profile": (C.c_int, [vp, P(Profile)]),
         "hf_reset_profile": (C.c_int, [vp]),
         "hf_get_tuning": (C.c_int, [vp, P(Tuning)]),
+        "hf_get_block_inverse": (C.c_int, [vp, C.c_int32, C.c_int64, vp, C.c_int, vp]),
         "hf_set_tuning": (C.c_int, [vp, P(Tuning)]),
         "hf_autotune": (C.c_int, [vp, C.c_int, C.c_char_p, P(Tuning)]),
     }
@@ -375,6 +379,15 @@ class Context:
         self._check(self.lib.hf_get_coupling(self.h, inst, _ptr(B), _ptr(Cm), _ptr(D)),
                     "hf_get_coupling")
         return B, Cm, D
+
+    def block_inverse(self, elems, precision=HF_FP64, inst=0):
+        """Preconditioner inverses of the given element blocks (row-major)."""
+        s = self.isizes[inst]
+        e = _arr(elems, np.int32)
+        out = np.empty((len(e), s.block_size, s.block_size))
+        self._check(self.lib.hf_get_block_inverse(self.h, inst, len(e), _ptr(e), precision,
+                                                  _ptr(out)), "hf_get_block_inverse")
+        return out
 
     def increment(self, inst=0):
         s = self.isizes[inst]

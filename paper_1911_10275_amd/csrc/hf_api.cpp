@@ -396,6 +396,7 @@ extern "C" void hf_default_options(hf_options *o) {
   o->device = 0;
   o->profile = 0;
   o->use_graphs = 1;
+  o->mfma_inverse = 1;
   o->stream = nullptr;
 }
 
@@ -1551,9 +1552,35 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
     TRY(dalloc(ctx, &ctx->D32, ctx->doff[B]));
   }
   HIPCHK(hipMemsetAsync(ctx->flag, 0, B * sizeof(int), ctx->stream));
-  {
+  // GMRES-IR on 30 x 30 blocks: FP32 inverses on the matrix cores, FP64
+  // inverses only where the Schur pressure block needs them (elements with
+  // coupling strips); otherwise (and as the fallback) FP64 Gauss-Jordan for
+  // every block, rounded for the FP32 copy
+  const bool mfma = ir && s.bu == 30 && ctx->opt.mfma_inverse;
+  bool done = false;
+  if (mfma) {
+    {
+      ProfScope ps(ctx, P_INV);
+      HIPCHK(launch_blockinv32_mfma(kp, ctx->A, ctx->inv32, ctx->flag, ctx->stream));
+    }
+    HIPCHK(launch_blockinv(kp, ctx->A, ctx->inv, nullptr, ctx->m.strip_elems, s.n_se, ctx->flag,
+                           ctx->stream));
+    TRY(get_i_async(ctx, ctx->flag, B, 0));
+    TRY(sync(ctx));
+    bool tile_fail = false;
+    for (int b = 0; b < B; ++b) tile_fail = tile_fail || (ctx->hi[b] & 4);
+    ctx->prof.n_inv_mfma += 1;
+    if (!tile_fail) {
+      done = true;
+    } else {
+      ctx->prof.n_inv_fallback += 1;
+      HIPCHK(hipMemsetAsync(ctx->flag, 0, B * sizeof(int), ctx->stream));
+    }
+  }
+  if (!done) {
     ProfScope ps(ctx, P_INV);
-    HIPCHK(launch_blockinv(kp, ctx->A, ctx->inv, ir ? ctx->inv32 : nullptr, ctx->flag, ctx->stream));
+    HIPCHK(launch_blockinv(kp, ctx->A, ctx->inv, ir ? ctx->inv32 : nullptr, nullptr, s.ne, ctx->flag,
+                           ctx->stream));
   }
   HIPCHK(launch_schur(kp, ctx->inv, ctx->Bs, ctx->Cs, ctx->D, nullptr, ctx->T, ctx->S, ctx->Sinv,
                       ctx->Sinv32, ctx->flag, ctx->stream));
@@ -2227,6 +2254,35 @@ extern "C" hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path,
     std::ofstream o(cache_path, std::ios::app);
     o << key << " " << t.spmv_var << " " << t.prec_var << " " << t.ortho_var << " " << t.reorth << " "
       << t.gmres_m << "\n";
+  }
+  return HF_OK;
+}
+
+extern "C" hf_status hf_get_block_inverse(hf_ctx *ctx, int32_t inst, int64_t n_rows,
+                                          const int32_t *elems, int precision, double *out) {
+  TRY(check_ctx(ctx, 5));
+  TRY(check_inst(ctx, inst));
+  const InstHost &h = ctx->inst[inst];
+  const int BU = ctx->s.bu;
+  if (n_rows < 0 || (n_rows && (!elems || !out))) return fail(ctx, HF_EINVAL, "bad arguments");
+  if (precision == HF_FP32_IR && !ctx->inv32) return fail(ctx, HF_ESTATE, "no FP32 inverses: solve in FP32-IR mode first");
+  if (precision != HF_FP64 && precision != HF_FP32_IR) return fail(ctx, HF_EINVAL, "precision");
+  TRY(sync(ctx));
+  std::vector<double> b64(BU * BU);
+  std::vector<float> b32(BU * BU);
+  for (int64_t i = 0; i < n_rows; ++i) {
+    if (elems[i] < 0 || elems[i] >= h.ne) return fail(ctx, HF_EINVAL, "element out of range");
+    const int64_t e = ctx->eoff[inst] + elems[i];
+    double *o = out + i * BU * BU;
+    if (precision == HF_FP64) {
+      HIPCHK(hipMemcpy(b64.data(), ctx->inv + e * BU * BU, BU * BU * sizeof(double), hipMemcpyDeviceToHost));
+      for (int c = 0; c < BU; ++c)
+        for (int r = 0; r < BU; ++r) o[r * BU + c] = b64[c * BU + r];
+    } else {
+      HIPCHK(hipMemcpy(b32.data(), ctx->inv32 + e * BU * BU, BU * BU * sizeof(float), hipMemcpyDeviceToHost));
+      for (int c = 0; c < BU; ++c)
+        for (int r = 0; r < BU; ++r) o[r * BU + c] = b32[c * BU + r];
+    }
   }
   return HF_OK;
 }

@@ -155,9 +155,15 @@ hipError_t launch_wmax(const KParams &kp, const double *w, double *out, hipStrea
 hipError_t launch_fluid_volume(const KParams &kp, const double *u, double *partial, double *out,
                                hipStream_t st);
 hipError_t launch_fill(double v, double *x, int64_t n, hipStream_t st);
-// flag[b] |= 1 on a zero or non-finite pivot in an element block of instance b
+// FP64 Gauss-Jordan inverses (and their FP32 copies when inv32 != null) of
+// the diagonal blocks of the n elements in elist (all ne elements when elist
+// is null, n = ne); flag[b] |= 1 on a zero or non-finite pivot in instance b
 hipError_t launch_blockinv(const KParams &kp, const double *A, double *inv, float *inv32,
-                           int *flag, hipStream_t st);
+                           const int32_t *elist, int64_t n, int *flag, hipStream_t st);
+// FP32 inverses of every 30 x 30 block on the matrix cores; flag[b] |= 4 when
+// a tile pivot fails in instance b (the caller falls back to launch_blockinv)
+hipError_t launch_blockinv32_mfma(const KParams &kp, const double *A, float *inv32, int *flag,
+                                  hipStream_t st);
 // flag[b] |= 2 on a zero or non-finite pivot in the pressure block of instance b
 hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,
                         const double *Cs, const double *D, double *Z, double *T, double *S,

@@ -14,12 +14,13 @@ namespace hf {
 // with the column permutation the pivot order implies.
 // ---------------------------------------------------------------------------
 template <int BU>
-__global__ __launch_bounds__(64) void k_blockinv(int64_t ne, const int64_t *__restrict__ blk_ptr,
+__global__ __launch_bounds__(64) void k_blockinv(const int32_t *__restrict__ elist,
+                                                 const int64_t *__restrict__ blk_ptr,
                                                  const int32_t *__restrict__ einst,
                                                  const double *__restrict__ A,
                                                  double *__restrict__ inv,
                                                  float *__restrict__ inv32, int *flag) {
-  const int64_t e = blockIdx.x;
+  const int64_t e = elist ? elist[blockIdx.x] : blockIdx.x;
   const int lane = threadIdx.x;
   __shared__ double prow[BU];
   __shared__ int s_pk[BU];
@@ -80,15 +81,175 @@ __global__ __launch_bounds__(64) void k_blockinv(int64_t ne, const int64_t *__re
 }
 
 hipError_t launch_blockinv(const KParams &kp, const double *A, double *inv, float *inv32,
-                           int *flag, hipStream_t st) {
-  const int64_t ne = kp.s.ne;
-  if (!ne) return hipSuccess;
+                           const int32_t *elist, int64_t n, int *flag, hipStream_t st) {
+  if (!n) return hipSuccess;
+  const dim3 g((unsigned)n), b(64);
   switch (kp.s.bu) {
-    case 6: hipLaunchKernelGGL(k_blockinv<6>, dim3((unsigned)ne), dim3(64), 0, st, ne, kp.m.blk_ptr, kp.einst, A, inv, inv32, flag); break;
-    case 12: hipLaunchKernelGGL(k_blockinv<12>, dim3((unsigned)ne), dim3(64), 0, st, ne, kp.m.blk_ptr, kp.einst, A, inv, inv32, flag); break;
-    case 30: hipLaunchKernelGGL(k_blockinv<30>, dim3((unsigned)ne), dim3(64), 0, st, ne, kp.m.blk_ptr, kp.einst, A, inv, inv32, flag); break;
+    case 6: hipLaunchKernelGGL(k_blockinv<6>, g, b, 0, st, elist, kp.m.blk_ptr, kp.einst, A, inv, inv32, flag); break;
+    case 12: hipLaunchKernelGGL(k_blockinv<12>, g, b, 0, st, elist, kp.m.blk_ptr, kp.einst, A, inv, inv32, flag); break;
+    case 30: hipLaunchKernelGGL(k_blockinv<30>, g, b, 0, st, elist, kp.m.blk_ptr, kp.einst, A, inv, inv32, flag); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP32 inverses of the 30 x 30 element blocks on the matrix cores.  A block
+// is padded to 32 x 32 (identity in the padding) and split into 16 x 16
+// tiles [[A11, A12], [A21, A22]]:
+//   X = A11^-1, T = A21 X, S = A22 - T A12, Y = S^-1, U = X A12,
+//   inverse = [[X + U Y T, -U Y], [-Y T, Y]].
+// The two 16 x 16 inverses are Gauss-Jordan with partial pivoting inside the
+// tile; the six 16 x 16 x 16 products are v_mfma_f32_16x16x4f32 chains
+// (4 per product).  One wavefront per block, all tiles in LDS.  A zero or
+// non-finite pivot in a tile (possible even for an invertible block, since
+// pivoting does not cross tiles) sets flag bit 4 for the block's instance;
+// the caller then falls back to the FP64 Gauss-Jordan inverses.
+// ---------------------------------------------------------------------------
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// c += a b for 16 x 16 tiles in LDS (row-major, leading dimensions la, lb).
+// Operand layout of the 16x16x4 instruction: lane l supplies a[l%16][4q + l/16]
+// and b[4q + l/16][l%16]; the accumulator's register r of lane l is
+// c[4(l/16) + r][l%16].
+__device__ inline floatx4 mfma16(const float *a, int la, const float *b, int lb, floatx4 c, int lane) {
+  const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i * la + 4 * q + kq], b[(4 * q + kq) * lb + i], c, 0, 0, 0);
+  return c;
+}
+__device__ inline floatx4 tile_load(const float *t, int ld, int lane) {
+  const int j = lane & 15, i0 = 4 * (lane >> 4);
+  floatx4 v;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = t[(i0 + r) * ld + j];
+  return v;
+}
+__device__ inline void tile_store(float *t, int ld, floatx4 v, int lane) {
+  const int j = lane & 15, i0 = 4 * (lane >> 4);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) t[(i0 + r) * ld + j] = v[r];
+}
+
+// in-place Gauss-Jordan inverse of a 16 x 16 LDS tile with partial pivoting
+// (row swaps, undone on the columns at the end); false on a zero or
+// non-finite pivot (uniform over the wavefront)
+__device__ bool gj16(float *M, int ld, int *perm, int lane) {
+  for (int k = 0; k < 16; ++k) {
+    float v = -1.f;
+    int idx = 16;
+    if (lane >= k && lane < 16) {
+      const float a = fabsf(M[lane * ld + k]);
+      v = isnan(a) ? INFINITY : a;  // NaN is picked and reported
+      idx = lane;
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+      const float ov = __shfl_xor(v, off, 64);
+      const int oi = __shfl_xor(idx, off, 64);
+      if (ov > v || (ov == v && oi < idx)) {
+        v = ov;
+        idx = oi;
+      }
+    }
+    const int p = __shfl(idx, 0, 64);
+    const float piv = M[p * ld + k];
+    if (!(fabsf(piv) > 0.f) || !isfinite(piv)) return false;
+    if (p != k && lane < 16) {
+      const float t = M[k * ld + lane];
+      M[k * ld + lane] = M[p * ld + lane];
+      M[p * ld + lane] = t;
+    }
+    if (lane == 0) perm[k] = p;
+    __syncthreads();
+    const float pinv = 1.f / piv;
+    if (lane < 16) M[k * ld + lane] = lane == k ? pinv : M[k * ld + lane] * pinv;
+    __syncthreads();
+    float f[4], rk[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = lane + 64 * q, r = t >> 4, c = t & 15;
+      f[q] = M[r * ld + k];
+      rk[q] = M[k * ld + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = lane + 64 * q, r = t >> 4, c = t & 15;
+      if (r != k) M[r * ld + c] = c == k ? -f[q] * pinv : M[r * ld + c] - f[q] * rk[q];
+    }
+    __syncthreads();
+  }
+  for (int k = 15; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k && lane < 16) {
+      const float t = M[lane * ld + k];
+      M[lane * ld + k] = M[lane * ld + p];
+      M[lane * ld + p] = t;
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(64) void k_blockinv32_mfma(const int64_t *__restrict__ blk_ptr,
+                                                        const int32_t *__restrict__ einst,
+                                                        const double *__restrict__ A,
+                                                        float *__restrict__ inv32, int *flag) {
+  constexpr int BU = 30, LD = 33, LT = 17;
+  __shared__ float M[32 * LD];
+  __shared__ float T[16 * LT], W[16 * LT];
+  __shared__ int perm[16];
+  const int64_t e = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double *blk = A + blk_ptr[e] * BU * BU;
+  for (int t = lane; t < 32 * 32; t += 64) {
+    const int r = t & 31, c = t >> 5;
+    M[r * LD + c] = (r < BU && c < BU) ? (float)blk[c * BU + r] : (r == c ? 1.f : 0.f);
+  }
+  __syncthreads();
+  float *A11 = M, *A12 = M + 16, *A21 = M + 16 * LD, *A22 = M + 16 * LD + 16;
+  const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+  bool ok = gj16(A11, LD, perm, lane);  // X
+  if (ok) {
+    tile_store(T, LT, mfma16(A21, LD, A11, LD, zero, lane), lane);  // T = A21 X
+    __syncthreads();
+    const floatx4 s = tile_load(A22, LD, lane) - mfma16(T, LT, A12, LD, zero, lane);
+    __syncthreads();
+    tile_store(A22, LD, s, lane);  // S
+    __syncthreads();
+    ok = gj16(A22, LD, perm, lane);  // Y
+  }
+  if (!ok) {
+    if (lane == 0) atomicOr(flag + einst[e], 4);
+    return;
+  }
+  tile_store(W, LT, mfma16(A11, LD, A12, LD, zero, lane), lane);  // U = X A12
+  __syncthreads();
+  const floatx4 b12 = -mfma16(W, LT, A22, LD, zero, lane);  // -U Y
+  const floatx4 b21 = -mfma16(A22, LD, T, LT, zero, lane);  // -Y T
+  __syncthreads();
+  tile_store(A12, LD, b12, lane);
+  tile_store(A21, LD, b21, lane);
+  __syncthreads();
+  const floatx4 b11 = tile_load(A11, LD, lane) - mfma16(A12, LD, T, LT, zero, lane);  // X + U Y T
+  __syncthreads();
+  tile_store(A11, LD, b11, lane);
+  __syncthreads();
+  float *out = inv32 + e * BU * BU;
+  for (int t = lane; t < BU * BU; t += 64) {
+    const int r = t % BU, c = t / BU;
+    out[t] = M[r * LD + c];  // column-major, like the FP64 blocks
+  }
+}
+
+hipError_t launch_blockinv32_mfma(const KParams &kp, const double *A, float *inv32, int *flag,
+                                  hipStream_t st) {
+  if (kp.s.bu != 30) return hipErrorInvalidValue;
+  if (!kp.s.ne) return hipSuccess;
+  hipLaunchKernelGGL(k_blockinv32_mfma, dim3((unsigned)kp.s.ne), dim3(64), 0, st, kp.m.blk_ptr,
+                     kp.einst, A, inv32, flag);
   return hipGetLastError();
 }
 

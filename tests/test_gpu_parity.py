@@ -232,3 +232,40 @@ def test_failure_paths():
     ns = ctx.newton_solve()
     assert ns.converged
     ctx.close()
+
+
+def test_block_inverses_fp32_on_matrix_cores():
+    """FP32-IR on 30 x 30 blocks: the matrix-core inverses are FP32 inverses
+    of the FP64 blocks (|X - A^-1| <= 50 eps32 kappa(A) |A^-1| per block),
+    they are not the rounded FP64 inverses (a different computation), and
+    with mfma_inverse = 0 the FP32 blocks are exactly the rounded FP64
+    Gauss-Jordan inverses."""
+    prob = SMALL["3d_p2_n3"]()
+    case, ctx = _pair(prob)
+    u, p, wo = _random_state(case, 8)
+    E = np.arange(case.mesh.ne, dtype=np.int32)
+    out = {}
+    for mf in (1, 0):
+        ctx.set_options(precision=hf.HF_FP32_IR, mfma_inverse=mf)
+        ctx.reset_profile()
+        ctx.set_state(u, p, wo)
+        ctx.assemble()
+        st = ctx.solve()
+        assert st.status == hf.HF_OK and st.true_relres <= 1e-10
+        prof = ctx.profile()
+        assert prof.n_inv_mfma == mf and prof.n_inv_fallback == 0
+        out[mf] = ctx.block_inverse(E, hf.HF_FP32_IR)
+    _, blocks = ctx.block_rows(E)
+    ctx.set_options(precision=hf.HF_FP64)
+    ctx.solve()
+    inv64 = ctx.block_inverse(E, hf.HF_FP64)
+    eps32 = np.finfo(np.float32).eps
+    for k in range(len(E)):
+        A = blocks[k, 0]
+        Ainv = np.linalg.inv(A)
+        kappa = np.linalg.cond(A)
+        err = np.abs(out[1][k] - Ainv).max() / np.abs(Ainv).max()
+        assert err <= 50 * eps32 * kappa, (k, err, kappa)
+        np.testing.assert_array_equal(out[0][k], inv64[k].astype(np.float32).astype(np.float64))
+    assert not np.array_equal(out[1], out[0])
+    ctx.close()
