@@ -155,6 +155,10 @@ def counters_probe(prob):
     for _ in range(5):
         ctx.apply_jacobian(x.data_ptr(), y.data_ptr())
     torch.cuda.synchronize()
+    # one FP32-IR preconditioner build (the solve stops after one iteration)
+    ctx.set_options(precision=hf.HF_FP32_IR, gmres_maxit=1)
+    ctx.solve(check=False)
+    torch.cuda.synchronize()
     print(f"counters probe done: copy 1 GiB, 5 products, N = {sz.n_total}, "
           f"tuning {ctx.tuning().as_dict()}", file=sys.stderr)
     ctx.close()
@@ -252,7 +256,8 @@ def main():
     ap.add_argument("--ensemble-m", type=int, default=120, help="GMRES restart length, ensemble")
     ap.add_argument("--counters", action="store_true",
                     help="hardware-counter probe: 5 FP64 Jacobian products of the workload and "
-                         "one 1 GiB device copy (calibration), nothing else")
+                         "one 1 GiB device copy (calibration), then one FP32-IR preconditioner "
+                         "build (matrix-core block inverses), nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
