@@ -82,10 +82,12 @@ typedef struct {
                           FP32 block inverses, FP64 residual and update */
   int gmres_m;         /* restart length, 1..256 (default 60) */
   int gmres_maxit;     /* GMRES iterations per linear solve (default 20000) */
-  int ir_maxit;        /* refinement steps per linear solve (default 100) */
+  int ir_maxit;        /* refinement steps per linear solve (default 1000) */
   int newton_maxit;    /* iterations of hf_newton_solve (default 25) */
   double rtol;         /* true relative residual of every solve (1e-10) */
-  double rtol_inner;   /* FP32 inner GMRES reduction per refinement (1e-2) */
+  double rtol_inner;   /* FP32-IR: a refinement step's inner GMRES stops once its
+                          residual estimate has fallen by this factor, or
+                          where the outer rtol is met (default 1e-4) */
   double newton_tol;   /* ||dU|| <= tol ||U|| and ||dP|| <= tol ||P|| (1e-10) */
   double b_stab;       /* DG stabilisation parameter b (default 10) */
   double p_cutoff;     /* pressure cut-off value when cutoff_on != 0 */
@@ -101,6 +103,16 @@ typedef struct {
                           scheme, falls back to FP64 Gauss-Jordan on a tile
                           pivot failure); 0: FP64 Gauss-Jordan rounded to
                           FP32 (default 1) */
+  int ir_inner_cycles; /* FP32-IR: GMRES(m) cycles per refinement step, >= 1
+                          (default 1: the refinement steps are the restarts) */
+  int incremental_assembly; /* 1: after the first full assembly, re-assemble
+                          only the row panels of elements that touch a
+                          cohesive or fluid interface, evaluate the other
+                          residual rows as the product with their (constant)
+                          cached blocks, and keep the constant blocks'
+                          inverses; a material or b_stab change triggers a
+                          full assembly (default 1); 0: full assembly and
+                          all inverses every time */
   void *stream;        /* hipStream_t to run on; NULL: a stream the ctx creates */
 } hf_options;
 
@@ -160,7 +172,9 @@ typedef struct {
                           FP64 solves; 3: MGS1 in FP64 solves; 4: MGS1 in
                           both precisions.  With 2 and 3 the FP32 inner
                           solves of GMRES-IR use CGS2 (single-pass schemes
-                          lose orthogonality too fast in FP32). */
+                          lose orthogonality faster in FP32).  hf_autotune
+                          level 1 chooses between 0 and 3 (FP64) or 0 and 4
+                          (FP32-IR). */
   int gmres_m;         /* restart length (0 = keep hf_options.gmres_m) */
   int reserved[3];
 } hf_tuning;

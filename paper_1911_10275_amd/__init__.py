@@ -44,6 +44,7 @@ class Options(C.Structure):
                 ("rtol_inner", C.c_double), ("newton_tol", C.c_double), ("b_stab", C.c_double),
                 ("p_cutoff", C.c_double), ("cutoff_on", C.c_int), ("device", C.c_int),
                 ("profile", C.c_int), ("use_graphs", C.c_int), ("mfma_inverse", C.c_int),
+                ("ir_inner_cycles", C.c_int), ("incremental_assembly", C.c_int),
                 ("stream", C.c_void_p)]
 
 

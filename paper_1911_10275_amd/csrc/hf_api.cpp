@@ -118,6 +118,15 @@ struct hf_ctx {
   bool hu_pending = false;  // an upload from hu may still be in flight
   bool capturing = false;   // a GMRES chunk is being captured into a graph
   hf_tuning tune{};         // kernel schedules and solver choices
+  // cached linear operator: the row panels of elements with no cohesive or
+  // fluid interface are constant while the mesh, interfaces, materials and
+  // b_stab are; lin_epoch counts full assemblies, the *_epoch fields record
+  // for which one the constant blocks' inverses / FP32 copies were computed
+  int32_t *crack_elems = nullptr;  // elements with a cohesive or fluid interface
+  int64_t n_crack = 0;
+  bool lin_valid = false;
+  double lin_bstab = 0.0;
+  int64_t lin_epoch = 0, inv64_epoch = -1, inv32_epoch = -1, a32_epoch = -1;
   std::vector<std::string> ierr;  // message of each instance's failure in the current call
   // profile
   std::vector<hipEvent_t> evpool;
@@ -385,10 +394,11 @@ extern "C" void hf_default_options(hf_options *o) {
   o->precision = HF_FP64;
   o->gmres_m = 60;
   o->gmres_maxit = 20000;
-  o->ir_maxit = 100;
+  o->ir_maxit = 1000;
   o->newton_maxit = 25;
   o->rtol = 1e-10;
-  o->rtol_inner = 1e-2;
+  o->rtol_inner = 1e-4;
+  o->ir_inner_cycles = 1;
   o->newton_tol = 1e-10;
   o->b_stab = 10.0;
   o->p_cutoff = 0.0;
@@ -397,6 +407,7 @@ extern "C" void hf_default_options(hf_options *o) {
   o->profile = 0;
   o->use_graphs = 1;
   o->mfma_inverse = 1;
+  o->incremental_assembly = 1;
   o->stream = nullptr;
 }
 
@@ -404,7 +415,7 @@ static hf_status validate_options(hf_ctx *ctx, const hf_options &o) {
   if (o.precision != HF_FP64 && o.precision != HF_FP32_IR)
     return fail(ctx, HF_EINVAL, "precision must be HF_FP64 or HF_FP32_IR");
   if (o.gmres_m < 1 || o.gmres_m > kMaxKrylov - 1) return fail(ctx, HF_EINVAL, "gmres_m out of range 1..256");
-  if (o.gmres_maxit < 1 || o.ir_maxit < 1 || o.newton_maxit < 1)
+  if (o.gmres_maxit < 1 || o.ir_maxit < 1 || o.newton_maxit < 1 || o.ir_inner_cycles < 1)
     return fail(ctx, HF_EINVAL, "iteration caps must be positive");
   if (!(o.rtol > 0 && o.rtol < 1) || !(o.rtol_inner > 0 && o.rtol_inner < 1) || !(o.newton_tol > 0))
     return fail(ctx, HF_EINVAL, "tolerances must lie in (0, 1)");
@@ -705,6 +716,7 @@ extern "C" hf_status hf_set_material(hf_ctx *ctx, int32_t inst, const hf_materia
   m.dt = mat->dt;
   m.set = true;
   if (ctx->stage >= 2) {  // a later load step may change the material (same layout)
+    ctx->lin_valid = false;  // the cached linear blocks depend on it
     const double s_p = ctx->ipar[inst].s_p;
     inst_par(m, ctx->ipar[inst]);
     ctx->ipar[inst].s_p = s_p;
@@ -860,6 +872,17 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
     pinst.insert(pinst.end(), (size_t)h.n_p, b);
   }
   s.n_src = (int64_t)src_node.size();
+  std::vector<int32_t> crack;
+  {
+    std::vector<uint8_t> mark(s.ne, 0);
+    for (int64_t f = 0; f < s.nf; ++f) {
+      bool c = beta[f] != 0;
+      for (int q = 0; q < NQ && !c; ++q) c = qp_state[f * NQ + q] != 0;
+      if (c) mark[face_em[f]] = mark[face_ep[f]] = 1;
+    }
+    for (int64_t e = 0; e < s.ne; ++e)
+      if (mark[e]) crack.push_back((int32_t)e);
+  }
 
   // ---- coupling strips: per element, the pressure nodes of its fluid faces --
   std::vector<int64_t> sp_ptr(s.ne + 1, 0);
@@ -1001,6 +1024,8 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
   TRY(upload(ctx, &m.t_ptr, t_ptr));
   TRY(upload(ctx, &m.ident_ptr, ident_ptr));
   TRY(upload(ctx, &m.ident_col, ident_col));
+  TRY(upload(ctx, &ctx->crack_elems, crack));
+  ctx->n_crack = (int64_t)crack.size();
   TRY(upload(ctx, &ctx->d_ipar, ctx->ipar));
   TRY(upload(ctx, &ctx->d_einst, einst));
   TRY(upload(ctx, &ctx->d_pinst, pinst));
@@ -1029,6 +1054,7 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
   TRY(dalloc(ctx, &kd.status, B));
   TRY(dalloc(ctx, &kd.nbasis, B));
   TRY(dalloc(ctx, &kd.itmax, B));
+  TRY(dalloc(ctx, &kd.rtol, B));
   TRY(dalloc(ctx, &kd.bnorm, B));
   TRY(dalloc(ctx, &ctx->k_n1, B));
   TRY(dalloc(ctx, &ctx->k_n2, B));
@@ -1231,10 +1257,24 @@ static hf_status do_assemble(hf_ctx *ctx, std::vector<double> &rn) {
   const Sizes &s = ctx->s;
   KParams kp = kparams(ctx);
   HIPCHK(launch_set_rules(ctx->rules, ctx->stream));  // the rule tables are module-global
+  const bool incr = ctx->opt.incremental_assembly && ctx->lin_valid && ctx->lin_bstab == ctx->opt.b_stab;
   {
     ProfScope ps(ctx, P_ASM);
-    HIPCHK(launch_assemble(kp, ctx->xs, ctx->xs + s.n_u, ctx->w_old, ctx->A, ctx->R, ctx->Bs,
-                           ctx->Cs, ctx->D, ctx->stream));
+    if (incr) {
+      // the rows of elements without cohesive or fluid interfaces are linear
+      // in u with the cached blocks: R = A u for them (the other rows, the
+      // strips and the fluid rows are recomputed below)
+      HIPCHK(launch_spmv<double>(kp, ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->xs, ctx->R, RowSel{},
+                                 ctx->stream));
+      HIPCHK(launch_assemble(kp, ctx->xs, ctx->xs + s.n_u, ctx->w_old, ctx->A, ctx->R, ctx->Bs,
+                             ctx->Cs, ctx->D, ctx->crack_elems, ctx->n_crack, ctx->stream));
+    } else {
+      HIPCHK(launch_assemble(kp, ctx->xs, ctx->xs + s.n_u, ctx->w_old, ctx->A, ctx->R, ctx->Bs,
+                             ctx->Cs, ctx->D, nullptr, s.ne, ctx->stream));
+      ctx->lin_valid = true;
+      ctx->lin_bstab = ctx->opt.b_stab;
+      ctx->lin_epoch += 1;
+    }
   }
   HIPCHK(launch_seg_norms(ctx->kd, ctx->R, ctx->partial, ctx->red, ctx->stream));
   TRY(get_d(ctx, ctx->red, nI(ctx)));
@@ -1347,7 +1387,7 @@ static hf_status apply_M(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const
 // H and g; v_{j+1} = w / ||w||.
 template <typename T>
 static hf_status arnoldi_step(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, KrylovWs<T> &ws,
-                              int j, double rtol) {
+                              int j) {
   const int64_t N = ctx->s.N();
   const KrylovDev &kd = ctx->kd;
   const int m = ws.m, k = j + 1, ks = j + 2;
@@ -1371,7 +1411,7 @@ static hf_status arnoldi_step(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, 
     HIPCHK(ks_icwy(kd, j, m, ctx->k_s1, kd.L, ctx->k_s2, m + 2, ctx->stream));
     HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s2, m + 2, ws.w, nullptr, ctx->partial, ctx->k_n1,
                         ctx->stream));
-    HIPCHK(ks_arnoldi(kd, j, m, ctx->k_s2, m + 2, ctx->k_s2, m + 2, nullptr, ctx->k_n1, ctx->k_n1, rtol,
+    HIPCHK(ks_arnoldi(kd, j, m, ctx->k_s2, m + 2, ctx->k_s2, m + 2, nullptr, ctx->k_n1, ctx->k_n1,
                       ctx->k_scale, ctx->stream));
     HIPCHK(ks_scale<T>(kd, ws.w, ctx->k_scale, ws.V + (int64_t)(j + 1) * N, ctx->stream));
     return HF_OK;
@@ -1384,7 +1424,7 @@ static hf_status arnoldi_step(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, 
     HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s2, ks, ws.w, ctx->k_flag, ctx->partial, ctx->k_n2,
                         ctx->stream));
   }
-  HIPCHK(ks_arnoldi(kd, j, m, ctx->k_s1, ks, ctx->k_s2, ks, ctx->k_flag, ctx->k_n1, ctx->k_n2, rtol,
+  HIPCHK(ks_arnoldi(kd, j, m, ctx->k_s1, ks, ctx->k_s2, ks, ctx->k_flag, ctx->k_n1, ctx->k_n2,
                     ctx->k_scale, ctx->stream));
   HIPCHK(ks_scale<T>(kd, ws.w, ctx->k_scale, ws.V + (int64_t)(j + 1) * N, ctx->stream));
   return HF_OK;
@@ -1393,9 +1433,9 @@ static hf_status arnoldi_step(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, 
 // Arnoldi steps j0 .. j1-1, replayed from a captured graph when enabled
 template <typename T>
 static hf_status arnoldi_chunk(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, KrylovWs<T> &ws,
-                               int j0, int j1, double rtol) {
+                               int j0, int j1) {
   if (!ctx->opt.use_graphs) {
-    for (int j = j0; j < j1; ++j) TRY(arnoldi_step<T>(ctx, kp, op, ws, j, rtol));
+    for (int j = j0; j < j1; ++j) TRY(arnoldi_step<T>(ctx, kp, op, ws, j));
     return HF_OK;
   }
   const size_t gi = (size_t)(j0 / kIterChunk);
@@ -1404,7 +1444,7 @@ static hf_status arnoldi_chunk(hf_ctx *ctx, const KParams &kp, const Ops<T> &op,
     HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
     ctx->capturing = true;
     hf_status st = HF_OK;
-    for (int j = j0; j < j1 && st == HF_OK; ++j) st = arnoldi_step<T>(ctx, kp, op, ws, j, rtol);
+    for (int j = j0; j < j1 && st == HF_OK; ++j) st = arnoldi_step<T>(ctx, kp, op, ws, j);
     ctx->capturing = false;
     hipGraph_t g = nullptr;
     hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
@@ -1426,13 +1466,13 @@ static hf_status arnoldi_chunk(hf_ctx *ctx, const KParams &kp, const Ops<T> &op,
 // Right-preconditioned restarted GMRES(m) on J x = b in precision T for the
 // instances with on[b] = 1, all in the same launches.  x starts at 0.  A
 // cycle of an instance ends when its recursive residual estimate reaches
-// rtol ||b_b||, at its iteration cap cap[b], or after m steps.  With
+// rtol[b] ||b_b||, at its iteration cap cap[b], or after m steps.  With
 // explicit_check the residual b - J x is then recomputed and decides; without
 // it (the inner solve of GMRES-IR) the estimate decides.  out[b] receives the
 // iterations, cycles, relative residual and status of each solved instance.
 template <typename T>
 static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T *bvec, T *x,
-                         double rtol, bool explicit_check, std::vector<int> on,
+                         const std::vector<double> &rtol, bool explicit_check, std::vector<int> on,
                          const std::vector<int> &cap, std::vector<SolveOut> &out) {
   const KParams kp = kparams(ctx);
   const int64_t N = ctx->s.N();
@@ -1442,6 +1482,7 @@ static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T
   out.assign(B, SolveOut{});
   TRY(put(ctx, kd.solving, on));
   TRY(put(ctx, kd.itmax, cap));
+  TRY(put(ctx, kd.rtol, rtol));
   HIPCHK(ks_zero<T>(kd, x, 1, st));
   HIPCHK(ks_norms<T>(kd, bvec, ctx->partial, ctx->k_beta2, st));
   HIPCHK(ks_begin(kd, ctx->k_beta2, st));
@@ -1470,7 +1511,7 @@ static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T
         out[b].st = HF_ENONFINITE;
         note(ctx, b, "non-finite residual in GMRES");
         on[b] = 0;
-      } else if (explicit_check && beta <= rtol * bnorm[b]) {
+      } else if (explicit_check && beta <= rtol[b] * bnorm[b]) {
         on[b] = 0;
       } else if (out[b].iters >= cap[b]) {
         if (explicit_check) {
@@ -1488,7 +1529,7 @@ static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T
     HIPCHK(ks_scale<T>(kd, ws.r, ctx->k_scale, ws.V, st));
     for (int j0 = 0; j0 < m; j0 += kIterChunk) {
       const int j1 = std::min(j0 + kIterChunk, m);
-      TRY(arnoldi_chunk<T>(ctx, kp, op, ws, j0, j1, rtol));
+      TRY(arnoldi_chunk<T>(ctx, kp, op, ws, j0, j1));
       if (j1 == m) break;
       HIPCHK(ks_count_active(kd, ctx->k_count, st));
       TRY(get_i_async(ctx, ctx->k_count, 1, 0));
@@ -1500,16 +1541,31 @@ static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T
     HIPCHK(ks_combine<T>(kd, ws.V, N, ctx->k_y, m, ws.t, st));
     TRY(apply_M<T>(ctx, kp, op, ws.t, ws.z, rows(ctx, 1)));
     HIPCHK((ks_axpy<T, T>(kd, nullptr, ws.z, x, st)));
-    // true residual: restart vector and explicit check
-    TRY(apply_J<T>(ctx, kp, op, x, ws.w, rows(ctx, 1)));
-    HIPCHK(ks_sub<T>(kd, bvec, ws.w, ws.r, st));
-    HIPCHK(ks_norms<T>(kd, ws.r, ctx->partial, ctx->k_beta2, st));
+    // true residual: restart vector and explicit check.  Without the check
+    // (an inner solve) the residual is only needed by instances that go on
+    // to another cycle: when the estimates and caps end all of them, it is
+    // skipped.
+    bool need_r = explicit_check;
+    if (!explicit_check) {
+      TRY(get_i_async(ctx, kd.its, B, 0));
+      TRY(get_i_async(ctx, kd.status, B, B));
+      TRY(get_d(ctx, ctx->k_est, B));
+      for (int b = 0; b < B; ++b)
+        if (on[b] && ctx->hi[B + b] == 0 && !(ctx->hd[b] <= rtol[b] * bnorm[b] || ctx->hi[b] >= cap[b]))
+          need_r = true;
+    }
+    if (need_r) {
+      TRY(apply_J<T>(ctx, kp, op, x, ws.w, rows(ctx, 1)));
+      HIPCHK(ks_sub<T>(kd, bvec, ws.w, ws.r, st));
+      HIPCHK(ks_norms<T>(kd, ws.r, ctx->partial, ctx->k_beta2, st));
+    }
     TRY(get_i_async(ctx, kd.its, B, 0));
     TRY(get_i_async(ctx, kd.status, B, B));
     HIPCHK(hipMemcpyAsync(ctx->hd + B, ctx->k_est, B * sizeof(double), hipMemcpyDeviceToHost, st));
     TRY(get_d(ctx, ctx->k_beta2, B));
     for (int b = 0; b < B; ++b) {
-      beta2[b] = ctx->hd[b];
+      // without a new residual the previous one stays (it is not used again)
+      if (need_r) beta2[b] = ctx->hd[b];
       est[b] = ctx->hd[B + b];
       its[b] = ctx->hi[b];
       stat[b] = ctx->hi[B + b];
@@ -1522,7 +1578,7 @@ static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T
         out[b].st = HF_ENONFINITE;
         note(ctx, b, "non-finite Krylov vector");
         on[b] = 0;
-      } else if (!explicit_check && (est[b] <= rtol * bnorm[b] || its[b] >= cap[b])) {
+      } else if (!explicit_check && (est[b] <= rtol[b] * bnorm[b] || its[b] >= cap[b])) {
         out[b].relres = est[b] / bnorm[b];
         on[b] = 0;
       }
@@ -1557,11 +1613,17 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
   // coupling strips); otherwise (and as the fallback) FP64 Gauss-Jordan for
   // every block, rounded for the FP32 copy
   const bool mfma = ir && s.bu == 30 && ctx->opt.mfma_inverse;
+  // the constant blocks' inverses are kept from the last full assembly: only
+  // the elements with cohesive or fluid interfaces need new ones
+  const bool cached = ctx->lin_valid && ctx->opt.incremental_assembly;
+  const int32_t *el64 = (cached && ctx->inv64_epoch == ctx->lin_epoch) ? ctx->crack_elems : nullptr;
+  const int32_t *el32 = (cached && ctx->inv32_epoch == ctx->lin_epoch) ? ctx->crack_elems : nullptr;
   bool done = false;
   if (mfma) {
     {
       ProfScope ps(ctx, P_INV);
-      HIPCHK(launch_blockinv32_mfma(kp, ctx->A, ctx->inv32, ctx->flag, ctx->stream));
+      HIPCHK(launch_blockinv32_mfma(kp, ctx->A, ctx->inv32, el32, el32 ? ctx->n_crack : s.ne, ctx->flag,
+                                    ctx->stream));
     }
     HIPCHK(launch_blockinv(kp, ctx->A, ctx->inv, nullptr, ctx->m.strip_elems, s.n_se, ctx->flag,
                            ctx->stream));
@@ -1572,6 +1634,7 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
     ctx->prof.n_inv_mfma += 1;
     if (!tile_fail) {
       done = true;
+      ctx->inv32_epoch = ctx->lin_epoch;
     } else {
       ctx->prof.n_inv_fallback += 1;
       HIPCHK(hipMemsetAsync(ctx->flag, 0, B * sizeof(int), ctx->stream));
@@ -1579,13 +1642,22 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
   }
   if (!done) {
     ProfScope ps(ctx, P_INV);
-    HIPCHK(launch_blockinv(kp, ctx->A, ctx->inv, ir ? ctx->inv32 : nullptr, nullptr, s.ne, ctx->flag,
-                           ctx->stream));
+    // FP64 inverses (rounded for the FP32 copy in FP32-IR mode); a partial
+    // update is enough only when both cached sets are current
+    const bool part = el64 && (!ir || el32);
+    HIPCHK(launch_blockinv(kp, ctx->A, ctx->inv, ir ? ctx->inv32 : nullptr, part ? ctx->crack_elems : nullptr,
+                           part ? ctx->n_crack : s.ne, ctx->flag, ctx->stream));
+    ctx->inv64_epoch = ctx->lin_epoch;
+    if (ir) ctx->inv32_epoch = ctx->lin_epoch;
   }
   HIPCHK(launch_schur(kp, ctx->inv, ctx->Bs, ctx->Cs, ctx->D, nullptr, ctx->T, ctx->S, ctx->Sinv,
                       ctx->Sinv32, ctx->flag, ctx->stream));
   if (ir) {
-    HIPCHK(launch_convert(ctx->A, ctx->A32, s.n_blocks * s.bu * s.bu, ctx->stream));
+    if (cached && ctx->a32_epoch == ctx->lin_epoch)
+      HIPCHK(launch_convert_panels(kp, ctx->crack_elems, ctx->n_crack, ctx->A, ctx->A32, ctx->stream));
+    else
+      HIPCHK(launch_convert(ctx->A, ctx->A32, s.n_blocks * s.bu * s.bu, ctx->stream));
+    ctx->a32_epoch = ctx->lin_epoch;
     HIPCHK(launch_convert(ctx->Bs, ctx->Bs32, s.n_strip * s.bu, ctx->stream));
     HIPCHK(launch_convert(ctx->Cs, ctx->Cs32, s.n_strip * s.bu, ctx->stream));
     HIPCHK(launch_convert(ctx->D, ctx->D32, ctx->doff[B], ctx->stream));
@@ -1622,7 +1694,7 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
     TRY(ensure_ws<double>(ctx, ctx->k64));
     Ops<double> op{ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->inv, ctx->Sinv};
     std::vector<SolveOut> out;
-    TRY(gmres_b<double>(ctx, op, ctx->k64, ctx->rhs, ctx->dx, ctx->opt.rtol, true, on,
+    TRY(gmres_b<double>(ctx, op, ctx->k64, ctx->rhs, ctx->dx, std::vector<double>(B, ctx->opt.rtol), true, on,
                         std::vector<int>(B, ctx->opt.gmres_maxit), out));
     for (int b = 0; b < B; ++b) {
       if (!on[b]) continue;
@@ -1652,7 +1724,11 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
         on[b] = 0;
       }
     }
-    const int cap_inner = 20 * ctx->opt.gmres_m;
+    // each refinement step runs at most ir_inner_cycles FP32 GMRES(m) cycles:
+    // with one cycle the refinement steps are exactly the restarts of
+    // GMRES(m) (the restart residual computed in FP64), so FP32 rounding only
+    // enters the per-cycle reduction, far above the FP32 floor
+    const int cap_inner = ctx->opt.ir_inner_cycles * ctx->opt.gmres_m;
     for (int outer = 0;; ++outer) {
       HIPCHK(ks_norms<double>(kd, ctx->r64, ctx->partial, ctx->red, stm));
       TRY(get_d(ctx, ctx->red, B));
@@ -1676,18 +1752,21 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
         }
       }
       if (!any) break;
-      std::vector<double> coef(B, 0.0);
+      std::vector<double> coef(B, 0.0), tol(B, ctx->opt.rtol_inner);
       std::vector<int> cap(B, 0);
       for (int b = 0; b < B; ++b)
         if (on[b]) {
           coef[b] = 1.0 / rn[b];
           cap[b] = std::min(cap_inner, ctx->opt.gmres_maxit - ls[b].gmres_iters);
+          // stop the inner solve where the outer target is met (with a margin
+          // for the FP32 estimate) rather than below it
+          tol[b] = std::max(ctx->opt.rtol_inner, 0.5 * ctx->opt.rtol * bnorm[b] / rn[b]);
         }
       TRY(put(ctx, kd.solving, on));
       TRY(put(ctx, ctx->k_coef, coef));
       HIPCHK((ks_cast<float, double>(kd, ctx->r64, ctx->k_coef, ctx->k32.b, stm)));
       std::vector<SolveOut> out;
-      TRY(gmres_b<float>(ctx, op32, ctx->k32, ctx->k32.b, ctx->k32.x, ctx->opt.rtol_inner, false, on,
+      TRY(gmres_b<float>(ctx, op32, ctx->k32, ctx->k32.b, ctx->k32.x, tol, false, on,
                          cap, out));
       for (int b = 0; b < B; ++b) {
         if (!on[b]) continue;
@@ -2227,8 +2306,10 @@ extern "C" hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path,
   if (level >= 1) {
     double best_s = 1e300;
     hf_tuning pick = best;
+    // restart length and orthogonalisation: CGS2 against single-reduction
+    // MGS (policy 3 is MGS for FP64 only, 4 also for the FP32 inner solves)
     const int ms[2] = {60, 120};
-    const int pols[2] = {0, 3};
+    const int pols[2] = {0, ctx->opt.precision == HF_FP64 ? 3 : 4};
     for (int mi = 0; mi < 2; ++mi)
       for (int pi = 0; pi < 2; ++pi) {
         hf_tuning t = best;

@@ -131,6 +131,7 @@ struct KrylovDev {
   const int32_t *c_len = nullptr, *c_inst = nullptr, *cptr = nullptr;
   int *solving = nullptr, *kconv = nullptr, *its = nullptr, *status = nullptr, *nbasis = nullptr;
   int *itmax = nullptr;  // per-instance cap on the iterations of the current solve
+  double *rtol = nullptr;  // per-instance relative tolerance of the current solve
   double *bnorm = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
   double *L = nullptr;  // strictly lower Gram factor of the basis (single-pass MGS)
 };
@@ -147,9 +148,13 @@ struct RowSel {
 namespace hf {
 // launchers (hf_kernels_*.hip)
 hipError_t launch_geometry(const KParams &kp, hipStream_t st);
+// R, the row panels, coupling strips and fluid rows; with elist only the row
+// panels, residual rows and strips of the n_el listed elements (and every
+// fluid row)
 hipError_t launch_assemble(const KParams &kp, const double *u, const double *p,
                            const double *w_old, double *A, double *R, double *Bs,
-                           double *Cs, double *D, hipStream_t st);
+                           double *Cs, double *D, const int32_t *elist, int64_t n_el,
+                           hipStream_t st);
 hipError_t launch_opening(const KParams &kp, const double *u, double *w, hipStream_t st);
 hipError_t launch_wmax(const KParams &kp, const double *w, double *out, hipStream_t st);
 hipError_t launch_fluid_volume(const KParams &kp, const double *u, double *partial, double *out,
@@ -160,10 +165,13 @@ hipError_t launch_fill(double v, double *x, int64_t n, hipStream_t st);
 // is null, n = ne); flag[b] |= 1 on a zero or non-finite pivot in instance b
 hipError_t launch_blockinv(const KParams &kp, const double *A, double *inv, float *inv32,
                            const int32_t *elist, int64_t n, int *flag, hipStream_t st);
-// FP32 inverses of every 30 x 30 block on the matrix cores; flag[b] |= 4 when
+// FP32 inverses of the 30 x 30 blocks of the n listed elements (every element
+// when elist is null, n = ne) on the matrix cores; flag[b] |= 4 when
 // a tile pivot fails in instance b (the caller falls back to launch_blockinv)
-hipError_t launch_blockinv32_mfma(const KParams &kp, const double *A, float *inv32, int *flag,
-                                  hipStream_t st);
+hipError_t launch_blockinv32_mfma(const KParams &kp, const double *A, float *inv32,
+                                  const int32_t *elist, int64_t n, int *flag, hipStream_t st);
+hipError_t launch_convert_panels(const KParams &kp, const int32_t *elist, int64_t n, const double *A,
+                                 float *A32, hipStream_t st);
 // flag[b] |= 2 on a zero or non-finite pivot in the pressure block of instance b
 hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,
                         const double *Cs, const double *D, double *Z, double *T, double *S,
@@ -215,7 +223,7 @@ hipError_t ks_zero(const KrylovDev &kd, T *x, int only_solving, hipStream_t st);
 hipError_t ks_reorth_flag(const KrylovDev &kd, const double *n0, int n0s, const double *n1, int policy,
                           int *flag, hipStream_t st);
 hipError_t ks_arnoldi(const KrylovDev &kd, int j, int m, const double *s1, int s1s, const double *s2,
-                      int s2s, const int *reorth, const double *n1, const double *n2, double rtol,
+                      int s2s, const int *reorth, const double *n1, const double *n2,
                       double *scale, hipStream_t st);
 // one-reduce projection for the single-pass modified Gram-Schmidt: out (per
 // instance, stride 2k-1) = V_{0..k-1}^T w, then V_{0..k-2}^T v_{k-1}

@@ -243,7 +243,8 @@ __device__ inline void traction_law(int state, double w, double sigma_c, double 
 // dphi_a/dx_x dphi_b/dx_y.
 // ---------------------------------------------------------------------------
 template <int DIM, int ORDER, int NT>
-__global__ __launch_bounds__(NT) void k_assemble(KParams kp, const double *__restrict__ u,
+__global__ __launch_bounds__(NT) void k_assemble(KParams kp, const int32_t *__restrict__ elist,
+                                                 const double *__restrict__ u,
                                                  const double *__restrict__ p,
                                                  const double *__restrict__ w_old,
                                                  double *__restrict__ A, double *__restrict__ R,
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const double *__res
   using C = Cfg<DIM, ORDER>;
   constexpr int NN = C::NN, BU = C::BU, NF = C::NF, NQF = C::NQF, NQV = C::NQV, NNF = C::NNF;
   constexpr int NQ = NQF > NQV ? NQF : NQV;
-  const int64_t e = blockIdx.x;
+  const int64_t e = elist ? elist[blockIdx.x] : blockIdx.x;
   const int tid = threadIdx.x;
   const InstPar P = kp.ip[kp.einst[e]];
   const double lam = P.lam, G = P.G;
@@ -730,10 +731,11 @@ __global__ void k_wmax(KParams kp, const double *__restrict__ w, double *out) {
 template <int DIM, int ORDER>
 static hipError_t assemble_impl(const KParams &kp, const double *u, const double *p,
                                 const double *w_old, double *A, double *R, double *Bs,
-                                double *Cs, double *D, hipStream_t st) {
+                                double *Cs, double *D, const int32_t *elist, int64_t n_el,
+                                hipStream_t st) {
   constexpr int NT = (Cfg<DIM, ORDER>::BU >= 24) ? 128 : 64;
-  if (kp.s.ne) hipLaunchKernelGGL((k_assemble<DIM, ORDER, NT>), dim3((unsigned)kp.s.ne), dim3(NT), 0, st,
-                                  kp, u, p, w_old, A, R, Bs, Cs);
+  if (n_el) hipLaunchKernelGGL((k_assemble<DIM, ORDER, NT>), dim3((unsigned)n_el), dim3(NT), 0, st,
+                               kp, elist, u, p, w_old, A, R, Bs, Cs);
   if (kp.s.n_p)
     hipLaunchKernelGGL((k_fluid_rows<DIM, ORDER>), dim3((unsigned)((kp.s.n_p + 63) / 64)), dim3(64), 0,
                        st, kp, u, p, w_old, R, D);
@@ -742,12 +744,13 @@ static hipError_t assemble_impl(const KParams &kp, const double *u, const double
 
 hipError_t launch_assemble(const KParams &kp, const double *u, const double *p,
                            const double *w_old, double *A, double *R, double *Bs, double *Cs,
-                           double *D, hipStream_t st) {
+                           double *D, const int32_t *elist, int64_t n_el, hipStream_t st) {
   const int d = kp.s.dim, o = kp.s.order;
-  if (d == 2 && o == 1) return assemble_impl<2, 1>(kp, u, p, w_old, A, R, Bs, Cs, D, st);
-  if (d == 2 && o == 2) return assemble_impl<2, 2>(kp, u, p, w_old, A, R, Bs, Cs, D, st);
-  if (d == 3 && o == 1) return assemble_impl<3, 1>(kp, u, p, w_old, A, R, Bs, Cs, D, st);
-  if (d == 3 && o == 2) return assemble_impl<3, 2>(kp, u, p, w_old, A, R, Bs, Cs, D, st);
+  if (!elist) n_el = kp.s.ne;
+  if (d == 2 && o == 1) return assemble_impl<2, 1>(kp, u, p, w_old, A, R, Bs, Cs, D, elist, n_el, st);
+  if (d == 2 && o == 2) return assemble_impl<2, 2>(kp, u, p, w_old, A, R, Bs, Cs, D, elist, n_el, st);
+  if (d == 3 && o == 1) return assemble_impl<3, 1>(kp, u, p, w_old, A, R, Bs, Cs, D, elist, n_el, st);
+  if (d == 3 && o == 2) return assemble_impl<3, 2>(kp, u, p, w_old, A, R, Bs, Cs, D, elist, n_el, st);
   return hipErrorInvalidValue;
 }
 

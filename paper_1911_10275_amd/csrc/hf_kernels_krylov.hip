@@ -22,43 +22,11 @@ namespace hf {
 
 constexpr int KT = 256;        // threads per block of the vector kernels
 constexpr int KTILE = 8;       // basis vectors per tile of the Gram-Schmidt passes
-constexpr int KTILE2 = 4;      // basis vectors per tile of the two-vector projection (registers)
 
 __device__ inline double kwave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
-}
-
-// Sums each of NV per-lane values over the 64 lanes of a wavefront by
-// recursive halving: at offsets 32, 16, ... a lane keeps half of its values
-// (chosen by its lane bit) and adds the partner's copy of that half; the last
-// offsets add single values.  Lane l ends with the total of value idx, idx
-// read from its high lane bits; the lanes whose low bits (below 64/NV) are
-// zero hold the NV totals.  NV - 1 + log2(64/NV) exchanges instead of
-// 6 NV; the order of the additions is fixed.
-template <int NV>
-__device__ inline double wave_multi_sum(double *v, int lane, int &idx) {
-  static_assert(NV == 8 || NV == 16, "tile of 8 or 16 values");
-  constexpr int LOGNV = NV == 8 ? 3 : 4;
-  idx = 0;
-#pragma unroll
-  for (int st = 0; st < LOGNV; ++st) {
-    const int o = 32 >> st;
-    const bool up = (lane & o) != 0;
-    const int h = NV >> (st + 1);
-#pragma unroll
-    for (int q = 0; q < h; ++q) {
-      const double mine = up ? v[q + h] : v[q];
-      const double other = up ? v[q] : v[q + h];
-      v[q] = mine + __shfl_xor(other, o, 64);
-    }
-    idx = 2 * idx + (up ? 1 : 0);
-  }
-  double t = v[0];
-#pragma unroll
-  for (int o = 32 >> LOGNV; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-  return t;
 }
 
 __device__ inline bool inst_on(const KrylovDev &kd, int b) {
@@ -67,13 +35,17 @@ __device__ inline bool inst_on(const KrylovDev &kd, int b) {
 
 // partial[c*(k+1) + i] = chunk sum of V_i w (i < k); partial[c*(k+1) + k] = chunk sum of w^2.
 // With gate != nullptr the chunk only works when gate[inst] != 0.
+// Each wavefront covers all rows of the chunk (KRL rows per lane, w held in
+// registers) for the basis vectors i = wave, wave + NW, ...: per vector a
+// lane issues its KRL loads at once and one wavefront sum gives the dot, so
+// there is no cross-wave combination; two vectors are in flight at a time.
+constexpr int KRL = kChunkRows / 64;  // rows per lane of a wavefront-wide chunk
 template <typename T, int RR>
 __global__ __launch_bounds__(kChunkRows / RR) void k_sproj(KrylovDev kd, const T *__restrict__ V, int64_t ldv,
-                                              int k, const T *__restrict__ w,
-                                              const int *__restrict__ gate,
-                                              double *__restrict__ partial) {
-  constexpr int NTH = kChunkRows / RR;
-  __shared__ double wsum[kMaxKrylov + 1][NTH / 64];
+                                                           int k, const T *__restrict__ w,
+                                                           const int *__restrict__ gate,
+                                                           double *__restrict__ partial) {
+  constexpr int NTH = kChunkRows / RR, NW = NTH / 64;
   const int c = blockIdx.x, tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int b = kd.c_inst[c];
   double *out = partial + (int64_t)c * (k + 1);
@@ -83,38 +55,48 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_sproj(KrylovDev kd, const T
   }
   const int64_t row0 = kd.c_row0[c];
   const int len = kd.c_len[c];
-  double wr[RR];
-  double nn = 0.0;
+  double wr[KRL];
 #pragma unroll
-  for (int s = 0; s < RR; ++s) {
-    const int rr = tid + s * NTH;
+  for (int s = 0; s < KRL; ++s) {
+    const int rr = lane + 64 * s;
     wr[s] = rr < len ? (double)w[row0 + rr] : 0.0;
-    nn += wr[s] * wr[s];
   }
-  for (int i0 = 0; i0 < k; i0 += KTILE) {
-    double acc[KTILE];
+  if (wv == NW - 1) {
+    double nn = 0.0;
 #pragma unroll
-    for (int q = 0; q < KTILE; ++q) acc[q] = 0.0;
+    for (int s = 0; s < KRL; ++s) nn += wr[s] * wr[s];
+    nn = kwave_sum(nn);
+    if (lane == 0) out[k] = nn;
+  }
+  int i = wv;
+  for (; i + NW < k; i += 2 * NW) {
+    const T *va = V + (int64_t)i * ldv + row0, *vb = V + (int64_t)(i + NW) * ldv + row0;
+    double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-    for (int s = 0; s < RR; ++s) {
-      const int rr = tid + s * NTH;
+    for (int s = 0; s < KRL; ++s) {
+      const int rr = lane + 64 * s;
       if (rr < len) {
-#pragma unroll
-        for (int q = 0; q < KTILE; ++q)
-          if (i0 + q < k) acc[q] += (double)V[(int64_t)(i0 + q) * ldv + row0 + rr] * wr[s];
+        a0 += (double)va[rr] * wr[s];
+        a1 += (double)vb[rr] * wr[s];
       }
     }
-    int idx;
-    const double v = wave_multi_sum<KTILE>(acc, lane, idx);
-    if ((lane & (64 / KTILE - 1)) == 0 && i0 + idx < k) wsum[i0 + idx][wv] = v;
+    a0 = kwave_sum(a0);
+    a1 = kwave_sum(a1);
+    if (lane == 0) {
+      out[i] = a0;
+      out[i + NW] = a1;
+    }
   }
-  nn = kwave_sum(nn);
-  if (lane == 0) wsum[k][wv] = nn;
-  __syncthreads();
-  for (int i = tid; i <= k; i += NTH) {
-    double s2 = 0.0;
-    for (int q = 0; q < NTH / 64; ++q) s2 += wsum[i][q];
-    out[i] = s2;
+  if (i < k) {
+    const T *va = V + (int64_t)i * ldv + row0;
+    double a0 = 0.0;
+#pragma unroll
+    for (int s = 0; s < KRL; ++s) {
+      const int rr = lane + 64 * s;
+      if (rr < len) a0 += (double)va[rr] * wr[s];
+    }
+    a0 = kwave_sum(a0);
+    if (lane == 0) out[i] = a0;
   }
 }
 
@@ -178,13 +160,13 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_supdate(KrylovDev kd, const
 // Gram-Schmidt: with k = j+1 basis vectors and v_j = V_{k-1},
 // partial[c*nout + i] = chunk sum of V_i w (i < k) and
 // partial[c*nout + k + l] = chunk sum of V_l v_j (l < k-1); nout = 2k - 1.
+// Same wavefront-per-vector scheme as k_sproj, with w and v_j in registers.
 template <typename T, int RR>
 __global__ __launch_bounds__(kChunkRows / RR) void k_sproj2(KrylovDev kd, const T *__restrict__ V,
                                                             int64_t ldv, int k,
                                                             const T *__restrict__ w,
                                                             double *__restrict__ partial) {
-  constexpr int NTH = kChunkRows / RR;
-  __shared__ double wsum[2 * kMaxKrylov][NTH / 64];
+  constexpr int NTH = kChunkRows / RR, NW = NTH / 64;
   const int c = blockIdx.x, tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int b = kd.c_inst[c];
   const int nout = 2 * k - 1;
@@ -195,44 +177,32 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_sproj2(KrylovDev kd, const 
   }
   const int64_t row0 = kd.c_row0[c];
   const int len = kd.c_len[c];
-  const T *vj = V + (int64_t)(k - 1) * ldv;
-  double wr[RR], vr[RR];
+  const T *vj = V + (int64_t)(k - 1) * ldv + row0;
+  double wr[KRL], vr[KRL];
 #pragma unroll
-  for (int s = 0; s < RR; ++s) {
-    const int rr = tid + s * NTH;
+  for (int s = 0; s < KRL; ++s) {
+    const int rr = lane + 64 * s;
     wr[s] = rr < len ? (double)w[row0 + rr] : 0.0;
-    vr[s] = rr < len ? (double)vj[row0 + rr] : 0.0;
+    vr[s] = rr < len ? (double)vj[rr] : 0.0;
   }
-  for (int i0 = 0; i0 < k; i0 += KTILE2) {
-    double acc[2 * KTILE2];
+  for (int i = wv; i < k; i += NW) {
+    const T *vi = V + (int64_t)i * ldv + row0;
+    double aw = 0.0, av = 0.0;
 #pragma unroll
-    for (int q = 0; q < 2 * KTILE2; ++q) acc[q] = 0.0;
-#pragma unroll
-    for (int s = 0; s < RR; ++s) {
-      const int rr = tid + s * NTH;
+    for (int s = 0; s < KRL; ++s) {
+      const int rr = lane + 64 * s;
       if (rr < len) {
-#pragma unroll
-        for (int q = 0; q < KTILE2; ++q)
-          if (i0 + q < k) {
-            const double x = (double)V[(int64_t)(i0 + q) * ldv + row0 + rr];
-            acc[q] += x * wr[s];
-            acc[KTILE2 + q] += x * vr[s];
-          }
+        const double x = (double)vi[rr];
+        aw += x * wr[s];
+        av += x * vr[s];
       }
     }
-    int idx;
-    const double v = wave_multi_sum<2 * KTILE2>(acc, lane, idx);
-    if ((lane & (64 / (2 * KTILE2) - 1)) == 0) {
-      const int i = i0 + (idx % KTILE2);
-      if (idx < KTILE2 && i < k) wsum[i][wv] = v;
-      if (idx >= KTILE2 && i < k - 1) wsum[k + i][wv] = v;
+    aw = kwave_sum(aw);
+    av = kwave_sum(av);
+    if (lane == 0) {
+      out[i] = aw;
+      if (i < k - 1) out[k + i] = av;
     }
-  }
-  __syncthreads();
-  for (int i = tid; i < nout; i += NTH) {
-    double s2 = 0.0;
-    for (int q = 0; q < NTH / 64; ++q) s2 += wsum[i][q];
-    out[i] = s2;
   }
 }
 
@@ -396,7 +366,7 @@ __global__ void k_reorth_flag(KrylovDev kd, const double *__restrict__ n0, int n
 // Arnoldi step j of every iterating instance: column j of H from the two
 // Gram-Schmidt passes, previous rotations, the new rotation, the residual
 // estimate; stop the cycle of an instance when the estimate reaches
-// rtol * bnorm, on breakdown, or at its iteration cap.
+// rtol[b] * bnorm[b], on breakdown, or at its iteration cap.
 // One wavefront per instance: the lanes gather column j of H (both passes)
 // and the previous rotations into LDS, lane 0 applies the rotations in
 // sequence (the column entry being rotated stays in a register), and the
@@ -406,7 +376,7 @@ __global__ __launch_bounds__(64) void k_arnoldi(KrylovDev kd, int j, int m,
                                                 const double *__restrict__ s2, int s2s,
                                                 const int *__restrict__ reorth,
                                                 const double *__restrict__ n1,
-                                                const double *__restrict__ n2, double rtol,
+                                                const double *__restrict__ n2,
                                                 double *__restrict__ scale) {
   __shared__ double col[kMaxKrylov + 1], c_s[kMaxKrylov], s_s[kMaxKrylov];
   const int b = blockIdx.x, lane = threadIdx.x;
@@ -446,7 +416,7 @@ __global__ __launch_bounds__(64) void k_arnoldi(KrylovDev kd, int j, int m,
     kd.its[b] = its;
     const bool fin = !isfinite(hn) || !isfinite(g[j + 1]);
     if (fin) kd.status[b] = 2;
-    if (fabs(g[j + 1]) <= rtol * kd.bnorm[b] || hn == 0.0 || its >= kd.itmax[b] || j + 1 == m || fin)
+    if (fabs(g[j + 1]) <= kd.rtol[b] * kd.bnorm[b] || hn == 0.0 || its >= kd.itmax[b] || j + 1 == m || fin)
       kd.kconv[b] = j + 1;
     scale[b] = hn > 0.0 ? 1.0 / hn : 0.0;
   }
@@ -610,10 +580,10 @@ hipError_t ks_reorth_flag(const KrylovDev &kd, const double *n0, int n0s, const 
   return hipGetLastError();
 }
 hipError_t ks_arnoldi(const KrylovDev &kd, int j, int m, const double *s1, int s1s, const double *s2,
-                      int s2s, const int *reorth, const double *n1, const double *n2, double rtol,
+                      int s2s, const int *reorth, const double *n1, const double *n2,
                       double *scale, hipStream_t st) {
   hipLaunchKernelGGL(k_arnoldi, dim3(kd.n_inst), dim3(64), 0, st, kd, j, m, s1, s1s, s2, s2s, reorth,
-                     n1, n2, rtol, scale);
+                     n1, n2, scale);
   return hipGetLastError();
 }
 hipError_t ks_count_active(const KrylovDev &kd, int *count, hipStream_t st) {

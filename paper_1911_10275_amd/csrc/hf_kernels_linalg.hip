@@ -193,7 +193,8 @@ __device__ bool gj16(float *M, int ld, int *perm, int lane) {
   return true;
 }
 
-__global__ __launch_bounds__(64) void k_blockinv32_mfma(const int64_t *__restrict__ blk_ptr,
+__global__ __launch_bounds__(64) void k_blockinv32_mfma(const int32_t *__restrict__ elist,
+                                                        const int64_t *__restrict__ blk_ptr,
                                                         const int32_t *__restrict__ einst,
                                                         const double *__restrict__ A,
                                                         float *__restrict__ inv32, int *flag) {
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(64) void k_blockinv32_mfma(const int64_t *__restric
   __shared__ float M[32 * LD];
   __shared__ float T[16 * LT], W[16 * LT];
   __shared__ int perm[16];
-  const int64_t e = blockIdx.x;
+  const int64_t e = elist ? elist[blockIdx.x] : blockIdx.x;
   const int lane = threadIdx.x;
   const double *blk = A + blk_ptr[e] * BU * BU;
   for (int t = lane; t < 32 * 32; t += 64) {
@@ -244,12 +245,27 @@ __global__ __launch_bounds__(64) void k_blockinv32_mfma(const int64_t *__restric
   }
 }
 
-hipError_t launch_blockinv32_mfma(const KParams &kp, const double *A, float *inv32, int *flag,
-                                  hipStream_t st) {
+hipError_t launch_blockinv32_mfma(const KParams &kp, const double *A, float *inv32,
+                                  const int32_t *elist, int64_t n, int *flag, hipStream_t st) {
   if (kp.s.bu != 30) return hipErrorInvalidValue;
-  if (!kp.s.ne) return hipSuccess;
-  hipLaunchKernelGGL(k_blockinv32_mfma, dim3((unsigned)kp.s.ne), dim3(64), 0, st, kp.m.blk_ptr,
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_blockinv32_mfma, dim3((unsigned)n), dim3(64), 0, st, elist, kp.m.blk_ptr,
                      kp.einst, A, inv32, flag);
+  return hipGetLastError();
+}
+
+// FP32 copies of the row panels of the listed elements
+__global__ void k_convert_panels(const int32_t *__restrict__ elist, const int64_t *__restrict__ blk_ptr,
+                                 int bs2, const double *__restrict__ A, float *__restrict__ A32) {
+  const int64_t e = elist[blockIdx.x];
+  const int64_t b0 = blk_ptr[e] * bs2, b1 = blk_ptr[e + 1] * bs2;
+  for (int64_t t = b0 + threadIdx.x; t < b1; t += blockDim.x) A32[t] = (float)A[t];
+}
+hipError_t launch_convert_panels(const KParams &kp, const int32_t *elist, int64_t n, const double *A,
+                                 float *A32, hipStream_t st) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_convert_panels, dim3((unsigned)n), dim3(256), 0, st, elist, kp.m.blk_ptr,
+                     kp.s.bu * kp.s.bu, A, A32);
   return hipGetLastError();
 }
 
@@ -309,40 +325,43 @@ __global__ void k_schur_gather(KParams kp, const double *__restrict__ D,
   }
 }
 
-// dense Gauss-Jordan inverse with partial pivoting, one workgroup, in place
+// dense Gauss-Jordan inverse with partial pivoting, one workgroup of 1024
+// threads per instance, in place; the elimination runs over a 32 x 32 thread
+// grid (rows by ty, columns by tx)
 constexpr int kMaxDenseP = 4096;
-__global__ __launch_bounds__(256) void k_dense_inv(const int32_t *__restrict__ poff,
+constexpr int kDT = 1024;
+__global__ __launch_bounds__(kDT) void k_dense_inv(const int32_t *__restrict__ poff,
                                                    const int64_t *__restrict__ doff,
                                                    double *__restrict__ Wall,
                                                    double *__restrict__ outall,
                                                    float *__restrict__ out32all, int *flag) {
   const int bi = blockIdx.x;
-  const int64_t n = poff[bi + 1] - poff[bi];
+  const int n = poff[bi + 1] - poff[bi];
   double *W = Wall + doff[bi];
   double *out = outall + doff[bi];
   float *out32 = out32all + doff[bi];
   __shared__ double colk[kMaxDenseP];
   __shared__ int perm[kMaxDenseP];
-  __shared__ double sv[256];
-  __shared__ int si[256];
-  const int tid = threadIdx.x;
-  for (int64_t k = 0; k < n; ++k) {
+  __shared__ double sv[kDT];
+  __shared__ int si[kDT];
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  for (int k = 0; k < n; ++k) {
     double v = -1.0;
-    int idx = (int)n;
-    for (int64_t r = k + tid; r < n; r += 256) {
-      double a = fabs(W[r * n + k]);
+    int idx = n;
+    for (int r = k + tid; r < n; r += kDT) {
+      const double a = fabs(W[(int64_t)r * n + k]);
       if (a > v || (a == v && r < idx)) {
         v = a;
-        idx = (int)r;
+        idx = r;
       }
     }
     sv[tid] = v;
     si[tid] = idx;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) {
-        double ov = sv[tid + s];
-        int oi = si[tid + s];
+    for (int s2 = kDT / 2; s2 > 0; s2 >>= 1) {
+      if (tid < s2) {
+        const double ov = sv[tid + s2];
+        const int oi = si[tid + s2];
         if (ov > sv[tid] || (ov == sv[tid] && oi < si[tid])) {
           sv[tid] = ov;
           si[tid] = oi;
@@ -359,35 +378,36 @@ __global__ __launch_bounds__(256) void k_dense_inv(const int32_t *__restrict__ p
     }
     if (tid == 0) perm[k] = p;
     if (p != k)
-      for (int64_t j = tid; j < n; j += 256) {
-        double t = W[k * n + j];
-        W[k * n + j] = W[(int64_t)p * n + j];
+      for (int j = tid; j < n; j += kDT) {
+        const double t = W[(int64_t)k * n + j];
+        W[(int64_t)k * n + j] = W[(int64_t)p * n + j];
         W[(int64_t)p * n + j] = t;
       }
     __syncthreads();
     const double pinv = 1.0 / pv;
-    for (int64_t j = tid; j < n; j += 256) W[k * n + j] = (j == k) ? pinv : W[k * n + j] * pinv;
-    for (int64_t r = tid; r < n; r += 256) colk[r] = W[r * n + k];
+    for (int j = tid; j < n; j += kDT) W[(int64_t)k * n + j] = (j == k) ? pinv : W[(int64_t)k * n + j] * pinv;
+    for (int r = tid; r < n; r += kDT) colk[r] = W[(int64_t)r * n + k];
     __syncthreads();
-    for (int64_t t = tid; t < n * n; t += 256) {
-      const int64_t r = t / n, j = t % n;
+    const double *Wk = W + (int64_t)k * n;
+    for (int r = ty; r < n; r += kDT / 32) {
       if (r == k) continue;
       const double f = colk[r];
-      W[t] = (j == k) ? -f * pinv : W[t] - f * W[k * n + j];
+      double *Wr = W + (int64_t)r * n;
+      for (int j = tx; j < n; j += 32) Wr[j] = (j == k) ? -f * pinv : Wr[j] - f * Wk[j];
     }
     __syncthreads();
   }
-  for (int64_t k = n - 1; k >= 0; --k) {
+  for (int k = n - 1; k >= 0; --k) {
     const int p = perm[k];
     if (p != k)
-      for (int64_t r = tid; r < n; r += 256) {
-        double t = W[r * n + k];
-        W[r * n + k] = W[r * n + p];
-        W[r * n + p] = t;
+      for (int r = tid; r < n; r += kDT) {
+        const double t = W[(int64_t)r * n + k];
+        W[(int64_t)r * n + k] = W[(int64_t)r * n + p];
+        W[(int64_t)r * n + p] = t;
       }
     __syncthreads();
   }
-  for (int64_t t = tid; t < n * n; t += 256) {
+  for (int64_t t = tid; t < (int64_t)n * n; t += kDT) {
     out[t] = W[t];
     out32[t] = (float)W[t];
   }
@@ -403,7 +423,7 @@ hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,
     hipLaunchKernelGGL(k_schur_t, dim3((unsigned)kp.s.n_se), dim3(64), 0, st, kp, inv, Bs, Cs, T);
   hipLaunchKernelGGL(k_schur_gather, dim3((unsigned)((np + 63) / 64)), dim3(64), 0, st, kp, D, T,
                      kp.m.sp_se, S);
-  hipLaunchKernelGGL(k_dense_inv, dim3(kp.n_inst), dim3(256), 0, st, kp.poff, kp.doff, S, Sinv,
+  hipLaunchKernelGGL(k_dense_inv, dim3(kp.n_inst), dim3(kDT), 0, st, kp.poff, kp.doff, S, Sinv,
                      Sinv32, flag);
   return hipGetLastError();
 }

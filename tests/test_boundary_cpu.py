@@ -34,7 +34,7 @@ def test_default_options_and_null_handling():
     lib = hf.load()
     o = hf.default_options()
     assert o.gmres_m == 60 and o.rtol == 1e-10 and o.precision == hf.HF_FP64
-    assert o.rtol_inner == 1e-2 and o.b_stab == 10.0 and o.newton_maxit == 25
+    assert o.rtol_inner == 1e-4 and o.ir_inner_cycles == 1 and o.b_stab == 10.0 and o.newton_maxit == 25
     assert lib.hf_create(C.byref(o), None) == hf.HF_EINVAL
     assert lib.hf_assemble(None, None) == hf.HF_EINVAL
     assert lib.hf_finalize(None) == hf.HF_EINVAL
