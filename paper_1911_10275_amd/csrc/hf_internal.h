@@ -133,7 +133,7 @@ struct KrylovDev {
   int *itmax = nullptr;  // per-instance cap on the iterations of the current solve
   double *rtol = nullptr;  // per-instance relative tolerance of the current solve
   double *bnorm = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
-  double *L = nullptr;  // strictly lower Gram factor of the basis (single-pass MGS)
+  double *L = nullptr;  // strictly lower Gram factor of the basis, packed by rows (single-pass MGS)
 };
 
 // rows a batched product works on: all (mode 0), the instances being solved

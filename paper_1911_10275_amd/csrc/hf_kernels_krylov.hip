@@ -23,10 +23,29 @@ namespace hf {
 constexpr int KT = 256;        // threads per block of the vector kernels
 constexpr int KTILE = 8;       // basis vectors per tile of the Gram-Schmidt passes
 
+// Wavefront sum without LDS round trips: two quad permutes and two row
+// rotations (DPP) give every lane the sum of its row of 16 lanes, and the
+// four row sums are read from lanes 0, 16, 32 and 48 in a fixed order.  The
+// whole wavefront must be active; every lane receives the total.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double lane_f64(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)x, l);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 __device__ inline double kwave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x124>(v);  // row_ror:4
+  v += dpp_f64<0x128>(v);  // row_ror:8
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
 __device__ inline bool inst_on(const KrylovDev &kd, int b) {
@@ -68,33 +87,37 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_sproj(KrylovDev kd, const T
     nn = kwave_sum(nn);
     if (lane == 0) out[k] = nn;
   }
+  // VF basis vectors per wavefront pass (their loads are issued together)
+  constexpr int VF = 2;
   int i = wv;
-  for (; i + NW < k; i += 2 * NW) {
-    const T *va = V + (int64_t)i * ldv + row0, *vb = V + (int64_t)(i + NW) * ldv + row0;
-    double a0 = 0.0, a1 = 0.0;
+  for (; i + (VF - 1) * NW < k; i += VF * NW) {
+    // all loads of the pass first (rows past len read the last row: wr is 0
+    // there), then the products
+    T x[VF][KRL];
 #pragma unroll
     for (int s = 0; s < KRL; ++s) {
-      const int rr = lane + 64 * s;
-      if (rr < len) {
-        a0 += (double)va[rr] * wr[s];
-        a1 += (double)vb[rr] * wr[s];
-      }
+      const int rc = min(lane + 64 * s, len - 1);
+#pragma unroll
+      for (int f = 0; f < VF; ++f) x[f][s] = V[(int64_t)(i + f * NW) * ldv + row0 + rc];
     }
-    a0 = kwave_sum(a0);
-    a1 = kwave_sum(a1);
-    if (lane == 0) {
-      out[i] = a0;
-      out[i + NW] = a1;
+    double a[VF];
+#pragma unroll
+    for (int f = 0; f < VF; ++f) a[f] = 0.0;
+#pragma unroll
+    for (int s = 0; s < KRL; ++s)
+#pragma unroll
+      for (int f = 0; f < VF; ++f) a[f] += (double)x[f][s] * wr[s];
+#pragma unroll
+    for (int f = 0; f < VF; ++f) {
+      const double t = kwave_sum(a[f]);
+      if (lane == 0) out[i + f * NW] = t;
     }
   }
-  if (i < k) {
+  for (; i < k; i += NW) {
     const T *va = V + (int64_t)i * ldv + row0;
     double a0 = 0.0;
 #pragma unroll
-    for (int s = 0; s < KRL; ++s) {
-      const int rr = lane + 64 * s;
-      if (rr < len) a0 += (double)va[rr] * wr[s];
-    }
+    for (int s = 0; s < KRL; ++s) a0 += (double)va[min(lane + 64 * s, len - 1)] * wr[s];
     a0 = kwave_sum(a0);
     if (lane == 0) out[i] = a0;
   }
@@ -125,16 +148,28 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_supdate(KrylovDev kd, const
     const int rr = tid + s * NTH;
     acc[s] = rr < len ? (double)w[row0 + rr] : 0.0;
   }
-  for (int i0 = 0; i0 < k; i0 += KTILE) {
+  // basis vectors per tile: twice as many in FP32 (the same bytes per
+  // lane).  The loads of a tile are issued together; rows past len read the
+  // chunk's last row and are never stored.
+  constexpr int TW = sizeof(T) == 4 ? 2 * KTILE : KTILE;
+  int rc[RR];
 #pragma unroll
-    for (int s = 0; s < RR; ++s) {
-      const int rr = tid + s * NTH;
-      if (rr < len) {
+  for (int s = 0; s < RR; ++s) rc[s] = min(tid + s * NTH, len - 1);
+  int i0 = 0;
+  for (; i0 + TW <= k; i0 += TW) {
+    T x[TW][RR];
 #pragma unroll
-        for (int q = 0; q < KTILE; ++q)
-          if (i0 + q < k) acc[s] -= sh[i0 + q] * (double)V[(int64_t)(i0 + q) * ldv + row0 + rr];
-      }
-    }
+    for (int q = 0; q < TW; ++q)
+#pragma unroll
+      for (int s = 0; s < RR; ++s) x[q][s] = V[(int64_t)(i0 + q) * ldv + row0 + rc[s]];
+#pragma unroll
+    for (int s = 0; s < RR; ++s)
+#pragma unroll
+      for (int q = 0; q < TW; ++q) acc[s] -= sh[i0 + q] * (double)x[q][s];
+  }
+  for (; i0 < k; ++i0) {
+#pragma unroll
+    for (int s = 0; s < RR; ++s) acc[s] -= sh[i0] * (double)V[(int64_t)i0 * ldv + row0 + rc[s]];
   }
   double nn = 0.0;
 #pragma unroll
@@ -160,13 +195,15 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_supdate(KrylovDev kd, const
 // Gram-Schmidt: with k = j+1 basis vectors and v_j = V_{k-1},
 // partial[c*nout + i] = chunk sum of V_i w (i < k) and
 // partial[c*nout + k + l] = chunk sum of V_l v_j (l < k-1); nout = 2k - 1.
-// Same wavefront-per-vector scheme as k_sproj, with w and v_j in registers.
+// Wavefront-per-vector as in k_sproj; w and v_j are staged in LDS (FP64) so
+// that the registers hold the loads of two basis vectors in flight.
 template <typename T, int RR>
 __global__ __launch_bounds__(kChunkRows / RR) void k_sproj2(KrylovDev kd, const T *__restrict__ V,
                                                             int64_t ldv, int k,
                                                             const T *__restrict__ w,
                                                             double *__restrict__ partial) {
   constexpr int NTH = kChunkRows / RR, NW = NTH / 64;
+  __shared__ double s_w[kChunkRows], s_v[kChunkRows];
   const int c = blockIdx.x, tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int b = kd.c_inst[c];
   const int nout = 2 * k - 1;
@@ -178,24 +215,56 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_sproj2(KrylovDev kd, const 
   const int64_t row0 = kd.c_row0[c];
   const int len = kd.c_len[c];
   const T *vj = V + (int64_t)(k - 1) * ldv + row0;
-  double wr[KRL], vr[KRL];
-#pragma unroll
-  for (int s = 0; s < KRL; ++s) {
-    const int rr = lane + 64 * s;
-    wr[s] = rr < len ? (double)w[row0 + rr] : 0.0;
-    vr[s] = rr < len ? (double)vj[rr] : 0.0;
+  for (int r = tid; r < kChunkRows; r += NTH) {
+    s_w[r] = r < len ? (double)w[row0 + r] : 0.0;
+    s_v[r] = r < len ? (double)vj[r] : 0.0;
   }
-  for (int i = wv; i < k; i += NW) {
-    const T *vi = V + (int64_t)i * ldv + row0;
+  __syncthreads();
+  int i = wv;
+  for (; i + NW < k; i += 2 * NW) {
+    const T *va = V + (int64_t)i * ldv + row0, *vb = va + (int64_t)NW * ldv;
+    // keep the compiler from holding w and v_j in registers across passes
+    // (that leaves too few for the loads in flight): they are re-read from
+    // LDS after the loads of the pass are issued
+    __asm__ volatile("" ::: "memory");
+    T xa[KRL], xb[KRL];
+#pragma unroll
+    for (int s = 0; s < KRL; ++s) {
+      const int rc = min(lane + 64 * s, len - 1);  // s_w, s_v are 0 past len
+      xa[s] = va[rc];
+      xb[s] = vb[rc];
+    }
+    double aw = 0.0, av = 0.0, bw = 0.0, bv = 0.0;
+#pragma unroll
+    for (int s = 0; s < KRL; ++s) {
+      const int rr = lane + 64 * s;
+      const double x = (double)xa[s], y = (double)xb[s];
+      const double ws = s_w[rr], vs = s_v[rr];
+      aw += x * ws;
+      av += x * vs;
+      bw += y * ws;
+      bv += y * vs;
+    }
+    aw = kwave_sum(aw);
+    av = kwave_sum(av);
+    bw = kwave_sum(bw);
+    bv = kwave_sum(bv);
+    if (lane == 0) {
+      out[i] = aw;
+      out[k + i] = av;  // i + NW < k, so i < k - 1
+      out[i + NW] = bw;
+      if (i + NW < k - 1) out[k + i + NW] = bv;
+    }
+  }
+  for (; i < k; i += NW) {
+    const T *va = V + (int64_t)i * ldv + row0;
     double aw = 0.0, av = 0.0;
 #pragma unroll
     for (int s = 0; s < KRL; ++s) {
       const int rr = lane + 64 * s;
-      if (rr < len) {
-        const double x = (double)vi[rr];
-        aw += x * wr[s];
-        av += x * vr[s];
-      }
+      const double x = (double)va[min(rr, len - 1)];
+      aw += x * s_w[rr];
+      av += x * s_v[rr];
     }
     aw = kwave_sum(aw);
     av = kwave_sum(av);
@@ -210,42 +279,56 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_sproj2(KrylovDev kd, const 
 // row j of the strictly lower Gram factor, L[j][l] = v_j . v_l (l < j), is
 // stored; h solves (I + L) h = s (s_i = v_i . w, i <= j) by forward
 // substitution, which reproduces the projections of the sequential
-// (modified) Gram-Schmidt.  One wavefront per iterating instance; for
-// j < 64 the factor is staged in LDS and eliminated column by column.
+// (modified) Gram-Schmidt.  L is stored packed by rows (row i, of length i,
+// at i (i - 1) / 2), so rows 1 .. j-1 are one contiguous range.  One
+// wavefront per iterating instance; for j < 64 the factor is staged in LDS
+// (eight loads in flight per lane) and eliminated column by column.
 constexpr int kIcwyLds = 64;
+__device__ inline int lrow(int i) { return i * (i - 1) / 2; }
 __global__ __launch_bounds__(64) void k_icwy(KrylovDev kd, int j, int m, const double *__restrict__ sv,
                                              double *__restrict__ Lmat, double *__restrict__ h,
                                              int hstride) {
   __shared__ double hs[kMaxKrylov];
-  __shared__ double Ls[kIcwyLds][kIcwyLds + 1];
+  __shared__ double Lp[kIcwyLds * (kIcwyLds - 1) / 2];
   const int b = blockIdx.x, lane = threadIdx.x;
   if (!inst_on(kd, b)) return;  // uniform over the block
   const int k = j + 1, nout = 2 * k - 1, ld = m + 1;
   const double *sb = sv + (int64_t)b * nout;
   double *Lb = Lmat + (int64_t)b * ld * ld;
-  for (int l = lane; l < j; l += 64) Lb[(int64_t)j * ld + l] = sb[k + l];
+  for (int l = lane; l < j; l += 64) Lb[lrow(j) + l] = sb[k + l];
   for (int i = lane; i <= j; i += 64) hs[i] = sb[i];
   if (j < kIcwyLds) {
-    for (int t = lane; t < j * j; t += 64) {
-      const int i = t / j, l = t % j;
-      if (l < i) Ls[i][l] = Lb[(int64_t)i * ld + l];
+    constexpr int U = 8;
+    const int n = lrow(j);
+    for (int t0 = 0; t0 < n; t0 += 64 * U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + 64 * u + lane;
+        v[u] = t < n ? Lb[t] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + 64 * u + lane;
+        if (t < n) Lp[t] = v[u];
+      }
     }
-    for (int l = lane; l < j; l += 64) Ls[j][l] = sb[k + l];
+    for (int l = lane; l < j; l += 64) Lp[n + l] = sb[k + l];
     __syncthreads();
     for (int l = 0; l < j; ++l) {  // h_l is final: remove it from the rows below
       const double hl = hs[l];
       const int i = l + 1 + lane;
-      if (i <= j) hs[i] -= Ls[i][l] * hl;
+      if (i <= j) hs[i] -= Lp[lrow(i) + l] * hl;
       __syncthreads();
     }
   } else {
     __syncthreads();
     for (int i = 0; i <= j; ++i) {
-      const double *Li = i == j ? sb + k : Lb + (int64_t)i * ld;  // row i of L (row j from sv)
+      const double *Li = i == j ? sb + k : Lb + lrow(i);  // row i of L (row j from sv)
       double acc = 0.0;
       for (int l = lane; l < i; l += 64) acc += Li[l] * hs[l];
       acc = kwave_sum(acc);
-      if (lane == 0) hs[i] -= acc;  // lane 0 holds the wave total
+      if (lane == 0) hs[i] -= acc;
       __syncthreads();
     }
   }
