@@ -113,6 +113,14 @@ typedef struct {
                           inverses; a material or b_stab change triggers a
                           full assembly (default 1); 0: full assembly and
                           all inverses every time */
+  int fold_preconditioner; /* 1: after each block-Jacobi build, form the
+                          right-preconditioned operator J M^-1 explicitly
+                          (every Jacobian block times its column element's
+                          inverse, the C strips times their element's
+                          inverse; S^-1 is applied to the pressure part at
+                          product time), so a GMRES iteration makes one
+                          product instead of a preconditioner apply and a
+                          product; 0: apply M^-1, then J (default 1) */
   void *stream;        /* hipStream_t to run on; NULL: a stream the ctx creates */
 } hf_options;
 
@@ -320,6 +328,13 @@ hf_status hf_get_block_inverse(hf_ctx *ctx, int32_t inst, int64_t n_rows, const 
    FP64 matrix (double*), HF_FP32_IR the FP32 copy (float*) built by the
    last hf_solve in FP32-IR mode. */
 hf_status hf_apply_jacobian(hf_ctx *ctx, int precision, const void *x, void *y);
+/* y = J M^-1 x, the right-preconditioned operator of GMRES, on device context
+   vectors, with the block-Jacobi factors of the last hf_solve in that
+   precision: folded = 1 uses the folded blocks (built by that solve when
+   hf_options.fold_preconditioner = 1; HF_ESTATE otherwise), folded = 0
+   applies M^-1 and then J.  HF_ESTATE when the last solve ran in the other
+   precision or the system was re-assembled since. */
+hf_status hf_apply_preconditioned(hf_ctx *ctx, int precision, int folded, const void *x, void *y);
 hf_status hf_get_profile(hf_ctx *ctx, hf_profile *out);
 
 /* ---- tuning ---- */

@@ -34,7 +34,7 @@ EXPORTS = [
     "hf_newton_step", "hf_newton_solve", "hf_end_load_step", "hf_initial_guess", "hf_get_residual",
     "hf_get_block_rows", "hf_get_coupling", "hf_get_increment", "hf_apply_jacobian",
     "hf_get_profile", "hf_reset_profile", "hf_get_tuning", "hf_set_tuning", "hf_autotune",
-    "hf_get_block_inverse",
+    "hf_get_block_inverse", "hf_apply_preconditioned",
 ]
 
 
@@ -45,7 +45,7 @@ class Options(C.Structure):
                 ("p_cutoff", C.c_double), ("cutoff_on", C.c_int), ("device", C.c_int),
                 ("profile", C.c_int), ("use_graphs", C.c_int), ("mfma_inverse", C.c_int),
                 ("ir_inner_cycles", C.c_int), ("incremental_assembly", C.c_int),
-                ("stream", C.c_void_p)]
+                ("fold_preconditioner", C.c_int), ("stream", C.c_void_p)]
 
 
 class Material(C.Structure):
@@ -146,6 +146,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hf_get_coupling": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
         "hf_get_increment": (C.c_int, [vp, C.c_int32, vp, vp]),
         "hf_apply_jacobian": (C.c_int, [vp, C.c_int, vp, vp]),
+        "hf_apply_preconditioned": (C.c_int, [vp, C.c_int, C.c_int, vp, vp]),
         "hf_get_profile": (C.c_int, [vp, P(Profile)]),
         "hf_reset_profile": (C.c_int, [vp]),
         "hf_get_tuning": (C.c_int, [vp, P(Tuning)]),
@@ -401,6 +402,10 @@ class Context:
     def apply_jacobian(self, x_ptr, y_ptr, precision=HF_FP64):
         self._check(self.lib.hf_apply_jacobian(self.h, precision, C.c_void_p(x_ptr),
                                                C.c_void_p(y_ptr)), "hf_apply_jacobian")
+
+    def apply_preconditioned(self, x_ptr, y_ptr, precision=HF_FP64, folded=1):
+        self._check(self.lib.hf_apply_preconditioned(self.h, precision, int(folded), C.c_void_p(x_ptr),
+                                                     C.c_void_p(y_ptr)), "hf_apply_preconditioned")
 
     def profile(self) -> Profile:
         p = Profile()

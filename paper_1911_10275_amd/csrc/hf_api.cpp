@@ -105,6 +105,12 @@ struct hf_ctx {
   float *A32 = nullptr, *Bs32 = nullptr, *Cs32 = nullptr, *D32 = nullptr, *Sinv32 = nullptr;
   float *inv32 = nullptr;
   bool have32 = false;
+  // folded preconditioned operator J M^-1 (blocks A_ef inv_f, C strips
+  // C_e inv_e) and the S^-1 x_p staging vector, per precision
+  double *Af64 = nullptr, *Cf64 = nullptr, *tp64 = nullptr;
+  float *Af32 = nullptr, *Cf32 = nullptr, *tp32 = nullptr;
+  bool have_f64 = false, have_f32 = false;
+  bool have_m64 = false;  // the FP64 block-Jacobi factors match the assembled system
   int *flag = nullptr;
   double *dx = nullptr, *rhs = nullptr, *r64 = nullptr, *t64 = nullptr;
   KrylovWs<double> k64;
@@ -408,6 +414,7 @@ extern "C" void hf_default_options(hf_options *o) {
   o->use_graphs = 1;
   o->mfma_inverse = 1;
   o->incremental_assembly = 1;
+  o->fold_preconditioner = 1;
   o->stream = nullptr;
 }
 
@@ -1280,7 +1287,7 @@ static hf_status do_assemble(hf_ctx *ctx, std::vector<double> &rn) {
   TRY(get_d(ctx, ctx->red, nI(ctx)));
   rn.assign(nI(ctx), 0.0);
   for (int b = 0; b < nI(ctx); ++b) rn[b] = std::sqrt(ctx->hd[b]);
-  ctx->have32 = false;
+  ctx->have32 = ctx->have_f64 = ctx->have_f32 = ctx->have_m64 = false;
   return HF_OK;
 }
 
@@ -1304,6 +1311,9 @@ extern "C" hf_status hf_assemble(hf_ctx *ctx, double *res_norm) {
 template <typename T>
 struct Ops {
   const T *A, *Bs, *Cs, *D, *inv, *Sinv;
+  // folded J M^-1 (null: apply M^-1, then J) and its S^-1 x_p staging vector
+  const T *Af = nullptr, *Cf = nullptr;
+  T *tp = nullptr;
 };
 
 template <typename T>
@@ -1380,6 +1390,20 @@ static hf_status apply_M(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const
   return HF_OK;
 }
 
+// w = J M^-1 v: one product with the folded blocks when they are built,
+// else the block-Jacobi apply into z followed by the Jacobian product
+template <typename T>
+static hf_status apply_JM(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *v, T *z, T *w,
+                          const RowSel &sel) {
+  if (!op.Af) {
+    TRY(apply_M<T>(ctx, kp, op, v, z, sel));
+    return apply_J<T>(ctx, kp, op, z, w, sel);
+  }
+  ProfScope ps(ctx, sizeof(T) == 8 ? P_SPMV64 : P_SPMV32);
+  HIPCHK(launch_spmv_folded<T>(kp, op.Af, op.Bs, op.Cf, op.D, op.Sinv, v, w, op.tp, sel, ctx->stream));
+  return HF_OK;
+}
+
 // Arnoldi step j of every instance still iterating (kernel launches only, so
 // that a chunk of steps can be captured in a graph): w = J M^-1 v_j;
 // classical Gram-Schmidt h = V^T w, w -= V h, repeated once when
@@ -1391,8 +1415,7 @@ static hf_status arnoldi_step(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, 
   const int64_t N = ctx->s.N();
   const KrylovDev &kd = ctx->kd;
   const int m = ws.m, k = j + 1, ks = j + 2;
-  TRY(apply_M<T>(ctx, kp, op, ws.V + (int64_t)j * N, ws.z, rows(ctx, 2)));
-  TRY(apply_J<T>(ctx, kp, op, ws.z, ws.w, rows(ctx, 2)));
+  TRY(apply_JM<T>(ctx, kp, op, ws.V + (int64_t)j * N, ws.z, ws.w, rows(ctx, 2)));
   ProfScope ps(ctx, P_ORTHO);
   // orthogonalisation scheme: single-pass modified Gram-Schmidt from one
   // reduction, or classical Gram-Schmidt with a second pass by policy
@@ -1663,6 +1686,30 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
     HIPCHK(launch_convert(ctx->D, ctx->D32, ctx->doff[B], ctx->stream));
     ctx->have32 = true;
   }
+  ctx->have_m64 = !ir;
+  if (ctx->opt.fold_preconditioner) {
+    // J M^-1 with the new inverses: every block of the row panels times its
+    // column element's inverse (and the C strips), in the solve's precision
+    ProfScope ps(ctx, P_INV);
+    const int64_t nb = s.n_blocks * s.bu * s.bu, nc = s.n_strip * s.bu;
+    if (ir) {
+      if (!ctx->Af32) {
+        TRY(dalloc(ctx, &ctx->Af32, nb));
+        TRY(dalloc(ctx, &ctx->Cf32, nc));
+        TRY(dalloc(ctx, &ctx->tp32, s.n_p));
+      }
+      HIPCHK((launch_fold<float, float>(kp, ctx->A, ctx->Cs, ctx->inv32, ctx->Af32, ctx->Cf32, ctx->stream)));
+      ctx->have_f32 = true;
+    } else {
+      if (!ctx->Af64) {
+        TRY(dalloc(ctx, &ctx->Af64, nb));
+        TRY(dalloc(ctx, &ctx->Cf64, nc));
+        TRY(dalloc(ctx, &ctx->tp64, s.n_p));
+      }
+      HIPCHK((launch_fold<double, double>(kp, ctx->A, ctx->Cs, ctx->inv, ctx->Af64, ctx->Cf64, ctx->stream)));
+      ctx->have_f64 = true;
+    }
+  }
   TRY(get_i_async(ctx, ctx->flag, B, 0));
   TRY(sync(ctx));
   for (int b = 0; b < B; ++b) {
@@ -1693,6 +1740,11 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
   if (ctx->opt.precision == HF_FP64) {
     TRY(ensure_ws<double>(ctx, ctx->k64));
     Ops<double> op{ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->inv, ctx->Sinv};
+    if (ctx->opt.fold_preconditioner && ctx->have_f64) {
+      op.Af = ctx->Af64;
+      op.Cf = ctx->Cf64;
+      op.tp = ctx->tp64;
+    }
     std::vector<SolveOut> out;
     TRY(gmres_b<double>(ctx, op, ctx->k64, ctx->rhs, ctx->dx, std::vector<double>(B, ctx->opt.rtol), true, on,
                         std::vector<int>(B, ctx->opt.gmres_maxit), out));
@@ -1707,6 +1759,11 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
     TRY(ensure_ws<float>(ctx, ctx->k32));
     Ops<double> op64{ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->inv, ctx->Sinv};
     Ops<float> op32{ctx->A32, ctx->Bs32, ctx->Cs32, ctx->D32, ctx->inv32, ctx->Sinv32};
+    if (ctx->opt.fold_preconditioner && ctx->have_f32) {
+      op32.Af = ctx->Af32;
+      op32.Cf = ctx->Cf32;
+      op32.tp = ctx->tp32;
+    }
     TRY(put(ctx, kd.solving, on));
     HIPCHK(ks_zero<double>(kd, ctx->dx, 1, stm));
     HIPCHK(hipMemcpyAsync(ctx->r64, ctx->rhs, N * sizeof(double), hipMemcpyDeviceToDevice, stm));
@@ -2134,6 +2191,39 @@ extern "C" hf_status hf_apply_jacobian(hf_ctx *ctx, int precision, const void *x
     if (!ctx->have32) return fail(ctx, HF_ESTATE, "no FP32 matrix: run hf_solve in FP32-IR mode first");
     Ops<float> op{ctx->A32, ctx->Bs32, ctx->Cs32, ctx->D32, ctx->inv32, ctx->Sinv32};
     TRY(apply_J<float>(ctx, kp, op, (const float *)x, (float *)y, RowSel{}));
+  } else {
+    return fail(ctx, HF_EINVAL, "precision");
+  }
+  return HF_OK;
+}
+
+extern "C" hf_status hf_apply_preconditioned(hf_ctx *ctx, int precision, int folded, const void *x,
+                                             void *y) {
+  TRY(check_ctx(ctx, 4));
+  if (!x || !y) return fail(ctx, HF_EINVAL, "null vector");
+  const KParams kp = kparams(ctx);
+  if (precision == HF_FP64) {
+    if (!ctx->have_m64) return fail(ctx, HF_ESTATE, "no FP64 block-Jacobi factors: run hf_solve in FP64 mode first");
+    if (!ctx->have_f64 && folded) return fail(ctx, HF_ESTATE, "no folded FP64 operator: run hf_solve in FP64 mode first");
+    TRY(ensure_ws<double>(ctx, ctx->k64));
+    Ops<double> op{ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->inv, ctx->Sinv};
+    if (folded) {
+      op.Af = ctx->Af64;
+      op.Cf = ctx->Cf64;
+      op.tp = ctx->tp64;
+    }
+    TRY(apply_JM<double>(ctx, kp, op, (const double *)x, ctx->k64.z, (double *)y, RowSel{}));
+  } else if (precision == HF_FP32_IR) {
+    if (!ctx->have32) return fail(ctx, HF_ESTATE, "no FP32 matrix: run hf_solve in FP32-IR mode first");
+    if (!ctx->have_f32 && folded) return fail(ctx, HF_ESTATE, "no folded FP32 operator: run hf_solve in FP32-IR mode first");
+    TRY(ensure_ws<float>(ctx, ctx->k32));
+    Ops<float> op{ctx->A32, ctx->Bs32, ctx->Cs32, ctx->D32, ctx->inv32, ctx->Sinv32};
+    if (folded) {
+      op.Af = ctx->Af32;
+      op.Cf = ctx->Cf32;
+      op.tp = ctx->tp32;
+    }
+    TRY(apply_JM<float>(ctx, kp, op, (const float *)x, ctx->k32.z, (float *)y, RowSel{}));
   } else {
     return fail(ctx, HF_EINVAL, "precision");
   }

@@ -172,6 +172,11 @@ hipError_t launch_blockinv32_mfma(const KParams &kp, const double *A, float *inv
                                   const int32_t *elist, int64_t n, int *flag, hipStream_t st);
 hipError_t launch_convert_panels(const KParams &kp, const int32_t *elist, int64_t n, const double *A,
                                  float *A32, hipStream_t st);
+// folded preconditioned operator: Af = A_ef inv_f for every block of the row
+// panels, Cf = C_e inv_e for every C strip entry (FP64 arithmetic)
+template <typename TI, typename TO>
+hipError_t launch_fold(const KParams &kp, const double *A, const double *Cs, const TI *inv, TO *Af, TO *Cf,
+                       hipStream_t st);
 // flag[b] |= 2 on a zero or non-finite pivot in the pressure block of instance b
 hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,
                         const double *Cs, const double *D, double *Z, double *T, double *S,
@@ -181,6 +186,11 @@ hipError_t launch_convert(const double *in, float *out, int64_t n, hipStream_t s
 template <typename T>
 hipError_t launch_spmv(const KParams &kp, const T *A, const T *Bs, const T *Cs, const T *D,
                        const T *x, T *y, const RowSel &sel, hipStream_t st);
+// y = J M^-1 x with the folded blocks: t_p = S^-1 x_p (into tp, n_p values),
+// y_u = Af x_u + B t_p, y_p = Cf x_u + D t_p (rows outside sel untouched)
+template <typename T>
+hipError_t launch_spmv_folded(const KParams &kp, const T *Af, const T *Bs, const T *Cf, const T *D,
+                              const T *Sinv, const T *x, T *y, T *tp, const RowSel &sel, hipStream_t st);
 // z = M^-1 r, block-Jacobi (rows outside sel are left untouched)
 template <typename T>
 hipError_t launch_precond(const KParams &kp, const T *inv, const T *Sinv, const T *r, T *z,

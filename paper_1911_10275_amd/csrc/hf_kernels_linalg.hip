@@ -270,6 +270,82 @@ hipError_t launch_convert_panels(const KParams &kp, const int32_t *elist, int64_
 }
 
 // ---------------------------------------------------------------------------
+// Folded right-preconditioned operator J M^-1: every block of the row panels
+// times the inverse of its column element, Af_ef = A_ef inv_f, and every C
+// strip entry times its element's inverse, Cf = C_e inv_e (the B strips and
+// D are used with S^-1 x_p at product time).  FP64 arithmetic; TI is the
+// precision of the inverses (FP64, or the FP32 set of GMRES-IR) and TO that
+// of the result.
+// ---------------------------------------------------------------------------
+template <int BU, typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_fold_blocks(int64_t n_blocks, const int32_t *__restrict__ blk_col,
+                                                     const double *__restrict__ A,
+                                                     const TI *__restrict__ inv, TO *__restrict__ Af) {
+  constexpr int B2 = BU * BU;
+  __shared__ double sa[B2], si[B2];
+  const int64_t blk = blockIdx.x;
+  if (blk >= n_blocks) return;
+  const int64_t f = blk_col[blk];
+  const double *a = A + blk * B2;
+  const TI *iv = inv + f * B2;
+  for (int t = threadIdx.x; t < B2; t += blockDim.x) {
+    sa[t] = a[t];
+    si[t] = (double)iv[t];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < B2; t += blockDim.x) {  // column-major: t = r + c BU
+    const int r = t % BU, c = t / BU;
+    double acc = 0.0;
+#pragma unroll 6
+    for (int k = 0; k < BU; ++k) acc += sa[r + k * BU] * si[k + c * BU];
+    Af[blk * B2 + t] = (TO)acc;
+  }
+}
+
+template <int BU, typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_fold_cstrips(int64_t n_strip, const int32_t *__restrict__ sp_elem,
+                                                      const double *__restrict__ Cs,
+                                                      const TI *__restrict__ inv, TO *__restrict__ Cf) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n_strip * BU) return;
+  const int64_t ent = t / BU;
+  const int c = (int)(t % BU);
+  const TI *iv = inv + (int64_t)sp_elem[ent] * BU * BU;
+  double acc = 0.0;
+  for (int r = 0; r < BU; ++r) acc += Cs[ent * BU + r] * (double)iv[r + c * BU];
+  Cf[t] = (TO)acc;
+}
+
+template <int BU, typename TI, typename TO>
+static void fold_bu(const KParams &kp, const double *A, const double *Cs, const TI *inv, TO *Af, TO *Cf,
+                    hipStream_t st) {
+  constexpr int NT = BU * BU >= 256 ? 256 : (BU * BU + 63) / 64 * 64;
+  if (kp.s.n_blocks)
+    hipLaunchKernelGGL((k_fold_blocks<BU, TI, TO>), dim3((unsigned)kp.s.n_blocks), dim3(NT), 0, st,
+                       kp.s.n_blocks, kp.m.blk_col, A, inv, Af);
+  const int64_t nc = kp.s.n_strip * BU;
+  if (nc)
+    hipLaunchKernelGGL((k_fold_cstrips<BU, TI, TO>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st,
+                       kp.s.n_strip, kp.m.sp_elem, Cs, inv, Cf);
+}
+
+template <typename TI, typename TO>
+hipError_t launch_fold(const KParams &kp, const double *A, const double *Cs, const TI *inv, TO *Af, TO *Cf,
+                       hipStream_t st) {
+  switch (kp.s.bu) {
+    case 6: fold_bu<6>(kp, A, Cs, inv, Af, Cf, st); break;
+    case 12: fold_bu<12>(kp, A, Cs, inv, Af, Cf, st); break;
+    case 30: fold_bu<30>(kp, A, Cs, inv, Af, Cf, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_fold<double, double>(const KParams &, const double *, const double *,
+                                                const double *, double *, double *, hipStream_t);
+template hipError_t launch_fold<float, float>(const KParams &, const double *, const double *, const float *,
+                                              float *, float *, hipStream_t);
+
+// ---------------------------------------------------------------------------
 // Schur pressure block S = D - C M_A^-1 B (dense n_p x n_p) and its inverse
 // ---------------------------------------------------------------------------
 constexpr int kMaxStrip = 32;  // strip entries per element (<= (dim+1) * face nodes)

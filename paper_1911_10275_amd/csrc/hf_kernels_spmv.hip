@@ -92,7 +92,26 @@ __global__ __launch_bounds__(NT) void k_bsr_spmv(
   if (live) {
     b0 = blk_ptr[e];
     nb = (int)(blk_ptr[e + 1] - b0);
-    for (int t = lane; t < nb * BU; t += L) xs[g][t] = x[(int64_t)blk_col[b0 + t / BU] * BU + t % BU];
+    // stage the x values of the row's (at most 5) block columns: the column
+    // indices of all of a lane's entries first, then all their x loads
+    constexpr int XT = (5 * BU + L - 1) / L;
+    int32_t col[XT];
+#pragma unroll
+    for (int i = 0; i < XT; ++i) col[i] = blk_col[b0 + min((lane + L * i) / BU, nb - 1)];  // nb >= 1
+    int64_t src[XT];
+#pragma unroll
+    for (int i = 0; i < XT; ++i) {
+      const int t = lane + L * i;
+      src[i] = t < nb * BU ? (int64_t)col[i] * BU + t % BU : -1;
+    }
+    T xv[XT];
+#pragma unroll
+    for (int i = 0; i < XT; ++i) xv[i] = src[i] >= 0 ? x[src[i]] : T(0);
+#pragma unroll
+    for (int i = 0; i < XT; ++i) {
+      const int t = lane + L * i;
+      if (t < nb * BU) xs[g][t] = xv[i];
+    }
   }
   __syncthreads();
   T acc[EL];
@@ -105,7 +124,7 @@ __global__ __launch_bounds__(NT) void k_bsr_spmv(
 #pragma unroll
     for (int s = 0; s < EL; ++s) colS[s] = (lane * EL + s) / BU;
     int f = lane * EL, cb = 0;
-#pragma unroll 4
+#pragma unroll 8
     for (; f < total; f += CH, cb += RPC) {
       const V v = *(const V *)(panel + f);
 #pragma unroll
@@ -208,6 +227,53 @@ template hipError_t launch_spmv<double>(const KParams &, const double *, const d
 template hipError_t launch_spmv<float>(const KParams &, const float *, const float *,
                                        const float *, const float *, const float *, float *,
                                        const RowSel &, hipStream_t);
+
+// folded product y = J M^-1 x: the pressure part of M^-1 first (t_p = S^-1
+// x_p), then the row panels of A M_A^-1 with the B strips on t_p, then the
+// pressure rows with the folded C strips and D on t_p
+template <typename T, int BU>
+static void spmv_folded_bu(const KParams &kp, const T *Af, const T *Bs, const T *Cf, const T *D,
+                           const T *Sinv, const T *x, T *y, T *tp, const RowSel &sel, hipStream_t st) {
+  const RowMask me{kp.einst, sel.solving, sel.kconv, sel.mode};
+  const RowMask mp{kp.pinst, sel.solving, sel.kconv, sel.mode};
+  constexpr int LW = wide_lanes(BU);
+  const int64_t ne = kp.s.ne;
+  if (kp.s.n_p)
+    hipLaunchKernelGGL((k_prows<T, BU>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp.s.n_p, kp.pinst,
+                       kp.poff, kp.doff, nullptr, nullptr, nullptr, nullptr, Sinv, x + kp.s.n_u,
+                       x + kp.s.n_u, tp, mp);
+  if (ne) {
+    if (kp.spmv_var == 1)
+      rows_launch<T, BU, LW / 2, true>(ne, kp.m.blk_ptr, kp.m.blk_col, Af, kp.m.sp_ptr, kp.m.sp_pnode,
+                                       Bs, x, tp, y, me, st);
+    else
+      rows_launch<T, BU, LW, true>(ne, kp.m.blk_ptr, kp.m.blk_col, Af, kp.m.sp_ptr, kp.m.sp_pnode, Bs,
+                                   x, tp, y, me, st);
+  }
+  if (kp.s.n_p)
+    hipLaunchKernelGGL((k_prows<T, BU>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp.s.n_p,
+                       kp.pinst, kp.poff, kp.doff, kp.m.pc_ptr, kp.m.pc_ent, kp.m.sp_elem, Cf, D, x,
+                       tp, y + kp.s.n_u, mp);
+}
+
+template <typename T>
+hipError_t launch_spmv_folded(const KParams &kp, const T *Af, const T *Bs, const T *Cf, const T *D,
+                              const T *Sinv, const T *x, T *y, T *tp, const RowSel &sel, hipStream_t st) {
+  switch (kp.s.bu) {
+    case 6: spmv_folded_bu<T, 6>(kp, Af, Bs, Cf, D, Sinv, x, y, tp, sel, st); break;
+    case 12: spmv_folded_bu<T, 12>(kp, Af, Bs, Cf, D, Sinv, x, y, tp, sel, st); break;
+    case 30: spmv_folded_bu<T, 30>(kp, Af, Bs, Cf, D, Sinv, x, y, tp, sel, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_spmv_folded<double>(const KParams &, const double *, const double *,
+                                               const double *, const double *, const double *,
+                                               const double *, double *, double *, const RowSel &,
+                                               hipStream_t);
+template hipError_t launch_spmv_folded<float>(const KParams &, const float *, const float *, const float *,
+                                              const float *, const float *, const float *, float *,
+                                              float *, const RowSel &, hipStream_t);
 
 // block-Jacobi apply: z_u = blockdiag(inv) r_u (the same streaming kernel on
 // the identity block pattern), z_p = S^-1 r_p

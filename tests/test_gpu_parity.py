@@ -177,6 +177,55 @@ def test_newton_load_steps_parity(name, precision):
 
 
 @pytest.mark.parametrize("name", ["2d_p1_n9", "3d_p2_n3"])
+@pytest.mark.parametrize("precision", [hf.HF_FP64, hf.HF_FP32_IR], ids=["fp64", "fp32ir"])
+def test_newton_load_steps_unfolded(name, precision):
+    """With the preconditioner applied before each product instead of folded
+    into the blocks, the converged states still match the oracle to 1e-8."""
+    prob = SMALL[name]()
+    case, ctx = _pair(prob)
+    ctx.set_options(fold_preconditioner=0)
+    ref = newton.run(case, prob.load_steps, solver="gmres")
+    got = _gpu_run(ctx, case, prob.load_steps, precision)
+    for (st, _), ((u, p, w, wo), ns) in zip(ref, got):
+        assert np.linalg.norm(u - st.u) <= 1e-8 * np.linalg.norm(st.u)
+        assert np.linalg.norm(p - st.p) <= 1e-8 * np.linalg.norm(st.p)
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_folded_operator(name):
+    """J M^-1 x from the folded blocks equals M^-1 then J (FP64: 1e-13 of the
+    largest entry; FP32: 1e-5, the two round differently) and the oracle's
+    J M^-1 x with its own block inverses and Schur block (1e-10)."""
+    torch = pytest.importorskip("torch")
+    prob = SMALL[name]()
+    case, ctx = _pair(prob)
+    u, p, wo = _random_state(case, 8)
+    rng = np.random.default_rng(9)
+    for precision, dt, tol in ((hf.HF_FP64, torch.float64, 1e-13), (hf.HF_FP32_IR, torch.float32, 1e-5)):
+        ctx.set_options(precision=precision, gmres_maxit=1)
+        ctx.set_state(u, p, wo)
+        ctx.assemble()
+        ctx.solve(check=False)  # builds the factors and the folded blocks; one iteration
+        n = ctx.sizes.n_total
+        x = rng.normal(size=n)
+        xd = torch.tensor(x, device="cuda", dtype=dt)
+        y1, y0 = torch.empty_like(xd), torch.empty_like(xd)
+        torch.cuda.synchronize()
+        ctx.apply_preconditioned(xd.data_ptr(), y1.data_ptr(), precision, folded=1)
+        ctx.apply_preconditioned(xd.data_ptr(), y0.data_ptr(), precision, folded=0)
+        torch.cuda.synchronize()
+        a, b = y1.double().cpu().numpy(), y0.double().cpu().numpy()
+        assert _rel(a, b) < tol
+        if precision == hf.HF_FP64:
+            S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo),
+                             case.src_pnode, case.src_q0)
+            ref = solve.Operator(case.mesh, S)(solve.BlockJacobi(case.mesh, S)(x))
+            assert _rel(a, ref) < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["2d_p1_n9", "3d_p2_n3"])
 def test_predictor_and_load_steps_parity(name):
     """The uniform-pressure elastic predictor (pressure and crack volume) and
     the load steps that start from it match the oracle."""
