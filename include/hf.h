@@ -105,6 +105,13 @@ typedef struct {
                           FP32 (default 1) */
   int ir_inner_cycles; /* FP32-IR: GMRES(m) cycles per refinement step, >= 1
                           (default 1: the refinement steps are the restarts) */
+  int ir_stall_steps;  /* FP32-IR: an instance whose true residual falls by
+                          less than half, and by less than a tenth of what
+                          its FP32 cycle estimated, in this many consecutive
+                          refinement steps (FP32 accuracy, not the Krylov
+                          space, limits it: kappa u_32 near 1) finishes its
+                          solve in FP64 GMRES from the current correction;
+                          0: every instance at once, < 0: never (default 2) */
   int incremental_assembly; /* 1: after the first full assembly, re-assemble
                           only the row panels of elements that touch a
                           cohesive or fluid interface, evaluate the other
@@ -144,6 +151,9 @@ typedef struct {
   int ir_steps;        /* refinement steps (FP32-IR), 0 for FP64 */
   int restarts;        /* GMRES cycles */
   int status;          /* hf_status of this instance's solve */
+  int fp64_iters;      /* FP32-IR: iterations of the FP64 GMRES that finished
+                          the solve after the refinement stalled (included in
+                          gmres_iters), 0 otherwise */
   double true_relres;  /* ||b - J dx|| / ||b||, recomputed in FP64 */
   double seconds;      /* wall time of the (batched) solve */
 } hf_solve_stats;

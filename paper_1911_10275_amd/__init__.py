@@ -44,7 +44,8 @@ class Options(C.Structure):
                 ("rtol_inner", C.c_double), ("newton_tol", C.c_double), ("b_stab", C.c_double),
                 ("p_cutoff", C.c_double), ("cutoff_on", C.c_int), ("device", C.c_int),
                 ("profile", C.c_int), ("use_graphs", C.c_int), ("mfma_inverse", C.c_int),
-                ("ir_inner_cycles", C.c_int), ("incremental_assembly", C.c_int),
+                ("ir_inner_cycles", C.c_int), ("ir_stall_steps", C.c_int),
+                ("incremental_assembly", C.c_int),
                 ("fold_preconditioner", C.c_int), ("stream", C.c_void_p)]
 
 
@@ -63,7 +64,8 @@ class Sizes(C.Structure):
 
 class SolveStats(C.Structure):
     _fields_ = [("gmres_iters", C.c_int), ("ir_steps", C.c_int), ("restarts", C.c_int),
-                ("status", C.c_int), ("true_relres", C.c_double), ("seconds", C.c_double)]
+                ("status", C.c_int), ("fp64_iters", C.c_int), ("true_relres", C.c_double),
+                ("seconds", C.c_double)]
 
 
 class NewtonStats(C.Structure):

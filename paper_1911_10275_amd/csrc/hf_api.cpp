@@ -130,6 +130,9 @@ struct hf_ctx {
   // for which one the constant blocks' inverses / FP32 copies were computed
   int32_t *crack_elems = nullptr;  // elements with a cohesive or fluid interface
   int64_t n_crack = 0;
+  int32_t *crack_blocks = nullptr;  // Jacobian blocks in a crack element's row or column
+  int64_t n_crack_blocks = 0;
+  int64_t f64_epoch = -1, f32_epoch = -1;  // assembly epoch of the folded blocks
   bool lin_valid = false;
   double lin_bstab = 0.0;
   int64_t lin_epoch = 0, inv64_epoch = -1, inv32_epoch = -1, a32_epoch = -1;
@@ -405,6 +408,7 @@ extern "C" void hf_default_options(hf_options *o) {
   o->rtol = 1e-10;
   o->rtol_inner = 1e-4;
   o->ir_inner_cycles = 1;
+  o->ir_stall_steps = 2;
   o->newton_tol = 1e-10;
   o->b_stab = 10.0;
   o->p_cutoff = 0.0;
@@ -806,7 +810,7 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
     }
     h.n_p = (int64_t)pidx.size();
     h.n_act = (int64_t)loc_act[b].size();
-    if (h.n_p > 4096)
+    if (h.n_p > kMaxPressureBlock)
       return fail(ctx, HF_EINVAL, "instance " + std::to_string(b) +
                                       ": more than 4096 pressure nodes (dense pressure block limit)");
     for (int32_t f : loc_act[b]) {
@@ -1033,6 +1037,18 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
   TRY(upload(ctx, &m.ident_col, ident_col));
   TRY(upload(ctx, &ctx->crack_elems, crack));
   ctx->n_crack = (int64_t)crack.size();
+  {
+    // the folded blocks A_ef inv_f that change when only the crack elements'
+    // rows and inverses do
+    std::vector<uint8_t> is_crack(s.ne, 0);
+    for (int32_t e : crack) is_crack[e] = 1;
+    std::vector<int32_t> cb;
+    for (int64_t e = 0; e < s.ne; ++e)
+      for (int64_t k = blk_ptr[e]; k < blk_ptr[e + 1]; ++k)
+        if (is_crack[e] || is_crack[blk_col[k]]) cb.push_back((int32_t)k);
+    TRY(upload(ctx, &ctx->crack_blocks, cb));
+    ctx->n_crack_blocks = (int64_t)cb.size();
+  }
   TRY(upload(ctx, &ctx->d_ipar, ctx->ipar));
   TRY(upload(ctx, &ctx->d_einst, einst));
   TRY(upload(ctx, &ctx->d_pinst, pinst));
@@ -1642,6 +1658,7 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
   const int32_t *el64 = (cached && ctx->inv64_epoch == ctx->lin_epoch) ? ctx->crack_elems : nullptr;
   const int32_t *el32 = (cached && ctx->inv32_epoch == ctx->lin_epoch) ? ctx->crack_elems : nullptr;
   bool done = false;
+  bool part32 = false, part64 = false;  // only the crack elements' inverses were recomputed
   if (mfma) {
     {
       ProfScope ps(ctx, P_INV);
@@ -1657,6 +1674,7 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
     ctx->prof.n_inv_mfma += 1;
     if (!tile_fail) {
       done = true;
+      part32 = el32 != nullptr;
       ctx->inv32_epoch = ctx->lin_epoch;
     } else {
       ctx->prof.n_inv_fallback += 1;
@@ -1672,6 +1690,8 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
                            part ? ctx->n_crack : s.ne, ctx->flag, ctx->stream));
     ctx->inv64_epoch = ctx->lin_epoch;
     if (ir) ctx->inv32_epoch = ctx->lin_epoch;
+    part64 = part;
+    part32 = ir && part;
   }
   HIPCHK(launch_schur(kp, ctx->inv, ctx->Bs, ctx->Cs, ctx->D, nullptr, ctx->T, ctx->S, ctx->Sinv,
                       ctx->Sinv32, ctx->flag, ctx->stream));
@@ -1698,7 +1718,12 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
         TRY(dalloc(ctx, &ctx->Cf32, nc));
         TRY(dalloc(ctx, &ctx->tp32, s.n_p));
       }
-      HIPCHK((launch_fold<float, float>(kp, ctx->A, ctx->Cs, ctx->inv32, ctx->Af32, ctx->Cf32, ctx->stream)));
+      // only the blocks in crack rows or columns change when the rest of the
+      // fold is from this assembly epoch and only crack inverses were redone
+      const bool pf = part32 && ctx->f32_epoch == ctx->lin_epoch;
+      HIPCHK((launch_fold<float, float>(kp, ctx->A, ctx->Cs, ctx->inv32, ctx->Af32, ctx->Cf32,
+                                        pf ? ctx->crack_blocks : nullptr, ctx->n_crack_blocks, ctx->stream)));
+      ctx->f32_epoch = ctx->lin_epoch;
       ctx->have_f32 = true;
     } else {
       if (!ctx->Af64) {
@@ -1706,7 +1731,10 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
         TRY(dalloc(ctx, &ctx->Cf64, nc));
         TRY(dalloc(ctx, &ctx->tp64, s.n_p));
       }
-      HIPCHK((launch_fold<double, double>(kp, ctx->A, ctx->Cs, ctx->inv, ctx->Af64, ctx->Cf64, ctx->stream)));
+      const bool pf = part64 && ctx->f64_epoch == ctx->lin_epoch;
+      HIPCHK((launch_fold<double, double>(kp, ctx->A, ctx->Cs, ctx->inv, ctx->Af64, ctx->Cf64,
+                                          pf ? ctx->crack_blocks : nullptr, ctx->n_crack_blocks, ctx->stream)));
+      ctx->f64_epoch = ctx->lin_epoch;
       ctx->have_f64 = true;
     }
   }
@@ -1719,6 +1747,67 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
     note(ctx, b, (ctx->hi[b] & 1) ? "zero or non-finite pivot in an element block"
                                   : "zero or non-finite pivot in the pressure block");
   }
+  return HF_OK;
+}
+
+// FP32-IR instances whose refinement stalled (fb[b] = 1): FP64 block-Jacobi
+// factors for every element (the FP32-IR build made FP64 ones only where the
+// Schur block needs them), then FP64 GMRES on J d = r (r = the current
+// refinement residual, norm rn[b]) to the outer target, and dx += d.
+static hf_status ir_fp64_finish(hf_ctx *ctx, const std::vector<int> &fb, const std::vector<double> &bnorm,
+                                const std::vector<double> &rn, std::vector<hf_solve_stats> &ls,
+                                std::vector<hf_status> &st) {
+  const Sizes &s = ctx->s;
+  const int B = nI(ctx);
+  const KParams kp = kparams(ctx);
+  KrylovDev &kd = ctx->kd;
+  if (!ctx->have_m64) {
+    ProfScope ps(ctx, P_INV);
+    HIPCHK(launch_blockinv(kp, ctx->A, ctx->inv, nullptr, nullptr, s.ne, ctx->flag, ctx->stream));
+    ctx->inv64_epoch = ctx->lin_epoch;
+    ctx->have_m64 = true;
+  }
+  Ops<double> op{ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->inv, ctx->Sinv};
+  if (ctx->opt.fold_preconditioner) {
+    if (!ctx->have_f64) {
+      ProfScope ps(ctx, P_INV);
+      if (!ctx->Af64) {
+        TRY(dalloc(ctx, &ctx->Af64, s.n_blocks * s.bu * s.bu));
+        TRY(dalloc(ctx, &ctx->Cf64, s.n_strip * s.bu));
+        TRY(dalloc(ctx, &ctx->tp64, s.n_p));
+      }
+      HIPCHK((launch_fold<double, double>(kp, ctx->A, ctx->Cs, ctx->inv, ctx->Af64, ctx->Cf64, nullptr, 0,
+                                          ctx->stream)));
+      ctx->f64_epoch = ctx->lin_epoch;
+      ctx->have_f64 = true;
+    }
+    op.Af = ctx->Af64;
+    op.Cf = ctx->Cf64;
+    op.tp = ctx->tp64;
+  }
+  TRY(ensure_ws<double>(ctx, ctx->k64));
+  std::vector<double> tol(B, 0.5);
+  std::vector<int> cap(B, 0);
+  for (int b = 0; b < B; ++b)
+    if (fb[b]) {
+      tol[b] = std::min(0.5, ctx->opt.rtol * bnorm[b] / rn[b]);
+      cap[b] = ctx->opt.gmres_maxit - ls[b].gmres_iters;
+    }
+  std::vector<SolveOut> out;
+  TRY(gmres_b<double>(ctx, op, ctx->k64, ctx->r64, ctx->t64, tol, true, fb, cap, out));
+  std::vector<double> one(B, 0.0);
+  for (int b = 0; b < B; ++b) {
+    if (!fb[b]) continue;
+    one[b] = 1.0;
+    ls[b].gmres_iters += out[b].iters;
+    ls[b].fp64_iters = out[b].iters;
+    ls[b].restarts += out[b].restarts;
+    ls[b].true_relres = out[b].relres * rn[b] / bnorm[b];
+    st[b] = out[b].st;
+  }
+  TRY(put(ctx, kd.solving, fb));
+  TRY(put(ctx, ctx->k_coef, one));
+  HIPCHK((ks_axpy<double, double>(kd, ctx->k_coef, ctx->t64, ctx->dx, ctx->stream)));
   return HF_OK;
 }
 
@@ -1786,6 +1875,11 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
     // GMRES(m) (the restart residual computed in FP64), so FP32 rounding only
     // enters the per-cycle reduction, far above the FP32 floor
     const int cap_inner = ctx->opt.ir_inner_cycles * ctx->opt.gmres_m;
+    // stall test: a refinement step whose true reduction is both weak and far
+    // short of its FP32 estimate is limited by FP32 accuracy
+    std::vector<double> rn_prev(B, 0.0), est(B, 1.0);
+    std::vector<int> slow(B, 0), fb(B, 0);
+    const int stall = ctx->opt.ir_stall_steps;
     for (int outer = 0;; ++outer) {
       HIPCHK(ks_norms<double>(kd, ctx->r64, ctx->partial, ctx->red, stm));
       TRY(get_d(ctx, ctx->red, B));
@@ -1794,11 +1888,19 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
         if (!on[b]) continue;
         rn[b] = std::sqrt(ctx->hd[b]);
         ls[b].true_relres = rn[b] / bnorm[b];
+        if (outer > 0) {
+          const double got = rn[b] / rn_prev[b];
+          slow[b] = (got > 0.5 && got > 10.0 * est[b]) ? slow[b] + 1 : 0;
+        }
+        rn_prev[b] = rn[b];
         if (!std::isfinite(rn[b])) {
           st[b] = HF_ENONFINITE;
           note(ctx, b, "non-finite refinement residual");
           on[b] = 0;
         } else if (rn[b] <= ctx->opt.rtol * bnorm[b]) {
+          on[b] = 0;
+        } else if (stall >= 0 && slow[b] >= stall && ls[b].gmres_iters < ctx->opt.gmres_maxit) {
+          fb[b] = 1;  // finished in FP64 below
           on[b] = 0;
         } else if (outer >= ctx->opt.ir_maxit || ls[b].gmres_iters >= ctx->opt.gmres_maxit) {
           st[b] = HF_ENOCONV;
@@ -1830,6 +1932,7 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
         ls[b].gmres_iters += out[b].iters;
         ls[b].restarts += out[b].restarts;
         ls[b].ir_steps += 1;
+        est[b] = out[b].relres;
         coef[b] = rn[b];
         if (out[b].st == HF_ENONFINITE) {
           st[b] = HF_ENONFINITE;
@@ -1843,6 +1946,9 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
       TRY(apply_J<double>(ctx, kp, op64, ctx->dx, ctx->t64, rows(ctx, 1)));
       HIPCHK(ks_sub<double>(kd, ctx->rhs, ctx->t64, ctx->r64, stm));
     }
+    bool anyfb = false;
+    for (int b = 0; b < B; ++b) anyfb = anyfb || fb[b];
+    if (anyfb) TRY(ir_fp64_finish(ctx, fb, bnorm, rn, ls, st));
   }
   TRY(sync(ctx));
   const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1963,6 +2069,7 @@ extern "C" hf_status hf_newton_solve(hf_ctx *ctx, hf_newton_stats *stats) {
       a.lin.gmres_iters += one[b].lin.gmres_iters;
       a.lin.ir_steps += one[b].lin.ir_steps;
       a.lin.restarts += one[b].lin.restarts;
+      a.lin.fp64_iters += one[b].lin.fp64_iters;
       a.lin.true_relres = std::max(a.lin.true_relres, one[b].lin.true_relres);
       a.lin.seconds += one[b].lin.seconds;
       a.lin.status = one[b].lin.status;

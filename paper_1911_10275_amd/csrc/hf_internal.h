@@ -30,6 +30,7 @@ constexpr int kMaxNq = 9;      // face points of 3D P2 (3 x 3)
 constexpr int kMaxKrylov = 257;  // basis vectors (restart length + 1)
 constexpr int kMaxNqv = 8;     // volume points of 3D P2 (2 x 2 x 2)
 constexpr int kChunkRows = 1024;  // rows of a reduction chunk of the batched Krylov kernels
+constexpr int kMaxPressureBlock = 4096;  // pressure nodes per instance (dense pressure block)
 
 // Rule tables, in the device constant bank (set per context before launch).
 struct RuleTables {
@@ -172,11 +173,12 @@ hipError_t launch_blockinv32_mfma(const KParams &kp, const double *A, float *inv
                                   const int32_t *elist, int64_t n, int *flag, hipStream_t st);
 hipError_t launch_convert_panels(const KParams &kp, const int32_t *elist, int64_t n, const double *A,
                                  float *A32, hipStream_t st);
-// folded preconditioned operator: Af = A_ef inv_f for every block of the row
-// panels, Cf = C_e inv_e for every C strip entry (FP64 arithmetic)
+// folded preconditioned operator: Af = A_ef inv_f for the nblk blocks of the
+// row panels in blist (every block when blist is null), Cf = C_e inv_e for
+// every C strip entry (FP64 arithmetic)
 template <typename TI, typename TO>
 hipError_t launch_fold(const KParams &kp, const double *A, const double *Cs, const TI *inv, TO *Af, TO *Cf,
-                       hipStream_t st);
+                       const int32_t *blist, int64_t nblk, hipStream_t st);
 // flag[b] |= 2 on a zero or non-finite pivot in the pressure block of instance b
 hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,
                         const double *Cs, const double *D, double *Z, double *T, double *S,

@@ -555,37 +555,48 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const int32_t *__re
 // Fluid rows: R_p and the dense row of D, one thread per pressure node
 // ---------------------------------------------------------------------------
 template <int DIM, int ORDER>
-__global__ void k_fluid_rows(KParams kp, const double *__restrict__ u,
-                             const double *__restrict__ p, const double *__restrict__ w_old,
-                             double *__restrict__ R, double *__restrict__ D) {
+__global__ __launch_bounds__(64) void k_fluid_rows(KParams kp, const double *__restrict__ u,
+                                                   const double *__restrict__ p,
+                                                   const double *__restrict__ w_old,
+                                                   double *__restrict__ R, double *__restrict__ D) {
   using C = Cfg<DIM, ORDER>;
   constexpr int NN = C::NN, BU = C::BU, NQF = C::NQF, NNF = C::NNF;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= kp.s.n_p) return;
+  __shared__ double srow[kMaxPressureBlock];  // the dense row of D being summed
+  __shared__ double s_r[64], s_d[64][NNF];
+  __shared__ int s_c[64][NNF];
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
   const int b = kp.pinst[i];
   const InstPar P = kp.ip[b];
   const int32_t p0 = kp.poff[b];
-  const int64_t nb = kp.poff[b + 1] - p0;
-  double *Drow = D + kp.doff[b] + (i - p0) * nb;
-  for (int64_t j = 0; j < nb; ++j) Drow[j] = 0.0;
+  const int nb = kp.poff[b + 1] - p0;
+  double *Drow = D + kp.doff[b] + (i - p0) * (int64_t)nb;
   if (kp.freeze_p) {  // pressure held at its current value: dp = 0
-    Drow[i - p0] = 1.0;
-    R[kp.s.n_u + i] = 0.0;
+    for (int j = lane; j < nb; j += 64) Drow[j] = (j == i - p0) ? 1.0 : 0.0;
+    if (lane == 0) R[kp.s.n_u + i] = 0.0;
     return;
   }
-  double Ri = 0.0;
-  for (int32_t t = kp.m.pf_ptr[i]; t < kp.m.pf_ptr[i + 1]; ++t) {
-    const int32_t fa = kp.m.pf_fa[t], kk = kp.m.pf_k[t];
-    const int32_t f = kp.m.act_face[fa];
-    const int32_t em = kp.m.face_em[f], ep = kp.m.face_ep[f];
-    double n[DIM];
-    for (int x = 0; x < DIM; ++x) n[x] = kp.m.normal[(int64_t)f * DIM + x];
-    const double area = kp.m.area[f];
-    double gi[(DIM - 1) * (DIM - 1)];
-    for (int s = 0; s < (DIM - 1) * (DIM - 1); ++s) gi[s] = kp.m.ginv[(int64_t)f * (DIM - 1) * (DIM - 1) + s];
-    int32_t pn[NNF];
-    for (int k = 0; k < NNF; ++k) pn[k] = kp.m.face_pn[(int64_t)fa * NNF + k];
-    for (int q = 0; q < NQF; ++q) {
+  for (int j = lane; j < nb; j += 64) srow[j] = 0.0;
+  const int32_t t0 = kp.m.pf_ptr[i];
+  const int nfq = (kp.m.pf_ptr[i + 1] - t0) * NQF;
+  double Ri = 0.0;  // lane NNF sums the residual terms
+  for (int base = 0; base < nfq; base += 64) {
+    // one (face, point) term per lane: its residual part and its NNF
+    // contributions to the row of D
+    const int idx = base + lane;
+    if (idx < nfq) {
+      const int32_t t = t0 + idx / NQF;
+      const int q = idx % NQF;
+      const int32_t fa = kp.m.pf_fa[t], kk = kp.m.pf_k[t];
+      const int32_t f = kp.m.act_face[fa];
+      const int32_t em = kp.m.face_em[f], ep = kp.m.face_ep[f];
+      double n[DIM];
+      for (int x = 0; x < DIM; ++x) n[x] = kp.m.normal[(int64_t)f * DIM + x];
+      const double area = kp.m.area[f];
+      double gi[(DIM - 1) * (DIM - 1)];
+      for (int s2 = 0; s2 < (DIM - 1) * (DIM - 1); ++s2) gi[s2] = kp.m.ginv[(int64_t)f * (DIM - 1) * (DIM - 1) + s2];
+      int32_t pn[NNF];
+      for (int k = 0; k < NNF; ++k) pn[k] = kp.m.face_pn[(int64_t)fa * NNF + k];
       double lm[DIM + 1], lp[DIM + 1];
       for (int k = 0; k <= DIM; ++k) lm[k] = lp[k] = 0.0;
       for (int k = 0; k < DIM; ++k) {
@@ -606,34 +617,49 @@ __global__ void k_fluid_rows(KParams kp, const double *__restrict__ u,
       double mu_[DIM];
       for (int k = 0; k < DIM; ++k) mu_[k] = c_rules.fq_mu[q][k];
       double gp[DIM - 1];
-      for (int s = 0; s < DIM - 1; ++s) gp[s] = 0.0;
+      for (int s2 = 0; s2 < DIM - 1; ++s2) gp[s2] = 0.0;
       for (int k = 0; k < NNF; ++k) {
         double dmu[DIM];
         Lag<DIM - 1, ORDER>::dphi_one(k, mu_, dmu);
-        for (int s = 0; s < DIM - 1; ++s) gp[s] += (dmu[s + 1] - dmu[0]) * p[pn[k]];
+        for (int s2 = 0; s2 < DIM - 1; ++s2) gp[s2] += (dmu[s2 + 1] - dmu[0]) * p[pn[k]];
       }
       double dk[DIM];
       Lag<DIM - 1, ORDER>::dphi_one(kk, mu_, dk);
       const double etak = Lag<DIM - 1, ORDER>::phi_one(kk, mu_);
       const double W = c_rules.fq_w[q] * area;
       double gpg = 0.0;
-      for (int s = 0; s < DIM - 1; ++s)
-        for (int t2 = 0; t2 < DIM - 1; ++t2) gpg += gp[s] * gi[s * (DIM - 1) + t2] * (dk[t2 + 1] - dk[0]);
+      for (int s2 = 0; s2 < DIM - 1; ++s2)
+        for (int t2 = 0; t2 < DIM - 1; ++t2) gpg += gp[s2] * gi[s2 * (DIM - 1) + t2] * (dk[t2 + 1] - dk[0]);
       const double wo = w_old[(int64_t)f * NQF + q];
-      Ri += P.s_p * W * (K * gpg + (w - wo) / P.dt * etak);
+      s_r[lane] = P.s_p * W * (K * gpg + (w - wo) / P.dt * etak);
       for (int l = 0; l < NNF; ++l) {
         double dl[DIM];
         Lag<DIM - 1, ORDER>::dphi_one(l, mu_, dl);
         double gg = 0.0;
-        for (int s = 0; s < DIM - 1; ++s)
-          for (int t2 = 0; t2 < DIM - 1; ++t2) gg += (dl[s + 1] - dl[0]) * gi[s * (DIM - 1) + t2] * (dk[t2 + 1] - dk[0]);
-        Drow[pn[l] - p0] += P.s_p * W * K * gg;
+        for (int s2 = 0; s2 < DIM - 1; ++s2)
+          for (int t2 = 0; t2 < DIM - 1; ++t2) gg += (dl[s2 + 1] - dl[0]) * gi[s2 * (DIM - 1) + t2] * (dk[t2 + 1] - dk[0]);
+        s_d[lane][l] = P.s_p * W * K * gg;
+        s_c[lane][l] = pn[l] - p0;
       }
     }
+    __syncthreads();
+    // sum in (face, point) order: at each term the NNF lanes touch NNF
+    // distinct columns (the face's pressure nodes), so every column and the
+    // residual receive their terms in the same order as a serial loop
+    const int cnt = min(64, nfq - base);
+    if (lane < NNF) {
+      for (int k = 0; k < cnt; ++k) srow[s_c[k][lane]] += s_d[k][lane];
+    } else if (lane == NNF) {
+      for (int k = 0; k < cnt; ++k) Ri += s_r[k];
+    }
+    __syncthreads();
   }
-  for (int64_t s = 0; s < kp.s.n_src; ++s)
-    if (kp.m.src_node[s] == i) Ri -= P.s_p * kp.m.src_q0[s];
-  R[kp.s.n_u + i] = Ri;
+  for (int j = lane; j < nb; j += 64) Drow[j] = srow[j];
+  if (lane == NNF) {
+    for (int64_t s2 = 0; s2 < kp.s.n_src; ++s2)
+      if (kp.m.src_node[s2] == i) Ri -= P.s_p * kp.m.src_q0[s2];
+    R[kp.s.n_u + i] = Ri;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -737,8 +763,8 @@ static hipError_t assemble_impl(const KParams &kp, const double *u, const double
   if (n_el) hipLaunchKernelGGL((k_assemble<DIM, ORDER, NT>), dim3((unsigned)n_el), dim3(NT), 0, st,
                                kp, elist, u, p, w_old, A, R, Bs, Cs);
   if (kp.s.n_p)
-    hipLaunchKernelGGL((k_fluid_rows<DIM, ORDER>), dim3((unsigned)((kp.s.n_p + 63) / 64)), dim3(64), 0,
-                       st, kp, u, p, w_old, R, D);
+    hipLaunchKernelGGL((k_fluid_rows<DIM, ORDER>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp, u, p,
+                       w_old, R, D);
   return hipGetLastError();
 }
 

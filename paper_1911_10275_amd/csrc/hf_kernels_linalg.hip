@@ -278,13 +278,14 @@ hipError_t launch_convert_panels(const KParams &kp, const int32_t *elist, int64_
 // of the result.
 // ---------------------------------------------------------------------------
 template <int BU, typename TI, typename TO>
-__global__ __launch_bounds__(256) void k_fold_blocks(int64_t n_blocks, const int32_t *__restrict__ blk_col,
+__global__ __launch_bounds__(256) void k_fold_blocks(int64_t n_blocks, const int32_t *__restrict__ blist,
+                                                     const int32_t *__restrict__ blk_col,
                                                      const double *__restrict__ A,
                                                      const TI *__restrict__ inv, TO *__restrict__ Af) {
   constexpr int B2 = BU * BU;
   __shared__ double sa[B2], si[B2];
-  const int64_t blk = blockIdx.x;
-  if (blk >= n_blocks) return;
+  if ((int64_t)blockIdx.x >= n_blocks) return;
+  const int64_t blk = blist ? (int64_t)blist[blockIdx.x] : (int64_t)blockIdx.x;
   const int64_t f = blk_col[blk];
   const double *a = A + blk * B2;
   const TI *iv = inv + f * B2;
@@ -318,11 +319,11 @@ __global__ __launch_bounds__(256) void k_fold_cstrips(int64_t n_strip, const int
 
 template <int BU, typename TI, typename TO>
 static void fold_bu(const KParams &kp, const double *A, const double *Cs, const TI *inv, TO *Af, TO *Cf,
-                    hipStream_t st) {
+                    const int32_t *blist, int64_t nblk, hipStream_t st) {
   constexpr int NT = BU * BU >= 256 ? 256 : (BU * BU + 63) / 64 * 64;
-  if (kp.s.n_blocks)
-    hipLaunchKernelGGL((k_fold_blocks<BU, TI, TO>), dim3((unsigned)kp.s.n_blocks), dim3(NT), 0, st,
-                       kp.s.n_blocks, kp.m.blk_col, A, inv, Af);
+  if (nblk)
+    hipLaunchKernelGGL((k_fold_blocks<BU, TI, TO>), dim3((unsigned)nblk), dim3(NT), 0, st, nblk, blist,
+                       kp.m.blk_col, A, inv, Af);
   const int64_t nc = kp.s.n_strip * BU;
   if (nc)
     hipLaunchKernelGGL((k_fold_cstrips<BU, TI, TO>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st,
@@ -331,19 +332,21 @@ static void fold_bu(const KParams &kp, const double *A, const double *Cs, const 
 
 template <typename TI, typename TO>
 hipError_t launch_fold(const KParams &kp, const double *A, const double *Cs, const TI *inv, TO *Af, TO *Cf,
-                       hipStream_t st) {
+                       const int32_t *blist, int64_t nblk, hipStream_t st) {
+  if (!blist) nblk = kp.s.n_blocks;
   switch (kp.s.bu) {
-    case 6: fold_bu<6>(kp, A, Cs, inv, Af, Cf, st); break;
-    case 12: fold_bu<12>(kp, A, Cs, inv, Af, Cf, st); break;
-    case 30: fold_bu<30>(kp, A, Cs, inv, Af, Cf, st); break;
+    case 6: fold_bu<6>(kp, A, Cs, inv, Af, Cf, blist, nblk, st); break;
+    case 12: fold_bu<12>(kp, A, Cs, inv, Af, Cf, blist, nblk, st); break;
+    case 30: fold_bu<30>(kp, A, Cs, inv, Af, Cf, blist, nblk, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 template hipError_t launch_fold<double, double>(const KParams &, const double *, const double *,
-                                                const double *, double *, double *, hipStream_t);
+                                                const double *, double *, double *, const int32_t *, int64_t,
+                                                hipStream_t);
 template hipError_t launch_fold<float, float>(const KParams &, const double *, const double *, const float *,
-                                              float *, float *, hipStream_t);
+                                              float *, float *, const int32_t *, int64_t, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Schur pressure block S = D - C M_A^-1 B (dense n_p x n_p) and its inverse

@@ -192,17 +192,38 @@ def test_newton_load_steps_unfolded(name, precision):
     ctx.close()
 
 
+@pytest.mark.parametrize("name", ["2d_p1_n9", "3d_p2_n3"])
+def test_ir_fp64_finish(name):
+    """The FP64 finish of a stalled GMRES-IR solve, forced for every solve
+    (ir_stall_steps = 0): each solve runs entirely in FP64 GMRES on the
+    refinement residual, and the converged states match the oracle."""
+    prob = SMALL[name]()
+    case, ctx = _pair(prob)
+    ctx.set_options(ir_stall_steps=0)
+    ref = newton.run(case, prob.load_steps, solver="gmres")
+    got = _gpu_run(ctx, case, prob.load_steps, hf.HF_FP32_IR)
+    for (st, _), ((u, p, w, wo), ns) in zip(ref, got):
+        assert np.linalg.norm(u - st.u) <= 1e-8 * np.linalg.norm(st.u)
+        assert np.linalg.norm(p - st.p) <= 1e-8 * np.linalg.norm(st.p)
+        assert ns.lin.ir_steps == 0 and ns.lin.fp64_iters == ns.lin.gmres_iters > 0
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", list(SMALL))
 def test_folded_operator(name):
     """J M^-1 x from the folded blocks equals M^-1 then J (FP64: 1e-13 of the
     largest entry; FP32: 1e-5, the two round differently) and the oracle's
-    J M^-1 x with its own block inverses and Schur block (1e-10)."""
+    J M^-1 x with its own block inverses and Schur block (1e-10).  Two states
+    per precision: the second build re-inverts and re-folds only what the
+    crack elements touch."""
     torch = pytest.importorskip("torch")
     prob = SMALL[name]()
     case, ctx = _pair(prob)
-    u, p, wo = _random_state(case, 8)
     rng = np.random.default_rng(9)
-    for precision, dt, tol in ((hf.HF_FP64, torch.float64, 1e-13), (hf.HF_FP32_IR, torch.float32, 1e-5)):
+    for precision, dt, tol, seed in ((hf.HF_FP64, torch.float64, 1e-13, 8), (hf.HF_FP64, torch.float64, 1e-13, 10),
+                                     (hf.HF_FP32_IR, torch.float32, 1e-5, 8),
+                                     (hf.HF_FP32_IR, torch.float32, 1e-5, 10)):
+        u, p, wo = _random_state(case, seed)
         ctx.set_options(precision=precision, gmres_maxit=1)
         ctx.set_state(u, p, wo)
         ctx.assemble()
