@@ -106,7 +106,7 @@ typedef struct {
   int ir_inner_cycles; /* FP32-IR: GMRES(m) cycles per refinement step, >= 1
                           (default 1: the refinement steps are the restarts) */
   int ir_stall_steps;  /* FP32-IR: an instance whose true residual falls by
-                          less than half, and by less than a tenth of what
+                          less than 10%, and by less than a tenth of what
                           its FP32 cycle estimated, in this many consecutive
                           refinement steps (FP32 accuracy, not the Krylov
                           space, limits it: kappa u_32 near 1) finishes its

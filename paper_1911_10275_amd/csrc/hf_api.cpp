@@ -1890,7 +1890,7 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
         ls[b].true_relres = rn[b] / bnorm[b];
         if (outer > 0) {
           const double got = rn[b] / rn_prev[b];
-          slow[b] = (got > 0.5 && got > 10.0 * est[b]) ? slow[b] + 1 : 0;
+          slow[b] = (got > 0.9 && got > 10.0 * est[b]) ? slow[b] + 1 : 0;
         }
         rn_prev[b] = rn[b];
         if (!std::isfinite(rn[b])) {
