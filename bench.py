@@ -15,7 +15,8 @@ throughput, the same steps in FP32-IR mode (speed-up and state error
 against FP64), the roofline of the dominant kernel (block-sparse Jacobian
 product, timed with HIP events on the library stream inside the timed
 region: the GMRES iterations replay captured HIP graphs, so the events time
-the products outside them, one per restart cycle, same kernel and data), the
+the product outside them that gives each incremental assembly's residual
+rows, the same kernel and pattern as the iterations' products), the
 batched ensemble workload (64 2D instances, see ``ensemble_block``), and the
 CPU oracle timed on a bounded sample of the same workload.
 """
@@ -164,7 +165,7 @@ def counters_probe(prob):
     ctx.close()
 
 
-def ensemble_block(K, gmres_m):
+def ensemble_block(K, gmres_m, tune_level=1):
     """The batched 2D KGD ensemble: 64 instances (1k-20k triangles, mixed P1 /
     P2, materials and injection drawn per instance).  The P1 and the P2
     instances each form one batched context (every kernel launch covers all
@@ -172,7 +173,8 @@ def ensemble_block(K, gmres_m):
     streams from two host threads.  One ensemble step = one Newton iteration
     (assemble, block-Jacobi, GMRES to 1e-10, update) of every instance, from
     the uniform-pressure predictor; K timed steps after one warm-up step and
-    a reset, in FP64 and in FP32-IR.  A linear solve that has not reached
+    a reset, in FP64 and in FP32-IR, each context autotuned (untimed, cached)
+    on its predictor state first.  A linear solve that has not reached
     1e-10 within 6,000 GMRES iterations counts as failed (reported; its
     instance keeps its state and its step is not counted)."""
     import threading
@@ -205,10 +207,16 @@ def ensemble_block(K, gmres_m):
             sink.append(c.newton_step(check=False))
 
     res = {}
+    cache = os.path.join(ROOT, "paper_1911_10275_amd", "tuning_cache.txt")
     for name, prec in (("fp64", hf.HF_FP64), ("fp32_ir", hf.HF_FP32_IR)):
+        tuned = []
         for c, st in zip(ctxs, starts):
             c.set_options(precision=prec)
             reset(c, st)
+            if tune_level >= 0:
+                c.assemble()
+                tuned.append(c.autotune(level=tune_level, cache_path=cache).as_dict())
+                reset(c, st)
             c.newton_step(check=False)
             reset(c, st)
         torch.cuda.synchronize()
@@ -229,7 +237,8 @@ def ensemble_block(K, gmres_m):
                      "ms_per_step": 1e3 * dt / K, "gmres_iters_per_s": gits / dt,
                      "failed_solves": len(flat) - len(ok),
                      "fp64_finished_solves": sum(1 for n in flat if n.lin.fp64_iters > 0),
-                     "max_true_relres_converged": max(n.lin.true_relres for n in ok)}
+                     "max_true_relres_converged": max(n.lin.true_relres for n in ok),
+                     "tuning": tuned}
         print(f"bench: ensemble {name} {K} steps in {dt:.3f} s", file=sys.stderr, flush=True)
     for c in ctxs:
         c.close()
@@ -341,7 +350,8 @@ def main():
                      "avg_launch_ms": spmv_ms, "launches": int(prof.n_spmv64)},
         # HIP-event times of the launches outside the graph-replayed GMRES chunks
         "kernel_ms_outside_graphs": {"assemble": prof.ms_assemble, "spmv64": prof.ms_spmv64,
-                                     "precond": prof.ms_precond, "blockinv": prof.ms_blockinv},
+                                     "precond": prof.ms_precond, "blockinv": prof.ms_blockinv,
+                                     "resid": prof.ms_resid},
         # the timed steps' assemblies are incremental (the context's first, full one ran
         # before timing): the product with the cached blocks (its bytes are a lower bound of
         # the assembly's algorithmic bytes) plus the crack elements and the fluid rows
@@ -373,7 +383,7 @@ def main():
     ctx.close()
     out["tuning"] = tuned
     if not args.no_ensemble:
-        out["ensemble"] = ensemble_block(args.ensemble_steps, args.ensemble_m)
+        out["ensemble"] = ensemble_block(args.ensemble_steps, args.ensemble_m, args.tune)
     if not args.no_cpu:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob, float(np.mean(iters64)))

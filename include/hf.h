@@ -192,7 +192,7 @@ typedef struct {
                           solves of GMRES-IR use CGS2 (single-pass schemes
                           lose orthogonality faster in FP32).  hf_autotune
                           level 1 chooses between 0 and 3 (FP64) or 0 and 4
-                          (FP32-IR). */
+                          (FP32-IR, single-instance contexts; batches keep 0). */
   int gmres_m;         /* restart length (0 = keep hf_options.gmres_m) */
   int reserved[3];
 } hf_tuning;
@@ -205,6 +205,14 @@ typedef struct {
   /* preconditioner builds with the matrix-core FP32 inverses, and those that
      fell back to FP64 Gauss-Jordan (counted whatever hf_options.profile is) */
   int64_t n_inv_mfma, n_inv_fallback;
+  /* FP64 residuals b - J x of the restarts and refinement steps (compensated
+     accumulation) */
+  double ms_resid;
+  int64_t n_resid;
+  /* FP64 solves that went on with M^-1 then J after the folded operator held
+     the true residual above the target for two cycles (counted whatever
+     hf_options.profile is) */
+  int64_t n_unfold;
 } hf_profile;
 
 /* Fill *opt with the defaults listed above. */

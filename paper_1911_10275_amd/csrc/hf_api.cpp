@@ -311,7 +311,7 @@ bool trace_on() {
 }
 
 // ---- profiling of kernel classes ------------------------------------------
-enum ProfClass { P_ASM = 0, P_INV, P_SPMV64, P_SPMV32, P_PREC, P_ORTHO, P_NCLASS };
+enum ProfClass { P_ASM = 0, P_INV, P_SPMV64, P_SPMV32, P_PREC, P_ORTHO, P_RESID, P_NCLASS };
 
 int take_event(hf_ctx *ctx) {
   if (ctx->ev_used == ctx->evpool.size()) {
@@ -349,9 +349,11 @@ void resolve_profile(hf_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   ctx->hu_pending = false;
   double *ms[P_NCLASS] = {&ctx->prof.ms_assemble, &ctx->prof.ms_blockinv, &ctx->prof.ms_spmv64,
-                          &ctx->prof.ms_spmv32, &ctx->prof.ms_precond, &ctx->prof.ms_ortho};
+                          &ctx->prof.ms_spmv32, &ctx->prof.ms_precond, &ctx->prof.ms_ortho,
+                          &ctx->prof.ms_resid};
   int64_t *cnt[P_NCLASS] = {&ctx->prof.n_assemble, &ctx->prof.n_blockinv, &ctx->prof.n_spmv64,
-                            &ctx->prof.n_spmv32, &ctx->prof.n_precond, &ctx->prof.n_ortho};
+                            &ctx->prof.n_spmv32, &ctx->prof.n_precond, &ctx->prof.n_ortho,
+                            &ctx->prof.n_resid};
   for (const auto &pe : ctx->ev_pending) {
     float t = 0.f;
     if (hipEventElapsedTime(&t, ctx->evpool[pe[1]], ctx->evpool[pe[2]]) == hipSuccess) {
@@ -1287,8 +1289,11 @@ static hf_status do_assemble(hf_ctx *ctx, std::vector<double> &rn) {
       // the rows of elements without cohesive or fluid interfaces are linear
       // in u with the cached blocks: R = A u for them (the other rows, the
       // strips and the fluid rows are recomputed below)
-      HIPCHK(launch_spmv<double>(kp, ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->xs, ctx->R, RowSel{},
-                                 ctx->stream));
+      {
+        ProfScope pj(ctx, P_SPMV64);  // the Jacobian product, timed on its own as well
+        HIPCHK(launch_spmv<double>(kp, ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->xs, ctx->R, RowSel{},
+                                   ctx->stream));
+      }
       HIPCHK(launch_assemble(kp, ctx->xs, ctx->xs + s.n_u, ctx->w_old, ctx->A, ctx->R, ctx->Bs,
                              ctx->Cs, ctx->D, ctx->crack_elems, ctx->n_crack, ctx->stream));
     } else {
@@ -1406,6 +1411,24 @@ static hf_status apply_M(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const
   return HF_OK;
 }
 
+// r = b - J x: in FP64 with compensated accumulation (the restart and
+// refinement residuals decide convergence, and near a Newton solution ||J||
+// ||x|| can exceed ||b|| by the factor that separates FP64 rounding from the
+// requested 1e-10); the FP32 inner solves form J x (into t) and subtract
+template <typename T>
+static hf_status residual(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *b, const T *x, T *t, T *r,
+                          const RowSel &sel) {
+  if constexpr (sizeof(T) == 8) {
+    (void)t;
+    ProfScope ps(ctx, P_RESID);
+    HIPCHK(launch_resid(kp, op.A, op.Bs, op.Cs, op.D, x, b, r, sel, ctx->stream));
+  } else {
+    TRY(apply_J<T>(ctx, kp, op, x, t, sel));
+    HIPCHK(ks_sub<T>(ctx->kd, b, t, r, ctx->stream));
+  }
+  return HF_OK;
+}
+
 // w = J M^-1 v: one product with the folded blocks when they are built,
 // else the block-Jacobi apply into z followed by the Jacobian product
 template <typename T>
@@ -1472,8 +1495,8 @@ static hf_status arnoldi_step(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, 
 // Arnoldi steps j0 .. j1-1, replayed from a captured graph when enabled
 template <typename T>
 static hf_status arnoldi_chunk(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, KrylovWs<T> &ws,
-                               int j0, int j1) {
-  if (!ctx->opt.use_graphs) {
+                               int j0, int j1, bool eager = false) {
+  if (!ctx->opt.use_graphs || eager) {
     for (int j = j0; j < j1; ++j) TRY(arnoldi_step<T>(ctx, kp, op, ws, j));
     return HF_OK;
   }
@@ -1509,10 +1532,20 @@ static hf_status arnoldi_chunk(hf_ctx *ctx, const KParams &kp, const Ops<T> &op,
 // explicit_check the residual b - J x is then recomputed and decides; without
 // it (the inner solve of GMRES-IR) the estimate decides.  out[b] receives the
 // iterations, cycles, relative residual and status of each solved instance.
+// With the folded operator, the Arnoldi operator and the residual operator
+// differ by rounding; on a nearly singular mode with a large solution
+// component that difference can hold the true residual just above the
+// target while every cycle's estimate reaches it.  After two such cycles of
+// an instance (explicit check only) the solve goes on with the operator
+// `alt` (M^-1 then J, the residual's own order), launched eagerly.
 template <typename T>
 static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T *bvec, T *x,
                          const std::vector<double> &rtol, bool explicit_check, std::vector<int> on,
-                         const std::vector<int> &cap, std::vector<SolveOut> &out) {
+                         const std::vector<int> &cap, std::vector<SolveOut> &out,
+                         const Ops<T> *alt = nullptr) {
+  const Ops<T> *cur = &op;
+  bool switched = false;
+  std::vector<int> miss(nI(ctx), 0);
   const KParams kp = kparams(ctx);
   const int64_t N = ctx->s.N();
   const int m = ws.m, B = nI(ctx);
@@ -1568,7 +1601,7 @@ static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T
     HIPCHK(ks_scale<T>(kd, ws.r, ctx->k_scale, ws.V, st));
     for (int j0 = 0; j0 < m; j0 += kIterChunk) {
       const int j1 = std::min(j0 + kIterChunk, m);
-      TRY(arnoldi_chunk<T>(ctx, kp, op, ws, j0, j1));
+      TRY(arnoldi_chunk<T>(ctx, kp, *cur, ws, j0, j1, switched));
       if (j1 == m) break;
       HIPCHK(ks_count_active(kd, ctx->k_count, st));
       TRY(get_i_async(ctx, ctx->k_count, 1, 0));
@@ -1594,8 +1627,7 @@ static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T
           need_r = true;
     }
     if (need_r) {
-      TRY(apply_J<T>(ctx, kp, op, x, ws.w, rows(ctx, 1)));
-      HIPCHK(ks_sub<T>(kd, bvec, ws.w, ws.r, st));
+      TRY(residual<T>(ctx, kp, op, bvec, x, ws.w, ws.r, rows(ctx, 1)));
       HIPCHK(ks_norms<T>(kd, ws.r, ctx->partial, ctx->k_beta2, st));
     }
     TRY(get_i_async(ctx, kd.its, B, 0));
@@ -1620,6 +1652,18 @@ static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T
       } else if (!explicit_check && (est[b] <= rtol[b] * bnorm[b] || its[b] >= cap[b])) {
         out[b].relres = est[b] / bnorm[b];
         on[b] = 0;
+      }
+    }
+    if (explicit_check && alt && !switched) {
+      for (int b = 0; b < B; ++b) {
+        if (!on[b]) continue;
+        const double thr = rtol[b] * bnorm[b];
+        miss[b] = (est[b] <= thr && std::sqrt(beta2[b]) > thr) ? miss[b] + 1 : 0;
+        if (miss[b] >= 2) switched = true;
+      }
+      if (switched) {
+        cur = alt;
+        ctx->prof.n_unfold += 1;
       }
     }
     if (trace_on())
@@ -1768,6 +1812,7 @@ static hf_status ir_fp64_finish(hf_ctx *ctx, const std::vector<int> &fb, const s
     ctx->have_m64 = true;
   }
   Ops<double> op{ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->inv, ctx->Sinv};
+  const Ops<double> seq = op;
   if (ctx->opt.fold_preconditioner) {
     if (!ctx->have_f64) {
       ProfScope ps(ctx, P_INV);
@@ -1794,7 +1839,7 @@ static hf_status ir_fp64_finish(hf_ctx *ctx, const std::vector<int> &fb, const s
       cap[b] = ctx->opt.gmres_maxit - ls[b].gmres_iters;
     }
   std::vector<SolveOut> out;
-  TRY(gmres_b<double>(ctx, op, ctx->k64, ctx->r64, ctx->t64, tol, true, fb, cap, out));
+  TRY(gmres_b<double>(ctx, op, ctx->k64, ctx->r64, ctx->t64, tol, true, fb, cap, out, op.Af ? &seq : nullptr));
   std::vector<double> one(B, 0.0);
   for (int b = 0; b < B; ++b) {
     if (!fb[b]) continue;
@@ -1829,6 +1874,7 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
   if (ctx->opt.precision == HF_FP64) {
     TRY(ensure_ws<double>(ctx, ctx->k64));
     Ops<double> op{ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->inv, ctx->Sinv};
+    const Ops<double> seq = op;  // M^-1, then J
     if (ctx->opt.fold_preconditioner && ctx->have_f64) {
       op.Af = ctx->Af64;
       op.Cf = ctx->Cf64;
@@ -1836,7 +1882,7 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
     }
     std::vector<SolveOut> out;
     TRY(gmres_b<double>(ctx, op, ctx->k64, ctx->rhs, ctx->dx, std::vector<double>(B, ctx->opt.rtol), true, on,
-                        std::vector<int>(B, ctx->opt.gmres_maxit), out));
+                        std::vector<int>(B, ctx->opt.gmres_maxit), out, op.Af ? &seq : nullptr));
     for (int b = 0; b < B; ++b) {
       if (!on[b]) continue;
       ls[b].gmres_iters = out[b].iters;
@@ -1943,8 +1989,7 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
       TRY(put(ctx, kd.solving, on));
       TRY(put(ctx, ctx->k_coef, coef));
       HIPCHK((ks_axpy<double, float>(kd, ctx->k_coef, ctx->k32.x, ctx->dx, stm)));
-      TRY(apply_J<double>(ctx, kp, op64, ctx->dx, ctx->t64, rows(ctx, 1)));
-      HIPCHK(ks_sub<double>(kd, ctx->rhs, ctx->t64, ctx->r64, stm));
+      TRY(residual<double>(ctx, kp, op64, ctx->rhs, ctx->dx, ctx->t64, ctx->r64, rows(ctx, 1)));
     }
     bool anyfb = false;
     for (int b = 0; b < B; ++b) anyfb = anyfb || fb[b];
@@ -2504,11 +2549,16 @@ extern "C" hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path,
     double best_s = 1e300;
     hf_tuning pick = best;
     // restart length and orthogonalisation: CGS2 against single-reduction
-    // MGS (policy 3 is MGS for FP64 only, 4 also for the FP32 inner solves)
+    // MGS (policy 3 is MGS for FP64 only, 4 also for the FP32 inner solves).
+    // FP32 MGS is tried for a single instance only: in a batch one
+    // ill-conditioned instance whose FP32 basis loses orthogonality stalls
+    // its refinement and sets the batch's time.
     const int ms[2] = {60, 120};
-    const int pols[2] = {0, ctx->opt.precision == HF_FP64 ? 3 : 4};
+    const bool fp64 = ctx->opt.precision == HF_FP64;
+    const int pols[2] = {0, fp64 ? 3 : 4};
+    const int npol = (fp64 || nI(ctx) == 1) ? 2 : 1;
     for (int mi = 0; mi < 2; ++mi)
-      for (int pi = 0; pi < 2; ++pi) {
+      for (int pi = 0; pi < npol; ++pi) {
         hf_tuning t = best;
         t.gmres_m = ms[mi];
         t.reorth = pols[pi];

@@ -193,6 +193,10 @@ hipError_t launch_spmv(const KParams &kp, const T *A, const T *Bs, const T *Cs, 
 template <typename T>
 hipError_t launch_spmv_folded(const KParams &kp, const T *Af, const T *Bs, const T *Cf, const T *D,
                               const T *Sinv, const T *x, T *y, T *tp, const RowSel &sel, hipStream_t st);
+// r = b - J x in FP64 with compensated (double-double) accumulation (rows
+// outside sel are left untouched)
+hipError_t launch_resid(const KParams &kp, const double *A, const double *Bs, const double *Cs, const double *D,
+                        const double *x, const double *b, double *r, const RowSel &sel, hipStream_t st);
 // z = M^-1 r, block-Jacobi (rows outside sel are left untouched)
 template <typename T>
 hipError_t launch_precond(const KParams &kp, const T *inv, const T *Sinv, const T *r, T *z,

@@ -228,6 +228,165 @@ template hipError_t launch_spmv<float>(const KParams &, const float *, const flo
                                        const float *, const float *, const float *, float *,
                                        const RowSel &, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Residual r = b - J x with compensated (double-double) accumulation: every
+// product a x is split exactly into p + e (two-product by FMA), the row sums
+// carry their rounding errors (two-sum), and the difference with b is
+// rounded once.  The computed residual is then accurate to about u ||r|| +
+// u^2 ||J|| ||x|| instead of u ||J|| ||x||, so a relative residual below
+// u ||J|| ||x|| / ||b|| stays attainable when the solution is large against
+// the right-hand side (late Newton iterations of ill-conditioned systems).
+// ---------------------------------------------------------------------------
+struct DD {
+  double hi, lo;
+};
+__device__ inline void dd_add(DD &s, double v) {  // s += v (two-sum, error kept in lo)
+#pragma clang fp contract(off)
+  const double t = s.hi + v;
+  const double bp = t - s.hi;
+  s.lo += (s.hi - (t - bp)) + (v - bp);
+  s.hi = t;
+}
+__device__ inline void dd_fma(DD &s, double a, double b) {  // s += a b
+#pragma clang fp contract(off)
+  const double p = a * b;
+  const double e = fma(a, b, -p);
+  dd_add(s, p);
+  s.lo += e;
+}
+__device__ inline void dd_merge(DD &s, const DD &o) {  // s += o
+  dd_add(s, o.hi);
+  s.lo += o.lo;
+}
+__device__ inline double dd_sub_from(double b, const DD &s) {  // b - s, rounded once
+#pragma clang fp contract(off)
+  DD t{b, 0.0};
+  dd_add(t, -s.hi);
+  return t.hi + (t.lo - s.lo);
+}
+
+template <int BU, int LN, int NT>
+__global__ __launch_bounds__(NT) void k_bsr_resid(
+    int64_t ne, const int64_t *__restrict__ blk_ptr, const int32_t *__restrict__ blk_col,
+    const double *__restrict__ A, const int64_t *__restrict__ sp_ptr,
+    const int32_t *__restrict__ sp_pnode, const double *__restrict__ Bs, const double *__restrict__ x,
+    const double *__restrict__ xp, const double *__restrict__ bvec, double *__restrict__ r, RowMask mask) {
+  using S = SpmvShape<double, BU, LN>;
+  constexpr int L = S::L, EL = S::EL, LA = S::LA, CH = S::CH, RPC = S::RPC, G = NT / L;
+  __shared__ double xs[G][5 * BU];
+  __shared__ double ph[G][CH], pl[G][CH];
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  const int64_t e = (int64_t)blockIdx.x * G + g;
+  const bool live = e < ne && mask.live(e);
+  int64_t b0 = 0;
+  int nb = 0;
+  if (live) {
+    b0 = blk_ptr[e];
+    nb = (int)(blk_ptr[e + 1] - b0);
+    for (int t = lane; t < nb * BU; t += L) xs[g][t] = x[(int64_t)blk_col[b0 + t / BU] * BU + t % BU];
+  }
+  __syncthreads();
+  DD acc[EL];
+#pragma unroll
+  for (int s2 = 0; s2 < EL; ++s2) acc[s2] = DD{0.0, 0.0};
+  if (live && lane < LA) {
+    const double *panel = A + b0 * BU * BU;
+    const int total = nb * BU * BU;
+    int colS[EL];
+#pragma unroll
+    for (int s2 = 0; s2 < EL; ++s2) colS[s2] = (lane * EL + s2) / BU;
+    int f = lane * EL, cb = 0;
+#pragma unroll 4
+    for (; f < total; f += CH, cb += RPC) {
+      const double2 v = *(const double2 *)(panel + f);
+      dd_fma(acc[0], v.x, xs[g][cb + colS[0]]);
+      dd_fma(acc[1], v.y, xs[g][cb + colS[1]]);
+    }
+  }
+  if (lane < LA) {
+#pragma unroll
+    for (int s2 = 0; s2 < EL; ++s2) {
+      ph[g][lane * EL + s2] = acc[s2].hi;
+      pl[g][lane * EL + s2] = acc[s2].lo;
+    }
+  }
+  __syncthreads();
+  if (live && lane < BU) {
+    DD sum{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < RPC; ++t) dd_merge(sum, DD{ph[g][lane + BU * t], pl[g][lane + BU * t]});
+    for (int64_t k = sp_ptr[e]; k < sp_ptr[e + 1]; ++k) dd_fma(sum, Bs[k * BU + lane], xp[sp_pnode[k]]);
+    const int64_t row = e * BU + lane;
+    r[row] = dd_sub_from(bvec[row], sum);
+  }
+}
+
+// pressure rows of the compensated residual (one wave per row)
+template <int BU>
+__global__ __launch_bounds__(64) void k_presid(int64_t np, const int32_t *__restrict__ pinst,
+                                               const int32_t *__restrict__ poff,
+                                               const int64_t *__restrict__ doff,
+                                               const int32_t *__restrict__ pc_ptr,
+                                               const int32_t *__restrict__ pc_ent,
+                                               const int32_t *__restrict__ sp_elem,
+                                               const double *__restrict__ Cs, const double *__restrict__ D,
+                                               const double *__restrict__ xu, const double *__restrict__ xp,
+                                               const double *__restrict__ bp, double *__restrict__ rp,
+                                               RowMask mask) {
+  __shared__ double sh[64], sl[64];
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (!mask.live(i)) return;  // the whole wave leaves together
+  DD acc{0.0, 0.0};
+  if (pc_ptr) {
+    for (int32_t c = pc_ptr[i]; c < pc_ptr[i + 1]; ++c) {
+      const int32_t ent = pc_ent[c];
+      const int64_t e = sp_elem[ent];
+      if (lane < BU) dd_fma(acc, Cs[(int64_t)ent * BU + lane], xu[e * BU + lane]);
+    }
+  }
+  const int b = pinst[i];
+  const int64_t p0 = poff[b], nb = poff[b + 1] - p0;
+  const double *Drow = D + doff[b] + (i - p0) * nb;
+  for (int64_t j = lane; j < nb; j += 64) dd_fma(acc, Drow[j], xp[p0 + j]);
+  sh[lane] = acc.hi;
+  sl[lane] = acc.lo;
+  __syncthreads();
+  if (lane == 0) {
+    DD tot{0.0, 0.0};
+    for (int t = 0; t < 64; ++t) dd_merge(tot, DD{sh[t], sl[t]});
+    rp[i] = dd_sub_from(bp[i], tot);
+  }
+}
+
+template <int BU>
+static void resid_bu(const KParams &kp, const double *A, const double *Bs, const double *Cs, const double *D,
+                     const double *x, const double *b, double *r, const RowSel &sel, hipStream_t st) {
+  const RowMask me{kp.einst, sel.solving, sel.kconv, sel.mode};
+  const RowMask mp{kp.pinst, sel.solving, sel.kconv, sel.mode};
+  constexpr int LW = wide_lanes(BU), NT = 256, G = NT / LW;
+  const int64_t ne = kp.s.ne;
+  if (ne)
+    hipLaunchKernelGGL((k_bsr_resid<BU, LW, NT>), dim3((unsigned)((ne + G - 1) / G)), dim3(NT), 0, st, ne,
+                       kp.m.blk_ptr, kp.m.blk_col, A, kp.m.sp_ptr, kp.m.sp_pnode, Bs, x, x + kp.s.n_u, b, r,
+                       me);
+  if (kp.s.n_p)
+    hipLaunchKernelGGL((k_presid<BU>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp.s.n_p, kp.pinst,
+                       kp.poff, kp.doff, kp.m.pc_ptr, kp.m.pc_ent, kp.m.sp_elem, Cs, D, x, x + kp.s.n_u,
+                       b + kp.s.n_u, r + kp.s.n_u, mp);
+}
+
+hipError_t launch_resid(const KParams &kp, const double *A, const double *Bs, const double *Cs, const double *D,
+                        const double *x, const double *b, double *r, const RowSel &sel, hipStream_t st) {
+  switch (kp.s.bu) {
+    case 6: resid_bu<6>(kp, A, Bs, Cs, D, x, b, r, sel, st); break;
+    case 12: resid_bu<12>(kp, A, Bs, Cs, D, x, b, r, sel, st); break;
+    case 30: resid_bu<30>(kp, A, Bs, Cs, D, x, b, r, sel, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // folded product y = J M^-1 x: the pressure part of M^-1 first (t_p = S^-1
 // x_p), then the row panels of A M_A^-1 with the B strips on t_p, then the
 // pressure rows with the folded C strips and D on t_p

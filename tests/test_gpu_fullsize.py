@@ -1,7 +1,8 @@
 """Parity at the full size of the 3D penny workload (48,000 P2 tetrahedra,
-1.44M displacement DOF), in the launch configuration the benchmark times
-(one context on the caller's torch stream, GMRES(60), graph-replayed
-iterations).
+1.44M displacement DOF) and of the three-disk multi-crack workload (196,608
+P2 tetrahedra, 5.9M displacement DOF, 948 pressure nodes), in the launch
+configuration the benchmark times (one context on the caller's torch stream,
+GMRES(60), graph-replayed iterations of the folded operator).
 
 The oracle cannot assemble or solve the whole system in test time, so it
 checks sampled outputs it computes one by one: the residual rows, the
@@ -32,9 +33,9 @@ hf = pytest.importorskip("paper_1911_10275_amd")
 torch = pytest.importorskip("torch")
 
 
-@pytest.fixture(scope="module")
-def penny():
-    prob = synth.config(2)
+@pytest.fixture(scope="module", params=[2, 5], ids=["penny48k", "multicrack197k"])
+def penny(request):
+    prob = synth.config(request.param)
     case = Case.from_problem(prob)
     m = case.mesh
     fa = case.itf.active_faces
