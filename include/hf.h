@@ -213,6 +213,9 @@ typedef struct {
      the true residual above the target for two cycles (counted whatever
      hf_options.profile is) */
   int64_t n_unfold;
+  /* FP64 solves whose restart length doubled after three cycles with less
+     than 1% progress (restarted-GMRES stagnation) */
+  int64_t n_mgrow;
 } hf_profile;
 
 /* Fill *opt with the defaults listed above. */

@@ -89,7 +89,8 @@ class Profile(C.Structure):
                [(n, C.c_int64) for n in ("n_assemble", "n_blockinv", "n_spmv64", "n_spmv32",
                                           "n_precond", "n_ortho", "n_inv_mfma",
                                           "n_inv_fallback")] + \
-               [("ms_resid", C.c_double), ("n_resid", C.c_int64), ("n_unfold", C.c_int64)]
+               [("ms_resid", C.c_double), ("n_resid", C.c_int64), ("n_unfold", C.c_int64),
+                ("n_mgrow", C.c_int64)]
 
 
 class HFError(RuntimeError):

@@ -1338,8 +1338,8 @@ struct Ops {
 };
 
 template <typename T>
-static hf_status ensure_ws(hf_ctx *ctx, KrylovWs<T> &ws) {
-  const int m = ctx->opt.gmres_m;
+static hf_status ensure_ws(hf_ctx *ctx, KrylovWs<T> &ws, int m_req = 0) {
+  const int m = m_req > 0 ? m_req : ctx->opt.gmres_m;
   const int64_t N = ctx->s.N();
   const int B = nI(ctx);
   if (ctx->kd_m < m) {
@@ -1545,10 +1545,12 @@ static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T
                          const Ops<T> *alt = nullptr) {
   const Ops<T> *cur = &op;
   bool switched = false;
-  std::vector<int> miss(nI(ctx), 0);
+  std::vector<int> miss(nI(ctx), 0), flat(nI(ctx), 0);
+  std::vector<double> beta_prev(nI(ctx), 0.0);
   const KParams kp = kparams(ctx);
   const int64_t N = ctx->s.N();
-  const int m = ws.m, B = nI(ctx);
+  int m = ws.m;
+  const int B = nI(ctx);
   KrylovDev &kd = ctx->kd;
   hipStream_t st = ctx->stream;
   out.assign(B, SolveOut{});
@@ -1664,6 +1666,33 @@ static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T
       if (switched) {
         cur = alt;
         ctx->prof.n_unfold += 1;
+      }
+    }
+    // restarted GMRES stagnation: when an instance's true residual falls by
+    // less than 1% in three consecutive cycles, the restart length doubles
+    // (up to 256) for the rest of the solve.  Only with an explicit check,
+    // where x and b live outside the workspace; the restart vector is
+    // recomputed in the new workspace.
+    if (explicit_check) {
+      bool grow = false;
+      for (int b = 0; b < B; ++b) {
+        if (!on[b]) continue;
+        const double beta = std::sqrt(beta2[b]);
+        flat[b] = (beta_prev[b] > 0.0 && beta > 0.99 * beta_prev[b]) ? flat[b] + 1 : 0;
+        beta_prev[b] = beta;
+        if (flat[b] >= 3) grow = true;
+      }
+      if (grow && m < kMaxKrylov - 1) {
+        m = std::min(2 * m, kMaxKrylov - 1);
+        TRY(ensure_ws<T>(ctx, ws, m));
+        TRY(residual<T>(ctx, kp, op, bvec, x, ws.w, ws.r, rows(ctx, 1)));
+        HIPCHK(ks_norms<T>(kd, ws.r, ctx->partial, ctx->k_beta2, st));
+        TRY(get_d(ctx, ctx->k_beta2, B));
+        for (int b = 0; b < B; ++b) {
+          if (on[b]) beta2[b] = ctx->hd[b];
+          flat[b] = 0;
+        }
+        ctx->prof.n_mgrow += 1;
       }
     }
     if (trace_on())
