@@ -192,7 +192,8 @@ typedef struct {
                           solves of GMRES-IR use CGS2 (single-pass schemes
                           lose orthogonality faster in FP32).  hf_autotune
                           level 1 chooses between 0 and 3 (FP64) or 0 and 4
-                          (FP32-IR, single-instance contexts; batches keep 0). */
+                          (FP32-IR: 4 only for single-instance contexts and
+                          a restart length of 60). */
   int gmres_m;         /* restart length (0 = keep hf_options.gmres_m) */
   int reserved[3];
 } hf_tuning;

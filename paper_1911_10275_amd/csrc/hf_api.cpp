@@ -1471,9 +1471,9 @@ static hf_status arnoldi_step(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, 
     // (I + L) h = s, one update pass w -= V h
     HIPCHK(ks_proj2<T>(kd, ws.V, N, k, ws.w, ctx->partial, ctx->k_s1, ctx->stream));
     HIPCHK(ks_icwy(kd, j, m, ctx->k_s1, kd.L, ctx->k_s2, m + 2, ctx->stream));
-    HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s2, m + 2, ws.w, nullptr, ctx->partial, ctx->k_n1,
+    HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s2, m + 2, ws.w, nullptr, ctx->partial, nullptr,
                         ctx->stream));
-    HIPCHK(ks_arnoldi(kd, j, m, ctx->k_s2, m + 2, ctx->k_s2, m + 2, nullptr, ctx->k_n1, ctx->k_n1,
+    HIPCHK(ks_arnoldi(kd, j, m, ctx->k_s2, m + 2, ctx->k_s2, m + 2, nullptr, nullptr, nullptr, ctx->partial,
                       ctx->k_scale, ctx->stream));
     HIPCHK(ks_scale<T>(kd, ws.w, ctx->k_scale, ws.V + (int64_t)(j + 1) * N, ctx->stream));
     return HF_OK;
@@ -1483,11 +1483,11 @@ static hf_status arnoldi_step(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, 
   HIPCHK(ks_reorth_flag(kd, ctx->k_s1 + k, ks, ctx->k_n1, pol, ctx->k_flag, ctx->stream));
   if (pol != 2) {
     HIPCHK(ks_proj<T>(kd, ws.V, N, k, ws.w, ctx->k_flag, ctx->partial, ctx->k_s2, ctx->stream));
-    HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s2, ks, ws.w, ctx->k_flag, ctx->partial, ctx->k_n2,
+    HIPCHK(ks_update<T>(kd, ws.V, N, k, ctx->k_s2, ks, ws.w, ctx->k_flag, ctx->partial, nullptr,
                         ctx->stream));
   }
-  HIPCHK(ks_arnoldi(kd, j, m, ctx->k_s1, ks, ctx->k_s2, ks, ctx->k_flag, ctx->k_n1, ctx->k_n2,
-                    ctx->k_scale, ctx->stream));
+  HIPCHK(ks_arnoldi(kd, j, m, ctx->k_s1, ks, ctx->k_s2, ks, ctx->k_flag, ctx->k_n1, nullptr,
+                    pol != 2 ? ctx->partial : nullptr, ctx->k_scale, ctx->stream));
   HIPCHK(ks_scale<T>(kd, ws.w, ctx->k_scale, ws.V + (int64_t)(j + 1) * N, ctx->stream));
   return HF_OK;
 }
@@ -2579,15 +2579,17 @@ extern "C" hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path,
     hf_tuning pick = best;
     // restart length and orthogonalisation: CGS2 against single-reduction
     // MGS (policy 3 is MGS for FP64 only, 4 also for the FP32 inner solves).
-    // FP32 MGS is tried for a single instance only: in a batch one
+    // FP32 MGS is tried for a single instance only (in a batch one
     // ill-conditioned instance whose FP32 basis loses orthogonality stalls
-    // its refinement and sets the batch's time.
+    // its refinement and sets the batch's time) and with the short restart
+    // only (the loss of orthogonality grows with the basis).
     const int ms[2] = {60, 120};
     const bool fp64 = ctx->opt.precision == HF_FP64;
     const int pols[2] = {0, fp64 ? 3 : 4};
     const int npol = (fp64 || nI(ctx) == 1) ? 2 : 1;
     for (int mi = 0; mi < 2; ++mi)
       for (int pi = 0; pi < npol; ++pi) {
+        if (!fp64 && pi == 1 && ms[mi] > 60) continue;
         hf_tuning t = best;
         t.gmres_m = ms[mi];
         t.reorth = pols[pi];

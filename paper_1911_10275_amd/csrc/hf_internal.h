@@ -238,8 +238,10 @@ hipError_t ks_zero(const KrylovDev &kd, T *x, int only_solving, hipStream_t st);
 // ||w1||^2 < ||w||^2 / 2 (n1, n0), 1 always, 2 never
 hipError_t ks_reorth_flag(const KrylovDev &kd, const double *n0, int n0s, const double *n1, int policy,
                           int *flag, hipStream_t st);
+// ||w||^2 from n2[b] (second pass) or n1[b], or, with pnorm, summed from the
+// last update's chunk partials (where n1 is null or the second pass ran)
 hipError_t ks_arnoldi(const KrylovDev &kd, int j, int m, const double *s1, int s1s, const double *s2,
-                      int s2s, const int *reorth, const double *n1, const double *n2,
+                      int s2s, const int *reorth, const double *n1, const double *n2, const double *pnorm,
                       double *scale, hipStream_t st);
 // one-reduce projection for the single-pass modified Gram-Schmidt: out (per
 // instance, stride 2k-1) = V_{0..k-1}^T w, then V_{0..k-2}^T v_{k-1}

@@ -460,12 +460,36 @@ __global__ __launch_bounds__(64) void k_arnoldi(KrylovDev kd, int j, int m,
                                                 const int *__restrict__ reorth,
                                                 const double *__restrict__ n1,
                                                 const double *__restrict__ n2,
+                                                const double *__restrict__ pnorm,
                                                 double *__restrict__ scale) {
   __shared__ double col[kMaxKrylov + 1], c_s[kMaxKrylov], s_s[kMaxKrylov];
+  __shared__ double s_nn;
   const int b = blockIdx.x, lane = threadIdx.x;
   if (!inst_on(kd, b)) {  // uniform over the block
     if (lane == 0) scale[b] = 0.0;
     return;
+  }
+  // ||w||^2 of the last pass: from the per-instance norms, or (pnorm) summed
+  // here from the last update's chunk partials of this instance, in a fixed
+  // order -- the update then needs no separate reduction launch
+  {
+    const bool ro0 = reorth && reorth[b] != 0;
+    if (pnorm && (ro0 || !n1)) {
+      // eight loads in flight per lane, summed in a fixed order
+      const int c1 = kd.cptr[b + 1];
+      double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      int c = kd.cptr[b] + lane;
+      for (; c + 7 * 64 < c1; c += 8 * 64) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += pnorm[c + u * 64];
+      }
+      for (; c < c1; c += 64) a[0] += pnorm[c];
+      double t = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+      t = kwave_sum(t);
+      if (lane == 0) s_nn = t;
+    } else if (lane == 0) {
+      s_nn = ro0 ? n2[b] : n1[b];
+    }
   }
   double *H = kd.H + (int64_t)b * (m + 1) * m;
   double *cs = kd.cs + (int64_t)b * m, *sn = kd.sn + (int64_t)b * m, *g = kd.g + (int64_t)b * (m + 1);
@@ -478,7 +502,7 @@ __global__ __launch_bounds__(64) void k_arnoldi(KrylovDev kd, int j, int m,
   }
   __syncthreads();
   if (lane == 0) {
-    const double hn = sqrt(ro ? n2[b] : n1[b]);
+    const double hn = sqrt(s_nn);
     double a = col[0];
     for (int i = 0; i < j; ++i) {
       const double nx = col[i + 1];
@@ -593,7 +617,7 @@ hipError_t ks_update(const KrylovDev &kd, const T *V, int64_t ldv, int k, const 
     case 2: supdate_launch<T, 2>(kd, V, ldv, k, h, hstride, w, gate, partial, st); break;
     default: supdate_launch<T, 4>(kd, V, ldv, k, h, hstride, w, gate, partial, st); break;
   }
-  hipLaunchKernelGGL(k_seg_reduce, dim3(kd.n_inst, 1), dim3(KT), 0, st, kd, partial, 1, out);
+  if (out) hipLaunchKernelGGL(k_seg_reduce, dim3(kd.n_inst, 1), dim3(KT), 0, st, kd, partial, 1, out);
   return hipGetLastError();
 }
 template <typename T>
@@ -663,10 +687,10 @@ hipError_t ks_reorth_flag(const KrylovDev &kd, const double *n0, int n0s, const 
   return hipGetLastError();
 }
 hipError_t ks_arnoldi(const KrylovDev &kd, int j, int m, const double *s1, int s1s, const double *s2,
-                      int s2s, const int *reorth, const double *n1, const double *n2,
+                      int s2s, const int *reorth, const double *n1, const double *n2, const double *pnorm,
                       double *scale, hipStream_t st) {
   hipLaunchKernelGGL(k_arnoldi, dim3(kd.n_inst), dim3(64), 0, st, kd, j, m, s1, s1s, s2, s2s, reorth,
-                     n1, n2, scale);
+                     n1, n2, pnorm, scale);
   return hipGetLastError();
 }
 hipError_t ks_count_active(const KrylovDev &kd, int *count, hipStream_t st) {
