@@ -131,6 +131,7 @@ struct hf_ctx {
   int32_t *crack_elems = nullptr;  // elements with a cohesive or fluid interface
   int64_t n_crack = 0;
   int32_t *crack_blocks = nullptr;  // Jacobian blocks in a crack element's row or column
+  uint8_t *crack_mask = nullptr;    // 1 for the elements in crack_elems
   int64_t n_crack_blocks = 0;
   int64_t f64_epoch = -1, f32_epoch = -1;  // assembly epoch of the folded blocks
   bool lin_valid = false;
@@ -1050,6 +1051,7 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
         if (is_crack[e] || is_crack[blk_col[k]]) cb.push_back((int32_t)k);
     TRY(upload(ctx, &ctx->crack_blocks, cb));
     ctx->n_crack_blocks = (int64_t)cb.size();
+    TRY(upload(ctx, &ctx->crack_mask, is_crack));
   }
   TRY(upload(ctx, &ctx->d_ipar, ctx->ipar));
   TRY(upload(ctx, &ctx->d_einst, einst));
@@ -1287,12 +1289,12 @@ static hf_status do_assemble(hf_ctx *ctx, std::vector<double> &rn) {
     ProfScope ps(ctx, P_ASM);
     if (incr) {
       // the rows of elements without cohesive or fluid interfaces are linear
-      // in u with the cached blocks: R = A u for them (the other rows, the
-      // strips and the fluid rows are recomputed below)
+      // in u with the cached blocks: R = A u for them (element rows only),
+      // then the crack elements' rows and strips and the fluid rows are
+      // re-assembled
       {
         ProfScope pj(ctx, P_SPMV64);  // the Jacobian product, timed on its own as well
-        HIPCHK(launch_spmv<double>(kp, ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->xs, ctx->R, RowSel{},
-                                   ctx->stream));
+        HIPCHK(launch_spmv_rows(kp, ctx->A, ctx->xs, ctx->R, ctx->crack_mask, ctx->stream));
       }
       HIPCHK(launch_assemble(kp, ctx->xs, ctx->xs + s.n_u, ctx->w_old, ctx->A, ctx->R, ctx->Bs,
                              ctx->Cs, ctx->D, ctx->crack_elems, ctx->n_crack, ctx->stream));

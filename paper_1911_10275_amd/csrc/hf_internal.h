@@ -193,6 +193,10 @@ hipError_t launch_spmv(const KParams &kp, const T *A, const T *Bs, const T *Cs, 
 template <typename T>
 hipError_t launch_spmv_folded(const KParams &kp, const T *Af, const T *Bs, const T *Cf, const T *D,
                               const T *Sinv, const T *x, T *y, T *tp, const RowSel &sel, hipStream_t st);
+// y_e = sum_f A_ef x_f for the element rows with skip[e] == 0 (no strips,
+// no pressure rows; the other rows are left untouched)
+hipError_t launch_spmv_rows(const KParams &kp, const double *A, const double *x, double *y,
+                            const uint8_t *skip, hipStream_t st);
 // r = b - J x in FP64 with compensated (double-double) accumulation (rows
 // outside sel are left untouched)
 hipError_t launch_resid(const KParams &kp, const double *A, const double *Bs, const double *Cs, const double *D,

@@ -545,25 +545,50 @@ __global__ void k_count_active(KrylovDev kd, int *count) {
   if (threadIdx.x == 0) *count = sm[0];
 }
 
-// y_b = H_b(1:k,1:k)^-1 g_b (back substitution), k = kconv[b]; est[b] = |g_b[k]|
-__global__ void k_solve_y(KrylovDev kd, int m, double *__restrict__ y, double *__restrict__ est) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= kd.n_inst) return;
-  if (!kd.solving[b]) {
-    kd.nbasis[b] = 0;
+// y_b = H_b(1:k,1:k)^-1 g_b (back substitution), k = kconv[b]; est[b] = |g_b[k]|.
+// One wavefront per instance: as each y_i becomes known its column is
+// removed from the rows above it (in LDS; H staged in LDS when k <= 64).
+constexpr int kSolveLds = 64;
+__global__ __launch_bounds__(64) void k_solve_y(KrylovDev kd, int m, double *__restrict__ y,
+                                                double *__restrict__ est) {
+  __shared__ double Hs[kSolveLds][kSolveLds + 1];
+  __shared__ double gs[kMaxKrylov + 1];
+  const int b = blockIdx.x, lane = threadIdx.x;
+  if (!kd.solving[b]) {  // uniform over the block
+    if (lane == 0) kd.nbasis[b] = 0;
     return;
   }
   const int k = kd.kconv[b] < 0 ? m : kd.kconv[b];
   const double *H = kd.H + (int64_t)b * (m + 1) * m;
   const double *g = kd.g + (int64_t)b * (m + 1);
-  double *yb = y + (int64_t)b * m;
-  for (int i = k - 1; i >= 0; --i) {
-    double acc = g[i];
-    for (int c2 = i + 1; c2 < k; ++c2) acc -= H[i * m + c2] * yb[c2];
-    yb[i] = acc / H[i * m + i];
+  for (int i = lane; i <= k; i += 64) gs[i] = g[i];
+  if (k <= kSolveLds) {
+    for (int t = lane; t < k * k; t += 64) {
+      const int i = t / k, c = t % k;
+      if (c >= i) Hs[i][c] = H[(int64_t)i * m + c];
+    }
+    __syncthreads();
+    for (int i = k - 1; i >= 0; --i) {
+      const double yi = gs[i] / Hs[i][i];
+      if (lane < i) gs[lane] -= Hs[lane][i] * yi;
+      if (lane == 0) gs[i] = yi;
+      __syncthreads();
+    }
+  } else {
+    __syncthreads();
+    for (int i = k - 1; i >= 0; --i) {
+      const double yi = gs[i] / H[(int64_t)i * m + i];
+      for (int c = lane; c < i; c += 64) gs[c] -= H[(int64_t)c * m + i] * yi;
+      if (lane == 0) gs[i] = yi;
+      __syncthreads();
+    }
   }
-  kd.nbasis[b] = k;
-  est[b] = fabs(g[k]);
+  double *yb = y + (int64_t)b * m;
+  for (int i = lane; i < k; i += 64) yb[i] = gs[i];
+  if (lane == 0) {
+    kd.nbasis[b] = k;
+    est[b] = fabs(g[k]);
+  }
 }
 
 // start of a cycle: g = (beta, 0, ...), kconv = -1, scale = 1/beta for
@@ -698,7 +723,7 @@ hipError_t ks_count_active(const KrylovDev &kd, int *count, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t ks_solve_y(const KrylovDev &kd, int m, double *y, double *est, hipStream_t st) {
-  hipLaunchKernelGGL(k_solve_y, dim3((kd.n_inst + 63) / 64), dim3(64), 0, st, kd, m, y, est);
+  hipLaunchKernelGGL(k_solve_y, dim3(kd.n_inst), dim3(64), 0, st, kd, m, y, est);
   return hipGetLastError();
 }
 hipError_t ks_cycle_start(const KrylovDev &kd, int m, const double *beta2, double *scale,

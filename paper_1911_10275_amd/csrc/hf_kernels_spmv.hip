@@ -66,7 +66,9 @@ struct RowMask {
   const int32_t *inst;  // instance of each element (or pressure node)
   const int *solving, *kconv;
   int mode;
+  const uint8_t *skip = nullptr;  // rows left to another kernel (skip[r] != 0)
   __device__ bool live(int64_t r) const {
+    if (skip && skip[r]) return false;
     if (!mode) return true;
     const int b = inst[r];
     return solving[b] != 0 && (mode == 1 || kconv[b] < 0);
@@ -227,6 +229,32 @@ template hipError_t launch_spmv<double>(const KParams &, const double *, const d
 template hipError_t launch_spmv<float>(const KParams &, const float *, const float *,
                                        const float *, const float *, const float *, float *,
                                        const RowSel &, hipStream_t);
+
+// element rows without strips or pressure rows, rows with skip[e] != 0 left
+// to another kernel (the residual rows of the crack-free elements in an
+// incremental assembly)
+hipError_t launch_spmv_rows(const KParams &kp, const double *A, const double *x, double *y,
+                            const uint8_t *skip, hipStream_t st) {
+  RowMask me{kp.einst, nullptr, nullptr, 0};
+  me.skip = skip;
+  if (!kp.s.ne) return hipSuccess;
+  switch (kp.s.bu) {
+    case 6:
+      rows_launch<double, 6, wide_lanes(6), false>(kp.s.ne, kp.m.blk_ptr, kp.m.blk_col, A, nullptr, nullptr,
+                                                   nullptr, x, nullptr, y, me, st);
+      break;
+    case 12:
+      rows_launch<double, 12, wide_lanes(12), false>(kp.s.ne, kp.m.blk_ptr, kp.m.blk_col, A, nullptr, nullptr,
+                                                     nullptr, x, nullptr, y, me, st);
+      break;
+    case 30:
+      rows_launch<double, 30, wide_lanes(30), false>(kp.s.ne, kp.m.blk_ptr, kp.m.blk_col, A, nullptr, nullptr,
+                                                     nullptr, x, nullptr, y, me, st);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // Residual r = b - J x with compensated (double-double) accumulation: every
