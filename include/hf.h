@@ -195,7 +195,11 @@ typedef struct {
                           (FP32-IR: 4 only for single-instance contexts and
                           a restart length of 60). */
   int gmres_m;         /* restart length (0 = keep hf_options.gmres_m) */
-  int reserved[3];
+  int dense_wide_min;  /* pressure blocks with at least this many nodes are
+                          inverted with one grid-wide launch pair per pivot
+                          step, the smaller ones by one workgroup each
+                          (0 = 192; the same arithmetic either way) */
+  int reserved[2];
 } hf_tuning;
 
 typedef struct {

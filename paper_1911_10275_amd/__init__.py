@@ -76,7 +76,8 @@ class NewtonStats(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("spmv_var", C.c_int), ("prec_var", C.c_int), ("ortho_var", C.c_int),
-                ("reorth", C.c_int), ("gmres_m", C.c_int), ("reserved", C.c_int * 3)]
+                ("reorth", C.c_int), ("gmres_m", C.c_int), ("dense_wide_min", C.c_int),
+                ("reserved", C.c_int * 2)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k in ("spmv_var", "prec_var", "ortho_var", "reorth",
@@ -428,7 +429,7 @@ class Context:
     def set_tuning(self, **kw):
         t = self.tuning()
         for k, v in kw.items():
-            if k not in Tuning().as_dict():
+            if k not in Tuning().as_dict() and k != "dense_wide_min":
                 raise KeyError(k)
             setattr(t, k, v)
         self._check(self.lib.hf_set_tuning(self.h, C.byref(t)), "hf_set_tuning")

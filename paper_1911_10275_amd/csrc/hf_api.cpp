@@ -111,6 +111,9 @@ struct hf_ctx {
   float *Af32 = nullptr, *Cf32 = nullptr, *tp32 = nullptr;
   bool have_f64 = false, have_f32 = false;
   bool have_m64 = false;  // the FP64 block-Jacobi factors match the assembled system
+  // scratch of the grid-wide pressure-block inverse
+  double *gj_colk = nullptr, *gj_piv = nullptr;
+  int *gj_perm = nullptr;
   int *flag = nullptr;
   double *dx = nullptr, *rhs = nullptr, *r64 = nullptr, *t64 = nullptr;
   KrylovWs<double> k64;
@@ -1768,8 +1771,20 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
     part64 = part;
     part32 = ir && part;
   }
+  const int n_wide = ctx->tune.dense_wide_min > 0 ? ctx->tune.dense_wide_min : kDenseWideMin;
   HIPCHK(launch_schur(kp, ctx->inv, ctx->Bs, ctx->Cs, ctx->D, nullptr, ctx->T, ctx->S, ctx->Sinv,
-                      ctx->Sinv32, ctx->flag, ctx->stream));
+                      ctx->Sinv32, ctx->flag, n_wide, ctx->stream));
+  for (int b = 0; b < B; ++b) {
+    const int nb = ctx->poff[b + 1] - ctx->poff[b];
+    if (nb < n_wide) continue;
+    if (!ctx->gj_colk) {
+      TRY(dalloc(ctx, &ctx->gj_colk, kMaxPressureBlock));
+      TRY(dalloc(ctx, &ctx->gj_perm, kMaxPressureBlock));
+      TRY(dalloc(ctx, &ctx->gj_piv, 1));
+    }
+    HIPCHK(launch_dense_inv_wide(ctx->S + ctx->doff[b], ctx->Sinv + ctx->doff[b], ctx->Sinv32 + ctx->doff[b], nb,
+                                 ctx->flag + b, ctx->gj_colk, ctx->gj_perm, ctx->gj_piv, ctx->stream));
+  }
   if (ir) {
     if (cached && ctx->a32_epoch == ctx->lin_epoch)
       HIPCHK(launch_convert_panels(kp, ctx->crack_elems, ctx->n_crack, ctx->A, ctx->A32, ctx->stream));
@@ -2440,7 +2455,8 @@ extern "C" hf_status hf_get_tuning(hf_ctx *ctx, hf_tuning *out) {
 extern "C" hf_status hf_set_tuning(hf_ctx *ctx, const hf_tuning *t) {
   if (!ctx || !t) return HF_EINVAL;
   if (t->spmv_var < 0 || t->spmv_var > 1 || t->prec_var < 0 || t->prec_var > 1 || t->ortho_var < 0 ||
-      t->ortho_var > 2 || t->reorth < 0 || t->reorth > 4 || t->gmres_m < 0 || t->gmres_m > kMaxKrylov - 1)
+      t->ortho_var > 2 || t->reorth < 0 || t->reorth > 4 || t->gmres_m < 0 || t->gmres_m > kMaxKrylov - 1 ||
+      t->dense_wide_min < 0)
     return fail(ctx, HF_EINVAL, "tuning value out of range");
   release_all_graphs(ctx);  // the captured chunks hold the old schedule
   ctx->tune = *t;

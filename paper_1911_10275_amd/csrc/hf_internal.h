@@ -31,6 +31,7 @@ constexpr int kMaxKrylov = 257;  // basis vectors (restart length + 1)
 constexpr int kMaxNqv = 8;     // volume points of 3D P2 (2 x 2 x 2)
 constexpr int kChunkRows = 1024;  // rows of a reduction chunk of the batched Krylov kernels
 constexpr int kMaxPressureBlock = 4096;  // pressure nodes per instance (dense pressure block)
+constexpr int kDenseWideMin = 192;       // pressure blocks from this size are inverted grid-wide
 
 // Rule tables, in the device constant bank (set per context before launch).
 struct RuleTables {
@@ -179,10 +180,17 @@ hipError_t launch_convert_panels(const KParams &kp, const int32_t *elist, int64_
 template <typename TI, typename TO>
 hipError_t launch_fold(const KParams &kp, const double *A, const double *Cs, const TI *inv, TO *Af, TO *Cf,
                        const int32_t *blist, int64_t nblk, hipStream_t st);
-// flag[b] |= 2 on a zero or non-finite pivot in the pressure block of instance b
+// flag[b] |= 2 on a zero or non-finite pivot in the pressure block of instance b;
+// the inverses of blocks with n_wide <= n (n_wide > 0) are left to
+// launch_dense_inv_wide
 hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,
                         const double *Cs, const double *D, double *Z, double *T, double *S,
-                        double *Sinv, float *Sinv32, int *flag, hipStream_t st);
+                        double *Sinv, float *Sinv32, int *flag, int n_wide, hipStream_t st);
+// inverse of one n x n block W (row-major, in place) into out / out32, one
+// pivot step per two launches over the whole GPU; scratch colk (n), perm (n),
+// piv (1); flag |= 2 on a zero or non-finite pivot
+hipError_t launch_dense_inv_wide(double *W, double *out, float *out32, int n, int *flag, double *colk, int *perm,
+                                 double *piv, hipStream_t st);
 hipError_t launch_convert(const double *in, float *out, int64_t n, hipStream_t st);
 // y = J x (rows outside sel are left untouched)
 template <typename T>

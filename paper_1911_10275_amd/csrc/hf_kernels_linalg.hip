@@ -1,6 +1,7 @@
 // Linear-algebra kernels for gfx950: batched inverses of the element
 // blocks, the Schur pressure block and its inverse, precision conversion and
 // vector fills.
+#include <algorithm>
 #include <cmath>
 
 #include "hf_internal.h"
@@ -413,9 +414,10 @@ __global__ __launch_bounds__(kDT) void k_dense_inv(const int32_t *__restrict__ p
                                                    const int64_t *__restrict__ doff,
                                                    double *__restrict__ Wall,
                                                    double *__restrict__ outall,
-                                                   float *__restrict__ out32all, int *flag) {
+                                                   float *__restrict__ out32all, int *flag, int n_wide) {
   const int bi = blockIdx.x;
   const int n = poff[bi + 1] - poff[bi];
+  if (n_wide > 0 && n >= n_wide) return;  // left to the grid-wide steps below
   double *W = Wall + doff[bi];
   double *out = outall + doff[bi];
   float *out32 = out32all + doff[bi];
@@ -492,9 +494,122 @@ __global__ __launch_bounds__(kDT) void k_dense_inv(const int32_t *__restrict__ p
   }
 }
 
+// The same Gauss-Jordan for one large pressure block, each pivot step in two
+// launches so that the rank-one update spans the whole GPU: k_gj_pivot (one
+// workgroup: pivot search, row swap, scaling of the pivot row, column k kept
+// in colk) and k_gj_update (every other row).  The operations and their
+// order per entry are those of k_dense_inv, so both give the same bits.
+__global__ __launch_bounds__(kDT) void k_gj_pivot(double *__restrict__ W, int n, int k, double *__restrict__ colk,
+                                                  int *__restrict__ perm, double *__restrict__ piv,
+                                                  int *__restrict__ flag) {
+  __shared__ double sv[kDT];
+  __shared__ int si[kDT];
+  const int tid = threadIdx.x;
+  if (*flag & 2) {  // an earlier pivot failed: nothing more to do
+    if (tid == 0) piv[0] = 0.0;
+    return;
+  }
+  double v = -1.0;
+  int idx = n;
+  for (int r = k + tid; r < n; r += kDT) {
+    const double a = fabs(W[(int64_t)r * n + k]);
+    if (a > v || (a == v && r < idx)) {
+      v = a;
+      idx = r;
+    }
+  }
+  sv[tid] = v;
+  si[tid] = idx;
+  __syncthreads();
+  for (int s2 = kDT / 2; s2 > 0; s2 >>= 1) {
+    if (tid < s2) {
+      const double ov = sv[tid + s2];
+      const int oi = si[tid + s2];
+      if (ov > sv[tid] || (ov == sv[tid] && oi < si[tid])) {
+        sv[tid] = ov;
+        si[tid] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const int p = si[0];
+  const double pv = (p < n) ? W[(int64_t)p * n + k] : 0.0;
+  __syncthreads();
+  if (!(fabs(pv) > 0.0) || !isfinite(pv)) {
+    if (tid == 0) {
+      atomicOr(flag, 2);
+      piv[0] = 0.0;
+    }
+    return;
+  }
+  if (tid == 0) perm[k] = p;
+  if (p != k)
+    for (int j = tid; j < n; j += kDT) {
+      const double t = W[(int64_t)k * n + j];
+      W[(int64_t)k * n + j] = W[(int64_t)p * n + j];
+      W[(int64_t)p * n + j] = t;
+    }
+  __syncthreads();
+  const double pinv = 1.0 / pv;
+  for (int j = tid; j < n; j += kDT) W[(int64_t)k * n + j] = (j == k) ? pinv : W[(int64_t)k * n + j] * pinv;
+  __syncthreads();
+  for (int r = tid; r < n; r += kDT) colk[r] = W[(int64_t)r * n + k];
+  if (tid == 0) piv[0] = pinv;
+}
+
+__global__ __launch_bounds__(256) void k_gj_update(double *__restrict__ W, int n, int k,
+                                                   const double *__restrict__ colk,
+                                                   const double *__restrict__ piv) {
+  const double pinv = piv[0];
+  if (pinv == 0.0) return;  // failed pivot
+  const double *Wk = W + (int64_t)k * n;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < (int64_t)n * n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(t / n), j = (int)(t % n);
+    if (r == k) continue;
+    const double f = colk[r];
+    W[t] = (j == k) ? -f * pinv : W[t] - f * Wk[j];
+  }
+}
+
+// undo the row exchanges on the columns (last to first), then copy out
+__global__ __launch_bounds__(kDT) void k_gj_finish(double *__restrict__ W, int n, const int *__restrict__ perm,
+                                                   double *__restrict__ out, float *__restrict__ out32,
+                                                   const int *__restrict__ flag) {
+  const int tid = threadIdx.x;
+  if (*flag & 2) return;
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k)
+      for (int r = tid; r < n; r += kDT) {
+        const double t = W[(int64_t)r * n + k];
+        W[(int64_t)r * n + k] = W[(int64_t)r * n + p];
+        W[(int64_t)r * n + p] = t;
+      }
+    __syncthreads();
+  }
+  for (int64_t t = tid; t < (int64_t)n * n; t += kDT) {
+    out[t] = W[t];
+    out32[t] = (float)W[t];
+  }
+}
+
+hipError_t launch_dense_inv_wide(double *W, double *out, float *out32, int n, int *flag, double *colk, int *perm,
+                                 double *piv, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nn = (int64_t)n * n;
+  const unsigned gu = (unsigned)std::min<int64_t>((nn + 255) / 256, 4096);
+  for (int k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kDT), 0, st, W, n, k, colk, perm, piv, flag);
+    hipLaunchKernelGGL(k_gj_update, dim3(gu), dim3(256), 0, st, W, n, k, colk, piv);
+  }
+  hipLaunchKernelGGL(k_gj_finish, dim3(1), dim3(kDT), 0, st, W, n, perm, out, out32, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,
                         const double *Cs, const double *D, double *Z, double *T, double *S,
-                        double *Sinv, float *Sinv32, int *flag, hipStream_t st) {
+                        double *Sinv, float *Sinv32, int *flag, int n_wide, hipStream_t st) {
   (void)Z;
   const int64_t np = kp.s.n_p;
   if (!np) return hipSuccess;
@@ -503,7 +618,7 @@ hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,
   hipLaunchKernelGGL(k_schur_gather, dim3((unsigned)((np + 63) / 64)), dim3(64), 0, st, kp, D, T,
                      kp.m.sp_se, S);
   hipLaunchKernelGGL(k_dense_inv, dim3(kp.n_inst), dim3(kDT), 0, st, kp.poff, kp.doff, S, Sinv,
-                     Sinv32, flag);
+                     Sinv32, flag, n_wide);
   return hipGetLastError();
 }
 

@@ -192,6 +192,66 @@ def test_newton_load_steps_unfolded(name, precision):
     ctx.close()
 
 
+@pytest.mark.parametrize("name", ["2d_p2_n7", "3d_p2_n3"])
+def test_dense_inverse_wide_path(name):
+    """The pressure-block inverse by grid-wide pivot steps (forced for every
+    block size) gives the preconditioner of the one-workgroup inverse (1e-13)
+    and the oracle's M^-1 (J M^-1 x to 1e-10)."""
+    torch = pytest.importorskip("torch")
+    prob = SMALL[name]()
+    case, ctx = _pair(prob)
+    u, p, wo = _random_state(case, 12)
+    x = np.random.default_rng(13).normal(size=ctx.sizes.n_total)
+    xd = torch.tensor(x, device="cuda")
+    ys = []
+    for wide in (0, 1):
+        ctx.set_tuning(dense_wide_min=wide)
+        ctx.set_options(gmres_maxit=1)
+        ctx.set_state(u, p, wo)
+        ctx.assemble()
+        ctx.solve(check=False)
+        yd = torch.empty_like(xd)
+        torch.cuda.synchronize()
+        ctx.apply_preconditioned(xd.data_ptr(), yd.data_ptr(), hf.HF_FP64, folded=0)
+        torch.cuda.synchronize()
+        ys.append(yd.cpu().numpy())
+    ctx.close()
+    assert _rel(ys[1], ys[0]) < 1e-13
+    S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo),
+                     case.src_pnode, case.src_q0)
+    ref = solve.Operator(case.mesh, S)(solve.BlockJacobi(case.mesh, S)(x))
+    assert _rel(ys[1], ref) < 1e-10
+
+
+def test_restart_growth_on_stagnation():
+    """GMRES(1) stagnates on the 3D P2 system; the restart length doubles
+    (in a new workspace, the restart residual recomputed) until the solve
+    reaches the 1e-10 true residual, checked again with the oracle's matrix
+    (bound 1e-10 ||R|| plus 1e-11 sum_j |J_ij dx_j| for the two matrices'
+    rounding)."""
+    prob = SMALL["3d_p2_n3"]()
+    case, ctx = _pair(prob)
+    st0 = newton.initial_state(case)
+    got = {}
+    for m in (60, 1):
+        ctx.set_options(gmres_m=m)
+        ctx.set_state(st0.u, st0.p, st0.w_old)
+        ctx.assemble()
+        ctx.reset_profile()
+        ls = ctx.solve()
+        assert ls.true_relres <= 1e-10
+        got[m] = (np.concatenate(ctx.increment()), ctx.profile().n_mgrow)
+    assert got[60][1] == 0 and got[1][1] >= 1
+    ctx.close()
+    S = asm.assemble(case.mesh, case.itf, case.prm, st0.u, st0.p, st0.w_old, st0.s_p,
+                     case.src_pnode, case.src_q0)
+    J = asm.full_matrix(case.mesh, S)
+    dx = got[1][0]
+    r = J @ dx + S.R
+    mag = abs(J) @ np.abs(dx)
+    assert np.all(np.abs(r) <= 1e-10 * np.linalg.norm(S.R) + 1e-11 * mag)
+
+
 @pytest.mark.parametrize("name", ["2d_p1_n9", "3d_p2_n3"])
 def test_ir_fp64_finish(name):
     """The FP64 finish of a stalled GMRES-IR solve, forced for every solve
