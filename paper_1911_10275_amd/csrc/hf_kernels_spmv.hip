@@ -3,10 +3,11 @@
 // Jacobian storage.  Element row e of A is one contiguous "row panel": its
 // blocks (diagonal first, then one per interior face in local-face order)
 // each stored column-major, so the panel is a column-major bs x (nb*bs)
-// matrix.  The product streams each panel with 16-byte loads: a group of L
-// lanes reads CH = LA*EL consecutive values per step, and because CH is a
-// multiple of bs every lane keeps the same rows at every step; the products
-// are summed per lane and combined across lanes in a fixed order at the end.
+// matrix.  The product streams each panel with 16-byte nontemporal loads: a
+// group of L lanes reads CH = LA*EL consecutive values per step, and because
+// CH is a multiple of bs every lane keeps the same rows at every step; the
+// products are summed per lane and combined across lanes in a fixed order at
+// the end.
 // The x values a row panel needs are staged in LDS first.
 #include <cmath>
 
@@ -48,6 +49,24 @@ struct SpmvShape {
   static constexpr int RPC = CH / BU;  // columns advanced per step
   static_assert(CH % BU == 0, "chunk must hold whole columns");
 };
+
+// 16-byte load of matrix values with the nontemporal hint: the panels are
+// read once per product, and keeping them out of the caches' working set
+// leaves L2 to the x gathers of neighbouring rows
+typedef double hf_double2v __attribute__((ext_vector_type(2)));
+typedef float hf_float4v __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ inline typename Vec16<T>::type load_stream(const T *p);
+template <>
+__device__ inline double2 load_stream<double>(const double *p) {
+  const hf_double2v v = __builtin_nontemporal_load((const hf_double2v *)p);
+  return double2(v.x, v.y);
+}
+template <>
+__device__ inline float4 load_stream<float>(const float *p) {
+  const hf_float4v v = __builtin_nontemporal_load((const hf_float4v *)p);
+  return float4(v.x, v.y, v.z, v.w);
+}
 
 template <typename T>
 __device__ inline T vget(const typename Vec16<T>::type &v, int s);
@@ -128,7 +147,7 @@ __global__ __launch_bounds__(NT) void k_bsr_spmv(
     int f = lane * EL, cb = 0;
 #pragma unroll 8
     for (; f < total; f += CH, cb += RPC) {
-      const V v = *(const V *)(panel + f);
+      const V v = load_stream<T>(panel + f);
 #pragma unroll
       for (int s = 0; s < EL; ++s) acc[s] += vget<T>(v, s) * xs[g][cb + colS[s]];
     }
@@ -326,7 +345,7 @@ __global__ __launch_bounds__(NT) void k_bsr_resid(
     int f = lane * EL, cb = 0;
 #pragma unroll 4
     for (; f < total; f += CH, cb += RPC) {
-      const double2 v = *(const double2 *)(panel + f);
+      const double2 v = load_stream<double>(panel + f);
       dd_fma(acc[0], v.x, xs[g][cb + colS[0]]);
       dd_fma(acc[1], v.y, xs[g][cb + colS[1]]);
     }
