@@ -105,13 +105,18 @@ typedef struct {
                           FP32 (default 1) */
   int ir_inner_cycles; /* FP32-IR: GMRES(m) cycles per refinement step, >= 1
                           (default 1: the refinement steps are the restarts) */
-  int ir_stall_steps;  /* FP32-IR: an instance whose true residual falls by
-                          less than 10%, and by less than a tenth of what
-                          its FP32 cycle estimated, in this many consecutive
-                          refinement steps (FP32 accuracy, not the Krylov
-                          space, limits it: kappa u_32 near 1) finishes its
-                          solve in FP64 GMRES from the current correction;
-                          0: every instance at once, < 0: never (default 2) */
+  int ir_stall_steps;  /* FP32-IR: an instance with this many refinement
+                          steps (consecutive or not) whose true residual
+                          falls by less than 90% and by less than a tenth of
+                          what the FP32 cycle estimated (FP32 accuracy, not
+                          the Krylov space, limits it: kappa u_32 near 1)
+                          finishes its solve in FP64 GMRES from the current
+                          correction; a step that raises the true residual
+                          is undone and the instance finishes in FP64 at
+                          once.  Three steps with less than 1% reduction
+                          double the inner restart length (up to 256; at
+                          256 the instance finishes in FP64).  0: every
+                          instance in FP64 at once, < 0: never (default 2) */
   int incremental_assembly; /* 1: after the first full assembly, re-assemble
                           only the row panels of elements that touch a
                           cohesive or fluid interface, evaluate the other

@@ -116,6 +116,7 @@ struct hf_ctx {
   int *gj_perm = nullptr;
   int *flag = nullptr;
   double *dx = nullptr, *rhs = nullptr, *r64 = nullptr, *t64 = nullptr;
+  double *dx_save = nullptr;  // FP32-IR: the correction before the last refinement step
   KrylovWs<double> k64;
   KrylovWs<float> k32;
   double *partial = nullptr, *red = nullptr;
@@ -1966,23 +1967,40 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
     // with one cycle the refinement steps are exactly the restarts of
     // GMRES(m) (the restart residual computed in FP64), so FP32 rounding only
     // enters the per-cycle reduction, far above the FP32 floor
-    const int cap_inner = ctx->opt.ir_inner_cycles * ctx->opt.gmres_m;
+    int m_ir = ctx->opt.gmres_m;
+    int cap_inner = ctx->opt.ir_inner_cycles * m_ir;
     // stall test: a refinement step whose true reduction is both weak and far
-    // short of its FP32 estimate is limited by FP32 accuracy
+    // short of its FP32 estimate is limited by FP32 accuracy; after `stall`
+    // such steps (consecutive or not), or at once after a step that raised
+    // the true residual, the instance finishes in FP64 -- from the correction
+    // before that step when it raised the residual.  Restart stagnation
+    // (a true reduction of less than 1% that the estimate agrees with) in
+    // three consecutive steps doubles the inner restart length as in the
+    // FP64 solver; at the largest length the instance is finished in FP64.
     std::vector<double> rn_prev(B, 0.0), est(B, 1.0);
-    std::vector<int> slow(B, 0), fb(B, 0);
+    std::vector<int> slow(B, 0), flat(B, 0), fb(B, 0), undo(B, 0);
     const int stall = ctx->opt.ir_stall_steps;
+    if (stall >= 0 && !ctx->dx_save) TRY(dalloc(ctx, &ctx->dx_save, N));
     for (int outer = 0;; ++outer) {
       HIPCHK(ks_norms<double>(kd, ctx->r64, ctx->partial, ctx->red, stm));
       TRY(get_d(ctx, ctx->red, B));
-      bool any = false;
+      bool any = false, grow = false, anyundo = false;
+      const bool m_max = m_ir >= kMaxKrylov - 1;
       for (int b = 0; b < B; ++b) {
         if (!on[b]) continue;
         rn[b] = std::sqrt(ctx->hd[b]);
         ls[b].true_relres = rn[b] / bnorm[b];
+        const double before = rn_prev[b];
         if (outer > 0) {
-          const double got = rn[b] / rn_prev[b];
-          slow[b] = (got > 0.9 && got > 10.0 * est[b]) ? slow[b] + 1 : 0;
+          const double got = rn[b] / before;
+          if (got >= 1.0)
+            slow[b] = std::max(slow[b], stall);
+          else if (got > 0.1 && got > 10.0 * est[b])
+            slow[b] += 1;
+          flat[b] = got > 0.99 ? flat[b] + 1 : 0;
+          if (trace_on())
+            std::fprintf(stderr, "hf ir inst %d: step %d iters %d fp32 estimate %.3e true reduction %.3e\n",
+                         b, outer, ls[b].gmres_iters, est[b], got);
         }
         rn_prev[b] = rn[b];
         if (!std::isfinite(rn[b])) {
@@ -1991,18 +2009,41 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
           on[b] = 0;
         } else if (rn[b] <= ctx->opt.rtol * bnorm[b]) {
           on[b] = 0;
-        } else if (stall >= 0 && slow[b] >= stall && ls[b].gmres_iters < ctx->opt.gmres_maxit) {
+        } else if (stall >= 0 && (slow[b] >= stall || (m_max && flat[b] >= 3)) &&
+                   ls[b].gmres_iters < ctx->opt.gmres_maxit) {
           fb[b] = 1;  // finished in FP64 below
           on[b] = 0;
+          if (outer > 0 && rn[b] >= before) {  // undo the step that raised the residual
+            undo[b] = 1;
+            anyundo = true;
+            rn[b] = before;
+            ls[b].true_relres = before / bnorm[b];
+          }
         } else if (outer >= ctx->opt.ir_maxit || ls[b].gmres_iters >= ctx->opt.gmres_maxit) {
           st[b] = HF_ENOCONV;
           note(ctx, b, "GMRES-IR did not reach rtol within its caps");
           on[b] = 0;
         } else {
           any = true;
+          grow = grow || flat[b] >= 3;
         }
       }
+      if (anyundo) {
+        // dx back to its value before the step; the residual is recomputed
+        // (the same rows, kernel and operands, so the same values as before)
+        TRY(put(ctx, kd.solving, undo));
+        HIPCHK(ks_copy(kd, ctx->dx_save, ctx->dx, stm));
+        TRY(residual<double>(ctx, kp, op64, ctx->rhs, ctx->dx, ctx->t64, ctx->r64, rows(ctx, 1)));
+        for (int b = 0; b < B; ++b) undo[b] = 0;
+      }
       if (!any) break;
+      if (grow && !m_max) {
+        m_ir = std::min(2 * m_ir, kMaxKrylov - 1);
+        cap_inner = ctx->opt.ir_inner_cycles * m_ir;
+        TRY(ensure_ws<float>(ctx, ctx->k32, m_ir));  // no state carried between steps
+        for (int b = 0; b < B; ++b) flat[b] = 0;
+        ctx->prof.n_mgrow += 1;
+      }
       std::vector<double> coef(B, 0.0), tol(B, ctx->opt.rtol_inner);
       std::vector<int> cap(B, 0);
       for (int b = 0; b < B; ++b)
@@ -2034,6 +2075,7 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
       // dx += ||r|| d ; r = b - J dx (FP64)
       TRY(put(ctx, kd.solving, on));
       TRY(put(ctx, ctx->k_coef, coef));
+      if (ctx->dx_save) HIPCHK(ks_copy(kd, ctx->dx, ctx->dx_save, stm));
       HIPCHK((ks_axpy<double, float>(kd, ctx->k_coef, ctx->k32.x, ctx->dx, stm)));
       TRY(residual<double>(ctx, kp, op64, ctx->rhs, ctx->dx, ctx->t64, ctx->r64, rows(ctx, 1)));
     }

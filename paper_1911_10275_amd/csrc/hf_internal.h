@@ -244,6 +244,8 @@ template <typename T>
 hipError_t ks_sub(const KrylovDev &kd, const T *b, const T *jx, T *r, hipStream_t st);
 template <typename TY, typename TX>
 hipError_t ks_cast(const KrylovDev &kd, const TX *x, const double *coef, TY *y, hipStream_t st);
+// y = x on the rows of iterating instances
+hipError_t ks_copy(const KrylovDev &kd, const double *x, double *y, hipStream_t st);
 template <typename T>
 hipError_t ks_zero(const KrylovDev &kd, T *x, int only_solving, hipStream_t st);
 // flag[b] = 1 when instance b takes a second Gram-Schmidt pass: policy 0 when

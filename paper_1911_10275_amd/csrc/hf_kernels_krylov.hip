@@ -424,6 +424,17 @@ __global__ __launch_bounds__(KT) void k_scast(KrylovDev kd, const TX *__restrict
   for (int rr = tid; rr < len; rr += KT) y[row0 + rr] = a == 0.0 ? TY(0) : (TY)(a * (double)x[row0 + rr]);
 }
 
+// y[r] = x[r] on the rows of iterating instances (other instances untouched)
+template <typename T>
+__global__ __launch_bounds__(KT) void k_scopy(KrylovDev kd, const T *__restrict__ x, T *__restrict__ y) {
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int b = kd.c_inst[c];
+  if (!kd.solving[b]) return;
+  const int64_t row0 = kd.c_row0[c];
+  const int len = kd.c_len[c];
+  for (int rr = tid; rr < len; rr += KT) y[row0 + rr] = x[row0 + rr];
+}
+
 // zero a vector segment-wise (graph-safe replacement of memset)
 template <typename T>
 __global__ __launch_bounds__(KT) void k_szero(KrylovDev kd, T *__restrict__ x, int only_solving) {
@@ -670,6 +681,10 @@ hipError_t ks_sub(const KrylovDev &kd, const T *b, const T *jx, T *r, hipStream_
 template <typename TY, typename TX>
 hipError_t ks_cast(const KrylovDev &kd, const TX *x, const double *coef, TY *y, hipStream_t st) {
   hipLaunchKernelGGL((k_scast<TY, TX>), dim3(kd.n_chunks), dim3(KT), 0, st, kd, x, coef, y);
+  return hipGetLastError();
+}
+hipError_t ks_copy(const KrylovDev &kd, const double *x, double *y, hipStream_t st) {
+  hipLaunchKernelGGL(k_scopy<double>, dim3(kd.n_chunks), dim3(KT), 0, st, kd, x, y);
   return hipGetLastError();
 }
 template <typename T>

@@ -252,6 +252,31 @@ def test_restart_growth_on_stagnation():
     assert np.all(np.abs(r) <= 1e-10 * np.linalg.norm(S.R) + 1e-11 * mag)
 
 
+def test_ir_restart_growth_on_stagnation():
+    """GMRES-IR with one FP32 GMRES(1) cycle per refinement step stagnates as
+    restarted GMRES(1) does; the inner restart length doubles until the
+    refinement reaches the 1e-10 true residual, checked with the oracle's
+    matrix as in the FP64 case."""
+    prob = SMALL["3d_p2_n3"]()
+    case, ctx = _pair(prob)
+    st0 = newton.initial_state(case)
+    ctx.set_options(precision=hf.HF_FP32_IR, gmres_m=1)
+    ctx.set_state(st0.u, st0.p, st0.w_old)
+    ctx.assemble()
+    ctx.reset_profile()
+    ls = ctx.solve()
+    assert ls.true_relres <= 1e-10 and ls.ir_steps > 0
+    assert ctx.profile().n_mgrow >= 1
+    dx = np.concatenate(ctx.increment())
+    ctx.close()
+    S = asm.assemble(case.mesh, case.itf, case.prm, st0.u, st0.p, st0.w_old, st0.s_p,
+                     case.src_pnode, case.src_q0)
+    J = asm.full_matrix(case.mesh, S)
+    r = J @ dx + S.R
+    mag = abs(J) @ np.abs(dx)
+    assert np.all(np.abs(r) <= 1e-10 * np.linalg.norm(S.R) + 1e-11 * mag)
+
+
 @pytest.mark.parametrize("name", ["2d_p1_n9", "3d_p2_n3"])
 def test_ir_fp64_finish(name):
     """The FP64 finish of a stalled GMRES-IR solve, forced for every solve
