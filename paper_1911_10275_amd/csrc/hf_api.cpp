@@ -2556,13 +2556,18 @@ hf_status tune_kernels(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, hf_tuning
   TRY(put(ctx, kd.solving, std::vector<int>(B, 1)));
   HIPCHK(hipMemsetAsync(kd.kconv, 0xFF, B * sizeof(int), ctx->stream));  // -1: iterating
   const RowSel all{};
+  // a later variant replaces the current pick only when it is faster by more
+  // than 2%: near-ties (the two product shapes) then keep the first variant
+  // instead of following timing noise, so that the same build makes the same
+  // choice (and rounds the same way) from run to run
+  constexpr double kMargin = 0.98;
   double best_ms = 1e300;
   for (int v = 0; v <= 1; ++v) {
     ctx->tune.spmv_var = v;
     const KParams kp = kparams(ctx);
     double ms = 0.0;
     TRY(time_ms(ctx, 10, [&]() { return apply_J<T>(ctx, kp, op, ws.z, ws.w, all); }, ms));
-    if (ms < best_ms) best_ms = ms, best.spmv_var = v;
+    if (ms < kMargin * best_ms) best_ms = ms, best.spmv_var = v;
   }
   best_ms = 1e300;
   for (int v = 0; v <= 1; ++v) {
@@ -2570,7 +2575,7 @@ hf_status tune_kernels(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, hf_tuning
     const KParams kp = kparams(ctx);
     double ms = 0.0;
     TRY(time_ms(ctx, 10, [&]() { return apply_M<T>(ctx, kp, op, ws.z, ws.t, all); }, ms));
-    if (ms < best_ms) best_ms = ms, best.prec_var = v;
+    if (ms < kMargin * best_ms) best_ms = ms, best.prec_var = v;
   }
   best_ms = 1e300;
   const int k = std::max(1, ws.m / 2), ks = k + 1;
@@ -2583,7 +2588,7 @@ hf_status tune_kernels(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, hf_tuning
                           ctx->stream));
       return HF_OK;
     }, ms));
-    if (ms < best_ms) best_ms = ms, best.ortho_var = v;
+    if (ms < kMargin * best_ms) best_ms = ms, best.ortho_var = v;
   }
   TRY(sync(ctx));
   return HF_OK;
@@ -2661,7 +2666,7 @@ extern "C" hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path,
         const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         bool ok = true;
         for (const auto &l : ls) ok = ok && l.status == HF_OK;
-        if (ok && sec < best_s) best_s = sec, pick = t;
+        if (ok && sec < 0.98 * best_s) best_s = sec, pick = t;  // same margin as above
       }
     ctx->ierr.clear();
     TRY(hf_set_tuning(ctx, &pick));
