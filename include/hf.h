@@ -223,9 +223,13 @@ typedef struct {
      the true residual above the target for two cycles (counted whatever
      hf_options.profile is) */
   int64_t n_unfold;
-  /* FP64 solves whose restart length doubled after three cycles with less
-     than 1% progress (restarted-GMRES stagnation) */
+  /* restart-length doublings after three cycles (FP64 solves) or three
+     refinement steps (FP32-IR) with less than 1% progress (restarted-GMRES
+     stagnation) */
   int64_t n_mgrow;
+  /* FP32-IR refinement steps undone because they raised the true residual
+     (each such instance then finishes its solve in FP64) */
+  int64_t n_ir_undo;
 } hf_profile;
 
 /* Fill *opt with the defaults listed above. */

@@ -2016,6 +2016,7 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
           if (outer > 0 && rn[b] >= before) {  // undo the step that raised the residual
             undo[b] = 1;
             anyundo = true;
+            ctx->prof.n_ir_undo += 1;
             rn[b] = before;
             ls[b].true_relres = before / bnorm[b];
           }

@@ -50,3 +50,41 @@ def test_create_without_gpu_fails_cleanly():
     with pytest.raises(hf.HFError) as ei:
         hf.Context()
     assert ei.value.status in (hf.HF_EDEVICE, hf.HF_EINVAL)
+
+
+_STRUCTS = {"hf_options": "Options", "hf_material": "Material", "hf_sizes": "Sizes",
+            "hf_solve_stats": "SolveStats", "hf_newton_stats": "NewtonStats",
+            "hf_tuning": "Tuning", "hf_profile": "Profile"}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every struct of include/hf.h, compiled by the host C compiler, has the
+    size and the field offsets of its ctypes mirror in the binding."""
+    import shutil
+    import subprocess
+    import paper_1911_10275_amd as hf
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "hf.h"', "int main(void) {"]
+    for cname, pname in _STRUCTS.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in getattr(hf, pname)._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    exe = tmp_path / "layout"
+    src.write_text("\n".join(lines) + "\n")
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            cname, what, val = line.split()
+            got[(cname, what)] = int(val)
+    for cname, pname in _STRUCTS.items():
+        py = getattr(hf, pname)
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
