@@ -59,6 +59,17 @@ __device__ inline bool inst_on(const KrylovDev &kd, int b) {
 // lane issues its KRL loads at once and one wavefront sum gives the dot, so
 // there is no cross-wave combination; two vectors are in flight at a time.
 constexpr int KRL = kChunkRows / 64;  // rows per lane of a wavefront-wide chunk
+
+// Load of a basis entry by the Gram-Schmidt passes: FP64 bases (m+1 vectors
+// of N doubles, far beyond the caches at full size) are streamed with the
+// nontemporal hint; FP32 bases use plain loads, which measured faster there.
+template <typename T>
+__device__ inline T ld_basis(const T *p) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
 template <typename T, int RR>
 __global__ __launch_bounds__(kChunkRows / RR) void k_sproj(KrylovDev kd, const T *__restrict__ V, int64_t ldv,
                                                            int k, const T *__restrict__ w,
@@ -98,7 +109,7 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_sproj(KrylovDev kd, const T
     for (int s = 0; s < KRL; ++s) {
       const int rc = min(lane + 64 * s, len - 1);
 #pragma unroll
-      for (int f = 0; f < VF; ++f) x[f][s] = V[(int64_t)(i + f * NW) * ldv + row0 + rc];
+      for (int f = 0; f < VF; ++f) x[f][s] = ld_basis(&V[(int64_t)(i + f * NW) * ldv + row0 + rc]);
     }
     double a[VF];
 #pragma unroll
@@ -117,7 +128,7 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_sproj(KrylovDev kd, const T
     const T *va = V + (int64_t)i * ldv + row0;
     double a0 = 0.0;
 #pragma unroll
-    for (int s = 0; s < KRL; ++s) a0 += (double)va[min(lane + 64 * s, len - 1)] * wr[s];
+    for (int s = 0; s < KRL; ++s) a0 += (double)ld_basis(&va[min(lane + 64 * s, len - 1)]) * wr[s];
     a0 = kwave_sum(a0);
     if (lane == 0) out[i] = a0;
   }
@@ -161,7 +172,7 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_supdate(KrylovDev kd, const
 #pragma unroll
     for (int q = 0; q < TW; ++q)
 #pragma unroll
-      for (int s = 0; s < RR; ++s) x[q][s] = V[(int64_t)(i0 + q) * ldv + row0 + rc[s]];
+      for (int s = 0; s < RR; ++s) x[q][s] = ld_basis(&V[(int64_t)(i0 + q) * ldv + row0 + rc[s]]);
 #pragma unroll
     for (int s = 0; s < RR; ++s)
 #pragma unroll
@@ -169,7 +180,7 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_supdate(KrylovDev kd, const
   }
   for (; i0 < k; ++i0) {
 #pragma unroll
-    for (int s = 0; s < RR; ++s) acc[s] -= sh[i0] * (double)V[(int64_t)i0 * ldv + row0 + rc[s]];
+    for (int s = 0; s < RR; ++s) acc[s] -= sh[i0] * (double)ld_basis(&V[(int64_t)i0 * ldv + row0 + rc[s]]);
   }
   double nn = 0.0;
 #pragma unroll
@@ -231,8 +242,8 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_sproj2(KrylovDev kd, const 
 #pragma unroll
     for (int s = 0; s < KRL; ++s) {
       const int rc = min(lane + 64 * s, len - 1);  // s_w, s_v are 0 past len
-      xa[s] = va[rc];
-      xb[s] = vb[rc];
+      xa[s] = ld_basis(&va[rc]);
+      xb[s] = ld_basis(&vb[rc]);
     }
     double aw = 0.0, av = 0.0, bw = 0.0, bv = 0.0;
 #pragma unroll
@@ -262,7 +273,7 @@ __global__ __launch_bounds__(kChunkRows / RR) void k_sproj2(KrylovDev kd, const 
 #pragma unroll
     for (int s = 0; s < KRL; ++s) {
       const int rr = lane + 64 * s;
-      const double x = (double)va[min(rr, len - 1)];
+      const double x = (double)ld_basis(&va[min(rr, len - 1)]);
       aw += x * s_w[rr];
       av += x * s_v[rr];
     }
