@@ -81,7 +81,9 @@ typedef struct {
   int precision;       /* HF_FP64: FP64 GMRES; HF_FP32_IR: FP32 inner GMRES +
                           FP32 block inverses, FP64 residual and update */
   int gmres_m;         /* restart length, 1..256 (default 60) */
-  int gmres_maxit;     /* GMRES iterations per linear solve (default 20000) */
+  int gmres_maxit;     /* GMRES iterations per linear solve (default 20000;
+                          in FP32-IR the FP32 refinement and an FP64 solve
+                          after it have one such budget each) */
   int ir_maxit;        /* refinement steps per linear solve (default 1000) */
   int newton_maxit;    /* iterations of hf_newton_solve (default 25) */
   double rtol;         /* true relative residual of every solve (1e-10) */
@@ -109,13 +111,15 @@ typedef struct {
                           steps (consecutive or not) whose true residual
                           falls by less than 90% and by less than a tenth of
                           what the FP32 cycle estimated (FP32 accuracy, not
-                          the Krylov space, limits it: kappa u_32 near 1)
-                          finishes its solve in FP64 GMRES from the current
-                          correction; a step that raises the true residual
-                          is undone and the instance finishes in FP64 at
-                          once.  Three steps with less than 1% reduction
-                          double the inner restart length (up to 256; at
-                          256 the instance finishes in FP64).  0: every
+                          the Krylov space, limits it: kappa u_32 near 1) is
+                          solved again in FP64: FP64 GMRES on J dx = b from
+                          dx = 0, with a gmres_maxit budget of its own (its
+                          iterations are added to the solve's count and
+                          reported as fp64_iters).  So is an instance after
+                          a step that raised the true residual, or at the
+                          refinement's caps.  Three steps with less than 1%
+                          reduction double the inner restart length (up to
+                          256; at 256 the instance goes to FP64).  0: every
                           instance in FP64 at once, < 0: never (default 2) */
   int incremental_assembly; /* 1: after the first full assembly, re-assemble
                           only the row panels of elements that touch a
@@ -227,9 +231,9 @@ typedef struct {
      refinement steps (FP32-IR) with less than 1% progress (restarted-GMRES
      stagnation) */
   int64_t n_mgrow;
-  /* FP32-IR refinement steps undone because they raised the true residual
-     (each such instance then finishes its solve in FP64) */
-  int64_t n_ir_undo;
+  /* FP32-IR refinement steps that raised the true residual (each sends its
+     instance to the FP64 solve at once) */
+  int64_t n_ir_rise;
 } hf_profile;
 
 /* Fill *opt with the defaults listed above. */

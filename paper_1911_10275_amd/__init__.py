@@ -91,7 +91,7 @@ class Profile(C.Structure):
                                           "n_precond", "n_ortho", "n_inv_mfma",
                                           "n_inv_fallback")] + \
                [("ms_resid", C.c_double), ("n_resid", C.c_int64), ("n_unfold", C.c_int64),
-                ("n_mgrow", C.c_int64), ("n_ir_undo", C.c_int64)]
+                ("n_mgrow", C.c_int64), ("n_ir_rise", C.c_int64)]
 
 
 class HFError(RuntimeError):

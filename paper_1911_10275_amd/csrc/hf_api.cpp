@@ -116,7 +116,6 @@ struct hf_ctx {
   int *gj_perm = nullptr;
   int *flag = nullptr;
   double *dx = nullptr, *rhs = nullptr, *r64 = nullptr, *t64 = nullptr;
-  double *dx_save = nullptr;  // FP32-IR: the correction before the last refinement step
   KrylovWs<double> k64;
   KrylovWs<float> k32;
   double *partial = nullptr, *red = nullptr;
@@ -1841,12 +1840,15 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
   return HF_OK;
 }
 
-// FP32-IR instances whose refinement stalled (fb[b] = 1): FP64 block-Jacobi
-// factors for every element (the FP32-IR build made FP64 ones only where the
-// Schur block needs them), then FP64 GMRES on J d = r (r = the current
-// refinement residual, norm rn[b]) to the outer target, and dx += d.
-static hf_status ir_fp64_finish(hf_ctx *ctx, const std::vector<int> &fb, const std::vector<double> &bnorm,
-                                const std::vector<double> &rn, std::vector<hf_solve_stats> &ls,
+// FP32-IR instances whose refinement stalled (fb[b] = 1) are solved again in
+// FP64: FP64 block-Jacobi factors for every element (the FP32-IR build made
+// FP64 ones only where the Schur block needs them), then FP64 GMRES on the
+// original system J dx = b from dx = 0, with a gmres_maxit budget of its own.
+// It does not go on from the refinement's correction: FP32 steps that stall
+// leave errors in the ill-conditioned directions of dx that are large against
+// the residual they leave, and removing them took FP64 GMRES far longer than
+// the whole solve (up to a floor of its own above the target).
+static hf_status ir_fp64_finish(hf_ctx *ctx, const std::vector<int> &fb, std::vector<hf_solve_stats> &ls,
                                 std::vector<hf_status> &st) {
   const Sizes &s = ctx->s;
   const int B = nI(ctx);
@@ -1878,13 +1880,12 @@ static hf_status ir_fp64_finish(hf_ctx *ctx, const std::vector<int> &fb, const s
     op.tp = ctx->tp64;
   }
   TRY(ensure_ws<double>(ctx, ctx->k64));
-  std::vector<double> tol(B, 0.5);
-  std::vector<int> cap(B, 0);
-  for (int b = 0; b < B; ++b)
-    if (fb[b]) {
-      tol[b] = std::min(0.5, ctx->opt.rtol * bnorm[b] / rn[b]);
-      cap[b] = ctx->opt.gmres_maxit - ls[b].gmres_iters;
-    }
+  // dx = 0 and r = b on the rows of these instances
+  TRY(put(ctx, kd.solving, fb));
+  HIPCHK(ks_zero<double>(kd, ctx->dx, 1, ctx->stream));
+  HIPCHK(ks_copy(kd, ctx->rhs, ctx->r64, ctx->stream));
+  std::vector<double> tol(B, ctx->opt.rtol);
+  std::vector<int> cap(B, ctx->opt.gmres_maxit);
   std::vector<SolveOut> out;
   TRY(gmres_b<double>(ctx, op, ctx->k64, ctx->r64, ctx->t64, tol, true, fb, cap, out, op.Af ? &seq : nullptr));
   std::vector<double> one(B, 0.0);
@@ -1894,7 +1895,7 @@ static hf_status ir_fp64_finish(hf_ctx *ctx, const std::vector<int> &fb, const s
     ls[b].gmres_iters += out[b].iters;
     ls[b].fp64_iters = out[b].iters;
     ls[b].restarts += out[b].restarts;
-    ls[b].true_relres = out[b].relres * rn[b] / bnorm[b];
+    ls[b].true_relres = out[b].relres;
     st[b] = out[b].st;
   }
   TRY(put(ctx, kd.solving, fb));
@@ -1971,32 +1972,32 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
     int cap_inner = ctx->opt.ir_inner_cycles * m_ir;
     // stall test: a refinement step whose true reduction is both weak and far
     // short of its FP32 estimate is limited by FP32 accuracy; after `stall`
-    // such steps (consecutive or not), or at once after a step that raised
-    // the true residual, the instance finishes in FP64 -- from the correction
-    // before that step when it raised the residual.  Restart stagnation
-    // (a true reduction of less than 1% that the estimate agrees with) in
-    // three consecutive steps doubles the inner restart length as in the
-    // FP64 solver; at the largest length the instance is finished in FP64.
+    // such steps (consecutive or not), at once after a step that raised the
+    // true residual, or when the refinement reaches its caps, the instance
+    // is solved again in FP64 (ir_fp64_finish).  Restart stagnation (a true
+    // reduction of less than 1% that the estimate agrees with) in three
+    // consecutive steps doubles the inner restart length as in the FP64
+    // solver; at the largest length the instance goes to FP64 as well.
     std::vector<double> rn_prev(B, 0.0), est(B, 1.0);
-    std::vector<int> slow(B, 0), flat(B, 0), fb(B, 0), undo(B, 0);
+    std::vector<int> slow(B, 0), flat(B, 0), fb(B, 0);
     const int stall = ctx->opt.ir_stall_steps;
-    if (stall >= 0 && !ctx->dx_save) TRY(dalloc(ctx, &ctx->dx_save, N));
     for (int outer = 0;; ++outer) {
       HIPCHK(ks_norms<double>(kd, ctx->r64, ctx->partial, ctx->red, stm));
       TRY(get_d(ctx, ctx->red, B));
-      bool any = false, grow = false, anyundo = false;
+      bool any = false, grow = false;
       const bool m_max = m_ir >= kMaxKrylov - 1;
       for (int b = 0; b < B; ++b) {
         if (!on[b]) continue;
         rn[b] = std::sqrt(ctx->hd[b]);
         ls[b].true_relres = rn[b] / bnorm[b];
-        const double before = rn_prev[b];
         if (outer > 0) {
-          const double got = rn[b] / before;
-          if (got >= 1.0)
+          const double got = rn[b] / rn_prev[b];
+          if (got >= 1.0) {
             slow[b] = std::max(slow[b], stall);
-          else if (got > 0.1 && got > 10.0 * est[b])
+            ctx->prof.n_ir_rise += 1;
+          } else if (got > 0.1 && got > 10.0 * est[b]) {
             slow[b] += 1;
+          }
           flat[b] = got > 0.99 ? flat[b] + 1 : 0;
           if (trace_on())
             std::fprintf(stderr, "hf ir inst %d: step %d iters %d fp32 estimate %.3e true reduction %.3e\n",
@@ -2009,17 +2010,10 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
           on[b] = 0;
         } else if (rn[b] <= ctx->opt.rtol * bnorm[b]) {
           on[b] = 0;
-        } else if (stall >= 0 && (slow[b] >= stall || (m_max && flat[b] >= 3)) &&
-                   ls[b].gmres_iters < ctx->opt.gmres_maxit) {
-          fb[b] = 1;  // finished in FP64 below
+        } else if (stall >= 0 && (slow[b] >= stall || (m_max && flat[b] >= 3) || outer >= ctx->opt.ir_maxit ||
+                                  ls[b].gmres_iters >= ctx->opt.gmres_maxit)) {
+          fb[b] = 1;  // solved in FP64 below
           on[b] = 0;
-          if (outer > 0 && rn[b] >= before) {  // undo the step that raised the residual
-            undo[b] = 1;
-            anyundo = true;
-            ctx->prof.n_ir_undo += 1;
-            rn[b] = before;
-            ls[b].true_relres = before / bnorm[b];
-          }
         } else if (outer >= ctx->opt.ir_maxit || ls[b].gmres_iters >= ctx->opt.gmres_maxit) {
           st[b] = HF_ENOCONV;
           note(ctx, b, "GMRES-IR did not reach rtol within its caps");
@@ -2028,14 +2022,6 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
           any = true;
           grow = grow || flat[b] >= 3;
         }
-      }
-      if (anyundo) {
-        // dx back to its value before the step; the residual is recomputed
-        // (the same rows, kernel and operands, so the same values as before)
-        TRY(put(ctx, kd.solving, undo));
-        HIPCHK(ks_copy(kd, ctx->dx_save, ctx->dx, stm));
-        TRY(residual<double>(ctx, kp, op64, ctx->rhs, ctx->dx, ctx->t64, ctx->r64, rows(ctx, 1)));
-        for (int b = 0; b < B; ++b) undo[b] = 0;
       }
       if (!any) break;
       if (grow && !m_max) {
@@ -2076,13 +2062,12 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
       // dx += ||r|| d ; r = b - J dx (FP64)
       TRY(put(ctx, kd.solving, on));
       TRY(put(ctx, ctx->k_coef, coef));
-      if (ctx->dx_save) HIPCHK(ks_copy(kd, ctx->dx, ctx->dx_save, stm));
       HIPCHK((ks_axpy<double, float>(kd, ctx->k_coef, ctx->k32.x, ctx->dx, stm)));
       TRY(residual<double>(ctx, kp, op64, ctx->rhs, ctx->dx, ctx->t64, ctx->r64, rows(ctx, 1)));
     }
     bool anyfb = false;
     for (int b = 0; b < B; ++b) anyfb = anyfb || fb[b];
-    if (anyfb) TRY(ir_fp64_finish(ctx, fb, bnorm, rn, ls, st));
+    if (anyfb) TRY(ir_fp64_finish(ctx, fb, ls, st));
   }
   TRY(sync(ctx));
   const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
