@@ -271,8 +271,8 @@ def main():
                          "build (matrix-core block inverses), nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
-              "multi-GPU sharding is a design, not an implementation", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for {args.gpus}); sharding over "
+              "several GPUs is designed, not implemented", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
