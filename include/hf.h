@@ -79,20 +79,21 @@ enum { HF_FP64 = 0, HF_FP32_IR = 1 };
 
 typedef struct {
   int precision;       /* HF_FP64: FP64 GMRES; HF_FP32_IR: FP32 inner GMRES +
-                          FP32 block inverses, FP64 residual and update */
+                          FP32 block inverses, FP64 residual and update
+                          (default 0 = HF_FP64) */
   int gmres_m;         /* restart length, 1..256 (default 60) */
   int gmres_maxit;     /* GMRES iterations per linear solve (default 20000;
                           in FP32-IR the FP32 refinement and an FP64 solve
                           after it have one such budget each) */
   int ir_maxit;        /* refinement steps per linear solve (default 1000) */
   int newton_maxit;    /* iterations of hf_newton_solve (default 25) */
-  double rtol;         /* true relative residual of every solve (1e-10) */
+  double rtol;         /* true relative residual of every solve (default 1e-10) */
   double rtol_inner;   /* FP32-IR: a refinement step's inner GMRES stops once its
                           residual estimate has fallen by this factor, or
                           where the outer rtol is met (default 1e-4) */
-  double newton_tol;   /* ||dU|| <= tol ||U|| and ||dP|| <= tol ||P|| (1e-10) */
+  double newton_tol;   /* ||dU|| <= tol ||U|| and ||dP|| <= tol ||P|| (default 1e-10) */
   double b_stab;       /* DG stabilisation parameter b (default 10) */
-  double p_cutoff;     /* pressure cut-off value when cutoff_on != 0 */
+  double p_cutoff;     /* pressure cut-off value when cutoff_on != 0 (default 0) */
   int cutoff_on;       /* clamp p >= p_cutoff after each update (default 0) */
   int device;          /* HIP device ordinal (default 0) */
   int profile;         /* 1: time kernel classes with HIP events (default 0);

@@ -88,3 +88,21 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_documented_option_defaults_match_the_library():
+    """Every '(default X)' that include/hf.h states for an hf_options field is
+    the value hf_default_options sets."""
+    import paper_1911_10275_amd as hf
+    txt = open(HEADER).read()
+    body = re.search(r"typedef struct \{(.*?)\} hf_options;", txt, re.S).group(1)
+    fields = re.findall(r"(?:int|double|void\s*\*)\s*(\w+);\s*/\*(.*?)\*/", body, re.S)
+    o = hf.default_options()
+    checked = 0
+    for name, comment in fields:
+        m = re.search(r"\(default\s*:?\s*([-+0-9.eE]+)", " ".join(comment.split()))
+        if m is None:
+            continue
+        assert getattr(o, name) == pytest.approx(float(m.group(1))), name
+        checked += 1
+    assert checked >= 12
