@@ -68,7 +68,8 @@ typedef enum {
   HF_ENOMEM = -2,     /* device or host allocation failed */
   HF_EDEVICE = -3,    /* a HIP runtime call or kernel launch failed */
   HF_ESTATE = -4,     /* call out of order */
-  HF_ESINGULAR = -5,  /* zero / non-finite pivot in a preconditioner block */
+  HF_ESINGULAR = -5,  /* singular (to working precision) or non-finite
+                         preconditioner block */
   HF_ENOCONV = -6,    /* GMRES, refinement or Newton hit its iteration cap */
   HF_ENONFINITE = -7  /* NaN or Inf in an input state or a computed result */
 } hf_status;
@@ -166,6 +167,12 @@ typedef struct {
                           gmres_iters), 0 otherwise */
   double true_relres;  /* ||b - J dx|| / ||b||, recomputed in FP64 */
   double seconds;      /* wall time of the (batched) solve */
+  double relres_u;     /* per-block true residuals after the solve (FP64,
+                          compensated): ||(b - J dx)_u|| / ||b_u|| over the
+                          displacement rows and */
+  double relres_p;     /* ||(b - J dx)_p|| / ||b_p|| over the pressure rows;
+                          a block whose part of b is zero is measured
+                          against ||b||; 0 for an instance not solved */
 } hf_solve_stats;
 
 typedef struct {
@@ -314,20 +321,38 @@ hf_status hf_get_state_device(hf_ctx *ctx, int32_t inst, double *u, double *p);
    (eq. discreteElastoStatics, eq. discreteLubrication and their exact
    derivative), all instances.  res_norm[b] = ||R_b|| (nullable array). */
 hf_status hf_assemble(hf_ctx *ctx, double *res_norm);
-/* Build the preconditioner and solve J dx = -R of every instance to the
-   true relative residual rtol (GMRES or GMRES-IR per options); dx is kept
-   in the ctx; stats[b] per instance (nullable array). */
+/* The linear solve of one Newton iteration: the 2x2 block system of eq.
+   (fully-coupled-fully-discrete), J dx = -R with J = [[A, B], [C, D]], which
+   the paper solves at every nonlinear iteration with a preconditioned Krylov
+   method (Sec. "Computational framework", implementation paragraph; here
+   element block-Jacobi with the pressure unknowns as one Schur block).
+   Builds the preconditioner and solves every instance to the true relative
+   residual rtol (GMRES or GMRES-IR per options); dx is kept in the ctx;
+   stats[b] per instance (nullable array).  HF_ESINGULAR: a preconditioner
+   block of the instance is singular to working precision (a pivot at most
+   1e-13 of the block's largest entry, or not finite); HF_ENOCONV: the
+   iteration caps were reached; HF_ENONFINITE: a non-finite right-hand side
+   or Krylov vector.  The failing instance's dx is undefined. */
 hf_status hf_solve(hf_ctx *ctx, hf_solve_stats *stats);
-/* One Newton iteration of every instance: assemble + solve + update u, p
-   (+ optional cut-off).  An instance whose solve fails (HF_ENOCONV,
-   HF_ESINGULAR, HF_ENONFINITE) keeps its state.  stats[b] per instance. */
+/* One Newton-Raphson iteration of every instance (Sec. "Computational
+   framework": the system is linearised at the current iterate, solved, and
+   the increments of both nodal arrays U and P are added; convergence is
+   judged on the Euclidean norms of the relative increments): assemble +
+   solve + update u, p (+ optional cut-off of the remark on fluid lag).  An
+   instance whose solve fails (HF_ENOCONV, HF_ESINGULAR, HF_ENONFINITE)
+   keeps its state.  stats[b] per instance. */
 hf_status hf_newton_step(hf_ctx *ctx, hf_newton_stats *stats);
-/* Newton iterations until every instance has converged or failed; an
-   instance stops iterating once converged.  An instance that has not
-   converged within newton_maxit (HF_ENOCONV) or failed gets back its state
-   at the start of the call.  stats[b] per instance (nullable array). */
+/* The Newton loop of one time step (Sec. "Computational framework"):
+   iterations until every instance has converged (||dU|| <= newton_tol
+   ||U||, ||dP|| <= newton_tol ||P||) or failed; an instance stops iterating
+   once converged.  An instance that has not converged within newton_maxit
+   (HF_ENOCONV) or failed gets back its state at the start of the call.
+   stats[b] per instance (nullable array). */
 hf_status hf_newton_solve(hf_ctx *ctx, hf_newton_stats *stats);
-/* End of a given-length load step: w_old <- w(u), s_p recomputed. */
+/* End of a given-length load step: the opening of the converged state
+   becomes the previous opening w^n of the storage term (w - w^n)/dt of eq.
+   (discreteLubrication), w_old <- w(u) at every face point, and the
+   fluid-row scale s_p is recomputed from it. */
 hf_status hf_end_load_step(hf_ctx *ctx);
 /* Starting state of the first load step: the uniform-pressure elastic
    predictor.  With the pressure held fixed at 1 the displacement rows are

@@ -65,7 +65,7 @@ class Sizes(C.Structure):
 class SolveStats(C.Structure):
     _fields_ = [("gmres_iters", C.c_int), ("ir_steps", C.c_int), ("restarts", C.c_int),
                 ("status", C.c_int), ("fp64_iters", C.c_int), ("true_relres", C.c_double),
-                ("seconds", C.c_double)]
+                ("seconds", C.c_double), ("relres_u", C.c_double), ("relres_p", C.c_double)]
 
 
 class NewtonStats(C.Structure):

@@ -82,6 +82,7 @@ struct hf_ctx {
   Sizes s;
   DevMesh m;
   RuleTables rules{};
+  RuleTables *d_rules = nullptr;  // device copy read by the kernels
   int freeze_p = 0;
   std::vector<void *> allocs;
   // per-instance offsets (host) and their device copies
@@ -155,11 +156,15 @@ hf_status fail(hf_ctx *ctx, hf_status st, const std::string &msg) {
   return st;
 }
 
+// A failed HIP call also leaves the thread's last-error state set; it is
+// cleared here so that it is not reported again by a later launch check.
 #define HIPCHK(call)                                                                  \
   do {                                                                                \
     hipError_t e_ = (call);                                                           \
-    if (e_ != hipSuccess)                                                             \
+    if (e_ != hipSuccess) {                                                           \
+      (void)hipGetLastError();                                                        \
       return fail(ctx, HF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    }                                                                                 \
   } while (0)
 
 #define TRY(call)               \
@@ -215,6 +220,7 @@ KParams kparams(const hf_ctx *ctx) {
   kp.poff = ctx->d_poff;
   kp.doff = ctx->d_doff;
   kp.aoff = ctx->d_aoff;
+  kp.rt = ctx->d_rules;
   kp.n_inst = nI(ctx);
   kp.b_stab = ctx->opt.b_stab;
   kp.freeze_p = ctx->freeze_p;
@@ -263,6 +269,17 @@ hf_status ensure_host(hf_ctx *ctx, size_t nd, size_t ni, size_t nu) {
       return fail(ctx, HF_ENOMEM, "pinned host allocation failed");
     ctx->hu_n = nu;
   }
+  return HF_OK;
+}
+
+// device -> host copy on the context stream, synchronised (the legacy
+// stream is never used: work on it would break a graph capture that
+// another thread runs on a blocking stream)
+hf_status d2h(hf_ctx *ctx, void *dst, const void *src, size_t bytes) {
+  if (!bytes) return HF_OK;
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->hu_pending = false;
   return HF_OK;
 }
 
@@ -1123,7 +1140,7 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
   TRY(ensure_host(ctx, 4 * (size_t)B + 8, 4 * (size_t)B + 8, 8 * (size_t)B + 64));
   HIPCHK(hipMemsetAsync(ctx->xs, 0, N * sizeof(double), ctx->stream));
   HIPCHK(hipMemsetAsync(ctx->w_old, 0, s.nf * NQ * sizeof(double), ctx->stream));
-  HIPCHK(launch_set_rules(ctx->rules, ctx->stream));
+  TRY(upload(ctx, &ctx->d_rules, std::vector<RuleTables>{ctx->rules}));
   HIPCHK(launch_geometry(kparams(ctx), ctx->stream));
   TRY(sync(ctx));
   ctx->stage = 2;
@@ -1255,7 +1272,6 @@ extern "C" hf_status hf_get_state(hf_ctx *ctx, int32_t inst, double *u, double *
     HIPCHK(hipMemcpyAsync(p, pseg(ctx, ctx->xs, inst), h.n_p * sizeof(double), hipMemcpyDeviceToHost,
                           ctx->stream));
   if (w) {
-    HIPCHK(launch_set_rules(ctx->rules, ctx->stream));
     HIPCHK(launch_opening(kparams(ctx), ctx->xs, ctx->w_tmp, ctx->stream));
     HIPCHK(hipMemcpyAsync(w, ctx->w_tmp + ctx->foff[inst] * nq, h.nf * nq * sizeof(double),
                           hipMemcpyDeviceToHost, ctx->stream));
@@ -1286,7 +1302,6 @@ extern "C" hf_status hf_get_state_device(hf_ctx *ctx, int32_t inst, double *u, d
 static hf_status do_assemble(hf_ctx *ctx, std::vector<double> &rn) {
   const Sizes &s = ctx->s;
   KParams kp = kparams(ctx);
-  HIPCHK(launch_set_rules(ctx->rules, ctx->stream));  // the rule tables are module-global
   const bool incr = ctx->opt.incremental_assembly && ctx->lin_valid && ctx->lin_bstab == ctx->opt.b_stab;
   {
     ProfScope ps(ctx, P_ASM);
@@ -1830,6 +1845,12 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
   }
   TRY(get_i_async(ctx, ctx->flag, B, 0));
   TRY(sync(ctx));
+  // a block whose inverse failed was left unwritten: the next build must
+  // not reuse any kept inverse or fold (the current ones stay valid for
+  // the instances that did not fail)
+  bool inv_fail = false;
+  for (int b = 0; b < B; ++b) inv_fail = inv_fail || (ctx->hi[b] & 1);
+  if (inv_fail) ctx->inv64_epoch = ctx->inv32_epoch = ctx->f64_epoch = ctx->f32_epoch = -1;
   for (int b = 0; b < B; ++b) {
     if (!on[b] || !ctx->hi[b]) continue;
     st[b] = HF_ESINGULAR;
@@ -1855,9 +1876,16 @@ static hf_status ir_fp64_finish(hf_ctx *ctx, const std::vector<int> &fb, std::ve
   const KParams kp = kparams(ctx);
   KrylovDev &kd = ctx->kd;
   if (!ctx->have_m64) {
-    ProfScope ps(ctx, P_INV);
-    HIPCHK(launch_blockinv(kp, ctx->A, ctx->inv, nullptr, nullptr, s.ne, ctx->flag, ctx->stream));
-    ctx->inv64_epoch = ctx->lin_epoch;
+    {
+      ProfScope ps(ctx, P_INV);
+      HIPCHK(hipMemsetAsync(ctx->flag, 0, B * sizeof(int), ctx->stream));
+      HIPCHK(launch_blockinv(kp, ctx->A, ctx->inv, nullptr, nullptr, s.ne, ctx->flag, ctx->stream));
+    }
+    TRY(get_i_async(ctx, ctx->flag, B, 0));
+    TRY(sync(ctx));
+    bool bad = false;  // only instances that failed earlier can have singular blocks here
+    for (int b = 0; b < B; ++b) bad = bad || (ctx->hi[b] & 1);
+    ctx->inv64_epoch = bad ? -1 : ctx->lin_epoch;
     ctx->have_m64 = true;
   }
   Ops<double> op{ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->inv, ctx->Sinv};
@@ -2069,11 +2097,28 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
     for (int b = 0; b < B; ++b) anyfb = anyfb || fb[b];
     if (anyfb) TRY(ir_fp64_finish(ctx, fb, ls, st));
   }
+  // per-block true residuals of the solved instances: r = b - J dx once
+  // more (compensated FP64), its displacement and pressure parts
+  bool any_on = false;
+  for (int b = 0; b < B; ++b) any_on = any_on || on0[b];
+  if (any_on) {
+    TRY(put(ctx, kd.solving, on0));
+    Ops<double> op64{ctx->A, ctx->Bs, ctx->Cs, ctx->D, ctx->inv, ctx->Sinv};
+    TRY(residual<double>(ctx, kp, op64, ctx->rhs, ctx->dx, ctx->t64, ctx->r64, rows(ctx, 1)));
+    HIPCHK(launch_seg_norms_up(kd, ctx->r64, ctx->rhs, s.n_u, ctx->partial, ctx->red, stm));
+    TRY(get_d(ctx, ctx->red, 4 * B));
+  }
   TRY(sync(ctx));
   const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   for (int b = 0; b < B; ++b) {
     ls[b].seconds = sec;
     ls[b].status = on0[b] ? st[b] : HF_OK;
+    if (!on0[b]) continue;
+    const double ru = std::sqrt(ctx->hd[4 * b]), bu = std::sqrt(ctx->hd[4 * b + 1]);
+    const double rp = std::sqrt(ctx->hd[4 * b + 2]), bp = std::sqrt(ctx->hd[4 * b + 3]);
+    const double bn = std::sqrt(bu * bu + bp * bp);
+    ls[b].relres_u = bu > 0.0 ? ru / bu : (bn > 0.0 ? ru / bn : ru);
+    ls[b].relres_p = bp > 0.0 ? rp / bp : (bn > 0.0 ? rp / bn : rp);
   }
   return HF_OK;
 }
@@ -2190,6 +2235,8 @@ extern "C" hf_status hf_newton_solve(hf_ctx *ctx, hf_newton_stats *stats) {
       a.lin.restarts += one[b].lin.restarts;
       a.lin.fp64_iters += one[b].lin.fp64_iters;
       a.lin.true_relres = std::max(a.lin.true_relres, one[b].lin.true_relres);
+      a.lin.relres_u = std::max(a.lin.relres_u, one[b].lin.relres_u);
+      a.lin.relres_p = std::max(a.lin.relres_p, one[b].lin.relres_p);
       a.lin.seconds += one[b].lin.seconds;
       a.lin.status = one[b].lin.status;
       a.du_rel = one[b].du_rel;
@@ -2267,7 +2314,6 @@ extern "C" hf_status hf_initial_guess(hf_ctx *ctx, double *p0_out) {
     if (pred[b])
       HIPCHK(hipMemcpyAsync(useg(ctx, ctx->xs, b), useg(ctx, ctx->dx, b), ulen(ctx, b) * sizeof(double),
                             hipMemcpyDeviceToDevice, ctx->stream));
-  HIPCHK(launch_set_rules(ctx->rules, ctx->stream));
   HIPCHK(launch_fluid_volume(kparams(ctx), ctx->xs, nullptr, ctx->red, ctx->stream));
   TRY(get_d(ctx, ctx->red, B));
   for (int b = 0; b < B; ++b) {
@@ -2294,7 +2340,6 @@ extern "C" hf_status hf_initial_guess(hf_ctx *ctx, double *p0_out) {
 extern "C" hf_status hf_end_load_step(hf_ctx *ctx) {
   TRY(check_ctx(ctx, 3));
   HIPCHK(hipSetDevice(ctx->opt.device));
-  HIPCHK(launch_set_rules(ctx->rules, ctx->stream));
   HIPCHK(launch_opening(kparams(ctx), ctx->xs, ctx->w_old, ctx->stream));
   TRY(update_fluid_scale(ctx));
   TRY(sync(ctx));
@@ -2337,11 +2382,11 @@ extern "C" hf_status hf_get_block_rows(hf_ctx *ctx, int32_t inst, int64_t n_rows
       int64_t blk = -1;
       int32_t col = -1;
       if (slot == 0) {
-        HIPCHK(hipMemcpy(&blk, ctx->m.blk_ptr + e, sizeof(int64_t), hipMemcpyDeviceToHost));
+        TRY(d2h(ctx, &blk, ctx->m.blk_ptr + e, sizeof(int64_t)));
         col = el;
       } else if (h.nbr[(int64_t)el * NF + slot - 1] >= 0) {
         int32_t bi = 0;
-        HIPCHK(hipMemcpy(&bi, ctx->m.blk_of + e * NF + slot - 1, sizeof(int32_t), hipMemcpyDeviceToHost));
+        TRY(d2h(ctx, &bi, ctx->m.blk_of + e * NF + slot - 1, sizeof(int32_t)));
         blk = bi;
         col = h.nbr[(int64_t)el * NF + slot - 1];
       }
@@ -2351,7 +2396,7 @@ extern "C" hf_status hf_get_block_rows(hf_ctx *ctx, int32_t inst, int64_t n_rows
         std::fill(out, out + BU * BU, 0.0);
         continue;
       }
-      HIPCHK(hipMemcpy(buf.data(), ctx->A + blk * BU * BU, BU * BU * sizeof(double), hipMemcpyDeviceToHost));
+      TRY(d2h(ctx, buf.data(), ctx->A + blk * BU * BU, BU * BU * sizeof(double)));
       for (int c = 0; c < BU; ++c)
         for (int r = 0; r < BU; ++r) out[r * BU + c] = buf[c * BU + r];
     }
@@ -2368,15 +2413,14 @@ extern "C" hf_status hf_get_coupling(hf_ctx *ctx, int32_t inst, double *B, doubl
   const int64_t e0 = ctx->eoff[inst], e1 = ctx->eoff[inst + 1], p0 = ctx->poff[inst];
   TRY(sync(ctx));
   std::vector<int64_t> sp_ptr(s.ne + 1);
-  HIPCHK(hipMemcpy(sp_ptr.data(), ctx->m.sp_ptr, sp_ptr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  TRY(d2h(ctx, sp_ptr.data(), ctx->m.sp_ptr, sp_ptr.size() * sizeof(int64_t)));
   const int64_t k0 = sp_ptr[e0], k1 = sp_ptr[e1];
   std::vector<double> bs((k1 - k0) * BU), cs((k1 - k0) * BU);
   std::vector<int32_t> sp_pnode(k1 - k0);
   if (k1 > k0) {
-    HIPCHK(hipMemcpy(bs.data(), ctx->Bs + k0 * BU, bs.size() * sizeof(double), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(cs.data(), ctx->Cs + k0 * BU, cs.size() * sizeof(double), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(sp_pnode.data(), ctx->m.sp_pnode + k0, sp_pnode.size() * sizeof(int32_t),
-                     hipMemcpyDeviceToHost));
+    TRY(d2h(ctx, bs.data(), ctx->Bs + k0 * BU, bs.size() * sizeof(double)));
+    TRY(d2h(ctx, cs.data(), ctx->Cs + k0 * BU, cs.size() * sizeof(double)));
+    TRY(d2h(ctx, sp_pnode.data(), ctx->m.sp_pnode + k0, sp_pnode.size() * sizeof(int32_t)));
   }
   if (B) std::fill(B, B + nu * np, 0.0);
   if (C) std::fill(C, C + np * nu, 0.0);
@@ -2389,7 +2433,7 @@ extern "C" hf_status hf_get_coupling(hf_ctx *ctx, int32_t inst, double *B, doubl
       }
     }
   if (D && np)
-    HIPCHK(hipMemcpy(D, ctx->D + ctx->doff[inst], np * np * sizeof(double), hipMemcpyDeviceToHost));
+    TRY(d2h(ctx, D, ctx->D + ctx->doff[inst], np * np * sizeof(double)));
   return HF_OK;
 }
 
@@ -2685,11 +2729,11 @@ extern "C" hf_status hf_get_block_inverse(hf_ctx *ctx, int32_t inst, int64_t n_r
     const int64_t e = ctx->eoff[inst] + elems[i];
     double *o = out + i * BU * BU;
     if (precision == HF_FP64) {
-      HIPCHK(hipMemcpy(b64.data(), ctx->inv + e * BU * BU, BU * BU * sizeof(double), hipMemcpyDeviceToHost));
+      TRY(d2h(ctx, b64.data(), ctx->inv + e * BU * BU, BU * BU * sizeof(double)));
       for (int c = 0; c < BU; ++c)
         for (int r = 0; r < BU; ++r) o[r * BU + c] = b64[c * BU + r];
     } else {
-      HIPCHK(hipMemcpy(b32.data(), ctx->inv32 + e * BU * BU, BU * BU * sizeof(float), hipMemcpyDeviceToHost));
+      TRY(d2h(ctx, b32.data(), ctx->inv32 + e * BU * BU, BU * BU * sizeof(float)));
       for (int c = 0; c < BU; ++c)
         for (int r = 0; r < BU; ++r) o[r * BU + c] = b32[c * BU + r];
     }

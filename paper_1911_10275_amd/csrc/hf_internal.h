@@ -33,7 +33,9 @@ constexpr int kChunkRows = 1024;  // rows of a reduction chunk of the batched Kr
 constexpr int kMaxPressureBlock = 4096;  // pressure nodes per instance (dense pressure block)
 constexpr int kDenseWideMin = 192;       // pressure blocks from this size are inverted grid-wide
 
-// Rule tables, in the device constant bank (set per context before launch).
+// Rule tables of a context, in device memory owned by the context (each
+// context has its own copy, so contexts of different element types can run
+// concurrently on different streams).
 struct RuleTables {
   double fq_mu[kMaxNq][3];     // face barycentrics over the sorted face vertices
   double fq_w[kMaxNq];         // face weights, sum 1
@@ -119,6 +121,7 @@ struct KParams {
   const int32_t *poff;     // n_inst+1: first pressure node of each instance
   const int64_t *doff;     // n_inst+1: offset of each instance's dense pressure block
   const int32_t *aoff;     // n_inst+1: first active (fluid) face of each instance
+  const RuleTables *rt;    // quadrature rules of the context (device)
   int n_inst;
   double b_stab;
   int freeze_p;  // 1: pressure held fixed (fluid rows become p-rows of the identity)
@@ -215,10 +218,13 @@ hipError_t launch_precond(const KParams &kp, const T *inv, const T *Sinv, const 
                           const RowSel &sel, hipStream_t st);
 hipError_t launch_axpby(double a, const double *x, double b, double *y, int64_t n,
                         hipStream_t st);
-hipError_t launch_set_rules(const RuleTables &rt, hipStream_t st);
 // out[b] = ||x_b||^2 of every instance
 hipError_t launch_seg_norms(const KrylovDev &kd, const double *x, double *partial, double *out,
                             hipStream_t st);
+// out[4b + 0..3] = ||r_u||^2, ||b_u||^2, ||r_p||^2, ||b_p||^2 of instance b
+// (displacement and pressure rows of two context vectors)
+hipError_t launch_seg_norms_up(const KrylovDev &kd, const double *r, const double *b, int64_t n_u,
+                               double *partial, double *out, hipStream_t st);
 // x += dx on instances with upd[b] != 0 (p clamped to the cut-off when on);
 // out[4b + 0..3] = ||du||^2, ||u||^2, ||dp||^2, ||p||^2 of instance b
 hipError_t launch_snewton_update(const KrylovDev &kd, const double *dx, double *x, int64_t n_u,

@@ -14,12 +14,6 @@
 
 namespace hf {
 
-__constant__ RuleTables c_rules;
-
-hipError_t launch_set_rules(const RuleTables &rt, hipStream_t st) {
-  return hipMemcpyToSymbolAsync(HIP_SYMBOL(c_rules), &rt, sizeof(RuleTables), 0,
-                                hipMemcpyHostToDevice, st);
-}
 
 // ---------------------------------------------------------------------------
 // Lagrange P1/P2 on simplices in barycentric coordinates
@@ -283,7 +277,7 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const int32_t *__re
   for (int t = tid; t < NQV * NN; t += NT) {
     const int q = t / NN, a = t % NN;
     double lamq[DIM + 1], dph[DIM + 1];
-    for (int k = 0; k <= DIM; ++k) lamq[k] = c_rules.vq_lam[q][k];
+    for (int k = 0; k <= DIM; ++k) lamq[k] = kp.rt->vq_lam[q][k];
     Lag<DIM, ORDER>::dphi_one(a, lamq, dph);
     for (int x = 0; x < DIM; ++x) {
       double g = 0.0;
@@ -304,7 +298,7 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const int32_t *__re
     for (int x = 0; x < DIM; ++x)
       for (int y = 0; y < DIM; ++y) P[x][y] = 0.0;
     for (int q = 0; q < NQV; ++q) {
-      const double wq = c_rules.vq_w[q] * det;
+      const double wq = kp.rt->vq_w[q] * det;
       for (int x = 0; x < DIM; ++x)
         for (int y = 0; y < DIM; ++y) P[x][y] += wq * s_gphE[q][a][x] * s_gphE[q][b][y];
     }
@@ -327,7 +321,7 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const int32_t *__re
         const double sig = G * (s_gu[q][i][x] + s_gu[q][x][i]) + (i == x ? lam * tr : 0.0);
         sn += sig * s_gphE[q][a][x];
       }
-      acc += c_rules.vq_w[q] * det * sn;
+      acc += kp.rt->vq_w[q] * det * sn;
     }
     s_R[r] = acc;
   }
@@ -369,7 +363,7 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const int32_t *__re
       double lamq[DIM + 1];
       for (int k = 0; k <= DIM; ++k) lamq[k] = 0.0;
       const int *perm = side == 0 ? s_pe : s_pn;
-      for (int k = 0; k < DIM; ++k) lamq[perm[k]] = c_rules.fq_mu[q][k];
+      for (int k = 0; k < DIM; ++k) lamq[perm[k]] = kp.rt->fq_mu[q][k];
       double dph[DIM + 1];
       Lag<DIM, ORDER>::dphi_one(a, lamq, dph);
       const double ph = Lag<DIM, ORDER>::phi_one(a, lamq);
@@ -412,7 +406,7 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const int32_t *__re
       for (int s2 = 0; s2 < DIM - 1; ++s2) gp[s2] = 0.0;
       if (beta) {
         double mu_[DIM];
-        for (int k = 0; k < DIM; ++k) mu_[k] = c_rules.fq_mu[q][k];
+        for (int k = 0; k < DIM; ++k) mu_[k] = kp.rt->fq_mu[q][k];
         for (int k = 0; k < NNF; ++k) {
           const double pk = p[kp.m.face_pn[(int64_t)slot * NNF + k]];
           double dmu[DIM];
@@ -430,7 +424,7 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const int32_t *__re
         const double cj = G * jump[i] + (lam + G) * s_n[i] * w;
         s_tau[q][i] = (1.0 - al) * (sn + bh * cj) + al * T * s_n[i] - (beta ? ph_p * s_n[i] : 0.0);
       }
-      s_W[q] = c_rules.fq_w[q] * area;
+      s_W[q] = kp.rt->fq_w[q] * area;
       s_al[q] = al;
       s_dT[q] = dT;
       s_wq[q] = w;
@@ -442,7 +436,7 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const int32_t *__re
       for (int t = tid; t < NQF * NNF; t += NT) {
         const int q = t / NNF, k = t % NNF;
         double mu_[DIM], dmu[DIM];
-        for (int c2 = 0; c2 < DIM; ++c2) mu_[c2] = c_rules.fq_mu[q][c2];
+        for (int c2 = 0; c2 < DIM; ++c2) mu_[c2] = kp.rt->fq_mu[q][c2];
         Lag<DIM - 1, ORDER>::dphi_one(k, mu_, dmu);
         const double eta = Lag<DIM - 1, ORDER>::phi_one(k, mu_);
         const double wp = s_wq[q] > 0.0 ? s_wq[q] : 0.0;
@@ -600,8 +594,8 @@ __global__ __launch_bounds__(64) void k_fluid_rows(KParams kp, const double *__r
       double lm[DIM + 1], lp[DIM + 1];
       for (int k = 0; k <= DIM; ++k) lm[k] = lp[k] = 0.0;
       for (int k = 0; k < DIM; ++k) {
-        lm[kp.m.fperm_m[(int64_t)f * DIM + k]] = c_rules.fq_mu[q][k];
-        lp[kp.m.fperm_p[(int64_t)f * DIM + k]] = c_rules.fq_mu[q][k];
+        lm[kp.m.fperm_m[(int64_t)f * DIM + k]] = kp.rt->fq_mu[q][k];
+        lp[kp.m.fperm_p[(int64_t)f * DIM + k]] = kp.rt->fq_mu[q][k];
       }
       double w = 0.0;
       for (int x = 0; x < DIM; ++x) {
@@ -615,7 +609,7 @@ __global__ __launch_bounds__(64) void k_fluid_rows(KParams kp, const double *__r
       const double wp = w > 0.0 ? w : 0.0;
       const double K = wp * wp * wp / (12.0 * P.mu);
       double mu_[DIM];
-      for (int k = 0; k < DIM; ++k) mu_[k] = c_rules.fq_mu[q][k];
+      for (int k = 0; k < DIM; ++k) mu_[k] = kp.rt->fq_mu[q][k];
       double gp[DIM - 1];
       for (int s2 = 0; s2 < DIM - 1; ++s2) gp[s2] = 0.0;
       for (int k = 0; k < NNF; ++k) {
@@ -626,7 +620,7 @@ __global__ __launch_bounds__(64) void k_fluid_rows(KParams kp, const double *__r
       double dk[DIM];
       Lag<DIM - 1, ORDER>::dphi_one(kk, mu_, dk);
       const double etak = Lag<DIM - 1, ORDER>::phi_one(kk, mu_);
-      const double W = c_rules.fq_w[q] * area;
+      const double W = kp.rt->fq_w[q] * area;
       double gpg = 0.0;
       for (int s2 = 0; s2 < DIM - 1; ++s2)
         for (int t2 = 0; t2 < DIM - 1; ++t2) gpg += gp[s2] * gi[s2 * (DIM - 1) + t2] * (dk[t2 + 1] - dk[0]);
@@ -677,8 +671,8 @@ __global__ void k_opening(KParams kp, const double *__restrict__ u, double *__re
   double lm[DIM + 1], lp[DIM + 1];
   for (int k = 0; k <= DIM; ++k) lm[k] = lp[k] = 0.0;
   for (int k = 0; k < DIM; ++k) {
-    lm[kp.m.fperm_m[f * DIM + k]] = c_rules.fq_mu[q][k];
-    lp[kp.m.fperm_p[f * DIM + k]] = c_rules.fq_mu[q][k];
+    lm[kp.m.fperm_m[f * DIM + k]] = kp.rt->fq_mu[q][k];
+    lp[kp.m.fperm_p[f * DIM + k]] = kp.rt->fq_mu[q][k];
   }
   double phm[NN], php[NN];
   Lag<DIM, ORDER>::phi(lm, phm);
@@ -712,8 +706,8 @@ __global__ __launch_bounds__(256) void k_fluid_volume(KParams kp, const double *
     double lm[DIM + 1], lp[DIM + 1];
     for (int k = 0; k <= DIM; ++k) lm[k] = lp[k] = 0.0;
     for (int k = 0; k < DIM; ++k) {
-      lm[kp.m.fperm_m[f * DIM + k]] = c_rules.fq_mu[q][k];
-      lp[kp.m.fperm_p[f * DIM + k]] = c_rules.fq_mu[q][k];
+      lm[kp.m.fperm_m[f * DIM + k]] = kp.rt->fq_mu[q][k];
+      lp[kp.m.fperm_p[f * DIM + k]] = kp.rt->fq_mu[q][k];
     }
     double w = 0.0;
     for (int x = 0; x < DIM; ++x) {
@@ -724,7 +718,7 @@ __global__ __launch_bounds__(256) void k_fluid_volume(KParams kp, const double *
       }
       w += (up - um) * kp.m.normal[f * DIM + x];
     }
-    acc += c_rules.fq_w[q] * kp.m.area[f] * w;
+    acc += kp.rt->fq_w[q] * kp.m.area[f] * w;
   }
   sm[threadIdx.x] = acc;
   __syncthreads();

@@ -816,6 +816,44 @@ hipError_t launch_seg_norms(const KrylovDev &kd, const double *x, double *partia
   return ks_norms<double>(kd, x, partial, out, st);
 }
 
+// partial[c*4 + (0..3)] = chunk sums of r^2 and b^2 on displacement rows
+// (0, 1) and on pressure rows (2, 3); a chunk lies in one of the two parts
+__global__ __launch_bounds__(KT) void k_snorm_up(KrylovDev kd, const double *__restrict__ r,
+                                                 const double *__restrict__ bv, int64_t n_u,
+                                                 double *__restrict__ partial) {
+  __shared__ double wsum[2][KT / 64];
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int64_t row0 = kd.c_row0[c];
+  const int len = kd.c_len[c];
+  double a0 = 0.0, a1 = 0.0;
+  for (int rr = tid; rr < len; rr += KT) {
+    const double x = r[row0 + rr], y = bv[row0 + rr];
+    a0 += x * x;
+    a1 += y * y;
+  }
+  a0 = kwave_sum(a0);
+  a1 = kwave_sum(a1);
+  if (lane == 0) {
+    wsum[0][wv] = a0;
+    wsum[1][wv] = a1;
+  }
+  __syncthreads();
+  if (tid < 4) {
+    const bool isp = row0 >= n_u;
+    double s2 = 0.0;
+    if ((tid >= 2) == isp)
+      for (int q = 0; q < KT / 64; ++q) s2 += wsum[tid & 1][q];
+    partial[(int64_t)c * 4 + tid] = s2;
+  }
+}
+
+hipError_t launch_seg_norms_up(const KrylovDev &kd, const double *r, const double *b, int64_t n_u,
+                               double *partial, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_snorm_up, dim3(kd.n_chunks), dim3(KT), 0, st, kd, r, b, n_u, partial);
+  hipLaunchKernelGGL(k_seg_reduce, dim3(kd.n_inst, 4), dim3(KT), 0, st, kd, partial, 4, out);
+  return hipGetLastError();
+}
+
 __global__ void k_begin(KrylovDev kd, const double *__restrict__ n2) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= kd.n_inst) return;

@@ -12,8 +12,14 @@ namespace hf {
 // Batched inverse of the diagonal element blocks: Gauss-Jordan with partial
 // (row) pivoting, one wavefront per block, lane r holds row r in registers.
 // Pivot rows are chosen in place (no physical swap); the inverse is read out
-// with the column permutation the pivot order implies.
+// with the column permutation the pivot order implies.  A block is singular
+// to working precision when a pivot is not larger than kSingularRel times its
+// largest entry (the rounding residue of an exactly rank-deficient block,
+// such as the stiffness of an element held by no face and no boundary
+// condition, is a few units of 1e-16 of it), or when a pivot is not finite.
 // ---------------------------------------------------------------------------
+constexpr double kSingularRel = 1e-13;
+
 template <int BU>
 __global__ __launch_bounds__(64) void k_blockinv(const int32_t *__restrict__ elist,
                                                  const int64_t *__restrict__ blk_ptr,
@@ -31,6 +37,12 @@ __global__ __launch_bounds__(64) void k_blockinv(const int32_t *__restrict__ eli
   for (int c = 0; c < BU; ++c) a[c] = lane < BU ? blk[c * BU + lane] : 0.0;
   bool used = lane >= BU;
   int mystep = 0;
+  double amax = 0.0;
+#pragma unroll
+  for (int c = 0; c < BU; ++c) amax = fmax(amax, isnan(a[c]) ? INFINITY : fabs(a[c]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+  const double tiny = kSingularRel * amax;
 #pragma unroll
   for (int k = 0; k < BU; ++k) {
     // NaN ranks above every number so that it is picked and reported
@@ -47,7 +59,7 @@ __global__ __launch_bounds__(64) void k_blockinv(const int32_t *__restrict__ eli
     }
     const int p = idx;
     const double piv = __shfl(a[k], p, 64);
-    if (!(fabs(piv) > 0.0) || !isfinite(piv)) {
+    if (!(fabs(piv) > tiny) || !isfinite(piv) || !isfinite(amax)) {
       if (lane == 0) atomicOr(flag + einst[e], 1);
       return;
     }

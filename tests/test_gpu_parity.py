@@ -79,9 +79,41 @@ def test_assembly_parity(name, incremental):
     ctx.close()
 
 
+def _branch_state(case):
+    """The first seeded state (larger displacements than ``_random_state``)
+    whose cohesive points visit every branch of the traction law: state 1
+    in contact (w < 0), softening (0 <= w <= delta_c) and fully softened
+    (w > delta_c); state 2 in contact and open."""
+    m = case.mesh
+    st, dc = case.itf.qp_state, case.prm.delta_c
+    c1, c2 = st == 1, st == 2
+    for seed in range(2000):
+        rng = np.random.default_rng(seed)
+        u = rng.normal(size=m.n_u) * 0.25
+        w = newton.opening(m, u)
+        hit = [c1 & (w < 0), c1 & (w >= 0) & (w <= dc), c1 & (w > dc), c2 & (w < 0), c2 & (w >= 0)]
+        if all(np.any(h) for h in hit):
+            return u, rng.uniform(0.0, 2e-3, case.itf.n_p), rng.uniform(0.0, 1e-2, (m.nf, m.nq))
+    raise AssertionError("no seeded state visits every traction-law branch")
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("incremental", [0, 1], ids=["full", "incremental"])
+def test_assembly_parity_every_traction_branch(name, incremental):
+    """R and every block at a state whose cohesive points lie in every
+    branch of the traction law (checked on the oracle side first), after a
+    full assembly at another state so that the incremental path is used."""
+    prob = SMALL[name]()
+    case, ctx = _pair(prob)
+    ctx.set_options(incremental_assembly=incremental)
+    _check_assembly_at(case, ctx, 13)
+    _check_assembly_at(case, ctx, _branch_state(case))
+    ctx.close()
+
+
 def _check_assembly_at(case, ctx, seed):
     m = case.mesh
-    u, p, wo = _random_state(case, seed)
+    u, p, wo = _random_state(case, seed) if isinstance(seed, int) else seed
     ctx.set_state(u, p, wo)
     rn = ctx.assemble()
     s_p = newton.fluid_scale(case, wo)
@@ -437,4 +469,86 @@ def test_block_inverses_fp32_on_matrix_cores():
         assert err <= 50 * eps32 * kappa, (k, err, kappa)
         np.testing.assert_array_equal(out[0][k], inv64[k].astype(np.float32).astype(np.float64))
     assert not np.array_equal(out[1], out[0])
+    ctx.close()
+
+
+def _floating_pair():
+    """Two P1 triangles that share only a vertex: no interior face, no
+    clamped boundary, so each diagonal block is a bare element stiffness
+    with the three rigid-body modes in its kernel (singular by construction)."""
+    xyz = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0], [2.0, 0.0], [1.0, 1.0]])
+    elem = np.array([[0, 1, 2], [1, 3, 4]], np.int32)
+    return synth.Problem(2, 1, xyz, elem, np.zeros(5, np.uint8), np.zeros((0, 2), np.int32),
+                         np.zeros(0, np.uint8), np.zeros(0, np.uint8), np.zeros(0, np.int64),
+                         np.zeros(0), synth.Material(1.0, 0.25, 1e-3, 1e-4, 1e-3, 1.0), 1,
+                         "floating")
+
+
+@pytest.mark.parametrize("precision,mfma", [(hf.HF_FP64, 1), (hf.HF_FP32_IR, 0)],
+                         ids=["fp64", "fp32ir"])
+def test_singular_block_reports_esingular(precision, mfma):
+    """A batch of a regular KGD instance and an instance whose element blocks
+    are singular (forced from the host by the mesh itself): the solve
+    reports HF_ESINGULAR for the second instance only, its Newton step
+    keeps its state, and the first instance's increment equals its solo
+    run bit for bit."""
+    good = SMALL["2d_p1_n9"]()
+    bad = _floating_pair()
+    ctx = hf.context_for_problems([good, bad], precision=precision, mfma_inverse=mfma)
+    case = Case.from_problem(good)
+    st0 = newton.initial_state(case)
+    ub = np.random.default_rng(3).normal(size=bad.n_udof) * 1e-3
+    ctx.set_state(st0.u, st0.p, st0.w_old, inst=0)
+    ctx.set_state(ub, np.zeros(0), np.zeros((0, 2)), inst=1)
+    ctx.assemble()
+    with pytest.raises(hf.HFError) as ei:
+        ctx.solve()
+    assert ei.value.status == hf.HF_ESINGULAR
+    stats = ctx.solve(check=False)
+    assert stats[1].status == hf.HF_ESINGULAR
+    assert stats[0].status == hf.HF_OK and stats[0].true_relres <= 1e-10
+    du0, dp0 = ctx.increment(0)
+    ns = ctx.newton_step(check=False)
+    assert ns[1].status == hf.HF_ESINGULAR and ns[0].status == hf.HF_OK
+    np.testing.assert_array_equal(ctx.get_state(1)[0], ub)
+    ctx.close()
+    solo = hf.context_for_problem(good, precision=precision, mfma_inverse=mfma)
+    solo.set_state(st0.u, st0.p, st0.w_old)
+    solo.assemble()
+    s1 = solo.solve()
+    du1, dp1 = solo.increment()
+    solo.close()
+    assert s1.gmres_iters == stats[0].gmres_iters
+    np.testing.assert_array_equal(du0, du1)
+    np.testing.assert_array_equal(dp0, dp1)
+
+
+@pytest.mark.parametrize("name", ["2d_p1_n9", "3d_p2_n3"])
+@pytest.mark.parametrize("precision", [hf.HF_FP64, hf.HF_FP32_IR], ids=["fp64", "fp32ir"])
+def test_per_block_residuals(name, precision):
+    """relres_u and relres_p are the true residual of the solve split over
+    the displacement and pressure rows: recombined with the blocks of b they
+    give true_relres, and both agree with the oracle's J applied to the
+    increment (plain FP64 product, so to within its rounding)."""
+    prob = SMALL[name]()
+    case, ctx = _pair(prob)
+    ctx.set_options(precision=precision)
+    u, p, wo = _random_state(case, 21)
+    ctx.set_state(u, p, wo)
+    ctx.assemble()
+    st = ctx.solve()
+    ru, rp = ctx.residual()
+    bu, bp = np.linalg.norm(ru), np.linalg.norm(rp)
+    comb = np.hypot(st.relres_u * bu, st.relres_p * bp) / np.hypot(bu, bp)
+    assert comb == pytest.approx(st.true_relres, rel=1e-6)
+    du, dp = ctx.increment()
+    S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo),
+                     case.src_pnode, case.src_q0)
+    J = asm.full_matrix(case.mesh, S)
+    r = -S.R - J @ np.concatenate([du, dp])
+    n_u = case.mesh.n_u
+    scale = np.abs(J).max() * np.abs(np.concatenate([du, dp])).max() * 1e-14
+    assert abs(np.linalg.norm(r[:n_u]) - st.relres_u * bu) <= scale * np.sqrt(len(r))
+    assert abs(np.linalg.norm(r[n_u:]) - st.relres_p * bp) <= scale * np.sqrt(len(r))
+    assert st.true_relres <= 1e-10
     ctx.close()
