@@ -400,6 +400,17 @@ hf_status hf_apply_jacobian(hf_ctx *ctx, int precision, const void *x, void *y);
    applies M^-1 and then J.  HF_ESTATE when the last solve ran in the other
    precision or the system was re-assembled since. */
 hf_status hf_apply_preconditioned(hf_ctx *ctx, int precision, int folded, const void *x, void *y);
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the
+   folded form (folded = 1) of hf_apply_preconditioned, y = J M^-1 x on
+   device context vectors, enqueued on the ctx stream with no allocation
+   and no host synchronisation.  The S^-1 x_p staging vector lives in a
+   fixed 512 KiB device array that the library holds on each GPU until the
+   process ends; HF_EINVAL when the context has more than 65,536 pressure
+   unknowns.  Every call on a GPU shares that array (its contents are fully
+   rewritten before use): calls that overlap on one GPU, from contexts on
+   different streams, race.  HF_ESTATE as for hf_apply_preconditioned. */
+hf_status hf_apply_preconditioned_noalloc(hf_ctx *ctx, int precision, const void *x, void *y);
 hf_status hf_get_profile(hf_ctx *ctx, hf_profile *out);
 
 /* ---- tuning ---- */

@@ -34,7 +34,7 @@ EXPORTS = [
     "hf_newton_step", "hf_newton_solve", "hf_end_load_step", "hf_initial_guess", "hf_get_residual",
     "hf_get_block_rows", "hf_get_coupling", "hf_get_increment", "hf_apply_jacobian",
     "hf_get_profile", "hf_reset_profile", "hf_get_tuning", "hf_set_tuning", "hf_autotune",
-    "hf_get_block_inverse", "hf_apply_preconditioned",
+    "hf_get_block_inverse", "hf_apply_preconditioned", "hf_apply_preconditioned_noalloc",
 ]
 
 
@@ -152,6 +152,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hf_get_increment": (C.c_int, [vp, C.c_int32, vp, vp]),
         "hf_apply_jacobian": (C.c_int, [vp, C.c_int, vp, vp]),
         "hf_apply_preconditioned": (C.c_int, [vp, C.c_int, C.c_int, vp, vp]),
+        "hf_apply_preconditioned_noalloc": (C.c_int, [vp, C.c_int, vp, vp]),
         "hf_get_profile": (C.c_int, [vp, P(Profile)]),
         "hf_reset_profile": (C.c_int, [vp]),
         "hf_get_tuning": (C.c_int, [vp, P(Tuning)]),
@@ -411,6 +412,13 @@ class Context:
     def apply_preconditioned(self, x_ptr, y_ptr, precision=HF_FP64, folded=1):
         self._check(self.lib.hf_apply_preconditioned(self.h, precision, int(folded), C.c_void_p(x_ptr),
                                                      C.c_void_p(y_ptr)), "hf_apply_preconditioned")
+
+    def apply_preconditioned_noalloc(self, x_ptr, y_ptr, precision=HF_FP64):
+        """The folded y = J M^-1 x with the library's fixed scratch array
+        (no allocation, no synchronisation)."""
+        self._check(self.lib.hf_apply_preconditioned_noalloc(self.h, precision, C.c_void_p(x_ptr),
+                                                             C.c_void_p(y_ptr)),
+                    "hf_apply_preconditioned_noalloc")
 
     def profile(self) -> Profile:
         p = Profile()

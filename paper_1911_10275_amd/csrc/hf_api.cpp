@@ -83,6 +83,7 @@ struct hf_ctx {
   DevMesh m;
   RuleTables rules{};
   RuleTables *d_rules = nullptr;  // device copy read by the kernels
+  void *noalloc = nullptr;        // the device's fixed scratch array (allocation-free product)
   int freeze_p = 0;
   std::vector<void *> allocs;
   // per-instance offsets (host) and their device copies
@@ -469,6 +470,11 @@ extern "C" hf_status hf_create(const hf_options *opt, hf_ctx **out) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) { delete ctx; return HF_EDEVICE; }
   if (ctx->opt.device < 0 || ctx->opt.device >= ndev) { delete ctx; return HF_EINVAL; }
   if (hipSetDevice(ctx->opt.device) != hipSuccess) { delete ctx; return HF_EDEVICE; }
+  if (noalloc_scratch(ctx->opt.device, &ctx->noalloc) != hipSuccess) {
+    (void)hipGetLastError();
+    delete ctx;
+    return HF_EDEVICE;
+  }
   if (ctx->opt.stream) {
     ctx->stream = (hipStream_t)ctx->opt.stream;
   } else {
@@ -2494,6 +2500,30 @@ extern "C" hf_status hf_apply_preconditioned(hf_ctx *ctx, int precision, int fol
       op.tp = ctx->tp32;
     }
     TRY(apply_JM<float>(ctx, kp, op, (const float *)x, ctx->k32.z, (float *)y, RowSel{}));
+  } else {
+    return fail(ctx, HF_EINVAL, "precision");
+  }
+  return HF_OK;
+}
+
+// The folded product of hf_apply_preconditioned with its staging vector in
+// the device's fixed scratch array: no allocation, no host synchronisation.
+extern "C" hf_status hf_apply_preconditioned_noalloc(hf_ctx *ctx, int precision, const void *x, void *y) {
+  TRY(check_ctx(ctx, 4));
+  if (!x || !y) return fail(ctx, HF_EINVAL, "null vector");
+  if (ctx->s.n_p > kNoAllocScratchElems)
+    return fail(ctx, HF_EINVAL, "more than " + std::to_string(kNoAllocScratchElems) +
+                                    " pressure unknowns: beyond the fixed scratch array");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  const KParams kp = kparams(ctx);
+  if (precision == HF_FP64) {
+    if (!ctx->have_f64) return fail(ctx, HF_ESTATE, "no folded FP64 operator: run hf_solve in FP64 mode first");
+    HIPCHK(launch_spmv_folded<double>(kp, ctx->Af64, ctx->Bs, ctx->Cf64, ctx->D, ctx->Sinv, (const double *)x,
+                                      (double *)y, (double *)ctx->noalloc, RowSel{}, ctx->stream));
+  } else if (precision == HF_FP32_IR) {
+    if (!ctx->have_f32) return fail(ctx, HF_ESTATE, "no folded FP32 operator: run hf_solve in FP32-IR mode first");
+    HIPCHK(launch_spmv_folded<float>(kp, ctx->Af32, ctx->Bs32, ctx->Cf32, ctx->D32, ctx->Sinv32, (const float *)x,
+                                     (float *)y, (float *)ctx->noalloc, RowSel{}, ctx->stream));
   } else {
     return fail(ctx, HF_EINVAL, "precision");
   }

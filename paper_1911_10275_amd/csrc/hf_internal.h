@@ -32,6 +32,10 @@ constexpr int kMaxNqv = 8;     // volume points of 3D P2 (2 x 2 x 2)
 constexpr int kChunkRows = 1024;  // rows of a reduction chunk of the batched Krylov kernels
 constexpr int kMaxPressureBlock = 4096;  // pressure nodes per instance (dense pressure block)
 constexpr int kDenseWideMin = 192;       // pressure blocks from this size are inverted grid-wide
+// fixed device array of the allocation-free folded product (its S^-1 x_p
+// staging vector): 512 KiB per GPU, i.e. 65,536 pressure unknowns per context
+constexpr int64_t kNoAllocScratchBytes = 512 * 1024;
+constexpr int64_t kNoAllocScratchElems = kNoAllocScratchBytes / 8;
 
 // Rule tables of a context, in device memory owned by the context (each
 // context has its own copy, so contexts of different element types can run
@@ -204,6 +208,9 @@ hipError_t launch_spmv(const KParams &kp, const T *A, const T *Bs, const T *Cs, 
 template <typename T>
 hipError_t launch_spmv_folded(const KParams &kp, const T *Af, const T *Bs, const T *Cf, const T *D,
                               const T *Sinv, const T *x, T *y, T *tp, const RowSel &sel, hipStream_t st);
+// device address of the fixed scratch array on `device`, which must be the
+// current device; resolved once per device and kept
+hipError_t noalloc_scratch(int device, void **ptr);
 // y_e = sum_f A_ef x_f for the element rows with skip[e] == 0 (no strips,
 // no pressure rows; the other rows are left untouched)
 hipError_t launch_spmv_rows(const KParams &kp, const double *A, const double *x, double *y,

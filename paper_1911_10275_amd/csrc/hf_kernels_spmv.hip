@@ -11,6 +11,9 @@
 // The x values a row panel needs are staged in LDS first.
 #include <cmath>
 
+#include <mutex>
+#include <vector>
+
 #include "hf_internal.h"
 
 namespace hf {
@@ -522,5 +525,30 @@ template hipError_t launch_precond<double>(const KParams &, const double *, cons
                                            const double *, double *, const RowSel &, hipStream_t);
 template hipError_t launch_precond<float>(const KParams &, const float *, const float *,
                                           const float *, float *, const RowSel &, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free folded product: the S^-1 x_p staging vector
+// of launch_spmv_folded in a file-scope device array instead of a context
+// buffer.  Each GPU holds its own copy of the array; its address on a device
+// is looked up once (with that device current) and kept.  Every caller on a
+// GPU shares the array: calls that overlap on one GPU race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kNoAllocScratchElems];
+
+hipError_t noalloc_scratch(int device, void **ptr) {
+  static std::mutex mu;
+  static std::vector<void *> per_device;
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if ((int)per_device.size() <= device) per_device.resize(device + 1, nullptr);
+  if (!per_device[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    per_device[device] = p;
+  }
+  *ptr = per_device[device];
+  return hipSuccess;
+}
 
 }  // namespace hf
