@@ -139,6 +139,23 @@ typedef struct {
                           product time), so a GMRES iteration makes one
                           product instead of a preconditioner apply and a
                           product; 0: apply M^-1, then J (default 1) */
+  int two_level;       /* 1: two-level block preconditioner (needs
+                          fold_preconditioner = 1): the displacement block
+                          is approximated by a coarse correction on P1
+                          vertex functions (continuous across intact
+                          interfaces, split across cracked ones; the coarse
+                          matrix P^T A P factorised by multifrontal
+                          Gauss-Jordan on a nested-dissection tree) followed
+                          by the element blocks, and the pressure unknowns
+                          by the Schur block D - C Ah^-1 B of that
+                          approximation, combined as the full block
+                          factorisation of J; a build whose coarse factor
+                          meets a zero pivot falls back to block-Jacobi
+                          (hf_profile.n_tl_fail); 0: block-Jacobi
+                          (default 0) */
+  int coarse_leaf;     /* vertex classes per leaf of the nested-dissection
+                          tree, 4..4096 (default 64); fixed at the first
+                          two-level build of a context */
   void *stream;        /* hipStream_t to run on; NULL: a stream the ctx creates */
 } hf_options;
 
@@ -242,6 +259,9 @@ typedef struct {
   /* FP32-IR refinement steps that raised the true residual (each sends its
      instance to the FP64 solve at once) */
   int64_t n_ir_rise;
+  /* two-level preconditioner builds, and those whose coarse factor failed
+     (block-Jacobi used for that solve) */
+  int64_t n_tl_builds, n_tl_fail;
 } hf_profile;
 
 /* Fill *opt with the defaults listed above. */
@@ -394,11 +414,13 @@ hf_status hf_get_block_inverse(hf_ctx *ctx, int32_t inst, int64_t n_rows, const 
    last hf_solve in FP32-IR mode. */
 hf_status hf_apply_jacobian(hf_ctx *ctx, int precision, const void *x, void *y);
 /* y = J M^-1 x, the right-preconditioned operator of GMRES, on device context
-   vectors, with the block-Jacobi factors of the last hf_solve in that
-   precision: folded = 1 uses the folded blocks (built by that solve when
-   hf_options.fold_preconditioner = 1; HF_ESTATE otherwise), folded = 0
-   applies M^-1 and then J.  HF_ESTATE when the last solve ran in the other
-   precision or the system was re-assembled since. */
+   vectors, with the factors of the last hf_solve in that precision:
+   folded = 1 uses the block-Jacobi M folded into the blocks (built by that
+   solve when hf_options.fold_preconditioner = 1; HF_ESTATE otherwise),
+   folded = 0 applies the block-Jacobi M^-1 and then J, folded = 2 uses the
+   two-level block preconditioner of that solve (hf_options.two_level = 1;
+   HF_ESTATE when it was not built).  HF_ESTATE when the last solve ran in the
+   other precision or the system was re-assembled since. */
 hf_status hf_apply_preconditioned(hf_ctx *ctx, int precision, int folded, const void *x, void *y);
 /* For callers that cannot allocate device memory (code under HIP graph
    capture, tight serving loops, harnesses that forbid hipMalloc): the

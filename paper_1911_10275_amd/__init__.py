@@ -46,7 +46,8 @@ class Options(C.Structure):
                 ("profile", C.c_int), ("use_graphs", C.c_int), ("mfma_inverse", C.c_int),
                 ("ir_inner_cycles", C.c_int), ("ir_stall_steps", C.c_int),
                 ("incremental_assembly", C.c_int),
-                ("fold_preconditioner", C.c_int), ("stream", C.c_void_p)]
+                ("fold_preconditioner", C.c_int), ("two_level", C.c_int), ("coarse_leaf", C.c_int),
+                ("stream", C.c_void_p)]
 
 
 class Material(C.Structure):
@@ -91,7 +92,8 @@ class Profile(C.Structure):
                                           "n_precond", "n_ortho", "n_inv_mfma",
                                           "n_inv_fallback")] + \
                [("ms_resid", C.c_double), ("n_resid", C.c_int64), ("n_unfold", C.c_int64),
-                ("n_mgrow", C.c_int64), ("n_ir_rise", C.c_int64)]
+                ("n_mgrow", C.c_int64), ("n_ir_rise", C.c_int64), ("n_tl_builds", C.c_int64),
+                ("n_tl_fail", C.c_int64)]
 
 
 class HFError(RuntimeError):

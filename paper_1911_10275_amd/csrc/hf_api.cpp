@@ -64,6 +64,24 @@ struct KrylovWs {
   std::vector<hipGraphExec_t> graphs;  // captured iteration chunks, by first iteration / kIterChunk
 };
 
+// two-level product of precision T: the pieces it reads (set by the
+// preconditioner build) and its work vectors
+template <typename T>
+struct TlBuf {
+  const T *AP = nullptr, *W = nullptr, *F = nullptr, *Sinv2 = nullptr;
+  T *rc1 = nullptr, *rc2 = nullptr, *zc1 = nullptr, *zc2 = nullptr, *y = nullptr, *upd = nullptr;
+  T *q = nullptr, *zp = nullptr, *t = nullptr, *apz = nullptr;
+};
+
+// concatenated host layout kept after hf_finalize for the coarse-space plan
+struct HostLayout {
+  std::vector<double> xyz;
+  std::vector<int32_t> elem, face_em, face_ep, fperm_m, fperm_p, blk_col;
+  std::vector<uint32_t> clamp;
+  std::vector<uint8_t> qp_state, beta;
+  std::vector<int64_t> blk_ptr;
+};
+
 struct SolveOut {
   int iters = 0, restarts = 0;
   double relres = 0.0;
@@ -142,6 +160,23 @@ struct hf_ctx {
   bool lin_valid = false;
   double lin_bstab = 0.0;
   int64_t lin_epoch = 0, inv64_epoch = -1, inv32_epoch = -1, a32_epoch = -1;
+  // two-level preconditioner (hf_options.two_level)
+  HostLayout hl;
+  bool tl_planned = false;  // the coarse plan exists (or was refused: tl_refused)
+  bool tl_refused = false;
+  bool tl_ok = false;       // the last preconditioner build produced a usable coarse factor
+  int graphs_tl = -1;       // two-level state the captured GMRES chunks were recorded with
+  CoarsePlan cplan;
+  CoarseHostView chv;
+  CoarseK ck;
+  double *cAP = nullptr, *cW = nullptr, *cF = nullptr, *cCp = nullptr, *cDsc = nullptr;
+  double *cR = nullptr, *cZ = nullptr, *cY = nullptr, *cU = nullptr, *S2 = nullptr, *Sinv2 = nullptr;
+  float *cAP32 = nullptr, *cW32 = nullptr, *cF32 = nullptr, *Sinv2_32 = nullptr;
+  int *cflag = nullptr;
+  int c_nrhs = 0;
+  int64_t c_ap_total = 0, c_w_total = 0;
+  TlBuf<double> tb64;
+  TlBuf<float> tb32;
   std::vector<std::string> ierr;  // message of each instance's failure in the current call
   // profile
   std::vector<hipEvent_t> evpool;
@@ -443,6 +478,8 @@ extern "C" void hf_default_options(hf_options *o) {
   o->mfma_inverse = 1;
   o->incremental_assembly = 1;
   o->fold_preconditioner = 1;
+  o->two_level = 0;
+  o->coarse_leaf = 64;
   o->stream = nullptr;
 }
 
@@ -455,6 +492,8 @@ static hf_status validate_options(hf_ctx *ctx, const hf_options &o) {
   if (!(o.rtol > 0 && o.rtol < 1) || !(o.rtol_inner > 0 && o.rtol_inner < 1) || !(o.newton_tol > 0))
     return fail(ctx, HF_EINVAL, "tolerances must lie in (0, 1)");
   if (!(o.b_stab > 0)) return fail(ctx, HF_EINVAL, "b_stab must be positive");
+  if (o.two_level != 0 && o.two_level != 1) return fail(ctx, HF_EINVAL, "two_level must be 0 or 1");
+  if (o.coarse_leaf < 4 || o.coarse_leaf > 4096) return fail(ctx, HF_EINVAL, "coarse_leaf out of range 4..4096");
   return HF_OK;
 }
 
@@ -1149,6 +1188,20 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
   TRY(upload(ctx, &ctx->d_rules, std::vector<RuleTables>{ctx->rules}));
   HIPCHK(launch_geometry(kparams(ctx), ctx->stream));
   TRY(sync(ctx));
+  {
+    HostLayout &hl = ctx->hl;
+    hl.xyz = std::move(xyz);
+    hl.elem = std::move(elem);
+    hl.face_em = std::move(face_em);
+    hl.face_ep = std::move(face_ep);
+    hl.fperm_m = std::move(fperm_m);
+    hl.fperm_p = std::move(fperm_p);
+    hl.clamp = std::move(clamp);
+    hl.qp_state = std::move(qp_state);
+    hl.beta = std::move(beta);
+    hl.blk_ptr = std::move(blk_ptr);
+    hl.blk_col = std::move(blk_col);
+  }
   ctx->stage = 2;
   return HF_OK;
 }
@@ -1361,6 +1414,8 @@ struct Ops {
   // folded J M^-1 (null: apply M^-1, then J) and its S^-1 x_p staging vector
   const T *Af = nullptr, *Cf = nullptr;
   T *tp = nullptr;
+  // two-level block preconditioner (needs the folded blocks); null: block-Jacobi
+  const TlBuf<T> *tl = nullptr;
 };
 
 template <typename T>
@@ -1455,11 +1510,58 @@ static hf_status residual(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, cons
   return HF_OK;
 }
 
+// The two-level block preconditioner, first part (every row, all
+// instances): from v the pressure correction z_p, the second coarse
+// solution z_c2, t = v_u - B z_p - A P z_c2 and apz = A P z_c2
+// (see hf_kernels_coarse.hip for the factorisation it applies).
+template <typename T>
+static hf_status tl_first(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *v) {
+  const TlBuf<T> &b = *op.tl;
+  const CoarseK &ck = ctx->ck;
+  hipStream_t st = ctx->stream;
+  const int64_t n_u = ctx->s.n_u;
+  HIPCHK(coarse_restrict<T>(kp, ck, v, nullptr, nullptr, nullptr, b.rc1, st));
+  HIPCHK(coarse_solve1<T>(ck, ctx->chv, b.F, b.rc1, b.upd, b.y, b.zc1, st));
+  HIPCHK(coarse_q<T>(kp, ck, op.Cf, b.W, v, v + n_u, b.zc1, b.q, st));
+  HIPCHK(coarse_pgemv<T>(kp, b.Sinv2, b.q, b.zp, st));
+  HIPCHK(coarse_restrict<T>(kp, ck, nullptr, op.Bs, b.zp, b.rc1, b.rc2, st));
+  HIPCHK(coarse_solve1<T>(ck, ctx->chv, b.F, b.rc2, b.upd, b.y, b.zc2, st));
+  HIPCHK(coarse_t<T>(kp, ck, b.AP, op.Bs, v, b.zp, b.zc2, b.t, b.apz, st));
+  return HF_OK;
+}
+
+// z = M^-1 r with the two-level preconditioner: z_u = P z_c2 + M_A^-1 t,
+// z_p = z_p (every row)
+template <typename T>
+static hf_status tl_apply_M(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *r, T *z) {
+  ProfScope ps(ctx, P_PREC);
+  TRY(tl_first<T>(ctx, kp, op, r));
+  const TlBuf<T> &b = *op.tl;
+  HIPCHK(launch_precond<T>(kp, op.inv, op.Sinv, b.t, z, RowSel{}, ctx->stream));
+  HIPCHK(coarse_prolong_add<T>(kp, ctx->ck, b.zc2, z, ctx->stream));
+  if (ctx->s.n_p)
+    HIPCHK(hipMemcpyAsync(z + ctx->s.n_u, b.zp, ctx->s.n_p * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+  return HF_OK;
+}
+
+// w = J M^-1 v with the two-level preconditioner, from the folded blocks:
+// w_u = Af t + B z_p + A P z_c2, w_p = Cf t + D z_p + C P z_c2 (every row)
+template <typename T>
+static hf_status tl_apply_JM(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *v, T *w) {
+  ProfScope ps(ctx, sizeof(T) == 8 ? P_SPMV64 : P_SPMV32);
+  TRY(tl_first<T>(ctx, kp, op, v));
+  const TlBuf<T> &b = *op.tl;
+  HIPCHK(launch_spmv_folded_rows<T>(kp, op.Af, op.Bs, b.t, b.zp, b.apz, w, ctx->stream));
+  HIPCHK(coarse_prows<T>(kp, ctx->ck, op.Cf, op.Cs, op.D, b.t, b.zp, b.zc2, w + ctx->s.n_u, ctx->stream));
+  return HF_OK;
+}
+
 // w = J M^-1 v: one product with the folded blocks when they are built,
 // else the block-Jacobi apply into z followed by the Jacobian product
 template <typename T>
 static hf_status apply_JM(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *v, T *z, T *w,
                           const RowSel &sel) {
+  if (op.tl) return tl_apply_JM<T>(ctx, kp, op, v, w);
   if (!op.Af) {
     TRY(apply_M<T>(ctx, kp, op, v, z, sel));
     return apply_J<T>(ctx, kp, op, z, w, sel);
@@ -1639,7 +1741,10 @@ static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T
     // x += M^-1 V y with y = H^-1 g per instance
     HIPCHK(ks_solve_y(kd, m, ctx->k_y, ctx->k_est, st));
     HIPCHK(ks_combine<T>(kd, ws.V, N, ctx->k_y, m, ws.t, st));
-    TRY(apply_M<T>(ctx, kp, op, ws.t, ws.z, rows(ctx, 1)));
+    if (op.tl)
+      TRY(tl_apply_M<T>(ctx, kp, op, ws.t, ws.z));
+    else
+      TRY(apply_M<T>(ctx, kp, op, ws.t, ws.z, rows(ctx, 1)));
     HIPCHK((ks_axpy<T, T>(kd, nullptr, ws.z, x, st)));
     // true residual: restart vector and explicit check.  Without the check
     // (an inner solve) the residual is only needed by instances that go on
@@ -1731,6 +1836,259 @@ static hf_status gmres_b(hf_ctx *ctx, const Ops<T> &op, KrylovWs<T> &ws, const T
   return HF_OK;
 }
 
+// Coarse-space plan of the two-level preconditioner (host symbolic work,
+// once per context) and its device arrays.  Refused (the context keeps the
+// block-Jacobi preconditioner) when a front's own block does not fit the
+// forward solve's LDS staging.
+static hf_status tl_plan(hf_ctx *ctx) {
+  ctx->tl_planned = true;
+  const Sizes &s = ctx->s;
+  const HostLayout &hl = ctx->hl;
+  CoarseIn in;
+  in.dim = s.dim;
+  in.order = s.order;
+  in.nn = s.nn;
+  in.nq = s.nqf;
+  in.n_inst = nI(ctx);
+  in.leaf_max = ctx->opt.coarse_leaf;
+  in.ne = s.ne;
+  in.nf = s.nf;
+  in.xyz = hl.xyz.data();
+  in.elem = hl.elem.data();
+  in.clamp = hl.clamp.data();
+  in.face_em = hl.face_em.data();
+  in.face_ep = hl.face_ep.data();
+  in.fperm_m = hl.fperm_m.data();
+  in.fperm_p = hl.fperm_p.data();
+  in.qp_state = hl.qp_state.data();
+  in.beta = hl.beta.data();
+  in.blk_ptr = hl.blk_ptr.data();
+  in.blk_col = hl.blk_col.data();
+  in.eoff = ctx->eoff.data();
+  CoarsePlan &cp = ctx->cplan;
+  try {
+    build_coarse_plan(in, cp);
+  } catch (const std::exception &ex) {
+    return fail(ctx, HF_EINVAL, std::string("coarse plan: ") + ex.what());
+  }
+  const int dim = s.dim, nv = dim + 1;
+  CoarseHostView &hv = ctx->chv;
+  hv = CoarseHostView{};
+  hv.n_levels = cp.n_levels;
+  hv.level_ptr = cp.level_ptr;
+  hv.level_maxk = cp.level_maxk;
+  hv.level_maxf = cp.level_maxf;
+  hv.level_maxf_minus_k.assign(cp.n_levels, 0);
+  hv.level_maxchild_upd.assign(cp.n_levels, 0);
+  std::vector<int32_t> children(2 * (size_t)std::max(cp.n_nodes, 1), -1);
+  for (int x = 0; x < cp.n_nodes; ++x)
+    if (cp.parent[x] >= 0) children[2 * cp.parent[x] + cp.child_slot[x]] = x;
+  std::vector<int64_t> cpo(std::max(cp.n_nodes, 1), 0);
+  int64_t cp_size = 0, dsc_nodes = 1;
+  for (int l = 0; l < cp.n_levels; ++l) {
+    int64_t off = 0;
+    for (int32_t t = cp.level_ptr[l]; t < cp.level_ptr[l + 1]; ++t) {
+      const int x = cp.level_nodes[t];
+      cpo[x] = off;
+      off += (int64_t)cp.ff[x] * 32;
+      hv.level_maxf_minus_k[l] = std::max(hv.level_maxf_minus_k[l], cp.ff[x] - cp.fk[x]);
+      for (int sl = 0; sl < 2; ++sl) {
+        const int ch = children[2 * x + sl];
+        if (ch >= 0) {
+          const int64_t m = cp.ff[ch] - cp.fk[ch];
+          hv.level_maxchild_upd[l] = std::max(hv.level_maxchild_upd[l], m * m);
+        }
+      }
+    }
+    cp_size = std::max(cp_size, off);
+    dsc_nodes = std::max<int64_t>(dsc_nodes, cp.level_ptr[l + 1] - cp.level_ptr[l]);
+  }
+  int maxk = 0;
+  for (int l = 0; l < cp.n_levels; ++l) maxk = std::max(maxk, cp.level_maxk[l]);
+  if ((int64_t)maxk * 8 > 60 * 1024 || cp.ncls == 0) {
+    ctx->tl_refused = true;
+    return HF_OK;
+  }
+  // W rows: one per strip entry, over its element's A P columns
+  std::vector<int64_t> w_off(std::max<int64_t>(s.n_strip, 1), 0);
+  {
+    std::vector<int64_t> sp_ptr(s.ne + 1);
+    std::vector<int32_t> sp_elem(std::max<int64_t>(s.n_strip, 1));
+    TRY(d2h(ctx, sp_ptr.data(), ctx->m.sp_ptr, sp_ptr.size() * sizeof(int64_t)));
+    if (s.n_strip) TRY(d2h(ctx, sp_elem.data(), ctx->m.sp_elem, s.n_strip * sizeof(int32_t)));
+    int64_t o = 0;
+    for (int64_t k = 0; k < s.n_strip; ++k) {
+      const int64_t e = sp_elem[k];
+      w_off[k] = o;
+      o += (cp.ap_ptr[e + 1] - cp.ap_ptr[e]) * dim;
+    }
+    ctx->c_w_total = std::max<int64_t>(o, 1);
+  }
+  ctx->c_ap_total = cp.ap_ptr[s.ne] * dim * s.bu;
+  CoarseK &ck = ctx->ck;
+  ck = CoarseK{};
+  ck.dim = dim;
+  ck.nv = nv;
+  ck.nn = s.nn;
+  ck.ncls = cp.ncls;
+  ck.n_pairs = cp.n_pairs;
+  ck.front_total = cp.front_total;
+  for (int v = 0; v < nv; ++v) {
+    int nodes[4];
+    double w[4];
+    ck.nw[v] = vertex_node_weights(dim, s.order, v, nodes, w);
+    for (int q = 0; q < ck.nw[v]; ++q) {
+      ck.wn[v][q] = nodes[q];
+      ck.ww[v][q] = w[q];
+    }
+  }
+  int32_t *p32;
+  int64_t *p64;
+  TRY(upload(ctx, &p32, cp.cls_of)); ck.cls_of = p32;
+  TRY(upload(ctx, &p32, cp.cinst)); ck.cinst = p32;
+  TRY(upload(ctx, &p32, cp.rc_ptr)); ck.rc_ptr = p32;
+  TRY(upload(ctx, &p32, cp.rc_list)); ck.rc_list = p32;
+  TRY(upload(ctx, &p64, cp.ap_ptr)); ck.ap_ptr = p64;
+  TRY(upload(ctx, &p32, cp.ap_cls)); ck.ap_cls = p32;
+  TRY(upload(ctx, &p64, w_off)); ck.w_off = p64;
+  TRY(upload(ctx, &p64, cp.pair_cptr)); ck.pair_cptr = p64;
+  TRY(upload(ctx, &p64, cp.pair_dest)); ck.pair_dest = p64;
+  TRY(upload(ctx, &p32, cp.pc_e)); ck.pc_e = p32;
+  TRY(upload(ctx, &p32, cp.pc_vj)); ck.pc_vj = p32;
+  TRY(upload(ctx, &p32, cp.pair_ld)); ck.pair_ld = p32;
+  TRY(upload(ctx, &p32, cp.level_ptr)); ck.level_ptr = p32;
+  TRY(upload(ctx, &p32, cp.level_nodes)); ck.level_nodes = p32;
+  TRY(upload(ctx, &p32, children)); ck.children = p32;
+  TRY(upload(ctx, &p32, cp.fk)); ck.fk = p32;
+  TRY(upload(ctx, &p32, cp.ff)); ck.ff = p32;
+  TRY(upload(ctx, &p32, cp.fd_dof)); ck.fd_dof = p32;
+  TRY(upload(ctx, &p32, cp.ea_map)); ck.ea_map = p32;
+  TRY(upload(ctx, &p64, cp.fo)); ck.fo = p64;
+  TRY(upload(ctx, &p64, cp.uo)); ck.uo = p64;
+  TRY(upload(ctx, &p64, cp.fd_ptr)); ck.fd_ptr = p64;
+  TRY(upload(ctx, &p64, cp.src0)); ck.src0 = p64;
+  TRY(upload(ctx, &p64, cp.src1)); ck.src1 = p64;
+  TRY(upload(ctx, &p64, cp.ea_ptr)); ck.ea_ptr = p64;
+  TRY(upload(ctx, &p64, cpo)); ck.cpo = p64;
+  // numeric storage
+  const int64_t nc = (int64_t)cp.ncls * dim;
+  int nrhs = 1;
+  for (int b = 0; b < nI(ctx); ++b) nrhs = std::max<int>(nrhs, (int)ctx->inst[b].n_p);
+  ctx->c_nrhs = nrhs;
+  TRY(dalloc(ctx, &ctx->cAP, ctx->c_ap_total));
+  TRY(dalloc(ctx, &ctx->cW, ctx->c_w_total));
+  TRY(dalloc(ctx, &ctx->cF, std::max<int64_t>(cp.front_total, 1)));
+  TRY(dalloc(ctx, &ctx->cCp, std::max<int64_t>(cp_size, 1)));
+  TRY(dalloc(ctx, &ctx->cDsc, dsc_nodes * 32 * 32));
+  TRY(dalloc(ctx, &ctx->cflag, 1));
+  if (s.n_p) {
+    TRY(dalloc(ctx, &ctx->cR, nc * nrhs));
+    TRY(dalloc(ctx, &ctx->cZ, nc * nrhs));
+    TRY(dalloc(ctx, &ctx->cY, nc * nrhs));
+    TRY(dalloc(ctx, &ctx->cU, std::max<int64_t>(cp.upd_total, 1) * nrhs));
+  }
+  TRY(dalloc(ctx, &ctx->S2, ctx->doff[nI(ctx)]));
+  TRY(dalloc(ctx, &ctx->Sinv2, ctx->doff[nI(ctx)]));
+  TRY(dalloc(ctx, &ctx->Sinv2_32, ctx->doff[nI(ctx)]));
+  auto vecs = [&](auto &b) -> hf_status {
+    TRY(dalloc(ctx, &b.rc1, nc));
+    TRY(dalloc(ctx, &b.rc2, nc));
+    TRY(dalloc(ctx, &b.zc1, nc));
+    TRY(dalloc(ctx, &b.zc2, nc));
+    TRY(dalloc(ctx, &b.y, nc));
+    TRY(dalloc(ctx, &b.upd, std::max<int64_t>(cp.upd_total, 1)));
+    TRY(dalloc(ctx, &b.q, s.n_p));
+    TRY(dalloc(ctx, &b.zp, s.n_p));
+    TRY(dalloc(ctx, &b.t, s.N()));
+    TRY(dalloc(ctx, &b.apz, s.n_u));
+    HIPCHK(hipMemsetAsync(b.t, 0, s.N() * sizeof(*b.t), ctx->stream));
+    return HF_OK;
+  };
+  TRY(vecs(ctx->tb64));
+  ctx->tb64.AP = ctx->cAP;
+  ctx->tb64.W = ctx->cW;
+  ctx->tb64.F = ctx->cF;
+  ctx->tb64.Sinv2 = ctx->Sinv2;
+  if (ctx->opt.precision == HF_FP32_IR) {
+    TRY(vecs(ctx->tb32));
+    TRY(dalloc(ctx, &ctx->cAP32, ctx->c_ap_total));
+    TRY(dalloc(ctx, &ctx->cW32, ctx->c_w_total));
+    TRY(dalloc(ctx, &ctx->cF32, std::max<int64_t>(cp.front_total, 1)));
+    ctx->tb32.AP = ctx->cAP32;
+    ctx->tb32.W = ctx->cW32;
+    ctx->tb32.F = ctx->cF32;
+    ctx->tb32.Sinv2 = ctx->Sinv2_32;
+  }
+  TRY(sync(ctx));
+  return HF_OK;
+}
+
+// numeric two-level setup after the block-Jacobi factors: A P, W, the
+// coarse factor, Z_c = A_c^-1 P^T B and the corrected pressure block
+// S2 = S - W Z_c (S2 holds S on entry), inverted into Sinv2; FP32 copies for
+// GMRES-IR.  ctx->tl_ok tells whether the coarse factor is usable.
+static hf_status tl_build(hf_ctx *ctx, int n_wide) {
+  const Sizes &s = ctx->s;
+  const KParams kp = kparams(ctx);
+  const CoarseK &ck = ctx->ck;
+  hipStream_t st = ctx->stream;
+  const int B = nI(ctx);
+  if (ctx->opt.precision == HF_FP32_IR && !ctx->cAP32) {
+    auto vecs = [&](auto &b) -> hf_status {
+      const int64_t nc = (int64_t)ctx->cplan.ncls * s.dim;
+      TRY(dalloc(ctx, &b.rc1, nc));
+      TRY(dalloc(ctx, &b.rc2, nc));
+      TRY(dalloc(ctx, &b.zc1, nc));
+      TRY(dalloc(ctx, &b.zc2, nc));
+      TRY(dalloc(ctx, &b.y, nc));
+      TRY(dalloc(ctx, &b.upd, std::max<int64_t>(ctx->cplan.upd_total, 1)));
+      TRY(dalloc(ctx, &b.q, s.n_p));
+      TRY(dalloc(ctx, &b.zp, s.n_p));
+      TRY(dalloc(ctx, &b.t, s.N()));
+      TRY(dalloc(ctx, &b.apz, s.n_u));
+      HIPCHK(hipMemsetAsync(b.t, 0, s.N() * sizeof(*b.t), st));
+      return HF_OK;
+    };
+    TRY(vecs(ctx->tb32));
+    TRY(dalloc(ctx, &ctx->cAP32, ctx->c_ap_total));
+    TRY(dalloc(ctx, &ctx->cW32, ctx->c_w_total));
+    TRY(dalloc(ctx, &ctx->cF32, std::max<int64_t>(ctx->cplan.front_total, 1)));
+    ctx->tb32.AP = ctx->cAP32;
+    ctx->tb32.W = ctx->cW32;
+    ctx->tb32.F = ctx->cF32;
+    ctx->tb32.Sinv2 = ctx->Sinv2_32;
+    release_all_graphs(ctx);
+  }
+  HIPCHK(hipMemsetAsync(ctx->cflag, 0, sizeof(int), st));
+  HIPCHK(coarse_build_ap(kp, ck, ctx->A, nullptr, s.ne, ctx->cAP, st));
+  HIPCHK(coarse_build_w(kp, ck, ctx->Cs, ctx->inv, ctx->cAP, ctx->cW, st));
+  HIPCHK(coarse_factor(kp, ck, ctx->chv, ctx->cAP, ctx->cF, ctx->cCp, ctx->cDsc, ctx->cflag, st));
+  if (s.n_p) {
+    const int nrhs = ctx->c_nrhs;
+    HIPCHK(coarse_ptb(kp, ck, ctx->Bs, nrhs, ctx->cR, st));
+    HIPCHK(coarse_solve_multi(ck, ctx->chv, ctx->cF, ctx->cR, nrhs, ctx->cU, ctx->cY, ctx->cZ, st));
+    HIPCHK(coarse_s_correct(kp, ck, ctx->cW, ctx->cZ, nrhs, ctx->S2, st));
+    HIPCHK(launch_schur_invert(kp, ctx->S2, ctx->Sinv2, ctx->Sinv2_32, ctx->flag, n_wide, st));
+    for (int b = 0; b < B; ++b) {
+      const int nb = ctx->poff[b + 1] - ctx->poff[b];
+      if (nb < n_wide) continue;
+      HIPCHK(launch_dense_inv_wide(ctx->S2 + ctx->doff[b], ctx->Sinv2 + ctx->doff[b], ctx->Sinv2_32 + ctx->doff[b],
+                                   nb, ctx->flag + b, ctx->gj_colk, ctx->gj_perm, ctx->gj_piv, st));
+    }
+  }
+  if (ctx->opt.precision == HF_FP32_IR) {
+    HIPCHK(launch_convert(ctx->cAP, ctx->cAP32, ctx->c_ap_total, st));
+    HIPCHK(launch_convert(ctx->cW, ctx->cW32, ctx->c_w_total, st));
+    HIPCHK(launch_convert(ctx->cF, ctx->cF32, ctx->cplan.front_total, st));
+  }
+  TRY(get_i_async(ctx, ctx->cflag, 1, 0));
+  TRY(sync(ctx));
+  ctx->tl_ok = ctx->hi[0] == 0;
+  if (!ctx->tl_ok) ctx->prof.n_tl_fail += 1;
+  ctx->prof.n_tl_builds += 1;
+  return HF_OK;
+}
+
 // block-Jacobi factors of every instance; instances with a singular block
 // are reported in st and dropped from on
 static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::vector<hf_status> &st) {
@@ -1793,8 +2151,14 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
     part32 = ir && part;
   }
   const int n_wide = ctx->tune.dense_wide_min > 0 ? ctx->tune.dense_wide_min : kDenseWideMin;
-  HIPCHK(launch_schur(kp, ctx->inv, ctx->Bs, ctx->Cs, ctx->D, nullptr, ctx->T, ctx->S, ctx->Sinv,
-                      ctx->Sinv32, ctx->flag, n_wide, ctx->stream));
+  // two-level preconditioner: needs the folded blocks (and its plan)
+  const bool want_tl = ctx->opt.two_level && ctx->opt.fold_preconditioner;
+  if (want_tl && !ctx->tl_planned) TRY(tl_plan(ctx));
+  const bool tl = want_tl && !ctx->tl_refused;
+  HIPCHK(launch_schur_form(kp, ctx->inv, ctx->Bs, ctx->Cs, ctx->D, ctx->T, ctx->S, ctx->stream));
+  if (tl && s.n_p)
+    HIPCHK(hipMemcpyAsync(ctx->S2, ctx->S, ctx->doff[B] * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(launch_schur_invert(kp, ctx->S, ctx->Sinv, ctx->Sinv32, ctx->flag, n_wide, ctx->stream));
   for (int b = 0; b < B; ++b) {
     const int nb = ctx->poff[b + 1] - ctx->poff[b];
     if (nb < n_wide) continue;
@@ -1849,6 +2213,8 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
       ctx->have_f64 = true;
     }
   }
+  ctx->tl_ok = false;
+  if (tl) TRY(tl_build(ctx, n_wide));
   TRY(get_i_async(ctx, ctx->flag, B, 0));
   TRY(sync(ctx));
   // a block whose inverse failed was left unwritten: the next build must
@@ -1912,6 +2278,7 @@ static hf_status ir_fp64_finish(hf_ctx *ctx, const std::vector<int> &fb, std::ve
     op.Af = ctx->Af64;
     op.Cf = ctx->Cf64;
     op.tp = ctx->tp64;
+    if (ctx->tl_ok) op.tl = &ctx->tb64;
   }
   TRY(ensure_ws<double>(ctx, ctx->k64));
   // dx = 0 and r = b on the rows of these instances
@@ -1921,7 +2288,8 @@ static hf_status ir_fp64_finish(hf_ctx *ctx, const std::vector<int> &fb, std::ve
   std::vector<double> tol(B, ctx->opt.rtol);
   std::vector<int> cap(B, ctx->opt.gmres_maxit);
   std::vector<SolveOut> out;
-  TRY(gmres_b<double>(ctx, op, ctx->k64, ctx->r64, ctx->t64, tol, true, fb, cap, out, op.Af ? &seq : nullptr));
+  TRY(gmres_b<double>(ctx, op, ctx->k64, ctx->r64, ctx->t64, tol, true, fb, cap, out,
+                      (op.Af && !op.tl) ? &seq : nullptr));
   std::vector<double> one(B, 0.0);
   for (int b = 0; b < B; ++b) {
     if (!fb[b]) continue;
@@ -1952,6 +2320,10 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
   ls.assign(B, hf_solve_stats{});
   const std::vector<int> on0 = on;
   TRY(build_preconditioner(ctx, on, st));
+  if (ctx->graphs_tl != (ctx->tl_ok ? 1 : 0)) {  // the captured chunks hold the other operator
+    release_all_graphs(ctx);
+    ctx->graphs_tl = ctx->tl_ok ? 1 : 0;
+  }
   HIPCHK(launch_axpby(-1.0, ctx->R, 0.0, ctx->rhs, N, stm));  // b = -R
   if (ctx->opt.precision == HF_FP64) {
     TRY(ensure_ws<double>(ctx, ctx->k64));
@@ -1961,10 +2333,11 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
       op.Af = ctx->Af64;
       op.Cf = ctx->Cf64;
       op.tp = ctx->tp64;
+      if (ctx->tl_ok) op.tl = &ctx->tb64;
     }
     std::vector<SolveOut> out;
     TRY(gmres_b<double>(ctx, op, ctx->k64, ctx->rhs, ctx->dx, std::vector<double>(B, ctx->opt.rtol), true, on,
-                        std::vector<int>(B, ctx->opt.gmres_maxit), out, op.Af ? &seq : nullptr));
+                        std::vector<int>(B, ctx->opt.gmres_maxit), out, (op.Af && !op.tl) ? &seq : nullptr));
     for (int b = 0; b < B; ++b) {
       if (!on[b]) continue;
       ls[b].gmres_iters = out[b].iters;
@@ -1980,6 +2353,7 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
       op32.Af = ctx->Af32;
       op32.Cf = ctx->Cf32;
       op32.tp = ctx->tp32;
+      if (ctx->tl_ok) op32.tl = &ctx->tb32;
     }
     TRY(put(ctx, kd.solving, on));
     HIPCHK(ks_zero<double>(kd, ctx->dx, 1, stm));
@@ -2478,6 +2852,9 @@ extern "C" hf_status hf_apply_preconditioned(hf_ctx *ctx, int precision, int fol
   TRY(check_ctx(ctx, 4));
   if (!x || !y) return fail(ctx, HF_EINVAL, "null vector");
   const KParams kp = kparams(ctx);
+  if (folded < 0 || folded > 2) return fail(ctx, HF_EINVAL, "folded must be 0, 1 or 2");
+  if (folded == 2 && !ctx->tl_ok)
+    return fail(ctx, HF_ESTATE, "no two-level preconditioner: run hf_solve with two_level = 1 first");
   if (precision == HF_FP64) {
     if (!ctx->have_m64) return fail(ctx, HF_ESTATE, "no FP64 block-Jacobi factors: run hf_solve in FP64 mode first");
     if (!ctx->have_f64 && folded) return fail(ctx, HF_ESTATE, "no folded FP64 operator: run hf_solve in FP64 mode first");
@@ -2487,6 +2864,7 @@ extern "C" hf_status hf_apply_preconditioned(hf_ctx *ctx, int precision, int fol
       op.Af = ctx->Af64;
       op.Cf = ctx->Cf64;
       op.tp = ctx->tp64;
+      if (folded == 2) op.tl = &ctx->tb64;
     }
     TRY(apply_JM<double>(ctx, kp, op, (const double *)x, ctx->k64.z, (double *)y, RowSel{}));
   } else if (precision == HF_FP32_IR) {
@@ -2498,6 +2876,7 @@ extern "C" hf_status hf_apply_preconditioned(hf_ctx *ctx, int precision, int fol
       op.Af = ctx->Af32;
       op.Cf = ctx->Cf32;
       op.tp = ctx->tp32;
+      if (folded == 2) op.tl = &ctx->tb32;
     }
     TRY(apply_JM<float>(ctx, kp, op, (const float *)x, ctx->k32.z, (float *)y, RowSel{}));
   } else {

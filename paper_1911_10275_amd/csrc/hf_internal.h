@@ -152,6 +152,113 @@ struct RowSel {
   int mode = 0;
 };
 
+// ---------------------------------------------------------------------------
+// Two-level preconditioner: host structure (hf_coarse.cpp)
+// ---------------------------------------------------------------------------
+struct CoarseIn {  // the concatenated layout of a finalized context
+  int dim = 0, order = 0, nn = 0, nq = 0, n_inst = 0, leaf_max = 64;
+  int64_t ne = 0, nf = 0;
+  const double *xyz = nullptr;
+  const int32_t *elem = nullptr;
+  const uint32_t *clamp = nullptr;
+  const int32_t *face_em = nullptr, *face_ep = nullptr, *fperm_m = nullptr, *fperm_p = nullptr;
+  const uint8_t *qp_state = nullptr, *beta = nullptr;
+  const int64_t *blk_ptr = nullptr;
+  const int32_t *blk_col = nullptr;
+  const int64_t *eoff = nullptr;  // n_inst+1
+};
+
+struct CoarsePlan {
+  int dim = 0, nv = 0, max_ap = 0;
+  int32_t ncls = 0;
+  std::vector<int32_t> cls_of;         // ne*nv: class of each vertex copy, or -1
+  std::vector<double> xyz;             // ncls*dim
+  std::vector<int32_t> cinst, coff;    // instance of each class; class offsets per instance
+  std::vector<int32_t> rc_ptr, rc_list;  // copies (e*nv + v) of each class
+  std::vector<int64_t> ap_ptr;         // ne+1: column classes of each element row of A P
+  std::vector<int32_t> ap_cls;
+  int64_t n_pairs = 0;                 // class pairs of A_c
+  std::vector<int64_t> pair_cptr;      // npair+1: contributions (e, v | j << 8) of each pair
+  std::vector<int32_t> pc_e, pc_vj;
+  std::vector<int64_t> pair_dest;      // front offset of the pair's dim x dim block
+  std::vector<int32_t> pair_ld;        // leading dimension of that front
+  int n_nodes = 0, n_levels = 0;
+  std::vector<int32_t> level_ptr, level_nodes, level_maxk, level_maxf;
+  std::vector<int32_t> fk, ff;         // own and front size (DOFs) per node
+  std::vector<int64_t> fo, uo;         // front storage offset; update-row offset
+  std::vector<int64_t> fd_ptr;         // nodes+1: front positions (DOFs)
+  std::vector<int32_t> fd_dof;         // global coarse DOF of each front position
+  std::vector<int64_t> src0, src1;     // update rows of the children landing at each position
+  std::vector<int64_t> ea_ptr;         // nodes+1: extend-add map of each node into its parent
+  std::vector<int32_t> ea_map;         // (class level) parent front position of each struct class
+  std::vector<int32_t> parent, child_slot;
+  int64_t front_total = 0, upd_total = 0;
+  double factor_flops = 0.0;
+};
+void build_coarse_plan(const CoarseIn &in, CoarsePlan &cp);
+
+// device view of the plan (kernel argument, by value)
+struct CoarseK {
+  int dim = 0, nv = 0, nn = 0;
+  int32_t ncls = 0;
+  int64_t n_pairs = 0, front_total = 0;
+  int nw[4] = {0, 0, 0, 0};  // P1 weights of the element nodes per local vertex
+  int wn[4][4] = {};
+  double ww[4][4] = {};
+  const int32_t *cls_of = nullptr, *cinst = nullptr, *rc_ptr = nullptr, *rc_list = nullptr;
+  const int64_t *ap_ptr = nullptr;
+  const int32_t *ap_cls = nullptr;
+  const int64_t *w_off = nullptr;  // per strip entry: offset of its W row
+  const int64_t *pair_cptr = nullptr, *pair_dest = nullptr;
+  const int32_t *pc_e = nullptr, *pc_vj = nullptr, *pair_ld = nullptr;
+  const int32_t *level_ptr = nullptr, *level_nodes = nullptr, *children = nullptr;
+  const int32_t *fk = nullptr, *ff = nullptr, *fd_dof = nullptr, *ea_map = nullptr;
+  const int64_t *fo = nullptr, *uo = nullptr, *fd_ptr = nullptr, *src0 = nullptr, *src1 = nullptr, *ea_ptr = nullptr;
+  const int64_t *cpo = nullptr;  // per node: offset of its Gauss-Jordan column-panel scratch
+};
+// per-level sizes the launchers need on the host
+struct CoarseHostView {
+  int n_levels = 0;
+  std::vector<int32_t> level_ptr, level_maxk, level_maxf, level_maxf_minus_k;
+  std::vector<int64_t> level_maxchild_upd;
+};
+
+hipError_t coarse_build_ap(const KParams &kp, const CoarseK &ck, const double *A, const int32_t *elist, int64_t n,
+                           double *AP, hipStream_t st);
+hipError_t coarse_build_w(const KParams &kp, const CoarseK &ck, const double *Cs, const double *inv,
+                          const double *AP, double *W, hipStream_t st);
+// fronts <- A_c entries, extend-add and Gauss-Jordan level by level;
+// flag != 0 on a zero or non-finite pivot
+hipError_t coarse_factor(const KParams &kp, const CoarseK &ck, const CoarseHostView &hv, const double *AP,
+                         double *F, double *Cp, double *Dsc, int *flag, hipStream_t st);
+hipError_t coarse_ptb(const KParams &kp, const CoarseK &ck, const double *Bs, int nrhs, double *R, hipStream_t st);
+hipError_t coarse_solve_multi(const CoarseK &ck, const CoarseHostView &hv, const double *F, const double *b,
+                              int nrhs, double *upd, double *y, double *xs, hipStream_t st);
+hipError_t coarse_s_correct(const KParams &kp, const CoarseK &ck, const double *W, const double *Z, int nrhs,
+                            double *S, hipStream_t st);
+template <typename T>
+hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const T *F, const T *b, T *upd, T *y, T *xs,
+                         hipStream_t st);
+template <typename T>
+hipError_t coarse_restrict(const KParams &kp, const CoarseK &ck, const T *v, const T *Bs, const T *zp,
+                           const T *base, T *rc, hipStream_t st);
+template <typename T>
+hipError_t coarse_q(const KParams &kp, const CoarseK &ck, const T *Cf, const T *W, const T *vu, const T *vp,
+                    const T *zc, T *qout, hipStream_t st);
+template <typename T>
+hipError_t coarse_t(const KParams &kp, const CoarseK &ck, const T *AP, const T *Bs, const T *vu, const T *zp,
+                    const T *zc, T *t, T *apz, hipStream_t st);
+template <typename T>
+hipError_t coarse_prows(const KParams &kp, const CoarseK &ck, const T *Cf, const T *Cs, const T *D, const T *tu,
+                        const T *zp, const T *zc, T *wp, hipStream_t st);
+template <typename T>
+hipError_t coarse_prolong_add(const KParams &kp, const CoarseK &ck, const T *zc, T *zu, hipStream_t st);
+// y_p = S x_p with the dense per-instance pressure blocks S (one wave per row)
+template <typename T>
+hipError_t coarse_pgemv(const KParams &kp, const T *S, const T *x, T *y, hipStream_t st);
+// nodes with a non-zero P1 weight for local vertex v and the weights
+int vertex_node_weights(int dim, int order, int v, int *nodes, double *w);
+
 }  // namespace hf
 
 namespace hf {
@@ -193,6 +300,13 @@ hipError_t launch_fold(const KParams &kp, const double *A, const double *Cs, con
 hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,
                         const double *Cs, const double *D, double *Z, double *T, double *S,
                         double *Sinv, float *Sinv32, int *flag, int n_wide, hipStream_t st);
+// S = D - C M_A^-1 B only (no inversion)
+hipError_t launch_schur_form(const KParams &kp, const double *inv, const double *Bs, const double *Cs,
+                             const double *D, double *T, double *S, hipStream_t st);
+// in-place inversion of the pressure blocks of S into Sinv / Sinv32 (the
+// blocks with n_wide <= n are left to launch_dense_inv_wide)
+hipError_t launch_schur_invert(const KParams &kp, double *S, double *Sinv, float *Sinv32, int *flag, int n_wide,
+                               hipStream_t st);
 // inverse of one n x n block W (row-major, in place) into out / out32, one
 // pivot step per two launches over the whole GPU; scratch colk (n), perm (n),
 // piv (1); flag |= 2 on a zero or non-finite pivot
@@ -211,6 +325,11 @@ hipError_t launch_spmv_folded(const KParams &kp, const T *Af, const T *Bs, const
 // device address of the fixed scratch array on `device`, which must be the
 // current device; resolved once per device and kept
 hipError_t noalloc_scratch(int device, void **ptr);
+// element rows of the folded product with the pressure staging given:
+// y_u = Af x_u + B tp + add (add nullable)
+template <typename T>
+hipError_t launch_spmv_folded_rows(const KParams &kp, const T *Af, const T *Bs, const T *x, const T *tp,
+                                   const T *add, T *y, hipStream_t st);
 // y_e = sum_f A_ef x_f for the element rows with skip[e] == 0 (no strips,
 // no pressure rows; the other rows are left untouched)
 hipError_t launch_spmv_rows(const KParams &kp, const double *A, const double *x, double *y,

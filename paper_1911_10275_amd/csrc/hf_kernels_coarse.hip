@@ -1,0 +1,777 @@
+// Two-level block preconditioner for gfx950: coarse space of P1 vertex
+// classes (see hf_coarse.cpp), multifrontal Gauss-Jordan factorisation of
+// the coarse matrix, and the kernels of one preconditioned product.
+//
+// Preconditioner (full block factorisation of J = [[A, B], [C, D]]):
+//   A^-1 ~ Ah^-1 r = P z_c + M_A^-1 (r - A P z_c),  z_c = A_c^-1 P^T r,
+//   A_c = P^T A P (the coarse matrix), M_A the element blocks,
+//   S = D - C Ah^-1 B = (D - C M_A^-1 B) - W Z_c,  W = C P - (C M_A^-1) (A P),
+//   Z_c = A_c^-1 P^T B;
+//   z_p = S^-1 (v_p - C Ah^-1 v_u),  z_u = Ah^-1 (v_u - B z_p).
+// The product w = J z the Krylov solver needs is formed without z:
+//   q = C Ah^-1 v_u = Cf v_u + W z_c1,  z_c1 = A_c^-1 P^T v_u,
+//   z_p = S^-1 (v_p - q),
+//   z_c2 = A_c^-1 (P^T v_u - P^T B z_p),
+//   t = v_u - B z_p - A P z_c2,
+//   w_u = Af t + B z_p + A P z_c2,  w_p = Cf t + D z_p + C P z_c2,
+// with Af = A M_A^-1 and Cf = C M_A^-1 the folded blocks.
+//
+// Front layout: row-major f x f; the first k rows / columns are the node's
+// own DOFs.  After the elimination a front holds
+//   [[F11^-1, F11^-1 F12], [-F21 F11^-1, F22 - F21 F11^-1 F12]].
+#include <algorithm>
+#include <cmath>
+
+#include "hf_internal.h"
+
+namespace hf {
+
+constexpr int kCT = 256;   // threads of the row-parallel kernels
+constexpr int kNB = 32;    // Gauss-Jordan panel width
+constexpr int kTile = 64;  // tile of the Gauss-Jordan update
+
+__device__ inline bool clamped(const uint32_t *clamp, int64_t e, int r) { return (clamp[e] >> r) & 1u; }
+
+// ---------------------------------------------------------------------------
+// A P panels: AP_e (bu x ncol*dim, column-major) = sum over the blocks of
+// row e of A_ef P_f.  One workgroup per element row, one thread per entry.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kCT) void k_ap_build(KParams kp, CoarseK ck, const double *__restrict__ A,
+                                                  const int32_t *__restrict__ elist, double *__restrict__ AP) {
+  const int64_t e = elist ? elist[blockIdx.x] : blockIdx.x;
+  const int bu = kp.s.bu, dim = ck.dim, nv = ck.nv;
+  const int64_t c0 = ck.ap_ptr[e];
+  const int ncol = (int)(ck.ap_ptr[e + 1] - c0);
+  const int64_t b0 = kp.m.blk_ptr[e], b1 = kp.m.blk_ptr[e + 1];
+  double *out = AP + c0 * dim * bu;
+  for (int t = threadIdx.x; t < ncol * dim * bu; t += kCT) {
+    const int r = t % bu, col = t / bu, j = col / dim, k = col % dim;
+    const int32_t cls = ck.ap_cls[c0 + j];
+    double acc = 0.0;
+    for (int64_t b = b0; b < b1; ++b) {
+      const int64_t f = kp.m.blk_col[b];
+      const double *Ab = A + b * bu * bu;
+      for (int v = 0; v < nv; ++v) {
+        if (ck.cls_of[f * nv + v] != cls) continue;
+        for (int q = 0; q < ck.nw[v]; ++q) {
+          const int a = ck.wn[v][q];
+          if (clamped(kp.m.clamp, f, a * dim + k)) continue;
+          acc += ck.ww[v][q] * Ab[(int64_t)(a * dim + k) * bu + r];
+        }
+      }
+    }
+    out[t] = acc;
+  }
+}
+
+// W rows per strip entry: W_ent = C_ent P_e - (C_ent M_e^-1) AP_e over the
+// AP columns of the entry's element (one workgroup per strip entry)
+__global__ __launch_bounds__(kCT) void k_w_build(KParams kp, CoarseK ck, const double *__restrict__ Cs,
+                                                 const double *__restrict__ inv, const double *__restrict__ AP,
+                                                 double *__restrict__ W) {
+  const int64_t ent = blockIdx.x;
+  const int bu = kp.s.bu, dim = ck.dim, nv = ck.nv;
+  const int64_t e = kp.m.sp_elem[ent];
+  const int64_t c0 = ck.ap_ptr[e];
+  const int ncol = (int)(ck.ap_ptr[e + 1] - c0);
+  __shared__ double cf[32];
+  const double *Ce = Cs + ent * bu;
+  const double *ie = inv + e * bu * bu;
+  for (int r = threadIdx.x; r < bu; r += kCT) {
+    double acc = 0.0;
+    for (int s = 0; s < bu; ++s) acc += Ce[s] * ie[(int64_t)r * bu + s];
+    cf[r] = acc;
+  }
+  __syncthreads();
+  const double *ap = AP + c0 * dim * bu;
+  double *out = W + ck.w_off[ent];
+  for (int col = threadIdx.x; col < ncol * dim; col += kCT) {
+    const int j = col / dim, k = col % dim;
+    const int32_t cls = ck.ap_cls[c0 + j];
+    double acc = 0.0;
+    for (int v = 0; v < nv; ++v) {
+      if (ck.cls_of[e * nv + v] != cls) continue;
+      for (int q = 0; q < ck.nw[v]; ++q) {
+        const int a = ck.wn[v][q];
+        if (!clamped(kp.m.clamp, e, a * dim + k)) acc += ck.ww[v][q] * Ce[a * dim + k];
+      }
+    }
+    for (int r = 0; r < bu; ++r) acc -= cf[r] * ap[(int64_t)col * bu + r];
+    out[col] = acc;
+  }
+}
+
+// coarse matrix entries into the fronts: thread per (pair, i, k)
+__global__ __launch_bounds__(kCT) void k_pairs(KParams kp, CoarseK ck, const double *__restrict__ AP,
+                                               double *__restrict__ F) {
+  const int dim = ck.dim, d2 = dim * dim, bu = kp.s.bu, nv = ck.nv;
+  const int64_t t = blockIdx.x * (int64_t)kCT + threadIdx.x;
+  if (t >= ck.n_pairs * d2) return;
+  const int64_t p = t / d2;
+  const int i = (int)(t % d2) / dim, k = (int)(t % d2) % dim;
+  double acc = 0.0;
+  for (int64_t c = ck.pair_cptr[p]; c < ck.pair_cptr[p + 1]; ++c) {
+    const int64_t e = ck.pc_e[c];
+    const int v = ck.pc_vj[c] & 255, j = ck.pc_vj[c] >> 8;
+    const double *ap = AP + ck.ap_ptr[e] * dim * bu + (int64_t)(j * dim + k) * bu;
+    for (int q = 0; q < ck.nw[v]; ++q) {
+      const int a = ck.wn[v][q];
+      if (!clamped(kp.m.clamp, e, a * dim + i)) acc += ck.ww[v][q] * ap[a * dim + i];
+    }
+  }
+  (void)nv;
+  F[ck.pair_dest[p] + (int64_t)i * ck.pair_ld[p] + k] = acc;
+}
+
+__global__ void k_cfill(double *__restrict__ x, int64_t n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    x[t] = 0.0;
+}
+
+// extend-add of the update blocks of the children in one slot into the
+// fronts of the parents at level lev (grid: entry tiles x parents)
+__global__ __launch_bounds__(kCT) void k_extend_add(CoarseK ck, int lev, int slot, double *__restrict__ F) {
+  const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
+  const int ch = ck.children[2 * x + slot];
+  if (ch < 0) return;
+  const int dim = ck.dim;
+  const int fc = ck.ff[ch], kc = ck.fk[ch], m = fc - kc;
+  const int fp = ck.ff[x];
+  const int64_t n = (int64_t)m * m;
+  const int32_t *map = ck.ea_map + ck.ea_ptr[ch];
+  const double *src = F + ck.fo[ch];
+  double *dst = F + ck.fo[x];
+  for (int64_t t = blockIdx.x * (int64_t)kCT + threadIdx.x; t < n; t += (int64_t)gridDim.x * kCT) {
+    const int a = (int)(t / m), b = (int)(t % m);
+    const int pa = map[a / dim] * dim + a % dim, pb = map[b / dim] * dim + b % dim;
+    dst[(int64_t)pa * fp + pb] += src[(int64_t)(kc + a) * fc + kc + b];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Multifrontal Gauss-Jordan, one panel of kNB pivots [p0, p0 + nb) of every
+// front at a level whose k exceeds p0.
+// Kernel A: invert the panel's diagonal block D (in LDS, no pivoting: the
+// coarse matrix is a stiffness), scale the row panel F[K, j] <- D^-1 F[K, j]
+// (j outside K), keep a copy of the column panel and D^-1 for kernel B.
+// ---------------------------------------------------------------------------
+__device__ bool panel_inverse(const double *F, int f, int p0, int nb, double (*D)[kNB + 1]) {
+  for (int t = threadIdx.x; t < nb * nb; t += kCT) D[t / nb][t % nb] = F[(int64_t)(p0 + t / nb) * f + p0 + t % nb];
+  __syncthreads();
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    const double pv = D[k][k];
+    const bool ok = fabs(pv) > 0.0 && isfinite(pv);
+    if (!ok) {
+      if (threadIdx.x == 0) bad = 1;
+      __syncthreads();
+      return false;
+    }
+    const double pinv = 1.0 / pv;
+    __syncthreads();
+    if ((int)threadIdx.x < nb) D[k][threadIdx.x] = (int)threadIdx.x == k ? pinv : D[k][threadIdx.x] * pinv;
+    __syncthreads();
+    double fk[(kNB * kNB + kCT - 1) / kCT];
+    int cnt = 0;
+    for (int t = threadIdx.x; t < nb * nb; t += kCT) fk[cnt++] = D[t / nb][k];
+    __syncthreads();
+    cnt = 0;
+    for (int t = threadIdx.x; t < nb * nb; t += kCT) {
+      const int r = t / nb, c = t % nb;
+      const double fr = fk[cnt++];
+      if (r != k) D[r][c] = c == k ? -fr * pinv : D[r][c] - fr * D[k][c];
+    }
+    __syncthreads();
+  }
+  return bad == 0;
+}
+
+__global__ __launch_bounds__(kCT) void k_gj_a(CoarseK ck, int lev, int p0, double *__restrict__ F,
+                                              double *__restrict__ Cp, double *__restrict__ Dsc, int *flag) {
+  const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
+  const int k = ck.fk[x], f = ck.ff[x];
+  if (p0 >= k) return;
+  const int nb = min(kNB, k - p0);
+  const int tile = blockIdx.x;
+  if (tile * kTile >= f) return;
+  double *Fx = F + ck.fo[x];
+  __shared__ double D[kNB][kNB + 1];
+  if (!panel_inverse(Fx, f, p0, nb, D)) {
+    if (threadIdx.x == 0) atomicOr(flag, 1);
+    return;
+  }
+  // rows [tile*64, +64) of the column panel, before kernel B changes it
+  double *cp = Cp + ck.cpo[x];
+  for (int t = threadIdx.x; t < kTile * nb; t += kCT) {
+    const int r = tile * kTile + t / nb, c = t % nb;
+    if (r < f) cp[(int64_t)r * kNB + c] = Fx[(int64_t)r * f + p0 + c];
+  }
+  if (tile == 0)
+    for (int t = threadIdx.x; t < nb * nb; t += kCT) Dsc[(int64_t)blockIdx.y * kNB * kNB + t] = D[t / nb][t % nb];
+  // columns [tile*64, +64) of the row panel: F[K, j] <- D^-1 F[K, j]
+  __shared__ double R[kNB][kTile];
+  for (int t = threadIdx.x; t < nb * kTile; t += kCT) {
+    const int r = t / kTile, c = tile * kTile + t % kTile;
+    R[r][t % kTile] = c < f ? Fx[(int64_t)(p0 + r) * f + c] : 0.0;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nb * kTile; t += kCT) {
+    const int r = t / kTile, cl = t % kTile, c = tile * kTile + cl;
+    if (c >= f || (c >= p0 && c < p0 + nb)) continue;
+    double acc = 0.0;
+    for (int s = 0; s < nb; ++s) acc += D[r][s] * R[s][cl];
+    Fx[(int64_t)(p0 + r) * f + c] = acc;
+  }
+}
+
+// Kernel B: F[i, j] -= Cp[i, :] F[K, j] outside the panel rows and columns,
+// F[i, K] = -Cp[i, :] D^-1 outside the panel rows, F[K, K] = D^-1
+__global__ __launch_bounds__(kCT) void k_gj_b(CoarseK ck, int lev, int p0, double *__restrict__ F,
+                                              const double *__restrict__ Cp, const double *__restrict__ Dsc,
+                                              const int *flag) {
+  if (*flag) return;
+  const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
+  const int k = ck.fk[x], f = ck.ff[x];
+  if (p0 >= k) return;
+  const int nb = min(kNB, k - p0);
+  const int nt = (f + kTile - 1) / kTile;
+  const int ti = blockIdx.x / nt, tj = blockIdx.x % nt;
+  if (ti >= nt) return;
+  double *Fx = F + ck.fo[x];
+  const double *cp = Cp + ck.cpo[x];
+  const double *Dn = Dsc + (int64_t)blockIdx.y * kNB * kNB;
+  __shared__ double Ct[kTile][kNB + 1];
+  __shared__ double Rt[kNB][kTile + 1];
+  __shared__ double Dt[kNB][kNB + 1];
+  const int i0 = ti * kTile, j0 = tj * kTile;
+  for (int t = threadIdx.x; t < kTile * kNB; t += kCT) {
+    const int r = t / kNB, c = t % kNB;
+    Ct[r][c] = (i0 + r < f && c < nb) ? cp[(int64_t)(i0 + r) * kNB + c] : 0.0;
+  }
+  for (int t = threadIdx.x; t < kNB * kTile; t += kCT) {
+    const int r = t / kTile, c = t % kTile;
+    Rt[r][c] = (r < nb && j0 + c < f) ? Fx[(int64_t)(p0 + r) * f + j0 + c] : 0.0;
+  }
+  for (int t = threadIdx.x; t < kNB * kNB; t += kCT) {
+    const int r = t / kNB, c = t % kNB;
+    Dt[r][c] = (r < nb && c < nb) ? Dn[r * nb + c] : 0.0;
+  }
+  __syncthreads();
+  // 4 x 4 entries per thread
+  const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int il = tr * 4 + a, i = i0 + il;
+    if (i >= f) continue;
+    const bool iK = i >= p0 && i < p0 + nb;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int jl = tc + 16 * b, j = j0 + jl;
+      if (j >= f) continue;
+      const bool jK = j >= p0 && j < p0 + nb;
+      if (iK && !jK) continue;  // the row panel, done by kernel A
+      double *dst = Fx + (int64_t)i * f + j;
+      if (iK && jK) {
+        *dst = Dt[i - p0][j - p0];
+      } else if (jK) {
+        double acc = 0.0;
+        for (int s = 0; s < nb; ++s) acc += Ct[il][s] * Dt[s][j - p0];
+        *dst = -acc;
+      } else {
+        double acc = 0.0;
+        for (int s = 0; s < nb; ++s) acc += Ct[il][s] * Rt[s][jl];
+        *dst -= acc;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense P^T B (coarse rows x the pressure columns of each instance,
+// row-major with nrhs columns): thread per (class, component)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kCT) void k_ptb(KParams kp, CoarseK ck, const double *__restrict__ Bs, int nrhs,
+                                             double *__restrict__ R) {
+  const int dim = ck.dim, nv = ck.nv, bu = kp.s.bu;
+  const int64_t t = blockIdx.x * (int64_t)kCT + threadIdx.x;
+  if (t >= (int64_t)ck.ncls * dim) return;
+  const int32_t c = (int32_t)(t / dim);
+  const int i = (int)(t % dim);
+  double *row = R + t * nrhs;
+  for (int j = 0; j < nrhs; ++j) row[j] = 0.0;
+  const int b = ck.cinst[c];
+  const int32_t p0 = kp.poff[b];
+  for (int32_t q = ck.rc_ptr[c]; q < ck.rc_ptr[c + 1]; ++q) {
+    const int64_t e = ck.rc_list[q] / nv;
+    const int v = ck.rc_list[q] % nv;
+    for (int64_t s = kp.m.sp_ptr[e]; s < kp.m.sp_ptr[e + 1]; ++s) {
+      double acc = 0.0;
+      for (int w = 0; w < ck.nw[v]; ++w) {
+        const int a = ck.wn[v][w];
+        if (!clamped(kp.m.clamp, e, a * dim + i)) acc += ck.ww[v][w] * Bs[s * bu + a * dim + i];
+      }
+      row[kp.m.sp_pnode[s] - p0] += acc;
+    }
+  }
+}
+
+// S_b[i][j] -= sum over i's strip entries of W_ent . Z_c[:, j] (the pressure
+// block of each instance; Z_c row-major with nrhs columns)
+__global__ __launch_bounds__(kCT) void k_s_correct(KParams kp, CoarseK ck, const double *__restrict__ W,
+                                                   const double *__restrict__ Z, int nrhs, double *__restrict__ S) {
+  const int64_t i = blockIdx.y;
+  const int b = kp.pinst[i];
+  const int64_t p0 = kp.poff[b], nb = kp.poff[b + 1] - p0;
+  const int64_t j = blockIdx.x * (int64_t)kCT + threadIdx.x;
+  if (j >= nb) return;
+  const int dim = ck.dim;
+  double acc = 0.0;
+  for (int32_t c = kp.m.pc_ptr[i]; c < kp.m.pc_ptr[i + 1]; ++c) {
+    const int32_t ent = kp.m.pc_ent[c];
+    const int64_t e = kp.m.sp_elem[ent];
+    const int64_t c0 = ck.ap_ptr[e];
+    const int ncol = (int)(ck.ap_ptr[e + 1] - c0);
+    const double *w = W + ck.w_off[ent];
+    for (int col = 0; col < ncol * dim; ++col)
+      acc += w[col] * Z[((int64_t)ck.ap_cls[c0 + col / dim] * dim + col % dim) * nrhs + j];
+  }
+  S[kp.doff[b] + (i - p0) * nb + j] -= acc;
+}
+
+// ---------------------------------------------------------------------------
+// Coarse solves.  Forward, level by level from the leaves: the node's own
+// right-hand side v = b_own + the children's update rows at its own
+// positions is kept in y; the update rows of its struct positions are
+// u = (children's rows there) + (-F21 F11^-1) v.  Backward, from the root:
+// x_own = F11^-1 v - (F11^-1 F12) x_struct.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline T own_rhs(const CoarseK &ck, int64_t pos, const T *b, const T *upd, int nrhs, int j) {
+  T v = b[(int64_t)ck.fd_dof[pos] * nrhs + j];
+  if (ck.src0[pos] >= 0) v += upd[ck.src0[pos] * nrhs + j];
+  if (ck.src1[pos] >= 0) v += upd[ck.src1[pos] * nrhs + j];
+  return v;
+}
+
+// one right-hand side: each workgroup keeps the node's own right-hand side
+// in LDS and computes kCT/64 rows (one wavefront per row)
+template <typename T>
+__global__ __launch_bounds__(kCT) void k_fwd1(CoarseK ck, int lev, const T *__restrict__ Fm, const T *__restrict__ b,
+                                              T *__restrict__ upd, T *__restrict__ y) {
+  extern __shared__ unsigned char smem_raw[];
+  T *vo = reinterpret_cast<T *>(smem_raw);
+  const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
+  const int k = ck.fk[x], f = ck.ff[x];
+  const int rows_per = kCT / 64;
+  const int r0 = blockIdx.x * rows_per;
+  if (r0 >= f) return;
+  const int64_t fd = ck.fd_ptr[x];
+  for (int c = threadIdx.x; c < k; c += kCT) vo[c] = own_rhs<T>(ck, fd + c, b, upd, 1, 0);
+  __syncthreads();
+  const int lane = threadIdx.x % 64, r = r0 + threadIdx.x / 64;
+  if (r >= f) return;
+  if (r < k) {
+    if (lane == 0) y[ck.fd_dof[fd + r]] = vo[r];
+    return;
+  }
+  const T *row = Fm + ck.fo[x] + (int64_t)r * f;
+  double acc = 0.0;
+  for (int c = lane; c < k; c += 64) acc += (double)row[c] * (double)vo[c];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) {
+    double v = acc;
+    const int64_t pos = fd + r;
+    if (ck.src0[pos] >= 0) v += (double)upd[ck.src0[pos]];
+    if (ck.src1[pos] >= 0) v += (double)upd[ck.src1[pos]];
+    upd[ck.uo[x] + r - k] = (T)v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCT) void k_bwd1(CoarseK ck, int lev, const T *__restrict__ Fm, const T *__restrict__ y,
+                                              T *__restrict__ xs) {
+  const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
+  const int k = ck.fk[x], f = ck.ff[x];
+  const int rows_per = kCT / 64;
+  const int lane = threadIdx.x % 64, r = blockIdx.x * rows_per + threadIdx.x / 64;
+  if (r >= k) return;
+  const int64_t fd = ck.fd_ptr[x];
+  const T *row = Fm + ck.fo[x] + (int64_t)r * f;
+  double acc = 0.0;
+  for (int c = lane; c < k; c += 64) acc += (double)row[c] * (double)y[ck.fd_dof[fd + c]];
+  for (int c = k + lane; c < f; c += 64) acc -= (double)row[c] * (double)xs[ck.fd_dof[fd + c]];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) xs[ck.fd_dof[fd + r]] = (T)acc;
+}
+
+// several right-hand sides (row-major, nrhs columns): own rows first, then
+// the struct rows, a thread per (row, column)
+__global__ __launch_bounds__(kCT) void k_fwdm_own(CoarseK ck, int lev, const double *__restrict__ b,
+                                                  const double *__restrict__ upd, int nrhs, double *__restrict__ y) {
+  const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
+  const int k = ck.fk[x];
+  const int64_t t = blockIdx.x * (int64_t)kCT + threadIdx.x;
+  if (t >= (int64_t)k * nrhs) return;
+  const int r = (int)(t / nrhs), j = (int)(t % nrhs);
+  const int64_t pos = ck.fd_ptr[x] + r;
+  y[(int64_t)ck.fd_dof[pos] * nrhs + j] = own_rhs<double>(ck, pos, b, upd, nrhs, j);
+}
+
+__global__ __launch_bounds__(kCT) void k_fwdm_upd(CoarseK ck, int lev, const double *__restrict__ Fm,
+                                                  const double *__restrict__ y, int nrhs, double *upd) {
+  const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
+  const int k = ck.fk[x], f = ck.ff[x];
+  const int64_t t = blockIdx.x * (int64_t)kCT + threadIdx.x;
+  if (t >= (int64_t)(f - k) * nrhs) return;
+  const int r = k + (int)(t / nrhs), j = (int)(t % nrhs);
+  const int64_t fd = ck.fd_ptr[x], pos = fd + r;
+  const double *row = Fm + ck.fo[x] + (int64_t)r * f;
+  double acc = 0.0;
+  for (int c = 0; c < k; ++c) acc += row[c] * y[(int64_t)ck.fd_dof[fd + c] * nrhs + j];
+  if (ck.src0[pos] >= 0) acc += upd[ck.src0[pos] * nrhs + j];
+  if (ck.src1[pos] >= 0) acc += upd[ck.src1[pos] * nrhs + j];
+  // the children's rows read here belong to lower levels (earlier launches)
+  upd[(ck.uo[x] + r - k) * nrhs + j] = acc;
+}
+
+__global__ __launch_bounds__(kCT) void k_bwdm(CoarseK ck, int lev, const double *__restrict__ Fm,
+                                              const double *__restrict__ y, int nrhs, double *__restrict__ xs) {
+  const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
+  const int k = ck.fk[x], f = ck.ff[x];
+  const int64_t t = blockIdx.x * (int64_t)kCT + threadIdx.x;
+  if (t >= (int64_t)k * nrhs) return;
+  const int r = (int)(t / nrhs), j = (int)(t % nrhs);
+  const int64_t fd = ck.fd_ptr[x];
+  const double *row = Fm + ck.fo[x] + (int64_t)r * f;
+  double acc = 0.0;
+  for (int c = 0; c < k; ++c) acc += row[c] * y[(int64_t)ck.fd_dof[fd + c] * nrhs + j];
+  for (int c = k; c < f; ++c) acc -= row[c] * xs[(int64_t)ck.fd_dof[fd + c] * nrhs + j];
+  xs[(int64_t)ck.fd_dof[fd + r] * nrhs + j] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels of one preconditioned product (precision T)
+// ---------------------------------------------------------------------------
+// rc = P^T v_u (minus P^T B z_p when zp != null): thread per (class, component)
+template <typename T>
+__global__ __launch_bounds__(kCT) void k_restrict(KParams kp, CoarseK ck, const T *__restrict__ v,
+                                                  const T *__restrict__ Bs, const T *__restrict__ zp,
+                                                  const T *__restrict__ base, T *__restrict__ rc) {
+  const int dim = ck.dim, nv = ck.nv, bu = kp.s.bu, nn = ck.nn;
+  const int64_t t = blockIdx.x * (int64_t)kCT + threadIdx.x;
+  if (t >= (int64_t)ck.ncls * dim) return;
+  const int32_t c = (int32_t)(t / dim);
+  const int i = (int)(t % dim);
+  double acc = 0.0;
+  for (int32_t q = ck.rc_ptr[c]; q < ck.rc_ptr[c + 1]; ++q) {
+    const int64_t e = ck.rc_list[q] / nv;
+    const int vv = ck.rc_list[q] % nv;
+    for (int w = 0; w < ck.nw[vv]; ++w) {
+      const int a = ck.wn[vv][w];
+      if (clamped(kp.m.clamp, e, a * dim + i)) continue;
+      if (v) acc += ck.ww[vv][w] * (double)v[(e * nn + a) * dim + i];
+      if (zp)
+        for (int64_t s = kp.m.sp_ptr[e]; s < kp.m.sp_ptr[e + 1]; ++s)
+          acc -= ck.ww[vv][w] * (double)Bs[s * bu + a * dim + i] * (double)zp[kp.m.sp_pnode[s]];
+    }
+  }
+  rc[t] = (T)((base ? (double)base[t] : 0.0) + acc);
+}
+
+// pressure rows of the first half: q'_i = v_p,i - (Cf v_u + W z_c1)_i
+template <typename T>
+__global__ __launch_bounds__(64) void k_tl_q(KParams kp, CoarseK ck, const T *__restrict__ Cf,
+                                             const T *__restrict__ W, const T *__restrict__ vu,
+                                             const T *__restrict__ vp, const T *__restrict__ zc,
+                                             T *__restrict__ qout) {
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x, bu = kp.s.bu, dim = ck.dim;
+  double acc = 0.0;
+  for (int32_t c = kp.m.pc_ptr[i]; c < kp.m.pc_ptr[i + 1]; ++c) {
+    const int32_t ent = kp.m.pc_ent[c];
+    const int64_t e = kp.m.sp_elem[ent];
+    if (lane < bu) acc += (double)Cf[(int64_t)ent * bu + lane] * (double)vu[e * bu + lane];
+    const int64_t c0 = ck.ap_ptr[e];
+    const int ncol = (int)(ck.ap_ptr[e + 1] - c0) * dim;
+    const T *w = W + ck.w_off[ent];
+    for (int col = lane; col < ncol; col += 64)
+      acc += (double)w[col] * (double)zc[(int64_t)ck.ap_cls[c0 + col / dim] * dim + col % dim];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) qout[i] = (T)((double)vp[i] - acc);
+}
+
+// t = v_u - B z_p - AP z_c2 and apz = AP z_c2: thread per (element, row)
+template <typename T>
+__global__ __launch_bounds__(kCT) void k_tl_t(KParams kp, CoarseK ck, const T *__restrict__ AP,
+                                              const T *__restrict__ Bs, const T *__restrict__ vu,
+                                              const T *__restrict__ zp, const T *__restrict__ zc,
+                                              T *__restrict__ t_out, T *__restrict__ apz) {
+  const int bu = kp.s.bu, dim = ck.dim;
+  const int64_t t = blockIdx.x * (int64_t)kCT + threadIdx.x;
+  if (t >= kp.s.n_u) return;
+  const int64_t e = t / bu;
+  const int r = (int)(t % bu);
+  const int64_t c0 = ck.ap_ptr[e];
+  const int ncol = (int)(ck.ap_ptr[e + 1] - c0) * dim;
+  const T *ap = AP + c0 * dim * bu + r;
+  double acc = 0.0;
+  for (int col = 0; col < ncol; ++col)
+    acc += (double)ap[(int64_t)col * bu] * (double)zc[(int64_t)ck.ap_cls[c0 + col / dim] * dim + col % dim];
+  double bz = 0.0;
+  for (int64_t s = kp.m.sp_ptr[e]; s < kp.m.sp_ptr[e + 1]; ++s)
+    bz += (double)Bs[s * bu + r] * (double)zp[kp.m.sp_pnode[s]];
+  apz[t] = (T)acc;
+  t_out[t] = (T)((double)vu[t] - bz - acc);
+}
+
+// pressure rows of the product: w_p = Cf t + D z_p + C P z_c2 (one wave per row)
+template <typename T>
+__global__ __launch_bounds__(64) void k_tl_prows(KParams kp, CoarseK ck, const T *__restrict__ Cf,
+                                                 const T *__restrict__ Cs, const T *__restrict__ D,
+                                                 const T *__restrict__ tu, const T *__restrict__ zp,
+                                                 const T *__restrict__ zc, T *__restrict__ wp) {
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x, bu = kp.s.bu, dim = ck.dim, nv = ck.nv;
+  double acc = 0.0;
+  for (int32_t c = kp.m.pc_ptr[i]; c < kp.m.pc_ptr[i + 1]; ++c) {
+    const int32_t ent = kp.m.pc_ent[c];
+    const int64_t e = kp.m.sp_elem[ent];
+    if (lane < bu) {
+      acc += (double)Cf[(int64_t)ent * bu + lane] * (double)tu[e * bu + lane];
+      // (C P z_c2): row lane = (a, comp) of the element gets the P1 value
+      const int a = lane / dim, comp = lane % dim;
+      if (!clamped(kp.m.clamp, e, lane)) {
+        double pz = 0.0;
+        for (int v = 0; v < nv; ++v) {
+          const int32_t cl = ck.cls_of[e * nv + v];
+          if (cl < 0) continue;
+          for (int w = 0; w < ck.nw[v]; ++w)
+            if (ck.wn[v][w] == a) pz += ck.ww[v][w] * (double)zc[(int64_t)cl * dim + comp];
+        }
+        acc += (double)Cs[(int64_t)ent * bu + lane] * pz;
+      }
+    }
+  }
+  const int b = kp.pinst[i];
+  const int64_t p0 = kp.poff[b], nb = kp.poff[b + 1] - p0;
+  const T *Drow = D + kp.doff[b] + (i - p0) * nb;
+  for (int64_t j = lane; j < nb; j += 64) acc += (double)Drow[j] * (double)zp[p0 + j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) wp[i] = (T)acc;
+}
+
+// y_p = S x_p with the dense pressure block of each instance (one wave per row)
+template <typename T>
+__global__ __launch_bounds__(64) void k_pgemv(KParams kp, const T *__restrict__ S, const T *__restrict__ x,
+                                              T *__restrict__ y) {
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int b = kp.pinst[i];
+  const int64_t p0 = kp.poff[b], nb = kp.poff[b + 1] - p0;
+  const T *row = S + kp.doff[b] + (i - p0) * nb;
+  double acc = 0.0;
+  for (int64_t j = lane; j < nb; j += 64) acc += (double)row[j] * (double)x[p0 + j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) y[i] = (T)acc;
+}
+
+// z_u += P z_c: thread per displacement DOF
+template <typename T>
+__global__ __launch_bounds__(kCT) void k_prolong_add(KParams kp, CoarseK ck, const T *__restrict__ zc,
+                                                     T *__restrict__ zu) {
+  const int bu = kp.s.bu, dim = ck.dim, nv = ck.nv;
+  const int64_t t = blockIdx.x * (int64_t)kCT + threadIdx.x;
+  if (t >= kp.s.n_u) return;
+  const int64_t e = t / bu;
+  const int r = (int)(t % bu), a = r / dim, comp = r % dim;
+  if (clamped(kp.m.clamp, e, r)) return;
+  double pz = 0.0;
+  for (int v = 0; v < nv; ++v) {
+    const int32_t cl = ck.cls_of[e * nv + v];
+    if (cl < 0) continue;
+    for (int w = 0; w < ck.nw[v]; ++w)
+      if (ck.wn[v][w] == a) pz += ck.ww[v][w] * (double)zc[(int64_t)cl * dim + comp];
+  }
+  zu[t] = (T)((double)zu[t] + pz);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static unsigned nblk(int64_t n, int t = kCT) { return (unsigned)std::max<int64_t>((n + t - 1) / t, 1); }
+
+hipError_t coarse_build_ap(const KParams &kp, const CoarseK &ck, const double *A, const int32_t *elist, int64_t n,
+                           double *AP, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ap_build, dim3((unsigned)n), dim3(kCT), 0, st, kp, ck, A, elist, AP);
+  return hipGetLastError();
+}
+
+hipError_t coarse_build_w(const KParams &kp, const CoarseK &ck, const double *Cs, const double *inv,
+                          const double *AP, double *W, hipStream_t st) {
+  if (kp.s.n_strip <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_w_build, dim3((unsigned)kp.s.n_strip), dim3(kCT), 0, st, kp, ck, Cs, inv, AP, W);
+  return hipGetLastError();
+}
+
+hipError_t coarse_factor(const KParams &kp, const CoarseK &ck, const CoarseHostView &hv, const double *AP,
+                         double *F, double *Cp, double *Dsc, int *flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_cfill, dim3(nblk(ck.front_total, 256) > 16384 ? 16384 : nblk(ck.front_total, 256)),
+                     dim3(256), 0, st, F, ck.front_total);
+  if (ck.n_pairs)
+    hipLaunchKernelGGL(k_pairs, dim3(nblk(ck.n_pairs * ck.dim * ck.dim)), dim3(kCT), 0, st, kp, ck, AP, F);
+  for (int l = 0; l < hv.n_levels; ++l) {
+    const int nodes = hv.level_ptr[l + 1] - hv.level_ptr[l];
+    if (!nodes) continue;
+    if (l > 0)
+      for (int slot = 0; slot < 2; ++slot) {
+        const int64_t m = hv.level_maxchild_upd[l];
+        if (m <= 0) break;
+        const unsigned gx = (unsigned)std::min<int64_t>((m + kCT - 1) / kCT, 4096);
+        hipLaunchKernelGGL(k_extend_add, dim3(gx, nodes), dim3(kCT), 0, st, ck, l, slot, F);
+      }
+    const int maxk = hv.level_maxk[l], maxf = hv.level_maxf[l];
+    const int nt = (maxf + kTile - 1) / kTile;
+    for (int p0 = 0; p0 < maxk; p0 += kNB) {
+      hipLaunchKernelGGL(k_gj_a, dim3(nt, nodes), dim3(kCT), 0, st, ck, l, p0, F, Cp, Dsc, flag);
+      hipLaunchKernelGGL(k_gj_b, dim3(nt * nt, nodes), dim3(kCT), 0, st, ck, l, p0, F, Cp, Dsc, flag);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t coarse_ptb(const KParams &kp, const CoarseK &ck, const double *Bs, int nrhs, double *R, hipStream_t st) {
+  if (!ck.ncls || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ptb, dim3(nblk((int64_t)ck.ncls * ck.dim)), dim3(kCT), 0, st, kp, ck, Bs, nrhs, R);
+  return hipGetLastError();
+}
+
+hipError_t coarse_solve_multi(const CoarseK &ck, const CoarseHostView &hv, const double *F, const double *b,
+                              int nrhs, double *upd, double *y, double *xs, hipStream_t st) {
+  for (int l = 0; l < hv.n_levels; ++l) {
+    const int nodes = hv.level_ptr[l + 1] - hv.level_ptr[l];
+    if (!nodes) continue;
+    hipLaunchKernelGGL(k_fwdm_own, dim3(nblk((int64_t)hv.level_maxk[l] * nrhs), nodes), dim3(kCT), 0, st, ck, l,
+                       b, upd, nrhs, y);
+    const int64_t mu = (int64_t)(hv.level_maxf_minus_k[l]) * nrhs;
+    if (mu > 0)
+      hipLaunchKernelGGL(k_fwdm_upd, dim3(nblk(mu), nodes), dim3(kCT), 0, st, ck, l, F, y, nrhs, upd);
+  }
+  for (int l = hv.n_levels - 1; l >= 0; --l) {
+    const int nodes = hv.level_ptr[l + 1] - hv.level_ptr[l];
+    if (!nodes) continue;
+    hipLaunchKernelGGL(k_bwdm, dim3(nblk((int64_t)hv.level_maxk[l] * nrhs), nodes), dim3(kCT), 0, st, ck, l, F, y,
+                       nrhs, xs);
+  }
+  return hipGetLastError();
+}
+
+hipError_t coarse_s_correct(const KParams &kp, const CoarseK &ck, const double *W, const double *Z, int nrhs,
+                            double *S, hipStream_t st) {
+  if (!kp.s.n_p) return hipSuccess;
+  hipLaunchKernelGGL(k_s_correct, dim3(nblk(nrhs), (unsigned)kp.s.n_p), dim3(kCT), 0, st, kp, ck, W, Z, nrhs, S);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const T *F, const T *b, T *upd, T *y, T *xs,
+                         hipStream_t st) {
+  constexpr int RP = kCT / 64;
+  for (int l = 0; l < hv.n_levels; ++l) {
+    const int nodes = hv.level_ptr[l + 1] - hv.level_ptr[l];
+    if (!nodes) continue;
+    const size_t sh = (size_t)std::max(hv.level_maxk[l], 1) * sizeof(T);
+    hipLaunchKernelGGL((k_fwd1<T>), dim3((hv.level_maxf[l] + RP - 1) / RP, nodes), dim3(kCT), sh, st, ck, l, F, b,
+                       upd, y);
+  }
+  for (int l = hv.n_levels - 1; l >= 0; --l) {
+    const int nodes = hv.level_ptr[l + 1] - hv.level_ptr[l];
+    if (!nodes) continue;
+    hipLaunchKernelGGL((k_bwd1<T>), dim3((hv.level_maxk[l] + RP - 1) / RP, nodes), dim3(kCT), 0, st, ck, l, F, y,
+                       xs);
+  }
+  return hipGetLastError();
+}
+template hipError_t coarse_solve1<double>(const CoarseK &, const CoarseHostView &, const double *, const double *,
+                                          double *, double *, double *, hipStream_t);
+template hipError_t coarse_solve1<float>(const CoarseK &, const CoarseHostView &, const float *, const float *,
+                                         float *, float *, float *, hipStream_t);
+
+template <typename T>
+hipError_t coarse_restrict(const KParams &kp, const CoarseK &ck, const T *v, const T *Bs, const T *zp,
+                           const T *base, T *rc, hipStream_t st) {
+  if (!ck.ncls) return hipSuccess;
+  hipLaunchKernelGGL((k_restrict<T>), dim3(nblk((int64_t)ck.ncls * ck.dim)), dim3(kCT), 0, st, kp, ck, v, Bs, zp,
+                     base, rc);
+  return hipGetLastError();
+}
+template hipError_t coarse_restrict<double>(const KParams &, const CoarseK &, const double *, const double *,
+                                            const double *, const double *, double *, hipStream_t);
+template hipError_t coarse_restrict<float>(const KParams &, const CoarseK &, const float *, const float *,
+                                           const float *, const float *, float *, hipStream_t);
+
+template <typename T>
+hipError_t coarse_q(const KParams &kp, const CoarseK &ck, const T *Cf, const T *W, const T *vu, const T *vp,
+                    const T *zc, T *qout, hipStream_t st) {
+  if (!kp.s.n_p) return hipSuccess;
+  hipLaunchKernelGGL((k_tl_q<T>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp, ck, Cf, W, vu, vp, zc, qout);
+  return hipGetLastError();
+}
+template hipError_t coarse_q<double>(const KParams &, const CoarseK &, const double *, const double *,
+                                     const double *, const double *, const double *, double *, hipStream_t);
+template hipError_t coarse_q<float>(const KParams &, const CoarseK &, const float *, const float *, const float *,
+                                    const float *, const float *, float *, hipStream_t);
+
+template <typename T>
+hipError_t coarse_t(const KParams &kp, const CoarseK &ck, const T *AP, const T *Bs, const T *vu, const T *zp,
+                    const T *zc, T *t, T *apz, hipStream_t st) {
+  hipLaunchKernelGGL((k_tl_t<T>), dim3(nblk(kp.s.n_u)), dim3(kCT), 0, st, kp, ck, AP, Bs, vu, zp, zc, t, apz);
+  return hipGetLastError();
+}
+template hipError_t coarse_t<double>(const KParams &, const CoarseK &, const double *, const double *,
+                                     const double *, const double *, const double *, double *, double *,
+                                     hipStream_t);
+template hipError_t coarse_t<float>(const KParams &, const CoarseK &, const float *, const float *, const float *,
+                                    const float *, const float *, float *, float *, hipStream_t);
+
+template <typename T>
+hipError_t coarse_prows(const KParams &kp, const CoarseK &ck, const T *Cf, const T *Cs, const T *D, const T *tu,
+                        const T *zp, const T *zc, T *wp, hipStream_t st) {
+  if (!kp.s.n_p) return hipSuccess;
+  hipLaunchKernelGGL((k_tl_prows<T>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp, ck, Cf, Cs, D, tu, zp, zc, wp);
+  return hipGetLastError();
+}
+template hipError_t coarse_prows<double>(const KParams &, const CoarseK &, const double *, const double *,
+                                         const double *, const double *, const double *, const double *, double *,
+                                         hipStream_t);
+template hipError_t coarse_prows<float>(const KParams &, const CoarseK &, const float *, const float *,
+                                        const float *, const float *, const float *, const float *, float *,
+                                        hipStream_t);
+
+template <typename T>
+hipError_t coarse_prolong_add(const KParams &kp, const CoarseK &ck, const T *zc, T *zu, hipStream_t st) {
+  hipLaunchKernelGGL((k_prolong_add<T>), dim3(nblk(kp.s.n_u)), dim3(kCT), 0, st, kp, ck, zc, zu);
+  return hipGetLastError();
+}
+template hipError_t coarse_prolong_add<double>(const KParams &, const CoarseK &, const double *, double *,
+                                               hipStream_t);
+template hipError_t coarse_prolong_add<float>(const KParams &, const CoarseK &, const float *, float *, hipStream_t);
+
+template <typename T>
+hipError_t coarse_pgemv(const KParams &kp, const T *S, const T *x, T *y, hipStream_t st) {
+  if (!kp.s.n_p) return hipSuccess;
+  hipLaunchKernelGGL((k_pgemv<T>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp, S, x, y);
+  return hipGetLastError();
+}
+template hipError_t coarse_pgemv<double>(const KParams &, const double *, const double *, double *, hipStream_t);
+template hipError_t coarse_pgemv<float>(const KParams &, const float *, const float *, float *, hipStream_t);
+
+}  // namespace hf

@@ -619,19 +619,32 @@ hipError_t launch_dense_inv_wide(double *W, double *out, float *out32, int n, in
   return hipGetLastError();
 }
 
-hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,
-                        const double *Cs, const double *D, double *Z, double *T, double *S,
-                        double *Sinv, float *Sinv32, int *flag, int n_wide, hipStream_t st) {
-  (void)Z;
+hipError_t launch_schur_form(const KParams &kp, const double *inv, const double *Bs, const double *Cs,
+                             const double *D, double *T, double *S, hipStream_t st) {
   const int64_t np = kp.s.n_p;
   if (!np) return hipSuccess;
   if (kp.s.n_se)
     hipLaunchKernelGGL(k_schur_t, dim3((unsigned)kp.s.n_se), dim3(64), 0, st, kp, inv, Bs, Cs, T);
   hipLaunchKernelGGL(k_schur_gather, dim3((unsigned)((np + 63) / 64)), dim3(64), 0, st, kp, D, T,
                      kp.m.sp_se, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_schur_invert(const KParams &kp, double *S, double *Sinv, float *Sinv32, int *flag, int n_wide,
+                               hipStream_t st) {
+  if (!kp.s.n_p) return hipSuccess;
   hipLaunchKernelGGL(k_dense_inv, dim3(kp.n_inst), dim3(kDT), 0, st, kp.poff, kp.doff, S, Sinv,
                      Sinv32, flag, n_wide);
   return hipGetLastError();
+}
+
+hipError_t launch_schur(const KParams &kp, const double *inv, const double *Bs,
+                        const double *Cs, const double *D, double *Z, double *T, double *S,
+                        double *Sinv, float *Sinv32, int *flag, int n_wide, hipStream_t st) {
+  (void)Z;
+  const hipError_t e = launch_schur_form(kp, inv, Bs, Cs, D, T, S, st);
+  if (e != hipSuccess) return e;
+  return launch_schur_invert(kp, S, Sinv, Sinv32, flag, n_wide, st);
 }
 
 __global__ void k_convert(const double *__restrict__ in, float *__restrict__ out, int64_t n) {

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(NT) void k_bsr_spmv(
     int64_t ne, const int64_t *__restrict__ blk_ptr, const int32_t *__restrict__ blk_col,
     const T *__restrict__ A, const int64_t *__restrict__ sp_ptr,
     const int32_t *__restrict__ sp_pnode, const T *__restrict__ Bs, const T *__restrict__ x,
-    const T *__restrict__ xp, T *__restrict__ y, RowMask mask) {
+    const T *__restrict__ xp, T *__restrict__ y, RowMask mask, const T *__restrict__ add) {
   using S = SpmvShape<T, BU, LN>;
   constexpr int L = S::L, EL = S::EL, LA = S::LA, CH = S::CH, RPC = S::RPC, G = NT / L;
   using V = typename Vec16<T>::type;
@@ -167,6 +167,7 @@ __global__ __launch_bounds__(NT) void k_bsr_spmv(
     if (STRIPS) {
       for (int64_t k = sp_ptr[e]; k < sp_ptr[e + 1]; ++k) sum += Bs[k * BU + lane] * xp[sp_pnode[k]];
     }
+    if (add) sum += add[e * BU + lane];
     y[e * BU + lane] = sum;
   }
 }
@@ -207,10 +208,10 @@ __global__ __launch_bounds__(64) void k_prows(int64_t np, const int32_t *__restr
 template <typename T, int BU, int LN, bool STRIPS>
 static void rows_launch(int64_t ne, const int64_t *ptr, const int32_t *col, const T *A,
                         const int64_t *sp_ptr, const int32_t *sp_pnode, const T *Bs, const T *x,
-                        const T *xp, T *y, const RowMask &me, hipStream_t st) {
+                        const T *xp, T *y, const RowMask &me, hipStream_t st, const T *add = nullptr) {
   constexpr int NT = 256, G = NT / LN;
   hipLaunchKernelGGL((k_bsr_spmv<T, BU, LN, NT, STRIPS>), dim3((unsigned)((ne + G - 1) / G)), dim3(NT),
-                     0, st, ne, ptr, col, A, sp_ptr, sp_pnode, Bs, x, xp, y, me);
+                     0, st, ne, ptr, col, A, sp_ptr, sp_pnode, Bs, x, xp, y, me, add);
 }
 
 template <typename T, int BU>
@@ -464,6 +465,37 @@ static void spmv_folded_bu(const KParams &kp, const T *Af, const T *Bs, const T 
                        kp.pinst, kp.poff, kp.doff, kp.m.pc_ptr, kp.m.pc_ent, kp.m.sp_elem, Cf, D, x,
                        tp, y + kp.s.n_u, mp);
 }
+
+template <typename T, int BU>
+static void folded_rows_bu(const KParams &kp, const T *Af, const T *Bs, const T *x, const T *tp, const T *add, T *y,
+                           hipStream_t st) {
+  const RowMask me{kp.einst, nullptr, nullptr, 0};
+  constexpr int LW = wide_lanes(BU);
+  if (!kp.s.ne) return;
+  if (kp.spmv_var == 1)
+    rows_launch<T, BU, LW / 2, true>(kp.s.ne, kp.m.blk_ptr, kp.m.blk_col, Af, kp.m.sp_ptr, kp.m.sp_pnode, Bs, x,
+                                     tp, y, me, st, add);
+  else
+    rows_launch<T, BU, LW, true>(kp.s.ne, kp.m.blk_ptr, kp.m.blk_col, Af, kp.m.sp_ptr, kp.m.sp_pnode, Bs, x, tp,
+                                 y, me, st, add);
+}
+
+template <typename T>
+hipError_t launch_spmv_folded_rows(const KParams &kp, const T *Af, const T *Bs, const T *x, const T *tp,
+                                   const T *add, T *y, hipStream_t st) {
+  switch (kp.s.bu) {
+    case 6: folded_rows_bu<T, 6>(kp, Af, Bs, x, tp, add, y, st); break;
+    case 12: folded_rows_bu<T, 12>(kp, Af, Bs, x, tp, add, y, st); break;
+    case 30: folded_rows_bu<T, 30>(kp, Af, Bs, x, tp, add, y, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_spmv_folded_rows<double>(const KParams &, const double *, const double *,
+                                                    const double *, const double *, const double *, double *,
+                                                    hipStream_t);
+template hipError_t launch_spmv_folded_rows<float>(const KParams &, const float *, const float *, const float *,
+                                                   const float *, const float *, float *, hipStream_t);
 
 template <typename T>
 hipError_t launch_spmv_folded(const KParams &kp, const T *Af, const T *Bs, const T *Cf, const T *D,
