@@ -166,7 +166,7 @@ def counters_probe(prob):
     ctx.close()
 
 
-def ensemble_block(K, gmres_m, tune_level=1):
+def ensemble_block(K, gmres_m, tune_level=1, two_level=0):
     """The batched 2D KGD ensemble: 64 instances (1k-20k triangles, mixed P1 /
     P2, materials and injection drawn per instance).  The P1 and the P2
     instances each form one batched context (every kernel launch covers all
@@ -188,7 +188,8 @@ def ensemble_block(K, gmres_m, tune_level=1):
     ctxs, starts, streams = [], [], []
     for ps in groups:
         stm = torch.cuda.Stream()
-        c = hf.context_for_problems(ps, device=0, stream=stm.cuda_stream, gmres_m=gmres_m)
+        c = hf.context_for_problems(ps, device=0, stream=stm.cuda_stream, gmres_m=gmres_m,
+                                    two_level=two_level)
         for i, p in enumerate(ps):
             s = c.isizes[i]
             c.set_state(np.zeros(s.n_u), np.full(s.n_p, p.material.sigma_c),
@@ -265,6 +266,8 @@ def main():
                          "paper_1911_10275_amd/tuning_cache.txt")
     ap.add_argument("--ensemble-steps", type=int, default=3)
     ap.add_argument("--ensemble-m", type=int, default=120, help="GMRES restart length, ensemble")
+    ap.add_argument("--two-level", type=int, default=0, choices=(0, 1),
+                    help="1: two-level block preconditioner, 0: block-Jacobi")
     ap.add_argument("--counters", action="store_true",
                     help="hardware-counter probe: 5 FP64 Jacobian products of the workload and "
                          "one 1 GiB device copy (calibration), then one FP32-IR preconditioner "
@@ -286,7 +289,8 @@ def main():
     print(f"bench: workload {prob.name}: {prob.n_elem} elements, {prob.n_udof} displacement DOF",
           file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream().cuda_stream
-    ctx = hf.context_for_problem(prob, device=0, stream=stream, gmres_m=args.gmres_m)
+    ctx = hf.context_for_problem(prob, device=0, stream=stream, gmres_m=args.gmres_m,
+                                 two_level=args.two_level)
     sz = ctx.sizes
     N = sz.n_u + sz.n_p
 
@@ -341,6 +345,7 @@ def main():
         "config": {"workload": prob.name, "elements": int(sz.n_elem), "dof": int(N),
                    "u_dof": int(sz.n_u), "p_dof": int(sz.n_p), "element": f"P{prob.order}",
                    "dim": prob.dim, "precision": "fp64",
+                   "preconditioner": "two-level" if args.two_level else "block-Jacobi",
                    "gmres_m": tuned.get("fp64", {}).get("gmres_m", args.gmres_m), "rtol": 1e-10},
         "median_step_ms": 1e3 * float(np.median([x[7] for x in st64])),
         "gmres": {"iters_per_step": float(np.mean(iters64)),
@@ -386,7 +391,7 @@ def main():
     ctx.close()
     out["tuning"] = tuned
     if not args.no_ensemble:
-        out["ensemble"] = ensemble_block(args.ensemble_steps, args.ensemble_m, args.tune)
+        out["ensemble"] = ensemble_block(args.ensemble_steps, args.ensemble_m, args.tune, args.two_level)
     if not args.no_cpu:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob, float(np.mean(iters64)))

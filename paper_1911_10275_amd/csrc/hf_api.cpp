@@ -68,15 +68,15 @@ struct KrylovWs {
 // preconditioner build) and its work vectors
 template <typename T>
 struct TlBuf {
-  const T *AP = nullptr, *W = nullptr, *F = nullptr, *Sinv2 = nullptr;
+  const T *AP = nullptr, *W = nullptr, *F = nullptr, *Sinv2 = nullptr, *Z = nullptr;
   T *rc1 = nullptr, *rc2 = nullptr, *zc1 = nullptr, *zc2 = nullptr, *y = nullptr, *upd = nullptr;
-  T *q = nullptr, *zp = nullptr, *t = nullptr, *apz = nullptr;
+  T *q = nullptr, *zp = nullptr, *t = nullptr, *apz = nullptr, *cpy = nullptr;
 };
 
 // concatenated host layout kept after hf_finalize for the coarse-space plan
 struct HostLayout {
   std::vector<double> xyz;
-  std::vector<int32_t> elem, face_em, face_ep, fperm_m, fperm_p, blk_col;
+  std::vector<int32_t> elem, face_em, face_ep, fperm_m, fperm_p, blk_col, nbr;
   std::vector<uint32_t> clamp;
   std::vector<uint8_t> qp_state, beta;
   std::vector<int64_t> blk_ptr;
@@ -171,7 +171,7 @@ struct hf_ctx {
   CoarseK ck;
   double *cAP = nullptr, *cW = nullptr, *cF = nullptr, *cCp = nullptr, *cDsc = nullptr;
   double *cR = nullptr, *cZ = nullptr, *cY = nullptr, *cU = nullptr, *S2 = nullptr, *Sinv2 = nullptr;
-  float *cAP32 = nullptr, *cW32 = nullptr, *cF32 = nullptr, *Sinv2_32 = nullptr;
+  float *cAP32 = nullptr, *cW32 = nullptr, *cF32 = nullptr, *Sinv2_32 = nullptr, *cZ32 = nullptr;
   int *cflag = nullptr;
   int c_nrhs = 0;
   int64_t c_ap_total = 0, c_w_total = 0;
@@ -1201,6 +1201,7 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
     hl.beta = std::move(beta);
     hl.blk_ptr = std::move(blk_ptr);
     hl.blk_col = std::move(blk_col);
+    hl.nbr = std::move(nbr);
   }
   ctx->stage = 2;
   return HF_OK;
@@ -1515,18 +1516,20 @@ static hf_status residual(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, cons
 // solution z_c2, t = v_u - B z_p - A P z_c2 and apz = A P z_c2
 // (see hf_kernels_coarse.hip for the factorisation it applies).
 template <typename T>
-static hf_status tl_first(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *v) {
+static hf_status tl_first(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *v, T *wp) {
   const TlBuf<T> &b = *op.tl;
   const CoarseK &ck = ctx->ck;
   hipStream_t st = ctx->stream;
   const int64_t n_u = ctx->s.n_u;
-  HIPCHK(coarse_restrict<T>(kp, ck, v, nullptr, nullptr, nullptr, b.rc1, st));
+  HIPCHK(coarse_restrict2<T>(kp, ck, v, b.cpy, b.rc1, st));
   HIPCHK(coarse_solve1<T>(ck, ctx->chv, b.F, b.rc1, b.upd, b.y, b.zc1, st));
-  HIPCHK(coarse_q<T>(kp, ck, op.Cf, b.W, v, v + n_u, b.zc1, b.q, st));
-  HIPCHK(coarse_pgemv<T>(kp, b.Sinv2, b.q, b.zp, st));
-  HIPCHK(coarse_restrict<T>(kp, ck, nullptr, op.Bs, b.zp, b.rc1, b.rc2, st));
-  HIPCHK(coarse_solve1<T>(ck, ctx->chv, b.F, b.rc2, b.upd, b.y, b.zc2, st));
-  HIPCHK(coarse_t<T>(kp, ck, b.AP, op.Bs, v, b.zp, b.zc2, b.t, b.apz, st));
+  if (ctx->s.n_p) {
+    HIPCHK(coarse_q<T>(kp, ck, op.Cf, b.W, v, v + n_u, b.zc1, b.q, wp, st));
+    HIPCHK(coarse_pgemv<T>(kp, b.Sinv2, b.q, b.zp, st));
+    HIPCHK(coarse_zc2<T>(kp, ck, b.Z, ctx->c_nrhs, b.zc1, b.zp, b.zc2, st));
+  }
+  const T *zc2 = ctx->s.n_p ? b.zc2 : b.zc1;
+  HIPCHK(coarse_t<T>(kp, ck, b.AP, op.Bs, v, b.zp, zc2, b.t, b.apz, st));
   return HF_OK;
 }
 
@@ -1535,24 +1538,24 @@ static hf_status tl_first(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, cons
 template <typename T>
 static hf_status tl_apply_M(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *r, T *z) {
   ProfScope ps(ctx, P_PREC);
-  TRY(tl_first<T>(ctx, kp, op, r));
+  TRY(tl_first<T>(ctx, kp, op, r, nullptr));
   const TlBuf<T> &b = *op.tl;
   HIPCHK(launch_precond<T>(kp, op.inv, op.Sinv, b.t, z, RowSel{}, ctx->stream));
-  HIPCHK(coarse_prolong_add<T>(kp, ctx->ck, b.zc2, z, ctx->stream));
+  HIPCHK(coarse_prolong_add<T>(kp, ctx->ck, ctx->s.n_p ? b.zc2 : b.zc1, z, ctx->stream));
   if (ctx->s.n_p)
     HIPCHK(hipMemcpyAsync(z + ctx->s.n_u, b.zp, ctx->s.n_p * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
   return HF_OK;
 }
 
 // w = J M^-1 v with the two-level preconditioner, from the folded blocks:
-// w_u = Af t + B z_p + A P z_c2, w_p = Cf t + D z_p + C P z_c2 (every row)
+// w_u = Af t + B z_p + A P z_c2, w_p = v_p (the factorisation is exact in
+// the pressure rows) (every row)
 template <typename T>
 static hf_status tl_apply_JM(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, const T *v, T *w) {
   ProfScope ps(ctx, sizeof(T) == 8 ? P_SPMV64 : P_SPMV32);
-  TRY(tl_first<T>(ctx, kp, op, v));
+  TRY(tl_first<T>(ctx, kp, op, v, w + ctx->s.n_u));
   const TlBuf<T> &b = *op.tl;
   HIPCHK(launch_spmv_folded_rows<T>(kp, op.Af, op.Bs, b.t, b.zp, b.apz, w, ctx->stream));
-  HIPCHK(coarse_prows<T>(kp, ctx->ck, op.Cf, op.Cs, op.D, b.t, b.zp, b.zc2, w + ctx->s.n_u, ctx->stream));
   return HF_OK;
 }
 
@@ -1864,6 +1867,7 @@ static hf_status tl_plan(hf_ctx *ctx) {
   in.beta = hl.beta.data();
   in.blk_ptr = hl.blk_ptr.data();
   in.blk_col = hl.blk_col.data();
+  in.nbr = hl.nbr.data();
   in.eoff = ctx->eoff.data();
   CoarsePlan &cp = ctx->cplan;
   try {
@@ -2001,6 +2005,7 @@ static hf_status tl_plan(hf_ctx *ctx) {
     TRY(dalloc(ctx, &b.zp, s.n_p));
     TRY(dalloc(ctx, &b.t, s.N()));
     TRY(dalloc(ctx, &b.apz, s.n_u));
+    TRY(dalloc(ctx, &b.cpy, s.ne * nv * dim));
     HIPCHK(hipMemsetAsync(b.t, 0, s.N() * sizeof(*b.t), ctx->stream));
     return HF_OK;
   };
@@ -2009,16 +2014,7 @@ static hf_status tl_plan(hf_ctx *ctx) {
   ctx->tb64.W = ctx->cW;
   ctx->tb64.F = ctx->cF;
   ctx->tb64.Sinv2 = ctx->Sinv2;
-  if (ctx->opt.precision == HF_FP32_IR) {
-    TRY(vecs(ctx->tb32));
-    TRY(dalloc(ctx, &ctx->cAP32, ctx->c_ap_total));
-    TRY(dalloc(ctx, &ctx->cW32, ctx->c_w_total));
-    TRY(dalloc(ctx, &ctx->cF32, std::max<int64_t>(cp.front_total, 1)));
-    ctx->tb32.AP = ctx->cAP32;
-    ctx->tb32.W = ctx->cW32;
-    ctx->tb32.F = ctx->cF32;
-    ctx->tb32.Sinv2 = ctx->Sinv2_32;
-  }
+  ctx->tb64.Z = ctx->cZ;
   TRY(sync(ctx));
   return HF_OK;
 }
@@ -2046,6 +2042,7 @@ static hf_status tl_build(hf_ctx *ctx, int n_wide) {
       TRY(dalloc(ctx, &b.zp, s.n_p));
       TRY(dalloc(ctx, &b.t, s.N()));
       TRY(dalloc(ctx, &b.apz, s.n_u));
+      TRY(dalloc(ctx, &b.cpy, s.ne * (s.dim + 1) * s.dim));
       HIPCHK(hipMemsetAsync(b.t, 0, s.N() * sizeof(*b.t), st));
       return HF_OK;
     };
@@ -2053,10 +2050,12 @@ static hf_status tl_build(hf_ctx *ctx, int n_wide) {
     TRY(dalloc(ctx, &ctx->cAP32, ctx->c_ap_total));
     TRY(dalloc(ctx, &ctx->cW32, ctx->c_w_total));
     TRY(dalloc(ctx, &ctx->cF32, std::max<int64_t>(ctx->cplan.front_total, 1)));
+    if (s.n_p) TRY(dalloc(ctx, &ctx->cZ32, (int64_t)ctx->cplan.ncls * s.dim * ctx->c_nrhs));
     ctx->tb32.AP = ctx->cAP32;
     ctx->tb32.W = ctx->cW32;
     ctx->tb32.F = ctx->cF32;
     ctx->tb32.Sinv2 = ctx->Sinv2_32;
+    ctx->tb32.Z = ctx->cZ32;
     release_all_graphs(ctx);
   }
   HIPCHK(hipMemsetAsync(ctx->cflag, 0, sizeof(int), st));
@@ -2080,6 +2079,7 @@ static hf_status tl_build(hf_ctx *ctx, int n_wide) {
     HIPCHK(launch_convert(ctx->cAP, ctx->cAP32, ctx->c_ap_total, st));
     HIPCHK(launch_convert(ctx->cW, ctx->cW32, ctx->c_w_total, st));
     HIPCHK(launch_convert(ctx->cF, ctx->cF32, ctx->cplan.front_total, st));
+    if (s.n_p) HIPCHK(launch_convert(ctx->cZ, ctx->cZ32, (int64_t)ctx->cplan.ncls * s.dim * ctx->c_nrhs, st));
   }
   TRY(get_i_async(ctx, ctx->cflag, 1, 0));
   TRY(sync(ctx));
@@ -2979,7 +2979,8 @@ std::string tune_key(hf_ctx *ctx, int level) {
     if (c == ' ' || c == ':') c = '_';
   std::ostringstream k;
   k << arch << "_d" << ctx->s.dim << "p" << ctx->s.order << "_ne" << ctx->s.ne << "_nf" << ctx->s.nf
-    << "_np" << ctx->s.n_p << "_B" << nI(ctx) << "_prec" << ctx->opt.precision << "_L" << level;
+    << "_np" << ctx->s.n_p << "_B" << nI(ctx) << "_prec" << ctx->opt.precision << "_L" << level
+    << (ctx->opt.two_level ? "_tl" : "");
   return k.str();
 }
 

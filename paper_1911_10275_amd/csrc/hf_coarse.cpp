@@ -77,7 +77,22 @@ int nd_build(std::vector<int32_t> ids, const std::vector<double> &xyz, int dim,
     const double xa = xyz[(int64_t)a * dim + ax], xb = xyz[(int64_t)b * dim + ax];
     return xa != xb ? xa < xb : a < b;
   });
-  const size_t mid = ids.size() / 2;
+  // split at the widest gap of the sorted coordinates within the middle
+  // fifth (on a layered mesh this cuts between two layers instead of
+  // through one, which would thicken the separator)
+  const size_t n = ids.size();
+  size_t mid = n / 2;
+  {
+    const size_t lo = std::max<size_t>(1, (size_t)(0.4 * n)), hi = std::min(n - 1, (size_t)(0.6 * n) + 1);
+    double best = -1.0;
+    for (size_t i = lo; i <= hi; ++i) {
+      const double gap = xyz[(int64_t)ids[i] * dim + ax] - xyz[(int64_t)ids[i - 1] * dim + ax];
+      if (gap > best) {
+        best = gap;
+        mid = i;
+      }
+    }
+  }
   for (size_t i = 0; i < ids.size(); ++i) side[ids[i]] = i < mid ? 0 : 1;
   std::vector<int32_t> left, right, sep;
   for (size_t i = 0; i < ids.size(); ++i) {
@@ -190,14 +205,50 @@ void build_coarse_plan(const CoarseIn &in, CoarsePlan &cp) {
     int32_t ci, cj, e;
     int16_t v, j;
   };
+  // Pattern of A_c: the pairs of classes that share an element, plus the
+  // pairs across interfaces that are not intact (kept apart in the coarse
+  // space): a class of a vertex of such a face with every class of the
+  // neighbour.  Any other pair (cI, cJ) gets contributions only through
+  // faces that do not contain cI's vertex, whose face integrals vanish with
+  // e's test functions there, so it is an exact zero.  Pairs in the
+  // pattern keep every contribution: those through an intact face from the
+  // two sides cancel only together.
+  std::vector<int64_t> pat;
+  for (int64_t e = 0; e < ne; ++e)
+    for (int v = 0; v < NV; ++v) {
+      const int32_t ci = cp.cls_of[e * NV + v];
+      if (ci < 0) continue;
+      for (int w = 0; w < NV; ++w)
+        if (cp.cls_of[e * NV + w] >= 0) pat.push_back((int64_t)ci * ncls + cp.cls_of[e * NV + w]);
+      for (int lf = 0; lf < NV; ++lf) {
+        if (lf == v) continue;  // the face opposite v does not contain it
+        const int64_t f = in.nbr[e * NV + lf];
+        if (f < 0) continue;
+        bool intact = true;  // the face's classes are shared across it
+        for (int w = 0; w < NV && intact; ++w) {
+          if (w == lf) continue;
+          const int32_t g = in.elem[e * NV + w];
+          for (int w2 = 0; w2 < NV; ++w2)
+            if (in.elem[f * NV + w2] == g && cp.cls_of[f * NV + w2] != cp.cls_of[e * NV + w]) intact = false;
+        }
+        if (intact) continue;
+        for (int w2 = 0; w2 < NV; ++w2)
+          if (cp.cls_of[f * NV + w2] >= 0) pat.push_back((int64_t)ci * ncls + cp.cls_of[f * NV + w2]);
+      }
+    }
+  std::sort(pat.begin(), pat.end());
+  pat.erase(std::unique(pat.begin(), pat.end()), pat.end());
   std::vector<Contrib> con;
   con.reserve((size_t)ne * NV * 8);
   for (int64_t e = 0; e < ne; ++e)
     for (int v = 0; v < NV; ++v) {
       const int32_t ci = cp.cls_of[e * NV + v];
       if (ci < 0) continue;
-      for (int64_t j = cp.ap_ptr[e]; j < cp.ap_ptr[e + 1]; ++j)
-        con.push_back({ci, cp.ap_cls[j], (int32_t)e, (int16_t)v, (int16_t)(j - cp.ap_ptr[e])});
+      for (int64_t j = cp.ap_ptr[e]; j < cp.ap_ptr[e + 1]; ++j) {
+        const int32_t cj = cp.ap_cls[j];
+        if (!std::binary_search(pat.begin(), pat.end(), (int64_t)ci * ncls + cj)) continue;
+        con.push_back({ci, cj, (int32_t)e, (int16_t)v, (int16_t)(j - cp.ap_ptr[e])});
+      }
     }
   std::sort(con.begin(), con.end(), [](const Contrib &a, const Contrib &b) {
     if (a.ci != b.ci) return a.ci < b.ci;

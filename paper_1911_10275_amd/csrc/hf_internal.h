@@ -165,6 +165,7 @@ struct CoarseIn {  // the concatenated layout of a finalized context
   const uint8_t *qp_state = nullptr, *beta = nullptr;
   const int64_t *blk_ptr = nullptr;
   const int32_t *blk_col = nullptr;
+  const int32_t *nbr = nullptr;   // ne*(dim+1): neighbour across each local face, or -1
   const int64_t *eoff = nullptr;  // n_inst+1
 };
 
@@ -239,18 +240,21 @@ hipError_t coarse_s_correct(const KParams &kp, const CoarseK &ck, const double *
 template <typename T>
 hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const T *F, const T *b, T *upd, T *y, T *xs,
                          hipStream_t st);
-template <typename T>
-hipError_t coarse_restrict(const KParams &kp, const CoarseK &ck, const T *v, const T *Bs, const T *zp,
-                           const T *base, T *rc, hipStream_t st);
+// q' = v_p - (Cf v_u + W z_c) per pressure row; w_p = v_p when wp != null
 template <typename T>
 hipError_t coarse_q(const KParams &kp, const CoarseK &ck, const T *Cf, const T *W, const T *vu, const T *vp,
-                    const T *zc, T *qout, hipStream_t st);
+                    const T *zc, T *qout, T *wp, hipStream_t st);
+// rc = P^T v_u: P_e^T v_e per vertex copy into cpy (ne*nv*dim), then the
+// sum over each class's copies
+template <typename T>
+hipError_t coarse_restrict2(const KParams &kp, const CoarseK &ck, const T *v, T *cpy, T *rc, hipStream_t st);
+// z_c2 = z_c1 - Z_c z_p (Z_c: coarse rows x nrhs, the instance's pressure nodes)
+template <typename T>
+hipError_t coarse_zc2(const KParams &kp, const CoarseK &ck, const T *Z, int nrhs, const T *zc1, const T *zp, T *zc2,
+                      hipStream_t st);
 template <typename T>
 hipError_t coarse_t(const KParams &kp, const CoarseK &ck, const T *AP, const T *Bs, const T *vu, const T *zp,
                     const T *zc, T *t, T *apz, hipStream_t st);
-template <typename T>
-hipError_t coarse_prows(const KParams &kp, const CoarseK &ck, const T *Cf, const T *Cs, const T *D, const T *tu,
-                        const T *zp, const T *zc, T *wp, hipStream_t st);
 template <typename T>
 hipError_t coarse_prolong_add(const KParams &kp, const CoarseK &ck, const T *zc, T *zu, hipStream_t st);
 // y_p = S x_p with the dense per-instance pressure blocks S (one wave per row)

@@ -11,10 +11,12 @@
 // The product w = J z the Krylov solver needs is formed without z:
 //   q = C Ah^-1 v_u = Cf v_u + W z_c1,  z_c1 = A_c^-1 P^T v_u,
 //   z_p = S^-1 (v_p - q),
-//   z_c2 = A_c^-1 (P^T v_u - P^T B z_p),
+//   z_c2 = A_c^-1 P^T (v_u - B z_p) = z_c1 - Z_c z_p,
 //   t = v_u - B z_p - A P z_c2,
-//   w_u = Af t + B z_p + A P z_c2,  w_p = Cf t + D z_p + C P z_c2,
-// with Af = A M_A^-1 and Cf = C M_A^-1 the folded blocks.
+//   w_u = Af t + B z_p + A P z_c2,  w_p = v_p,
+// with Af = A M_A^-1 and Cf = C M_A^-1 the folded blocks: the factorisation
+// M differs from J only in its displacement block (Ah for A), so the
+// pressure rows of J M^-1 are those of the identity.
 //
 // Front layout: row-major f x f; the first k rows / columns are the node's
 // own DOFs.  After the elimination a front holds
@@ -456,30 +458,53 @@ __global__ __launch_bounds__(kCT) void k_bwdm(CoarseK ck, int lev, const double 
 // ---------------------------------------------------------------------------
 // Kernels of one preconditioned product (precision T)
 // ---------------------------------------------------------------------------
-// rc = P^T v_u (minus P^T B z_p when zp != null): thread per (class, component)
+// P_e^T v_e per vertex copy: cpy[(e*nv + v)*dim + i] (thread per entry)
 template <typename T>
-__global__ __launch_bounds__(kCT) void k_restrict(KParams kp, CoarseK ck, const T *__restrict__ v,
-                                                  const T *__restrict__ Bs, const T *__restrict__ zp,
-                                                  const T *__restrict__ base, T *__restrict__ rc) {
-  const int dim = ck.dim, nv = ck.nv, bu = kp.s.bu, nn = ck.nn;
+__global__ __launch_bounds__(kCT) void k_restrict_copies(KParams kp, CoarseK ck, const T *__restrict__ v,
+                                                         T *__restrict__ cpy) {
+  const int dim = ck.dim, nv = ck.nv, nn = ck.nn;
+  const int64_t t = blockIdx.x * (int64_t)kCT + threadIdx.x;
+  if (t >= kp.s.ne * nv * dim) return;
+  const int64_t e = t / (nv * dim);
+  const int vv = (int)(t / dim % nv), i = (int)(t % dim);
+  double acc = 0.0;
+  for (int w = 0; w < ck.nw[vv]; ++w) {
+    const int a = ck.wn[vv][w];
+    if (!clamped(kp.m.clamp, e, a * dim + i)) acc += ck.ww[vv][w] * (double)v[(e * nn + a) * dim + i];
+  }
+  cpy[t] = (T)acc;
+}
+
+// rc = sum over the copies of each class (thread per (class, component))
+template <typename T>
+__global__ __launch_bounds__(kCT) void k_restrict_gather(CoarseK ck, const T *__restrict__ cpy, T *__restrict__ rc) {
+  const int dim = ck.dim;
   const int64_t t = blockIdx.x * (int64_t)kCT + threadIdx.x;
   if (t >= (int64_t)ck.ncls * dim) return;
   const int32_t c = (int32_t)(t / dim);
   const int i = (int)(t % dim);
   double acc = 0.0;
-  for (int32_t q = ck.rc_ptr[c]; q < ck.rc_ptr[c + 1]; ++q) {
-    const int64_t e = ck.rc_list[q] / nv;
-    const int vv = ck.rc_list[q] % nv;
-    for (int w = 0; w < ck.nw[vv]; ++w) {
-      const int a = ck.wn[vv][w];
-      if (clamped(kp.m.clamp, e, a * dim + i)) continue;
-      if (v) acc += ck.ww[vv][w] * (double)v[(e * nn + a) * dim + i];
-      if (zp)
-        for (int64_t s = kp.m.sp_ptr[e]; s < kp.m.sp_ptr[e + 1]; ++s)
-          acc -= ck.ww[vv][w] * (double)Bs[s * bu + a * dim + i] * (double)zp[kp.m.sp_pnode[s]];
-    }
-  }
-  rc[t] = (T)((base ? (double)base[t] : 0.0) + acc);
+  for (int32_t q = ck.rc_ptr[c]; q < ck.rc_ptr[c + 1]; ++q) acc += (double)cpy[(int64_t)ck.rc_list[q] * dim + i];
+  rc[t] = (T)acc;
+}
+
+// z_c2 = z_c1 - Z_c z_p (Z_c row-major, nrhs columns: the pressure nodes of
+// the row's instance); one wavefront per coarse DOF
+template <typename T>
+__global__ __launch_bounds__(kCT) void k_zc2(KParams kp, CoarseK ck, const T *__restrict__ Z, int nrhs,
+                                             const T *__restrict__ zc1, const T *__restrict__ zp,
+                                             T *__restrict__ zc2) {
+  const int64_t r = blockIdx.x * (int64_t)(kCT / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (r >= (int64_t)ck.ncls * ck.dim) return;
+  const int b = ck.cinst[r / ck.dim];
+  const int32_t p0 = kp.poff[b], np = kp.poff[b + 1] - p0;
+  const T *row = Z + r * nrhs;
+  double acc = 0.0;
+  for (int j = lane; j < np; j += 64) acc += (double)row[j] * (double)zp[p0 + j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) zc2[r] = (T)((double)zc1[r] - acc);
 }
 
 // pressure rows of the first half: q'_i = v_p,i - (Cf v_u + W z_c1)_i
@@ -487,7 +512,7 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_tl_q(KParams kp, CoarseK ck, const T *__restrict__ Cf,
                                              const T *__restrict__ W, const T *__restrict__ vu,
                                              const T *__restrict__ vp, const T *__restrict__ zc,
-                                             T *__restrict__ qout) {
+                                             T *__restrict__ qout, T *__restrict__ wp) {
   const int64_t i = blockIdx.x;
   const int lane = threadIdx.x, bu = kp.s.bu, dim = ck.dim;
   double acc = 0.0;
@@ -503,7 +528,10 @@ __global__ __launch_bounds__(64) void k_tl_q(KParams kp, CoarseK ck, const T *__
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) qout[i] = (T)((double)vp[i] - acc);
+  if (lane == 0) {
+    qout[i] = (T)((double)vp[i] - acc);
+    if (wp) wp[i] = vp[i];
+  }
 }
 
 // t = v_u - B z_p - AP z_c2 and apz = AP z_c2: thread per (element, row)
@@ -528,43 +556,6 @@ __global__ __launch_bounds__(kCT) void k_tl_t(KParams kp, CoarseK ck, const T *_
     bz += (double)Bs[s * bu + r] * (double)zp[kp.m.sp_pnode[s]];
   apz[t] = (T)acc;
   t_out[t] = (T)((double)vu[t] - bz - acc);
-}
-
-// pressure rows of the product: w_p = Cf t + D z_p + C P z_c2 (one wave per row)
-template <typename T>
-__global__ __launch_bounds__(64) void k_tl_prows(KParams kp, CoarseK ck, const T *__restrict__ Cf,
-                                                 const T *__restrict__ Cs, const T *__restrict__ D,
-                                                 const T *__restrict__ tu, const T *__restrict__ zp,
-                                                 const T *__restrict__ zc, T *__restrict__ wp) {
-  const int64_t i = blockIdx.x;
-  const int lane = threadIdx.x, bu = kp.s.bu, dim = ck.dim, nv = ck.nv;
-  double acc = 0.0;
-  for (int32_t c = kp.m.pc_ptr[i]; c < kp.m.pc_ptr[i + 1]; ++c) {
-    const int32_t ent = kp.m.pc_ent[c];
-    const int64_t e = kp.m.sp_elem[ent];
-    if (lane < bu) {
-      acc += (double)Cf[(int64_t)ent * bu + lane] * (double)tu[e * bu + lane];
-      // (C P z_c2): row lane = (a, comp) of the element gets the P1 value
-      const int a = lane / dim, comp = lane % dim;
-      if (!clamped(kp.m.clamp, e, lane)) {
-        double pz = 0.0;
-        for (int v = 0; v < nv; ++v) {
-          const int32_t cl = ck.cls_of[e * nv + v];
-          if (cl < 0) continue;
-          for (int w = 0; w < ck.nw[v]; ++w)
-            if (ck.wn[v][w] == a) pz += ck.ww[v][w] * (double)zc[(int64_t)cl * dim + comp];
-        }
-        acc += (double)Cs[(int64_t)ent * bu + lane] * pz;
-      }
-    }
-  }
-  const int b = kp.pinst[i];
-  const int64_t p0 = kp.poff[b], nb = kp.poff[b + 1] - p0;
-  const T *Drow = D + kp.doff[b] + (i - p0) * nb;
-  for (int64_t j = lane; j < nb; j += 64) acc += (double)Drow[j] * (double)zp[p0 + j];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) wp[i] = (T)acc;
 }
 
 // y_p = S x_p with the dense pressure block of each instance (one wave per row)
@@ -706,29 +697,42 @@ template hipError_t coarse_solve1<float>(const CoarseK &, const CoarseHostView &
                                          float *, float *, float *, hipStream_t);
 
 template <typename T>
-hipError_t coarse_restrict(const KParams &kp, const CoarseK &ck, const T *v, const T *Bs, const T *zp,
-                           const T *base, T *rc, hipStream_t st) {
-  if (!ck.ncls) return hipSuccess;
-  hipLaunchKernelGGL((k_restrict<T>), dim3(nblk((int64_t)ck.ncls * ck.dim)), dim3(kCT), 0, st, kp, ck, v, Bs, zp,
-                     base, rc);
-  return hipGetLastError();
-}
-template hipError_t coarse_restrict<double>(const KParams &, const CoarseK &, const double *, const double *,
-                                            const double *, const double *, double *, hipStream_t);
-template hipError_t coarse_restrict<float>(const KParams &, const CoarseK &, const float *, const float *,
-                                           const float *, const float *, float *, hipStream_t);
-
-template <typename T>
 hipError_t coarse_q(const KParams &kp, const CoarseK &ck, const T *Cf, const T *W, const T *vu, const T *vp,
-                    const T *zc, T *qout, hipStream_t st) {
+                    const T *zc, T *qout, T *wp, hipStream_t st) {
   if (!kp.s.n_p) return hipSuccess;
-  hipLaunchKernelGGL((k_tl_q<T>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp, ck, Cf, W, vu, vp, zc, qout);
+  hipLaunchKernelGGL((k_tl_q<T>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp, ck, Cf, W, vu, vp, zc, qout, wp);
   return hipGetLastError();
 }
 template hipError_t coarse_q<double>(const KParams &, const CoarseK &, const double *, const double *,
-                                     const double *, const double *, const double *, double *, hipStream_t);
+                                     const double *, const double *, const double *, double *, double *,
+                                     hipStream_t);
 template hipError_t coarse_q<float>(const KParams &, const CoarseK &, const float *, const float *, const float *,
-                                    const float *, const float *, float *, hipStream_t);
+                                    const float *, const float *, float *, float *, hipStream_t);
+
+template <typename T>
+hipError_t coarse_restrict2(const KParams &kp, const CoarseK &ck, const T *v, T *cpy, T *rc, hipStream_t st) {
+  if (!ck.ncls) return hipSuccess;
+  hipLaunchKernelGGL((k_restrict_copies<T>), dim3(nblk(kp.s.ne * ck.nv * ck.dim)), dim3(kCT), 0, st, kp, ck, v, cpy);
+  hipLaunchKernelGGL((k_restrict_gather<T>), dim3(nblk((int64_t)ck.ncls * ck.dim)), dim3(kCT), 0, st, ck, cpy, rc);
+  return hipGetLastError();
+}
+template hipError_t coarse_restrict2<double>(const KParams &, const CoarseK &, const double *, double *, double *,
+                                             hipStream_t);
+template hipError_t coarse_restrict2<float>(const KParams &, const CoarseK &, const float *, float *, float *,
+                                            hipStream_t);
+
+template <typename T>
+hipError_t coarse_zc2(const KParams &kp, const CoarseK &ck, const T *Z, int nrhs, const T *zc1, const T *zp, T *zc2,
+                      hipStream_t st) {
+  if (!ck.ncls) return hipSuccess;
+  hipLaunchKernelGGL((k_zc2<T>), dim3(nblk((int64_t)ck.ncls * ck.dim, kCT / 64)), dim3(kCT), 0, st, kp, ck, Z, nrhs,
+                     zc1, zp, zc2);
+  return hipGetLastError();
+}
+template hipError_t coarse_zc2<double>(const KParams &, const CoarseK &, const double *, int, const double *,
+                                       const double *, double *, hipStream_t);
+template hipError_t coarse_zc2<float>(const KParams &, const CoarseK &, const float *, int, const float *,
+                                      const float *, float *, hipStream_t);
 
 template <typename T>
 hipError_t coarse_t(const KParams &kp, const CoarseK &ck, const T *AP, const T *Bs, const T *vu, const T *zp,
@@ -741,20 +745,6 @@ template hipError_t coarse_t<double>(const KParams &, const CoarseK &, const dou
                                      hipStream_t);
 template hipError_t coarse_t<float>(const KParams &, const CoarseK &, const float *, const float *, const float *,
                                     const float *, const float *, float *, float *, hipStream_t);
-
-template <typename T>
-hipError_t coarse_prows(const KParams &kp, const CoarseK &ck, const T *Cf, const T *Cs, const T *D, const T *tu,
-                        const T *zp, const T *zc, T *wp, hipStream_t st) {
-  if (!kp.s.n_p) return hipSuccess;
-  hipLaunchKernelGGL((k_tl_prows<T>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp, ck, Cf, Cs, D, tu, zp, zc, wp);
-  return hipGetLastError();
-}
-template hipError_t coarse_prows<double>(const KParams &, const CoarseK &, const double *, const double *,
-                                         const double *, const double *, const double *, const double *, double *,
-                                         hipStream_t);
-template hipError_t coarse_prows<float>(const KParams &, const CoarseK &, const float *, const float *,
-                                        const float *, const float *, const float *, const float *, float *,
-                                        hipStream_t);
 
 template <typename T>
 hipError_t coarse_prolong_add(const KParams &kp, const CoarseK &ck, const T *zc, T *zu, hipStream_t st) {
