@@ -325,8 +325,9 @@ hf_status hf_get_pnodes(hf_ctx *ctx, int32_t inst, int64_t *keys);
    the opening of the previous step, source of eq. discreteLubrication;
    nullable = keep).  Rejects non-finite values (HF_ENONFINITE).  Also fixes
    the fluid-row scale s_p = 12 mu (L / w_ref)^3 with L the largest bounding
-   box extent and w_ref = max(max w_old on fluid faces, 0.01 delta_c), per
-   instance.  Instances never given a state start from zero. */
+   box extent and w_ref the largest opening of the start state on the fluid
+   faces' points (of w_old and of u's own opening w(u)), at least 0.01
+   delta_c, per instance.  Instances never given a state start from zero. */
 hf_status hf_set_state(hf_ctx *ctx, int32_t inst, const double *u, const double *p,
                        const double *w_old);
 /* u, p, w (current opening at face points), w_old: each nullable. */
@@ -369,6 +370,30 @@ hf_status hf_newton_step(hf_ctx *ctx, hf_newton_stats *stats);
    (HF_ENOCONV) or failed gets back its state at the start of the call.
    stats[b] per instance (nullable array). */
 hf_status hf_newton_solve(hf_ctx *ctx, hf_newton_stats *stats);
+/* One iteration of the staggered (sequential) comparison scheme of Sec.
+   "Fully-coupled vs. staggered hydro-mechanics with applied inflow boundary
+   conditions": each field is solved from its own equations with the other
+   taken from the previous iteration, the decoupled forms A U = E - B P and
+   D P = F - C U of eq. (fully-coupled-fully-discrete).  First the solid rows
+   with the pressure held, A dU = -R_u(U, P) (same solver and options as
+   hf_solve; one solve for the linear solid, a Newton sub-step where cohesive
+   tractions make it nonlinear), then the fluid rows with the new opening
+   held, D dP = -R_p(U, P) with D = dR_p/dP the Poiseuille flux operator
+   alone: the decoupled fluid equation is elliptic and needs an essential
+   condition, here the row of pressure node dir_node[b] (instance-local
+   index, see hf_get_pnodes) replaced by P[dir_node[b]] = dir_value[b]
+   (dir_value nullable = 0).  dir_node may be null only when no instance has
+   pressure nodes.  The optional cut-off applies to the new pressure.
+   stats[b]: lin = the solid solve, du_rel and dp_rel of the two halves,
+   res_norm = hypot(||R|| at the start with the fluid rows held, ||R|| after
+   the solid half), converged when both relative increments <= newton_tol.
+   An instance whose solid solve fails (its status) or whose modified
+   pressure block is singular (HF_ESINGULAR: a zero or non-finite pivot,
+   e.g. a node whose faces are all closed and conduct nothing) gets back its
+   state from the start of the call.  The assembled system is left modified:
+   assemble again before hf_solve. */
+hf_status hf_staggered_step(hf_ctx *ctx, const int32_t *dir_node, const double *dir_value,
+                            hf_newton_stats *stats);
 /* End of a given-length load step: the opening of the converged state
    becomes the previous opening w^n of the storage term (w - w^n)/dt of eq.
    (discreteLubrication), w_old <- w(u) at every face point, and the
@@ -385,7 +410,9 @@ hf_status hf_end_load_step(hf_ctx *ctx);
    test from uniform pressure and opening, Sec. "Verification of the
    fully-coupled algorithm").  p0_out[b] (nullable array) = p0 of instance b;
    instances without pressure nodes or injection keep their state (p0 = 0);
-   an instance whose predictor fails keeps its state. */
+   an instance whose predictor fails keeps its state.  The fluid-row scale
+   s_p is then recomputed from the predictor's opening (as hf_set_state
+   does). */
 hf_status hf_initial_guess(hf_ctx *ctx, double *p0_out);
 
 /* ---- inspection hooks (tests, benchmarks) ---- */

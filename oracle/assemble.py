@@ -313,11 +313,13 @@ def assemble(mesh: Mesh, itf: Interfaces, prm: Params, u: np.ndarray, p: np.ndar
         v = np.concatenate([t[2] for t in tr])
         return sp.coo_matrix((v, (r, c)), shape=shape).tocsr()
 
-    Bm = coo(Bt, (m.n_u, n_p)).tolil()
-    if n_p:
-        Bm[np.nonzero(cl)[0], :] = 0.0
+    Bm = coo(Bt, (m.n_u, n_p))
+    if n_p:   # Dirichlet rows of B are zero
+        row_of = np.repeat(np.arange(m.n_u), np.diff(Bm.indptr))
+        Bm.data[cl[row_of]] = 0.0
+        Bm.eliminate_zeros()
     sysm.A_diag, sysm.A_mp, sysm.A_pm = A_diag, A_mp, A_pm
-    sysm.B = Bm.tocsr()
+    sysm.B = Bm
     sysm.C = coo(Ct, (n_p, m.n_u))
     sysm.D = coo(Dt, (n_p, n_p))
     return sysm

@@ -66,17 +66,23 @@ def opening(mesh: Mesh, u: np.ndarray) -> np.ndarray:
     return np.einsum("fqi,fi->fq", up - um, m.normal)
 
 
-def fluid_scale(case: Case, w_old: np.ndarray) -> float:
+def fluid_scale(case: Case, w_old: np.ndarray, u: Optional[np.ndarray] = None) -> float:
     """Fluid-row scale s_p = 12 mu (L / w_ref)^3.
 
     A reading of the paper's (unpublished) remark on bringing the fluid
     equations to the units of the solid ones with c^n = 12 mu (L/max w^n)^3:
-    L is the largest bounding-box extent of the mesh and w_ref = max(max
-    w^n over fluid faces, 0.01 delta_c) so that it is defined at w^n = 0.
-    Fixed for a load step."""
+    L is the largest bounding-box extent of the mesh and w_ref is the
+    largest opening of the state a load step starts from, over the fluid
+    faces' points: the larger of w^n and, when the start displacement u is
+    given, its own opening w(u) (the elastic predictor opens the crack
+    before w^n does at the first load step), floored at 0.01 delta_c so that
+    it is defined for a closed crack.  Fixed for a load step."""
     m, itf = case.mesh, case.itf
     L = float(np.max(m.xyz.max(axis=0) - m.xyz.min(axis=0)))
-    wmax = float(np.max(w_old[itf.active_faces])) if len(itf.active_faces) else 0.0
+    fa = itf.active_faces
+    wmax = float(np.max(w_old[fa])) if len(fa) else 0.0
+    if u is not None and len(fa):
+        wmax = max(wmax, float(np.max(opening(m, u)[fa])))
     w_ref = max(wmax, 0.01 * case.prm.delta_c)
     return 12.0 * case.prm.mu * (L / w_ref) ** 3
 
@@ -104,7 +110,8 @@ def initial_state(case: Case, predictor: bool = False) -> State:
     fa = case.itf.active_faces
     V1 = float(np.sum(m.fq_w[None, :] * m.area[fa][:, None] * opening(m, u1)[fa]))
     p0 = q * case.prm.dt / V1
-    return State(u=p0 * u1, p=np.full(case.itf.n_p, p0), w_old=w0, s_p=st.s_p)
+    u0 = p0 * u1
+    return State(u=u0, p=np.full(case.itf.n_p, p0), w_old=w0, s_p=fluid_scale(case, w0, u0))
 
 
 @dataclasses.dataclass
@@ -188,3 +195,41 @@ def run(case: Case, steps: int, predictor: bool = False, **kw):
         st = end_load_step(case, st)
         out.append((st, ns))
     return out
+
+
+def staggered_step(case: Case, state: State, dir_node: int, dir_value: float = 0.0):
+    """One iteration of the staggered (sequential) scheme of Sec. "Fully-coupled
+    vs. staggered hydro-mechanics with applied inflow boundary conditions":
+    each field is solved from its own equation with the other field taken
+    from the previous iteration, i.e. the decoupled forms A U = E - B P and
+    D P = F - C U of the linear system of eq. (fully-coupled-fully-discrete).
+
+    1. Solid: with the pressure held, A dU = -R_u(U, P), U <- U + dU (A is
+       the displacement block, dR_u/dU: one solve for the linear solid; a
+       Newton sub-step where cohesive tractions make it nonlinear).
+    2. Fluid: with the new opening held, D dP = -R_p(U, P), P <- P + dP.
+       D = dR_p/dP is the Poiseuille flux operator alone (the storage term
+       depends on the opening only), so the decoupled fluid equation is
+       elliptic and needs an essential condition: the row of pressure node
+       ``dir_node`` is replaced by P[dir_node] = dir_value.  Faces that
+       are closed (w <= 0: no conductivity) can leave parts of the crack
+       without a fixed pressure; the decoupled block is then singular
+       (numpy.linalg.LinAlgError).
+
+    Returns the new State and the increments (dU, dP)."""
+    import scipy.sparse.linalg as spla
+    from .assemble import bsr_A
+    m = case.mesh
+    S = assemble(m, case.itf, case.prm, state.u, state.p, state.w_old, state.s_p,
+                 case.src_pnode, case.src_q0)
+    du = spla.spsolve(bsr_A(m, S).tocsc(), -S.R_u)
+    u = state.u + du
+    S = assemble(m, case.itf, case.prm, u, state.p, state.w_old, state.s_p,
+                 case.src_pnode, case.src_q0)
+    D = S.D.toarray()
+    r = S.R_p.copy()
+    D[dir_node, :] = 0.0
+    D[dir_node, dir_node] = 1.0
+    r[dir_node] = state.p[dir_node] - dir_value
+    dp = np.linalg.solve(D, -r)
+    return State(u, state.p + dp, state.w_old, state.s_p), du, dp

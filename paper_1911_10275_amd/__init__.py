@@ -31,7 +31,7 @@ EXPORTS = [
     "hf_upload_mesh", "hf_get_faces", "hf_upload_interfaces", "hf_set_material",
     "hf_set_injection", "hf_finalize", "hf_get_sizes", "hf_get_pnodes", "hf_set_state",
     "hf_get_state", "hf_set_state_device", "hf_get_state_device", "hf_assemble", "hf_solve",
-    "hf_newton_step", "hf_newton_solve", "hf_end_load_step", "hf_initial_guess", "hf_get_residual",
+    "hf_newton_step", "hf_newton_solve", "hf_staggered_step", "hf_end_load_step", "hf_initial_guess", "hf_get_residual",
     "hf_get_block_rows", "hf_get_coupling", "hf_get_increment", "hf_apply_jacobian",
     "hf_get_profile", "hf_reset_profile", "hf_get_tuning", "hf_set_tuning", "hf_autotune",
     "hf_get_block_inverse", "hf_apply_preconditioned", "hf_apply_preconditioned_noalloc",
@@ -146,6 +146,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hf_solve": (C.c_int, [vp, P(SolveStats)]),
         "hf_newton_step": (C.c_int, [vp, P(NewtonStats)]),
         "hf_newton_solve": (C.c_int, [vp, P(NewtonStats)]),
+        "hf_staggered_step": (C.c_int, [vp, P(C.c_int32), P(C.c_double), P(NewtonStats)]),
         "hf_end_load_step": (C.c_int, [vp]),
         "hf_initial_guess": (C.c_int, [vp, P(C.c_double)]),
         "hf_get_residual": (C.c_int, [vp, C.c_int32, vp, vp]),
@@ -350,6 +351,23 @@ class Context:
         rc = self.lib.hf_newton_solve(self.h, st)
         if check:
             self._check(rc, "hf_newton_solve")
+        return self._one(list(st))
+
+    def staggered_step(self, dir_node, dir_value=None, check=True):
+        """One iteration of the staggered comparison scheme; dir_node /
+        dir_value: the essential pressure condition of each instance
+        (instance-local pressure-node index and value; scalars for one
+        instance)."""
+        node = np.ascontiguousarray(np.atleast_1d(dir_node), dtype=np.int32)
+        val = None if dir_value is None else np.ascontiguousarray(np.atleast_1d(dir_value), dtype=np.float64)
+        if len(node) != self.n_inst or (val is not None and len(val) != self.n_inst):
+            raise ValueError("one dir_node (and dir_value) per instance")
+        st = (NewtonStats * self.n_inst)()
+        rc = self.lib.hf_staggered_step(self.h, node.ctypes.data_as(C.POINTER(C.c_int32)),
+                                        None if val is None else val.ctypes.data_as(C.POINTER(C.c_double)),
+                                        st)
+        if check:
+            self._check(rc, "hf_staggered_step")
         return self._one(list(st))
 
     def end_load_step(self):

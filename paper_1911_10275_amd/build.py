@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhf.so")
 SOURCES = ["hf_api.cpp", "hf_rules.cpp", "hf_coarse.cpp", "hf_kernels_assemble.hip", "hf_kernels_linalg.hip",
-           "hf_kernels_spmv.hip", "hf_kernels_krylov.hip", "hf_kernels_coarse.hip"]
+           "hf_kernels_spmv.hip", "hf_kernels_krylov.hip", "hf_kernels_coarse.hip",
+           "hf_kernels_staggered.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -134,6 +134,9 @@ struct hf_ctx {
   // scratch of the grid-wide pressure-block inverse
   double *gj_colk = nullptr, *gj_piv = nullptr;
   int *gj_perm = nullptr;
+  // essential pressure condition of the staggered iteration, per instance
+  int32_t *stag_node = nullptr;
+  double *stag_val = nullptr;
   int *flag = nullptr;
   double *dx = nullptr, *rhs = nullptr, *r64 = nullptr, *t64 = nullptr;
   KrylovWs<double> k64;
@@ -1257,17 +1260,22 @@ static hf_status copy_inst(hf_ctx *ctx, double *dst, double *src, int b) {
   return HF_OK;
 }
 
-// fluid-row scale of every instance from its w_old
+// fluid-row scale of every instance from the state a load step starts from:
+// w_ref = the largest opening over the fluid faces' points of w_old and of the
+// current displacement's own opening w(u), floored at 0.01 delta_c
 static hf_status update_fluid_scale(hf_ctx *ctx) {
   const int B = nI(ctx);
   if (ctx->s.n_act) {
-    HIPCHK(launch_wmax(kparams(ctx), ctx->w_old, ctx->red, ctx->stream));
-    TRY(get_d(ctx, ctx->red, B));
+    const KParams kp = kparams(ctx);
+    HIPCHK(launch_opening(kp, ctx->xs, ctx->w_tmp, ctx->stream));
+    HIPCHK(launch_wmax(kp, ctx->w_old, ctx->red, ctx->stream));
+    HIPCHK(launch_wmax(kp, ctx->w_tmp, ctx->red + B, ctx->stream));
+    TRY(get_d(ctx, ctx->red, 2 * (int64_t)B));
   }
   for (int b = 0; b < B; ++b) {
     const Mat &m = ctx->inst[b].mat;
     const double delta_c = 2.0 * m.G_c / m.sigma_c;
-    const double wmax = ctx->inst[b].n_act ? ctx->hd[b] : -1e300;
+    const double wmax = ctx->inst[b].n_act ? std::max(ctx->hd[b], ctx->hd[B + b]) : -1e300;
     const double w_ref = std::max(wmax, 0.01 * delta_c);
     ctx->ipar[b].s_p = 12.0 * m.mu * std::pow(ctx->inst[b].bbox_L / w_ref, 3);
   }
@@ -2594,6 +2602,150 @@ extern "C" hf_status hf_newton_step(hf_ctx *ctx, hf_newton_stats *stats) {
   return newton_status(ctx, ns);
 }
 
+// ===========================================================================
+// Staggered iteration (comparison solver)
+// ===========================================================================
+// One iteration of the sequential scheme: the solid rows with the pressure
+// held (the fluid rows become identity rows with zero residual, so the solve
+// gives A dU = -R_u and dP = 0), then the fluid rows with the new opening
+// held, D dP = -R_p with row node[b] replaced by the essential condition,
+// solved with the dense inverse of the modified pressure block.  An instance
+// whose solid solve fails or whose modified block is singular gets back its
+// state from the start of the iteration.
+static hf_status do_staggered_step(hf_ctx *ctx, const std::vector<int32_t> &node,
+                                   const std::vector<double> &val, std::vector<hf_newton_stats> &ns) {
+  const Sizes &s = ctx->s;
+  const int B = nI(ctx);
+  ns.assign(B, hf_newton_stats{});
+  HIPCHK(hipMemcpyAsync(ctx->xs_start, ctx->xs, s.N() * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  // solid half
+  std::vector<double> rn1, rn2;
+  std::vector<int> act(B, 1);
+  std::vector<hf_solve_stats> ls;
+  ctx->freeze_p = 1;
+  hf_status st = do_assemble(ctx, rn1);
+  if (st == HF_OK) {
+    for (int b = 0; b < B; ++b)
+      if (!std::isfinite(rn1[b])) {
+        act[b] = 0;
+        ns[b].status = HF_ENONFINITE;
+        note(ctx, b, "non-finite residual");
+      }
+    st = do_solve(ctx, act, ls);
+  }
+  ctx->freeze_p = 0;
+  TRY(st);
+  std::vector<int> upd(B, 0);
+  for (int b = 0; b < B; ++b) {
+    ns[b].lin = ls[b];
+    if (act[b]) ns[b].status = ls[b].status;
+    upd[b] = act[b] && ls[b].status == HF_OK;
+  }
+  if (s.n_p) HIPCHK(launch_fill(0.0, ctx->dx + s.n_u, s.n_p, ctx->stream));
+  TRY(put(ctx, ctx->k_upd, upd));
+  HIPCHK(launch_snewton_update(ctx->kd, ctx->dx, ctx->xs, s.n_u, ctx->k_upd, 0, 0.0, ctx->partial, ctx->red,
+                               ctx->stream));
+  TRY(get_d(ctx, ctx->red, 4 * B));
+  std::vector<double> du(B, 0.0), un(B, 0.0);
+  for (int b = 0; b < B; ++b) {
+    du[b] = std::sqrt(ctx->hd[4 * b]);
+    un[b] = std::sqrt(ctx->hd[4 * b + 1]);
+  }
+  // fluid half
+  TRY(do_assemble(ctx, rn2));
+  std::vector<int> upd2(upd);
+  if (s.n_p) {
+    if (!ctx->stag_node) {
+      TRY(dalloc(ctx, &ctx->stag_node, B));
+      TRY(dalloc(ctx, &ctx->stag_val, B));
+    }
+    TRY(put(ctx, ctx->stag_node, node));
+    TRY(put(ctx, ctx->stag_val, val));
+    const KParams kp = kparams(ctx);
+    HIPCHK(hipMemcpyAsync(ctx->S, ctx->D, ctx->doff[B] * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(launch_stag_dirichlet(kp, ctx->stag_node, ctx->stag_val, ctx->xs + s.n_u, ctx->S, ctx->R + s.n_u,
+                                 ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->flag, 0, B * sizeof(int), ctx->stream));
+    const int n_wide = ctx->tune.dense_wide_min > 0 ? ctx->tune.dense_wide_min : kDenseWideMin;
+    HIPCHK(launch_schur_invert(kp, ctx->S, ctx->Sinv, ctx->Sinv32, ctx->flag, n_wide, ctx->stream));
+    for (int b = 0; b < B; ++b) {
+      const int nb = ctx->poff[b + 1] - ctx->poff[b];
+      if (nb < n_wide) continue;
+      if (!ctx->gj_colk) {
+        TRY(dalloc(ctx, &ctx->gj_colk, kMaxPressureBlock));
+        TRY(dalloc(ctx, &ctx->gj_perm, kMaxPressureBlock));
+        TRY(dalloc(ctx, &ctx->gj_piv, 1));
+      }
+      HIPCHK(launch_dense_inv_wide(ctx->S + ctx->doff[b], ctx->Sinv + ctx->doff[b], ctx->Sinv32 + ctx->doff[b],
+                                   nb, ctx->flag + b, ctx->gj_colk, ctx->gj_perm, ctx->gj_piv, ctx->stream));
+    }
+    HIPCHK(launch_fill(0.0, ctx->dx, s.n_u, ctx->stream));
+    HIPCHK(launch_stag_dp(kp, ctx->Sinv, ctx->R + s.n_u, ctx->dx + s.n_u, ctx->stream));
+    TRY(get_i_async(ctx, ctx->flag, B, 0));
+    TRY(sync(ctx));
+    for (int b = 0; b < B; ++b)
+      if (upd2[b] && ctx->hi[b]) {
+        upd2[b] = 0;
+        ns[b].status = HF_ESINGULAR;
+        note(ctx, b, "decoupled fluid block is singular (zero or non-finite pivot)");
+      }
+    TRY(put(ctx, ctx->k_upd, upd2));
+    HIPCHK(launch_snewton_update(ctx->kd, ctx->dx, ctx->xs, s.n_u, ctx->k_upd, ctx->opt.cutoff_on,
+                                 ctx->opt.p_cutoff, ctx->partial, ctx->red, ctx->stream));
+    TRY(get_d(ctx, ctx->red, 4 * B));
+  } else {
+    std::fill(ctx->hd, ctx->hd + 4 * B, 0.0);
+  }
+  for (int b = 0; b < B; ++b) {
+    ns[b].res_norm = std::hypot(rn1[b], rn2[b]);
+    if (upd[b] && !upd2[b]) TRY(copy_inst(ctx, ctx->xs, ctx->xs_start, b));
+    if (!upd2[b]) continue;
+    const double dp = std::sqrt(ctx->hd[4 * b + 2]), pn = std::sqrt(ctx->hd[4 * b + 3]);
+    if (!std::isfinite(du[b]) || !std::isfinite(un[b]) || !std::isfinite(dp) || !std::isfinite(pn)) {
+      TRY(copy_inst(ctx, ctx->xs, ctx->xs_start, b));
+      ns[b].status = HF_ENONFINITE;
+      note(ctx, b, "non-finite staggered update");
+      continue;
+    }
+    const double ru = un[b] > 0.0 ? du[b] / un[b] : du[b];
+    const double rp = ctx->inst[b].n_p ? (pn > 0.0 ? dp / pn : dp) : 0.0;
+    ns[b].du_rel = ru;
+    ns[b].dp_rel = rp;
+    ns[b].iterations = 1;
+    ns[b].converged = (ru <= ctx->opt.newton_tol && rp <= ctx->opt.newton_tol) ? 1 : 0;
+  }
+  TRY(sync(ctx));
+  ctx->stage = 3;  // the assembled fluid rows were modified: assemble again before a solve
+  return HF_OK;
+}
+
+extern "C" hf_status hf_staggered_step(hf_ctx *ctx, const int32_t *dir_node, const double *dir_value,
+                                       hf_newton_stats *stats) {
+  TRY(check_ctx(ctx, 3));
+  ctx->ierr.clear();
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  const int B = nI(ctx);
+  std::vector<int32_t> node(B, 0);
+  std::vector<double> val(B, 0.0);
+  for (int b = 0; b < B; ++b) {
+    const int64_t np = ctx->inst[b].n_p;
+    if (!np) continue;
+    if (!dir_node) return fail(ctx, HF_EINVAL, "dir_node is required when an instance has pressure nodes");
+    if (dir_node[b] < 0 || dir_node[b] >= np)
+      return fail(ctx, HF_EINVAL, "instance " + std::to_string(b) + ": dir_node out of range");
+    node[b] = dir_node[b];
+    if (dir_value) {
+      if (!std::isfinite(dir_value[b]))
+        return fail(ctx, HF_ENONFINITE, "instance " + std::to_string(b) + ": non-finite dir_value");
+      val[b] = dir_value[b];
+    }
+  }
+  std::vector<hf_newton_stats> ns;
+  TRY(do_staggered_step(ctx, node, val, ns));
+  if (stats) std::copy(ns.begin(), ns.end(), stats);
+  return newton_status(ctx, ns);
+}
+
 extern "C" hf_status hf_newton_solve(hf_ctx *ctx, hf_newton_stats *stats) {
   TRY(check_ctx(ctx, 3));
   ctx->ierr.clear();
@@ -2711,6 +2863,7 @@ extern "C" hf_status hf_initial_guess(hf_ctx *ctx, double *p0_out) {
   }
   for (int b = 0; b < B; ++b)
     if (fst[b] != HF_OK) TRY(copy_inst(ctx, ctx->xs, ctx->xs_save, b));  // keep the old state
+  TRY(update_fluid_scale(ctx));  // the predictor's opening sets the first load step's scale
   TRY(sync(ctx));
   if (p0_out) std::copy(p0.begin(), p0.end(), p0_out);
   ctx->stage = 3;

@@ -317,6 +317,13 @@ hipError_t launch_schur_invert(const KParams &kp, double *S, double *Sinv, float
 hipError_t launch_dense_inv_wide(double *W, double *out, float *out32, int n, int *flag, double *colk, int *perm,
                                  double *piv, hipStream_t st);
 hipError_t launch_convert(const double *in, float *out, int64_t n, hipStream_t st);
+// staggered iteration, fluid half: row node[b] of instance b's pressure block
+// W (a copy of D) becomes the identity row, R_p[node] = p[node] - value[b]
+hipError_t launch_stag_dirichlet(const KParams &kp, const int32_t *node, const double *value,
+                                 const double *p, double *W, double *Rp, hipStream_t st);
+// dp = -Winv R_p per instance (Winv: the inverted pressure blocks)
+hipError_t launch_stag_dp(const KParams &kp, const double *Winv, const double *Rp, double *dp,
+                          hipStream_t st);
 // y = J x (rows outside sel are left untouched)
 template <typename T>
 hipError_t launch_spmv(const KParams &kp, const T *A, const T *Bs, const T *Cs, const T *D,

@@ -101,7 +101,7 @@ def test_concurrent_contexts_match_oracle():
         rec, ns, (u, p, _, wo) = out[name]
         for k, ru, rp, cols, blocks, (B, Cm, D) in rec:
             us, ps, wos = _state(case, 100 + k)
-            S = asm.assemble(m, case.itf, case.prm, us, ps, wos, newton.fluid_scale(case, wos),
+            S = asm.assemble(m, case.itf, case.prm, us, ps, wos, newton.fluid_scale(case, wos, us),
                              case.src_pnode, case.src_q0)
             assert _rel(ru, S.R_u) < 1e-12, (name, k)
             assert _rel(rp, S.R_p) < 1e-12, (name, k)

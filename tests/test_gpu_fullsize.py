@@ -1,8 +1,11 @@
 """Parity at the full size of the 3D penny workload (48,000 P2 tetrahedra,
-1.44M displacement DOF) and of the three-disk multi-crack workload (196,608
-P2 tetrahedra, 5.9M displacement DOF, 948 pressure nodes), in the launch
-configuration the benchmark times (one context on the caller's torch stream,
-GMRES(60), graph-replayed iterations of the folded operator).
+1.44M displacement DOF), of its precision form (384,000 P2 tetrahedra,
+11.52M displacement DOF, viscosity-dominated parameters) and of the
+three-disk multi-crack workload (196,608 P2 tetrahedra, 5.9M displacement
+DOF, 948 pressure nodes), in the launch configuration the benchmark times
+(one context on the caller's torch stream, GMRES(60), graph-replayed
+iterations; the two pennies with the two-level preconditioner, the
+multi-crack with block-Jacobi).
 
 The oracle cannot assemble or solve the whole system in test time, so it
 checks sampled outputs it computes one by one: the residual rows, the
@@ -33,7 +36,7 @@ hf = pytest.importorskip("paper_1911_10275_amd")
 torch = pytest.importorskip("torch")
 
 
-@pytest.fixture(scope="module", params=[2, 5], ids=["penny48k", "multicrack197k"])
+@pytest.fixture(scope="module", params=[2, 3, 5], ids=["penny48k", "penny384k", "multicrack197k"])
 def penny(request):
     prob = synth.config(request.param)
     case = Case.from_problem(prob)
@@ -44,13 +47,14 @@ def penny(request):
     F = np.nonzero(np.isin(m.face_em, E) | np.isin(m.face_ep, E))[0]
     F = np.unique(np.concatenate([F, fa]))
     stream = torch.cuda.current_stream().cuda_stream
-    ctx = hf.context_for_problem(prob, device=0, stream=stream, gmres_m=60)
+    ctx = hf.context_for_problem(prob, device=0, stream=stream, gmres_m=60,
+                                 two_level=1 if request.param in (2, 3) else 0)
     yield prob, case, ctx, E, F
     ctx.close()
 
 
 def _oracle(case, E, F, u, p, w_old):
-    s_p = newton.fluid_scale(case, w_old)
+    s_p = newton.fluid_scale(case, w_old, u)
     return asm.assemble(case.mesh, case.itf, case.prm, u, p, w_old, s_p, case.src_pnode,
                         case.src_q0, faces=F, elements=E)
 
@@ -171,3 +175,65 @@ def test_fullsize_predictor_state_solve(penny, precision):
     st = ctx.solve()
     assert st.status == hf.HF_OK and st.true_relres <= 1e-10
     _check_solve(ctx, case, E, S)
+
+
+def _crack_volume(case, w):
+    m = case.mesh
+    fa = case.itf.active_faces
+    return float(np.sum(m.fq_w[None, :] * m.area[fa][:, None] * w[fa]))
+
+
+def test_fullsize_load_steps(penny):
+    """The first two load steps from the predictor, in FP64 and in FP32-IR:
+    every Newton iteration's solve reaches the true relative residual 1e-10
+    and Newton converges; both precisions end at the same states (1e-8);
+    the crack holds the injected volume, sum Q0 n dt after load step n
+    (1e-8: summing the fluid rows over all pressure nodes cancels the flux
+    terms, since the test functions sum to one, and leaves the global
+    balance of stored and injected volume); and at each converged state the
+    oracle's residual on the sampled displacement rows and on every pressure
+    row vanishes to 1e-9 of the size of its terms, sum_j |J_ij x_j|."""
+    prob, case, ctx, E, F = penny
+    if prob.name.startswith("multicrack"):
+        pytest.skip("Newton from the predictor does not converge on the three-disk workload: "
+                    "pressures at nodes whose faces' opening changes sign cycle")
+    m = case.mesh
+    q = float(np.sum(case.src_q0)) * prob.material.dt
+    finals = {}
+    for precision in (hf.HF_FP64, hf.HF_FP32_IR):
+        ctx.set_options(precision=precision)
+        st0 = newton.initial_state(case)
+        ctx.set_state(st0.u, st0.p, st0.w_old)
+        ctx.initial_guess()
+        states = []
+        for n in (1, 2):
+            its = 0
+            for _ in range(25):
+                ns = ctx.newton_step(check=False)
+                assert ns.status == hf.HF_OK and ns.lin.true_relres <= 1e-10, (precision, n, its)
+                its += 1
+                if ns.converged:
+                    break
+            assert ns.converged, (precision, n)
+            u, p, w, wo = ctx.get_state()
+            assert _crack_volume(case, w) == pytest.approx(n * q, rel=1e-8)
+            if precision == hf.HF_FP64:
+                S = _oracle(case, E, F, u, p, wo)
+                ctx.assemble()
+                cols, _ = ctx.block_rows(E)
+                ref = {}
+                for f in F:
+                    ref[(m.face_em[f], m.face_ep[f])] = S.A_mp[f]
+                    ref[(m.face_ep[f], m.face_em[f])] = S.A_pm[f]
+                mag_u, mag_p = _term_size(case, E, S, ref, cols, u, p)
+                rows = (E[:, None] * m.bu + np.arange(m.bu)[None, :]).reshape(-1)
+                assert np.all(np.abs(S.R_u[rows]) <= 1e-9 * mag_u.max())
+                assert np.all(np.abs(S.R_p) <= 1e-9 * mag_p.max())
+            print(f"{prob.name} precision {precision} load step {n}: {its} Newton iterations",
+                  flush=True)
+            states.append((u, p))
+            ctx.end_load_step()
+        finals[precision] = states
+    for (u64, p64), (u32, p32) in zip(finals[hf.HF_FP64], finals[hf.HF_FP32_IR]):
+        assert np.linalg.norm(u32 - u64) <= 1e-8 * np.linalg.norm(u64)
+        assert np.linalg.norm(p32 - p64) <= 1e-8 * np.linalg.norm(p64)

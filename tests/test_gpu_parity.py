@@ -116,7 +116,7 @@ def _check_assembly_at(case, ctx, seed):
     u, p, wo = _random_state(case, seed) if isinstance(seed, int) else seed
     ctx.set_state(u, p, wo)
     rn = ctx.assemble()
-    s_p = newton.fluid_scale(case, wo)
+    s_p = newton.fluid_scale(case, wo, u)
     S = asm.assemble(m, case.itf, case.prm, u, p, wo, s_p, case.src_pnode, case.src_q0)
     ru, rp = ctx.residual()
     assert _rel(ru, S.R_u) < 1e-12
@@ -156,7 +156,7 @@ def test_jacobian_product_parity(name):
     u, p, wo = _random_state(case, 4)
     ctx.set_state(u, p, wo)
     ctx.assemble()
-    S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo),
+    S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo, u),
                      case.src_pnode, case.src_q0)
     op = solve.Operator(case.mesh, S)
     rng = np.random.default_rng(5)
@@ -249,7 +249,7 @@ def test_dense_inverse_wide_path(name):
         ys.append(yd.cpu().numpy())
     ctx.close()
     assert _rel(ys[1], ys[0]) < 1e-13
-    S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo),
+    S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo, u),
                      case.src_pnode, case.src_q0)
     ref = solve.Operator(case.mesh, S)(solve.BlockJacobi(case.mesh, S)(x))
     assert _rel(ys[1], ref) < 1e-10
@@ -356,7 +356,7 @@ def test_folded_operator(name):
         a, b = y1.double().cpu().numpy(), y0.double().cpu().numpy()
         assert _rel(a, b) < tol
         if precision == hf.HF_FP64:
-            S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo),
+            S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo, u),
                              case.src_pnode, case.src_q0)
             ref = solve.Operator(case.mesh, S)(solve.BlockJacobi(case.mesh, S)(x))
             assert _rel(a, ref) < 1e-10
@@ -377,6 +377,12 @@ def test_predictor_and_load_steps_parity(name):
     assert p0 == pytest.approx(ref0.p[0], rel=1e-8)
     np.testing.assert_allclose(p, ref0.p, rtol=1e-8)
     assert np.linalg.norm(u - ref0.u) <= 1e-7 * np.linalg.norm(ref0.u)
+    # the fluid rows carry the scale of the predictor's opening
+    ctx.assemble()
+    _, rp = ctx.residual()
+    S = asm.assemble(case.mesh, case.itf, case.prm, ref0.u, ref0.p, ref0.w_old, ref0.s_p,
+                     case.src_pnode, case.src_q0)
+    assert np.linalg.norm(rp - S.R_p) <= 1e-6 * np.linalg.norm(S.R_p)
     ref = newton.run(case, prob.load_steps, predictor=True)
     got = _gpu_run(ctx, case, prob.load_steps, hf.HF_FP64, predictor=True)
     for (st, _), ((u, p, w, wo), ns) in zip(ref, got):
@@ -542,7 +548,7 @@ def test_per_block_residuals(name, precision):
     comb = np.hypot(st.relres_u * bu, st.relres_p * bp) / np.hypot(bu, bp)
     assert comb == pytest.approx(st.true_relres, rel=1e-6)
     du, dp = ctx.increment()
-    S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo),
+    S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo, u),
                      case.src_pnode, case.src_q0)
     J = asm.full_matrix(case.mesh, S)
     r = -S.R - J @ np.concatenate([du, dp])

@@ -124,7 +124,7 @@ def test_two_level_operator_matches_dense_reference(name, leaf):
     assert st.status == hf.HF_OK and st.true_relres <= 1e-10
     prof = ctx.profile()
     assert prof.n_tl_builds == 1 and prof.n_tl_fail == 0
-    S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo),
+    S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo, u),
                      case.src_pnode, case.src_q0)
     n = ctx.sizes.n_total
     x = np.random.default_rng(2).normal(size=n)

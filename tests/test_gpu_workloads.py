@@ -50,6 +50,39 @@ def test_kgd2048_predictor_and_first_load_step():
     assert _close(wo[fa], st.w_old[fa])
 
 
+def test_kgd2048_all_load_steps():
+    """All 10 load steps of the 2D KGD workload from the predictor (FP64,
+    block-Jacobi): each converges with every solve at 1e-10; the crack holds
+    the injected volume, n Q0 dt after load step n (1e-8); and each converged
+    state is a root of the oracle's discrete equations: the oracle's residual
+    there is at most 1e-9 of the size of its terms, sum_j |J_ij x_j| over
+    the whole system."""
+    from oracle import assemble as asm
+    prob = synth.config(1)
+    case = Case.from_problem(prob)
+    m = case.mesh
+    fa = case.itf.active_faces
+    q = float(np.sum(case.src_q0)) * prob.material.dt
+    ctx = hf.context_for_problem(prob)
+    st0 = newton.initial_state(case)
+    ctx.set_state(st0.u, st0.p, st0.w_old)
+    ctx.initial_guess()
+    for n in range(1, prob.load_steps + 1):
+        ns = ctx.newton_solve()
+        assert ns.converged and ns.lin.true_relres <= 1e-10, n
+        u, p, w, wo = ctx.get_state()
+        V = float(np.sum(m.fq_w[None, :] * m.area[fa][:, None] * w[fa]))
+        assert V == pytest.approx(n * q, rel=1e-8), n
+        S = asm.assemble(m, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo),
+                         case.src_pnode, case.src_q0)
+        J = asm.full_matrix(m, S)
+        x = np.concatenate([u, p])
+        mag = abs(J) @ np.abs(x)
+        assert np.abs(S.R).max() <= 1e-9 * mag.max(), n
+        ctx.end_load_step()
+    ctx.close()
+
+
 @pytest.mark.parametrize("precision", [hf.HF_FP64, hf.HF_FP32_IR], ids=["fp64", "fp32ir"])
 def test_ensemble_batched_sampled_instances(precision):
     probs = synth.ensemble(64, seed=4)
@@ -89,6 +122,9 @@ def test_ensemble_fp32ir_fp64_solves():
     for i, s in enumerate(st0):
         ctx.set_state(s.u, s.p, s.w_old, inst=i)
     ctx.initial_guess()
+    # the fluid-row scale of the load step, fixed by the predictor's opening
+    s_p = [newton.fluid_scale(c, wo, u) for c, (u, _, _, wo) in
+           zip(cases, (ctx.get_state(i) for i in range(len(probs))))]
     ctx.set_options(gmres_maxit=6000)
     ctx.reset_profile()
     finished = []
@@ -106,7 +142,7 @@ def test_ensemble_fp32ir_fp64_solves():
     assert rises >= 1 and finished
     for _, it, i, (u, p, _, wo), dx in sorted(finished, key=lambda f: f[0])[:3]:
         c = cases[i]
-        S = asm.assemble(c.mesh, c.itf, c.prm, u, p, wo, st0[i].s_p, c.src_pnode, c.src_q0)
+        S = asm.assemble(c.mesh, c.itf, c.prm, u, p, wo, s_p[i], c.src_pnode, c.src_q0)
         J = asm.full_matrix(c.mesh, S)
         r = J @ dx + S.R
         mag = abs(J) @ np.abs(dx)
