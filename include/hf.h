@@ -156,6 +156,17 @@ typedef struct {
   int coarse_leaf;     /* vertex classes per leaf of the nested-dissection
                           tree, 4..4096 (default 64); fixed at the first
                           two-level build of a context */
+  int coarse_reuse;    /* two-level builds that keep the last coarse
+                          factorisation (and Z_c = A_c^-1 P^T B) instead of
+                          refactorising P^T A P, 0..1000 (default 4): the
+                          coarse matrix then lags the current one in the
+                          rows of cracked elements, the only blocks that
+                          change between Newton iterations; A P, W and the
+                          Schur block are recomputed at every build, so the
+                          preconditioner stays the exact full block
+                          factorisation built on that coarse matrix.  A full
+                          assembly or a failed build forces a new
+                          factorisation; 0 refactorises at every build */
   void *stream;        /* hipStream_t to run on; NULL: a stream the ctx creates */
 } hf_options;
 
@@ -262,6 +273,9 @@ typedef struct {
   /* two-level preconditioner builds, and those whose coarse factor failed
      (block-Jacobi used for that solve) */
   int64_t n_tl_builds, n_tl_fail;
+  /* coarse factorisations among the builds (the others kept the last one,
+     coarse_reuse) */
+  int64_t n_tl_factor;
 } hf_profile;
 
 /* Fill *opt with the defaults listed above. */
@@ -414,6 +428,29 @@ hf_status hf_end_load_step(hf_ctx *ctx);
    s_p is then recomputed from the predictor's opening (as hf_set_state
    does). */
 hf_status hf_initial_guess(hf_ctx *ctx, double *p0_out);
+
+/* ---- fracture and fluid activation (end of a load step) ---- */
+/* Normal traction the DG method exchanges at every face point of instance
+   inst at the current state (the flux of the consistency and stabilisation
+   terms of eq. weakElastoStatics): tn[f*nq + q] = n.{sigma(u)} n +
+   (b/h_f)(lambda + 2G) [[u]].n, the quantity the fracture activation of eq.
+   (fractureActivation) compares with sigma_c.  tn: caller array of
+   n_face*nq_face doubles (instance-local face order of hf_get_faces). */
+hf_status hf_get_interface_traction(hf_ctx *ctx, int32_t inst, double *tn);
+/* Activation checks on the current (converged) state of instance inst,
+   eq. (fractureActivation) and eq. (fluidActivation): an intact point
+   (state 0) whose DG normal traction exceeds sigma_c becomes cohesive
+   (state 1, irreversible); a face without fluid whose points are all in
+   state >= 1 becomes a fluid face (beta = 1) once its opening exceeds
+   delta_c at any point (the fluid threshold taken as delta_c).  Writes the
+   new states into the caller arrays qp_state (n_face*nq_face) and beta
+   (n_face) in the layout of hf_upload_interfaces, and n_new[0] = points
+   newly activated, n_new[1] = faces newly fluid (nullable).  The context is
+   not changed: the fluid unknowns follow beta, so applying the new states
+   means uploading them to a new context (hf_create ... hf_finalize) and
+   carrying the state over (pressure nodes matched by hf_get_pnodes keys). */
+hf_status hf_detect_activation(hf_ctx *ctx, int32_t inst, uint8_t *qp_state, uint8_t *beta,
+                               int64_t *n_new);
 
 /* ---- inspection hooks (tests, benchmarks) ---- */
 /* R_u (n_u), R_p (n_p) of the last hf_assemble. */

@@ -31,7 +31,8 @@ EXPORTS = [
     "hf_upload_mesh", "hf_get_faces", "hf_upload_interfaces", "hf_set_material",
     "hf_set_injection", "hf_finalize", "hf_get_sizes", "hf_get_pnodes", "hf_set_state",
     "hf_get_state", "hf_set_state_device", "hf_get_state_device", "hf_assemble", "hf_solve",
-    "hf_newton_step", "hf_newton_solve", "hf_staggered_step", "hf_end_load_step", "hf_initial_guess", "hf_get_residual",
+    "hf_newton_step", "hf_newton_solve", "hf_staggered_step", "hf_end_load_step",
+    "hf_get_interface_traction", "hf_detect_activation", "hf_initial_guess", "hf_get_residual",
     "hf_get_block_rows", "hf_get_coupling", "hf_get_increment", "hf_apply_jacobian",
     "hf_get_profile", "hf_reset_profile", "hf_get_tuning", "hf_set_tuning", "hf_autotune",
     "hf_get_block_inverse", "hf_apply_preconditioned", "hf_apply_preconditioned_noalloc",
@@ -47,6 +48,7 @@ class Options(C.Structure):
                 ("ir_inner_cycles", C.c_int), ("ir_stall_steps", C.c_int),
                 ("incremental_assembly", C.c_int),
                 ("fold_preconditioner", C.c_int), ("two_level", C.c_int), ("coarse_leaf", C.c_int),
+                ("coarse_reuse", C.c_int),
                 ("stream", C.c_void_p)]
 
 
@@ -93,7 +95,7 @@ class Profile(C.Structure):
                                           "n_inv_fallback")] + \
                [("ms_resid", C.c_double), ("n_resid", C.c_int64), ("n_unfold", C.c_int64),
                 ("n_mgrow", C.c_int64), ("n_ir_rise", C.c_int64), ("n_tl_builds", C.c_int64),
-                ("n_tl_fail", C.c_int64)]
+                ("n_tl_fail", C.c_int64), ("n_tl_factor", C.c_int64)]
 
 
 class HFError(RuntimeError):
@@ -147,6 +149,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hf_newton_step": (C.c_int, [vp, P(NewtonStats)]),
         "hf_newton_solve": (C.c_int, [vp, P(NewtonStats)]),
         "hf_staggered_step": (C.c_int, [vp, P(C.c_int32), P(C.c_double), P(NewtonStats)]),
+        "hf_get_interface_traction": (C.c_int, [vp, C.c_int32, P(C.c_double)]),
+        "hf_detect_activation": (C.c_int, [vp, C.c_int32, P(C.c_uint8), P(C.c_uint8), P(C.c_int64)]),
         "hf_end_load_step": (C.c_int, [vp]),
         "hf_initial_guess": (C.c_int, [vp, P(C.c_double)]),
         "hf_get_residual": (C.c_int, [vp, C.c_int32, vp, vp]),
@@ -372,6 +376,27 @@ class Context:
 
     def end_load_step(self):
         self._check(self.lib.hf_end_load_step(self.h), "hf_end_load_step")
+
+    def interface_traction(self, inst=0):
+        """DG normal traction at every face point, (n_face, nq_face)."""
+        s = self.isizes[inst]
+        tn = np.empty((s.n_face, s.nq_face))
+        self._check(self.lib.hf_get_interface_traction(self.h, inst, tn.ctypes.data_as(C.POINTER(C.c_double))),
+                    "hf_get_interface_traction")
+        return tn
+
+    def detect_activation(self, inst=0):
+        """New interface states after the activation checks: (qp_state, beta,
+        points newly activated, faces newly fluid)."""
+        s = self.isizes[inst]
+        qp = np.empty((s.n_face, s.nq_face), dtype=np.uint8)
+        beta = np.empty(s.n_face, dtype=np.uint8)
+        n = np.zeros(2, dtype=np.int64)
+        self._check(self.lib.hf_detect_activation(self.h, inst, qp.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                                  beta.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                                  n.ctypes.data_as(C.POINTER(C.c_int64))),
+                    "hf_detect_activation")
+        return qp, beta, int(n[0]), int(n[1])
 
     def initial_guess(self):
         """Uniform-pressure elastic predictor for the first load step; returns p0

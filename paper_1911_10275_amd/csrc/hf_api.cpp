@@ -137,6 +137,9 @@ struct hf_ctx {
   // essential pressure condition of the staggered iteration, per instance
   int32_t *stag_node = nullptr;
   double *stag_val = nullptr;
+  // activation checks: DG normal traction per face point, new interface states
+  double *tn_buf = nullptr;
+  uint8_t *act_qp = nullptr, *act_beta = nullptr;
   int *flag = nullptr;
   double *dx = nullptr, *rhs = nullptr, *r64 = nullptr, *t64 = nullptr;
   KrylovWs<double> k64;
@@ -168,6 +171,11 @@ struct hf_ctx {
   bool tl_planned = false;  // the coarse plan exists (or was refused: tl_refused)
   bool tl_refused = false;
   bool tl_ok = false;       // the last preconditioner build produced a usable coarse factor
+  // the coarse factorisation kept across builds (coarse_reuse): valid, the
+  // assembly epoch it was built in, builds since, FP32 copy current
+  bool c_valid = false, c_f32 = false;
+  int64_t c_epoch = -1;
+  int c_age = 0;
   int graphs_tl = -1;       // two-level state the captured GMRES chunks were recorded with
   CoarsePlan cplan;
   CoarseHostView chv;
@@ -483,6 +491,7 @@ extern "C" void hf_default_options(hf_options *o) {
   o->fold_preconditioner = 1;
   o->two_level = 0;
   o->coarse_leaf = 64;
+  o->coarse_reuse = 4;
   o->stream = nullptr;
 }
 
@@ -497,6 +506,7 @@ static hf_status validate_options(hf_ctx *ctx, const hf_options &o) {
   if (!(o.b_stab > 0)) return fail(ctx, HF_EINVAL, "b_stab must be positive");
   if (o.two_level != 0 && o.two_level != 1) return fail(ctx, HF_EINVAL, "two_level must be 0 or 1");
   if (o.coarse_leaf < 4 || o.coarse_leaf > 4096) return fail(ctx, HF_EINVAL, "coarse_leaf out of range 4..4096");
+  if (o.coarse_reuse < 0 || o.coarse_reuse > 1000) return fail(ctx, HF_EINVAL, "coarse_reuse out of range 0..1000");
   return HF_OK;
 }
 
@@ -2066,14 +2076,22 @@ static hf_status tl_build(hf_ctx *ctx, int n_wide) {
     ctx->tb32.Z = ctx->cZ32;
     release_all_graphs(ctx);
   }
+  // keep the last coarse factorisation (and Z_c) while it is younger than
+  // coarse_reuse builds and no full assembly has replaced A since
+  const bool reuse = ctx->c_valid && ctx->c_age < ctx->opt.coarse_reuse && ctx->c_epoch == ctx->lin_epoch;
   HIPCHK(hipMemsetAsync(ctx->cflag, 0, sizeof(int), st));
   HIPCHK(coarse_build_ap(kp, ck, ctx->A, nullptr, s.ne, ctx->cAP, st));
   HIPCHK(coarse_build_w(kp, ck, ctx->Cs, ctx->inv, ctx->cAP, ctx->cW, st));
-  HIPCHK(coarse_factor(kp, ck, ctx->chv, ctx->cAP, ctx->cF, ctx->cCp, ctx->cDsc, ctx->cflag, st));
+  if (!reuse) {
+    HIPCHK(coarse_factor(kp, ck, ctx->chv, ctx->cAP, ctx->cF, ctx->cCp, ctx->cDsc, ctx->cflag, st));
+    ctx->c_f32 = false;
+  }
   if (s.n_p) {
     const int nrhs = ctx->c_nrhs;
-    HIPCHK(coarse_ptb(kp, ck, ctx->Bs, nrhs, ctx->cR, st));
-    HIPCHK(coarse_solve_multi(ck, ctx->chv, ctx->cF, ctx->cR, nrhs, ctx->cU, ctx->cY, ctx->cZ, st));
+    if (!reuse) {
+      HIPCHK(coarse_ptb(kp, ck, ctx->Bs, nrhs, ctx->cR, st));
+      HIPCHK(coarse_solve_multi(ck, ctx->chv, ctx->cF, ctx->cR, nrhs, ctx->cU, ctx->cY, ctx->cZ, st));
+    }
     HIPCHK(coarse_s_correct(kp, ck, ctx->cW, ctx->cZ, nrhs, ctx->S2, st));
     HIPCHK(launch_schur_invert(kp, ctx->S2, ctx->Sinv2, ctx->Sinv2_32, ctx->flag, n_wide, st));
     for (int b = 0; b < B; ++b) {
@@ -2086,12 +2104,23 @@ static hf_status tl_build(hf_ctx *ctx, int n_wide) {
   if (ctx->opt.precision == HF_FP32_IR) {
     HIPCHK(launch_convert(ctx->cAP, ctx->cAP32, ctx->c_ap_total, st));
     HIPCHK(launch_convert(ctx->cW, ctx->cW32, ctx->c_w_total, st));
-    HIPCHK(launch_convert(ctx->cF, ctx->cF32, ctx->cplan.front_total, st));
-    if (s.n_p) HIPCHK(launch_convert(ctx->cZ, ctx->cZ32, (int64_t)ctx->cplan.ncls * s.dim * ctx->c_nrhs, st));
+    if (!ctx->c_f32) {
+      HIPCHK(launch_convert(ctx->cF, ctx->cF32, ctx->cplan.front_total, st));
+      if (s.n_p) HIPCHK(launch_convert(ctx->cZ, ctx->cZ32, (int64_t)ctx->cplan.ncls * s.dim * ctx->c_nrhs, st));
+      ctx->c_f32 = true;
+    }
   }
   TRY(get_i_async(ctx, ctx->cflag, 1, 0));
   TRY(sync(ctx));
   ctx->tl_ok = ctx->hi[0] == 0;
+  if (reuse) {
+    ctx->c_age += 1;
+  } else {
+    ctx->c_age = 0;
+    ctx->c_epoch = ctx->lin_epoch;
+    ctx->prof.n_tl_factor += 1;
+  }
+  ctx->c_valid = ctx->tl_ok;
   if (!ctx->tl_ok) ctx->prof.n_tl_fail += 1;
   ctx->prof.n_tl_builds += 1;
   return HF_OK;
@@ -2507,6 +2536,7 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
     const double bn = std::sqrt(bu * bu + bp * bp);
     ls[b].relres_u = bu > 0.0 ? ru / bu : (bn > 0.0 ? ru / bn : ru);
     ls[b].relres_p = bp > 0.0 ? rp / bp : (bn > 0.0 ? rp / bn : rp);
+    if (ls[b].status != HF_OK) ctx->c_valid = false;  // the next build factorises afresh
   }
   return HF_OK;
 }
@@ -2877,6 +2907,60 @@ extern "C" hf_status hf_end_load_step(hf_ctx *ctx) {
   TRY(update_fluid_scale(ctx));
   TRY(sync(ctx));
   ctx->stage = 3;
+  return HF_OK;
+}
+
+// ===========================================================================
+// Fracture and fluid activation checks
+// ===========================================================================
+static hf_status face_traction(hf_ctx *ctx) {
+  const Sizes &s = ctx->s;
+  if (!ctx->tn_buf) TRY(dalloc(ctx, &ctx->tn_buf, std::max<int64_t>(s.nf * s.nqf, 1)));
+  HIPCHK(launch_face_traction(kparams(ctx), ctx->xs, ctx->tn_buf, ctx->stream));
+  return HF_OK;
+}
+
+extern "C" hf_status hf_get_interface_traction(hf_ctx *ctx, int32_t inst, double *tn) {
+  TRY(check_ctx(ctx, 3));
+  TRY(check_inst(ctx, inst));
+  if (!tn) return fail(ctx, HF_EINVAL, "null output array");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  TRY(face_traction(ctx));
+  const int nq = ctx->s.nqf;
+  HIPCHK(hipMemcpyAsync(tn, ctx->tn_buf + ctx->foff[inst] * nq, ctx->inst[inst].nf * nq * sizeof(double),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  TRY(sync(ctx));
+  return HF_OK;
+}
+
+extern "C" hf_status hf_detect_activation(hf_ctx *ctx, int32_t inst, uint8_t *qp_state, uint8_t *beta,
+                                          int64_t *n_new) {
+  TRY(check_ctx(ctx, 3));
+  TRY(check_inst(ctx, inst));
+  if (!qp_state || !beta) return fail(ctx, HF_EINVAL, "null output array");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  const Sizes &s = ctx->s;
+  if (!ctx->act_qp) {
+    TRY(dalloc(ctx, &ctx->act_qp, std::max<int64_t>(s.nf * s.nqf, 1)));
+    TRY(dalloc(ctx, &ctx->act_beta, std::max<int64_t>(s.nf, 1)));
+  }
+  const KParams kp = kparams(ctx);
+  TRY(face_traction(ctx));
+  HIPCHK(launch_opening(kp, ctx->xs, ctx->w_tmp, ctx->stream));
+  HIPCHK(launch_activation(kp, ctx->tn_buf, ctx->w_tmp, ctx->act_qp, ctx->act_beta, ctx->stream));
+  const InstHost &h = ctx->inst[inst];
+  const int nq = s.nqf;
+  HIPCHK(hipMemcpyAsync(qp_state, ctx->act_qp + ctx->foff[inst] * nq, h.nf * nq, hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipMemcpyAsync(beta, ctx->act_beta + ctx->foff[inst], h.nf, hipMemcpyDeviceToHost, ctx->stream));
+  TRY(sync(ctx));
+  if (n_new) {
+    int64_t na = 0, nb = 0;
+    for (int64_t i = 0; i < h.nf * nq; ++i) na += qp_state[i] != h.qp_state[i];
+    for (int64_t f = 0; f < h.nf; ++f) nb += beta[f] != h.beta[f];
+    n_new[0] = na;
+    n_new[1] = nb;
+  }
   return HF_OK;
 }
 

@@ -277,6 +277,11 @@ hipError_t launch_assemble(const KParams &kp, const double *u, const double *p,
                            hipStream_t st);
 hipError_t launch_opening(const KParams &kp, const double *u, double *w, hipStream_t st);
 hipError_t launch_wmax(const KParams &kp, const double *w, double *out, hipStream_t st);
+// DG normal traction t.n at every face point (nf*nq)
+hipError_t launch_face_traction(const KParams &kp, const double *u, double *tn, hipStream_t st);
+// new interface states after the activation checks (nf*nq states, nf fluid flags)
+hipError_t launch_activation(const KParams &kp, const double *tn, const double *w, uint8_t *qp_out,
+                             uint8_t *beta_out, hipStream_t st);
 hipError_t launch_fluid_volume(const KParams &kp, const double *u, double *partial, double *out,
                                hipStream_t st);
 hipError_t launch_fill(double v, double *x, int64_t n, hipStream_t st);

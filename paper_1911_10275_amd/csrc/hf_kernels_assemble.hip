@@ -689,6 +689,83 @@ __global__ void k_opening(KParams kp, const double *__restrict__ u, double *__re
   w[t] = acc;
 }
 
+// normal traction the DG method exchanges at every face point, the flux of
+// the consistency and stabilisation terms: t.n = n.{sigma(u)} n +
+// (b/h_f)(lambda + 2G) [[u]].n (Chat(n) n = (lambda + 2G) n); one thread per
+// (face, point)
+template <int DIM, int ORDER>
+__global__ void k_face_traction(KParams kp, const double *__restrict__ u, double *__restrict__ tn) {
+  using C = Cfg<DIM, ORDER>;
+  constexpr int NN = C::NN, BU = C::BU, NQF = C::NQF;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= kp.s.nf * NQF) return;
+  const int64_t f = t / NQF;
+  const int q = (int)(t % NQF);
+  const int32_t es[2] = {kp.m.face_em[f], kp.m.face_ep[f]};
+  const int32_t *perm[2] = {kp.m.fperm_m, kp.m.fperm_p};
+  const InstPar P = kp.ip[kp.einst[es[0]]];
+  double n[DIM];
+  for (int x = 0; x < DIM; ++x) n[x] = kp.m.normal[f * DIM + x];
+  double snn = 0.0, w = 0.0;
+  for (int side = 0; side < 2; ++side) {
+    const int64_t e = es[side];
+    double lam[DIM + 1];
+    for (int k = 0; k <= DIM; ++k) lam[k] = 0.0;
+    for (int k = 0; k < DIM; ++k) lam[perm[side][f * DIM + k]] = kp.rt->fq_mu[q][k];
+    const double *gl = kp.m.gl + e * (DIM + 1) * DIM;
+    double gu[DIM][DIM], uv[DIM];
+    for (int i = 0; i < DIM; ++i) {
+      uv[i] = 0.0;
+      for (int x = 0; x < DIM; ++x) gu[i][x] = 0.0;
+    }
+    for (int a = 0; a < NN; ++a) {
+      double dl[DIM + 1];
+      Lag<DIM, ORDER>::dphi_one(a, lam, dl);
+      double g[DIM];
+      for (int x = 0; x < DIM; ++x) {
+        g[x] = 0.0;
+        for (int k = 0; k <= DIM; ++k) g[x] += dl[k] * gl[k * DIM + x];
+      }
+      const double ph = Lag<DIM, ORDER>::phi_one(a, lam);
+      for (int i = 0; i < DIM; ++i) {
+        const double ua = u[e * BU + a * DIM + i];
+        uv[i] += ph * ua;
+        for (int x = 0; x < DIM; ++x) gu[i][x] += ua * g[x];
+      }
+    }
+    double tr = 0.0, nen = 0.0;
+    for (int i = 0; i < DIM; ++i) {
+      tr += gu[i][i];
+      for (int x = 0; x < DIM; ++x) nen += n[i] * 0.5 * (gu[i][x] + gu[x][i]) * n[x];
+    }
+    snn += 0.5 * (P.lam * tr + 2.0 * P.G * nen);
+    for (int i = 0; i < DIM; ++i) w += (side ? uv[i] : -uv[i]) * n[i];
+  }
+  tn[t] = snn + kp.b_stab / kp.m.hf[f] * (P.lam + 2.0 * P.G) * w;
+}
+
+// activation checks on a converged state, one thread per face: an intact
+// point whose DG normal traction exceeds sigma_c becomes cohesive (state 1);
+// a face without fluid whose points are all cohesive or traction-free becomes
+// a fluid face once its opening exceeds delta_c at any point
+template <int NQF>
+__global__ void k_activation(KParams kp, const double *__restrict__ tn, const double *__restrict__ w,
+                             uint8_t *__restrict__ qp_out, uint8_t *__restrict__ beta_out) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= kp.s.nf) return;
+  const InstPar P = kp.ip[kp.einst[kp.m.face_em[f]]];
+  bool all_open = true, wide = false;
+  for (int q = 0; q < NQF; ++q) {
+    const int64_t t = f * NQF + q;
+    uint8_t st = kp.m.qp_state[t];
+    if (st == 0 && tn[t] > P.sigma_c) st = 1;
+    qp_out[t] = st;
+    all_open = all_open && st >= 1;
+    wide = wide || w[t] > P.delta_c;
+  }
+  beta_out[f] = (kp.m.beta[f] || (all_open && wide)) ? 1 : 0;
+}
+
 // crack volume of each instance: out[b] = sum over its fluid faces and points of W_q w_q
 template <int DIM, int ORDER>
 __global__ __launch_bounds__(256) void k_fluid_volume(KParams kp, const double *__restrict__ u,
@@ -783,6 +860,32 @@ hipError_t launch_opening(const KParams &kp, const double *u, double *w, hipStre
   else if (d == 2 && o == 2) hipLaunchKernelGGL((k_opening<2, 2>), g, b, 0, st, kp, u, w);
   else if (d == 3 && o == 1) hipLaunchKernelGGL((k_opening<3, 1>), g, b, 0, st, kp, u, w);
   else hipLaunchKernelGGL((k_opening<3, 2>), g, b, 0, st, kp, u, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_traction(const KParams &kp, const double *u, double *tn, hipStream_t st) {
+  const int64_t n = kp.s.nf * kp.s.nqf;
+  if (!n) return hipSuccess;
+  dim3 g((unsigned)((n + 127) / 128)), b(128);
+  const int d = kp.s.dim, o = kp.s.order;
+  if (d == 2 && o == 1) hipLaunchKernelGGL((k_face_traction<2, 1>), g, b, 0, st, kp, u, tn);
+  else if (d == 2 && o == 2) hipLaunchKernelGGL((k_face_traction<2, 2>), g, b, 0, st, kp, u, tn);
+  else if (d == 3 && o == 1) hipLaunchKernelGGL((k_face_traction<3, 1>), g, b, 0, st, kp, u, tn);
+  else hipLaunchKernelGGL((k_face_traction<3, 2>), g, b, 0, st, kp, u, tn);
+  return hipGetLastError();
+}
+
+hipError_t launch_activation(const KParams &kp, const double *tn, const double *w, uint8_t *qp_out,
+                             uint8_t *beta_out, hipStream_t st) {
+  if (!kp.s.nf) return hipSuccess;
+  dim3 g((unsigned)((kp.s.nf + 127) / 128)), b(128);
+  switch (kp.s.nqf) {
+    case 2: hipLaunchKernelGGL((k_activation<2>), g, b, 0, st, kp, tn, w, qp_out, beta_out); break;
+    case 3: hipLaunchKernelGGL((k_activation<3>), g, b, 0, st, kp, tn, w, qp_out, beta_out); break;
+    case 4: hipLaunchKernelGGL((k_activation<4>), g, b, 0, st, kp, tn, w, qp_out, beta_out); break;
+    case 9: hipLaunchKernelGGL((k_activation<9>), g, b, 0, st, kp, tn, w, qp_out, beta_out); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -19,17 +19,19 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_counter_summary_matches_the_product_kernel_source():
-    """The summary names the sha256 of the kernel source its counters were
-    taken on; bench.py reports the traffic only while they agree, so a change
-    to the kernel must come with a new counter run."""
+    """The default workload's counter summary names the sha256 of the kernel
+    source its counters were taken on; bench.py reports the traffic only while
+    they agree, so a change to the kernel must come with a new counter run."""
     sys.path.insert(0, ROOT)
     import bench
-    text = open(os.path.join(ROOT, "profiles", "spmv_fp64_penny3d_p2_48k.md")).read()
+    name = "penny3d_p2_384k"
+    text = open(os.path.join(ROOT, "profiles", f"spmv_fp64_{name}.md")).read()
     sha = re.search(r"^source_sha256 = ([0-9a-f]{64})$", text, re.M).group(1)
+    alg = int(re.search(r"^algorithmic_bytes_per_launch = (\d+)$", text, re.M).group(1))
     src = os.path.join(ROOT, "paper_1911_10275_amd", "csrc", "hf_kernels_spmv.hip")
     assert hashlib.sha256(open(src, "rb").read()).hexdigest() == sha
-    traffic = bench.spmv_traffic(2)
-    # scaled FETCH_SIZE + WRITE_SIZE bytes per launch, at least the algorithmic bytes of
-    # one product (1,717,807,064 B) and within 10% of them
-    assert traffic is not None and 1717807064 <= traffic <= 1.1 * 1717807064
-    assert bench.spmv_traffic(3) is None
+    traffic = bench.spmv_traffic(name)
+    # scaled FETCH_SIZE + WRITE_SIZE bytes per launch: at least the algorithmic
+    # bytes of one product and within 10% of them
+    assert traffic is not None and alg <= traffic <= 1.1 * alg
+    assert bench.spmv_traffic("no_such_workload") is None

@@ -227,3 +227,27 @@ def test_two_level_batched_equals_single_instance_bitwise(precision):
             np.testing.assert_array_equal(x, y)
         assert ns[i].converged == 1 and nss.converged == 1
         assert ns[i].lin.gmres_iters == nss.lin.gmres_iters
+
+
+@pytest.mark.parametrize("precision", [hf.HF_FP64, hf.HF_FP32_IR], ids=["fp64", "fp32ir"])
+def test_coarse_reuse_keeps_the_factorisation_and_the_results(precision):
+    """coarse_reuse = 3: one coarse factorisation serves up to four builds
+    (the profile counts them); the load steps end at the oracle's states as
+    with a factorisation at every build."""
+    prob = SMALL["3d_p2_n4"]()
+    case = Case.from_problem(prob)
+    ref = newton.run(case, prob.load_steps, solver="gmres")
+    builds = {}
+    for reuse in (0, 3):
+        ctx = hf.context_for_problem(prob, two_level=1, coarse_reuse=reuse)
+        got = _load_steps(ctx, case, prob.load_steps, precision)
+        prof = ctx.profile()
+        builds[reuse] = (prof.n_tl_builds, prof.n_tl_factor)
+        ctx.close()
+        for (st, _), ((u, p, w, wo), ns) in zip(ref, got):
+            assert np.linalg.norm(u - st.u) <= 1e-8 * np.linalg.norm(st.u)
+            assert np.linalg.norm(p - st.p) <= 1e-8 * np.linalg.norm(st.p)
+    n0, f0 = builds[0]
+    n3, f3 = builds[3]
+    assert f0 == n0 and n3 >= 4
+    assert f3 == -(-n3 // 4)   # one factorisation per four builds
