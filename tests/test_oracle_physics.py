@@ -131,3 +131,39 @@ def test_discrete_mass_conservation(prob):
         assert dv == pytest.approx(case.src_q0.sum() * case.prm.dt, rel=1e-8)
         assert ns.iterations <= 8
         st = newton.end_load_step(case, new)
+
+
+def test_viscosity_scaling_forms():
+    """The scaling forms of the zero-toughness plane-strain solution (eq.
+    DimensionalSol1-3): w ~ mu'^(1/6) Q0^(1/2) t^(1/3) E'^(-1/6),
+    p ~ mu'^(1/3) E'^(2/3) t^(-1/3), l ~ Q0^(1/2) E'^(1/6) t^(2/3) mu'^(-1/6).
+    Their exponents leave w and l unchanged and multiply p by the predicted
+    factor under two rescalings of the inputs, which the discrete equations
+    must reproduce exactly (one load step from the predictor, dense solves):
+    (a) mu x a, t (the time step) x a, Q0 / a: predicted factors w a^0, p a^0;
+    (b) E, sigma_c, G_c, mu all x b (delta_c fixed): w b^0, p b^1."""
+    import dataclasses
+    from oracle import newton
+    from oracle.newton import Case
+
+    def solve(mat, q0):
+        prob = synth.kgd_problem(10, 1, 2, mat, q0, half_length=0.2, ring=1, load_steps=1)
+        (st, ns), = newton.run(Case.from_problem(prob), 1, predictor=True, solver="dense")
+        assert ns.converged
+        return st
+
+    base = synth.Material(E=1.0, nu=0.25, sigma_c=1e-3, G_c=1e-4, mu=1e-3, dt=1.0)
+    ref = solve(base, 1e-4)
+    a, b = 10.0, 3.0
+    pred_p = lambda fmu, fE, ft: fmu ** (1 / 3) * fE ** (2 / 3) * ft ** (-1 / 3)
+    pred_w = lambda fmu, fq, ft, fE: fmu ** (1 / 6) * fq ** 0.5 * ft ** (1 / 3) * fE ** (-1 / 6)
+    st = solve(dataclasses.replace(base, mu=base.mu * a, dt=base.dt * a), 1e-4 / a)
+    assert pred_w(a, 1 / a, a, 1.0) == pytest.approx(1.0) and pred_p(a, 1.0, a) == pytest.approx(1.0)
+    np.testing.assert_allclose(st.u, ref.u, rtol=0, atol=1e-9 * np.abs(ref.u).max())
+    np.testing.assert_allclose(st.p, ref.p, rtol=1e-9)
+    st = solve(dataclasses.replace(base, E=base.E * b, sigma_c=base.sigma_c * b, G_c=base.G_c * b,
+                                   mu=base.mu * b), 1e-4)
+    fw, fp = pred_w(b, 1.0, 1.0, b), pred_p(b, b, 1.0)
+    assert fw == pytest.approx(1.0) and fp == pytest.approx(b)
+    np.testing.assert_allclose(st.u, fw * ref.u, rtol=0, atol=1e-9 * np.abs(ref.u).max())
+    np.testing.assert_allclose(st.p, fp * ref.p, rtol=1e-9)
