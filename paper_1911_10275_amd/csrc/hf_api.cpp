@@ -71,6 +71,7 @@ struct TlBuf {
   const T *AP = nullptr, *W = nullptr, *F = nullptr, *Sinv2 = nullptr, *Z = nullptr;
   T *rc1 = nullptr, *rc2 = nullptr, *zc1 = nullptr, *zc2 = nullptr, *y = nullptr, *upd = nullptr;
   T *q = nullptr, *zp = nullptr, *t = nullptr, *apz = nullptr, *cpy = nullptr;
+  T *cv = nullptr;  // front vectors of the coarse solves (one entry per front position)
 };
 
 // concatenated host layout kept after hf_finalize for the coarse-space plan
@@ -1540,7 +1541,7 @@ static hf_status tl_first(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, cons
   hipStream_t st = ctx->stream;
   const int64_t n_u = ctx->s.n_u;
   HIPCHK(coarse_restrict2<T>(kp, ck, v, b.cpy, b.rc1, st));
-  HIPCHK(coarse_solve1<T>(ck, ctx->chv, b.F, b.rc1, b.upd, b.y, b.zc1, st));
+  HIPCHK(coarse_solve1<T>(ck, ctx->chv, b.F, b.rc1, b.upd, b.y, b.cv, b.zc1, st));
   if (ctx->s.n_p) {
     HIPCHK(coarse_q<T>(kp, ck, op.Cf, b.W, v, v + n_u, b.zc1, b.q, wp, st));
     HIPCHK(coarse_pgemv<T>(kp, b.Sinv2, b.q, b.zp, st));
@@ -2019,6 +2020,7 @@ static hf_status tl_plan(hf_ctx *ctx) {
     TRY(dalloc(ctx, &b.zc2, nc));
     TRY(dalloc(ctx, &b.y, nc));
     TRY(dalloc(ctx, &b.upd, std::max<int64_t>(cp.upd_total, 1)));
+    TRY(dalloc(ctx, &b.cv, std::max<int64_t>(cp.fd_ptr.back(), 1)));
     TRY(dalloc(ctx, &b.q, s.n_p));
     TRY(dalloc(ctx, &b.zp, s.n_p));
     TRY(dalloc(ctx, &b.t, s.N()));
@@ -2056,6 +2058,7 @@ static hf_status tl_build(hf_ctx *ctx, int n_wide) {
       TRY(dalloc(ctx, &b.zc2, nc));
       TRY(dalloc(ctx, &b.y, nc));
       TRY(dalloc(ctx, &b.upd, std::max<int64_t>(ctx->cplan.upd_total, 1)));
+      TRY(dalloc(ctx, &b.cv, std::max<int64_t>(ctx->cplan.fd_ptr.back(), 1)));
       TRY(dalloc(ctx, &b.q, s.n_p));
       TRY(dalloc(ctx, &b.zp, s.n_p));
       TRY(dalloc(ctx, &b.t, s.N()));

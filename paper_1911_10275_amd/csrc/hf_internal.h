@@ -237,9 +237,10 @@ hipError_t coarse_solve_multi(const CoarseK &ck, const CoarseHostView &hv, const
                               int nrhs, double *upd, double *y, double *xs, hipStream_t st);
 hipError_t coarse_s_correct(const KParams &kp, const CoarseK &ck, const double *W, const double *Z, int nrhs,
                             double *S, hipStream_t st);
+// one coarse solve xs = A_c^-1 b; upd, y and the front vectors cv are scratch
 template <typename T>
-hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const T *F, const T *b, T *upd, T *y, T *xs,
-                         hipStream_t st);
+hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const T *F, const T *b, T *upd, T *y, T *cv,
+                         T *xs, hipStream_t st);
 // q' = v_p - (Cf v_u + W z_c) per pressure row; w_p = v_p when wp != null
 template <typename T>
 hipError_t coarse_q(const KParams &kp, const CoarseK &ck, const T *Cf, const T *W, const T *vu, const T *vp,

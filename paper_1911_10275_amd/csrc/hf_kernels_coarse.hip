@@ -357,54 +357,68 @@ __device__ inline T own_rhs(const CoarseK &ck, int64_t pos, const T *b, const T 
   return v;
 }
 
-// one right-hand side: each workgroup keeps the node's own right-hand side
-// in LDS and computes kCT/64 rows (one wavefront per row)
+// one right-hand side.  Forward: each own position's right-hand side is
+// formed once (one thread each) into y and into the front vector cv, then
+// one wavefront per struct row reads its row of the column panel against
+// cv.  Backward: the front vector [y_own; -x_struct] is gathered once, then
+// one wavefront per own row reads its row of [F11^-1, F11^-1 F12].  The
+// front vectors are contiguous, so the rows stream without index loads.
 template <typename T>
-__global__ __launch_bounds__(kCT) void k_fwd1(CoarseK ck, int lev, const T *__restrict__ Fm, const T *__restrict__ b,
-                                              T *__restrict__ upd, T *__restrict__ y) {
-  extern __shared__ unsigned char smem_raw[];
-  T *vo = reinterpret_cast<T *>(smem_raw);
+__global__ __launch_bounds__(kCT) void k_fwd_own(CoarseK ck, int lev, const T *__restrict__ b,
+                                                 const T *__restrict__ upd, T *__restrict__ y, T *__restrict__ cv) {
+  const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
+  const int c = blockIdx.x * kCT + threadIdx.x;
+  if (c >= ck.fk[x]) return;
+  const int64_t pos = ck.fd_ptr[x] + c;
+  const T v = own_rhs<T>(ck, pos, b, upd, 1, 0);
+  y[ck.fd_dof[pos]] = v;
+  cv[pos] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCT) void k_fwd_rows(CoarseK ck, int lev, const T *__restrict__ Fm,
+                                                  const T *__restrict__ cv, T *__restrict__ upd) {
   const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
   const int k = ck.fk[x], f = ck.ff[x];
-  const int rows_per = kCT / 64;
-  const int r0 = blockIdx.x * rows_per;
-  if (r0 >= f) return;
-  const int64_t fd = ck.fd_ptr[x];
-  for (int c = threadIdx.x; c < k; c += kCT) vo[c] = own_rhs<T>(ck, fd + c, b, upd, 1, 0);
-  __syncthreads();
-  const int lane = threadIdx.x % 64, r = r0 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64, r = k + blockIdx.x * (kCT / 64) + threadIdx.x / 64;
   if (r >= f) return;
-  if (r < k) {
-    if (lane == 0) y[ck.fd_dof[fd + r]] = vo[r];
-    return;
-  }
+  const int64_t fd = ck.fd_ptr[x];
   const T *row = Fm + ck.fo[x] + (int64_t)r * f;
+  const T *v = cv + fd;
   double acc = 0.0;
-  for (int c = lane; c < k; c += 64) acc += (double)row[c] * (double)vo[c];
+  for (int c = lane; c < k; c += 64) acc += (double)row[c] * (double)v[c];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) {
-    double v = acc;
     const int64_t pos = fd + r;
-    if (ck.src0[pos] >= 0) v += (double)upd[ck.src0[pos]];
-    if (ck.src1[pos] >= 0) v += (double)upd[ck.src1[pos]];
-    upd[ck.uo[x] + r - k] = (T)v;
+    if (ck.src0[pos] >= 0) acc += (double)upd[ck.src0[pos]];
+    if (ck.src1[pos] >= 0) acc += (double)upd[ck.src1[pos]];
+    upd[ck.uo[x] + r - k] = (T)acc;
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kCT) void k_bwd1(CoarseK ck, int lev, const T *__restrict__ Fm, const T *__restrict__ y,
-                                              T *__restrict__ xs) {
+__global__ __launch_bounds__(kCT) void k_bwd_gather(CoarseK ck, int lev, const T *__restrict__ y,
+                                                    const T *__restrict__ xs, T *__restrict__ cv) {
+  const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
+  const int c = blockIdx.x * kCT + threadIdx.x;
+  if (c >= ck.ff[x]) return;
+  const int64_t pos = ck.fd_ptr[x] + c;
+  cv[pos] = c < ck.fk[x] ? y[ck.fd_dof[pos]] : -xs[ck.fd_dof[pos]];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCT) void k_bwd_rows(CoarseK ck, int lev, const T *__restrict__ Fm,
+                                                  const T *__restrict__ cv, T *__restrict__ xs) {
   const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
   const int k = ck.fk[x], f = ck.ff[x];
-  const int rows_per = kCT / 64;
-  const int lane = threadIdx.x % 64, r = blockIdx.x * rows_per + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64, r = blockIdx.x * (kCT / 64) + threadIdx.x / 64;
   if (r >= k) return;
   const int64_t fd = ck.fd_ptr[x];
   const T *row = Fm + ck.fo[x] + (int64_t)r * f;
+  const T *v = cv + fd;
   double acc = 0.0;
-  for (int c = lane; c < k; c += 64) acc += (double)row[c] * (double)y[ck.fd_dof[fd + c]];
-  for (int c = k + lane; c < f; c += 64) acc -= (double)row[c] * (double)xs[ck.fd_dof[fd + c]];
+  for (int c = lane; c < f; c += 64) acc += (double)row[c] * (double)v[c];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) xs[ck.fd_dof[fd + r]] = (T)acc;
@@ -673,28 +687,32 @@ hipError_t coarse_s_correct(const KParams &kp, const CoarseK &ck, const double *
 }
 
 template <typename T>
-hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const T *F, const T *b, T *upd, T *y, T *xs,
-                         hipStream_t st) {
+hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const T *F, const T *b, T *upd, T *y, T *cv,
+                         T *xs, hipStream_t st) {
   constexpr int RP = kCT / 64;
   for (int l = 0; l < hv.n_levels; ++l) {
     const int nodes = hv.level_ptr[l + 1] - hv.level_ptr[l];
     if (!nodes) continue;
-    const size_t sh = (size_t)std::max(hv.level_maxk[l], 1) * sizeof(T);
-    hipLaunchKernelGGL((k_fwd1<T>), dim3((hv.level_maxf[l] + RP - 1) / RP, nodes), dim3(kCT), sh, st, ck, l, F, b,
-                       upd, y);
+    hipLaunchKernelGGL((k_fwd_own<T>), dim3((std::max(hv.level_maxk[l], 1) + kCT - 1) / kCT, nodes), dim3(kCT), 0, st, ck, l, b,
+                       upd, y, cv);
+    if (hv.level_maxf_minus_k[l] > 0)
+      hipLaunchKernelGGL((k_fwd_rows<T>), dim3((hv.level_maxf_minus_k[l] + RP - 1) / RP, nodes), dim3(kCT), 0, st,
+                         ck, l, F, cv, upd);
   }
   for (int l = hv.n_levels - 1; l >= 0; --l) {
     const int nodes = hv.level_ptr[l + 1] - hv.level_ptr[l];
     if (!nodes) continue;
-    hipLaunchKernelGGL((k_bwd1<T>), dim3((hv.level_maxk[l] + RP - 1) / RP, nodes), dim3(kCT), 0, st, ck, l, F, y,
-                       xs);
+    hipLaunchKernelGGL((k_bwd_gather<T>), dim3((std::max(hv.level_maxf[l], 1) + kCT - 1) / kCT, nodes), dim3(kCT), 0, st, ck, l,
+                       y, xs, cv);
+    hipLaunchKernelGGL((k_bwd_rows<T>), dim3((std::max(hv.level_maxk[l], 1) + RP - 1) / RP, nodes), dim3(kCT), 0, st, ck, l, F,
+                       cv, xs);
   }
   return hipGetLastError();
 }
 template hipError_t coarse_solve1<double>(const CoarseK &, const CoarseHostView &, const double *, const double *,
-                                          double *, double *, double *, hipStream_t);
+                                          double *, double *, double *, double *, hipStream_t);
 template hipError_t coarse_solve1<float>(const CoarseK &, const CoarseHostView &, const float *, const float *,
-                                         float *, float *, float *, hipStream_t);
+                                         float *, float *, float *, float *, hipStream_t);
 
 template <typename T>
 hipError_t coarse_q(const KParams &kp, const CoarseK &ck, const T *Cf, const T *W, const T *vu, const T *vp,
