@@ -310,34 +310,38 @@ def penny_problem(n: int, order: int, seed: int, material: Material, q0: float,
 def multicrack_problem(n: int, order: int, seed: int, material: Material, q0: float,
                        n_disks: int = 3, radius: float = 0.05, load_steps: int = 5,
                        name: str = "") -> Problem:
-    """Several pre-cracked disks of random centre (U[0.3, 0.7]^3) and normal
-    (uniform on the sphere) in a Kuhn-meshed unit cube.  A face belongs to a
-    disk when the centroids of its two elements lie on opposite sides of the
-    disk plane; it is pre-cracked when its centroid projects within
-    ``radius`` of the disk centre and cohesive within ``radius + 2h``.  One
-    injection per disk at the nearest crack vertex.
+    """Several pre-cracked disks in a Kuhn-meshed unit cube, of random centre
+    (U[0.3, 0.7]^3) and random orientation among the three coordinate planes
+    the mesh resolves: disk k lies on the grid plane x_a = l h nearest its
+    centre, a drawn from {x, y, z}, and the vertices on that plane keep their
+    normal coordinate (no jitter across it), so the crack is flat and made of
+    whole mesh faces.  Its faces are the faces of that plane whose centroid
+    lies within ``radius`` of the disk centre (pre-cracked) or within
+    ``radius + 2h`` (cohesive).  One injection per disk at the crack vertex
+    nearest its centre.
     """
-    xyz, elem, grid = kuhn3d(n, seed)
     h = 1.0 / n
     u = uniform(seed, STREAM_DISK, 5 * n_disks).reshape(n_disks, 5)
-    faces, e_lo, e_hi = interior_faces(elem)
-    cent_e = xyz[elem].mean(axis=1)
+    centres = 0.3 + 0.4 * u[:, :3]
+    axes = np.minimum((3.0 * u[:, 3]).astype(np.int64), 2)
+    levels = np.rint(centres[np.arange(n_disks), axes] * n).astype(np.int64)
+    xyz, elem, grid = kuhn3d(n, seed)
+    for a, lev in zip(axes, levels):
+        xyz[grid[:, a] == lev, a] = lev * h
+    faces, _, _ = interior_faces(elem)
     cent_f = xyz[faces].mean(axis=1)
     state = np.zeros(len(faces), dtype=np.uint8)
     srcs = []
     for k in range(n_disks):
-        c = 0.3 + 0.4 * u[k, :3]
-        zc = 2.0 * u[k, 3] - 1.0
-        ph = 2.0 * math.pi * u[k, 4]
-        s = math.sqrt(max(0.0, 1.0 - zc * zc))
-        nrm = np.array([s * math.cos(ph), s * math.sin(ph), zc])
-        side_lo = (cent_e[e_lo] - c) @ nrm
-        side_hi = (cent_e[e_hi] - c) @ nrm
-        cross = (side_lo * side_hi) < 0.0
+        a, lev = int(axes[k]), int(levels[k])
+        c = centres[k].copy()
+        c[a] = lev * h
+        inplane = np.all(grid[faces][:, :, a] == lev, axis=1)
         rel = cent_f - c
-        rproj = np.linalg.norm(rel - np.outer(rel @ nrm, nrm), axis=1)
-        pre = cross & (rproj < radius)
-        ring = cross & (rproj >= radius) & (rproj < radius + 2.0 * h)
+        rel[:, a] = 0.0
+        rproj = np.linalg.norm(rel, axis=1)
+        pre = inplane & (rproj < radius)
+        ring = inplane & (rproj >= radius) & (rproj < radius + 2.0 * h)
         state[ring & (state == 0)] = 1
         state[pre] = 2
         if np.any(pre):
@@ -381,7 +385,8 @@ def config(idx: int) -> Problem:
     2: 3D penny, Kuhn n=20 -> 48,000 P2 tets, 1.44M DOF
     3: 3D penny, Kuhn n=40 -> 384,000 P2 tets, 11.52M DOF, viscosity params
     4: ensemble of 64 2D KGD instances (use ``ensemble()``)
-    5: 3D three-disk multi-crack, Kuhn n=32 -> 196,608 P2 tets, 5.90M DOF
+    5: 3D three-disk multi-crack, Kuhn n=32 -> 196,608 P2 tets, 5.90M DOF (disks on
+       coordinate planes of the mesh, see ``multicrack_problem``)
     """
     if idx == 1:
         mat = Material(E=1.0, nu=0.25, sigma_c=1e-3, G_c=1e-4, mu=1e-3, dt=1.0)
