@@ -158,7 +158,7 @@ typedef struct {
                           two-level build of a context */
   int coarse_reuse;    /* two-level builds that keep the last coarse
                           factorisation (and Z_c = A_c^-1 P^T B) instead of
-                          refactorising P^T A P, 0..1000 (default 4): the
+                          refactorising P^T A P, 0..1000 (default 16): the
                           coarse matrix then lags the current one in the
                           rows of cracked elements, the only blocks that
                           change between Newton iterations; A P, W and the
@@ -244,7 +244,13 @@ typedef struct {
                           inverted with one grid-wide launch pair per pivot
                           step, the smaller ones by one workgroup each
                           (0 = 192; the same arithmetic either way) */
-  int reserved[2];
+  int inv_var;         /* element-block inverses of the FP32-IR
+                          preconditioner (block size 30): 0 = as
+                          hf_options.mfma_inverse, 1 = FP32 Gauss-Jordan on
+                          the matrix cores, 2 = FP64 Gauss-Jordan rounded to
+                          FP32; hf_autotune (level >= 0, FP32-IR) times both
+                          on every block and keeps the faster */
+  int reserved;
 } hf_tuning;
 
 typedef struct {

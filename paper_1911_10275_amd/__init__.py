@@ -80,11 +80,11 @@ class NewtonStats(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("spmv_var", C.c_int), ("prec_var", C.c_int), ("ortho_var", C.c_int),
                 ("reorth", C.c_int), ("gmres_m", C.c_int), ("dense_wide_min", C.c_int),
-                ("reserved", C.c_int * 2)]
+                ("inv_var", C.c_int), ("reserved", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k in ("spmv_var", "prec_var", "ortho_var", "reorth",
-                                               "gmres_m")}
+                                               "gmres_m", "inv_var")}
 
 
 class Profile(C.Structure):

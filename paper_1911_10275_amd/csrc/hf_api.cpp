@@ -492,7 +492,7 @@ extern "C" void hf_default_options(hf_options *o) {
   o->fold_preconditioner = 1;
   o->two_level = 0;
   o->coarse_leaf = 64;
-  o->coarse_reuse = 4;
+  o->coarse_reuse = 16;
   o->stream = nullptr;
 }
 
@@ -2148,7 +2148,7 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
   // inverses only where the Schur pressure block needs them (elements with
   // coupling strips); otherwise (and as the fallback) FP64 Gauss-Jordan for
   // every block, rounded for the FP32 copy
-  const bool mfma = ir && s.bu == 30 && ctx->opt.mfma_inverse;
+  const bool mfma = ir && s.bu == 30 && (ctx->tune.inv_var ? ctx->tune.inv_var == 1 : ctx->opt.mfma_inverse != 0);
   // the constant blocks' inverses are kept from the last full assembly: only
   // the elements with cohesive or fluid interfaces need new ones
   const bool cached = ctx->lin_valid && ctx->opt.incremental_assembly;
@@ -3177,7 +3177,7 @@ extern "C" hf_status hf_set_tuning(hf_ctx *ctx, const hf_tuning *t) {
   if (!ctx || !t) return HF_EINVAL;
   if (t->spmv_var < 0 || t->spmv_var > 1 || t->prec_var < 0 || t->prec_var > 1 || t->ortho_var < 0 ||
       t->ortho_var > 2 || t->reorth < 0 || t->reorth > 4 || t->gmres_m < 0 || t->gmres_m > kMaxKrylov - 1 ||
-      t->dense_wide_min < 0)
+      t->dense_wide_min < 0 || t->inv_var < 0 || t->inv_var > 2)
     return fail(ctx, HF_EINVAL, "tuning value out of range");
   release_all_graphs(ctx);  // the captured chunks hold the old schedule
   ctx->tune = *t;
@@ -3291,6 +3291,7 @@ extern "C" hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path,
       std::string k;
       hf_tuning t{};
       if (ls >> k >> t.spmv_var >> t.prec_var >> t.ortho_var >> t.reorth >> t.gmres_m && k == key) {
+        if (!(ls >> t.inv_var)) t.inv_var = 0;  // lines written before the block-inverse choice
         TRY(hf_set_tuning(ctx, &t));
         if (out) TRY(hf_get_tuning(ctx, out));
         return HF_OK;
@@ -3318,6 +3319,23 @@ extern "C" hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path,
     TRY(tune_kernels<float>(ctx, op, ctx->k32, best));
   }
   best.gmres_m = ctx->opt.gmres_m;
+  if (ctx->opt.precision == HF_FP32_IR && ctx->s.bu == 30 && ctx->inv32) {
+    // block-inverse schedule: FP32 Gauss-Jordan on the matrix cores against
+    // FP64 Gauss-Jordan rounded to FP32, every block, on the assembled blocks
+    const KParams kp = kparams(ctx);
+    double t_mfma = 0.0, t_gj = 0.0;
+    TRY(time_ms(ctx, 3, [&]() -> hf_status {
+      HIPCHK(launch_blockinv32_mfma(kp, ctx->A, ctx->inv32, nullptr, ctx->s.ne, ctx->flag, ctx->stream));
+      return HF_OK;
+    }, t_mfma));
+    TRY(time_ms(ctx, 3, [&]() -> hf_status {
+      HIPCHK(launch_blockinv(kp, ctx->A, ctx->inv, ctx->inv32, nullptr, ctx->s.ne, ctx->flag, ctx->stream));
+      return HF_OK;
+    }, t_gj));
+    HIPCHK(hipMemsetAsync(ctx->flag, 0, nI(ctx) * sizeof(int), ctx->stream));
+    best.inv_var = t_mfma <= t_gj ? 1 : 2;
+    ctx->inv32_epoch = -1;  // both variants wrote inv32: the next build makes every block anew
+  }
   TRY(hf_set_tuning(ctx, &best));
   if (level >= 1) {
     double best_s = 1e300;
@@ -3357,7 +3375,7 @@ extern "C" hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path,
     TRY(hf_get_tuning(ctx, &t));
     std::ofstream o(cache_path, std::ios::app);
     o << key << " " << t.spmv_var << " " << t.prec_var << " " << t.ortho_var << " " << t.reorth << " "
-      << t.gmres_m << "\n";
+      << t.gmres_m << " " << t.inv_var << "\n";
   }
   return HF_OK;
 }
