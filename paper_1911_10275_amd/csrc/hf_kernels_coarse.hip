@@ -549,13 +549,33 @@ __global__ __launch_bounds__(64) void k_tl_q(KParams kp, CoarseK ck, const T *__
 }
 
 // t = v_u - B z_p - AP z_c2 and apz = AP z_c2: thread per (element, row)
+// columns of one element row of A P whose coarse values a workgroup stages in
+// LDS (an element touches at most 20 vertex classes: 60 columns in 3D)
+constexpr int kTlCols = 96;
+
 template <typename T>
 __global__ __launch_bounds__(kCT) void k_tl_t(KParams kp, CoarseK ck, const T *__restrict__ AP,
                                               const T *__restrict__ Bs, const T *__restrict__ vu,
                                               const T *__restrict__ zp, const T *__restrict__ zc,
                                               T *__restrict__ t_out, T *__restrict__ apz) {
+  // the workgroup's elements (at most kCT / 6 + 2 for block sizes >= 6) get
+  // their z_c values staged once, so the row loop streams A P alone
+  constexpr int EMAX = kCT / 6 + 2;
+  __shared__ double zs[EMAX * kTlCols];
   const int bu = kp.s.bu, dim = ck.dim;
-  const int64_t t = blockIdx.x * (int64_t)kCT + threadIdx.x;
+  const int64_t t0 = blockIdx.x * (int64_t)kCT;
+  const int64_t e0 = t0 / bu;
+  const int64_t e1 = (std::min<int64_t>(t0 + kCT, kp.s.n_u) - 1) / bu;
+  const int ne_b = (int)(e1 - e0 + 1);
+  for (int i = threadIdx.x; i < ne_b * kTlCols; i += kCT) {
+    const int64_t e = e0 + i / kTlCols;
+    const int col = i % kTlCols;
+    const int64_t c0 = ck.ap_ptr[e];
+    if (col < (int)(ck.ap_ptr[e + 1] - c0) * dim)
+      zs[i] = (double)zc[(int64_t)ck.ap_cls[c0 + col / dim] * dim + col % dim];
+  }
+  __syncthreads();
+  const int64_t t = t0 + threadIdx.x;
   if (t >= kp.s.n_u) return;
   const int64_t e = t / bu;
   const int r = (int)(t % bu);
@@ -563,8 +583,13 @@ __global__ __launch_bounds__(kCT) void k_tl_t(KParams kp, CoarseK ck, const T *_
   const int ncol = (int)(ck.ap_ptr[e + 1] - c0) * dim;
   const T *ap = AP + c0 * dim * bu + r;
   double acc = 0.0;
-  for (int col = 0; col < ncol; ++col)
-    acc += (double)ap[(int64_t)col * bu] * (double)zc[(int64_t)ck.ap_cls[c0 + col / dim] * dim + col % dim];
+  if (ncol <= kTlCols) {
+    const double *z = zs + (e - e0) * kTlCols;
+    for (int col = 0; col < ncol; ++col) acc += (double)ap[(int64_t)col * bu] * z[col];
+  } else {
+    for (int col = 0; col < ncol; ++col)
+      acc += (double)ap[(int64_t)col * bu] * (double)zc[(int64_t)ck.ap_cls[c0 + col / dim] * dim + col % dim];
+  }
   double bz = 0.0;
   for (int64_t s = kp.m.sp_ptr[e]; s < kp.m.sp_ptr[e + 1]; ++s)
     bz += (double)Bs[s * bu + r] * (double)zp[kp.m.sp_pnode[s]];
