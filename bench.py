@@ -301,6 +301,8 @@ def main():
                          "paper_1911_10275_amd/tuning_cache.txt")
     ap.add_argument("--ensemble-steps", type=int, default=3)
     ap.add_argument("--ensemble-m", type=int, default=120, help="GMRES restart length, ensemble")
+    ap.add_argument("--coarse-fp32", type=int, default=1, choices=(0, 1),
+                    help="1: FP64 solves apply the coarse factorisation rounded to FP32")
     ap.add_argument("--two-level", type=int, default=1, choices=(0, 1),
                     help="1: two-level block preconditioner, 0: block-Jacobi")
     ap.add_argument("--counters", action="store_true",
@@ -325,7 +327,7 @@ def main():
           file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream().cuda_stream
     ctx = hf.context_for_problem(prob, device=0, stream=stream, gmres_m=args.gmres_m,
-                                 two_level=args.two_level)
+                                 two_level=args.two_level, coarse_fp32=args.coarse_fp32)
     sz = ctx.sizes
     N = sz.n_u + sz.n_p
 
@@ -380,7 +382,8 @@ def main():
         "config": {"workload": prob.name, "elements": int(sz.n_elem), "dof": int(N),
                    "u_dof": int(sz.n_u), "p_dof": int(sz.n_p), "element": f"P{prob.order}",
                    "dim": prob.dim, "precision": "fp64",
-                   "preconditioner": "two-level" if args.two_level else "block-Jacobi",
+                   "preconditioner": ("two-level" + (", coarse factor in FP32" if args.coarse_fp32 else ""))
+                   if args.two_level else "block-Jacobi",
                    "gmres_m": tuned.get("fp64", {}).get("gmres_m", args.gmres_m), "rtol": 1e-10},
         "median_step_ms": 1e3 * float(np.median([x[7] for x in st64])),
         "gmres": {"iters_per_step": float(np.mean(iters64)),

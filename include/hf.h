@@ -167,6 +167,14 @@ typedef struct {
                           factorisation built on that coarse matrix.  A full
                           assembly or a failed build forces a new
                           factorisation; 0 refactorises at every build */
+  int coarse_fp32;     /* 1: the coarse factorisation is rounded to FP32
+                          once and FP64 solves apply that rounded factor
+                          (FP64 arithmetic, half the bytes per coarse
+                          solve); Z_c is computed with the same factor, so
+                          the preconditioner is an exact block
+                          factorisation on the rounded coarse matrix and
+                          every solve still reaches rtol; 0: FP64 factor
+                          (default 0) */
   void *stream;        /* hipStream_t to run on; NULL: a stream the ctx creates */
 } hf_options;
 

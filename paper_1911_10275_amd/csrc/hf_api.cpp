@@ -12,6 +12,7 @@
 // has converged or failed is masked out of the rest of a solve; the status of
 // every instance is reported separately.
 #include <algorithm>
+#include <type_traits>
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -72,6 +73,7 @@ struct TlBuf {
   T *rc1 = nullptr, *rc2 = nullptr, *zc1 = nullptr, *zc2 = nullptr, *y = nullptr, *upd = nullptr;
   T *q = nullptr, *zp = nullptr, *t = nullptr, *apz = nullptr, *cpy = nullptr;
   T *cv = nullptr;  // front vectors of the coarse solves (one entry per front position)
+  const float *F32 = nullptr;  // FP64 solves: the coarse factor stored in FP32 (coarse_fp32)
 };
 
 // concatenated host layout kept after hf_finalize for the coarse-space plan
@@ -174,7 +176,7 @@ struct hf_ctx {
   bool tl_ok = false;       // the last preconditioner build produced a usable coarse factor
   // the coarse factorisation kept across builds (coarse_reuse): valid, the
   // assembly epoch it was built in, builds since, FP32 copy current
-  bool c_valid = false, c_f32 = false;
+  bool c_valid = false, c_f32 = false, c_z32 = false, c_fp32 = false;
   int64_t c_epoch = -1;
   int c_age = 0;
   int graphs_tl = -1;       // two-level state the captured GMRES chunks were recorded with
@@ -493,6 +495,7 @@ extern "C" void hf_default_options(hf_options *o) {
   o->two_level = 0;
   o->coarse_leaf = 64;
   o->coarse_reuse = 16;
+  o->coarse_fp32 = 0;
   o->stream = nullptr;
 }
 
@@ -508,6 +511,7 @@ static hf_status validate_options(hf_ctx *ctx, const hf_options &o) {
   if (o.two_level != 0 && o.two_level != 1) return fail(ctx, HF_EINVAL, "two_level must be 0 or 1");
   if (o.coarse_leaf < 4 || o.coarse_leaf > 4096) return fail(ctx, HF_EINVAL, "coarse_leaf out of range 4..4096");
   if (o.coarse_reuse < 0 || o.coarse_reuse > 1000) return fail(ctx, HF_EINVAL, "coarse_reuse out of range 0..1000");
+  if (o.coarse_fp32 < 0 || o.coarse_fp32 > 1) return fail(ctx, HF_EINVAL, "coarse_fp32 must be 0 or 1");
   return HF_OK;
 }
 
@@ -1541,7 +1545,10 @@ static hf_status tl_first(hf_ctx *ctx, const KParams &kp, const Ops<T> &op, cons
   hipStream_t st = ctx->stream;
   const int64_t n_u = ctx->s.n_u;
   HIPCHK(coarse_restrict2<T>(kp, ck, v, b.cpy, b.rc1, st));
-  HIPCHK(coarse_solve1<T>(ck, ctx->chv, b.F, b.rc1, b.upd, b.y, b.cv, b.zc1, st));
+  if (std::is_same<T, double>::value && b.F32)
+    HIPCHK((coarse_solve1<T, float>(ck, ctx->chv, b.F32, b.rc1, b.upd, b.y, b.cv, b.zc1, st)));
+  else
+    HIPCHK((coarse_solve1<T, T>(ck, ctx->chv, b.F, b.rc1, b.upd, b.y, b.cv, b.zc1, st)));
   if (ctx->s.n_p) {
     HIPCHK(coarse_q<T>(kp, ck, op.Cf, b.W, v, v + n_u, b.zc1, b.q, wp, st));
     HIPCHK(coarse_pgemv<T>(kp, b.Sinv2, b.q, b.zp, st));
@@ -2070,7 +2077,7 @@ static hf_status tl_build(hf_ctx *ctx, int n_wide) {
     TRY(vecs(ctx->tb32));
     TRY(dalloc(ctx, &ctx->cAP32, ctx->c_ap_total));
     TRY(dalloc(ctx, &ctx->cW32, ctx->c_w_total));
-    TRY(dalloc(ctx, &ctx->cF32, std::max<int64_t>(ctx->cplan.front_total, 1)));
+    if (!ctx->cF32) TRY(dalloc(ctx, &ctx->cF32, std::max<int64_t>(ctx->cplan.front_total, 1)));
     if (s.n_p) TRY(dalloc(ctx, &ctx->cZ32, (int64_t)ctx->cplan.ncls * s.dim * ctx->c_nrhs));
     ctx->tb32.AP = ctx->cAP32;
     ctx->tb32.W = ctx->cW32;
@@ -2081,20 +2088,33 @@ static hf_status tl_build(hf_ctx *ctx, int n_wide) {
   }
   // keep the last coarse factorisation (and Z_c) while it is younger than
   // coarse_reuse builds and no full assembly has replaced A since
-  const bool reuse = ctx->c_valid && ctx->c_age < ctx->opt.coarse_reuse && ctx->c_epoch == ctx->lin_epoch;
+  const bool f32 = ctx->opt.coarse_fp32 != 0;  // FP64 solves read the factor rounded to FP32
+  const bool reuse = ctx->c_valid && ctx->c_age < ctx->opt.coarse_reuse && ctx->c_epoch == ctx->lin_epoch &&
+                     ctx->c_fp32 == f32;
+  if (f32 && !ctx->cF32) TRY(dalloc(ctx, &ctx->cF32, std::max<int64_t>(ctx->cplan.front_total, 1)));
   HIPCHK(hipMemsetAsync(ctx->cflag, 0, sizeof(int), st));
   HIPCHK(coarse_build_ap(kp, ck, ctx->A, nullptr, s.ne, ctx->cAP, st));
   HIPCHK(coarse_build_w(kp, ck, ctx->Cs, ctx->inv, ctx->cAP, ctx->cW, st));
   if (!reuse) {
     HIPCHK(coarse_factor(kp, ck, ctx->chv, ctx->cAP, ctx->cF, ctx->cCp, ctx->cDsc, ctx->cflag, st));
     ctx->c_f32 = false;
+    if (f32) {  // the rounded factor is the one every solve applies, Z_c included
+      HIPCHK(launch_convert(ctx->cF, ctx->cF32, ctx->cplan.front_total, st));
+      ctx->c_f32 = true;
+    }
+    ctx->c_fp32 = f32;
   }
+  ctx->tb64.F32 = f32 ? ctx->cF32 : nullptr;
   if (s.n_p) {
     const int nrhs = ctx->c_nrhs;
     if (!reuse) {
       HIPCHK(coarse_ptb(kp, ck, ctx->Bs, nrhs, ctx->cR, st));
-      HIPCHK(coarse_solve_multi(ck, ctx->chv, ctx->cF, ctx->cR, nrhs, ctx->cU, ctx->cY, ctx->cZ, st));
+      if (f32)
+        HIPCHK(coarse_solve_multi<float>(ck, ctx->chv, ctx->cF32, ctx->cR, nrhs, ctx->cU, ctx->cY, ctx->cZ, st));
+      else
+        HIPCHK(coarse_solve_multi<double>(ck, ctx->chv, ctx->cF, ctx->cR, nrhs, ctx->cU, ctx->cY, ctx->cZ, st));
     }
+    if (!reuse) ctx->c_z32 = false;
     HIPCHK(coarse_s_correct(kp, ck, ctx->cW, ctx->cZ, nrhs, ctx->S2, st));
     HIPCHK(launch_schur_invert(kp, ctx->S2, ctx->Sinv2, ctx->Sinv2_32, ctx->flag, n_wide, st));
     for (int b = 0; b < B; ++b) {
@@ -2109,8 +2129,11 @@ static hf_status tl_build(hf_ctx *ctx, int n_wide) {
     HIPCHK(launch_convert(ctx->cW, ctx->cW32, ctx->c_w_total, st));
     if (!ctx->c_f32) {
       HIPCHK(launch_convert(ctx->cF, ctx->cF32, ctx->cplan.front_total, st));
-      if (s.n_p) HIPCHK(launch_convert(ctx->cZ, ctx->cZ32, (int64_t)ctx->cplan.ncls * s.dim * ctx->c_nrhs, st));
       ctx->c_f32 = true;
+    }
+    if (!ctx->c_z32) {
+      if (s.n_p) HIPCHK(launch_convert(ctx->cZ, ctx->cZ32, (int64_t)ctx->cplan.ncls * s.dim * ctx->c_nrhs, st));
+      ctx->c_z32 = true;
     }
   }
   TRY(get_i_async(ctx, ctx->cflag, 1, 0));

@@ -233,13 +233,14 @@ hipError_t coarse_build_w(const KParams &kp, const CoarseK &ck, const double *Cs
 hipError_t coarse_factor(const KParams &kp, const CoarseK &ck, const CoarseHostView &hv, const double *AP,
                          double *F, double *Cp, double *Dsc, int *flag, hipStream_t st);
 hipError_t coarse_ptb(const KParams &kp, const CoarseK &ck, const double *Bs, int nrhs, double *R, hipStream_t st);
-hipError_t coarse_solve_multi(const CoarseK &ck, const CoarseHostView &hv, const double *F, const double *b,
+template <typename TF>
+hipError_t coarse_solve_multi(const CoarseK &ck, const CoarseHostView &hv, const TF *F, const double *b,
                               int nrhs, double *upd, double *y, double *xs, hipStream_t st);
 hipError_t coarse_s_correct(const KParams &kp, const CoarseK &ck, const double *W, const double *Z, int nrhs,
                             double *S, hipStream_t st);
 // one coarse solve xs = A_c^-1 b; upd, y and the front vectors cv are scratch
-template <typename T>
-hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const T *F, const T *b, T *upd, T *y, T *cv,
+template <typename T, typename TF>
+hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const TF *F, const T *b, T *upd, T *y, T *cv,
                          T *xs, hipStream_t st);
 // q' = v_p - (Cf v_u + W z_c) per pressure row; w_p = v_p when wp != null
 template <typename T>

@@ -375,15 +375,15 @@ __global__ __launch_bounds__(kCT) void k_fwd_own(CoarseK ck, int lev, const T *_
   cv[pos] = v;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kCT) void k_fwd_rows(CoarseK ck, int lev, const T *__restrict__ Fm,
+template <typename T, typename TF>
+__global__ __launch_bounds__(kCT) void k_fwd_rows(CoarseK ck, int lev, const TF *__restrict__ Fm,
                                                   const T *__restrict__ cv, T *__restrict__ upd) {
   const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
   const int k = ck.fk[x], f = ck.ff[x];
   const int lane = threadIdx.x % 64, r = k + blockIdx.x * (kCT / 64) + threadIdx.x / 64;
   if (r >= f) return;
   const int64_t fd = ck.fd_ptr[x];
-  const T *row = Fm + ck.fo[x] + (int64_t)r * f;
+  const TF *row = Fm + ck.fo[x] + (int64_t)r * f;
   const T *v = cv + fd;
   double acc = 0.0;
   for (int c = lane; c < k; c += 64) acc += (double)row[c] * (double)v[c];
@@ -407,15 +407,15 @@ __global__ __launch_bounds__(kCT) void k_bwd_gather(CoarseK ck, int lev, const T
   cv[pos] = c < ck.fk[x] ? y[ck.fd_dof[pos]] : -xs[ck.fd_dof[pos]];
 }
 
-template <typename T>
-__global__ __launch_bounds__(kCT) void k_bwd_rows(CoarseK ck, int lev, const T *__restrict__ Fm,
+template <typename T, typename TF>
+__global__ __launch_bounds__(kCT) void k_bwd_rows(CoarseK ck, int lev, const TF *__restrict__ Fm,
                                                   const T *__restrict__ cv, T *__restrict__ xs) {
   const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
   const int k = ck.fk[x], f = ck.ff[x];
   const int lane = threadIdx.x % 64, r = blockIdx.x * (kCT / 64) + threadIdx.x / 64;
   if (r >= k) return;
   const int64_t fd = ck.fd_ptr[x];
-  const T *row = Fm + ck.fo[x] + (int64_t)r * f;
+  const TF *row = Fm + ck.fo[x] + (int64_t)r * f;
   const T *v = cv + fd;
   double acc = 0.0;
   for (int c = lane; c < f; c += 64) acc += (double)row[c] * (double)v[c];
@@ -437,7 +437,8 @@ __global__ __launch_bounds__(kCT) void k_fwdm_own(CoarseK ck, int lev, const dou
   y[(int64_t)ck.fd_dof[pos] * nrhs + j] = own_rhs<double>(ck, pos, b, upd, nrhs, j);
 }
 
-__global__ __launch_bounds__(kCT) void k_fwdm_upd(CoarseK ck, int lev, const double *__restrict__ Fm,
+template <typename TF>
+__global__ __launch_bounds__(kCT) void k_fwdm_upd(CoarseK ck, int lev, const TF *__restrict__ Fm,
                                                   const double *__restrict__ y, int nrhs, double *upd) {
   const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
   const int k = ck.fk[x], f = ck.ff[x];
@@ -445,16 +446,17 @@ __global__ __launch_bounds__(kCT) void k_fwdm_upd(CoarseK ck, int lev, const dou
   if (t >= (int64_t)(f - k) * nrhs) return;
   const int r = k + (int)(t / nrhs), j = (int)(t % nrhs);
   const int64_t fd = ck.fd_ptr[x], pos = fd + r;
-  const double *row = Fm + ck.fo[x] + (int64_t)r * f;
+  const TF *row = Fm + ck.fo[x] + (int64_t)r * f;
   double acc = 0.0;
-  for (int c = 0; c < k; ++c) acc += row[c] * y[(int64_t)ck.fd_dof[fd + c] * nrhs + j];
+  for (int c = 0; c < k; ++c) acc += (double)row[c] * y[(int64_t)ck.fd_dof[fd + c] * nrhs + j];
   if (ck.src0[pos] >= 0) acc += upd[ck.src0[pos] * nrhs + j];
   if (ck.src1[pos] >= 0) acc += upd[ck.src1[pos] * nrhs + j];
   // the children's rows read here belong to lower levels (earlier launches)
   upd[(ck.uo[x] + r - k) * nrhs + j] = acc;
 }
 
-__global__ __launch_bounds__(kCT) void k_bwdm(CoarseK ck, int lev, const double *__restrict__ Fm,
+template <typename TF>
+__global__ __launch_bounds__(kCT) void k_bwdm(CoarseK ck, int lev, const TF *__restrict__ Fm,
                                               const double *__restrict__ y, int nrhs, double *__restrict__ xs) {
   const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
   const int k = ck.fk[x], f = ck.ff[x];
@@ -462,10 +464,10 @@ __global__ __launch_bounds__(kCT) void k_bwdm(CoarseK ck, int lev, const double 
   if (t >= (int64_t)k * nrhs) return;
   const int r = (int)(t / nrhs), j = (int)(t % nrhs);
   const int64_t fd = ck.fd_ptr[x];
-  const double *row = Fm + ck.fo[x] + (int64_t)r * f;
+  const TF *row = Fm + ck.fo[x] + (int64_t)r * f;
   double acc = 0.0;
-  for (int c = 0; c < k; ++c) acc += row[c] * y[(int64_t)ck.fd_dof[fd + c] * nrhs + j];
-  for (int c = k; c < f; ++c) acc -= row[c] * xs[(int64_t)ck.fd_dof[fd + c] * nrhs + j];
+  for (int c = 0; c < k; ++c) acc += (double)row[c] * y[(int64_t)ck.fd_dof[fd + c] * nrhs + j];
+  for (int c = k; c < f; ++c) acc -= (double)row[c] * xs[(int64_t)ck.fd_dof[fd + c] * nrhs + j];
   xs[(int64_t)ck.fd_dof[fd + r] * nrhs + j] = acc;
 }
 
@@ -684,7 +686,8 @@ hipError_t coarse_ptb(const KParams &kp, const CoarseK &ck, const double *Bs, in
   return hipGetLastError();
 }
 
-hipError_t coarse_solve_multi(const CoarseK &ck, const CoarseHostView &hv, const double *F, const double *b,
+template <typename TF>
+hipError_t coarse_solve_multi(const CoarseK &ck, const CoarseHostView &hv, const TF *F, const double *b,
                               int nrhs, double *upd, double *y, double *xs, hipStream_t st) {
   for (int l = 0; l < hv.n_levels; ++l) {
     const int nodes = hv.level_ptr[l + 1] - hv.level_ptr[l];
@@ -693,16 +696,21 @@ hipError_t coarse_solve_multi(const CoarseK &ck, const CoarseHostView &hv, const
                        b, upd, nrhs, y);
     const int64_t mu = (int64_t)(hv.level_maxf_minus_k[l]) * nrhs;
     if (mu > 0)
-      hipLaunchKernelGGL(k_fwdm_upd, dim3(nblk(mu), nodes), dim3(kCT), 0, st, ck, l, F, y, nrhs, upd);
+      hipLaunchKernelGGL((k_fwdm_upd<TF>), dim3(nblk(mu), nodes), dim3(kCT), 0, st, ck, l, F, y, nrhs, upd);
   }
   for (int l = hv.n_levels - 1; l >= 0; --l) {
     const int nodes = hv.level_ptr[l + 1] - hv.level_ptr[l];
     if (!nodes) continue;
-    hipLaunchKernelGGL(k_bwdm, dim3(nblk((int64_t)hv.level_maxk[l] * nrhs), nodes), dim3(kCT), 0, st, ck, l, F, y,
+    hipLaunchKernelGGL((k_bwdm<TF>), dim3(nblk((int64_t)hv.level_maxk[l] * nrhs), nodes), dim3(kCT), 0, st, ck, l, F, y,
                        nrhs, xs);
   }
   return hipGetLastError();
 }
+
+template hipError_t coarse_solve_multi<double>(const CoarseK &, const CoarseHostView &, const double *,
+                                               const double *, int, double *, double *, double *, hipStream_t);
+template hipError_t coarse_solve_multi<float>(const CoarseK &, const CoarseHostView &, const float *,
+                                              const double *, int, double *, double *, double *, hipStream_t);
 
 hipError_t coarse_s_correct(const KParams &kp, const CoarseK &ck, const double *W, const double *Z, int nrhs,
                             double *S, hipStream_t st) {
@@ -711,8 +719,8 @@ hipError_t coarse_s_correct(const KParams &kp, const CoarseK &ck, const double *
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const T *F, const T *b, T *upd, T *y, T *cv,
+template <typename T, typename TF>
+hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const TF *F, const T *b, T *upd, T *y, T *cv,
                          T *xs, hipStream_t st) {
   constexpr int RP = kCT / 64;
   for (int l = 0; l < hv.n_levels; ++l) {
@@ -721,7 +729,7 @@ hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const T *F
     hipLaunchKernelGGL((k_fwd_own<T>), dim3((std::max(hv.level_maxk[l], 1) + kCT - 1) / kCT, nodes), dim3(kCT), 0, st, ck, l, b,
                        upd, y, cv);
     if (hv.level_maxf_minus_k[l] > 0)
-      hipLaunchKernelGGL((k_fwd_rows<T>), dim3((hv.level_maxf_minus_k[l] + RP - 1) / RP, nodes), dim3(kCT), 0, st,
+      hipLaunchKernelGGL((k_fwd_rows<T, TF>), dim3((hv.level_maxf_minus_k[l] + RP - 1) / RP, nodes), dim3(kCT), 0, st,
                          ck, l, F, cv, upd);
   }
   for (int l = hv.n_levels - 1; l >= 0; --l) {
@@ -729,15 +737,17 @@ hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const T *F
     if (!nodes) continue;
     hipLaunchKernelGGL((k_bwd_gather<T>), dim3((std::max(hv.level_maxf[l], 1) + kCT - 1) / kCT, nodes), dim3(kCT), 0, st, ck, l,
                        y, xs, cv);
-    hipLaunchKernelGGL((k_bwd_rows<T>), dim3((std::max(hv.level_maxk[l], 1) + RP - 1) / RP, nodes), dim3(kCT), 0, st, ck, l, F,
+    hipLaunchKernelGGL((k_bwd_rows<T, TF>), dim3((std::max(hv.level_maxk[l], 1) + RP - 1) / RP, nodes), dim3(kCT), 0, st, ck, l, F,
                        cv, xs);
   }
   return hipGetLastError();
 }
-template hipError_t coarse_solve1<double>(const CoarseK &, const CoarseHostView &, const double *, const double *,
-                                          double *, double *, double *, double *, hipStream_t);
-template hipError_t coarse_solve1<float>(const CoarseK &, const CoarseHostView &, const float *, const float *,
-                                         float *, float *, float *, float *, hipStream_t);
+template hipError_t coarse_solve1<double, double>(const CoarseK &, const CoarseHostView &, const double *,
+                                                  const double *, double *, double *, double *, double *, hipStream_t);
+template hipError_t coarse_solve1<double, float>(const CoarseK &, const CoarseHostView &, const float *,
+                                                 const double *, double *, double *, double *, double *, hipStream_t);
+template hipError_t coarse_solve1<float, float>(const CoarseK &, const CoarseHostView &, const float *, const float *,
+                                                float *, float *, float *, float *, hipStream_t);
 
 template <typename T>
 hipError_t coarse_q(const KParams &kp, const CoarseK &ck, const T *Cf, const T *W, const T *vu, const T *vp,

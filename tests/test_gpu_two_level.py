@@ -251,3 +251,38 @@ def test_coarse_reuse_keeps_the_factorisation_and_the_results(precision):
     n3, f3 = builds[3]
     assert f0 == n0 and n3 >= 4
     assert f3 == -(-n3 // 4)   # one factorisation per four builds
+
+
+@pytest.mark.parametrize("precision", [hf.HF_FP64, hf.HF_FP32_IR], ids=["fp64", "fp32ir"])
+def test_coarse_factor_in_fp32_keeps_the_results(precision):
+    """coarse_fp32 = 1: FP64 solves apply the coarse factorisation rounded to
+    FP32 (Z_c computed with the same rounded factor).  The operator moves from
+    the exact-coarse reference by about the FP32 rounding of the coarse
+    correction, and the load steps still end at the oracle's states."""
+    name = "3d_p2_n4"
+    prob = SMALL[name]()
+    case = Case.from_problem(prob)
+    ctx = hf.context_for_problem(prob, two_level=1, coarse_fp32=1)
+    u, p, wo = _state(case, 5)
+    ctx.set_state(u, p, wo)
+    ctx.assemble()
+    st = ctx.solve()
+    assert st.status == hf.HF_OK and st.true_relres <= 1e-10
+    S = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, newton.fluid_scale(case, wo, u),
+                     case.src_pnode, case.src_q0)
+    x = np.random.default_rng(2).normal(size=ctx.sizes.n_total)
+    xd = torch.tensor(x, device="cuda")
+    yd = torch.empty_like(xd)
+    ctx.apply_preconditioned(xd.data_ptr(), yd.data_ptr(), hf.HF_FP64, folded=2)
+    torch.cuda.synchronize()
+    ref = reference_operator(case, S, x)
+    err = np.abs(yd.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert 1e-12 < err <= 1e-5, err
+    ctx.close()
+    ref_steps = newton.run(case, prob.load_steps, solver="gmres")
+    ctx = hf.context_for_problem(prob, two_level=1, coarse_fp32=1)
+    got = _load_steps(ctx, case, prob.load_steps, precision)
+    ctx.close()
+    for (st, _), ((u, p, w, wo), ns) in zip(ref_steps, got):
+        assert np.linalg.norm(u - st.u) <= 1e-8 * np.linalg.norm(st.u)
+        assert np.linalg.norm(p - st.p) <= 1e-8 * np.linalg.norm(st.p)
