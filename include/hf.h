@@ -175,6 +175,11 @@ typedef struct {
                           factorisation on the rounded coarse matrix and
                           every solve still reaches rtol; 0: FP64 factor
                           (default 0) */
+  int scale_fluid_rows; /* 1: the fluid rows carry the scale s_p of
+                          hf_set_state (default 1); 0: s_p = 1, the rows of
+                          eq. (discreteLubrication) as written.  The Newton
+                          iterates do not depend on it; the relative
+                          residuals of the linear solves do */
   void *stream;        /* hipStream_t to run on; NULL: a stream the ctx creates */
 } hf_options;
 

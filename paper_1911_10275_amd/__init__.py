@@ -49,6 +49,7 @@ class Options(C.Structure):
                 ("incremental_assembly", C.c_int),
                 ("fold_preconditioner", C.c_int), ("two_level", C.c_int), ("coarse_leaf", C.c_int),
                 ("coarse_reuse", C.c_int), ("coarse_fp32", C.c_int),
+                ("scale_fluid_rows", C.c_int),
                 ("stream", C.c_void_p)]
 
 

@@ -496,6 +496,7 @@ extern "C" void hf_default_options(hf_options *o) {
   o->coarse_leaf = 64;
   o->coarse_reuse = 16;
   o->coarse_fp32 = 0;
+  o->scale_fluid_rows = 1;
   o->stream = nullptr;
 }
 
@@ -512,6 +513,7 @@ static hf_status validate_options(hf_ctx *ctx, const hf_options &o) {
   if (o.coarse_leaf < 4 || o.coarse_leaf > 4096) return fail(ctx, HF_EINVAL, "coarse_leaf out of range 4..4096");
   if (o.coarse_reuse < 0 || o.coarse_reuse > 1000) return fail(ctx, HF_EINVAL, "coarse_reuse out of range 0..1000");
   if (o.coarse_fp32 < 0 || o.coarse_fp32 > 1) return fail(ctx, HF_EINVAL, "coarse_fp32 must be 0 or 1");
+  if (o.scale_fluid_rows < 0 || o.scale_fluid_rows > 1) return fail(ctx, HF_EINVAL, "scale_fluid_rows must be 0 or 1");
   return HF_OK;
 }
 
@@ -564,13 +566,21 @@ extern "C" const char *hf_last_error(const hf_ctx *ctx) {
   return ctx ? ctx->err.c_str() : "null context";
 }
 
+static hf_status update_fluid_scale(hf_ctx *ctx);
+
 extern "C" hf_status hf_set_options(hf_ctx *ctx, const hf_options *opt) {
   if (!ctx || !opt) return HF_EINVAL;
   TRY(validate_options(ctx, *opt));
   if (opt->device != ctx->opt.device || opt->stream != ctx->opt.stream)
     return fail(ctx, HF_EINVAL, "device and stream are fixed at hf_create");
   release_all_graphs(ctx);  // captured chunks hold the old tolerances and restart length
+  const bool rescale = opt->scale_fluid_rows != ctx->opt.scale_fluid_rows;
   ctx->opt = *opt;
+  if (rescale && ctx->stage >= 3) {  // the fluid rows take the new scale from the current state
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    TRY(update_fluid_scale(ctx));
+    TRY(sync(ctx));
+  }
   return HF_OK;
 }
 
@@ -1292,7 +1302,7 @@ static hf_status update_fluid_scale(hf_ctx *ctx) {
     const double delta_c = 2.0 * m.G_c / m.sigma_c;
     const double wmax = ctx->inst[b].n_act ? std::max(ctx->hd[b], ctx->hd[B + b]) : -1e300;
     const double w_ref = std::max(wmax, 0.01 * delta_c);
-    ctx->ipar[b].s_p = 12.0 * m.mu * std::pow(ctx->inst[b].bbox_L / w_ref, 3);
+    ctx->ipar[b].s_p = ctx->opt.scale_fluid_rows ? 12.0 * m.mu * std::pow(ctx->inst[b].bbox_L / w_ref, 3) : 1.0;
   }
   TRY(put(ctx, ctx->d_ipar, ctx->ipar));
   return HF_OK;

@@ -558,3 +558,39 @@ def test_per_block_residuals(name, precision):
     assert abs(np.linalg.norm(r[n_u:]) - st.relres_p * bp) <= scale * np.sqrt(len(r))
     assert st.true_relres <= 1e-10
     ctx.close()
+
+
+@pytest.mark.parametrize("name", ["2d_p1_n9", "3d_p1_n4"])
+def test_unscaled_fluid_rows(name):
+    """scale_fluid_rows = 0: the fluid rows are those of eq. (discreteLubrication)
+    as written (s_p = 1): R_p and D equal the oracle's assembled with s_p = 1,
+    switching the option on a live context rescales them, and a converged
+    load step ends at the same state as with the scaled rows (the Newton
+    iterates do not depend on the row scale)."""
+    prob = SMALL[name]()
+    case = Case.from_problem(prob)
+    ctx = hf.context_for_problem(prob, scale_fluid_rows=0)
+    u, p, wo = _random_state(case, 31)
+    ctx.set_state(u, p, wo)
+    ctx.assemble()
+    _, rp = ctx.residual()
+    S1 = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, 1.0, case.src_pnode, case.src_q0)
+    assert np.abs(rp - S1.R_p).max() <= 1e-12 * np.abs(S1.R_p).max()
+    ctx.set_options(scale_fluid_rows=1)
+    ctx.assemble()
+    _, rp = ctx.residual()
+    sp = newton.fluid_scale(case, wo, u)
+    S2 = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, sp, case.src_pnode, case.src_q0)
+    assert np.abs(rp - S2.R_p).max() <= 1e-12 * np.abs(S2.R_p).max()
+    ctx.close()
+    ref = newton.run(case, 1, solver="gmres")
+    ctx = hf.context_for_problem(prob, scale_fluid_rows=0)
+    st0 = newton.initial_state(case)
+    ctx.set_state(st0.u, st0.p, st0.w_old)
+    ns = ctx.newton_solve()
+    u1, p1, _, _ = ctx.get_state()
+    ctx.close()
+    assert ns.converged
+    st = ref[0][0]
+    assert np.linalg.norm(u1 - st.u) <= 1e-8 * np.linalg.norm(st.u)
+    assert np.linalg.norm(p1 - st.p) <= 1e-8 * np.linalg.norm(st.p)
