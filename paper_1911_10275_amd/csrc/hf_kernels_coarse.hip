@@ -552,22 +552,38 @@ __global__ __launch_bounds__(64) void k_tl_q(KParams kp, CoarseK ck, const T *__
 
 // t = v_u - B z_p - AP z_c2 and apz = AP z_c2: thread per (element, row)
 // columns of one element row of A P whose coarse values a workgroup stages in
-// LDS (an element touches at most 20 vertex classes: 60 columns in 3D)
-constexpr int kTlCols = 96;
+// LDS (an element touches at most 20 vertex classes: 60 columns in 3D, 24 in 2D)
+constexpr int kTlCols = 64;
 
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  using type = double2;
+};
+template <>
+struct Pair<float> {
+  using type = float2;
+};
+
+// t = v_u - B z_p - AP z_c2 and apz = AP z_c2, one thread per pair of rows
+// (2j, 2j+1) of an element row (block sizes are even), reading both rows'
+// entries of a column of A P with one two-wide load
 template <typename T>
 __global__ __launch_bounds__(kCT) void k_tl_t(KParams kp, CoarseK ck, const T *__restrict__ AP,
                                               const T *__restrict__ Bs, const T *__restrict__ vu,
                                               const T *__restrict__ zp, const T *__restrict__ zc,
                                               T *__restrict__ t_out, T *__restrict__ apz) {
-  // the workgroup's elements (at most kCT / 6 + 2 for block sizes >= 6) get
+  using V2 = typename Pair<T>::type;
+  // the workgroup's elements (at most 2 kCT / 6 + 2 for block sizes >= 6) get
   // their z_c values staged once, so the row loop streams A P alone
-  constexpr int EMAX = kCT / 6 + 2;
+  constexpr int EMAX = 2 * kCT / 6 + 2;
   __shared__ double zs[EMAX * kTlCols];
-  const int bu = kp.s.bu, dim = ck.dim;
-  const int64_t t0 = blockIdx.x * (int64_t)kCT;
-  const int64_t e0 = t0 / bu;
-  const int64_t e1 = (std::min<int64_t>(t0 + kCT, kp.s.n_u) - 1) / bu;
+  const int bu = kp.s.bu, hb = bu / 2, dim = ck.dim;
+  const int64_t npair = kp.s.n_u / 2;
+  const int64_t q0 = blockIdx.x * (int64_t)kCT;
+  const int64_t e0 = q0 / hb;
+  const int64_t e1 = (std::min<int64_t>(q0 + kCT, npair) - 1) / hb;
   const int ne_b = (int)(e1 - e0 + 1);
   for (int i = threadIdx.x; i < ne_b * kTlCols; i += kCT) {
     const int64_t e = e0 + i / kTlCols;
@@ -577,26 +593,40 @@ __global__ __launch_bounds__(kCT) void k_tl_t(KParams kp, CoarseK ck, const T *_
       zs[i] = (double)zc[(int64_t)ck.ap_cls[c0 + col / dim] * dim + col % dim];
   }
   __syncthreads();
-  const int64_t t = t0 + threadIdx.x;
-  if (t >= kp.s.n_u) return;
-  const int64_t e = t / bu;
-  const int r = (int)(t % bu);
+  const int64_t q = q0 + threadIdx.x;
+  if (q >= npair) return;
+  const int64_t e = q / hb;
+  const int r = 2 * (int)(q % hb);
   const int64_t c0 = ck.ap_ptr[e];
   const int ncol = (int)(ck.ap_ptr[e + 1] - c0) * dim;
-  const T *ap = AP + c0 * dim * bu + r;
-  double acc = 0.0;
+  const V2 *ap = reinterpret_cast<const V2 *>(AP + c0 * dim * bu + r);
+  double a0 = 0.0, a1 = 0.0;
   if (ncol <= kTlCols) {
     const double *z = zs + (e - e0) * kTlCols;
-    for (int col = 0; col < ncol; ++col) acc += (double)ap[(int64_t)col * bu] * z[col];
+    for (int col = 0; col < ncol; ++col) {
+      const V2 v = ap[(int64_t)col * hb];
+      a0 += (double)v.x * z[col];
+      a1 += (double)v.y * z[col];
+    }
   } else {
-    for (int col = 0; col < ncol; ++col)
-      acc += (double)ap[(int64_t)col * bu] * (double)zc[(int64_t)ck.ap_cls[c0 + col / dim] * dim + col % dim];
+    for (int col = 0; col < ncol; ++col) {
+      const V2 v = ap[(int64_t)col * hb];
+      const double zv = (double)zc[(int64_t)ck.ap_cls[c0 + col / dim] * dim + col % dim];
+      a0 += (double)v.x * zv;
+      a1 += (double)v.y * zv;
+    }
   }
-  double bz = 0.0;
-  for (int64_t s = kp.m.sp_ptr[e]; s < kp.m.sp_ptr[e + 1]; ++s)
-    bz += (double)Bs[s * bu + r] * (double)zp[kp.m.sp_pnode[s]];
-  apz[t] = (T)acc;
-  t_out[t] = (T)((double)vu[t] - bz - acc);
+  double b0 = 0.0, b1 = 0.0;
+  for (int64_t s = kp.m.sp_ptr[e]; s < kp.m.sp_ptr[e + 1]; ++s) {
+    const double zv = (double)zp[kp.m.sp_pnode[s]];
+    b0 += (double)Bs[s * bu + r] * zv;
+    b1 += (double)Bs[s * bu + r + 1] * zv;
+  }
+  const int64_t t = e * bu + r;
+  apz[t] = (T)a0;
+  apz[t + 1] = (T)a1;
+  t_out[t] = (T)((double)vu[t] - b0 - a0);
+  t_out[t + 1] = (T)((double)vu[t + 1] - b1 - a1);
 }
 
 // y_p = S x_p with the dense pressure block of each instance (one wave per row)
@@ -790,7 +820,8 @@ template hipError_t coarse_zc2<float>(const KParams &, const CoarseK &, const fl
 template <typename T>
 hipError_t coarse_t(const KParams &kp, const CoarseK &ck, const T *AP, const T *Bs, const T *vu, const T *zp,
                     const T *zc, T *t, T *apz, hipStream_t st) {
-  hipLaunchKernelGGL((k_tl_t<T>), dim3(nblk(kp.s.n_u)), dim3(kCT), 0, st, kp, ck, AP, Bs, vu, zp, zc, t, apz);
+  if (kp.s.bu % 2) return hipErrorInvalidValue;  // row pairs need an even block size
+  hipLaunchKernelGGL((k_tl_t<T>), dim3(nblk(kp.s.n_u / 2)), dim3(kCT), 0, st, kp, ck, AP, Bs, vu, zp, zc, t, apz);
   return hipGetLastError();
 }
 template hipError_t coarse_t<double>(const KParams &, const CoarseK &, const double *, const double *,
