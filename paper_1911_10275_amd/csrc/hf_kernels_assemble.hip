@@ -8,12 +8,41 @@
 // every block is written exactly once, with a fixed summation order, no
 // atomics and no staging.  Each interface integral is therefore evaluated by
 // both of its elements, each for its own test functions.
+#include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "hf_internal.h"
 
 namespace hf {
 
+// Grid of a persistent kernel: the workgroups of one kernel that the device
+// holds at once (its occupancy per CU times the CU count), capped at the
+// number of work items.  Queried once per device and kernel, then kept.
+class ResidentGrid {
+ public:
+  hipError_t size(const void *kernel, int threads, int64_t n_items, unsigned *grid) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu_);
+    if ((int)cap_.size() <= dev) cap_.resize(dev + 1, 0);
+    if (cap_[dev] <= 0) {
+      int occ = 0, ncu = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0);
+      if (e != hipSuccess) return e;
+      e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+      cap_[dev] = std::max(occ, 1) * std::max(ncu, 1);
+    }
+    *grid = (unsigned)std::min<int64_t>(n_items, cap_[dev]);
+    return hipSuccess;
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<int64_t> cap_;
+};
 
 // ---------------------------------------------------------------------------
 // Lagrange P1/P2 on simplices in barycentric coordinates
@@ -237,7 +266,7 @@ __device__ inline void traction_law(int state, double w, double sigma_c, double 
 // dphi_a/dx_x dphi_b/dx_y.
 // ---------------------------------------------------------------------------
 template <int DIM, int ORDER, int NT>
-__global__ __launch_bounds__(NT) void k_assemble(KParams kp, const int32_t *__restrict__ elist,
+__device__ __forceinline__ void assemble_element(const KParams &kp, const int64_t e,
                                                  const double *__restrict__ u,
                                                  const double *__restrict__ p,
                                                  const double *__restrict__ w_old,
@@ -247,7 +276,6 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const int32_t *__re
   using C = Cfg<DIM, ORDER>;
   constexpr int NN = C::NN, BU = C::BU, NF = C::NF, NQF = C::NQF, NQV = C::NQV, NNF = C::NNF;
   constexpr int NQ = NQF > NQV ? NQF : NQV;
-  const int64_t e = elist ? elist[blockIdx.x] : blockIdx.x;
   const int tid = threadIdx.x;
   const InstPar P = kp.ip[kp.einst[e]];
   const double lam = P.lam, G = P.G;
@@ -545,20 +573,39 @@ __global__ __launch_bounds__(NT) void k_assemble(KParams kp, const int32_t *__re
   }
 }
 
+// Persistent form: a grid sized to the workgroups the chip holds at once
+// walks the element list (all instances of the batch, concatenated), one
+// element per workgroup at a time; the barrier at the end of each element
+// keeps the next element's LDS writes behind this one's last reads.
+template <int DIM, int ORDER, int NT>
+__global__ __launch_bounds__(NT) void k_assemble(KParams kp, const int32_t *__restrict__ elist,
+                                                 int64_t n_items, const double *__restrict__ u,
+                                                 const double *__restrict__ p,
+                                                 const double *__restrict__ w_old,
+                                                 double *__restrict__ A, double *__restrict__ R,
+                                                 double *__restrict__ Bs,
+                                                 double *__restrict__ Cs) {
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int64_t e = elist ? (int64_t)elist[it] : it;
+    assemble_element<DIM, ORDER, NT>(kp, e, u, p, w_old, A, R, Bs, Cs);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Fluid rows: R_p and the dense row of D, one thread per pressure node
 // ---------------------------------------------------------------------------
 template <int DIM, int ORDER>
-__global__ __launch_bounds__(64) void k_fluid_rows(KParams kp, const double *__restrict__ u,
-                                                   const double *__restrict__ p,
-                                                   const double *__restrict__ w_old,
-                                                   double *__restrict__ R, double *__restrict__ D) {
+__device__ __forceinline__ void fluid_row(const KParams &kp, const int64_t i,
+                                          const double *__restrict__ u,
+                                          const double *__restrict__ p,
+                                          const double *__restrict__ w_old,
+                                          double *__restrict__ R, double *__restrict__ D) {
   using C = Cfg<DIM, ORDER>;
   constexpr int NN = C::NN, BU = C::BU, NQF = C::NQF, NNF = C::NNF;
   __shared__ double srow[kMaxPressureBlock];  // the dense row of D being summed
   __shared__ double s_r[64], s_d[64][NNF];
   __shared__ int s_c[64][NNF];
-  const int64_t i = blockIdx.x;
   const int lane = threadIdx.x;
   const int b = kp.pinst[i];
   const InstPar P = kp.ip[b];
@@ -653,6 +700,18 @@ __global__ __launch_bounds__(64) void k_fluid_rows(KParams kp, const double *__r
     for (int64_t s2 = 0; s2 < kp.s.n_src; ++s2)
       if (kp.m.src_node[s2] == i) Ri -= P.s_p * kp.m.src_q0[s2];
     R[kp.s.n_u + i] = Ri;
+  }
+}
+
+// Persistent form over the pressure nodes of the batch, as for k_assemble.
+template <int DIM, int ORDER>
+__global__ __launch_bounds__(64) void k_fluid_rows(KParams kp, const double *__restrict__ u,
+                                                   const double *__restrict__ p,
+                                                   const double *__restrict__ w_old,
+                                                   double *__restrict__ R, double *__restrict__ D) {
+  for (int64_t i = blockIdx.x; i < kp.s.n_p; i += gridDim.x) {
+    fluid_row<DIM, ORDER>(kp, i, u, p, w_old, R, D);
+    __syncthreads();
   }
 }
 
@@ -831,11 +890,20 @@ static hipError_t assemble_impl(const KParams &kp, const double *u, const double
                                 double *Cs, double *D, const int32_t *elist, int64_t n_el,
                                 hipStream_t st) {
   constexpr int NT = (Cfg<DIM, ORDER>::BU >= 24) ? 128 : 64;
-  if (n_el) hipLaunchKernelGGL((k_assemble<DIM, ORDER, NT>), dim3((unsigned)n_el), dim3(NT), 0, st,
-                               kp, elist, u, p, w_old, A, R, Bs, Cs);
-  if (kp.s.n_p)
-    hipLaunchKernelGGL((k_fluid_rows<DIM, ORDER>), dim3((unsigned)kp.s.n_p), dim3(64), 0, st, kp, u, p,
-                       w_old, R, D);
+  static ResidentGrid g_el, g_fl;
+  if (n_el) {
+    unsigned g = 0;
+    hipError_t err = g_el.size((const void *)k_assemble<DIM, ORDER, NT>, NT, n_el, &g);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((k_assemble<DIM, ORDER, NT>), dim3(g), dim3(NT), 0, st, kp, elist, n_el, u,
+                       p, w_old, A, R, Bs, Cs);
+  }
+  if (kp.s.n_p) {
+    unsigned g = 0;
+    hipError_t err = g_fl.size((const void *)k_fluid_rows<DIM, ORDER>, 64, kp.s.n_p, &g);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL((k_fluid_rows<DIM, ORDER>), dim3(g), dim3(64), 0, st, kp, u, p, w_old, R, D);
+  }
   return hipGetLastError();
 }
 
