@@ -266,7 +266,8 @@ __device__ inline void traction_law(int state, double w, double sigma_c, double 
 // dphi_a/dx_x dphi_b/dx_y.
 // ---------------------------------------------------------------------------
 template <int DIM, int ORDER, int NT>
-__device__ __forceinline__ void assemble_element(const KParams &kp, const int64_t e,
+__device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTables &rt,
+                                                 const int64_t e,
                                                  const double *__restrict__ u,
                                                  const double *__restrict__ p,
                                                  const double *__restrict__ w_old,
@@ -276,36 +277,81 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const int64_
   using C = Cfg<DIM, ORDER>;
   constexpr int NN = C::NN, BU = C::BU, NF = C::NF, NQF = C::NQF, NQV = C::NQV, NNF = C::NNF;
   constexpr int NQ = NQF > NQV ? NQF : NQV;
-  const int tid = threadIdx.x;
+  constexpr int NG = (DIM - 1) * (DIM - 1);
+  // An empty asm that claims to change the thread index keeps the compiler from
+  // hoisting every phase's per-thread LDS addresses out of the element and face
+  // loops (kept live across all phases, they would double the register count).
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   const InstPar P = kp.ip[kp.einst[e]];
   const double lam = P.lam, G = P.G;
 
-  __shared__ double s_gl[NF][DIM], s_gln[NF][DIM];
-  __shared__ double s_ue[BU], s_un[BU];
-  __shared__ double s_diag[BU * BU], s_off[BU * BU];
+  __shared__ double s_gl[NF][DIM];
+  __shared__ double s_ue[BU];
+  __shared__ double s_diag[BU * BU];
   __shared__ double s_phE[NQ][NN], s_gphE[NQ][NN][DIM];
   __shared__ double s_phN[NQF][NN], s_gphN[NQF][NN][DIM];
   __shared__ double s_c[NQF][NN];             // W_q s_e phi^e_a
   __shared__ double s_M[2][NN][NN][DIM + 3];  // M1 (DIM), M2, M3, M4 per trial side
-  __shared__ double s_gu[NQ][DIM][DIM];       // displacement gradient at the points
+  __shared__ double s_gu[NQV][DIM][DIM];      // displacement gradient at the volume points
+  __shared__ double s_gj[NQF][DIM][DIM + 1];  // averaged gradient and jump at the face points
   __shared__ double s_tau[NQF][DIM], s_W[NQF], s_al[NQF], s_dT[NQF];
   __shared__ double s_eta[NQF][NNF], s_fc[NQF][NNF];
   __shared__ double s_wq[NQF], s_gp[NQF][DIM - 1];
   __shared__ double s_R[BU];
-  __shared__ double s_n[DIM];
-  __shared__ double s_ginv[(DIM - 1) * (DIM - 1)];
-  __shared__ int s_pe[DIM], s_pn[DIM];
+  // every interface element of this element, read once up front
+  __shared__ int32_t s_f[NF], s_nb[NF], s_slot[NF], s_beta[NF], s_minus[NF];
+  __shared__ int32_t s_pe[NF][DIM], s_pn[NF][DIM], s_qst[NF][NQF];
+  __shared__ double s_un[NF][BU], s_gln[NF][NF][DIM];
+  __shared__ double s_n[NF][DIM], s_area[NF], s_bh[NF], s_ginv[NF][NG > 0 ? NG : 1];
+  __shared__ double s_pv[NF][NNF];
 
   const double det = kp.m.detabs[e];
+  // ---- element data and the ids of its interface elements ----------------
   if (tid < NF * DIM) s_gl[tid / DIM][tid % DIM] = kp.m.gl[e * NF * DIM + tid];
   for (int r = tid; r < BU; r += NT) s_ue[r] = u[e * BU + r];
+  if (tid < NF) {
+    s_f[tid] = kp.m.fid[e * NF + tid];
+    s_nb[tid] = kp.m.nbr[e * NF + tid];
+  }
   __syncthreads();
+  asm volatile("" : "+v"(tid));
 
-  // ---- bulk term ----------------------------------------------------------
+  // ---- neighbour and interface data of all faces; bulk shape gradients ----
+  for (int t = tid; t < NF * BU; t += NT) {
+    const int lf = t / BU, r = t % BU;
+    if (s_f[lf] >= 0) s_un[lf][r] = u[(int64_t)s_nb[lf] * BU + r];
+  }
+  for (int t = tid; t < NF * NF * DIM; t += NT) {
+    const int lf = t / (NF * DIM), k = t % (NF * DIM);
+    if (s_f[lf] >= 0) s_gln[lf][k / DIM][k % DIM] = kp.m.gl[(int64_t)s_nb[lf] * NF * DIM + k];
+  }
+  for (int t = tid; t < NF * NQF; t += NT) {
+    const int lf = t / NQF, q = t % NQF;
+    if (s_f[lf] >= 0) s_qst[lf][q] = kp.m.qp_state[(int64_t)s_f[lf] * NQF + q];
+  }
+  if (tid < NF) {
+    const int32_t f = s_f[tid];
+    if (f >= 0) {
+      const bool minus = (kp.m.face_em[f] == (int32_t)e);
+      s_minus[tid] = minus;
+      s_area[tid] = kp.m.area[f];
+      s_bh[tid] = kp.b_stab / kp.m.hf[f];
+      s_beta[tid] = kp.m.beta[f];
+      s_slot[tid] = kp.m.slot[f];
+      for (int c = 0; c < DIM; ++c) {
+        s_n[tid][c] = kp.m.normal[(int64_t)f * DIM + c];
+        const int32_t pm = kp.m.fperm_m[(int64_t)f * DIM + c], pp = kp.m.fperm_p[(int64_t)f * DIM + c];
+        s_pe[tid][c] = minus ? pm : pp;
+        s_pn[tid][c] = minus ? pp : pm;
+      }
+      for (int c = 0; c < NG; ++c) s_ginv[tid][c] = kp.m.ginv[(int64_t)f * NG + c];
+    }
+  }
   for (int t = tid; t < NQV * NN; t += NT) {
     const int q = t / NN, a = t % NN;
     double lamq[DIM + 1], dph[DIM + 1];
-    for (int k = 0; k <= DIM; ++k) lamq[k] = kp.rt->vq_lam[q][k];
+    for (int k = 0; k <= DIM; ++k) lamq[k] = rt.vq_lam[q][k];
     Lag<DIM, ORDER>::dphi_one(a, lamq, dph);
     for (int x = 0; x < DIM; ++x) {
       double g = 0.0;
@@ -314,6 +360,14 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const int64_
     }
   }
   __syncthreads();
+  asm volatile("" : "+v"(tid));
+
+  // ---- bulk term; pressures of the fluid faces ----------------------------
+  for (int t = tid; t < NF * NNF; t += NT) {
+    const int lf = t / NNF, k = t % NNF;
+    if (s_f[lf] >= 0 && s_beta[lf])
+      s_pv[lf][k] = p[kp.m.face_pn[(int64_t)s_slot[lf] * NNF + k]];
+  }
   for (int t = tid; t < NQV * DIM * DIM; t += NT) {
     const int q = t / (DIM * DIM), i = (t / DIM) % DIM, x = t % DIM;
     double g = 0.0;
@@ -322,22 +376,30 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const int64_
   }
   for (int t = tid; t < NN * NN; t += NT) {
     const int a = t / NN, b = t % NN;
-    double P[DIM][DIM];
+    double Pm[DIM][DIM];
     for (int x = 0; x < DIM; ++x)
-      for (int y = 0; y < DIM; ++y) P[x][y] = 0.0;
+      for (int y = 0; y < DIM; ++y) Pm[x][y] = 0.0;
     for (int q = 0; q < NQV; ++q) {
-      const double wq = kp.rt->vq_w[q] * det;
+      const double wq = rt.vq_w[q] * det;
       for (int x = 0; x < DIM; ++x)
-        for (int y = 0; y < DIM; ++y) P[x][y] += wq * s_gphE[q][a][x] * s_gphE[q][b][y];
+        for (int y = 0; y < DIM; ++y) Pm[x][y] += wq * s_gphE[q][a][x] * s_gphE[q][b][y];
     }
     double tr = 0.0;
-    for (int x = 0; x < DIM; ++x) tr += P[x][x];
+    for (int x = 0; x < DIM; ++x) tr += Pm[x][x];
     for (int i = 0; i < DIM; ++i)
       for (int j = 0; j < DIM; ++j)
         s_diag[(b * DIM + j) * BU + a * DIM + i] =
-            lam * P[i][j] + G * P[j][i] + (i == j ? G * tr : 0.0);
+            lam * Pm[i][j] + G * Pm[j][i] + (i == j ? G * tr : 0.0);
   }
+  // zero this element's coupling strips (owned by this workgroup)
+  const int64_t sp0 = kp.m.sp_ptr[e], sp1 = kp.m.sp_ptr[e + 1];
+  for (int r = tid; r < BU; r += NT)
+    for (int64_t k = sp0; k < sp1; ++k) {
+      Bs[k * BU + r] = 0.0;
+      Cs[k * BU + r] = 0.0;
+    }
   __syncthreads();
+  asm volatile("" : "+v"(tid));
   for (int r = tid; r < BU; r += NT) {
     const int a = r / DIM, i = r % DIM;
     double acc = 0.0;
@@ -349,83 +411,82 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const int64_
         const double sig = G * (s_gu[q][i][x] + s_gu[q][x][i]) + (i == x ? lam * tr : 0.0);
         sn += sig * s_gphE[q][a][x];
       }
-      acc += kp.rt->vq_w[q] * det * sn;
+      acc += rt.vq_w[q] * det * sn;
     }
     s_R[r] = acc;
   }
-  // zero this element's coupling strips (owned by this workgroup)
-  const int64_t sp0 = kp.m.sp_ptr[e], sp1 = kp.m.sp_ptr[e + 1];
-  for (int r = tid; r < BU; r += NT)
-    for (int64_t k = sp0; k < sp1; ++k) {
-      Bs[k * BU + r] = 0.0;
-      Cs[k * BU + r] = 0.0;
-    }
   __syncthreads();
+  asm volatile("" : "+v"(tid));
 
   const uint32_t clamp = kp.m.clamp[e];
 
   // ---- interface elements -----------------------------------------------
+  // Phases per face: shape functions; jump and gradient; traction; fluid and
+  // test coefficients; residual, moments and coupling strips; the blocks.  The
+  // last phase reads only s_M, s_n and s_bh, which the next face's first four
+  // phases do not write, so no barrier follows it.
+#pragma unroll 1
   for (int lf = 0; lf < NF; ++lf) {
-    const int32_t f = kp.m.fid[e * NF + lf];
+    const int32_t f = s_f[lf];
     if (f < 0) continue;  // boundary facet: clamped rows or zero traction
-    const int32_t nb = kp.m.nbr[e * NF + lf];
-    const bool minus = (kp.m.face_em[f] == (int32_t)e);
-    const double sgE = minus ? -1.0 : 1.0, sgN = -sgE;
-    const double area = kp.m.area[f];
-    const double bh = kp.b_stab / kp.m.hf[f];
+    int ft = tid;
+    asm volatile("" : "+v"(ft));
+    const int32_t nb = s_nb[lf];
+    const double sgE = s_minus[lf] ? -1.0 : 1.0, sgN = -sgE;
+    const double area = s_area[lf];
+    const double bh = s_bh[lf];
     const double kc = bh * (lam + 2.0 * G);
-    const int beta = kp.m.beta[f];
-    const int slot = kp.m.slot[f];
-    if (tid < DIM) {
-      s_n[tid] = kp.m.normal[(int64_t)f * DIM + tid];
-      s_pe[tid] = minus ? kp.m.fperm_m[(int64_t)f * DIM + tid] : kp.m.fperm_p[(int64_t)f * DIM + tid];
-      s_pn[tid] = minus ? kp.m.fperm_p[(int64_t)f * DIM + tid] : kp.m.fperm_m[(int64_t)f * DIM + tid];
-    }
-    if (tid < (DIM - 1) * (DIM - 1)) s_ginv[tid] = kp.m.ginv[(int64_t)f * (DIM - 1) * (DIM - 1) + tid];
-    if (tid < NF * DIM) s_gln[tid / DIM][tid % DIM] = kp.m.gl[(int64_t)nb * NF * DIM + tid];
-    for (int r = tid; r < BU; r += NT) s_un[r] = u[(int64_t)nb * BU + r];
-    __syncthreads();
+    const int beta = s_beta[lf];
+    const double *nrm = s_n[lf];
     // shape functions of both elements at the face points
-    for (int t = tid; t < 2 * NQF * NN; t += NT) {
+    for (int t = ft; t < 2 * NQF * NN; t += NT) {
       const int side = t / (NQF * NN), q = (t / NN) % NQF, a = t % NN;
       double lamq[DIM + 1];
       for (int k = 0; k <= DIM; ++k) lamq[k] = 0.0;
-      const int *perm = side == 0 ? s_pe : s_pn;
-      for (int k = 0; k < DIM; ++k) lamq[perm[k]] = kp.rt->fq_mu[q][k];
+      const int *perm = side == 0 ? s_pe[lf] : s_pn[lf];
+      for (int k = 0; k < DIM; ++k) lamq[perm[k]] = rt.fq_mu[q][k];
       double dph[DIM + 1];
       Lag<DIM, ORDER>::dphi_one(a, lamq, dph);
       const double ph = Lag<DIM, ORDER>::phi_one(a, lamq);
       for (int x = 0; x < DIM; ++x) {
         double g = 0.0;
-        for (int k = 0; k <= DIM; ++k) g += dph[k] * (side == 0 ? s_gl[k][x] : s_gln[k][x]);
+        for (int k = 0; k <= DIM; ++k) g += dph[k] * (side == 0 ? s_gl[k][x] : s_gln[lf][k][x]);
         if (side == 0) s_gphE[q][a][x] = g; else s_gphN[q][a][x] = g;
       }
       if (side == 0) s_phE[q][a] = ph; else s_phN[q][a] = ph;
     }
     __syncthreads();
-    // per-point traction tau and interface-law tangent
-    for (int q = tid; q < NQF; q += NT) {
-      double jump[DIM], ga[DIM][DIM];
-      for (int i = 0; i < DIM; ++i) {
+    asm volatile("" : "+v"(ft));
+    // jump and averaged displacement gradient at the points, one entry per thread
+    const double *un = s_un[lf];
+    for (int t = ft; t < NQF * DIM * (DIM + 1); t += NT) {
+      const int q = t / (DIM * (DIM + 1)), i = (t / (DIM + 1)) % DIM, x = t % (DIM + 1);
+      double acc;
+      if (x == DIM) {
         double a0 = 0.0, a1 = 0.0;
         for (int a = 0; a < NN; ++a) {
           a0 += s_phE[q][a] * s_ue[a * DIM + i];
-          a1 += s_phN[q][a] * s_un[a * DIM + i];
+          a1 += s_phN[q][a] * un[a * DIM + i];
         }
-        jump[i] = sgE * a0 + sgN * a1;  // u+ - u-
-        for (int x = 0; x < DIM; ++x) {
-          double b0 = 0.0;
-          for (int a = 0; a < NN; ++a)
-            b0 += s_ue[a * DIM + i] * s_gphE[q][a][x] + s_un[a * DIM + i] * s_gphN[q][a][x];
-          ga[i][x] = 0.5 * b0;  // average of the two sides' displacement gradients
-        }
+        acc = sgE * a0 + sgN * a1;  // u+ - u-
+      } else {
+        double b0 = 0.0;
+        for (int a = 0; a < NN; ++a)
+          b0 += s_ue[a * DIM + i] * s_gphE[q][a][x] + un[a * DIM + i] * s_gphN[q][a][x];
+        acc = 0.5 * b0;  // average of the two sides' displacement gradients
       }
+      s_gj[q][i][x] = acc;
+    }
+    __syncthreads();
+    asm volatile("" : "+v"(ft));
+    // per-point traction tau and interface-law tangent
+    for (int q = ft; q < NQF; q += NT) {
       double tr = 0.0, w = 0.0;
       for (int x = 0; x < DIM; ++x) {
-        tr += ga[x][x];
-        w += jump[x] * s_n[x];
+        tr += s_gj[q][x][x];
+        w += s_gj[q][x][DIM] * nrm[x];
       }
-      const int st = kp.m.qp_state[(int64_t)f * NQF + q];
+      const int st = s_qst[lf][q];
       const double al = st > 0 ? 1.0 : 0.0;
       double T, dT;
       traction_law(st, w, P.sigma_c, P.delta_c, kc, T, dT);
@@ -434,9 +495,9 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const int64_
       for (int s2 = 0; s2 < DIM - 1; ++s2) gp[s2] = 0.0;
       if (beta) {
         double mu_[DIM];
-        for (int k = 0; k < DIM; ++k) mu_[k] = kp.rt->fq_mu[q][k];
+        for (int k = 0; k < DIM; ++k) mu_[k] = rt.fq_mu[q][k];
         for (int k = 0; k < NNF; ++k) {
-          const double pk = p[kp.m.face_pn[(int64_t)slot * NNF + k]];
+          const double pk = s_pv[lf][k];
           double dmu[DIM];
           Lag<DIM - 1, ORDER>::dphi_one(k, mu_, dmu);
           ph_p += Lag<DIM - 1, ORDER>::phi_one(k, mu_) * pk;
@@ -446,25 +507,26 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const int64_
       for (int i = 0; i < DIM; ++i) {
         double sn = 0.0;  // <sigma> n, component i (sigma is linear in grad u)
         for (int x = 0; x < DIM; ++x) {
-          const double sa = G * (ga[i][x] + ga[x][i]) + (i == x ? lam * tr : 0.0);
-          sn += sa * s_n[x];
+          const double sa = G * (s_gj[q][i][x] + s_gj[q][x][i]) + (i == x ? lam * tr : 0.0);
+          sn += sa * nrm[x];
         }
-        const double cj = G * jump[i] + (lam + G) * s_n[i] * w;
-        s_tau[q][i] = (1.0 - al) * (sn + bh * cj) + al * T * s_n[i] - (beta ? ph_p * s_n[i] : 0.0);
+        const double cj = G * s_gj[q][i][DIM] + (lam + G) * nrm[i] * w;
+        s_tau[q][i] = (1.0 - al) * (sn + bh * cj) + al * T * nrm[i] - (beta ? ph_p * nrm[i] : 0.0);
       }
-      s_W[q] = kp.rt->fq_w[q] * area;
+      s_W[q] = rt.fq_w[q] * area;
       s_al[q] = al;
       s_dT[q] = dT;
       s_wq[q] = w;
       for (int s2 = 0; s2 < DIM - 1; ++s2) s_gp[q][s2] = gp[s2];
     }
     __syncthreads();
+    asm volatile("" : "+v"(ft));
     // fluid coefficients of the C strips: s_p (K'(w) grad p . grad eta_k + eta_k / dt)
     if (beta) {
-      for (int t = tid; t < NQF * NNF; t += NT) {
+      for (int t = ft; t < NQF * NNF; t += NT) {
         const int q = t / NNF, k = t % NNF;
         double mu_[DIM], dmu[DIM];
-        for (int c2 = 0; c2 < DIM; ++c2) mu_[c2] = kp.rt->fq_mu[q][c2];
+        for (int c2 = 0; c2 < DIM; ++c2) mu_[c2] = rt.fq_mu[q][c2];
         Lag<DIM - 1, ORDER>::dphi_one(k, mu_, dmu);
         const double eta = Lag<DIM - 1, ORDER>::phi_one(k, mu_);
         const double wp = s_wq[q] > 0.0 ? s_wq[q] : 0.0;
@@ -472,28 +534,30 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const int64_
         double gg = 0.0;
         for (int s2 = 0; s2 < DIM - 1; ++s2)
           for (int t2 = 0; t2 < DIM - 1; ++t2)
-            gg += s_gp[q][s2] * s_ginv[s2 * (DIM - 1) + t2] * (dmu[t2 + 1] - dmu[0]);
+            gg += s_gp[q][s2] * s_ginv[lf][s2 * (DIM - 1) + t2] * (dmu[t2 + 1] - dmu[0]);
         s_eta[q][k] = eta;
         s_fc[q][k] = P.s_p * (dK * gg + eta / P.dt);
       }
     }
-    for (int t = tid; t < NQF * NN; t += NT) {
+    for (int t = ft; t < NQF * NN; t += NT) {
       const int q = t / NN, a = t % NN;
       s_c[q][a] = s_W[q] * sgE * s_phE[q][a];
     }
     __syncthreads();
+    asm volatile("" : "+v"(ft));
     // residual of this element's test functions
-    for (int r = tid; r < BU; r += NT) {
+    for (int r = ft; r < BU; r += NT) {
       const int a = r / DIM, i = r % DIM;
       double acc = 0.0;
       for (int q = 0; q < NQF; ++q) acc += s_c[q][a] * s_tau[q][i];
       s_R[r] += acc;
     }
     // moment matrices M1..M4 of both trial sides
-    for (int t = tid; t < 2 * NN * NN; t += NT) {
+    for (int t = ft; t < 2 * NN * NN; t += NT) {
       const int side = t / (NN * NN), a = (t / NN) % NN, b = t % NN;
       double m1[DIM], m2 = 0.0, m3 = 0.0, m4 = 0.0;
       for (int x = 0; x < DIM; ++x) m1[x] = 0.0;
+#pragma unroll 3
       for (int q = 0; q < NQF; ++q) {
         const double ca = s_c[q][a];
         const double c1 = ca * (1.0 - s_al[q]);
@@ -502,7 +566,7 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const int64_
         for (int x = 0; x < DIM; ++x) {
           const double g = side == 0 ? s_gphE[q][b][x] : s_gphN[q][b][x];
           m1[x] += c1 * g;
-          gn += g * s_n[x];
+          gn += g * nrm[x];
         }
         m2 += c1 * gn;
         m3 += c1 * ph;
@@ -513,49 +577,48 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const int64_
       s_M[side][a][b][DIM + 1] = m3;
       s_M[side][a][b][DIM + 2] = m4;
     }
+    // coupling strips: B (d R_u / d p) and C (d R_p / d u_e) of this face
+    if (beta) {
+      for (int t = ft; t < BU * NNF; t += NT) {
+        const int r = t % BU, k = t / BU;
+        const int a = r / DIM, i = r % DIM;
+        const int32_t ix = kp.m.fs_idx[((int64_t)e * NF + lf) * NNF + k];
+        double bv = 0.0, cv = 0.0;
+        for (int q = 0; q < NQF; ++q) {
+          bv -= s_c[q][a] * s_eta[q][k] * nrm[i];
+          cv += s_W[q] * s_fc[q][k] * sgE * s_phE[q][a] * nrm[i];
+        }
+        Bs[(int64_t)ix * BU + r] += bv;
+        if (!kp.freeze_p) Cs[(int64_t)ix * BU + r] += cv;
+      }
+    }
     __syncthreads();
-    // self block (into the diagonal) and the off-diagonal block
-    for (int t = tid; t < NN * NN; t += NT) {
-      const int a = t / NN, b = t % NN;
+    asm volatile("" : "+v"(ft));
+    // self block (into the diagonal) and the off-diagonal block (straight to
+    // memory: for each (b, j) the threads of consecutive a write one run of BU)
+    double *Aoff = A + (int64_t)kp.m.blk_of[e * NF + lf] * BU * BU;
+    for (int t = ft; t < NN * NN; t += NT) {
+      const int b = t / NN, a = t % NN;
       for (int side = 0; side < 2; ++side) {
         const double sg = side == 0 ? sgE : sgN;
         const double *M = s_M[side][a][b];
-        for (int i = 0; i < DIM; ++i)
-          for (int j = 0; j < DIM; ++j) {
-            const double ninj = s_n[i] * s_n[j];
+        for (int j = 0; j < DIM; ++j)
+          for (int i = 0; i < DIM; ++i) {
+            const double ninj = nrm[i] * nrm[j];
             const double chat = (i == j ? G : 0.0) + (lam + G) * ninj;
-            double v = 0.5 * lam * s_n[i] * M[j] + 0.5 * G * s_n[j] * M[i] +
+            double v = 0.5 * lam * nrm[i] * M[j] + 0.5 * G * nrm[j] * M[i] +
                        bh * sg * chat * M[DIM + 1] + sg * ninj * M[DIM + 2];
             if (i == j) v += 0.5 * G * M[DIM];
-            const int idx = (b * DIM + j) * BU + a * DIM + i;
-            if (side == 0) s_diag[idx] += v; else s_off[idx] = v;
+            const int r = a * DIM + i;
+            const int idx = (b * DIM + j) * BU + r;
+            if (side == 0) s_diag[idx] += v;
+            else Aoff[idx] = ((clamp >> r) & 1u) ? 0.0 : v;
           }
       }
     }
-    __syncthreads();
-    double *Aoff = A + (int64_t)kp.m.blk_of[e * NF + lf] * BU * BU;
-    for (int idx = tid; idx < BU * BU; idx += NT) {
-      const int r = idx % BU;
-      Aoff[idx] = ((clamp >> r) & 1u) ? 0.0 : s_off[idx];
-    }
-    // coupling strips: B (d R_u / d p) and C (d R_p / d u_e) of this face
-    if (beta) {
-      for (int r = tid; r < BU; r += NT) {
-        const int a = r / DIM, i = r % DIM;
-        for (int k = 0; k < NNF; ++k) {
-          const int32_t ix = kp.m.fs_idx[((int64_t)e * NF + lf) * NNF + k];
-          double bv = 0.0, cv = 0.0;
-          for (int q = 0; q < NQF; ++q) {
-            bv -= s_c[q][a] * s_eta[q][k] * s_n[i];
-            cv += s_W[q] * s_fc[q][k] * sgE * s_phE[q][a] * s_n[i];
-          }
-          Bs[(int64_t)ix * BU + r] += bv;
-          if (!kp.freeze_p) Cs[(int64_t)ix * BU + r] += cv;
-        }
-      }
-    }
-    __syncthreads();
+    (void)nb;
   }
+  __syncthreads();
 
   // ---- strong Dirichlet rows and write-back ------------------------------
   double *Ad = A + kp.m.blk_ptr[e] * BU * BU;
@@ -576,18 +639,26 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const int64_
 // Persistent form: a grid sized to the workgroups the chip holds at once
 // walks the element list (all instances of the batch, concatenated), one
 // element per workgroup at a time; the barrier at the end of each element
-// keeps the next element's LDS writes behind this one's last reads.
+// keeps the next element's LDS writes behind this one's last reads.  The
+// quadrature rules of the context are staged in LDS once per workgroup.
 template <int DIM, int ORDER, int NT>
-__global__ __launch_bounds__(NT) void k_assemble(KParams kp, const int32_t *__restrict__ elist,
+__global__ __launch_bounds__(NT, 3) void k_assemble(KParams kp, const int32_t *__restrict__ elist,
                                                  int64_t n_items, const double *__restrict__ u,
                                                  const double *__restrict__ p,
                                                  const double *__restrict__ w_old,
                                                  double *__restrict__ A, double *__restrict__ R,
                                                  double *__restrict__ Bs,
                                                  double *__restrict__ Cs) {
+  __shared__ RuleTables s_rt;
+  {
+    const int *src = reinterpret_cast<const int *>(kp.rt);
+    int *dst = reinterpret_cast<int *>(&s_rt);
+    for (int i = threadIdx.x; i < (int)(sizeof(RuleTables) / sizeof(int)); i += NT) dst[i] = src[i];
+  }
+  __syncthreads();
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int64_t e = elist ? (int64_t)elist[it] : it;
-    assemble_element<DIM, ORDER, NT>(kp, e, u, p, w_old, A, R, Bs, Cs);
+    assemble_element<DIM, ORDER, NT>(kp, s_rt, e, u, p, w_old, A, R, Bs, Cs);
     __syncthreads();
   }
 }
