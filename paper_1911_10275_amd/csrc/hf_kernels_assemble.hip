@@ -291,13 +291,10 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
   __shared__ double s_diag[BU * BU];
   __shared__ double s_phE[NQ][NN], s_gphE[NQ][NN][DIM];
   __shared__ double s_phN[NQF][NN], s_gphN[NQF][NN][DIM];
-  __shared__ double s_c[NQF][NN];             // W_q s_e phi^e_a
-  __shared__ double s_M[2][NN][NN][DIM + 3];  // M1 (DIM), M2, M3, M4 per trial side
   __shared__ double s_gu[NQV][DIM][DIM];      // displacement gradient at the volume points
   __shared__ double s_gj[NQF][DIM][DIM + 1];  // averaged gradient and jump at the face points
   __shared__ double s_tau[NQF][DIM], s_W[NQF], s_al[NQF], s_dT[NQF];
   __shared__ double s_eta[NQF][NNF], s_fc[NQF][NNF];
-  __shared__ double s_wq[NQF], s_gp[NQF][DIM - 1];
   __shared__ double s_R[BU];
   // every interface element of this element, read once up front
   __shared__ int32_t s_f[NF], s_nb[NF], s_slot[NF], s_beta[NF], s_minus[NF];
@@ -421,17 +418,19 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
   const uint32_t clamp = kp.m.clamp[e];
 
   // ---- interface elements -----------------------------------------------
-  // Phases per face: shape functions; jump and gradient; traction; fluid and
-  // test coefficients; residual, moments and coupling strips; the blocks.  The
-  // last phase reads only s_M, s_n and s_bh, which the next face's first four
-  // phases do not write, so no barrier follows it.
+  // Four phases per face: shape functions of both elements at the face
+  // points; jump and averaged gradient; traction, tangent and fluid
+  // coefficients per point; then residual rows, coupling strips and both
+  // blocks (each thread forms the moments of one test/trial node pair and
+  // expands them).  The last phase reads only what the next face's first two
+  // phases do not write (s_phE, s_phN, s_gphE, s_gphN are read there, so the
+  // next face's first phase waits at the barrier that closes this one).
 #pragma unroll 1
   for (int lf = 0; lf < NF; ++lf) {
     const int32_t f = s_f[lf];
     if (f < 0) continue;  // boundary facet: clamped rows or zero traction
     int ft = tid;
     asm volatile("" : "+v"(ft));
-    const int32_t nb = s_nb[lf];
     const double sgE = s_minus[lf] ? -1.0 : 1.0, sgN = -sgE;
     const double area = s_area[lf];
     const double bh = s_bh[lf];
@@ -479,7 +478,8 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
     }
     __syncthreads();
     asm volatile("" : "+v"(ft));
-    // per-point traction tau and interface-law tangent
+    // per point: traction tau, interface-law tangent, weight; on fluid faces
+    // the coefficients of the C strips, s_p (K'(w) grad p . grad eta_k + eta_k / dt)
     for (int q = ft; q < NQF; q += NT) {
       double tr = 0.0, w = 0.0;
       for (int x = 0; x < DIM; ++x) {
@@ -503,6 +503,19 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
           ph_p += Lag<DIM - 1, ORDER>::phi_one(k, mu_) * pk;
           for (int s2 = 0; s2 < DIM - 1; ++s2) gp[s2] += (dmu[s2 + 1] - dmu[0]) * pk;
         }
+        const double wp = w > 0.0 ? w : 0.0;
+        const double dK = 3.0 * wp * wp / (12.0 * P.mu);
+        for (int k = 0; k < NNF; ++k) {
+          double dmu[DIM];
+          Lag<DIM - 1, ORDER>::dphi_one(k, mu_, dmu);
+          const double eta = Lag<DIM - 1, ORDER>::phi_one(k, mu_);
+          double gg = 0.0;
+          for (int s2 = 0; s2 < DIM - 1; ++s2)
+            for (int t2 = 0; t2 < DIM - 1; ++t2)
+              gg += gp[s2] * s_ginv[lf][s2 * (DIM - 1) + t2] * (dmu[t2 + 1] - dmu[0]);
+          s_eta[q][k] = eta;
+          s_fc[q][k] = P.s_p * (dK * gg + eta / P.dt);
+        }
       }
       for (int i = 0; i < DIM; ++i) {
         double sn = 0.0;  // <sigma> n, component i (sigma is linear in grad u)
@@ -516,66 +529,15 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
       s_W[q] = rt.fq_w[q] * area;
       s_al[q] = al;
       s_dT[q] = dT;
-      s_wq[q] = w;
-      for (int s2 = 0; s2 < DIM - 1; ++s2) s_gp[q][s2] = gp[s2];
     }
     __syncthreads();
     asm volatile("" : "+v"(ft));
-    // fluid coefficients of the C strips: s_p (K'(w) grad p . grad eta_k + eta_k / dt)
-    if (beta) {
-      for (int t = ft; t < NQF * NNF; t += NT) {
-        const int q = t / NNF, k = t % NNF;
-        double mu_[DIM], dmu[DIM];
-        for (int c2 = 0; c2 < DIM; ++c2) mu_[c2] = rt.fq_mu[q][c2];
-        Lag<DIM - 1, ORDER>::dphi_one(k, mu_, dmu);
-        const double eta = Lag<DIM - 1, ORDER>::phi_one(k, mu_);
-        const double wp = s_wq[q] > 0.0 ? s_wq[q] : 0.0;
-        const double dK = 3.0 * wp * wp / (12.0 * P.mu);
-        double gg = 0.0;
-        for (int s2 = 0; s2 < DIM - 1; ++s2)
-          for (int t2 = 0; t2 < DIM - 1; ++t2)
-            gg += s_gp[q][s2] * s_ginv[lf][s2 * (DIM - 1) + t2] * (dmu[t2 + 1] - dmu[0]);
-        s_eta[q][k] = eta;
-        s_fc[q][k] = P.s_p * (dK * gg + eta / P.dt);
-      }
-    }
-    for (int t = ft; t < NQF * NN; t += NT) {
-      const int q = t / NN, a = t % NN;
-      s_c[q][a] = s_W[q] * sgE * s_phE[q][a];
-    }
-    __syncthreads();
-    asm volatile("" : "+v"(ft));
-    // residual of this element's test functions
+    // residual of this element's test functions (c_qa = W_q s_e phi^e_a)
     for (int r = ft; r < BU; r += NT) {
       const int a = r / DIM, i = r % DIM;
       double acc = 0.0;
-      for (int q = 0; q < NQF; ++q) acc += s_c[q][a] * s_tau[q][i];
+      for (int q = 0; q < NQF; ++q) acc += s_W[q] * sgE * s_phE[q][a] * s_tau[q][i];
       s_R[r] += acc;
-    }
-    // moment matrices M1..M4 of both trial sides
-    for (int t = ft; t < 2 * NN * NN; t += NT) {
-      const int side = t / (NN * NN), a = (t / NN) % NN, b = t % NN;
-      double m1[DIM], m2 = 0.0, m3 = 0.0, m4 = 0.0;
-      for (int x = 0; x < DIM; ++x) m1[x] = 0.0;
-#pragma unroll 3
-      for (int q = 0; q < NQF; ++q) {
-        const double ca = s_c[q][a];
-        const double c1 = ca * (1.0 - s_al[q]);
-        const double ph = side == 0 ? s_phE[q][b] : s_phN[q][b];
-        double gn = 0.0;
-        for (int x = 0; x < DIM; ++x) {
-          const double g = side == 0 ? s_gphE[q][b][x] : s_gphN[q][b][x];
-          m1[x] += c1 * g;
-          gn += g * nrm[x];
-        }
-        m2 += c1 * gn;
-        m3 += c1 * ph;
-        m4 += ca * s_al[q] * s_dT[q] * ph;
-      }
-      for (int x = 0; x < DIM; ++x) s_M[side][a][b][x] = m1[x];
-      s_M[side][a][b][DIM] = m2;
-      s_M[side][a][b][DIM + 1] = m3;
-      s_M[side][a][b][DIM + 2] = m4;
     }
     // coupling strips: B (d R_u / d p) and C (d R_p / d u_e) of this face
     if (beta) {
@@ -585,23 +547,44 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
         const int32_t ix = kp.m.fs_idx[((int64_t)e * NF + lf) * NNF + k];
         double bv = 0.0, cv = 0.0;
         for (int q = 0; q < NQF; ++q) {
-          bv -= s_c[q][a] * s_eta[q][k] * nrm[i];
+          const double ca = s_W[q] * sgE * s_phE[q][a];
+          bv -= ca * s_eta[q][k] * nrm[i];
           cv += s_W[q] * s_fc[q][k] * sgE * s_phE[q][a] * nrm[i];
         }
         Bs[(int64_t)ix * BU + r] += bv;
         if (!kp.freeze_p) Cs[(int64_t)ix * BU + r] += cv;
       }
     }
-    __syncthreads();
-    asm volatile("" : "+v"(ft));
-    // self block (into the diagonal) and the off-diagonal block (straight to
-    // memory: for each (b, j) the threads of consecutive a write one run of BU)
+    // self block (into the diagonal) and the off-diagonal block: per test node
+    // a / trial node b the moments over the points of both trial sides
+    //   M1[x] = sum_q c_qa (1-alpha_q) dphi_b/dx_x,  M2 = sum_q c_qa (1-alpha_q) grad phi_b . n,
+    //   M3    = sum_q c_qa (1-alpha_q) phi_b,         M4 = sum_q c_qa alpha_q T'(w_q) phi_b,
+    // expanded to the 3x3 (2x2) node block; the off-diagonal block goes
+    // straight to memory (for each (b, j) the threads of consecutive a write
+    // one run of BU values)
     double *Aoff = A + (int64_t)kp.m.blk_of[e * NF + lf] * BU * BU;
     for (int t = ft; t < NN * NN; t += NT) {
       const int b = t / NN, a = t % NN;
+#pragma unroll 1
       for (int side = 0; side < 2; ++side) {
         const double sg = side == 0 ? sgE : sgN;
-        const double *M = s_M[side][a][b];
+        double M[DIM + 3];
+        for (int x = 0; x < DIM + 3; ++x) M[x] = 0.0;
+#pragma unroll 3
+        for (int q = 0; q < NQF; ++q) {
+          const double ca = s_W[q] * sgE * s_phE[q][a];
+          const double c1 = ca * (1.0 - s_al[q]);
+          const double ph = side == 0 ? s_phE[q][b] : s_phN[q][b];
+          double gn = 0.0;
+          for (int x = 0; x < DIM; ++x) {
+            const double g = side == 0 ? s_gphE[q][b][x] : s_gphN[q][b][x];
+            M[x] += c1 * g;
+            gn += g * nrm[x];
+          }
+          M[DIM] += c1 * gn;
+          M[DIM + 1] += c1 * ph;
+          M[DIM + 2] += ca * s_al[q] * s_dT[q] * ph;
+        }
         for (int j = 0; j < DIM; ++j)
           for (int i = 0; i < DIM; ++i) {
             const double ninj = nrm[i] * nrm[j];
@@ -616,9 +599,8 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
           }
       }
     }
-    (void)nb;
+    __syncthreads();
   }
-  __syncthreads();
 
   // ---- strong Dirichlet rows and write-back ------------------------------
   double *Ad = A + kp.m.blk_ptr[e] * BU * BU;
