@@ -293,7 +293,9 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
   __shared__ double s_phN[NQF][NN], s_gphN[NQF][NN][DIM];
   __shared__ double s_gu[NQV][DIM][DIM];      // displacement gradient at the volume points
   __shared__ double s_gj[NQF][DIM][DIM + 1];  // averaged gradient and jump at the face points
-  __shared__ double s_tau[NQF][DIM], s_W[NQF], s_al[NQF], s_dT[NQF];
+  __shared__ double s_gnE[NQF][NN], s_gnN[NQF][NN];  // grad phi . n at the face points
+  __shared__ double s_tau[NQF][DIM], s_W[NQF];
+  __shared__ double s_c1[NQF], s_c4[NQF];  // W_q s_e (1 - alpha_q), W_q s_e alpha_q T'(w_q)
   __shared__ double s_eta[NQF][NNF], s_fc[NQF][NNF];
   __shared__ double s_R[BU];
   // every interface element of this element, read once up front
@@ -447,12 +449,14 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
       double dph[DIM + 1];
       Lag<DIM, ORDER>::dphi_one(a, lamq, dph);
       const double ph = Lag<DIM, ORDER>::phi_one(a, lamq);
+      double gn = 0.0;
       for (int x = 0; x < DIM; ++x) {
         double g = 0.0;
         for (int k = 0; k <= DIM; ++k) g += dph[k] * (side == 0 ? s_gl[k][x] : s_gln[lf][k][x]);
         if (side == 0) s_gphE[q][a][x] = g; else s_gphN[q][a][x] = g;
+        gn += g * nrm[x];
       }
-      if (side == 0) s_phE[q][a] = ph; else s_phN[q][a] = ph;
+      if (side == 0) { s_phE[q][a] = ph; s_gnE[q][a] = gn; } else { s_phN[q][a] = ph; s_gnN[q][a] = gn; }
     }
     __syncthreads();
     asm volatile("" : "+v"(ft));
@@ -526,9 +530,10 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
         const double cj = G * s_gj[q][i][DIM] + (lam + G) * nrm[i] * w;
         s_tau[q][i] = (1.0 - al) * (sn + bh * cj) + al * T * nrm[i] - (beta ? ph_p * nrm[i] : 0.0);
       }
-      s_W[q] = rt.fq_w[q] * area;
-      s_al[q] = al;
-      s_dT[q] = dT;
+      const double W = rt.fq_w[q] * area;
+      s_W[q] = W;
+      s_c1[q] = W * sgE * (1.0 - al);
+      s_c4[q] = W * sgE * al * dT;
     }
     __syncthreads();
     asm volatile("" : "+v"(ft));
@@ -565,33 +570,43 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
     double *Aoff = A + (int64_t)kp.m.blk_of[e * NF + lf] * BU * BU;
     for (int t = ft; t < NN * NN; t += NT) {
       const int b = t / NN, a = t % NN;
-#pragma unroll 1
+      double M[2][DIM + 3];
+      for (int side = 0; side < 2; ++side)
+        for (int x = 0; x < DIM + 3; ++x) M[side][x] = 0.0;
+#pragma unroll 3
+      for (int q = 0; q < NQF; ++q) {
+        const double pa = s_phE[q][a];
+        const double c1 = s_c1[q] * pa, c4 = s_c4[q] * pa;
+        for (int x = 0; x < DIM; ++x) {
+          M[0][x] += c1 * s_gphE[q][b][x];
+          M[1][x] += c1 * s_gphN[q][b][x];
+        }
+        M[0][DIM] += c1 * s_gnE[q][b];
+        M[1][DIM] += c1 * s_gnN[q][b];
+        const double pe = s_phE[q][b], pn = s_phN[q][b];
+        M[0][DIM + 1] += c1 * pe;
+        M[1][DIM + 1] += c1 * pn;
+        M[0][DIM + 2] += c4 * pe;
+        M[1][DIM + 2] += c4 * pn;
+      }
+      // B[a i][b j] = n_i (lam/2 M1_j) + n_j (G/2 M1_i) + n_i n_j s1 + d_ij s2 with
+      // s1 = s_t ((b/h)(lam+G) M3 + M4), s2 = s_t (b/h) G M3 + G/2 M2
+      // (the expansion of lam/2 n_i M1_j + G/2 n_j M1_i + G/2 d_ij M2
+      //  + (b/h) s_t Chat_ij M3 + s_t n_i n_j M4, Chat = G I + (lam+G) n n)
+#pragma unroll
       for (int side = 0; side < 2; ++side) {
         const double sg = side == 0 ? sgE : sgN;
-        double M[DIM + 3];
-        for (int x = 0; x < DIM + 3; ++x) M[x] = 0.0;
-#pragma unroll 3
-        for (int q = 0; q < NQF; ++q) {
-          const double ca = s_W[q] * sgE * s_phE[q][a];
-          const double c1 = ca * (1.0 - s_al[q]);
-          const double ph = side == 0 ? s_phE[q][b] : s_phN[q][b];
-          double gn = 0.0;
-          for (int x = 0; x < DIM; ++x) {
-            const double g = side == 0 ? s_gphE[q][b][x] : s_gphN[q][b][x];
-            M[x] += c1 * g;
-            gn += g * nrm[x];
-          }
-          M[DIM] += c1 * gn;
-          M[DIM + 1] += c1 * ph;
-          M[DIM + 2] += ca * s_al[q] * s_dT[q] * ph;
+        const double s1 = sg * (bh * (lam + G) * M[side][DIM + 1] + M[side][DIM + 2]);
+        const double s2 = sg * bh * G * M[side][DIM + 1] + 0.5 * G * M[side][DIM];
+        double pl[DIM], pg[DIM];
+        for (int x = 0; x < DIM; ++x) {
+          pl[x] = 0.5 * lam * M[side][x];
+          pg[x] = 0.5 * G * M[side][x];
         }
         for (int j = 0; j < DIM; ++j)
           for (int i = 0; i < DIM; ++i) {
-            const double ninj = nrm[i] * nrm[j];
-            const double chat = (i == j ? G : 0.0) + (lam + G) * ninj;
-            double v = 0.5 * lam * nrm[i] * M[j] + 0.5 * G * nrm[j] * M[i] +
-                       bh * sg * chat * M[DIM + 1] + sg * ninj * M[DIM + 2];
-            if (i == j) v += 0.5 * G * M[DIM];
+            double v = nrm[i] * pl[j] + nrm[j] * pg[i] + nrm[i] * nrm[j] * s1;
+            if (i == j) v += s2;
             const int r = a * DIM + i;
             const int idx = (b * DIM + j) * BU + r;
             if (side == 0) s_diag[idx] += v;
