@@ -201,6 +201,40 @@ def counters_probe(prob):
     ctx.close()
 
 
+def assembly_probe(prob, n):
+    """n full assemblies of the workload (incremental assembly off), timed
+    with HIP events on the library stream, after one untimed; one 1 GiB device
+    copy first (a kernel of known traffic, for calibrating the hardware
+    counters).  Prints one JSON line: ms per assembly and the rate of its
+    algorithmic bytes (the Jacobian blocks written once, u read, R written)."""
+    import numpy as np
+    import torch
+    import paper_1911_10275_amd as hf
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = hf.context_for_problem(prob, device=0, stream=stream, incremental_assembly=0, profile=1)
+    sz = ctx.sizes
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    del a, b
+    rng = np.random.default_rng(0)
+    ctx.set_state(rng.normal(0.0, 1e-3, sz.n_u), np.full(sz.n_p, prob.material.sigma_c),
+                  np.zeros((sz.n_face, sz.nq_face)))
+    ctx.assemble()
+    ctx.reset_profile()
+    for _ in range(n):
+        ctx.assemble()
+    torch.cuda.synchronize()
+    pr = ctx.profile()
+    ms = pr.ms_assemble / max(pr.n_assemble, 1)
+    nbytes = sz.n_blocks * sz.block_size ** 2 * 8 + 2 * sz.n_u * 8
+    print(json.dumps({"probe": "full assembly", "workload": prob.name, "elements": int(sz.n_elem),
+                      "assemblies": int(pr.n_assemble), "ms_per_assembly": ms,
+                      "algorithmic_bytes": int(nbytes), "GBps": nbytes / (ms * 1e-3) / 1e9,
+                      "frac_hbm": nbytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}), flush=True)
+    ctx.close()
+
+
 def ensemble_block(K, gmres_m, tune_level=1, two_level=0):
     """The batched 2D KGD ensemble: 64 instances (1k-20k triangles, mixed P1 /
     P2, materials and injection drawn per instance).  The P1 and the P2
@@ -309,6 +343,9 @@ def main():
                     help="hardware-counter probe: 5 FP64 Jacobian products of the workload and "
                          "one 1 GiB device copy (calibration), then one FP32-IR preconditioner "
                          "build (matrix-core block inverses), nothing else")
+    ap.add_argument("--assembly", type=int, default=0, metavar="N",
+                    help="assembly probe: N full assemblies of the workload timed with HIP "
+                         "events (after one 1 GiB device copy for counter calibration), nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only (asked for {args.gpus}); sharding over "
@@ -322,6 +359,9 @@ def main():
     prob = synth.config(args.workload)
     if args.counters:
         counters_probe(prob)
+        return
+    if args.assembly > 0:
+        assembly_probe(prob, args.assembly)
         return
     print(f"bench: workload {prob.name}: {prob.n_elem} elements, {prob.n_udof} displacement DOF",
           file=sys.stderr, flush=True)
