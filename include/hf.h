@@ -527,8 +527,9 @@ hf_status hf_set_tuning(hf_ctx *ctx, const hf_tuning *t);
    block-Jacobi apply and the Gram-Schmidt passes (HIP events, 10 launches
    each after warm-up) in the context's precision and keeps the fastest;
    level 1: then also times complete linear solves for restart lengths
-   {60, 120} x orthogonalisation {0, 3} (FP32-IR: {0, 4}, the latter for
-   one instance at m = 60 only) and keeps the fastest whose solves all
+   {30, 60, 120} (30 for one instance only) x orthogonalisation {0, 3}
+   (FP32-IR: {0, 4}, the latter for one instance at m <= 60 only) and keeps
+   the fastest whose solves all
    converge.  At both levels a candidate replaces an earlier one only when
    it is faster by more than 2%, so near-ties keep the first candidate.  cache_path (nullable): a text file of
    "key choices" lines; the key names the GPU architecture, dim, order,

@@ -3375,17 +3375,22 @@ extern "C" hf_status hf_autotune(hf_ctx *ctx, int level, const char *cache_path,
     hf_tuning pick = best;
     // restart length and orthogonalisation: CGS2 against single-reduction
     // MGS (policy 3 is MGS for FP64 only, 4 also for the FP32 inner solves).
+    // The short restart (30) is tried for a single instance only: on the
+    // 64-instance 2D ensemble the solves at the first Newton iterate favoured
+    // it while the following iterations ran 9.7 against 13.4 batch steps/s at
+    // m = 60 (the 384k-tet penny: 1.51 against 1.42 Newton steps/s).
     // FP32 MGS is tried for a single instance only (in a batch one
     // ill-conditioned instance whose FP32 basis loses orthogonality stalls
     // its refinement and sets the batch's time) and with the short restart
     // only (the loss of orthogonality grows with the basis).
-    const int ms[2] = {60, 120};
+    const int ms[3] = {30, 60, 120};
     const bool fp64 = ctx->opt.precision == HF_FP64;
     const int pols[2] = {0, fp64 ? 3 : 4};
     const int npol = (fp64 || nI(ctx) == 1) ? 2 : 1;
-    for (int mi = 0; mi < 2; ++mi)
+    for (int mi = 0; mi < 3; ++mi)
       for (int pi = 0; pi < npol; ++pi) {
         if (!fp64 && pi == 1 && ms[mi] > 60) continue;
+        if (ms[mi] < 60 && nI(ctx) > 1) continue;
         hf_tuning t = best;
         t.gmres_m = ms[mi];
         t.reorth = pols[pi];
