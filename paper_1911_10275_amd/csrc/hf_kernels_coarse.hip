@@ -386,7 +386,8 @@ __global__ __launch_bounds__(kCT) void k_fwd_rows(CoarseK ck, int lev, const TF 
   const TF *row = Fm + ck.fo[x] + (int64_t)r * f;
   const T *v = cv + fd;
   double acc = 0.0;
-  for (int c = lane; c < k; c += 64) acc += (double)row[c] * (double)v[c];
+#pragma unroll 4
+  for (int c = lane; c < k; c += 64) acc += (double)__builtin_nontemporal_load(row + c) * (double)v[c];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) {
@@ -418,7 +419,8 @@ __global__ __launch_bounds__(kCT) void k_bwd_rows(CoarseK ck, int lev, const TF 
   const TF *row = Fm + ck.fo[x] + (int64_t)r * f;
   const T *v = cv + fd;
   double acc = 0.0;
-  for (int c = lane; c < f; c += 64) acc += (double)row[c] * (double)v[c];
+#pragma unroll 4
+  for (int c = lane; c < f; c += 64) acc += (double)__builtin_nontemporal_load(row + c) * (double)v[c];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) xs[ck.fd_dof[fd + r]] = (T)acc;
