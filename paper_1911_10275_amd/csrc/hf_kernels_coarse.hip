@@ -375,22 +375,36 @@ __global__ __launch_bounds__(kCT) void k_fwd_own(CoarseK ck, int lev, const T *_
   cv[pos] = v;
 }
 
+// Lanes per row of a front's row products: short rows take a segment of a
+// wave (16 or 32 lanes, two or four rows per wave) so that the lanes stay
+// busy; the choice depends on the front alone, so a front is summed the same
+// way in a batch and alone.
+__device__ inline int row_lanes(int len) { return len <= 256 ? 16 : (len <= 1024 ? 32 : 64); }
+
+// dot product of one row segment with the front vector; the lanes of a
+// segment reduce among themselves (segments are aligned, so every lane of a
+// segment has the same row and either all of them or none return early)
+template <typename T, typename TF>
+__device__ inline double row_dot(const TF *__restrict__ row, const T *__restrict__ v, int len, int sl, int lpr) {
+  double acc = 0.0;
+#pragma unroll 4
+  for (int c = sl; c < len; c += lpr) acc += (double)__builtin_nontemporal_load(row + c) * (double)v[c];
+  for (int off = lpr / 2; off > 0; off >>= 1) acc += __shfl_down(acc, off, lpr);
+  return acc;
+}
+
 template <typename T, typename TF>
 __global__ __launch_bounds__(kCT) void k_fwd_rows(CoarseK ck, int lev, const TF *__restrict__ Fm,
                                                   const T *__restrict__ cv, T *__restrict__ upd) {
   const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
   const int k = ck.fk[x], f = ck.ff[x];
-  const int lane = threadIdx.x % 64, r = k + blockIdx.x * (kCT / 64) + threadIdx.x / 64;
+  const int lpr = row_lanes(k);
+  const int lane = threadIdx.x % 64, sl = lane % lpr;
+  const int r = k + ((blockIdx.x * (kCT / 64) + threadIdx.x / 64) * 64 + lane) / lpr;
   if (r >= f) return;
   const int64_t fd = ck.fd_ptr[x];
-  const TF *row = Fm + ck.fo[x] + (int64_t)r * f;
-  const T *v = cv + fd;
-  double acc = 0.0;
-#pragma unroll 4
-  for (int c = lane; c < k; c += 64) acc += (double)__builtin_nontemporal_load(row + c) * (double)v[c];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) {
+  double acc = row_dot<T, TF>(Fm + ck.fo[x] + (int64_t)r * f, cv + fd, k, sl, lpr);
+  if (sl == 0) {
     const int64_t pos = fd + r;
     if (ck.src0[pos] >= 0) acc += (double)upd[ck.src0[pos]];
     if (ck.src1[pos] >= 0) acc += (double)upd[ck.src1[pos]];
@@ -413,17 +427,13 @@ __global__ __launch_bounds__(kCT) void k_bwd_rows(CoarseK ck, int lev, const TF 
                                                   const T *__restrict__ cv, T *__restrict__ xs) {
   const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
   const int k = ck.fk[x], f = ck.ff[x];
-  const int lane = threadIdx.x % 64, r = blockIdx.x * (kCT / 64) + threadIdx.x / 64;
+  const int lpr = row_lanes(f);
+  const int lane = threadIdx.x % 64, sl = lane % lpr;
+  const int r = ((blockIdx.x * (kCT / 64) + threadIdx.x / 64) * 64 + lane) / lpr;
   if (r >= k) return;
   const int64_t fd = ck.fd_ptr[x];
-  const TF *row = Fm + ck.fo[x] + (int64_t)r * f;
-  const T *v = cv + fd;
-  double acc = 0.0;
-#pragma unroll 4
-  for (int c = lane; c < f; c += 64) acc += (double)__builtin_nontemporal_load(row + c) * (double)v[c];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) xs[ck.fd_dof[fd + r]] = (T)acc;
+  const double acc = row_dot<T, TF>(Fm + ck.fo[x] + (int64_t)r * f, cv + fd, f, sl, lpr);
+  if (sl == 0) xs[ck.fd_dof[fd + r]] = (T)acc;
 }
 
 // several right-hand sides (row-major, nrhs columns): own rows first, then
