@@ -284,10 +284,9 @@ def ensemble_block(K, gmres_m, tune_level=1, two_level=0):
         for c, st in zip(ctxs, starts):
             c.set_options(precision=prec)
             reset(c, st)
-            if tune_level >= 0:
-                c.assemble()
-                tuned.append(c.autotune(level=tune_level, cache_path=cache).as_dict())
-                reset(c, st)
+            c.assemble()
+            tuned.append(c.autotune(level=tune_level, cache_path=cache).as_dict())
+            reset(c, st)
             c.newton_step(check=False)
             reset(c, st)
         torch.cuda.synchronize()
@@ -331,8 +330,8 @@ def main():
     ap.add_argument("--gmres-m", type=int, default=60, help="GMRES restart length")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--tune", type=int, default=1, choices=(-1, 0, 1),
-                    help="autotune level before timing (-1: none); choices cached in "
-                         "paper_1911_10275_amd/tuning_cache.txt")
+                    help="autotune level before timing (-1: apply a cached choice only, never "
+                         "time); choices cached in paper_1911_10275_amd/tuning_cache.txt")
     ap.add_argument("--ensemble-steps", type=int, default=3)
     ap.add_argument("--ensemble-m", type=int, default=120, help="GMRES restart length, ensemble")
     ap.add_argument("--coarse-fp32", type=int, default=1, choices=(0, 1),
@@ -384,8 +383,6 @@ def main():
     tune_cache = os.path.join(ROOT, "paper_1911_10275_amd", "tuning_cache.txt")
 
     def tune(name):
-        if args.tune < 0:
-            return
         ctx.set_state(St.u, St.p, St.w_old)
         ctx.assemble()
         t0 = time.perf_counter()

@@ -251,7 +251,7 @@ typedef struct {
                           lose orthogonality faster in FP32).  hf_autotune
                           level 1 chooses between 0 and 3 (FP64) or 0 and 4
                           (FP32-IR: 4 only for single-instance contexts and
-                          a restart length of 60). */
+                          restart lengths up to 60). */
   int gmres_m;         /* restart length (0 = keep hf_options.gmres_m) */
   int dense_wide_min;  /* pressure blocks with at least this many nodes are
                           inverted with one grid-wide launch pair per pivot
