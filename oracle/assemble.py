@@ -30,8 +30,9 @@ Interface law (eq. tsl, extended where the paper is silent):
   state 1 (cohesive): T = sigma_c (1 - w/delta_c) for 0 <= w <= delta_c,
                       T = 0 for w > delta_c, T = sigma_c + k_c w for w < 0
   state 2 (pre-crack, traction free): T = 0 for w >= 0, T = k_c w for w < 0
-  k_c = (b/h_f)(lambda + 2G) (contact penalty; parity unpinned beyond the
-  finite-difference check), delta_c = 2 G_c / sigma_c.
+  k_c = (b/h_f)(lambda + 2G) (contact penalty: the normal stiffness of the DG
+  stabilisation, so a closing rigid motion meets the force it meets on an
+  intact face), delta_c = 2 G_c / sigma_c.
 alpha = 1 at integration points with state >= 1.
 
 Clamped displacement copies get the row R = u - ubar with an identity

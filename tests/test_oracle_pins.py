@@ -194,6 +194,37 @@ def test_penalty_force_two_triangles(order):
     np.testing.assert_allclose(Ru[0], [-32.0, -16.0], rtol=1e-13)
 
 
+@pytest.mark.parametrize("order", [1, 2])
+def test_contact_branch_matches_the_intact_penalty(order):
+    """Contact branch of the traction law (the reading for w < 0): element 1
+    pushed rigidly into element 0 by delta = 0.01 along n, so the opening is
+    w = -0.01 at every point and the strains vanish.  On an intact face the
+    stabilisation alone acts, (b/h_f)|f| Chat(n) (-delta n) = -40 (lambda + 2G)
+    delta n (Chat n = (lambda + 2G) n); the contact stiffness k_c = (b/h_f)
+    (lambda + 2G) gives a traction-free face (state 2) exactly that force, and
+    a cohesive face (state 1, T = sigma_c + k_c w, continuous at w = 0) that
+    force plus the strength sigma_c |f| n."""
+    m = _two_triangles(order)
+    prm = asm.Params(1.0, 0.25, 1e-3, 1e-4, 1e-3, 1.0, b_stab=10.0)
+    n = np.array([1.0, 1.0]) / math.sqrt(2.0)
+    delta = 0.01
+    u = np.zeros((2, m.nn, 2))
+    u[1, :, :] = -delta * n
+    face = np.array([[1, 2]], np.int32)
+    forces = {}
+    for state in (0, 1, 2):
+        itf = Interfaces(m, face, np.array([state], np.uint8), np.zeros(1, np.uint8))
+        S = asm.assemble(m, itf, prm, u.reshape(-1), np.zeros(0), np.zeros((1, m.nq)), 1.0, [], [],
+                         jacobian=False)
+        Ru = S.R_u.reshape(2, m.nn, 2).sum(axis=1)
+        np.testing.assert_allclose(Ru[0], -Ru[1], rtol=1e-13, atol=1e-18)
+        forces[state] = Ru[1]
+    lam_2g = 0.4 + 2 * 0.4                         # E = 1, nu = 0.25
+    np.testing.assert_allclose(forces[0], -40.0 * lam_2g * delta * n, rtol=1e-13)
+    np.testing.assert_allclose(forces[2], forces[0], rtol=1e-13)
+    np.testing.assert_allclose(forces[1], forces[0] + 1e-3 * math.sqrt(8.0) * n, rtol=1e-13)
+
+
 # --------------------------------------------------------------------------
 # Sneddon's penny crack
 # --------------------------------------------------------------------------
