@@ -336,6 +336,9 @@ def main():
     ap.add_argument("--ensemble-m", type=int, default=120, help="GMRES restart length, ensemble")
     ap.add_argument("--coarse-fp32", type=int, default=1, choices=(0, 1),
                     help="1: FP64 solves apply the coarse factorisation rounded to FP32")
+    ap.add_argument("--coarse-reuse", type=int, default=16,
+                    help="two-level builds that keep the last coarse factorisation (0: refactorise "
+                         "at every build)")
     ap.add_argument("--two-level", type=int, default=1, choices=(0, 1),
                     help="1: two-level block preconditioner, 0: block-Jacobi")
     ap.add_argument("--counters", action="store_true",
@@ -366,7 +369,8 @@ def main():
           file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream().cuda_stream
     ctx = hf.context_for_problem(prob, device=0, stream=stream, gmres_m=args.gmres_m,
-                                 two_level=args.two_level, coarse_fp32=args.coarse_fp32)
+                                 two_level=args.two_level, coarse_fp32=args.coarse_fp32,
+                                 coarse_reuse=args.coarse_reuse)
     sz = ctx.sizes
     N = sz.n_u + sz.n_p
 
