@@ -87,6 +87,25 @@ struct Lag {
       out[eb(k)] = 4.0 * lam[ea(k)];
     }
   }
+  // Every P1/P2 node function in one product form, phi_a = c1 lam_i lam_j +
+  // c2 lam_i (vertex of P2: i = j = a, c1 = 2, c2 = -1; edge (i, j): c1 = 4,
+  // c2 = 0; P1: i = j = a, c1 = 0, c2 = 1), so that its gradient is
+  // c1 (lam_j grad lam_i + lam_i grad lam_j) + c2 grad lam_i without branches.
+  __device__ static void node_form(int a, int &i, int &j, double &c1, double &c2) {
+    if (K == 1) {
+      i = a;
+      j = a;
+      c1 = 0.0;
+      c2 = 1.0;
+    } else {
+      const bool v = a <= D;
+      const int k = v ? 0 : a - D - 1;
+      i = v ? a : ea(k);
+      j = v ? a : eb(k);
+      c1 = v ? 2.0 : 4.0;
+      c2 = v ? -1.0 : 0.0;
+    }
+  }
   // d phi_a / d lam_k
   __device__ static void dphi(const double *lam, double out[][D + 1]) {
 #pragma unroll
@@ -349,14 +368,12 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
   }
   for (int t = tid; t < NQV * NN; t += NT) {
     const int q = t / NN, a = t % NN;
-    double lamq[DIM + 1], dph[DIM + 1];
-    for (int k = 0; k <= DIM; ++k) lamq[k] = rt.vq_lam[q][k];
-    Lag<DIM, ORDER>::dphi_one(a, lamq, dph);
-    for (int x = 0; x < DIM; ++x) {
-      double g = 0.0;
-      for (int k = 0; k <= DIM; ++k) g += dph[k] * s_gl[k][x];
-      s_gphE[q][a][x] = g;
-    }
+    int i, j;
+    double c1, c2;
+    Lag<DIM, ORDER>::node_form(a, i, j, c1, c2);
+    const double li = rt.vq_lam[q][i], lj = rt.vq_lam[q][j];
+    for (int x = 0; x < DIM; ++x)
+      s_gphE[q][a][x] = c1 * (lj * s_gl[i][x] + li * s_gl[j][x]) + c2 * s_gl[i][x];
   }
   __syncthreads();
   asm volatile("" : "+v"(tid));
@@ -442,17 +459,23 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
     // shape functions of both elements at the face points
     for (int t = ft; t < 2 * NQF * NN; t += NT) {
       const int side = t / (NQF * NN), q = (t / NN) % NQF, a = t % NN;
-      double lamq[DIM + 1];
-      for (int k = 0; k <= DIM; ++k) lamq[k] = 0.0;
+      int i, j;
+      double c1, c2;
+      Lag<DIM, ORDER>::node_form(a, i, j, c1, c2);
+      // barycentrics of nodes i and j at the point: face vertex k of the
+      // point's rule sits at local vertex perm[k]; the opposite vertex is 0
       const int *perm = side == 0 ? s_pe[lf] : s_pn[lf];
-      for (int k = 0; k < DIM; ++k) lamq[perm[k]] = rt.fq_mu[q][k];
-      double dph[DIM + 1];
-      Lag<DIM, ORDER>::dphi_one(a, lamq, dph);
-      const double ph = Lag<DIM, ORDER>::phi_one(a, lamq);
+      double li = 0.0, lj = 0.0;
+      for (int k = 0; k < DIM; ++k) {
+        const double mu = rt.fq_mu[q][k];
+        li = perm[k] == i ? mu : li;
+        lj = perm[k] == j ? mu : lj;
+      }
+      const double(*gl)[DIM] = side == 0 ? s_gl : s_gln[lf];
+      const double ph = c1 * li * lj + c2 * li;
       double gn = 0.0;
       for (int x = 0; x < DIM; ++x) {
-        double g = 0.0;
-        for (int k = 0; k <= DIM; ++k) g += dph[k] * (side == 0 ? s_gl[k][x] : s_gln[lf][k][x]);
+        const double g = c1 * (lj * gl[i][x] + li * gl[j][x]) + c2 * gl[i][x];
         if (side == 0) s_gphE[q][a][x] = g; else s_gphN[q][a][x] = g;
         gn += g * nrm[x];
       }
