@@ -587,10 +587,11 @@ __global__ __launch_bounds__(kCT) void k_tl_t(KParams kp, CoarseK ck, const T *_
                                               const T *__restrict__ zp, const T *__restrict__ zc,
                                               T *__restrict__ t_out, T *__restrict__ apz) {
   using V2 = typename Pair<T>::type;
-  // the workgroup's elements (at most 2 kCT / 6 + 2 for block sizes >= 6) get
-  // their z_c values staged once, so the row loop streams A P alone
-  constexpr int EMAX = 2 * kCT / 6 + 2;
-  __shared__ double zs[EMAX * kTlCols];
+  // the workgroup's elements (at most tl_t_elems(bu)) get their z_c values
+  // staged once in dynamic LDS sized for the block size, so the row loop
+  // streams A P alone (a 30 x 30 block size needs 9.7 KB, not the 44.5 KB of
+  // the 6 x 6 case, which leaves room for more resident workgroups)
+  extern __shared__ double zs[];
   const int bu = kp.s.bu, hb = bu / 2, dim = ck.dim;
   const int64_t npair = kp.s.n_u / 2;
   const int64_t q0 = blockIdx.x * (int64_t)kCT;
@@ -833,7 +834,9 @@ template <typename T>
 hipError_t coarse_t(const KParams &kp, const CoarseK &ck, const T *AP, const T *Bs, const T *vu, const T *zp,
                     const T *zc, T *t, T *apz, hipStream_t st) {
   if (kp.s.bu % 2) return hipErrorInvalidValue;  // row pairs need an even block size
-  hipLaunchKernelGGL((k_tl_t<T>), dim3(nblk(kp.s.n_u / 2)), dim3(kCT), 0, st, kp, ck, AP, Bs, vu, zp, zc, t, apz);
+  // elements a workgroup of kCT row pairs can touch: (kCT - 1) / (bu / 2) + 2
+  const size_t lds = (size_t)((kCT - 1) / (kp.s.bu / 2) + 2) * kTlCols * sizeof(double);
+  hipLaunchKernelGGL((k_tl_t<T>), dim3(nblk(kp.s.n_u / 2)), dim3(kCT), lds, st, kp, ck, AP, Bs, vu, zp, zc, t, apz);
   return hipGetLastError();
 }
 template hipError_t coarse_t<double>(const KParams &, const CoarseK &, const double *, const double *,
