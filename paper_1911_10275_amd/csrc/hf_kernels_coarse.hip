@@ -522,17 +522,16 @@ template <typename T>
 __global__ __launch_bounds__(kCT) void k_zc2(KParams kp, CoarseK ck, const T *__restrict__ Z, int nrhs,
                                              const T *__restrict__ zc1, const T *__restrict__ zp,
                                              T *__restrict__ zc2) {
-  const int64_t r = blockIdx.x * (int64_t)(kCT / 64) + threadIdx.x / 64;
-  const int lane = threadIdx.x % 64;
+  // a 16-lane segment of a wave per row (rows are as long as the instance's
+  // pressure unknowns, a few hundred: a whole wave would leave most lanes idle)
+  constexpr int LPR = 16;
+  const int64_t r = (blockIdx.x * (int64_t)kCT + threadIdx.x) / LPR;
+  const int sl = threadIdx.x % LPR;
   if (r >= (int64_t)ck.ncls * ck.dim) return;
   const int b = ck.cinst[r / ck.dim];
   const int32_t p0 = kp.poff[b], np = kp.poff[b + 1] - p0;
-  const T *row = Z + r * nrhs;
-  double acc = 0.0;
-  for (int j = lane; j < np; j += 64) acc += (double)row[j] * (double)zp[p0 + j];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) zc2[r] = (T)((double)zc1[r] - acc);
+  const double acc = row_dot<T, T>(Z + r * nrhs, zp + p0, np, sl, LPR);
+  if (sl == 0) zc2[r] = (T)((double)zc1[r] - acc);
 }
 
 // pressure rows of the first half: q'_i = v_p,i - (Cf v_u + W z_c1)_i
@@ -821,7 +820,7 @@ template <typename T>
 hipError_t coarse_zc2(const KParams &kp, const CoarseK &ck, const T *Z, int nrhs, const T *zc1, const T *zp, T *zc2,
                       hipStream_t st) {
   if (!ck.ncls) return hipSuccess;
-  hipLaunchKernelGGL((k_zc2<T>), dim3(nblk((int64_t)ck.ncls * ck.dim, kCT / 64)), dim3(kCT), 0, st, kp, ck, Z, nrhs,
+  hipLaunchKernelGGL((k_zc2<T>), dim3(nblk((int64_t)ck.ncls * ck.dim, kCT / 16)), dim3(kCT), 0, st, kp, ck, Z, nrhs,
                      zc1, zp, zc2);
   return hipGetLastError();
 }
