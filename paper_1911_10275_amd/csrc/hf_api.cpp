@@ -908,7 +908,7 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
     h.n_act = (int64_t)loc_act[b].size();
     if (h.n_p > kMaxPressureBlock)
       return fail(ctx, HF_EINVAL, "instance " + std::to_string(b) +
-                                      ": more than 4096 pressure nodes (dense pressure block limit)");
+                                      ": more than 16384 pressure nodes (dense pressure block limit)");
     for (int32_t f : loc_act[b]) {
       face_keys(f, ks);
       for (int k = 0; k < NNF; ++k) loc_face_pn[b].push_back(pidx.at(ks[k]));
@@ -2236,8 +2236,8 @@ static hf_status build_preconditioner(hf_ctx *ctx, std::vector<int> &on, std::ve
     const int nb = ctx->poff[b + 1] - ctx->poff[b];
     if (nb < n_wide) continue;
     if (!ctx->gj_colk) {
-      TRY(dalloc(ctx, &ctx->gj_colk, kMaxPressureBlock));
-      TRY(dalloc(ctx, &ctx->gj_perm, kMaxPressureBlock));
+      TRY(dalloc(ctx, &ctx->gj_colk, (int64_t)(kGjPanel + 1) * kMaxPressureBlock));
+      TRY(dalloc(ctx, &ctx->gj_perm, 2 * (int64_t)kMaxPressureBlock));
       TRY(dalloc(ctx, &ctx->gj_piv, 1));
     }
     HIPCHK(launch_dense_inv_wide(ctx->S + ctx->doff[b], ctx->Sinv + ctx->doff[b], ctx->Sinv32 + ctx->doff[b], nb,
@@ -2738,8 +2738,8 @@ static hf_status do_staggered_step(hf_ctx *ctx, const std::vector<int32_t> &node
       const int nb = ctx->poff[b + 1] - ctx->poff[b];
       if (nb < n_wide) continue;
       if (!ctx->gj_colk) {
-        TRY(dalloc(ctx, &ctx->gj_colk, kMaxPressureBlock));
-        TRY(dalloc(ctx, &ctx->gj_perm, kMaxPressureBlock));
+        TRY(dalloc(ctx, &ctx->gj_colk, (int64_t)(kGjPanel + 1) * kMaxPressureBlock));
+        TRY(dalloc(ctx, &ctx->gj_perm, 2 * (int64_t)kMaxPressureBlock));
         TRY(dalloc(ctx, &ctx->gj_piv, 1));
       }
       HIPCHK(launch_dense_inv_wide(ctx->S + ctx->doff[b], ctx->Sinv + ctx->doff[b], ctx->Sinv32 + ctx->doff[b],

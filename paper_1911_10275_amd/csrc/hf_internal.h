@@ -30,7 +30,8 @@ constexpr int kMaxNq = 9;      // face points of 3D P2 (3 x 3)
 constexpr int kMaxKrylov = 257;  // basis vectors (restart length + 1)
 constexpr int kMaxNqv = 8;     // volume points of 3D P2 (2 x 2 x 2)
 constexpr int kChunkRows = 1024;  // rows of a reduction chunk of the batched Krylov kernels
-constexpr int kMaxPressureBlock = 4096;  // pressure nodes per instance (dense pressure block)
+constexpr int kMaxPressureBlock = 16384;  // pressure nodes per instance (dense pressure block)
+constexpr int kGjPanel = 32;  // pivots per panel of the blocked Gauss-Jordan of large pressure blocks
 constexpr int kDenseWideMin = 192;       // pressure blocks from this size are inverted grid-wide
 // fixed device array of the allocation-free folded product (its S^-1 x_p
 // staging vector): 512 KiB per GPU, i.e. 65,536 pressure unknowns per context
@@ -318,9 +319,11 @@ hipError_t launch_schur_form(const KParams &kp, const double *inv, const double 
 // blocks with n_wide <= n are left to launch_dense_inv_wide)
 hipError_t launch_schur_invert(const KParams &kp, double *S, double *Sinv, float *Sinv32, int *flag, int n_wide,
                                hipStream_t st);
-// inverse of one n x n block W (row-major, in place) into out / out32, one
-// pivot step per two launches over the whole GPU; scratch colk (n), perm (n),
-// piv (1); flag |= 2 on a zero or non-finite pivot
+// inverse of one n x n block W (row-major, in place) into out / out32 by
+// Gauss-Jordan with partial pivoting blocked over panels of kGjPanel pivots
+// (n <= kMaxPressureBlock); scratch colk ((kGjPanel + 1) kMaxPressureBlock
+// doubles), perm (2 kMaxPressureBlock ints), piv (1); flag |= 2 on a zero or
+// non-finite pivot
 hipError_t launch_dense_inv_wide(double *W, double *out, float *out32, int n, int *flag, double *colk, int *perm,
                                  double *piv, hipStream_t st);
 hipError_t launch_convert(const double *in, float *out, int64_t n, hipStream_t st);

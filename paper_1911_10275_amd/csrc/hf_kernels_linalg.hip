@@ -506,14 +506,22 @@ __global__ __launch_bounds__(kDT) void k_dense_inv(const int32_t *__restrict__ p
   }
 }
 
-// The same Gauss-Jordan for one large pressure block, each pivot step in two
-// launches so that the rank-one update spans the whole GPU: k_gj_pivot (one
-// workgroup: pivot search, row swap, scaling of the pivot row, column k kept
-// in colk) and k_gj_update (every other row).  The operations and their
-// order per entry are those of k_dense_inv, so both give the same bits.
-__global__ __launch_bounds__(kDT) void k_gj_pivot(double *__restrict__ W, int n, int k, double *__restrict__ colk,
-                                                  int *__restrict__ perm, double *__restrict__ piv,
-                                                  int *__restrict__ flag) {
+// The same Gauss-Jordan with partial pivoting for one large pressure block,
+// blocked over panels of kGjPanel pivots so that the matrix is swept once per
+// panel instead of once per pivot.  A pivot step k of the unblocked form
+// exchanges whole rows k and p, scales row k by 1/W_kk and subtracts f_r times
+// row k from every other row r (f_r = W_rk), storing -f_r/W_kk and 1/W_kk in
+// column k.  For a panel K = [k0, k1) those steps act on a column j outside
+// K as x <- P x, then x <- x + (W[:, K] - I[:, K]) x[K] with the panel
+// columns as they stand after the panel (P: the panel's row exchanges, which
+// the pivot kernel applies to whole rows at once).  So each panel runs its
+// pivot steps on its own columns (k_gjb_pivot, k_gjb_panel), stages the pivot
+// rows (k_gjb_stage) and updates every other column with one rank-|K|
+// product (k_gjb_update); at the end the row exchanges are undone on the
+// columns, last to first, as one gather (k_gjb_perm, k_gjb_finish).
+__global__ __launch_bounds__(kDT) void k_gjb_pivot(double *__restrict__ W, int n, int k, int k0, int k1,
+                                                   double *__restrict__ colk, int *__restrict__ perm,
+                                                   double *__restrict__ piv, int *__restrict__ flag) {
   __shared__ double sv[kDT];
   __shared__ int si[kDT];
   const int tid = threadIdx.x;
@@ -563,59 +571,155 @@ __global__ __launch_bounds__(kDT) void k_gj_pivot(double *__restrict__ W, int n,
     }
   __syncthreads();
   const double pinv = 1.0 / pv;
-  for (int j = tid; j < n; j += kDT) W[(int64_t)k * n + j] = (j == k) ? pinv : W[(int64_t)k * n + j] * pinv;
+  for (int j = k0 + tid; j < k1; j += kDT) W[(int64_t)k * n + j] = (j == k) ? pinv : W[(int64_t)k * n + j] * pinv;
   __syncthreads();
   for (int r = tid; r < n; r += kDT) colk[r] = W[(int64_t)r * n + k];
   if (tid == 0) piv[0] = pinv;
 }
 
-__global__ __launch_bounds__(256) void k_gj_update(double *__restrict__ W, int n, int k,
+// the panel columns of every row but k: W_rj -= f_r W_kj, and column k
+// becomes -f_r / W_kk
+__global__ __launch_bounds__(256) void k_gjb_panel(double *__restrict__ W, int n, int k, int k0, int k1,
                                                    const double *__restrict__ colk,
                                                    const double *__restrict__ piv) {
   const double pinv = piv[0];
   if (pinv == 0.0) return;  // failed pivot
+  const int w = k1 - k0;
   const double *Wk = W + (int64_t)k * n;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < (int64_t)n * n;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < (int64_t)n * w;
        t += (int64_t)gridDim.x * blockDim.x) {
-    const int r = (int)(t / n), j = (int)(t % n);
+    const int r = (int)(t / w), j = k0 + (int)(t % w);
     if (r == k) continue;
     const double f = colk[r];
-    W[t] = (j == k) ? -f * pinv : W[t] - f * Wk[j];
+    W[(int64_t)r * n + j] = (j == k) ? -f * pinv : W[(int64_t)r * n + j] - f * Wk[j];
   }
 }
 
-// undo the row exchanges on the columns (last to first), then copy out
-__global__ __launch_bounds__(kDT) void k_gj_finish(double *__restrict__ W, int n, const int *__restrict__ perm,
-                                                   double *__restrict__ out, float *__restrict__ out32,
-                                                   const int *__restrict__ flag) {
-  const int tid = threadIdx.x;
+// X[i][j] = W[k0 + i][j]: the panel's pivot rows after the exchanges
+__global__ __launch_bounds__(256) void k_gjb_stage(const double *__restrict__ W, int n, int k0, int k1,
+                                                   double *__restrict__ X, const int *__restrict__ flag) {
   if (*flag & 2) return;
-  for (int k = n - 1; k >= 0; --k) {
-    const int p = perm[k];
-    if (p != k)
-      for (int r = tid; r < n; r += kDT) {
-        const double t = W[(int64_t)r * n + k];
-        W[(int64_t)r * n + k] = W[(int64_t)r * n + p];
-        W[(int64_t)r * n + p] = t;
-      }
-    __syncthreads();
+  const int64_t m = (int64_t)(k1 - k0) * n;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x)
+    X[t] = W[(int64_t)k0 * n + t];
+}
+
+// every column j outside the panel: W_rj = [r outside K] W_rj + sum_i W_r,k0+i X_ij,
+// on 64 x 64 tiles (4 x 4 per thread), the panel columns and pivot rows in LDS
+constexpr int kGjTile = 64;
+__global__ __launch_bounds__(256) void k_gjb_update(double *__restrict__ W, int n, int k0, int k1,
+                                                    const double *__restrict__ X, const int *__restrict__ flag) {
+  __shared__ double Pt[kGjTile][kGjPanel + 1];
+  __shared__ double Xt[kGjPanel][kGjTile];
+  if (*flag & 2) return;
+  const int w = k1 - k0;
+  const int r0 = blockIdx.y * kGjTile, c0 = blockIdx.x * kGjTile;
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  for (int t = tid; t < kGjTile * kGjPanel; t += 256) {
+    const int rr = t / kGjPanel, i = t % kGjPanel;
+    const int row = r0 + rr;
+    Pt[rr][i] = (i < w && row < n) ? W[(int64_t)row * n + k0 + i] : 0.0;
   }
-  for (int64_t t = tid; t < (int64_t)n * n; t += kDT) {
-    out[t] = W[t];
-    out32[t] = (float)W[t];
+  for (int t = tid; t < kGjPanel * kGjTile; t += 256) {
+    const int i = t / kGjTile, cc = t % kGjTile;
+    const int col = c0 + cc;
+    Xt[i][cc] = (i < w && col < n) ? X[(int64_t)i * n + col] : 0.0;
+  }
+  __syncthreads();
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int i = 0; i < w; ++i) {
+    double pa[4], xb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) pa[a] = Pt[ty * 4 + a][i];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) xb[b] = Xt[i][tx + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += pa[a] * xb[b];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int row = r0 + ty * 4 + a;
+    if (row >= n) continue;
+    const bool in_panel = row >= k0 && row < k1;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int col = c0 + tx + 16 * b;
+      if (col >= n || (col >= k0 && col < k1)) continue;
+      double *e = W + (int64_t)row * n + col;
+      *e = (in_panel ? 0.0 : *e) + acc[a][b];
+    }
+  }
+}
+
+// the column permutation that undoes the row exchanges, last to first:
+// column c of the inverse is column idx[c] of W (one workgroup, in LDS)
+static_assert(kMaxPressureBlock <= 65536, "pivot rows are staged as 16-bit indices");
+__global__ __launch_bounds__(kDT) void k_gjb_perm(int n, const int *__restrict__ perm, int *__restrict__ idx,
+                                                  const int *__restrict__ flag) {
+  __shared__ uint16_t sp[kMaxPressureBlock], sx[kMaxPressureBlock];  // 64 KB at 16,384 nodes
+  if (*flag & 2) return;
+  for (int c = threadIdx.x; c < n; c += kDT) {
+    sp[c] = (uint16_t)perm[c];
+    sx[c] = (uint16_t)c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = n - 1; k >= 0; --k) {
+      const int p = sp[k];
+      if (p != k) {
+        const uint16_t t = sx[k];
+        sx[k] = sx[p];
+        sx[p] = t;
+      }
+    }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += kDT) idx[c] = sx[c];
+}
+
+__global__ __launch_bounds__(256) void k_gjb_finish(const double *__restrict__ W, int n, const int *__restrict__ idx,
+                                                    double *__restrict__ out, float *__restrict__ out32,
+                                                    const int *__restrict__ flag) {
+  if (*flag & 2) return;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < (int64_t)n * n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(t / n), c = (int)(t % n);
+    const double v = W[(int64_t)r * n + idx[c]];
+    out[t] = v;
+    out32[t] = (float)v;
   }
 }
 
 hipError_t launch_dense_inv_wide(double *W, double *out, float *out32, int n, int *flag, double *colk, int *perm,
                                  double *piv, hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  if (n > kMaxPressureBlock) return hipErrorInvalidValue;
+  // scratch: colk holds n multipliers then the staged pivot rows (kGjPanel x n),
+  // perm holds n pivot rows then the final column gather (n)
+  double *X = colk + kMaxPressureBlock;
+  int *idx = perm + kMaxPressureBlock;
   const int64_t nn = (int64_t)n * n;
-  const unsigned gu = (unsigned)std::min<int64_t>((nn + 255) / 256, 4096);
-  for (int k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kDT), 0, st, W, n, k, colk, perm, piv, flag);
-    hipLaunchKernelGGL(k_gj_update, dim3(gu), dim3(256), 0, st, W, n, k, colk, piv);
+  const unsigned gf = (unsigned)std::min<int64_t>((nn + 255) / 256, 4096);
+  const int nt = (n + kGjTile - 1) / kGjTile;
+  for (int k0 = 0; k0 < n; k0 += kGjPanel) {
+    const int k1 = std::min(k0 + kGjPanel, n);
+    const unsigned gp = (unsigned)std::min<int64_t>(((int64_t)n * (k1 - k0) + 255) / 256, 4096);
+    for (int k = k0; k < k1; ++k) {
+      hipLaunchKernelGGL(k_gjb_pivot, dim3(1), dim3(kDT), 0, st, W, n, k, k0, k1, colk, perm, piv, flag);
+      hipLaunchKernelGGL(k_gjb_panel, dim3(gp), dim3(256), 0, st, W, n, k, k0, k1, colk, piv);
+    }
+    if (k1 - k0 < n) {  // columns outside the panel exist
+      hipLaunchKernelGGL(k_gjb_stage, dim3(gp), dim3(256), 0, st, W, n, k0, k1, X, flag);
+      hipLaunchKernelGGL(k_gjb_update, dim3(nt, nt), dim3(256), 0, st, W, n, k0, k1, X, flag);
+    }
   }
-  hipLaunchKernelGGL(k_gj_finish, dim3(1), dim3(kDT), 0, st, W, n, perm, out, out32, flag);
+  hipLaunchKernelGGL(k_gjb_perm, dim3(1), dim3(kDT), 0, st, n, perm, idx, flag);
+  hipLaunchKernelGGL(k_gjb_finish, dim3(gf), dim3(256), 0, st, W, n, idx, out, out32, flag);
   return hipGetLastError();
 }
 
