@@ -254,9 +254,10 @@ typedef struct {
                           restart lengths up to 60). */
   int gmres_m;         /* restart length (0 = keep hf_options.gmres_m) */
   int dense_wide_min;  /* pressure blocks with at least this many nodes are
-                          inverted with one grid-wide launch pair per pivot
-                          step, the smaller ones by one workgroup each
-                          (0 = 192; the same arithmetic either way) */
+                          inverted by a grid-wide Gauss-Jordan blocked over
+                          panels of 32 pivots, the smaller ones by one
+                          workgroup each (0 = 192; both with partial
+                          pivoting, their results differ by rounding) */
   int inv_var;         /* element-block inverses of the FP32-IR
                           preconditioner (block size 30): 0 = as
                           hf_options.mfma_inverse, 1 = FP32 Gauss-Jordan on
@@ -347,8 +348,8 @@ hf_status hf_set_injection(hf_ctx *ctx, int32_t inst, int32_t n_src, const int64
 
 /* Build layout, block pattern, geometry and pressure numbering on the
    device for all instances.  No mesh, interface or injection uploads after
-   this call.  Limit: 4096 pressure nodes per instance (dense pressure
-   block). */
+   this call.  Limit: 16384 pressure nodes per instance (dense pressure
+   block, inverted by a blocked Gauss-Jordan above 192 nodes). */
 hf_status hf_finalize(hf_ctx *ctx);
 hf_status hf_get_sizes(hf_ctx *ctx, int32_t inst, hf_sizes *out);
 /* Pressure-node keys (n_p*2): (vertex, -1) or (lo, hi) of an edge node. */
