@@ -108,7 +108,7 @@ def run(case: Case, steps: int, predictor: bool = True, **kw):
         if na or nb:
             new = rebuild(case, qp, beta)
             p = carry_pressure(case, state.p, new)
-            state = State(state.u, p, state.w_old, fluid_scale(new, state.w_old, state.u))
+            state = State(state.u, p, state.w_old, fluid_scale(new, state.w_old, state.u), state.w_max)
             case = new
         out.append((case, state, ns, na, nb))
     return out

@@ -34,6 +34,13 @@ Interface law (eq. tsl, extended where the paper is silent):
   stabilisation, so a closing rigid motion meets the force it meets on an
   intact face), delta_c = 2 G_c / sigma_c.
 alpha = 1 at integration points with state >= 1.
+Unloading (optional history w_max per face point, the largest opening a
+cohesive point has reached at the end of a load step; the paper cites the
+Camacho-Ortiz law for eq. tsl and prints only its loading envelope; the
+reading here is that law's irreversible linear unloading to the origin):
+in state 1, with w_m = max(w_max, 0) > 0 and w < w_m, T = (T_env(w_m)/w_m) w
+for 0 <= w < w_m and T = k_c w for w < 0 (the secant reaches zero at w = 0);
+from w >= w_m on the envelope applies again.
 
 Clamped displacement copies get the row R = u - ubar with an identity
 Jacobian row.  Plane strain in 2D.
@@ -72,12 +79,13 @@ class Params:
         return 2.0 * self.G_c / self.sigma_c
 
 
-def traction_law(state, w, sigma_c, delta_c, kc):
+def traction_law(state, w, sigma_c, delta_c, kc, w_max=None):
     """Normal cohesive traction T(w) and dT/dw for interface state 1 or 2.
 
     Follows eq. (tsl) on 0 <= w <= delta_c; see the module docstring for the
-    branches outside it (a reading).  ``w >= 0`` selects the softening /
-    free branch at w = 0."""
+    branches outside it and for the unloading branch of a state-1 point
+    whose history w_max exceeds its opening (readings).  ``w >= 0`` selects
+    the softening / free branch at w = 0."""
     T = np.zeros_like(w)
     dT = np.zeros_like(w)
     neg = w < 0.0
@@ -92,6 +100,18 @@ def traction_law(state, w, sigma_c, delta_c, kc):
     c2 = s2 & neg
     T[c2] = kc[c2] * w[c2]
     dT[c2] = kc[c2]
+    if w_max is not None:
+        wm = np.maximum(w_max, 0.0)
+        un = s1 & (wm > 0.0) & (w < wm)
+        if np.any(un):
+            # secant slope T_env(w_m) / w_m of the point's envelope value at w_m
+            k_s = np.where(wm <= delta_c, sigma_c * (1.0 - wm / delta_c), 0.0) / np.where(un, wm, 1.0)
+            op = un & ~neg
+            T[op] = k_s[op] * w[op]
+            dT[op] = k_s[op]
+            cl = un & neg
+            T[cl] = kc[cl] * w[cl]
+            dT[cl] = kc[cl]
     return T, dT
 
 
@@ -135,12 +155,15 @@ class System:
 def assemble(mesh: Mesh, itf: Interfaces, prm: Params, u: np.ndarray, p: np.ndarray,
              w_old: np.ndarray, s_p: float, src_pnode, src_q0, ubar: Optional[np.ndarray] = None,
              jacobian: bool = True, faces: Optional[np.ndarray] = None,
-             elements: Optional[np.ndarray] = None, face_chunk: int = 4096) -> System:
+             elements: Optional[np.ndarray] = None, face_chunk: int = 4096,
+             w_max: Optional[np.ndarray] = None) -> System:
     """Residual (and Jacobian) at the state (u, p).
 
     u: (n_u,) element-major DG displacement copies, index (e*nn + a)*d + i
     p: (n_p,) pressure at the active skeleton nodes
     w_old: (nf, nq) opening of the previous load step at face points
+    w_max: optional (nf, nq) unloading history of the cohesive points (None:
+        the loading envelope only)
     faces: optional subset of interior faces to include (default all); used
         to evaluate selected element rows.
     elements: optional subset of elements whose bulk term is included
@@ -205,7 +228,8 @@ def assemble(mesh: Mesh, itf: Interfaces, prm: Params, u: np.ndarray, p: np.ndar
         avg_sn = 0.5 * np.einsum("fqix,fx->fqi", side["m"][4] + side["p"][4], n)
         Chat = G * np.eye(d)[None] + (lam + G) * np.einsum("fi,fj->fij", n, n)
         kc = np.repeat((bh * (lam + 2.0 * G))[:, None], m.nq, axis=1)
-        T, dT = traction_law(st, w, prm.sigma_c, prm.delta_c, kc)
+        T, dT = traction_law(st, w, prm.sigma_c, prm.delta_c, kc,
+                             None if w_max is None else w_max[F])
         # pressure at the face points (beta faces only)
         slot = face_slot[F]
         act = slot >= 0

@@ -54,6 +54,7 @@ class State:
     p: np.ndarray          # (n_p,)
     w_old: np.ndarray      # (nf, nq)
     s_p: float
+    w_max: Optional[np.ndarray] = None   # (nf, nq) unloading history, or None (envelope only)
 
 
 def opening(mesh: Mesh, u: np.ndarray) -> np.ndarray:
@@ -151,7 +152,7 @@ def newton_solve(case: Case, state: State, solver: str = "gmres", tol: float = 1
     ns = NewtonStats()
     for k in range(maxit):
         sysm = assemble(case.mesh, case.itf, case.prm, u, p, state.w_old, state.s_p,
-                        case.src_pnode, case.src_q0)
+                        case.src_pnode, case.src_q0, w_max=state.w_max)
         ns.res_norm.append(float(np.linalg.norm(sysm.R)))
         dx, ls = linear_solve(case, sysm, solver, m, rtol, lin_maxit, rtol_inner)
         ns.linear_iterations += ls.iterations
@@ -159,7 +160,7 @@ def newton_solve(case: Case, state: State, solver: str = "gmres", tol: float = 1
         ns.max_true_relres = max(ns.max_true_relres, ls.true_relres)
         if not ls.converged:
             ns.iterations = k + 1
-            return State(u, p, state.w_old, state.s_p), ns
+            return State(u, p, state.w_old, state.s_p, state.w_max), ns
         du, dp = dx[:case.mesh.n_u], dx[case.mesh.n_u:]
         u = u + du
         p = p + dp
@@ -173,13 +174,16 @@ def newton_solve(case: Case, state: State, solver: str = "gmres", tol: float = 1
         if ru <= tol and rp <= tol:
             ns.converged = True
             break
-    return State(u, p, state.w_old, state.s_p), ns
+    return State(u, p, state.w_old, state.s_p, state.w_max), ns
 
 
 def end_load_step(case: Case, state: State) -> State:
-    """w^n <- w(u) at the face points; s_p recomputed (alpha, beta frozen)."""
+    """w^n <- w(u) at the face points; s_p recomputed (alpha, beta frozen);
+    with an unloading history, w_max <- max(w_max, w) at every face point
+    (only the cohesive points use it)."""
     w = opening(case.mesh, state.u)
-    return State(state.u, state.p, w, fluid_scale(case, w))
+    wm = None if state.w_max is None else np.maximum(state.w_max, w)
+    return State(state.u, state.p, w, fluid_scale(case, w), wm)
 
 
 def run(case: Case, steps: int, predictor: bool = False, **kw):
@@ -221,15 +225,15 @@ def staggered_step(case: Case, state: State, dir_node: int, dir_value: float = 0
     from .assemble import bsr_A
     m = case.mesh
     S = assemble(m, case.itf, case.prm, state.u, state.p, state.w_old, state.s_p,
-                 case.src_pnode, case.src_q0)
+                 case.src_pnode, case.src_q0, w_max=state.w_max)
     du = spla.spsolve(bsr_A(m, S).tocsc(), -S.R_u)
     u = state.u + du
     S = assemble(m, case.itf, case.prm, u, state.p, state.w_old, state.s_p,
-                 case.src_pnode, case.src_q0)
+                 case.src_pnode, case.src_q0, w_max=state.w_max)
     D = S.D.toarray()
     r = S.R_p.copy()
     D[dir_node, :] = 0.0
     D[dir_node, dir_node] = 1.0
     r[dir_node] = state.p[dir_node] - dir_value
     dp = np.linalg.solve(D, -r)
-    return State(u, state.p + dp, state.w_old, state.s_p), du, dp
+    return State(u, state.p + dp, state.w_old, state.s_p, state.w_max), du, dp

@@ -80,6 +80,46 @@ def test_fd_jacobian_full_2d_p1():
         assert blk.nnz > 0
 
 
+def test_fd_jacobian_with_unloading_history():
+    """The full finite-difference Jacobian with an unloading history w_max at
+    the cohesive points, chosen so that the points visit every branch: the
+    secant (0 < w < w_max), closed after unloading (w < 0 < w_max), the
+    envelope beyond w_max and a fully softened history (w_max > delta_c)."""
+    case = Case.from_problem(synth.kgd_small(6, 1))
+    crack = case.itf.qp_state == 1
+    dc = case.prm.delta_c
+    rng = np.random.default_rng(5)
+    for seed in range(200):
+        u, p, wo = _random_state(case, seed)
+        w = newton.opening(case.mesh, u)
+        wm = np.where(rng.uniform(size=w.shape) < 0.6, np.abs(w) + rng.uniform(0.02, 0.3, w.shape),
+                      np.abs(w) * rng.uniform(0.2, 0.8, w.shape))
+        wc, mc = w[crack], wm[crack]
+        if (np.any((wc > 0) & (wc < mc)) and np.any((wc < 0) & (mc > 0)) and np.any(wc > mc)
+                and np.any(mc > dc)):
+            break
+    else:
+        raise AssertionError("no seeded state covers every unloading branch")
+    R = lambda uu, pp, jac=False: asm.assemble(case.mesh, case.itf, case.prm, uu, pp, wo, 10.0,
+                                               case.src_pnode, case.src_q0, jacobian=jac, w_max=wm)
+    S = R(u, p, jac=True)
+    J = asm.full_matrix(case.mesh, S).toarray()
+    x = np.concatenate([u, p])
+    nu = case.mesh.n_u
+    h = 1e-7
+    Jfd = np.empty_like(J)
+    for k in range(len(x)):
+        xp, xm = x.copy(), x.copy()
+        xp[k] += h; xm[k] -= h
+        Jfd[:, k] = (R(xp[:nu], xp[nu:]).R - R(xm[:nu], xm[nu:]).R) / (2 * h)
+    assert np.abs(J - Jfd).max() / np.abs(J).max() < 1e-6
+    # the history changes the cohesive rows (and nothing when it is all zero)
+    S0 = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, 10.0, case.src_pnode, case.src_q0)
+    Sz = asm.assemble(case.mesh, case.itf, case.prm, u, p, wo, 10.0, case.src_pnode, case.src_q0,
+                      w_max=np.zeros_like(wm))
+    assert np.array_equal(S0.R, Sz.R) and np.abs(S.R - S0.R).max() > 1e-8
+
+
 @pytest.mark.parametrize("prob", [synth.kgd_small(4, 2), synth.penny_small(4, 2)],
                          ids=["2d_p2", "3d_p2"])
 def test_fd_jacobian_directional(prob):

@@ -58,6 +58,35 @@ def test_traction_law_envelope():
     assert np.all(T2 == 0.0) and np.all(dT2 == 0.0)
 
 
+def test_traction_law_unloading_branch():
+    """Unloading of a cohesive point (the reading of irreversible linear
+    unloading to the origin): sigma_c = 1e-3, delta_c = 0.2, k_c = 1.  With
+    w_max = 0.1 (envelope value 0.5e-3) the point unloads on the secant of
+    slope 5e-3: T(0.05) = 2.5e-4, T(0) = 0; from w_max on it follows the
+    envelope again (T(0.15) = 0.25e-3); a closed face meets the contact
+    penalty without the strength offset (T(-0.01) = -0.01); a point beyond
+    delta_c has nothing left (secant slope 0); traction-free faces (state 2)
+    and points with no history ignore it."""
+    sc, dc = 1e-3, 0.2
+    w = np.array([0.05, 0.0, 0.1, 0.15, -0.01, 0.1, 0.05, 0.05])
+    wm = np.array([0.1, 0.1, 0.1, 0.1, 0.1, 0.3, 0.1, 0.0])
+    st = np.array([1, 1, 1, 1, 1, 1, 2, 1])
+    T, dT = asm.traction_law(st, w, sc, dc, np.ones_like(w), w_max=wm)
+    np.testing.assert_allclose(T, [2.5e-4, 0.0, 0.5e-3, 0.25e-3, -0.01, 0.0, 0.0, 0.75e-3],
+                               rtol=1e-14, atol=1e-18)
+    np.testing.assert_allclose(dT, [5e-3, 5e-3, -5e-3, -5e-3, 1.0, 0.0, 0.0, -5e-3], rtol=1e-14)
+    # a point loaded to delta_c and unloaded has dissipated all of G_c =
+    # sigma_c delta_c / 2: the area under the envelope up to w_max minus the
+    # triangle that unloading along the secant gives back
+    for w_m, dissipated in ((0.2, 1e-4), (0.1, 0.75e-4 - 0.25e-4)):
+        ws = np.linspace(0.0, w_m, 20001)
+        Tl, _ = asm.traction_law(np.ones_like(ws, dtype=int), ws, sc, dc, np.ones_like(ws))
+        Tu, _ = asm.traction_law(np.ones_like(ws, dtype=int), ws, sc, dc, np.ones_like(ws),
+                                 w_max=np.full_like(ws, w_m))
+        work = np.trapezoid(Tl, ws) - np.trapezoid(Tu, ws)
+        assert work == pytest.approx(dissipated, rel=1e-8)
+
+
 # --------------------------------------------------------------------------
 # a crack opened rigidly: two bodies separated along a through crack
 # --------------------------------------------------------------------------
