@@ -180,6 +180,17 @@ typedef struct {
                           eq. (discreteLubrication) as written.  The Newton
                           iterates do not depend on it; the relative
                           residuals of the linear solves do */
+  int cohesive_unloading; /* 1: cohesive points unload irreversibly: each
+                          face point keeps the largest opening w_max reached
+                          at the end of a load step (hf_end_load_step; set
+                          and read with hf_set_history / hf_get_history),
+                          and a state-1 point with 0 < w < w_max follows the
+                          secant T = (T_env(w_max) / w_max) w back to the
+                          origin (w < 0: contact, k_c w), the envelope of
+                          eq. (tsl) from w_max on -- the irreversible law of
+                          the cohesive model the paper cites, whose
+                          unloading it does not print (a reading); 0: the
+                          envelope only (default 0) */
   void *stream;        /* hipStream_t to run on; NULL: a stream the ctx creates */
 } hf_options;
 
@@ -431,8 +442,16 @@ hf_status hf_staggered_step(hf_ctx *ctx, const int32_t *dir_node, const double *
 /* End of a given-length load step: the opening of the converged state
    becomes the previous opening w^n of the storage term (w - w^n)/dt of eq.
    (discreteLubrication), w_old <- w(u) at every face point, and the
-   fluid-row scale s_p is recomputed from it. */
+   fluid-row scale s_p is recomputed from it; with cohesive_unloading the
+   unloading history becomes max(w_max, w) at every face point. */
 hf_status hf_end_load_step(hf_ctx *ctx);
+/* Unloading history of instance inst (cohesive_unloading): w_max per face
+   point, n_face * nq_face values in the order of hf_get_faces (host array,
+   copied).  hf_finalize sets it to zero; hf_end_load_step raises it to the
+   opening of the converged state when cohesive_unloading is 1.  HF_ESTATE
+   before hf_finalize, HF_ENONFINITE on a NaN or Inf. */
+hf_status hf_set_history(hf_ctx *ctx, int32_t inst, const double *w_max);
+hf_status hf_get_history(hf_ctx *ctx, int32_t inst, double *w_max);
 /* Starting state of the first load step: the uniform-pressure elastic
    predictor.  With the pressure held fixed at 1 the displacement rows are
    solved for u1 (one linear solve, same solver options); V1 = crack volume

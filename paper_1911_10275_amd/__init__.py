@@ -32,7 +32,8 @@ EXPORTS = [
     "hf_set_injection", "hf_finalize", "hf_get_sizes", "hf_get_pnodes", "hf_set_state",
     "hf_get_state", "hf_set_state_device", "hf_get_state_device", "hf_assemble", "hf_solve",
     "hf_newton_step", "hf_newton_solve", "hf_staggered_step", "hf_end_load_step",
-    "hf_get_interface_traction", "hf_detect_activation", "hf_initial_guess", "hf_get_residual",
+    "hf_get_interface_traction", "hf_detect_activation", "hf_set_history", "hf_get_history",
+    "hf_initial_guess", "hf_get_residual",
     "hf_get_block_rows", "hf_get_coupling", "hf_get_increment", "hf_apply_jacobian",
     "hf_get_profile", "hf_reset_profile", "hf_get_tuning", "hf_set_tuning", "hf_autotune",
     "hf_get_block_inverse", "hf_apply_preconditioned", "hf_apply_preconditioned_noalloc",
@@ -49,7 +50,7 @@ class Options(C.Structure):
                 ("incremental_assembly", C.c_int),
                 ("fold_preconditioner", C.c_int), ("two_level", C.c_int), ("coarse_leaf", C.c_int),
                 ("coarse_reuse", C.c_int), ("coarse_fp32", C.c_int),
-                ("scale_fluid_rows", C.c_int),
+                ("scale_fluid_rows", C.c_int), ("cohesive_unloading", C.c_int),
                 ("stream", C.c_void_p)]
 
 
@@ -153,6 +154,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "hf_get_interface_traction": (C.c_int, [vp, C.c_int32, P(C.c_double)]),
         "hf_detect_activation": (C.c_int, [vp, C.c_int32, P(C.c_uint8), P(C.c_uint8), P(C.c_int64)]),
         "hf_end_load_step": (C.c_int, [vp]),
+        "hf_set_history": (C.c_int, [vp, C.c_int32, vp]),
+        "hf_get_history": (C.c_int, [vp, C.c_int32, vp]),
         "hf_initial_guess": (C.c_int, [vp, P(C.c_double)]),
         "hf_get_residual": (C.c_int, [vp, C.c_int32, vp, vp]),
         "hf_get_block_rows": (C.c_int, [vp, C.c_int32, C.c_int64, vp, vp, vp]),
@@ -320,6 +323,17 @@ class Context:
         self._check(self.lib.hf_get_state(self.h, inst, _ptr(u), _ptr(p), _ptr(w), _ptr(wo)),
                     "hf_get_state")
         return u, p, w, wo
+
+    def set_history(self, w_max, inst=0):
+        """Unloading history w_max per face point (cohesive_unloading)."""
+        w = _arr(w_max, np.float64)
+        self._check(self.lib.hf_set_history(self.h, inst, _ptr(w)), "hf_set_history")
+
+    def get_history(self, inst=0):
+        s = self.isizes[inst]
+        w = np.empty((s.n_face, s.nq_face))
+        self._check(self.lib.hf_get_history(self.h, inst, _ptr(w)), "hf_get_history")
+        return w
 
     def set_state_device(self, u_ptr, p_ptr, w_old_ptr=None, inst=0):
         self._check(self.lib.hf_set_state_device(self.h, inst, C.c_void_p(u_ptr),

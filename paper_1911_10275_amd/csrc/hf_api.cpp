@@ -122,6 +122,7 @@ struct hf_ctx {
   int *k_flag = nullptr, *k_count = nullptr, *k_upd = nullptr;
   // state xs = [u; p] of all instances
   double *xs = nullptr, *xs_save = nullptr, *xs_start = nullptr, *w_old = nullptr, *w_tmp = nullptr;
+  double *w_max = nullptr;  // unloading history of the face points (cohesive_unloading)
   // assembled system
   double *R = nullptr, *A = nullptr, *Bs = nullptr, *Cs = nullptr;
   double *D = nullptr, *S = nullptr, *Sinv = nullptr, *T = nullptr, *inv = nullptr;
@@ -276,6 +277,7 @@ KParams kparams(const hf_ctx *ctx) {
   kp.freeze_p = ctx->freeze_p;
   kp.spmv_var = ctx->tune.spmv_var;
   kp.prec_var = ctx->tune.prec_var;
+  kp.wmax = ctx->opt.cohesive_unloading ? ctx->w_max : nullptr;
   return kp;
 }
 
@@ -497,6 +499,7 @@ extern "C" void hf_default_options(hf_options *o) {
   o->coarse_reuse = 16;
   o->coarse_fp32 = 0;
   o->scale_fluid_rows = 1;
+  o->cohesive_unloading = 0;
   o->stream = nullptr;
 }
 
@@ -514,6 +517,8 @@ static hf_status validate_options(hf_ctx *ctx, const hf_options &o) {
   if (o.coarse_reuse < 0 || o.coarse_reuse > 1000) return fail(ctx, HF_EINVAL, "coarse_reuse out of range 0..1000");
   if (o.coarse_fp32 < 0 || o.coarse_fp32 > 1) return fail(ctx, HF_EINVAL, "coarse_fp32 must be 0 or 1");
   if (o.scale_fluid_rows < 0 || o.scale_fluid_rows > 1) return fail(ctx, HF_EINVAL, "scale_fluid_rows must be 0 or 1");
+  if (o.cohesive_unloading < 0 || o.cohesive_unloading > 1)
+    return fail(ctx, HF_EINVAL, "cohesive_unloading must be 0 or 1");
   return HF_OK;
 }
 
@@ -1192,6 +1197,7 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
   TRY(dalloc(ctx, &ctx->xs_start, N));
   TRY(dalloc(ctx, &ctx->w_old, s.nf * NQ));
   TRY(dalloc(ctx, &ctx->w_tmp, s.nf * NQ));
+  TRY(dalloc(ctx, &ctx->w_max, std::max<int64_t>(s.nf * NQ, 1)));
   TRY(dalloc(ctx, &ctx->R, N));
   TRY(dalloc(ctx, &ctx->A, s.n_blocks * BU * BU));
   TRY(dalloc(ctx, &ctx->Bs, s.n_strip * BU));
@@ -1213,6 +1219,7 @@ extern "C" hf_status hf_finalize(hf_ctx *ctx) {
   TRY(ensure_host(ctx, 4 * (size_t)B + 8, 4 * (size_t)B + 8, 8 * (size_t)B + 64));
   HIPCHK(hipMemsetAsync(ctx->xs, 0, N * sizeof(double), ctx->stream));
   HIPCHK(hipMemsetAsync(ctx->w_old, 0, s.nf * NQ * sizeof(double), ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->w_max, 0, std::max<int64_t>(s.nf * NQ, 1) * sizeof(double), ctx->stream));
   TRY(upload(ctx, &ctx->d_rules, std::vector<RuleTables>{ctx->rules}));
   HIPCHK(launch_geometry(kparams(ctx), ctx->stream));
   TRY(sync(ctx));
@@ -2940,9 +2947,40 @@ extern "C" hf_status hf_end_load_step(hf_ctx *ctx) {
   TRY(check_ctx(ctx, 3));
   HIPCHK(hipSetDevice(ctx->opt.device));
   HIPCHK(launch_opening(kparams(ctx), ctx->xs, ctx->w_old, ctx->stream));
+  if (ctx->opt.cohesive_unloading)  // the history keeps the largest opening reached
+    HIPCHK(launch_max_into(ctx->w_old, ctx->w_max, ctx->s.nf * ctx->s.nqf, ctx->stream));
   TRY(update_fluid_scale(ctx));
   TRY(sync(ctx));
   ctx->stage = 3;
+  return HF_OK;
+}
+
+extern "C" hf_status hf_set_history(hf_ctx *ctx, int32_t inst, const double *w_max) {
+  TRY(check_ctx(ctx, 2));
+  TRY(check_inst(ctx, inst));
+  const InstHost &h = ctx->inst[inst];
+  const int nq = ctx->s.nqf;
+  if (h.nf && !w_max) return fail(ctx, HF_EINVAL, "null history array");
+  if (h.nf && !all_finite(w_max, h.nf * nq)) return fail(ctx, HF_ENONFINITE, "non-finite history");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  if (h.nf)
+    HIPCHK(hipMemcpyAsync(ctx->w_max + ctx->foff[inst] * nq, w_max, h.nf * nq * sizeof(double),
+                          hipMemcpyHostToDevice, ctx->stream));
+  TRY(sync(ctx));
+  return HF_OK;
+}
+
+extern "C" hf_status hf_get_history(hf_ctx *ctx, int32_t inst, double *w_max) {
+  TRY(check_ctx(ctx, 2));
+  TRY(check_inst(ctx, inst));
+  const InstHost &h = ctx->inst[inst];
+  const int nq = ctx->s.nqf;
+  if (h.nf && !w_max) return fail(ctx, HF_EINVAL, "null output array");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  if (h.nf)
+    HIPCHK(hipMemcpyAsync(w_max, ctx->w_max + ctx->foff[inst] * nq, h.nf * nq * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+  TRY(sync(ctx));
   return HF_OK;
 }
 

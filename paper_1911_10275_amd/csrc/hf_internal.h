@@ -131,6 +131,7 @@ struct KParams {
   double b_stab;
   int freeze_p;  // 1: pressure held fixed (fluid rows become p-rows of the identity)
   int spmv_var = 0, prec_var = 0;  // lanes per element row: 0 wide, 1 half (tuning)
+  const double *wmax = nullptr;    // nf*nq unloading history of the face points, or null (envelope only)
 };
 
 // device view of the batched Krylov state (see hf_kernels_krylov.hip)
@@ -327,6 +328,8 @@ hipError_t launch_schur_invert(const KParams &kp, double *S, double *Sinv, float
 hipError_t launch_dense_inv_wide(double *W, double *out, float *out32, int n, int *flag, double *colk, int *perm,
                                  double *piv, hipStream_t st);
 hipError_t launch_convert(const double *in, float *out, int64_t n, hipStream_t st);
+// y[i] = max(y[i], x[i]), i < n
+hipError_t launch_max_into(const double *x, double *y, int64_t n, hipStream_t st);
 // staggered iteration, fluid half: row node[b] of instance b's pressure block
 // W (a copy of D) becomes the identity row, R_p[node] = p[node] - value[b]
 hipError_t launch_stag_dirichlet(const KParams &kp, const int32_t *node, const double *value,

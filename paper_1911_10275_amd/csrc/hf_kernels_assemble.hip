@@ -247,12 +247,24 @@ hipError_t launch_geometry(const KParams &kp, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Interface law (normal cohesive traction) and cubic-law conductivity
 // ---------------------------------------------------------------------------
+// wm: the point's unloading history (0: none).  A cohesive point that has
+// opened to wm > 0 and stands below it unloads on the secant to the origin,
+// T = (T_env(wm) / wm) w, and meets plain contact k_c w once closed.
 __device__ inline void traction_law(int state, double w, double sigma_c, double delta_c,
-                                    double kc, double &T, double &dT) {
+                                    double kc, double wm, double &T, double &dT) {
   T = 0.0;
   dT = 0.0;
   if (state == 1) {
-    if (w < 0.0) {
+    if (wm > 0.0 && w < wm) {
+      if (w < 0.0) {
+        T = kc * w;
+        dT = kc;
+      } else {
+        const double ks = (wm <= delta_c ? sigma_c * (1.0 - wm / delta_c) : 0.0) / wm;
+        T = ks * w;
+        dT = ks;
+      }
+    } else if (w < 0.0) {
       T = sigma_c + kc * w;
       dT = kc;
     } else if (w <= delta_c) {
@@ -320,6 +332,7 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
   // every interface element of this element, read once up front
   __shared__ int32_t s_f[NF], s_nb[NF], s_slot[NF], s_beta[NF], s_minus[NF];
   __shared__ int32_t s_pe[NF][DIM], s_pn[NF][DIM], s_qst[NF][NQF];
+  __shared__ double s_wm[NF][NQF];  // unloading history of the face points (0: none)
   __shared__ double s_un[NF][BU], s_gln[NF][NF][DIM];
   __shared__ double s_n[NF][DIM], s_area[NF], s_bh[NF], s_ginv[NF][NG > 0 ? NG : 1];
   __shared__ double s_pv[NF][NNF];
@@ -346,7 +359,10 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
   }
   for (int t = tid; t < NF * NQF; t += NT) {
     const int lf = t / NQF, q = t % NQF;
-    if (s_f[lf] >= 0) s_qst[lf][q] = kp.m.qp_state[(int64_t)s_f[lf] * NQF + q];
+    if (s_f[lf] >= 0) {
+      s_qst[lf][q] = kp.m.qp_state[(int64_t)s_f[lf] * NQF + q];
+      s_wm[lf][q] = kp.wmax ? kp.wmax[(int64_t)s_f[lf] * NQF + q] : 0.0;
+    }
   }
   if (tid < NF) {
     const int32_t f = s_f[tid];
@@ -516,7 +532,7 @@ __device__ __forceinline__ void assemble_element(const KParams &kp, const RuleTa
       const int st = s_qst[lf][q];
       const double al = st > 0 ? 1.0 : 0.0;
       double T, dT;
-      traction_law(st, w, P.sigma_c, P.delta_c, kc, T, dT);
+      traction_law(st, w, P.sigma_c, P.delta_c, kc, s_wm[lf][q], T, dT);
       double ph_p = 0.0;
       double gp[DIM - 1];
       for (int s2 = 0; s2 < DIM - 1; ++s2) gp[s2] = 0.0;
@@ -1057,6 +1073,18 @@ hipError_t launch_fluid_volume(const KParams &kp, const double *u, double *parti
   else if (d == 2 && o == 2) hipLaunchKernelGGL((k_fluid_volume<2, 2>), dim3(nb), dim3(256), 0, st, kp, u, out);
   else if (d == 3 && o == 1) hipLaunchKernelGGL((k_fluid_volume<3, 1>), dim3(nb), dim3(256), 0, st, kp, u, out);
   else hipLaunchKernelGGL((k_fluid_volume<3, 2>), dim3(nb), dim3(256), 0, st, kp, u, out);
+  return hipGetLastError();
+}
+
+__global__ void k_max_into(const double *__restrict__ x, double *__restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = fmax(y[i], x[i]);
+}
+
+hipError_t launch_max_into(const double *x, double *y, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_max_into, dim3(g), dim3(256), 0, st, x, y, n);
   return hipGetLastError();
 }
 

@@ -68,6 +68,8 @@ class Propagation:
         low = float(p.min()) if p.size else 0.0
         p_new = np.array([p[old_index[k]] if k in old_index else low for k in _keys(new)])
         new.set_state(u, p_new, wo)
+        if self.options.get("cohesive_unloading"):  # the faces keep their unloading history
+            new.set_history(old.get_history())
         old.close()
         self.ctx = new
 

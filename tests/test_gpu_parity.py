@@ -111,13 +111,85 @@ def test_assembly_parity_every_traction_branch(name, incremental):
     ctx.close()
 
 
-def _check_assembly_at(case, ctx, seed):
+def _unloading_state(case):
+    """A state of ``_branch_state`` with an unloading history that puts
+    cohesive points on the secant (0 <= w < w_max), closed after unloading
+    (w < 0 < w_max), beyond their history (w > w_max) and on a fully
+    softened history (w_max > delta_c), each checked on the oracle side."""
+    m = case.mesh
+    u, p, wo = _branch_state(case)
+    w = newton.opening(m, u)
+    rng = np.random.default_rng(99)
+    wm = np.where(rng.uniform(size=w.shape) < 0.6, np.abs(w) + rng.uniform(0.02, 0.3, w.shape),
+                  np.abs(w) * rng.uniform(0.2, 0.8, w.shape))
+    c1, dc = case.itf.qp_state == 1, case.prm.delta_c
+    hit = [c1 & (w >= 0) & (w < wm), c1 & (w < 0) & (wm > 0), c1 & (w > wm), c1 & (wm > dc) & (w < wm)]
+    assert all(np.any(h) for h in hit)
+    return (u, p, wo), wm
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("incremental", [0, 1], ids=["full", "incremental"])
+def test_assembly_parity_unloading(name, incremental):
+    """With cohesive unloading on: a zero history gives the envelope (the
+    oracle without history), and a history that puts cohesive points in
+    every unloading branch gives the oracle's R and blocks with that history
+    (1e-12), in full and incremental assembly."""
+    prob = SMALL[name]()
+    case, ctx = _pair(prob)
+    ctx.set_options(incremental_assembly=incremental, cohesive_unloading=1)
+    _check_assembly_at(case, ctx, 13)
+    st, wm = _unloading_state(case)
+    ctx.set_history(wm)
+    np.testing.assert_array_equal(ctx.get_history(), wm)
+    _check_assembly_at(case, ctx, st, w_max=wm)
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["2d_p1_n9", "3d_p2_n3"])
+@pytest.mark.parametrize("precision", [hf.HF_FP64, hf.HF_FP32_IR], ids=["fp64", "fp32ir"])
+def test_newton_load_steps_unloading(name, precision):
+    """Two load steps with cohesive unloading from a history that is zero at
+    half of the face points and in [0.2, 0.8] delta_c at the others: the
+    converged states match the oracle's (1e-8), every solve at 1e-10, and
+    after each step the history is max(w_max, w) of the oracle (1e-8; the
+    points without history take their opening)."""
+    prob = SMALL[name]()
+    case, ctx = _pair(prob)
+    m, dc = case.mesh, case.prm.delta_c
+    rng = np.random.default_rng(7)
+    H = np.where(rng.uniform(size=(m.nf, m.nq)) < 0.5, 0.0, rng.uniform(0.2 * dc, 0.8 * dc, (m.nf, m.nq)))
+    st = newton.initial_state(case)
+    st.w_max = H.copy()
+    ctx.set_options(precision=precision, cohesive_unloading=1)
+    ctx.set_state(st.u, st.p, st.w_old)
+    ctx.set_history(H)
+    c1 = case.itf.qp_state == 1
+    for step in range(2):
+        st, ns_ref = newton.newton_solve(case, st)
+        assert ns_ref.converged
+        w_ref = newton.opening(m, st.u)
+        assert np.any(c1 & (w_ref >= 0) & (w_ref < st.w_max))   # the secant is in use
+        st = newton.end_load_step(case, st)
+        ns = ctx.newton_solve()
+        assert ns.converged and ns.lin.true_relres <= 1e-10
+        ctx.end_load_step()
+        u, p, w, wo = ctx.get_state()
+        assert np.linalg.norm(u - st.u) <= 1e-8 * np.linalg.norm(st.u)
+        if case.itf.n_p:
+            assert np.linalg.norm(p - st.p) <= 1e-8 * np.linalg.norm(st.p)
+        wm = ctx.get_history()
+        assert np.linalg.norm(wm - st.w_max) <= 1e-8 * np.linalg.norm(st.w_max)
+    ctx.close()
+
+
+def _check_assembly_at(case, ctx, seed, w_max=None):
     m = case.mesh
     u, p, wo = _random_state(case, seed) if isinstance(seed, int) else seed
     ctx.set_state(u, p, wo)
     rn = ctx.assemble()
     s_p = newton.fluid_scale(case, wo, u)
-    S = asm.assemble(m, case.itf, case.prm, u, p, wo, s_p, case.src_pnode, case.src_q0)
+    S = asm.assemble(m, case.itf, case.prm, u, p, wo, s_p, case.src_pnode, case.src_q0, w_max=w_max)
     ru, rp = ctx.residual()
     assert _rel(ru, S.R_u) < 1e-12
     if case.itf.n_p:
