@@ -379,7 +379,7 @@ __global__ __launch_bounds__(kCT) void k_fwd_own(CoarseK ck, int lev, const T *_
 // wave (16 or 32 lanes, two or four rows per wave) so that the lanes stay
 // busy; the choice depends on the front alone, so a front is summed the same
 // way in a batch and alone.
-__device__ inline int row_lanes(int len) { return len <= 256 ? 16 : (len <= 1024 ? 32 : 64); }
+__host__ __device__ inline int row_lanes(int len) { return len <= 256 ? 16 : (len <= 1024 ? 32 : 64); }
 
 // dot product of one row segment with the front vector; the lanes of a
 // segment reduce among themselves (segments are aligned, so every lane of a
@@ -398,17 +398,19 @@ __global__ __launch_bounds__(kCT) void k_fwd_rows(CoarseK ck, int lev, const TF 
                                                   const T *__restrict__ cv, T *__restrict__ upd) {
   const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
   const int k = ck.fk[x], f = ck.ff[x];
-  const int lpr = row_lanes(k);
-  const int lane = threadIdx.x % 64, sl = lane % lpr;
-  const int r = k + ((blockIdx.x * (kCT / 64) + threadIdx.x / 64) * 64 + lane) / lpr;
-  if (r >= f) return;
+  const int lpr = row_lanes(k), rpb = kCT / lpr;  // lanes per row, rows per workgroup pass
+  const int sl = threadIdx.x % lpr;
   const int64_t fd = ck.fd_ptr[x];
-  double acc = row_dot<T, TF>(Fm + ck.fo[x] + (int64_t)r * f, cv + fd, k, sl, lpr);
-  if (sl == 0) {
-    const int64_t pos = fd + r;
-    if (ck.src0[pos] >= 0) acc += (double)upd[ck.src0[pos]];
-    if (ck.src1[pos] >= 0) acc += (double)upd[ck.src1[pos]];
-    upd[ck.uo[x] + r - k] = (T)acc;
+  // the workgroups of a front stride over its rows (the grid is sized for the
+  // level's longest rows, so fronts with short rows need fewer passes)
+  for (int r = k + blockIdx.x * rpb + threadIdx.x / lpr; r < f; r += gridDim.x * rpb) {
+    double acc = row_dot<T, TF>(Fm + ck.fo[x] + (int64_t)r * f, cv + fd, k, sl, lpr);
+    if (sl == 0) {
+      const int64_t pos = fd + r;
+      if (ck.src0[pos] >= 0) acc += (double)upd[ck.src0[pos]];
+      if (ck.src1[pos] >= 0) acc += (double)upd[ck.src1[pos]];
+      upd[ck.uo[x] + r - k] = (T)acc;
+    }
   }
 }
 
@@ -427,13 +429,13 @@ __global__ __launch_bounds__(kCT) void k_bwd_rows(CoarseK ck, int lev, const TF 
                                                   const T *__restrict__ cv, T *__restrict__ xs) {
   const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
   const int k = ck.fk[x], f = ck.ff[x];
-  const int lpr = row_lanes(f);
-  const int lane = threadIdx.x % 64, sl = lane % lpr;
-  const int r = ((blockIdx.x * (kCT / 64) + threadIdx.x / 64) * 64 + lane) / lpr;
-  if (r >= k) return;
+  const int lpr = row_lanes(f), rpb = kCT / lpr;
+  const int sl = threadIdx.x % lpr;
   const int64_t fd = ck.fd_ptr[x];
-  const double acc = row_dot<T, TF>(Fm + ck.fo[x] + (int64_t)r * f, cv + fd, f, sl, lpr);
-  if (sl == 0) xs[ck.fd_dof[fd + r]] = (T)acc;
+  for (int r = blockIdx.x * rpb + threadIdx.x / lpr; r < k; r += gridDim.x * rpb) {
+    const double acc = row_dot<T, TF>(Fm + ck.fo[x] + (int64_t)r * f, cv + fd, f, sl, lpr);
+    if (sl == 0) xs[ck.fd_dof[fd + r]] = (T)acc;
+  }
 }
 
 // several right-hand sides (row-major, nrhs columns): own rows first, then
@@ -764,23 +766,26 @@ hipError_t coarse_s_correct(const KParams &kp, const CoarseK &ck, const double *
 template <typename T, typename TF>
 hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const TF *F, const T *b, T *upd, T *y, T *cv,
                          T *xs, hipStream_t st) {
-  constexpr int RP = kCT / 64;
   for (int l = 0; l < hv.n_levels; ++l) {
     const int nodes = hv.level_ptr[l + 1] - hv.level_ptr[l];
     if (!nodes) continue;
     hipLaunchKernelGGL((k_fwd_own<T>), dim3((std::max(hv.level_maxk[l], 1) + kCT - 1) / kCT, nodes), dim3(kCT), 0, st, ck, l, b,
                        upd, y, cv);
-    if (hv.level_maxf_minus_k[l] > 0)
-      hipLaunchKernelGGL((k_fwd_rows<T, TF>), dim3((hv.level_maxf_minus_k[l] + RP - 1) / RP, nodes), dim3(kCT), 0, st,
-                         ck, l, F, cv, upd);
+    // rows per workgroup pass: kCT / (lanes per row of the level's longest rows)
+    if (hv.level_maxf_minus_k[l] > 0) {
+      const int rpb = kCT / row_lanes(std::max(hv.level_maxk[l], 1));
+      hipLaunchKernelGGL((k_fwd_rows<T, TF>), dim3((hv.level_maxf_minus_k[l] + rpb - 1) / rpb, nodes), dim3(kCT), 0,
+                         st, ck, l, F, cv, upd);
+    }
   }
   for (int l = hv.n_levels - 1; l >= 0; --l) {
     const int nodes = hv.level_ptr[l + 1] - hv.level_ptr[l];
     if (!nodes) continue;
     hipLaunchKernelGGL((k_bwd_gather<T>), dim3((std::max(hv.level_maxf[l], 1) + kCT - 1) / kCT, nodes), dim3(kCT), 0, st, ck, l,
                        y, xs, cv);
-    hipLaunchKernelGGL((k_bwd_rows<T, TF>), dim3((std::max(hv.level_maxk[l], 1) + RP - 1) / RP, nodes), dim3(kCT), 0, st, ck, l, F,
-                       cv, xs);
+    const int rpb = kCT / row_lanes(std::max(hv.level_maxf[l], 1));
+    hipLaunchKernelGGL((k_bwd_rows<T, TF>), dim3((std::max(hv.level_maxk[l], 1) + rpb - 1) / rpb, nodes), dim3(kCT), 0,
+                       st, ck, l, F, cv, xs);
   }
   return hipGetLastError();
 }
