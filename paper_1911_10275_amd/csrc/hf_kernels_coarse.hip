@@ -438,6 +438,76 @@ __global__ __launch_bounds__(kCT) void k_bwd_rows(CoarseK ck, int lev, const TF 
   }
 }
 
+// The same two sweeps with the front vector staged in LDS by every workgroup
+// of the front (levels whose fronts hold at most kFrontLds values and take
+// at most kFusedMaxGroups workgroups): the
+// forward kernel forms the own right-hand sides itself (workgroup 0 also
+// stores them in y) and the backward one gathers [y_own; -x_struct] itself,
+// so each level takes one launch instead of two.  The products read the same
+// values in the same order as with the staged front vector in memory.
+constexpr int kFrontLds = 2048;
+// every workgroup of a front stages the whole front vector, so the fused form
+// is used only where a front takes few workgroups (measured: with up to ~125
+// per front the redundant gathers cost more than the saved launches)
+constexpr unsigned kFusedMaxGroups = 8;
+
+template <typename T>
+__device__ inline double row_dot_lds(const T *__restrict__ row, const double *__restrict__ v, int len, int sl,
+                                     int lpr) {
+  double acc = 0.0;
+#pragma unroll 4
+  for (int c = sl; c < len; c += lpr) acc += (double)__builtin_nontemporal_load(row + c) * v[c];
+  for (int off = lpr / 2; off > 0; off >>= 1) acc += __shfl_down(acc, off, lpr);
+  return acc;
+}
+
+template <typename T, typename TF>
+__global__ __launch_bounds__(kCT) void k_fwd_fused(CoarseK ck, int lev, const TF *__restrict__ Fm,
+                                                   const T *__restrict__ b, T *__restrict__ upd,
+                                                   T *__restrict__ y) {
+  __shared__ double sv[kFrontLds];
+  const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
+  const int k = ck.fk[x], f = ck.ff[x];
+  const int64_t fd = ck.fd_ptr[x];
+  for (int c = threadIdx.x; c < k; c += kCT) {
+    const T v = own_rhs<T>(ck, fd + c, b, upd, 1, 0);
+    sv[c] = (double)v;
+    if (blockIdx.x == 0) y[ck.fd_dof[fd + c]] = v;
+  }
+  __syncthreads();
+  const int lpr = row_lanes(k), rpb = kCT / lpr;
+  const int sl = threadIdx.x % lpr;
+  for (int r = k + blockIdx.x * rpb + threadIdx.x / lpr; r < f; r += gridDim.x * rpb) {
+    double acc = row_dot_lds<TF>(Fm + ck.fo[x] + (int64_t)r * f, sv, k, sl, lpr);
+    if (sl == 0) {
+      const int64_t pos = fd + r;
+      if (ck.src0[pos] >= 0) acc += (double)upd[ck.src0[pos]];
+      if (ck.src1[pos] >= 0) acc += (double)upd[ck.src1[pos]];
+      upd[ck.uo[x] + r - k] = (T)acc;
+    }
+  }
+}
+
+template <typename T, typename TF>
+__global__ __launch_bounds__(kCT) void k_bwd_fused(CoarseK ck, int lev, const TF *__restrict__ Fm,
+                                                   const T *__restrict__ y, T *__restrict__ xs) {
+  __shared__ double sv[kFrontLds];
+  const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
+  const int k = ck.fk[x], f = ck.ff[x];
+  const int64_t fd = ck.fd_ptr[x];
+  for (int c = threadIdx.x; c < f; c += kCT) {
+    const T v = c < k ? y[ck.fd_dof[fd + c]] : -xs[ck.fd_dof[fd + c]];
+    sv[c] = (double)v;
+  }
+  __syncthreads();
+  const int lpr = row_lanes(f), rpb = kCT / lpr;
+  const int sl = threadIdx.x % lpr;
+  for (int r = blockIdx.x * rpb + threadIdx.x / lpr; r < k; r += gridDim.x * rpb) {
+    const double acc = row_dot_lds<TF>(Fm + ck.fo[x] + (int64_t)r * f, sv, f, sl, lpr);
+    if (sl == 0) xs[ck.fd_dof[fd + r]] = (T)acc;
+  }
+}
+
 // several right-hand sides (row-major, nrhs columns): own rows first, then
 // the struct rows, a thread per (row, column)
 __global__ __launch_bounds__(kCT) void k_fwdm_own(CoarseK ck, int lev, const double *__restrict__ b,
@@ -766,26 +836,33 @@ hipError_t coarse_s_correct(const KParams &kp, const CoarseK &ck, const double *
 template <typename T, typename TF>
 hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const TF *F, const T *b, T *upd, T *y, T *cv,
                          T *xs, hipStream_t st) {
+  // rows per workgroup pass: kCT / (lanes per row of the level's longest rows)
   for (int l = 0; l < hv.n_levels; ++l) {
     const int nodes = hv.level_ptr[l + 1] - hv.level_ptr[l];
     if (!nodes) continue;
+    const int rpb = kCT / row_lanes(std::max(hv.level_maxk[l], 1));
+    const unsigned gx = (unsigned)std::max((hv.level_maxf_minus_k[l] + rpb - 1) / rpb, 1);
+    if (hv.level_maxk[l] <= kFrontLds && gx <= kFusedMaxGroups) {
+      hipLaunchKernelGGL((k_fwd_fused<T, TF>), dim3(gx, nodes), dim3(kCT), 0, st, ck, l, F, b, upd, y);
+      continue;
+    }
     hipLaunchKernelGGL((k_fwd_own<T>), dim3((std::max(hv.level_maxk[l], 1) + kCT - 1) / kCT, nodes), dim3(kCT), 0, st, ck, l, b,
                        upd, y, cv);
-    // rows per workgroup pass: kCT / (lanes per row of the level's longest rows)
-    if (hv.level_maxf_minus_k[l] > 0) {
-      const int rpb = kCT / row_lanes(std::max(hv.level_maxk[l], 1));
-      hipLaunchKernelGGL((k_fwd_rows<T, TF>), dim3((hv.level_maxf_minus_k[l] + rpb - 1) / rpb, nodes), dim3(kCT), 0,
-                         st, ck, l, F, cv, upd);
-    }
+    if (hv.level_maxf_minus_k[l] > 0)
+      hipLaunchKernelGGL((k_fwd_rows<T, TF>), dim3(gx, nodes), dim3(kCT), 0, st, ck, l, F, cv, upd);
   }
   for (int l = hv.n_levels - 1; l >= 0; --l) {
     const int nodes = hv.level_ptr[l + 1] - hv.level_ptr[l];
     if (!nodes) continue;
+    const int rpb = kCT / row_lanes(std::max(hv.level_maxf[l], 1));
+    const unsigned gx = (unsigned)((std::max(hv.level_maxk[l], 1) + rpb - 1) / rpb);
+    if (hv.level_maxf[l] <= kFrontLds && gx <= kFusedMaxGroups) {
+      hipLaunchKernelGGL((k_bwd_fused<T, TF>), dim3(gx, nodes), dim3(kCT), 0, st, ck, l, F, y, xs);
+      continue;
+    }
     hipLaunchKernelGGL((k_bwd_gather<T>), dim3((std::max(hv.level_maxf[l], 1) + kCT - 1) / kCT, nodes), dim3(kCT), 0, st, ck, l,
                        y, xs, cv);
-    const int rpb = kCT / row_lanes(std::max(hv.level_maxf[l], 1));
-    hipLaunchKernelGGL((k_bwd_rows<T, TF>), dim3((std::max(hv.level_maxk[l], 1) + rpb - 1) / rpb, nodes), dim3(kCT), 0,
-                       st, ck, l, F, cv, xs);
+    hipLaunchKernelGGL((k_bwd_rows<T, TF>), dim3(gx, nodes), dim3(kCT), 0, st, ck, l, F, cv, xs);
   }
   return hipGetLastError();
 }
