@@ -121,8 +121,12 @@ typedef struct {
                           a step that raised the true residual, or at the
                           refinement's caps.  Three steps with less than 1%
                           reduction double the inner restart length (up to
-                          256; at 256 the instance goes to FP64).  0: every
-                          instance in FP64 at once, < 0: never (default 2) */
+                          256; at 256 the instance goes to FP64).  An
+                          instance that went to FP64 is solved in FP64 at
+                          once in the later solves of the same load step
+                          (until hf_end_load_step or hf_set_state).  0:
+                          every instance in FP64 at once, < 0: never
+                          (default 2) */
   int incremental_assembly; /* 1: after the first full assembly, re-assemble
                           only the row panels of elements that touch a
                           cohesive or fluid interface, evaluate the other

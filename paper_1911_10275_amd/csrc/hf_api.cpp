@@ -123,6 +123,9 @@ struct hf_ctx {
   // state xs = [u; p] of all instances
   double *xs = nullptr, *xs_save = nullptr, *xs_start = nullptr, *w_old = nullptr, *w_tmp = nullptr;
   double *w_max = nullptr;  // unloading history of the face points (cohesive_unloading)
+  // GMRES-IR: instances whose refinement stalled in an earlier solve of the
+  // current load step (solved in FP64 directly until the step ends)
+  std::vector<uint8_t> ir_fp64;
   // assembled system
   double *R = nullptr, *A = nullptr, *Bs = nullptr, *Cs = nullptr;
   double *D = nullptr, *S = nullptr, *Sinv = nullptr, *T = nullptr, *inv = nullptr;
@@ -1318,6 +1321,7 @@ static hf_status update_fluid_scale(hf_ctx *ctx) {
 static hf_status set_state_impl(hf_ctx *ctx, int32_t inst, const double *u, const double *p,
                                 const double *w_old, hipMemcpyKind kind) {
   const InstHost &h = ctx->inst[inst];
+  if ((int)ctx->ir_fp64.size() > inst) ctx->ir_fp64[inst] = 0;
   const int nq = ctx->s.nqf;
   HIPCHK(hipMemcpyAsync(useg(ctx, ctx->xs, inst), u, ulen(ctx, inst) * sizeof(double), kind, ctx->stream));
   if (h.n_p) HIPCHK(hipMemcpyAsync(pseg(ctx, ctx->xs, inst), p, h.n_p * sizeof(double), kind, ctx->stream));
@@ -2469,6 +2473,15 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
     std::vector<double> rn_prev(B, 0.0), est(B, 1.0);
     std::vector<int> slow(B, 0), flat(B, 0), fb(B, 0);
     const int stall = ctx->opt.ir_stall_steps;
+    // an instance whose refinement stalled earlier in this load step goes to
+    // FP64 at once: its FP32 steps would stall again (the system changes
+    // little between Newton iterations) and in a batch they set the pace
+    if ((int)ctx->ir_fp64.size() != B) ctx->ir_fp64.assign(B, 0);
+    for (int b = 0; b < B; ++b)
+      if (on[b] && ctx->ir_fp64[b] && stall >= 0) {
+        fb[b] = 1;
+        on[b] = 0;
+      }
     for (int outer = 0;; ++outer) {
       HIPCHK(ks_norms<double>(kd, ctx->r64, ctx->partial, ctx->red, stm));
       TRY(get_d(ctx, ctx->red, B));
@@ -2502,6 +2515,7 @@ static hf_status do_solve(hf_ctx *ctx, std::vector<int> on, std::vector<hf_solve
                                   ls[b].gmres_iters >= ctx->opt.gmres_maxit)) {
           fb[b] = 1;  // solved in FP64 below
           on[b] = 0;
+          ctx->ir_fp64[b] = 1;
         } else if (outer >= ctx->opt.ir_maxit || ls[b].gmres_iters >= ctx->opt.gmres_maxit) {
           st[b] = HF_ENOCONV;
           note(ctx, b, "GMRES-IR did not reach rtol within its caps");
@@ -2949,6 +2963,7 @@ extern "C" hf_status hf_end_load_step(hf_ctx *ctx) {
   HIPCHK(launch_opening(kparams(ctx), ctx->xs, ctx->w_old, ctx->stream));
   if (ctx->opt.cohesive_unloading)  // the history keeps the largest opening reached
     HIPCHK(launch_max_into(ctx->w_old, ctx->w_max, ctx->s.nf * ctx->s.nqf, ctx->stream));
+  std::fill(ctx->ir_fp64.begin(), ctx->ir_fp64.end(), 0);  // FP32 gets a new chance each load step
   TRY(update_fluid_scale(ctx));
   TRY(sync(ctx));
   ctx->stage = 3;
