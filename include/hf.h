@@ -124,7 +124,10 @@ typedef struct {
                           256; at 256 the instance goes to FP64).  An
                           instance that went to FP64 is solved in FP64 at
                           once in the later solves of the same load step
-                          (until hf_end_load_step or hf_set_state).  0:
+                          (until hf_end_load_step or hf_set_state; a stall
+                          in the predictor's solve of hf_initial_guess
+                          carries into the first load step, whose operator
+                          is conditioned alike).  0:
                           every instance in FP64 at once, < 0: never
                           (default 2) */
   int incremental_assembly; /* 1: after the first full assembly, re-assemble
