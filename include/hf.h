@@ -557,8 +557,12 @@ hf_status hf_set_tuning(hf_ctx *ctx, const hf_tuning *t);
    {30, 60, 120} (30 for one instance only) x orthogonalisation {0, 3}
    (FP32-IR: {0, 4}, the latter for one instance at m <= 60 only) and keeps
    the fastest whose solves all
-   converge.  At both levels a candidate replaces an earlier one only when
-   it is faster by more than 2%, so near-ties keep the first candidate.  cache_path (nullable): a text file of
+   converge (the candidates are timed on the context's current system;
+   later solves do not re-check the choice, but a restart length that
+   stagnates there is doubled by the solver itself and an FP32-IR instance
+   that stalls is solved in FP64).  At both levels a candidate replaces an
+   earlier one only when it is faster by more than 2%, so near-ties keep the
+   first candidate.  cache_path (nullable): a text file of
    "key choices" lines; the key names the GPU architecture, dim, order,
    sizes, instance count, precision and level.  A line with the context's
    key is applied without timing; otherwise the result is appended.
