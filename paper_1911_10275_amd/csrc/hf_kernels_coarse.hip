@@ -383,17 +383,39 @@ __host__ __device__ inline int row_lanes(int len) { return len <= 256 ? 16 : (le
 
 // dot product of one row segment with the front vector; the lanes of a
 // segment reduce among themselves (segments are aligned, so every lane of a
-// segment has the same row and either all of them or none return early)
-template <typename T, typename TF>
+// segment has the same row and either all of them or none return early).
+// LONG (levels whose rows exceed kLongRow entries, near the root): a lane
+// first takes its entries in whole chunks of kDotChunk whose loads are issued
+// together, since such a row is otherwise a chain of dependent HBM round
+// trips; the rest goes one at a time.  The chunks cost registers, so the
+// levels of short rows (the leaves) keep the plain loop.  Each lane adds its
+// products in the same order either way.
+constexpr int kLongRow = 1024;
+constexpr int kDotChunk = 16;
+template <typename T, typename TF, bool LONG = false>
 __device__ inline double row_dot(const TF *__restrict__ row, const T *__restrict__ v, int len, int sl, int lpr) {
   double acc = 0.0;
+  int c = sl;
+  if constexpr (LONG) {
+    for (; c + (kDotChunk - 1) * lpr < len; c += kDotChunk * lpr) {
+      TF x[kDotChunk];
+      double y[kDotChunk];
+#pragma unroll
+      for (int u = 0; u < kDotChunk; ++u) {
+        x[u] = __builtin_nontemporal_load(row + c + u * lpr);
+        y[u] = (double)v[c + u * lpr];
+      }
+#pragma unroll
+      for (int u = 0; u < kDotChunk; ++u) acc += (double)x[u] * y[u];
+    }
+  }
 #pragma unroll 4
-  for (int c = sl; c < len; c += lpr) acc += (double)__builtin_nontemporal_load(row + c) * (double)v[c];
+  for (; c < len; c += lpr) acc += (double)__builtin_nontemporal_load(row + c) * (double)v[c];
   for (int off = lpr / 2; off > 0; off >>= 1) acc += __shfl_down(acc, off, lpr);
   return acc;
 }
 
-template <typename T, typename TF>
+template <typename T, typename TF, bool LONG>
 __global__ __launch_bounds__(kCT) void k_fwd_rows(CoarseK ck, int lev, const TF *__restrict__ Fm,
                                                   const T *__restrict__ cv, T *__restrict__ upd) {
   const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
@@ -404,7 +426,7 @@ __global__ __launch_bounds__(kCT) void k_fwd_rows(CoarseK ck, int lev, const TF 
   // the workgroups of a front stride over its rows (the grid is sized for the
   // level's longest rows, so fronts with short rows need fewer passes)
   for (int r = k + blockIdx.x * rpb + threadIdx.x / lpr; r < f; r += gridDim.x * rpb) {
-    double acc = row_dot<T, TF>(Fm + ck.fo[x] + (int64_t)r * f, cv + fd, k, sl, lpr);
+    double acc = row_dot<T, TF, LONG>(Fm + ck.fo[x] + (int64_t)r * f, cv + fd, k, sl, lpr);
     if (sl == 0) {
       const int64_t pos = fd + r;
       if (ck.src0[pos] >= 0) acc += (double)upd[ck.src0[pos]];
@@ -424,7 +446,7 @@ __global__ __launch_bounds__(kCT) void k_bwd_gather(CoarseK ck, int lev, const T
   cv[pos] = c < ck.fk[x] ? y[ck.fd_dof[pos]] : -xs[ck.fd_dof[pos]];
 }
 
-template <typename T, typename TF>
+template <typename T, typename TF, bool LONG>
 __global__ __launch_bounds__(kCT) void k_bwd_rows(CoarseK ck, int lev, const TF *__restrict__ Fm,
                                                   const T *__restrict__ cv, T *__restrict__ xs) {
   const int x = ck.level_nodes[ck.level_ptr[lev] + blockIdx.y];
@@ -433,7 +455,7 @@ __global__ __launch_bounds__(kCT) void k_bwd_rows(CoarseK ck, int lev, const TF 
   const int sl = threadIdx.x % lpr;
   const int64_t fd = ck.fd_ptr[x];
   for (int r = blockIdx.x * rpb + threadIdx.x / lpr; r < k; r += gridDim.x * rpb) {
-    const double acc = row_dot<T, TF>(Fm + ck.fo[x] + (int64_t)r * f, cv + fd, f, sl, lpr);
+    const double acc = row_dot<T, TF, LONG>(Fm + ck.fo[x] + (int64_t)r * f, cv + fd, f, sl, lpr);
     if (sl == 0) xs[ck.fd_dof[fd + r]] = (T)acc;
   }
 }
@@ -848,8 +870,12 @@ hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const TF *
     }
     hipLaunchKernelGGL((k_fwd_own<T>), dim3((std::max(hv.level_maxk[l], 1) + kCT - 1) / kCT, nodes), dim3(kCT), 0, st, ck, l, b,
                        upd, y, cv);
-    if (hv.level_maxf_minus_k[l] > 0)
-      hipLaunchKernelGGL((k_fwd_rows<T, TF>), dim3(gx, nodes), dim3(kCT), 0, st, ck, l, F, cv, upd);
+    if (hv.level_maxf_minus_k[l] > 0) {
+      if (hv.level_maxk[l] > kLongRow)
+        hipLaunchKernelGGL((k_fwd_rows<T, TF, true>), dim3(gx, nodes), dim3(kCT), 0, st, ck, l, F, cv, upd);
+      else
+        hipLaunchKernelGGL((k_fwd_rows<T, TF, false>), dim3(gx, nodes), dim3(kCT), 0, st, ck, l, F, cv, upd);
+    }
   }
   for (int l = hv.n_levels - 1; l >= 0; --l) {
     const int nodes = hv.level_ptr[l + 1] - hv.level_ptr[l];
@@ -862,7 +888,10 @@ hipError_t coarse_solve1(const CoarseK &ck, const CoarseHostView &hv, const TF *
     }
     hipLaunchKernelGGL((k_bwd_gather<T>), dim3((std::max(hv.level_maxf[l], 1) + kCT - 1) / kCT, nodes), dim3(kCT), 0, st, ck, l,
                        y, xs, cv);
-    hipLaunchKernelGGL((k_bwd_rows<T, TF>), dim3(gx, nodes), dim3(kCT), 0, st, ck, l, F, cv, xs);
+    if (hv.level_maxf[l] > kLongRow)
+      hipLaunchKernelGGL((k_bwd_rows<T, TF, true>), dim3(gx, nodes), dim3(kCT), 0, st, ck, l, F, cv, xs);
+    else
+      hipLaunchKernelGGL((k_bwd_rows<T, TF, false>), dim3(gx, nodes), dim3(kCT), 0, st, ck, l, F, cv, xs);
   }
   return hipGetLastError();
 }
