@@ -389,7 +389,9 @@ __host__ __device__ inline int row_lanes(int len) { return len <= 256 ? 16 : (le
 // together, since such a row is otherwise a chain of dependent HBM round
 // trips; the rest goes one at a time.  The chunks cost registers, so the
 // levels of short rows (the leaves) keep the plain loop.  Each lane adds its
-// products in the same order either way.
+// products in the same order, one fused multiply-add each, either way, so a
+// front's result does not depend on the path its level takes (in a batch the
+// longest row of the level over all instances picks it).
 constexpr int kLongRow = 1024;
 constexpr int kDotChunk = 16;
 template <typename T, typename TF, bool LONG = false>
