@@ -452,11 +452,16 @@ hf_status hf_staggered_step(hf_ctx *ctx, const int32_t *dir_node, const double *
    fluid-row scale s_p is recomputed from it; with cohesive_unloading the
    unloading history becomes max(w_max, w) at every face point. */
 hf_status hf_end_load_step(hf_ctx *ctx);
-/* Unloading history of instance inst (cohesive_unloading): w_max per face
-   point, n_face * nq_face values in the order of hf_get_faces (host array,
-   copied).  hf_finalize sets it to zero; hf_end_load_step raises it to the
-   opening of the converged state when cohesive_unloading is 1.  HF_ESTATE
-   before hf_finalize, HF_ENONFINITE on a NaN or Inf. */
+/* Unloading history of instance inst (cohesive_unloading; the irreversible
+   form of the cohesive law of eq. (tsl)): w_max per face point,
+   n_face * nq_face values in the order of hf_get_faces (host array, read or
+   written during the call, owned by the caller).  hf_finalize sets it to
+   zero; hf_end_load_step raises it to the opening of the converged state
+   when cohesive_unloading is 1.  A negative entry acts as 0 (no history).
+   The history is kept whatever cohesive_unloading says, and only read when
+   it is 1.  HF_ESTATE before hf_finalize, HF_EINVAL for an instance out of
+   range or a null array (when the instance has faces), HF_ENONFINITE on a
+   NaN or Inf (nothing is copied then). */
 hf_status hf_set_history(hf_ctx *ctx, int32_t inst, const double *w_max);
 hf_status hf_get_history(hf_ctx *ctx, int32_t inst, double *w_max);
 /* Starting state of the first load step: the uniform-pressure elastic
