@@ -10,14 +10,21 @@
  * the continuous P^k lubrication equation eq. (discreteLubrication) on the
  * interface skeleton, linearised as the 2x2 block system eq.
  * (fully-coupled-fully-discrete) and solved with right-preconditioned
- * restarted GMRES (block-Jacobi preconditioner) in FP64, or with an FP32
+ * restarted GMRES (element block-Jacobi or a two-level block
+ * preconditioner with a vertex coarse space) in FP64, or with an FP32
  * inner GMRES under FP64 iterative refinement (GMRES-IR).  alpha (the
- * cohesive-law activation) and beta (the fluid flag) are inputs and stay
- * frozen, as inside one time step of the paper's algorithm.
+ * cohesive-law activation) and beta (the fluid flag) stay frozen inside a
+ * load step, as in one time step of the paper's algorithm; between load
+ * steps hf_detect_activation applies the fracture and fluid activation
+ * checks of eq. (fractureActivation) and eq. (fluidActivation).
  *
  * Conventions
  *  - Every call returns hf_status (HF_OK = 0); no C++ exception crosses the
  *    ABI.  hf_last_error() gives the message of the last failure of a ctx.
+ *    Any call may return HF_EINVAL (a null required pointer, an instance id
+ *    out of range, a size or value out of range), HF_ESTATE (call order),
+ *    HF_ENOMEM and HF_EDEVICE (the HIP runtime); a call's comment names the
+ *    other codes it returns.
  *  - Host arrays passed in are borrowed for the duration of the call and
  *    copied; output arrays are caller-allocated.  *_device variants take
  *    device pointers that must stay valid until the ctx stream has finished
